@@ -1,0 +1,151 @@
+"""Pins of the oracle's full time step (CPU only).
+
+* T6  energy conservation of the step: the last grey solve balances radiation
+      plus material energy change against the boundary inflow;
+* T7  a spatially uniform problem whose boundaries receive the 0-D solution
+      reproduces the 0-D backward-Euler step (per-group energy balance plus the
+      scalar MEB, solved independently here), and an equilibrium state stays put;
+* T8  converged V, W and F cycles reach the same discrete solution as the
+      single-grid method (Alg. 1, multigroup LOQD + MEB solved together);
+* T10 the cycle schedules reproduce the paper's low-order solve counts from its
+      cycle counts (Tables 1-2), and the oracle's own counters obey the same law;
+      with lmax = 1 every step runs one more cycle than it sweeps.
+"""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from oracle import mlqd, planck
+from oracle.moments import factors
+from paper_2011_05427_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def tiny_problem(nx=6, ng=8, nmu=4, **kw):
+    slab = inputs.make_slab(nx, ng, nmu, **kw)
+    return slab, mlqd.problem_from_slab(slab)
+
+
+def test_step_energy_conservation():
+    slab, pb = tiny_problem(nx=10, ng=16, nmu=8, dt=0.01)
+    st0 = mlqd.initial_state(pb, slab.T0)
+    st1 = mlqd.step(pb, [16, 4, 1], [1], 2, 1e-12, 1e-13, st0)
+    dx = pb.dx
+    # the carried fine-grid state (from the last fine solve) balances to the
+    # convergence tolerance; the sum of its groups is the radiation energy
+    Erad1 = st1.E.sum(axis=0)
+    Erad0 = st0.E.sum(axis=0)
+    F = st1.F.sum(axis=0)
+    lhs = np.sum(dx * ((Erad1 - Erad0) + pb.cv * (st1.T - st0.T)))
+    rhs = -pb.dt * (F[-1] - F[0])
+    scale = np.sum(dx * (Erad1 + pb.cv * st1.T))
+    assert abs(lhs - rhs) < 1e-9 * scale
+
+
+def _zero_d(pb, T_old, E_old, dt):
+    """Backward-Euler step of the infinite medium: E_g(T) from the group
+    balance, then the scalar MEB root in T."""
+    c, cv = pb.c, pb.cv
+
+    def Eg(T):
+        k = planck.opacity(pb.nu_center, pb.C_cell[:1], np.array([T]))[:, 0]
+        B = planck.planck_groups(pb.nu_edges, np.array([T]), pb.aR, c)[:, 0]
+        return k, B, (E_old / dt + 2 * k * B) / (1 / dt + c * k)
+
+    def r(T):
+        k, B, E = Eg(T)
+        return cv * (T - T_old) / dt - np.sum(c * k * E - 2 * k * B)
+
+    T = brentq(r, 0.5 * T_old, 4.0 * T_old, xtol=1e-17, rtol=1e-15, maxiter=500)
+    return T, Eg(T)[2]
+
+
+def _uniform_state(pb, T, E):
+    G, nx, M = pb.G, pb.nx, len(pb.mu)
+    I = np.broadcast_to((pb.c * E / 2)[:, None, None, None], (G, M, nx, 2)).copy()
+    fac = factors(pb.mu, pb.w, I, pb.inc_left, pb.inc_right, pb.c)
+    Ec = np.broadcast_to(E[:, None], (G, nx)).copy()
+    return mlqd.State(T=np.full(nx, T), I=I, E=Ec, F=np.zeros((G, nx + 1)),
+                      Ebnd=np.stack([E, E], axis=1), fac=fac, Egrey=Ec.sum(axis=0))
+
+
+@pytest.mark.parametrize("cycle", ["V", "W"])
+def test_uniform_medium_matches_zero_d(cycle):
+    slab, pb = tiny_problem(nx=6, ng=8, nmu=8, C1=5.0, C2=5.0, dt=0.01)
+    T_old = 0.3
+    E_old = 2 * planck.planck_groups(pb.nu_edges, np.array([0.5]), pb.aR, pb.c)[:, 0] / pb.c
+    T1, E1 = _zero_d(pb, T_old, E_old, pb.dt)
+    pb = dataclasses.replace(pb, inc_left=pb.c * E1 / 2, inc_right=pb.c * E1 / 2)
+    st0 = _uniform_state(pb, T_old, E_old)
+    levels, sched = ([8, 1], []) if cycle == "V" else ([8, 2, 1], [1])
+    st1 = mlqd.step(pb, levels, sched, 3, 1e-13, 1e-14, st0)
+    np.testing.assert_allclose(st1.T, T1, rtol=1e-11)
+    np.testing.assert_allclose(st1.E, np.broadcast_to(E1[:, None], st1.E.shape), rtol=1e-10,
+                               atol=1e-12 * E1.max())
+    assert np.max(np.abs(st1.F.sum(axis=0))) < 1e-9 * pb.c * E1.sum()
+    assert T1 > T_old  # the hotter radiation heats the material
+
+
+def test_equilibrium_is_stationary():
+    slab, pb = tiny_problem(nx=5, ng=8, nmu=8, T_left=0.4, T_right=0.4, T0=0.4, dt=0.05)
+    st0 = mlqd.initial_state(pb, 0.4)
+    st1 = mlqd.step(pb, [8, 2, 1], [1], 2, 1e-12, 1e-13, st0)
+    np.testing.assert_allclose(st1.T, 0.4, rtol=1e-13)
+    np.testing.assert_allclose(st1.E, st0.E, rtol=1e-12)
+
+
+@pytest.mark.parametrize("cycle,levels,sched", [
+    ("V", [8, 1], []),
+    ("W", [8, 4, 1], [1]),
+    ("F", [8, 4, 2, 1], [2, 1]),
+])
+def test_multigrid_matches_single_grid(cycle, levels, sched):
+    slab, pb = tiny_problem(nx=6, ng=8, nmu=4, dt=0.004, T0=0.01, C1=4.0, C2=1.0)
+    st0 = mlqd.initial_state(pb, slab.T0)
+    ref = st0
+    mg = st0
+    for _ in range(2):
+        ref = mlqd.alg1_step(pb, ref, eps=1e-14)
+        mg = mlqd.step(pb, levels, sched, 4, 1e-14, 1e-15, mg)
+    np.testing.assert_allclose(mg.T, ref.T, rtol=1e-10)
+    np.testing.assert_allclose(mg.E, ref.E, rtol=1e-9, atol=1e-12 * ref.E.max())
+
+
+def _per_cycle_cost(levels, cycle):
+    cfg = inputs.SolverCfg(levels=levels, cycle={"V": 0, "W": 1, "F": 2}[cycle])
+    return levels[0] + 1 + sum(levels[g] + 1 for g in cfg.schedule())
+
+
+def test_paper_table_arithmetic():
+    rows = json.load(open(os.path.join(HERE, "golden", "paper_tables.json")))["rows"]
+    ok = 0
+    for r in rows:
+        if r["N_c"] * _per_cycle_cost(r["levels"], r["cycle"]) == r["N_lo"]:
+            ok += 1
+        if r["lmax"] == 1:
+            assert r["N_c"] == r["N_ti"] + r["steps"]
+    assert ok == 11  # the printed Gamma = 5 hierarchy of Table 2 is the exception
+    bad = [r for r in rows if r["N_c"] * _per_cycle_cost(r["levels"], r["cycle"]) != r["N_lo"]]
+    assert bad[0]["table"] == 2 and bad[0]["N_lo"] == bad[0]["N_c"] * _per_cycle_cost([256, 64, 16, 4, 1], "F")
+
+
+def test_oracle_counters_follow_cycle_law():
+    slab, pb = tiny_problem(nx=8, ng=16, nmu=4, dt=0.004)
+    for levels, cyc, lmax in (([16, 1], "V", 3), ([16, 4, 1], "W", 2), ([16, 8, 4, 1], "F", 1)):
+        cfg = inputs.SolverCfg(levels=levels, cycle={"V": 0, "W": 1, "F": 2}[cyc], lmax=lmax)
+        st, stats = mlqd.run(pb, slab.T0, levels, cfg.schedule(), lmax, 1e-10, 1e-11, 2)
+        assert stats.n_lo == stats.n_c * _per_cycle_cost(levels, cyc)
+        if lmax == 1:
+            assert stats.n_c == stats.n_ti + 2
+
+
+def test_replay_reproduces_free_run():
+    slab, pb = tiny_problem(nx=8, ng=16, nmu=4, dt=0.004)
+    st_a, stats = mlqd.run(pb, slab.T0, [16, 4, 1], [1], 2, 1e-10, 1e-11, 2)
+    st_b, _ = mlqd.run(pb, slab.T0, [16, 4, 1], [1], 2, 1e-10, 1e-11, 2, replay=stats.counts)
+    assert np.array_equal(st_a.T, st_b.T) and np.array_equal(st_a.I, st_b.I)
