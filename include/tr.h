@@ -1,0 +1,254 @@
+/*
+ * tr.h - C ABI of the MI355X (gfx950) library for the multilevel quasidiffusion
+ * (MLQD) method with multigrid in photon frequency for time-dependent
+ * multigroup thermal radiative transfer in 1-D slabs (Anistratov, arXiv
+ * 2011.05427).
+ *
+ * Conventions (every entry point):
+ *  - Arrays named in a call are DEVICE pointers owned by the caller unless a
+ *    comment says "host".  The library never frees caller memory.
+ *  - Work is enqueued asynchronously on the given stream (0 = default stream);
+ *    the caller synchronises.  tr_step synchronises internally once per
+ *    transport iteration to read a convergence flag.
+ *  - Every call returns TR_OK (0) or a negative TR_E* code; tr_error_string()
+ *    gives a message.  Nothing throws across the ABI.
+ *  - One context serves one stream at a time; calls on one context are not
+ *    thread-safe.
+ *  - Floating point is IEEE binary64 throughout.
+ *
+ * Batched layout ("pooled" arrays).  A context holds n_slab independent slab
+ * problems.  Every per-slab array is stored slab after slab in creation order;
+ * tr_layout() returns, per slab, the element offset of its part in each kind
+ * of pooled array.  Within one slab (nx cells, ng groups, nmu directions, cell
+ * i, edge e = 0..nx at x_edges[e], group g, direction m, corner k = 0 (left,
+ * x_{i-1/2}) / 1 (right, x_{i+1/2})):
+ *     cell     [nx]                T, grey E
+ *     I        [ng][nmu][nx][2]    corner intensities      (kind TR_K_I)
+ *     gi       [ng][nx]            kappa, B, E_g, f        (kind TR_K_GI)
+ *     ge       [ng][nx+1]          F_g at edges            (kind TR_K_GE)
+ *     g2       [ng][2]             boundary values (x=0, x=X)
+ *     level-l  [n_l][nx], [n_l][nx+1], [n_l][2] for frequency level l
+ *              (level 0 is the fine grid, the last level is grey, n = 1).
+ */
+#ifndef TR_H
+#define TR_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TR_OK = 0,
+  TR_EINVAL = -1,  /* bad argument or shape */
+  TR_ENOMEM = -2,  /* device allocation failed */
+  TR_EHIP = -3,    /* a HIP runtime call failed */
+  TR_ENOCONV = -4, /* a slab exceeded max_outer transport iterations */
+  TR_ENAN = -5     /* a non-finite temperature or energy appeared */
+};
+
+enum { TR_CYCLE_V = 0, TR_CYCLE_W = 1, TR_CYCLE_F = 2 };
+enum { TR_MAX_LEVELS = 8 };
+
+/* Array kinds for tr_layout(). */
+enum {
+  TR_K_CELL = 0, /* [nx]               */
+  TR_K_EDGE = 1, /* [nx+1]             */
+  TR_K_I = 2,    /* [ng][nmu][nx][2]   */
+  TR_K_GI = 3,   /* [ng][nx]           */
+  TR_K_GE = 4,   /* [ng][nx+1]         */
+  TR_K_G2 = 5,   /* [ng][2]            */
+  TR_K_G = 6,    /* [ng]               */
+  TR_K_LEV_PI = 8,  /* + level: [n_l][nx]   */
+  TR_K_LEV_PE = 16, /* + level: [n_l][nx+1] */
+  TR_K_LEV_P2 = 24  /* + level: [n_l][2]    */
+};
+
+/*
+ * One slab problem (all pointers HOST, copied at tr_create).  Paper Sec. 2
+ * (Eqs. rt-nu, eb-nu, rt-nu-bc and the multigroup Eqs. rt, rt-bc, rt-ic) with
+ * the opacity law kappa_g(T) = C_cell / nu_c^3 (1 - exp(-nu_c / T)) at the
+ * group centre nu_c (sigma_E = sigma_B = sigma_R = kappa_g) and eps = cv T.
+ */
+typedef struct tr_problem {
+  int nx;                  /* cells, >= 2 */
+  int ng;                  /* fine groups, >= 1 */
+  int nmu;                 /* directions, even, mu ascending, symmetric */
+  const double *x_edges;   /* [nx+1] increasing */
+  const double *nu_edges;  /* [ng+1] group edges for the Planck integrals;
+                              nu_edges[0] may be 0 and nu_edges[ng] +inf */
+  const double *nu_center; /* [ng] opacity evaluation point of each group */
+  const double *mu;        /* [nmu] direction cosines, ascending */
+  const double *w;         /* [nmu] quadrature weights (sum 2) */
+  const double *C_cell;    /* [nx] opacity constant per cell */
+  double T_left, T_right;  /* isotropic incoming Planck radiation at this
+                              temperature at x=0 / x=X; <= 0 means vacuum */
+  double cv;               /* material heat capacity, eps = cv T */
+  double dt;               /* time step */
+  double c, aR;            /* speed of light, radiation constant */
+  int n_levels;            /* frequency grids incl. fine and grey, 2..8 */
+  const int *level_ng;     /* [n_levels] groups per grid: ng, ..., 1; each
+                              divides the previous (uniform coarsening) */
+} tr_problem;
+
+/* Iteration settings shared by all slabs of a context (paper Alg. 3). */
+typedef struct tr_solver_cfg {
+  int cycle;        /* TR_CYCLE_V / W / F: schedule of grids visited after each
+                       grey solve (V none, W the middle grid, F every
+                       intermediate grid from coarse to fine) */
+  int lmax;         /* maximum cycles per transport iteration (>= 1) */
+  double eps;       /* outer tolerance on T and grey E (relative, inf-norm) */
+  double eps_inner; /* inner tolerance */
+  int max_outer;    /* transport iterations before TR_ENOCONV */
+  int secant;       /* 1: diagonal secant Frechet derivative of the grey
+                       sigma_E (Eq. f-derivative-d); 0: D = 0 */
+} tr_solver_cfg;
+
+typedef struct tr_ctx tr_ctx;
+
+/* Creates a context for n_slab problems (host arrays) and allocates its
+ * device workspace.  Errors: TR_EINVAL (shapes, levels not dividing, nmu odd,
+ * non-symmetric mu), TR_ENOMEM, TR_EHIP. */
+int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver_cfg *cfg);
+int tr_destroy(tr_ctx *ctx);
+const char *tr_error_string(int code);
+
+/* Element offset of slab `slab` inside pooled arrays of `kind`, and the total
+ * element count of that kind (host outputs).  Errors: TR_EINVAL. */
+int tr_layout(const tr_ctx *ctx, int kind, int slab, long long *offset, long long *total);
+
+/* Overrides the isotropic incoming intensity per group of one slab (host
+ * arrays [ng]; NULL keeps the current side). */
+int tr_set_incoming(tr_ctx *ctx, int slab, const double *inc_left, const double *inc_right);
+
+/*
+ * A1 (paper Sec. 2 opacity/Planck; config law).  For every slab, cell and
+ * group: kappa[g][i] = kappa_g(T_i), B[g][i] = group Planck integral
+ *   B_g = (aR c T^4 / 2) (15/pi^4) int_{nu_g/T}^{nu_{g+1}/T} t^3/(e^t-1) dt
+ * and dS[i] = d/dT sum_g 2 kappa_g B_g at T_i.
+ * T: cell (pooled); kappa, B: gi (pooled); dS: cell (pooled).
+ */
+int tr_opacity(tr_ctx *ctx, const double *T, double *kappa, double *B, double *dS, hipStream_t stream);
+
+/*
+ * A2 + partial A3: one transport sweep (paper Sec. 5: implicit Euler, simple
+ * corner balance) of every (group, direction) of every slab with opacity and
+ * Planck tables kappa, B (gi), previous-time-level corner intensities I_prev
+ * (I), writing I_out (I) and the half-range partial moments
+ *   mom[h][g][i][2] = (sum_{m in h} w Ibar, sum_{m in h} w mu^2 Ibar),
+ *   bnd[h][g][3]    = outgoing edge sums (sum w psi, sum w mu psi,
+ *                     sum w mu^2 psi) of half h at its outflow boundary,
+ * h = 0 for mu > 0, 1 for mu < 0.  mom has 4 * gi elements per slab, bnd
+ * 6 * ng (offsets: 4 * gi offset, 6 * g offset).  I_prev and I_out must not
+ * alias.
+ */
+int tr_sweep(tr_ctx *ctx, const double *kappa, const double *B, const double *I_prev, double *I_out,
+             double *mom, double *bnd, hipStream_t stream);
+
+/*
+ * A3: QD factors from sweep partials (paper Eqs. f_g, c_g, mloqd-bcs):
+ * f[g][i] = chi/phi (gi), fbnd[g][2] edge factors, C[g][2] = (C^-, C^+),
+ * Phi[g][2] = F_in - c C E_in (g2).  Isotropic quadrature values replace
+ * 0/0 ratios.
+ */
+int tr_moments(tr_ctx *ctx, const double *mom, const double *bnd, double *f, double *fbnd, double *C,
+               double *Phi, hipStream_t stream);
+
+/* Coefficients of one frequency level (all device, pooled level-l arrays, or
+ * for level 0 the fine-grid tables). */
+typedef struct tr_lo_coeffs {
+  /* level 0 (fine): */
+  const double *kappa, *B;   /* gi, tables at the level's temperature */
+  const double *f, *fbnd;    /* gi, g2 QD factors */
+  /* levels >= 1: */
+  const double *sigE, *emis; /* [n][nx] absorption, emission e = sum 2 kappa B */
+  const double *a, *b;       /* [n][nx+1] coefficients of E right / left of edge */
+  const double *sigR;        /* [n][nx+1] edge opacity */
+  /* all levels: */
+  const double *C, *Phi;     /* [n][2] boundary factors / inhomogeneous part */
+  const double *Eold, *Fold; /* [n][nx], [n][nx+1] previous time level */
+} tr_lo_coeffs;
+
+typedef struct tr_lo_fields {
+  double *E;    /* [n][nx]   */
+  double *F;    /* [n][nx+1] */
+  double *Ebnd; /* [n][2]    */
+} tr_lo_fields;
+
+/* Writable level coefficients (output of tr_restrict). */
+typedef struct tr_lo_out {
+  double *sigE, *emis, *a, *b, *sigR, *C, *Phi, *Eold, *Fold;
+  double *Esum; /* [n][nx] sum of the finer E over each group (E* of the MEB) */
+} tr_lo_out;
+
+/*
+ * A4 / A6: discrete LOQD equations of every group of level `level` (paper
+ * Eqs. mloqd1-d, mloqd2-d; coarse Eqs. mloqd1-d-gamma, mloqd2-d-gamma; the
+ * boundary conditions Eq. mloqd-bcs closed on boundary half cells).  The
+ * tridiagonal system in (E_{1/2}, E_1..E_nx, E_{nx+1/2}) is solved per group.
+ */
+int tr_lo_solve(tr_ctx *ctx, int level, const tr_lo_coeffs *in, const tr_lo_fields *out, hipStream_t stream);
+
+/*
+ * A5: restriction of level `from` (coefficients + its solution) to level
+ * `to` > from (paper Eqs. coeff-gamma, g-notation, eta-gamma, coeff-Gamma,
+ * eta-Gamma): E-weighted sigma_E, right/left E-weighted a, b, |F|-weighted
+ * sigma_R with the upwind-split compensation eta, E_boundary-weighted C, and
+ * sums of emission, Phi and old-time values.  For from = 0 the fine
+ * coefficients come from kappa/B (at the stage temperature) and f, fbnd.
+ */
+int tr_restrict(tr_ctx *ctx, int from, int to, const tr_lo_coeffs *in, const tr_lo_fields *sol,
+                const tr_lo_out *out, hipStream_t stream);
+
+/*
+ * A7: grey LOQD + MEB, one Newton iteration (paper Eq. eb-Gamma-d, Newton
+ * with the diagonal Frechet derivative D of the grey sigma_E, Eq.
+ * f-derivative-d).  grey: level-last coefficients; Tstar: stage temperature;
+ * Told: previous time level; dS: d/dT sum 2 kappa B at Tstar; Estar: stage
+ * spectrum total; D: secant derivative (cell arrays).  Writes T_out = Tstar +
+ * alpha + beta E (floored at Tstar/2) and the grey fields.
+ */
+int tr_grey_solve(tr_ctx *ctx, const tr_lo_coeffs *grey, const double *Tstar, const double *Told,
+                  const double *dS, const double *Estar, const double *D, double *T_out,
+                  const tr_lo_fields *out, hipStream_t stream);
+
+/* Caller-owned step state (device, pooled). */
+typedef struct tr_state {
+  double *T;       /* cell: material temperature */
+  const double *I_prev; /* I: corner intensities of the previous time level */
+  double *I_out;   /* I: written by every sweep; holds I^j after the step */
+  double *E, *F, *Ebnd; /* gi, ge, g2: fine LO solution (old-time values in,
+                           new values out) */
+  double *f, *fbnd, *C; /* gi, g2, g2: QD factors of the last sweep */
+  double *Egrey;   /* cell: grey energy density of the last grey solve */
+} tr_state;
+
+/* Fills a state with the initial condition T = T0, I^0 = B_g(T0) in every
+ * corner and direction, E = (1/c) sum w I^0, F = 0 and the factors of I^0
+ * (written to I_out; the caller uses I_out as I_prev of the first step). */
+int tr_state_init(tr_ctx *ctx, const tr_state *st, double T0, hipStream_t stream);
+
+typedef struct tr_stats {
+  long long n_ti;  /* transport sweeps */
+  long long n_c;   /* cycles */
+  long long n_lo;  /* group LO solves (grey counted 1) */
+  long long n_floor; /* temperature floor activations */
+  int n_outer;     /* transport iterations of the last step incl. s = 0 */
+  int cycles[64];  /* cycles per transport iteration of the last step */
+} tr_stats;
+
+/*
+ * A8: one backward-Euler step of paper Alg. 3 for every slab (V/W/F cycles,
+ * grid skipping, inner/outer infinity-norm tests, lmax cap).  replay (host,
+ * nullable): per slab, a row of 64 ints = cycles per transport iteration
+ * (0 terminates), executed instead of the convergence tests.  stats (host,
+ * nullable): [n_slab] counters accumulated over calls.
+ * Errors: TR_ENOCONV, TR_ENAN, TR_EHIP.
+ */
+int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TR_H */

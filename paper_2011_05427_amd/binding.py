@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libtr.so (argument marshalling only).
+
+PyTorch is used for device memory and the current stream; every computation
+runs in the library's HIP kernels.  There is no fallback: if the library is not
+built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtr.so")
+
+TR_OK, TR_EINVAL, TR_ENOMEM, TR_EHIP, TR_ENOCONV, TR_ENAN = 0, -1, -2, -3, -4, -5
+TR_K_CELL, TR_K_EDGE, TR_K_I, TR_K_GI, TR_K_GE, TR_K_G2, TR_K_G = 0, 1, 2, 3, 4, 5, 6
+TR_K_LEV_PI, TR_K_LEV_PE, TR_K_LEV_P2 = 8, 16, 24
+MAXOUT = 64
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class TrProblem(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ng", C.c_int), ("nmu", C.c_int),
+                ("x_edges", _dp), ("nu_edges", _dp), ("nu_center", _dp), ("mu", _dp), ("w", _dp),
+                ("C_cell", _dp), ("T_left", C.c_double), ("T_right", C.c_double), ("cv", C.c_double),
+                ("dt", C.c_double), ("c", C.c_double), ("aR", C.c_double), ("n_levels", C.c_int),
+                ("level_ng", _ip)]
+
+
+class TrSolverCfg(C.Structure):
+    _fields_ = [("cycle", C.c_int), ("lmax", C.c_int), ("eps", C.c_double), ("eps_inner", C.c_double),
+                ("max_outer", C.c_int), ("secant", C.c_int)]
+
+
+class TrLoCoeffs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in
+                ("kappa", "B", "f", "fbnd", "sigE", "emis", "a", "b", "sigR", "C", "Phi", "Eold", "Fold")]
+
+
+class TrLoFields(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("E", "F", "Ebnd")]
+
+
+class TrLoOut(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in
+                ("sigE", "emis", "a", "b", "sigR", "C", "Phi", "Eold", "Fold", "Esum")]
+
+
+class TrState(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in
+                ("T", "I_prev", "I_out", "E", "F", "Ebnd", "f", "fbnd", "C", "Egrey")]
+
+
+class TrStats(C.Structure):
+    _fields_ = [("n_ti", C.c_longlong), ("n_c", C.c_longlong), ("n_lo", C.c_longlong),
+                ("n_floor", C.c_longlong), ("n_outer", C.c_int), ("cycles", C.c_int * 64)]
+
+
+EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_incoming", "tr_opacity",
+           "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step"]
+
+_lib = None
+
+
+class TrError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {load().tr_error_string(code).decode()} ({code})")
+
+
+def load():
+    """Loads libtr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2011_05427_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.tr_create.argtypes = [C.POINTER(vp), C.POINTER(TrProblem), C.c_int, C.POINTER(TrSolverCfg)]
+    lib.tr_destroy.argtypes = [vp]
+    lib.tr_error_string.argtypes = [C.c_int]
+    lib.tr_error_string.restype = C.c_char_p
+    lib.tr_layout.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
+    lib.tr_set_incoming.argtypes = [vp, C.c_int, _dp, _dp]
+    lib.tr_opacity.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tr_sweep.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.tr_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.tr_lo_solve.argtypes = [vp, C.c_int, C.POINTER(TrLoCoeffs), C.POINTER(TrLoFields), vp]
+    lib.tr_restrict.argtypes = [vp, C.c_int, C.c_int, C.POINTER(TrLoCoeffs), C.POINTER(TrLoFields),
+                                C.POINTER(TrLoOut), vp]
+    lib.tr_grey_solve.argtypes = [vp, C.POINTER(TrLoCoeffs), vp, vp, vp, vp, vp, vp, C.POINTER(TrLoFields), vp]
+    lib.tr_state_init.argtypes = [vp, C.POINTER(TrState), C.c_double, vp]
+    lib.tr_step.argtypes = [vp, C.POINTER(TrState), _ip, C.POINTER(TrStats), vp]
+    for name in EXPORTS:
+        if name not in ("tr_error_string",):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code, what):
+    if code != TR_OK:
+        raise TrError(code, what)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _as_dp(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class Solver:
+    """One context over a batch of slab problems.
+
+    slabs: sequence of ``inputs.Slab``; levels: per-slab list of groups per
+    frequency grid (fine first, grey last); cfg: ``inputs.SolverCfg``."""
+
+    def __init__(self, slabs: Sequence, levels: Sequence[Sequence[int]], cfg):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the MLQD library needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.lib = load()
+        self.slabs = list(slabs)
+        self._keep = []
+        probs = (TrProblem * len(self.slabs))()
+        for k, (s, lv) in enumerate(zip(self.slabs, levels)):
+            arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in
+                    (s.x_edges, s.nu_edges, s.nu_center, s.mu, s.w, s.C_cell)]
+            lvl = np.ascontiguousarray(lv, dtype=np.int32)
+            self._keep += arrs + [lvl]
+            p = probs[k]
+            p.nx, p.ng, p.nmu = s.nx, s.ng, s.nmu
+            p.x_edges, p.nu_edges, p.nu_center, p.mu, p.w, p.C_cell = [_as_dp(a) for a in arrs]
+            p.T_left, p.T_right, p.cv, p.dt, p.c, p.aR = s.T_left, s.T_right, s.cv, s.dt, s.c, s.aR
+            p.n_levels = len(lv)
+            p.level_ng = lvl.ctypes.data_as(_ip)
+        self.levels = [list(lv) for lv in levels]
+        self.nlev = len(self.levels[0])
+        c = TrSolverCfg(cycle=cfg.cycle, lmax=cfg.lmax, eps=cfg.eps, eps_inner=cfg.eps_inner,
+                        max_outer=cfg.max_outer, secant=1 if cfg.secant else 0)
+        self._ctx = C.c_void_p()
+        _check(self.lib.tr_create(C.byref(self._ctx), probs, len(self.slabs), C.byref(c)), "tr_create")
+        self.n = len(self.slabs)
+
+    def close(self):
+        if self._ctx:
+            self.lib.tr_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- layout -----------------------------------------------------------
+    def layout(self, kind: int, slab: int = 0):
+        off, tot = C.c_longlong(), C.c_longlong()
+        _check(self.lib.tr_layout(self._ctx, kind, slab, C.byref(off), C.byref(tot)), "tr_layout")
+        return off.value, tot.value
+
+    def total(self, kind: int) -> int:
+        return self.layout(kind, 0)[1]
+
+    def offsets(self, kind: int) -> List[int]:
+        return [self.layout(kind, s)[0] for s in range(self.n)]
+
+    def empty(self, kind: int, mult: int = 1):
+        return self.torch.zeros(self.total(kind) * mult, dtype=self.torch.float64, device="cuda")
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    # -- stages -----------------------------------------------------------
+    def set_incoming(self, slab: int, left=None, right=None):
+        l = None if left is None else np.ascontiguousarray(left, dtype=np.float64)
+        r = None if right is None else np.ascontiguousarray(right, dtype=np.float64)
+        _check(self.lib.tr_set_incoming(self._ctx, slab, None if l is None else _as_dp(l),
+                                        None if r is None else _as_dp(r)), "tr_set_incoming")
+
+    def opacity(self, T, kappa, B, dS=None):
+        _check(self.lib.tr_opacity(self._ctx, _ptr(T), _ptr(kappa), _ptr(B), _ptr(dS), self._stream()),
+               "tr_opacity")
+
+    def sweep(self, kappa, B, I_prev, I_out, mom, bnd):
+        _check(self.lib.tr_sweep(self._ctx, _ptr(kappa), _ptr(B), _ptr(I_prev), _ptr(I_out), _ptr(mom),
+                                 _ptr(bnd), self._stream()), "tr_sweep")
+
+    def moments(self, mom, bnd, f, fbnd, Cb, Phi):
+        _check(self.lib.tr_moments(self._ctx, _ptr(mom), _ptr(bnd), _ptr(f), _ptr(fbnd), _ptr(Cb), _ptr(Phi),
+                                   self._stream()), "tr_moments")
+
+    @staticmethod
+    def _coeffs(d: Dict) -> TrLoCoeffs:
+        c = TrLoCoeffs()
+        for name, _ in TrLoCoeffs._fields_:
+            setattr(c, name, _ptr(d.get(name)))
+        return c
+
+    def lo_solve(self, level: int, coeffs: Dict, E, F, Ebnd):
+        f = TrLoFields(E=_ptr(E), F=_ptr(F), Ebnd=_ptr(Ebnd))
+        _check(self.lib.tr_lo_solve(self._ctx, level, C.byref(self._coeffs(coeffs)), C.byref(f), self._stream()),
+               "tr_lo_solve")
+
+    def restrict(self, frm: int, to: int, coeffs: Dict, sol: Dict, out: Dict):
+        s = TrLoFields(E=_ptr(sol["E"]), F=_ptr(sol["F"]), Ebnd=_ptr(sol["Ebnd"]))
+        o = TrLoOut()
+        for name, _ in TrLoOut._fields_:
+            setattr(o, name, _ptr(out[name]))
+        _check(self.lib.tr_restrict(self._ctx, frm, to, C.byref(self._coeffs(coeffs)), C.byref(s), C.byref(o),
+                                    self._stream()), "tr_restrict")
+
+    def grey_solve(self, grey: Dict, Tstar, Told, dS, Estar, D, T_out, E, F, Ebnd):
+        f = TrLoFields(E=_ptr(E), F=_ptr(F), Ebnd=_ptr(Ebnd))
+        _check(self.lib.tr_grey_solve(self._ctx, C.byref(self._coeffs(grey)), _ptr(Tstar), _ptr(Told), _ptr(dS),
+                                      _ptr(Estar), _ptr(D), _ptr(T_out), C.byref(f), self._stream()),
+               "tr_grey_solve")
+
+    # -- state and steps ----------------------------------------------------
+    def new_state(self) -> Dict:
+        e = self.empty
+        return dict(T=e(TR_K_CELL), I_prev=e(TR_K_I), I_out=e(TR_K_I), E=e(TR_K_GI), F=e(TR_K_GE),
+                    Ebnd=e(TR_K_G2), f=e(TR_K_GI), fbnd=e(TR_K_G2), C=e(TR_K_G2), Egrey=e(TR_K_CELL))
+
+    @staticmethod
+    def _state(st: Dict) -> TrState:
+        s = TrState()
+        for name, _ in TrState._fields_:
+            setattr(s, name, _ptr(st[name]))
+        return s
+
+    def state_init(self, st: Dict, T0: float):
+        """Initial condition into st; afterwards I_prev holds I^0."""
+        _check(self.lib.tr_state_init(self._ctx, C.byref(self._state(st)), float(T0), self._stream()),
+               "tr_state_init")
+        st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
+
+    def step(self, st: Dict, replay: Optional[Sequence[Sequence[int]]] = None, stats=None, swap: bool = True):
+        """One time step of every slab; returns the per-slab TrStats array.
+        replay: per slab, cycles per transport iteration."""
+        if stats is None:
+            stats = (TrStats * self.n)()
+        rp = None
+        if replay is not None:
+            arr = np.zeros((self.n, MAXOUT), dtype=np.int32)
+            for k, row in enumerate(replay):
+                arr[k, :len(row)] = row
+            self._replay = arr
+            rp = arr.ctypes.data_as(_ip)
+        code = self.lib.tr_step(self._ctx, C.byref(self._state(st)), rp, stats, self._stream())
+        _check(code, "tr_step")
+        if swap:
+            st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
+        return stats

@@ -1,0 +1,720 @@
+// C ABI of the MLQD library: context set-up, pooled layout, stage entry points
+// and the host orchestration of one time step (paper Alg. 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "tr.h"
+#include "tr_kernels.h"
+
+#define TR_NHEAD 40
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct tr_ctx {
+  int nslab = 0;
+  tr_solver_cfg cfg{};
+  int nlev = 0;
+  std::vector<int> sched;
+  int lo_threads = 64;
+  std::vector<SlabDev> hs;  // host copies of the slab descriptors
+  std::vector<double> h_inc;
+  // totals per kind
+  long long n_cell = 0, n_edge = 0, n_I = 0, n_gi = 0, n_ge = 0, n_g = 0, n_nu = 0, n_mu = 0, n_chunk = 0, n_red = 0;
+  long long n_lpi[TR_MAXLEV] = {}, n_lpe[TR_MAXLEV] = {}, n_lp2[TR_MAXLEV] = {};
+  std::vector<void *> allocs;
+  SlabDev *d_sd = nullptr;
+  ProbDev pd{};
+  double *d_inc = nullptr;
+  // workspace
+  double *kappa = nullptr, *B = nullptr, *dSpart = nullptr, *mom = nullptr, *bnd = nullptr, *Phi = nullptr;
+  double *Eold = nullptr, *Fold = nullptr, *red = nullptr;
+  double *Told = nullptr, *Ts = nullptr, *Tcyc = nullptr, *Tstar = nullptr, *Tprev = nullptr, *sigprev = nullptr;
+  double *Ecyc = nullptr, *Es = nullptr;
+  struct Lev {
+    double *sigE, *emis, *a, *b, *sigR, *C, *Phi, *Eold, *Fold, *E, *F, *Ebnd, *Esum;
+  } lev[TR_MAXLEV]{};
+  Ctl *d_ctl = nullptr;
+  int *d_cost = nullptr;
+  int *d_count = nullptr;
+  int *h_count = nullptr;  // pinned
+  // work tables
+  Table t_opac{}, t_cell{}, t_sweep{}, t_gi{}, t_g{}, t_grey{};
+  Table t_lo[TR_MAXLEV]{};
+  std::map<std::pair<int, int>, RestrictTables> t_red;
+};
+
+namespace {
+
+int hip_err(hipError_t e) { return e == hipSuccess ? TR_OK : TR_EHIP; }
+
+template <class T>
+int dalloc(tr_ctx *c, T **p, long long n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  void *q = nullptr;
+  if (hipMalloc(&q, sizeof(T) * (size_t)n) != hipSuccess) return TR_ENOMEM;
+  c->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return TR_OK;
+}
+
+int upload_table(tr_ctx *c, const std::vector<Item> &h, Table &t) {
+  t.n = (int)h.size();
+  t.d = nullptr;
+  if (h.empty()) return TR_OK;
+  Item *d = nullptr;
+  int rc = dalloc(c, &d, (long long)h.size());
+  if (rc) return rc;
+  if (hipMemcpy(d, h.data(), sizeof(Item) * h.size(), hipMemcpyHostToDevice) != hipSuccess) return TR_EHIP;
+  t.d = d;
+  return TR_OK;
+}
+
+// Head coefficients c_k = B_k / (k! (k + 3)) of int_0^x t^3/(e^t - 1) dt.
+// Odd Bernoulli numbers vanish beyond B_1 = -1/2; the even ones follow from
+// B_2j / (2j)! = (-1)^(j+1) 2 zeta(2j) / (2 pi)^(2j), with zeta(2) = pi^2/6
+// and zeta(s >= 4) summed directly with an Euler-Maclaurin tail.
+void head_coefficients(double *out) {
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < TR_NHEAD; ++k) out[k] = 0.0;
+  out[0] = 1.0 / 3.0;
+  out[1] = -0.5 / 4.0;
+  for (int k = 2; k < TR_NHEAD; k += 2) {
+    const int s = k;
+    double zeta;
+    if (s == 2) {
+      zeta = pi * pi / 6.0;
+    } else {
+      const int N = 64;
+      double acc = 0.0;
+      for (int n = N - 1; n >= 1; --n) acc += std::pow((double)n, -s);
+      const double Nd = N;
+      acc += std::pow(Nd, 1.0 - s) / (s - 1) + 0.5 * std::pow(Nd, -s) + s * std::pow(Nd, -s - 1.0) / 12.0 -
+             (double)s * (s + 1) * (s + 2) * std::pow(Nd, -s - 3.0) / 720.0;
+      zeta = acc;
+    }
+    const int j = k / 2;
+    const double sign = (j % 2 == 1) ? 1.0 : -1.0;
+    out[k] = sign * 2.0 * zeta / std::pow(2.0 * pi, k) / (k + 3);
+  }
+}
+
+std::vector<int> schedule_for(int cycle, int nlev) {
+  std::vector<int> s;
+  if (cycle == TR_CYCLE_V || nlev <= 2) return s;
+  if (cycle == TR_CYCLE_W) {
+    s.push_back(1);
+    return s;
+  }
+  for (int l = nlev - 2; l >= 1; --l) s.push_back(l);
+  return s;
+}
+
+int build_restrict_tables(tr_ctx *c, int from, int to) {
+  auto key = std::make_pair(from, to);
+  if (c->t_red.count(key)) return TR_OK;
+  std::vector<Item> single, part, fin;
+  for (int s = 0; s < c->nslab; ++s) {
+    const SlabDev &S = c->hs[s];
+    const int ne = S.nx + 1;
+    const int nf = S.lev_ng[from], nt = S.lev_ng[to];
+    const int r = nf / nt;
+    if (r <= 64) {
+      for (int st = 0; st < nt * ne; st += 256) single.push_back({s, st});
+    } else {
+      const int nchunk = nf / 64;
+      for (int st = 0; st < nchunk * ne; st += 256) part.push_back({s, st});
+      for (int st = 0; st < nt * ne; st += 256) fin.push_back({s, st});
+    }
+  }
+  RestrictTables rt{};
+  int rc = upload_table(c, single, rt.single);
+  if (!rc) rc = upload_table(c, part, rt.part);
+  if (!rc) rc = upload_table(c, fin, rt.fin);
+  if (rc) return rc;
+  c->t_red[key] = rt;
+  return TR_OK;
+}
+
+LaunchEnv env_of(const tr_ctx *c, hipStream_t st) { return LaunchEnv{c->d_sd, c->pd, st}; }
+
+LoIn fine_in(const tr_ctx *c, const double *kappa, const double *B, const double *f, const double *fbnd,
+             const double *C, const double *Phi, const double *Eold, const double *Fold) {
+  LoIn in{};
+  in.kappa = kappa;
+  in.B = B;
+  in.f = f;
+  in.fbnd = fbnd;
+  in.C = C;
+  in.Phi = Phi;
+  in.Eold = Eold;
+  in.Fold = Fold;
+  return in;
+}
+
+LoIn level_in(const tr_ctx *c, int l) {
+  LoIn in{};
+  const auto &L = c->lev[l];
+  in.sigE = L.sigE;
+  in.emis = L.emis;
+  in.a = L.a;
+  in.b = L.b;
+  in.sigR = L.sigR;
+  in.C = L.C;
+  in.Phi = L.Phi;
+  in.Eold = L.Eold;
+  in.Fold = L.Fold;
+  return in;
+}
+
+LoSol level_sol(const tr_ctx *c, int l) {
+  const auto &L = c->lev[l];
+  return LoSol{L.E, L.F, L.Ebnd};
+}
+
+LoOut level_out(const tr_ctx *c, int l) {
+  const auto &L = c->lev[l];
+  return LoOut{L.sigE, L.emis, L.a, L.b, L.sigR, L.C, L.Phi, L.Eold, L.Fold, L.Esum};
+}
+
+LoIn coeffs_in(const tr_lo_coeffs *in) {
+  LoIn r{};
+  r.kappa = in->kappa;
+  r.B = in->B;
+  r.f = in->f;
+  r.fbnd = in->fbnd;
+  r.sigE = in->sigE;
+  r.emis = in->emis;
+  r.a = in->a;
+  r.b = in->b;
+  r.sigR = in->sigR;
+  r.C = in->C;
+  r.Phi = in->Phi;
+  r.Eold = in->Eold;
+  r.Fold = in->Fold;
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tr_error_string(int code) {
+  switch (code) {
+    case TR_OK: return "ok";
+    case TR_EINVAL: return "invalid argument or shape";
+    case TR_ENOMEM: return "device allocation failed";
+    case TR_EHIP: return "HIP runtime call failed";
+    case TR_ENOCONV: return "transport iterations did not converge within max_outer";
+    case TR_ENAN: return "non-finite temperature or energy density";
+  }
+  return "unknown error";
+}
+
+int tr_destroy(tr_ctx *c) {
+  if (!c) return TR_OK;
+  for (void *p : c->allocs) (void)hipFree(p);
+  if (c->h_count) (void)hipHostFree(c->h_count);
+  delete c;
+  return TR_OK;
+}
+
+int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver_cfg *cfg) {
+  if (!out || !probs || n_slab <= 0 || !cfg) return TR_EINVAL;
+  *out = nullptr;
+  if (cfg->lmax < 1 || cfg->lmax > TR_MAXOUT || cfg->max_outer < 1 || cfg->max_outer >= TR_MAXOUT ||
+      cfg->cycle < 0 || cfg->cycle > 2)
+    return TR_EINVAL;
+  const int nlev = probs[0].n_levels;
+  if (nlev < 2 || nlev > TR_MAXLEV) return TR_EINVAL;
+  int nx_max = 0;
+  for (int s = 0; s < n_slab; ++s) {
+    const tr_problem &P = probs[s];
+    if (P.nx < 2 || P.ng < 1 || P.nmu < 2 || (P.nmu & 1) || P.nmu > 64 || P.n_levels != nlev || !P.level_ng ||
+        !P.x_edges || !P.nu_edges || !P.nu_center || !P.mu || !P.w || !P.C_cell)
+      return TR_EINVAL;
+    if (!(P.dt > 0) || !(P.cv > 0) || !(P.c > 0) || !(P.aR > 0)) return TR_EINVAL;
+    if (P.level_ng[0] != P.ng || P.level_ng[nlev - 1] != 1) return TR_EINVAL;
+    for (int l = 1; l < nlev; ++l) {
+      const int a = P.level_ng[l - 1], b = P.level_ng[l];
+      if (b < 1 || a % b) return TR_EINVAL;
+    }
+    // restriction chunks: every restriction ratio used is <= 64 or a multiple of 64
+    for (int l = 1; l < nlev; ++l) {
+      const int r0 = P.ng / P.level_ng[l];
+      if (r0 > 64 && r0 % 64) return TR_EINVAL;
+      const int r1 = P.level_ng[l];  // level l -> grey
+      if (l < nlev - 1 && r1 > 64 && r1 % 64) return TR_EINVAL;
+    }
+    for (int i = 0; i < P.nx; ++i)
+      if (!(P.x_edges[i + 1] > P.x_edges[i])) return TR_EINVAL;
+    for (int m = 0; m < P.nmu; ++m) {
+      if (m > 0 && !(P.mu[m] > P.mu[m - 1])) return TR_EINVAL;
+      if (std::fabs(P.mu[m] + P.mu[P.nmu - 1 - m]) > 1e-14) return TR_EINVAL;
+    }
+    nx_max = std::max(nx_max, P.nx);
+  }
+  const int rows = nx_max + 2;
+  int T = ((rows + TR_LO_K - 1) / TR_LO_K + 63) / 64 * 64;
+  if (T > 256) return TR_EINVAL;  // nx <= 2046
+
+  tr_ctx *c = new (std::nothrow) tr_ctx();
+  if (!c) return TR_ENOMEM;
+  c->nslab = n_slab;
+  c->cfg = *cfg;
+  c->nlev = nlev;
+  c->sched = schedule_for(cfg->cycle, nlev);
+  c->lo_threads = T;
+  c->hs.resize(n_slab);
+
+  std::vector<double> h_dx, h_C, h_mu, h_w, h_nue, h_nuc;
+  for (int s = 0; s < n_slab; ++s) {
+    const tr_problem &P = probs[s];
+    SlabDev &S = c->hs[s];
+    std::memset(&S, 0, sizeof(S));
+    S.nx = P.nx;
+    S.ng = P.ng;
+    S.nmu = P.nmu;
+    S.nlev = nlev;
+    for (int l = 0; l < nlev; ++l) S.lev_ng[l] = P.level_ng[l];
+    S.nsched = (int)c->sched.size();
+    for (size_t q = 0; q < c->sched.size(); ++q) S.sched[q] = c->sched[q];
+    S.nchunk = (P.ng + 63) / 64;
+    S.cv = P.cv;
+    S.dt = P.dt;
+    S.c = P.c;
+    S.aR = P.aR;
+    S.inv_cdt = 1.0 / (P.c * P.dt);
+    double wall = 0.0, wmu2all = 0.0;
+    for (int m = 0; m < P.nmu; ++m) {
+      const double mu = P.mu[m], w = P.w[m];
+      wall += w;
+      wmu2all += w * mu * mu;
+      if (mu > 0) {
+        S.wpos += w;
+        S.wmupos += w * mu;
+        S.wmu2pos += w * mu * mu;
+      } else {
+        S.wneg += w;
+        S.wmuneg += w * mu;
+        S.wmu2neg += w * mu * mu;
+      }
+    }
+    S.f_iso = wmu2all / wall;
+    S.c_iso = S.wmupos / S.wpos;
+    S.o_cell = c->n_cell;
+    S.o_edge = c->n_edge;
+    S.o_I = c->n_I;
+    S.o_gi = c->n_gi;
+    S.o_ge = c->n_ge;
+    S.o_g = c->n_g;
+    S.o_g2 = 2 * c->n_g;
+    S.o_nu = c->n_nu;
+    S.o_mu = c->n_mu;
+    S.o_chunk = c->n_chunk;
+    S.o_red = c->n_red;
+    c->n_cell += P.nx;
+    c->n_edge += P.nx + 1;
+    c->n_I += (long long)P.ng * P.nmu * P.nx * 2;
+    c->n_gi += (long long)P.ng * P.nx;
+    c->n_ge += (long long)P.ng * (P.nx + 1);
+    c->n_g += P.ng;
+    c->n_nu += P.ng + 1;
+    c->n_mu += P.nmu;
+    c->n_chunk += (long long)S.nchunk * P.nx;
+    c->n_red += (long long)S.nchunk * (P.nx + 1) * 21;
+    S.o_lpi[0] = S.o_gi;
+    S.o_lpe[0] = S.o_ge;
+    S.o_lp2[0] = S.o_g2;
+    for (int l = 1; l < nlev; ++l) {
+      S.o_lpi[l] = c->n_lpi[l];
+      S.o_lpe[l] = c->n_lpe[l];
+      S.o_lp2[l] = c->n_lp2[l];
+      c->n_lpi[l] += (long long)S.lev_ng[l] * P.nx;
+      c->n_lpe[l] += (long long)S.lev_ng[l] * (P.nx + 1);
+      c->n_lp2[l] += 2LL * S.lev_ng[l];
+    }
+    for (int i = 0; i < P.nx; ++i) {
+      h_dx.push_back(P.x_edges[i + 1] - P.x_edges[i]);
+      h_C.push_back(P.C_cell[i]);
+    }
+    for (int m = 0; m < P.nmu; ++m) {
+      h_mu.push_back(P.mu[m]);
+      h_w.push_back(P.w[m]);
+    }
+    for (int g = 0; g <= P.ng; ++g) h_nue.push_back(P.nu_edges[g]);
+    for (int g = 0; g < P.ng; ++g) h_nuc.push_back(P.nu_center[g]);
+  }
+  // incoming radiation: computed after the head coefficients are on the device
+  int rc = TR_OK;
+  auto fail = [&](int code) {
+    tr_destroy(c);
+    return code;
+  };
+  double coef[TR_NHEAD];
+  head_coefficients(coef);
+  if (upload_head_coef(coef)) return fail(TR_EHIP);
+
+  double *d_dx, *d_C, *d_mu, *d_w, *d_nue, *d_nuc;
+  if ((rc = dalloc(c, &d_dx, c->n_cell)) || (rc = dalloc(c, &d_C, c->n_cell)) || (rc = dalloc(c, &d_mu, c->n_mu)) ||
+      (rc = dalloc(c, &d_w, c->n_mu)) || (rc = dalloc(c, &d_nue, c->n_nu)) || (rc = dalloc(c, &d_nuc, c->n_g)) ||
+      (rc = dalloc(c, &c->d_inc, 2 * c->n_g)) || (rc = dalloc(c, &c->d_sd, n_slab)))
+    return fail(rc);
+  auto up = [&](void *d, const void *h, size_t bytes) { return hipMemcpy(d, h, bytes, hipMemcpyHostToDevice); };
+  if (up(d_dx, h_dx.data(), 8 * h_dx.size()) || up(d_C, h_C.data(), 8 * h_C.size()) ||
+      up(d_mu, h_mu.data(), 8 * h_mu.size()) || up(d_w, h_w.data(), 8 * h_w.size()) ||
+      up(d_nue, h_nue.data(), 8 * h_nue.size()) || up(d_nuc, h_nuc.data(), 8 * h_nuc.size()) ||
+      up(c->d_sd, c->hs.data(), sizeof(SlabDev) * n_slab))
+    return fail(TR_EHIP);
+  c->pd.dx = d_dx;
+  c->pd.Ccell = d_C;
+  c->pd.mu = d_mu;
+  c->pd.w = d_w;
+  c->pd.nu_e = d_nue;
+  c->pd.nu_c = d_nuc;
+  c->pd.inc = c->d_inc;
+
+  // workspace
+  if ((rc = dalloc(c, &c->kappa, c->n_gi)) || (rc = dalloc(c, &c->B, c->n_gi)) ||
+      (rc = dalloc(c, &c->dSpart, c->n_chunk)) || (rc = dalloc(c, &c->mom, 4 * c->n_gi)) ||
+      (rc = dalloc(c, &c->bnd, 6 * c->n_g)) || (rc = dalloc(c, &c->Phi, 2 * c->n_g)) ||
+      (rc = dalloc(c, &c->Eold, c->n_gi)) || (rc = dalloc(c, &c->Fold, c->n_ge)) || (rc = dalloc(c, &c->red, c->n_red)))
+    return fail(rc);
+  double **cells[] = {&c->Told, &c->Ts, &c->Tcyc, &c->Tstar, &c->Tprev, &c->sigprev, &c->Ecyc, &c->Es};
+  for (double **p : cells)
+    if ((rc = dalloc(c, p, c->n_cell))) return fail(rc);
+  for (int l = 1; l < nlev; ++l) {
+    auto &L = c->lev[l];
+    double **pi[] = {&L.sigE, &L.emis, &L.Eold, &L.E, &L.Esum};
+    double **pe[] = {&L.a, &L.b, &L.sigR, &L.Fold, &L.F};
+    double **p2[] = {&L.C, &L.Phi, &L.Ebnd};
+    for (double **p : pi)
+      if ((rc = dalloc(c, p, c->n_lpi[l]))) return fail(rc);
+    for (double **p : pe)
+      if ((rc = dalloc(c, p, c->n_lpe[l]))) return fail(rc);
+    for (double **p : p2)
+      if ((rc = dalloc(c, p, c->n_lp2[l]))) return fail(rc);
+  }
+  if ((rc = dalloc(c, &c->d_ctl, n_slab)) || (rc = dalloc(c, &c->d_cost, n_slab)) || (rc = dalloc(c, &c->d_count, 1)))
+    return fail(rc);
+  if (hipHostMalloc((void **)&c->h_count, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(TR_ENOMEM);
+  std::vector<int> cost(n_slab);
+  for (int s = 0; s < n_slab; ++s) {
+    const SlabDev &S = c->hs[s];
+    int k = S.lev_ng[0] + 1;
+    for (int q = 0; q < S.nsched; ++q) k += S.lev_ng[S.sched[q]] + 1;
+    cost[s] = k;
+  }
+  if (up(c->d_cost, cost.data(), sizeof(int) * n_slab)) return fail(TR_EHIP);
+
+  // work tables
+  {
+    std::vector<Item> opac, cell, sweep, gi, g, grey;
+    std::vector<std::vector<Item>> lo(nlev);
+    for (int s = 0; s < n_slab; ++s) {
+      const SlabDev &S = c->hs[s];
+      const int ncb = (S.nx + 255) / 256;
+      for (int q = 0; q < S.nchunk * ncb; ++q) opac.push_back({s, q});
+      for (int st = 0; st < S.nx; st += 256) cell.push_back({s, st});
+      for (int gg = 0; gg < S.ng; ++gg) sweep.push_back({s, gg});
+      for (long long st = 0; st < (long long)S.ng * S.nx; st += 256) gi.push_back({s, (int)st});
+      for (int st = 0; st < S.ng; st += 256) g.push_back({s, st});
+      grey.push_back({s, 0});
+      for (int l = 0; l < nlev; ++l)
+        for (int p = 0; p < S.lev_ng[l]; ++p) lo[l].push_back({s, p});
+    }
+    if ((rc = upload_table(c, opac, c->t_opac)) || (rc = upload_table(c, cell, c->t_cell)) ||
+        (rc = upload_table(c, sweep, c->t_sweep)) || (rc = upload_table(c, gi, c->t_gi)) ||
+        (rc = upload_table(c, g, c->t_g)) || (rc = upload_table(c, grey, c->t_grey)))
+      return fail(rc);
+    for (int l = 0; l < nlev; ++l)
+      if ((rc = upload_table(c, lo[l], c->t_lo[l]))) return fail(rc);
+    if ((rc = build_restrict_tables(c, 0, nlev - 1))) return fail(rc);
+    for (int gsched : c->sched) {
+      if ((rc = build_restrict_tables(c, 0, gsched)) || (rc = build_restrict_tables(c, gsched, nlev - 1)))
+        return fail(rc);
+    }
+  }
+
+  // incoming Planck radiation at T_left / T_right: B table of a one-cell
+  // evaluation per slab through the opacity kernel would need a second
+  // layout, so evaluate the same device routine on a scratch pooled table.
+  c->h_inc.assign(2 * c->n_g, 0.0);
+  {
+    // temperature per cell: left boundary temperature in even passes
+    std::vector<double> Tb(c->n_cell);
+    for (int side = 0; side < 2; ++side) {
+      for (int s = 0; s < n_slab; ++s) {
+        const double Tv = side == 0 ? probs[s].T_left : probs[s].T_right;
+        for (int i = 0; i < c->hs[s].nx; ++i) Tb[c->hs[s].o_cell + i] = Tv > 0 ? Tv : 1.0;
+      }
+      if (up(c->Told, Tb.data(), 8 * Tb.size())) return fail(TR_EHIP);
+      LaunchEnv env = env_of(c, 0);
+      launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, c->Told, c->kappa, c->B, c->dSpart);
+      if (hipDeviceSynchronize() != hipSuccess) return fail(TR_EHIP);
+      std::vector<double> hB(c->n_gi);
+      if (hipMemcpy(hB.data(), c->B, 8 * hB.size(), hipMemcpyDeviceToHost) != hipSuccess) return fail(TR_EHIP);
+      for (int s = 0; s < n_slab; ++s) {
+        const SlabDev &S = c->hs[s];
+        const double Tv = side == 0 ? probs[s].T_left : probs[s].T_right;
+        for (int gg = 0; gg < S.ng; ++gg)
+          c->h_inc[2 * S.o_g + side * S.ng + gg] = Tv > 0 ? hB[S.o_gi + (long long)gg * S.nx] : 0.0;
+      }
+    }
+    if (up(c->d_inc, c->h_inc.data(), 8 * c->h_inc.size())) return fail(TR_EHIP);
+  }
+  *out = c;
+  return TR_OK;
+}
+
+int tr_layout(const tr_ctx *c, int kind, int slab, long long *offset, long long *total) {
+  if (!c || slab < 0 || slab >= c->nslab) return TR_EINVAL;
+  const SlabDev &S = c->hs[slab];
+  long long o = 0, t = 0;
+  if (kind >= TR_K_LEV_P2 && kind < TR_K_LEV_P2 + c->nlev) {
+    const int l = kind - TR_K_LEV_P2;
+    o = S.o_lp2[l];
+    t = l == 0 ? 2 * c->n_g : c->n_lp2[l];
+  } else if (kind >= TR_K_LEV_PE && kind < TR_K_LEV_PE + c->nlev) {
+    const int l = kind - TR_K_LEV_PE;
+    o = S.o_lpe[l];
+    t = l == 0 ? c->n_ge : c->n_lpe[l];
+  } else if (kind >= TR_K_LEV_PI && kind < TR_K_LEV_PI + c->nlev) {
+    const int l = kind - TR_K_LEV_PI;
+    o = S.o_lpi[l];
+    t = l == 0 ? c->n_gi : c->n_lpi[l];
+  } else {
+    switch (kind) {
+      case TR_K_CELL: o = S.o_cell; t = c->n_cell; break;
+      case TR_K_EDGE: o = S.o_edge; t = c->n_edge; break;
+      case TR_K_I: o = S.o_I; t = c->n_I; break;
+      case TR_K_GI: o = S.o_gi; t = c->n_gi; break;
+      case TR_K_GE: o = S.o_ge; t = c->n_ge; break;
+      case TR_K_G2: o = S.o_g2; t = 2 * c->n_g; break;
+      case TR_K_G: o = S.o_g; t = c->n_g; break;
+      default: return TR_EINVAL;
+    }
+  }
+  if (offset) *offset = o;
+  if (total) *total = t;
+  return TR_OK;
+}
+
+int tr_set_incoming(tr_ctx *c, int slab, const double *inc_left, const double *inc_right) {
+  if (!c || slab < 0 || slab >= c->nslab) return TR_EINVAL;
+  const SlabDev &S = c->hs[slab];
+  if (inc_left)
+    for (int g = 0; g < S.ng; ++g) c->h_inc[2 * S.o_g + g] = inc_left[g];
+  if (inc_right)
+    for (int g = 0; g < S.ng; ++g) c->h_inc[2 * S.o_g + S.ng + g] = inc_right[g];
+  return hip_err(hipMemcpy(c->d_inc, c->h_inc.data(), 8 * c->h_inc.size(), hipMemcpyHostToDevice));
+}
+
+int tr_opacity(tr_ctx *c, const double *T, double *kappa, double *B, double *dS, hipStream_t st) {
+  if (!c || !T || !kappa || !B) return TR_EINVAL;
+  LaunchEnv env = env_of(c, st);
+  launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, T, kappa, B, c->dSpart);
+  if (dS) launch_dS_sum(env, c->t_cell, c->dSpart, dS);
+  return hip_err(hipGetLastError());
+}
+
+int tr_sweep(tr_ctx *c, const double *kappa, const double *B, const double *I_prev, double *I_out, double *mom,
+             double *bnd, hipStream_t st) {
+  if (!c || !kappa || !B || !I_prev || !I_out || !mom || !bnd || I_prev == I_out) return TR_EINVAL;
+  launch_sweep(env_of(c, st), c->t_sweep, nullptr, PRED_ALL, 0, kappa, B, I_prev, I_out, mom, bnd);
+  return hip_err(hipGetLastError());
+}
+
+int tr_moments(tr_ctx *c, const double *mom, const double *bnd, double *f, double *fbnd, double *C, double *Phi,
+               hipStream_t st) {
+  if (!c || !mom || !bnd || !f || !fbnd || !C || !Phi) return TR_EINVAL;
+  launch_moments(env_of(c, st), c->t_gi, nullptr, PRED_ALL, 0, mom, bnd, f, fbnd, C, Phi);
+  return hip_err(hipGetLastError());
+}
+
+int tr_lo_solve(tr_ctx *c, int level, const tr_lo_coeffs *in, const tr_lo_fields *out, hipStream_t st) {
+  if (!c || !in || !out || level < 0 || level >= c->nlev || !out->E || !out->F || !out->Ebnd) return TR_EINVAL;
+  if (level == 0 && (!in->kappa || !in->B || !in->f || !in->fbnd)) return TR_EINVAL;
+  if (level > 0 && (!in->sigE || !in->emis || !in->a || !in->b || !in->sigR)) return TR_EINVAL;
+  if (!in->C || !in->Phi || !in->Eold || !in->Fold) return TR_EINVAL;
+  LoSol sol{out->E, out->F, out->Ebnd};
+  launch_lo(env_of(c, st), c->t_lo[level], c->lo_threads, nullptr, PRED_ALL, 0, level, coeffs_in(in), sol);
+  return hip_err(hipGetLastError());
+}
+
+int tr_restrict(tr_ctx *c, int from, int to, const tr_lo_coeffs *in, const tr_lo_fields *sol, const tr_lo_out *out,
+                hipStream_t st) {
+  if (!c || !in || !sol || !out || from < 0 || to <= from || to >= c->nlev) return TR_EINVAL;
+  for (int s = 0; s < c->nslab; ++s) {
+    const SlabDev &S = c->hs[s];
+    const int r = S.lev_ng[from] / S.lev_ng[to];
+    if (S.lev_ng[from] % S.lev_ng[to] || (r > 64 && r % 64)) return TR_EINVAL;
+  }
+  int rc = build_restrict_tables(c, from, to);
+  if (rc) return rc;
+  LoSol s{sol->E, sol->F, sol->Ebnd};
+  LoOut o{out->sigE, out->emis, out->a, out->b, out->sigR, out->C, out->Phi, out->Eold, out->Fold, out->Esum};
+  launch_restrict(env_of(c, st), c->t_red[std::make_pair(from, to)], nullptr, PRED_ALL, 0, from, to, coeffs_in(in), s,
+                  o, c->red);
+  return hip_err(hipGetLastError());
+}
+
+int tr_grey_solve(tr_ctx *c, const tr_lo_coeffs *grey, const double *Tstar, const double *Told, const double *dS,
+                  const double *Estar, const double *D, double *T_out, const tr_lo_fields *out, hipStream_t st) {
+  if (!c || !grey || !Tstar || !Told || !dS || !Estar || !D || !T_out || !out) return TR_EINVAL;
+  GreyArgs ga{};
+  ga.grey = coeffs_in(grey);
+  ga.Estar = Estar;
+  ga.sol = LoSol{out->E, out->F, out->Ebnd};
+  ga.Tstar = Tstar;
+  ga.Tout = T_out;
+  ga.Told = Told;
+  ga.dS = dS;
+  ga.D = D;
+  launch_grey(env_of(c, st), c->t_grey, c->lo_threads, nullptr, PRED_ALL, 0, ga);
+  return hip_err(hipGetLastError());
+}
+
+int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
+  if (!c || !s || !s->T || !s->I_out || !s->E || !s->F || !s->Ebnd || !s->f || !s->fbnd || !s->C || !s->Egrey ||
+      !(T0 > 0))
+    return TR_EINVAL;
+  LaunchEnv env = env_of(c, st);
+  launch_fill(env, s->T, T0, c->n_cell);
+  launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, s->T, c->kappa, c->B, c->dSpart);
+  launch_init_state(env, c->t_gi, c->B, s->I_out, s->E, s->F, s->Ebnd, c->mom, c->bnd);
+  launch_moments(env, c->t_gi, nullptr, PRED_ALL, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
+  launch_group_sum(env, c->t_cell, s->E, s->Egrey);
+  return hip_err(hipGetLastError());
+}
+
+int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st) {
+  if (!c || !s || !s->T || !s->I_prev || !s->I_out || s->I_prev == s->I_out || !s->E || !s->F || !s->Ebnd ||
+      !s->f || !s->fbnd || !s->C || !s->Egrey)
+    return TR_EINVAL;
+  const int ns = c->nslab, nlev = c->nlev, gl = nlev - 1;
+  // control records
+  std::vector<Ctl> hc(ns);
+  int Lmax = c->cfg.lmax;
+  for (int q = 0; q < ns; ++q) {
+    Ctl &k = hc[q];
+    std::memset(&k, 0, sizeof(Ctl));
+    k.active = 1;
+    if (replay) {
+      const int *row = replay + (size_t)q * TR_MAXOUT;
+      int n = 0;
+      while (n < TR_MAXOUT && row[n] > 0) {
+        k.replay[n] = row[n];
+        Lmax = std::max(Lmax, row[n]);
+        ++n;
+      }
+      if (n == 0) return TR_EINVAL;
+      k.n_replay = n;
+    }
+  }
+  if (hipMemcpyAsync(c->d_ctl, hc.data(), sizeof(Ctl) * ns, hipMemcpyHostToDevice, st) != hipSuccess) return TR_EHIP;
+  LaunchEnv env = env_of(c, st);
+  // step start: old-time copies, convergence references, Phi with the current incoming
+  launch_copy(env, s->T, c->Told, c->n_cell);
+  launch_copy(env, s->T, c->Ts, c->n_cell);
+  launch_copy(env, s->T, c->Tcyc, c->n_cell);
+  launch_copy(env, s->T, c->Tstar, c->n_cell);
+  launch_copy(env, s->Egrey, c->Es, c->n_cell);
+  launch_copy(env, s->Egrey, c->Ecyc, c->n_cell);
+  launch_copy(env, s->E, c->Eold, c->n_gi);
+  launch_copy(env, s->F, c->Fold, c->n_ge);
+  launch_phi(env, c->t_g, s->C, c->Phi);
+  launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
+
+  const LoIn fine = fine_in(c, c->kappa, c->B, s->f, s->fbnd, s->C, c->Phi, c->Eold, c->Fold);
+  const LoSol fsol{s->E, s->F, s->Ebnd};
+  GreyArgs ga{};
+  ga.grey = level_in(c, gl);
+  ga.Estar = c->lev[gl].Esum;
+  ga.sol = level_sol(c, gl);
+  ga.Tstar = c->Tstar;
+  ga.Tout = c->Tstar;
+  ga.Told = c->Told;
+  ga.dS = nullptr;
+  ga.dSpart = c->dSpart;
+  ga.D = nullptr;
+  ga.Tprev = c->Tprev;
+  ga.sigprev = c->sigprev;
+  ga.Egrey = s->Egrey;
+  ga.Tcyc = c->Tcyc;
+  ga.Ecyc = c->Ecyc;
+  ga.Ts = c->Ts;
+  ga.Es = c->Es;
+  ga.cyc_cost = c->d_cost;
+  ga.secant = c->cfg.secant;
+  ga.lmax = c->cfg.lmax;
+  ga.eps = c->cfg.eps;
+  ga.eps_inner = c->cfg.eps_inner;
+
+  const int nsch = (int)c->sched.size();
+  for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
+    if (outer > 0) {
+      launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
+      launch_sweep(env, c->t_sweep, c->d_ctl, PRED_SWEEP, 0, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
+      launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
+    }
+    for (int l = 0; l < Lmax; ++l) {
+      launch_lo(env, c->t_lo[0], c->lo_threads, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
+      launch_restrict(env, c->t_red[std::make_pair(0, gl)], c->d_ctl, PRED_CYCLE, l, 0, gl, fine, fsol,
+                      level_out(c, gl), c->red);
+      ga.end_cycle = nsch == 0;
+      launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
+      for (int q = 0; q < nsch; ++q) {
+        const int gm = c->sched[q];
+        launch_opacity(env, c->t_opac, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
+        launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
+                        level_out(c, gm), c->red);
+        launch_lo(env, c->t_lo[gm], c->lo_threads, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm), level_sol(c, gm));
+        launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
+                        level_sol(c, gm), level_out(c, gl), c->red);
+        ga.end_cycle = q == nsch - 1;
+        launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
+      }
+      launch_opacity(env, c->t_opac, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
+    }
+    launch_count_active(env, c->d_ctl, ns, c->d_count);
+    if (hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return TR_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return TR_EHIP;
+    if (*c->h_count == 0) break;
+  }
+  launch_copy(env, c->Tstar, s->T, c->n_cell);
+  if (hipMemcpyAsync(hc.data(), c->d_ctl, sizeof(Ctl) * ns, hipMemcpyDeviceToHost, st) != hipSuccess) return TR_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return TR_EHIP;
+  int err = TR_OK;
+  for (int q = 0; q < ns; ++q) {
+    const Ctl &k = hc[q];
+    if (k.active) err = TR_ENOCONV;
+    if (k.err) err = k.err;
+    if (stats) {
+      tr_stats &o = stats[q];
+      o.n_ti += k.n_ti;
+      o.n_c += k.n_c;
+      o.n_lo += k.n_lo;
+      o.n_floor += k.n_floor;
+      o.n_outer = k.s + 1;
+      for (int i = 0; i < 64; ++i) o.cycles[i] = i < TR_MAXOUT ? k.cycles[i] : 0;
+    }
+  }
+  return err;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Device helpers: Planck group integrals, opacity law, tridiagonal solver.
+#pragma once
+
+#include "tr_common.h"
+
+// ---------------------------------------------------------------------------
+// Planck integral  Q(x) = int_0^x t^3/(e^t - 1) dt  (total pi^4/15).
+// Below x = 2 the Bernoulli series t/(e^t-1) = sum B_k t^k / k! integrated
+// term by term; above, the geometric expansion 1/(e^t-1) = sum_n e^{-n t}
+// integrated exactly:  int_x^inf t^3 e^{-n t} dt = e^{-nx}(x^3/n + 3x^2/n^2 +
+// 6x/n^3 + 6/n^4).  The head coefficients c_k = B_k / (k! (k+3)) are filled
+// by the host at context creation.
+// ---------------------------------------------------------------------------
+#define TR_NHEAD 40
+extern __constant__ double tr_head_coef[TR_NHEAD];
+
+static constexpr double TR_PI4_15 = 6.4939394022668291491;  // pi^4 / 15
+static constexpr double TR_XSW = 2.0;
+
+// Head part int_0^x (x < 2).
+__device__ inline double q_head(double x) {
+  double acc = tr_head_coef[TR_NHEAD - 1];
+#pragma unroll
+  for (int k = TR_NHEAD - 2; k >= 0; --k) acc = fma(acc, x, tr_head_coef[k]);
+  return acc * x * x * x;
+}
+
+// Tail part int_x^inf (x >= 2), given ex = e^{-x}.  Terms decay like e^{-nx};
+// n_max = 40/x + 2 keeps the truncation below 1e-17 relative.
+__device__ inline double q_tail(double x, double ex) {
+  if (!(ex > 0.0)) return 0.0;
+  int nmax = (int)(40.0 / x) + 2;
+  double en = ex, acc = 0.0;
+  double x2 = x * x, x3 = x2 * x;
+  for (int n = 1; n <= nmax; ++n) {
+    double rn = 1.0 / n;
+    // x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4 = (x^3 + (3x^2 + (6x + 6/n)/n)/n)/n
+    double poly = fma(rn, fma(rn, fma(rn, 6.0, 6.0 * x), 3.0 * x2), x3);
+    acc = fma(en * rn, poly, acc);
+    en *= ex;
+  }
+  return acc;
+}
+
+// One group edge: x = nu/T with its head/tail representation.
+struct EdgeQ {
+  double x;     // nu / T (may be +inf)
+  double head;  // int_0^x if x < 2
+  double tail;  // int_x^inf if x >= 2
+  double g4;    // x^4 / (e^x - 1) (0 at x = 0 and x = inf)
+  int is_tail;
+};
+
+__device__ inline EdgeQ edge_q(double nu, double T) {
+  EdgeQ e;
+  double x = nu / T;
+  e.x = x;
+  if (nu == 0.0) {
+    e.head = 0.0; e.tail = 0.0; e.g4 = 0.0; e.is_tail = 0;
+  } else if (x < TR_XSW) {
+    e.head = q_head(x); e.tail = 0.0; e.is_tail = 0;
+    double x2 = x * x;
+    e.g4 = x2 * x2 / expm1(x);
+  } else if (isinf(x)) {
+    e.head = 0.0; e.tail = 0.0; e.g4 = 0.0; e.is_tail = 1;
+  } else {
+    double ex = exp(-x);
+    e.head = 0.0; e.tail = q_tail(x, ex); e.is_tail = 1;
+    double x2 = x * x;
+    e.g4 = (ex > 0.0) ? x2 * x2 * ex / (-expm1(-x)) : 0.0;
+  }
+  return e;
+}
+
+// int_{x_lo}^{x_hi} t^3/(e^t-1) dt from two edge representations.
+__device__ inline double q_interval(const EdgeQ &lo, const EdgeQ &hi) {
+  if (lo.is_tail) return lo.tail - hi.tail;           // both in the tail range
+  if (!hi.is_tail) return hi.head - lo.head;          // both in the head range
+  return (TR_PI4_15 - hi.tail) - lo.head;             // straddles x = 2
+}
+
+// ---------------------------------------------------------------------------
+// Partitioned tridiagonal solver for one system per thread block.
+//
+// Rows j = 0..N-1:  a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j  (a_0 = c_{N-1} = 0).
+// Thread t owns rows s = tK .. e = tK + K - 1 (rows >= N are identity rows).
+// Local elimination gives, for every partition, a row of x_s in terms of the
+// neighbours x_{s-1} (last row of partition t-1) and x_e, and a row of x_e in
+// terms of x_s and x_{e+1} (first row of partition t+1).  These 2T rows form a
+// tridiagonal "interface" system solved by parallel cyclic reduction in LDS;
+// the interior rows then follow by back substitution.  The systems here are
+// column diagonally dominant M-matrices, so no pivoting is needed.
+// lds must hold 8 * T doubles.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ inline void tri_solve_block(const double (&a)[K], const double (&b)[K], const double (&c)[K],
+                                       const double (&d)[K], double (&x)[K], double *lds, int T) {
+  const int t = threadIdx.x;
+  // downward: rows s+1..e in terms of x_s:  ah_i x_s + bh_i x_i + c_i x_{i+1} = dh_i
+  double ah[K], bh[K], dh[K];
+  ah[1] = a[1];
+  bh[1] = b[1];
+  dh[1] = d[1];
+#pragma unroll
+  for (int i = 2; i < K; ++i) {
+    double r = a[i] / bh[i - 1];
+    ah[i] = -r * ah[i - 1];
+    bh[i] = b[i] - r * c[i - 1];
+    dh[i] = d[i] - r * dh[i - 1];
+  }
+  // upward: rows e-1..s in terms of x_e:  a_i x_{i-1} + bv_i x_i + cv_i x_e = dv_i
+  double bv = b[K - 2], cv = c[K - 2], dv = d[K - 2];
+#pragma unroll
+  for (int i = K - 3; i >= 0; --i) {
+    double r = c[i] / bv;
+    bv = b[i] - r * a[i + 1];
+    cv = -r * cv;
+    dv = d[i] - r * dv;
+  }
+  // interface rows: 2t -> x_s, 2t+1 -> x_e
+  double *ra = lds, *rb = lds + 2 * T, *rc = lds + 4 * T, *rd = lds + 6 * T;
+  ra[2 * t] = a[0];
+  rb[2 * t] = bv;
+  rc[2 * t] = cv;
+  rd[2 * t] = dv;
+  ra[2 * t + 1] = ah[K - 1];
+  rb[2 * t + 1] = bh[K - 1];
+  rc[2 * t + 1] = c[K - 1];
+  rd[2 * t + 1] = dh[K - 1];
+  __syncthreads();
+  const int R = 2 * T;
+  for (int st = 1; st < R; st <<= 1) {
+    double na[2], nb[2], nc[2], nd[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      int i = 2 * t + q;
+      double ai = ra[i], bi = rb[i], ci = rc[i], di = rd[i];
+      double al = 0.0, ga = 0.0;
+      double am = 0.0, cm = 0.0, dm = 0.0, ap = 0.0, cp = 0.0, dp = 0.0;
+      if (i - st >= 0) {
+        al = ai / rb[i - st];
+        am = ra[i - st];
+        cm = rc[i - st];
+        dm = rd[i - st];
+      }
+      if (i + st < R) {
+        ga = ci / rb[i + st];
+        ap = ra[i + st];
+        cp = rc[i + st];
+        dp = rd[i + st];
+      }
+      na[q] = -al * am;
+      nc[q] = -ga * cp;
+      nb[q] = bi - al * cm - ga * ap;
+      nd[q] = di - al * dm - ga * dp;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      int i = 2 * t + q;
+      ra[i] = na[q];
+      rb[i] = nb[q];
+      rc[i] = nc[q];
+      rd[i] = nd[q];
+    }
+    __syncthreads();
+  }
+  const double xs = rd[2 * t] / rb[2 * t];
+  const double xe = rd[2 * t + 1] / rb[2 * t + 1];
+  x[0] = xs;
+  x[K - 1] = xe;
+#pragma unroll
+  for (int i = K - 2; i >= 1; --i) x[i] = (dh[i] - ah[i] * xs - c[i] * x[i + 1]) / bh[i];
+  __syncthreads();
+  // publish the first unknown of every partition for neighbours (reuse ra)
+  ra[t] = xs;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide max reduction (exact, order independent).  lds: blockDim doubles.
+// ---------------------------------------------------------------------------
+__device__ inline double block_max(double v, double *lds) {
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+  for (int st = blockDim.x >> 1; st > 0; st >>= 1) {
+    if (t < st) lds[t] = fmax(lds[t], lds[t + st]);
+    __syncthreads();
+  }
+  double r = lds[0];
+  __syncthreads();
+  return r;
+}

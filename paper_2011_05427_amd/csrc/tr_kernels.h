@@ -1,0 +1,80 @@
+// Kernel argument structures and host launchers (internal to the library).
+#pragma once
+
+#include "tr_common.h"
+
+#define TR_LO_K 8  // rows per thread of the partitioned tridiagonal solver
+
+enum { PRED_ALL = 0, PRED_CYCLE = 1, PRED_DONECYC = 2, PRED_SWEEP = 3, PRED_ACTIVE = 4 };
+
+// Coefficients of a level (fine: kappa/B/f/fbnd; coarse: level arrays).
+struct LoIn {
+  const double *kappa, *B, *f, *fbnd;
+  const double *sigE, *emis, *a, *b, *sigR;
+  const double *C, *Phi, *Eold, *Fold;
+};
+
+struct LoSol {
+  double *E, *F, *Ebnd;
+};
+
+struct LoOut {
+  double *sigE, *emis, *a, *b, *sigR, *C, *Phi, *Eold, *Fold, *Esum;
+};
+
+struct GreyArgs {
+  LoIn grey;             // grey-level coefficient arrays
+  const double *Estar;   // grey-level Esum (stage spectrum total)
+  LoSol sol;             // grey-level fields
+  const double *Tstar;   // cell: stage temperature
+  double *Tout;          // cell: new temperature (may equal Tstar)
+  const double *Told;    // cell: previous time level
+  const double *dS;      // cell: explicit dS (nullable)
+  const double *dSpart;  // chunk partials of dS (used when dS is null)
+  const double *D;       // cell: explicit Frechet derivative (nullable)
+  double *Tprev, *sigprev;         // secant memory (step mode)
+  double *Egrey;                   // cell: grey E output (nullable)
+  double *Tcyc, *Ecyc, *Ts, *Es;   // convergence references (step mode)
+  const int *cyc_cost;             // per slab: LO solves per cycle
+  int secant, end_cycle, lmax;
+  double eps, eps_inner;
+};
+
+struct LaunchEnv {
+  const SlabDev *sd;
+  ProbDev pd;
+  hipStream_t stream;
+};
+
+struct Table {
+  const Item *d;
+  int n;
+};
+
+void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *T,
+                    double *kappa, double *B, double *dSpart);
+void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart, double *dS);
+void launch_sweep(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *kappa,
+                  const double *B, const double *Ip, double *Io, double *mom, double *bnd);
+void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
+                    const double *bnd, double *f, double *fbnd, double *C, double *Phi);
+void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi);
+void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
+               const LoIn &in, const LoSol &sol);
+// Restriction work: slabs whose coarse groups hold <= 64 finer groups use one
+// pass; the others a chunk pass plus a final pass.
+struct RestrictTables {
+  Table single, part, fin;
+};
+void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
+                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red);
+void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
+                 const GreyArgs &ga);
+void launch_outer_begin(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer);
+void launch_count_active(const LaunchEnv &env, const Ctl *ctl, int nslab, int *out);
+void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n);
+void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
+void launch_init_state(const LaunchEnv &env, const Table &tab, const double *Bt, double *I, double *E, double *F,
+                       double *Ebnd, double *mom, double *bnd);
+void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, double *out);
+int upload_head_coef(const double *coef);

@@ -1,0 +1,1025 @@
+// HIP kernels (gfx950, FP64) of the MLQD step with multigrid in frequency.
+//
+// Every kernel is batched over slabs through a work table (Item = slab, index)
+// and can be predicated on the per-slab iteration control, so one launch
+// sequence serves a batch of slabs that converge at different iterations.
+#include "tr_device.h"
+#include "tr_kernels.h"
+
+__constant__ double tr_head_coef[TR_NHEAD];
+
+// ---------------------------------------------------------------------------
+// predication
+// ---------------------------------------------------------------------------
+__device__ inline bool pred_ok(const Ctl *ctl, int slab, int mode, int l) {
+  if (ctl == nullptr || mode == PRED_ALL) return true;
+  const Ctl &c = ctl[slab];
+  switch (mode) {
+    case PRED_CYCLE:  // body of cycle l+1 of the current transport iteration
+      return c.active && !c.inner_done && c.ncyc == l;
+    case PRED_DONECYC:  // the slab has just completed cycle l
+      return c.active && c.ncyc == l;
+    case PRED_SWEEP:  // start of a transport iteration s >= 1
+      return c.active && !c.inner_done && c.ncyc == 0 && c.s > 0;
+    case PRED_ACTIVE:
+      return c.active;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// A1: opacity and group Planck tables at T, with the chunk partial sums of
+// dS = d/dT sum_g 2 kappa_g B_g.  Thread = (slab, 64-group chunk, cell).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                 const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
+                                                 const double *__restrict__ T, double *__restrict__ kappa,
+                                                 double *__restrict__ B, double *__restrict__ dSpart) {
+  const Item it = tab[blockIdx.x];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ng = S.ng;
+  const int ncb = (nx + 255) >> 8;
+  const int chunk = it.idx / ncb, cb = it.idx % ncb;
+  const int i = cb * 256 + threadIdx.x;
+  if (i >= nx) return;
+  const double Ti = T[S.o_cell + i];
+  const double Cc = pd.Ccell[S.o_cell + i];
+  const double T2 = Ti * Ti;
+  const double scale = S.aR * S.c * T2 * T2 * 0.5 / TR_PI4_15;
+  const double *nue = pd.nu_e + S.o_nu;
+  const double *nuc = pd.nu_c + S.o_g;
+  const int g0 = chunk * 64, g1 = min(ng, g0 + 64);
+  EdgeQ lo = edge_q(nue[g0], Ti);
+  double dS = 0.0;
+  for (int g = g0; g < g1; ++g) {
+    const EdgeQ hi = edge_q(nue[g + 1], Ti);
+    const double Bg = scale * q_interval(lo, hi);
+    const double dBg = 4.0 * Bg / Ti - scale / Ti * (hi.g4 - lo.g4);
+    const double nu = nuc[g];
+    const double y = nu / Ti;
+    const double nu3 = nu * nu * nu;
+    const double kap = Cc / nu3 * (-expm1(-y));
+    const double dkap = -Cc / (nu * nu) * exp(-y) / T2;
+    const long long o = S.o_gi + (long long)g * nx + i;
+    kappa[o] = kap;
+    B[o] = Bg;
+    dS += 2.0 * (dkap * Bg + kap * dBg);
+    lo = hi;
+  }
+  dSpart[S.o_chunk + (long long)chunk * nx + i] = dS;
+}
+
+// Sums the chunk partials of dS (standalone tr_opacity).  Thread = cell.
+__global__ __launch_bounds__(256) void k_dS_sum(const SlabDev *__restrict__ sd, const Item *__restrict__ tab,
+                                                const double *__restrict__ dSpart, double *__restrict__ dS) {
+  const Item it = tab[blockIdx.x];
+  const SlabDev &S = sd[it.slab];
+  const int i = it.idx + threadIdx.x;
+  if (i >= S.nx) return;
+  double acc = 0.0;
+  for (int q = 0; q < S.nchunk; ++q) acc += dSpart[S.o_chunk + (long long)q * S.nx + i];
+  dS[S.o_cell + i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// A2 (+ partial A3): SCB sweep.  One wavefront per (slab, group, half range);
+// lanes own K consecutive cells along the sweep direction.  Per cell the 2x2
+// corner system makes the outflow an affine function of the inflow,
+// I_dn = al I_in + be and I_up = ga I_in + de; a lane composes its K maps and
+// a wavefront prefix scan of the composed maps gives every lane its inflow, so
+// a row of nx cells advances 64 K cells per step instead of one.  Directions
+// of the half range are processed in turn; the cell-average moments
+// sum w Ibar and sum w mu^2 Ibar accumulate in registers.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, ProbDev pd,
+                                               const Item *__restrict__ tab, int nitems, const Ctl *ctl, int pmode,
+                                               int lcyc, const double *__restrict__ kappa,
+                                               const double *__restrict__ Bt, const double *__restrict__ Ip,
+                                               double *__restrict__ Io, double *__restrict__ mom,
+                                               double *__restrict__ bnd) {
+  const int lane = threadIdx.x & 63;
+  const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int item = wv >> 1, half = wv & 1;
+  if (item >= nitems) return;
+  const Item it = tab[item];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  const int g = it.idx, nx = S.nx, ng = S.ng, M = S.nmu, Mh = M >> 1;
+  const int m0 = half ? 0 : Mh;  // mu ascending: mu < 0 first
+  const double inv_cdt = S.inv_cdt;
+  const double *dx = pd.dx + S.o_cell;
+  const double *kp = kappa + S.o_gi + (long long)g * nx;
+  const double *bp = Bt + S.o_gi + (long long)g * nx;
+  const double *ip = Ip + S.o_I + (long long)g * M * nx * 2;
+  double *io = Io + S.o_I + (long long)g * M * nx * 2;
+  const double *mu = pd.mu + S.o_mu;
+  const double *w = pd.w + S.o_mu;
+  double carry = pd.inc[2 * S.o_g + (half ? ng : 0) + g];  // lane j: inflow of direction m0 + j
+  double *mp = mom + 4 * S.o_gi + (long long)half * 2 * ng * nx + (long long)g * nx * 2;
+  const int npass = (nx + 64 * K - 1) / (64 * K);
+  for (int pass = 0; pass < npass; ++pass) {
+    double bb[K], ee[K], phi[K], chi[K];
+    int cell[K];
+    bool ok[K];
+    double hh[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = pass * 64 * K + lane * K + k;
+      ok[k] = q < nx;
+      const int i = half ? nx - 1 - q : q;
+      cell[k] = ok[k] ? i : 0;
+      double dxi = 0.0, kap = 0.0, bpl = 0.0;
+      if (ok[k]) {
+        dxi = dx[i];
+        kap = kp[i];
+        bpl = bp[i];
+      }
+      bb[k] = 0.5 * (kap + inv_cdt) * dxi;
+      ee[k] = 0.5 * dxi * kap * bpl;
+      hh[k] = 0.5 * dxi * inv_cdt;
+      phi[k] = 0.0;
+      chi[k] = 0.0;
+    }
+    for (int j = 0; j < Mh; ++j) {
+      const int m = m0 + j;
+      const double mum = mu[m], wm = w[m];
+      const double amu = fabs(mum), a = 0.5 * amu, a2 = a * a, aamu = a * amu;
+      const double wmu2 = wm * mum * mum;
+      const double *row = ip + (long long)m * nx * 2;
+      double al[K], be[K], ga[K], de[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (ok[k]) {
+          const double2 v = *reinterpret_cast<const double2 *>(row + 2 * cell[k]);
+          const double up = half ? v.y : v.x;
+          const double dn = half ? v.x : v.y;
+          const double s_up = fma(hh[k], up, ee[k]);
+          const double s_dn = fma(hh[k], dn, ee[k]);
+          const double apb = a + bb[k];
+          const double r = 1.0 / fma(apb, apb, a2);
+          al[k] = aamu * r;
+          ga[k] = apb * amu * r;
+          be[k] = fma(apb, s_dn, a * s_up) * r;
+          de[k] = fma(apb, s_up, -a * s_dn) * r;
+        } else {
+          al[k] = 1.0;
+          be[k] = 0.0;
+          ga[k] = 0.0;
+          de[k] = 0.0;
+        }
+      }
+      double A = al[0], Bc = be[0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) {
+        Bc = fma(al[k], Bc, be[k]);
+        A = al[k] * A;
+      }
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const double Ap = __shfl_up(A, d);
+        const double Bp = __shfl_up(Bc, d);
+        if (lane >= d) {
+          Bc = fma(A, Bp, Bc);
+          A = A * Ap;
+        }
+      }
+      const double Ae = __shfl_up(A, 1);
+      const double Be = __shfl_up(Bc, 1);
+      const double cin = __shfl(carry, j);
+      double Iin = (lane == 0) ? cin : fma(Ae, cin, Be);
+      double *orow = io + (long long)m * nx * 2;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double Iup = fma(ga[k], Iin, de[k]);
+        const double Idn = fma(al[k], Iin, be[k]);
+        if (ok[k]) {
+          double2 o;
+          o.x = half ? Idn : Iup;
+          o.y = half ? Iup : Idn;
+          *reinterpret_cast<double2 *>(orow + 2 * cell[k]) = o;
+          const double Ibar = 0.5 * (Iup + Idn);
+          phi[k] = fma(wm, Ibar, phi[k]);
+          chi[k] = fma(wmu2, Ibar, chi[k]);
+        }
+        Iin = Idn;
+      }
+      const double cout = __shfl(Iin, 63);
+      if (lane == j) carry = cout;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (ok[k]) {
+        double2 o;
+        o.x = phi[k];
+        o.y = chi[k];
+        *reinterpret_cast<double2 *>(mp + 2 * cell[k]) = o;
+      }
+    }
+  }
+  // outflow-edge sums of this half range: carry = intensity leaving the slab
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (lane < Mh) {
+    const double wl = w[m0 + lane], ml = mu[m0 + lane];
+    s0 = wl * carry;
+    s1 = wl * ml * carry;
+    s2 = wl * ml * ml * carry;
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    s0 += __shfl_xor(s0, d);
+    s1 += __shfl_xor(s1, d);
+    s2 += __shfl_xor(s2, d);
+  }
+  if (lane == 0) {
+    double *bo = bnd + 6 * S.o_g + (long long)half * 3 * ng + 3 * g;
+    bo[0] = s0;
+    bo[1] = s1;
+    bo[2] = s2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A3: QD factors from the half-range partials.  Thread = (slab, g, i); the
+// i = 0 thread of each group also forms the boundary factors.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_moments(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                 const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
+                                                 const double *__restrict__ mom, const double *__restrict__ bnd,
+                                                 double *__restrict__ f, double *__restrict__ fbnd,
+                                                 double *__restrict__ C, double *__restrict__ Phi) {
+  const Item it = tab[blockIdx.x];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ng = S.ng;
+  const int idx = it.idx + threadIdx.x;
+  if (idx >= ng * nx) return;
+  const int g = idx / nx, i = idx - g * nx;
+  const double *h0 = mom + 4 * S.o_gi + 2LL * idx;
+  const double *h1 = h0 + 2LL * ng * nx;
+  const double phi = h0[0] + h1[0];
+  const double chi = h0[1] + h1[1];
+  f[S.o_gi + idx] = (phi > 0.0 && chi > 0.0) ? chi / phi : S.f_iso;
+  if (i != 0) return;
+  const double inl = pd.inc[2 * S.o_g + g], inr = pd.inc[2 * S.o_g + ng + g];
+  const double *b0 = bnd + 6 * S.o_g + 3 * g;            // mu > 0: leaves at x = X
+  const double *b1 = bnd + 6 * S.o_g + 3 * ng + 3 * g;   // mu < 0: leaves at x = 0
+  const long long o2 = 2 * S.o_g + 2 * g;
+  // x = 0
+  {
+    const double den = b1[0] + inl * S.wpos, num = b1[2] + inl * S.wmu2pos;
+    fbnd[o2] = (den > 0.0 && num > 0.0) ? num / den : S.f_iso;
+    const double Cm = (b1[0] > 0.0) ? b1[1] / b1[0] : -S.c_iso;
+    C[o2] = Cm;
+    Phi[o2] = inl * S.wmupos - S.c * Cm * (inl * S.wpos / S.c);
+  }
+  // x = X
+  {
+    const double den = b0[0] + inr * S.wneg, num = b0[2] + inr * S.wmu2neg;
+    fbnd[o2 + 1] = (den > 0.0 && num > 0.0) ? num / den : S.f_iso;
+    const double Cp = (b0[0] > 0.0) ? b0[1] / b0[0] : S.c_iso;
+    C[o2 + 1] = Cp;
+    Phi[o2 + 1] = inr * S.wmuneg - S.c * Cp * (inr * S.wneg / S.c);
+  }
+}
+
+// Phi = F_in - c C E_in from given C and the current incoming (step start).
+__global__ __launch_bounds__(256) void k_phi(const SlabDev *__restrict__ sd, ProbDev pd,
+                                             const Item *__restrict__ tab, const double *__restrict__ C,
+                                             double *__restrict__ Phi) {
+  const Item it = tab[blockIdx.x];
+  const SlabDev &S = sd[it.slab];
+  const int g = it.idx + threadIdx.x;
+  if (g >= S.ng) return;
+  const double inl = pd.inc[2 * S.o_g + g], inr = pd.inc[2 * S.o_g + S.ng + g];
+  const long long o2 = 2 * S.o_g + 2 * g;
+  Phi[o2] = inl * S.wmupos - S.c * C[o2] * (inl * S.wpos / S.c);
+  Phi[o2 + 1] = inr * S.wmuneg - S.c * C[o2 + 1] * (inr * S.wneg / S.c);
+}
+
+// ---------------------------------------------------------------------------
+// Edge and cell coefficients of one LO level.
+//   edge e (0..nx):  h_e, A_e = h_e / (c dt), a_e, b_e, sigma_R,e, F^old_e
+//   cell i:          sigma_E,i, e_i (emission), E^old_i
+// MODE 0: fine grid from kappa/B tables and QD factors; MODE 1: level arrays.
+// ---------------------------------------------------------------------------
+struct LevelView {
+  int mode;
+  int nx;
+  const double *dx;
+  // fine
+  const double *kap, *Bt, *f, *fbnd;
+  // coarse
+  const double *sigE, *emis, *a, *b, *sigR;
+  // both
+  const double *C, *Phi, *Eold, *Fold;
+};
+
+__device__ inline double lv_h(const LevelView &v, int e) {
+  if (e == 0) return 0.5 * v.dx[0];
+  if (e == v.nx) return 0.5 * v.dx[v.nx - 1];
+  return 0.5 * (v.dx[e - 1] + v.dx[e]);
+}
+
+__device__ inline void lv_edge(const LevelView &v, int e, double &ae, double &be, double &sr) {
+  const int nx = v.nx;
+  if (v.mode == 0) {
+    ae = (e < nx) ? v.f[e] : v.fbnd[1];
+    be = (e > 0) ? v.f[e - 1] : v.fbnd[0];
+    if (e == 0)
+      sr = v.kap[0];
+    else if (e == nx)
+      sr = v.kap[nx - 1];
+    else
+      sr = (v.kap[e - 1] * v.dx[e - 1] + v.kap[e] * v.dx[e]) / (v.dx[e - 1] + v.dx[e]);
+  } else {
+    ae = v.a[e];
+    be = v.b[e];
+    sr = v.sigR[e];
+  }
+}
+
+__device__ inline void lv_cell(const LevelView &v, int i, double &se, double &em) {
+  if (v.mode == 0) {
+    se = v.kap[i];
+    em = 2.0 * v.kap[i] * v.Bt[i];
+  } else {
+    se = v.sigE[i];
+    em = v.emis[i];
+  }
+}
+
+// Builds the K rows of this thread; optional per-cell overrides (grey Newton).
+// With eff = true the absorption / emission of the cell of row k come from
+// se_eff[k] / em_eff[k] (the grey level coupled to the MEB).
+template <int K>
+__device__ inline void lo_rows(const LevelView &v, double c, double dt, double inv_cdt, bool eff,
+                               const double (&se_eff)[K], const double (&em_eff)[K], double (&ra)[K],
+                               double (&rb)[K], double (&rc)[K], double (&rd)[K], double (&Ak)[K + 1],
+                               double (&ca)[K + 1], double (&cb)[K + 1]) {
+  const int t = threadIdx.x, nx = v.nx;
+#pragma unroll
+  for (int q = 0; q <= K; ++q) {
+    const int e = t * K - 1 + q;
+    if (e < 0 || e > nx) {
+      Ak[q] = 0.0;
+      ca[q] = 0.0;
+      cb[q] = 0.0;
+      continue;
+    }
+    double ae, be, sr;
+    lv_edge(v, e, ae, be, sr);
+    const double h = lv_h(v, e);
+    const double A = h * inv_cdt;
+    const double ke = 1.0 / (A + sr * h);
+    Ak[q] = ke * A * v.Fold[e];
+    ca[q] = c * ke * ae;
+    cb[q] = c * ke * be;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int j = t * K + k;
+    if (j == 0) {
+      ra[k] = 0.0;
+      rb[k] = cb[k + 1] - c * v.C[0];
+      rc[k] = -ca[k + 1];
+      rd[k] = v.Phi[0] - Ak[k + 1];
+    } else if (j <= nx) {
+      const int i = j - 1;
+      double se, em;
+      if (eff) {
+        se = se_eff[k];
+        em = em_eff[k];
+      } else {
+        lv_cell(v, i, se, em);
+      }
+      const double dxi = v.dx[i];
+      ra[k] = -cb[k];
+      rb[k] = dxi / dt + c * se * dxi + cb[k + 1] + ca[k];
+      rc[k] = -ca[k + 1];
+      rd[k] = dxi * em + dxi / dt * v.Eold[i] - Ak[k + 1] + Ak[k];
+    } else if (j == nx + 1) {
+      ra[k] = -cb[k];
+      rb[k] = ca[k] + c * v.C[1];
+      rc[k] = 0.0;
+      rd[k] = Ak[k] - v.Phi[1];
+    } else {
+      ra[k] = 0.0;
+      rb[k] = 1.0;
+      rc[k] = 0.0;
+      rd[k] = 0.0;
+    }
+  }
+}
+
+// Writes E, boundary E and F of one system after tri_solve_block.
+template <int K>
+__device__ inline void lo_store(int nx, const double (&x)[K], const double (&Ak)[K + 1], const double (&ca)[K + 1],
+                                const double (&cb)[K + 1], const double *first, double *E, double *F,
+                                double *Ebnd) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int j = t * K + k;
+    if (j == 0)
+      Ebnd[0] = x[k];
+    else if (j <= nx)
+      E[j - 1] = x[k];
+    else if (j == nx + 1)
+      Ebnd[1] = x[k];
+    // flux on edge e = j: u_e = x[k], u_{e+1} = next row
+    if (j <= nx) {
+      const double un = (k + 1 < K) ? x[k + 1] : first[t + 1];  // row j + 1 < T K
+      F[j] = Ak[k + 1] - ca[k + 1] * un + cb[k + 1] * x[k];
+    }
+  }
+}
+
+__device__ inline LevelView make_view(const SlabDev &S, ProbDev pd, int level, const LoIn &in, int p) {
+  LevelView v;
+  v.nx = S.nx;
+  v.dx = pd.dx + S.o_cell;
+  const int nx = S.nx;
+  if (level == 0) {
+    v.mode = 0;
+    const long long gi = S.o_gi + (long long)p * nx, g2 = 2 * S.o_g + 2 * p;
+    v.kap = in.kappa + gi;
+    v.Bt = in.B + gi;
+    v.f = in.f + gi;
+    v.fbnd = in.fbnd + g2;
+    v.C = in.C + g2;
+    v.Phi = in.Phi + g2;
+    v.Eold = in.Eold + gi;
+    v.Fold = in.Fold + S.o_ge + (long long)p * (nx + 1);
+    v.sigE = v.emis = v.a = v.b = v.sigR = nullptr;
+  } else {
+    v.mode = 1;
+    const long long pi = S.o_lpi[level] + (long long)p * nx;
+    const long long pe = S.o_lpe[level] + (long long)p * (nx + 1);
+    const long long p2 = S.o_lp2[level] + 2 * p;
+    v.sigE = in.sigE + pi;
+    v.emis = in.emis + pi;
+    v.a = in.a + pe;
+    v.b = in.b + pe;
+    v.sigR = in.sigR + pe;
+    v.C = in.C + p2;
+    v.Phi = in.Phi + p2;
+    v.Eold = in.Eold + pi;
+    v.Fold = in.Fold + pe;
+    v.kap = v.Bt = v.f = v.fbnd = nullptr;
+  }
+  return v;
+}
+
+__device__ inline void level_out(const SlabDev &S, int level, int p, const LoSol &sol, double *&E, double *&F,
+                                 double *&Eb) {
+  const int nx = S.nx;
+  if (level == 0) {
+    E = sol.E + S.o_gi + (long long)p * nx;
+    F = sol.F + S.o_ge + (long long)p * (nx + 1);
+    Eb = sol.Ebnd + 2 * S.o_g + 2 * p;
+  } else {
+    E = sol.E + S.o_lpi[level] + (long long)p * nx;
+    F = sol.F + S.o_lpe[level] + (long long)p * (nx + 1);
+    Eb = sol.Ebnd + S.o_lp2[level] + 2 * p;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A4 / A6: LO solve, one thread block per (slab, group of the level).
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void k_lo(const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab,
+                                            const Ctl *ctl, int pmode, int lcyc, int level, LoIn in, LoSol sol) {
+  __shared__ double lds[8 * 256];
+  const Item it = tab[blockIdx.x];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  const int p = it.idx;
+  const LevelView v = make_view(S, pd, level, in, p);
+  double ra[K], rb[K], rc[K], rd[K], x[K], Ak[K + 1], ca[K + 1], cb[K + 1], dummy[K];
+  lo_rows<K>(v, S.c, S.dt, S.inv_cdt, false, dummy, dummy, ra, rb, rc, rd, Ak, ca, cb);
+  tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
+  double *E, *F, *Eb;
+  level_out(S, level, p, sol, E, F, Eb);
+  lo_store<K>(S.nx, x, Ak, ca, cb, lds, E, F, Eb);
+}
+
+// ---------------------------------------------------------------------------
+// A5: restriction.  Sum records per (block of finer groups, edge e): e < nx
+// also carries the sums of cell e, e = 0 / nx the boundary sums of side 0 / 1.
+// ---------------------------------------------------------------------------
+enum {
+  R_E = 0, R_SEE, R_SE, R_EM, R_EOLD,       // cell
+  R_ER, R_AER, R_A, R_EL, R_BEL, R_B,       // edge: right / left weights
+  R_AF, R_SAF, R_S, R_SF, R_F, R_FOLD,      // edge: |F| weights, flux sums
+  R_EB, R_CEB, R_C, R_PHI,                  // boundary side
+  R_N
+};
+
+struct SrcView {
+  LevelView v;
+  const double *E, *F, *Eb;  // solution of the source level (group p)
+};
+
+__device__ inline void accumulate(const SrcView &s, int e, double (&r)[R_N]) {
+  const int nx = s.v.nx;
+  if (e < nx) {
+    double se, em;
+    lv_cell(s.v, e, se, em);
+    const double E = s.E[e];
+    r[R_E] += E;
+    r[R_SEE] += se * E;
+    r[R_SE] += se;
+    r[R_EM] += em;
+    r[R_EOLD] += s.v.Eold[e];
+  }
+  double ae, be, sr;
+  lv_edge(s.v, e, ae, be, sr);
+  const double ER = (e < nx) ? s.E[e] : s.Eb[1];
+  const double EL = (e > 0) ? s.E[e - 1] : s.Eb[0];
+  const double F = s.F[e];
+  r[R_ER] += ER;
+  r[R_AER] += ae * ER;
+  r[R_A] += ae;
+  r[R_EL] += EL;
+  r[R_BEL] += be * EL;
+  r[R_B] += be;
+  r[R_AF] += fabs(F);
+  r[R_SAF] += sr * fabs(F);
+  r[R_S] += sr;
+  r[R_SF] += sr * F;
+  r[R_F] += F;
+  r[R_FOLD] += s.v.Fold[e];
+  if (e == 0 || e == nx) {
+    const int side = (e == 0) ? 0 : 1;
+    const double Eb = s.Eb[side];
+    const double Cs = s.v.C[side];
+    r[R_EB] += Eb;
+    r[R_CEB] += Cs * Eb;
+    r[R_C] += Cs;
+    r[R_PHI] += s.v.Phi[side];
+  }
+}
+
+// Final coefficients of coarse group p at edge e from the block sums.
+__device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int e, int r, const double (&s)[R_N],
+                                const LoOut &o) {
+  const int nx = S.nx;
+  const double rinv = 1.0 / r;
+  const double c = S.c;
+  const long long pi = S.o_lpi[to] + (long long)p * nx;
+  const long long pe = S.o_lpe[to] + (long long)p * (nx + 1);
+  const long long p2 = S.o_lp2[to] + 2 * p;
+  if (e < nx) {
+    o.sigE[pi + e] = (s[R_E] > 0.0) ? s[R_SEE] / s[R_E] : s[R_SE] * rinv;
+    o.emis[pi + e] = s[R_EM];
+    o.Eold[pi + e] = s[R_EOLD];
+    o.Esum[pi + e] = s[R_E];
+  }
+  const double abar = (s[R_ER] > 0.0) ? s[R_AER] / s[R_ER] : s[R_A] * rinv;
+  const double bbar = (s[R_EL] > 0.0) ? s[R_BEL] / s[R_EL] : s[R_B] * rinv;
+  const double sR = (s[R_AF] > 0.0) ? s[R_SAF] / s[R_AF] : s[R_S] * rinv;
+  const double *dx = pd.dx + S.o_cell;
+  const double h = (e == 0) ? 0.5 * dx[0] : (e == nx) ? 0.5 * dx[nx - 1] : 0.5 * (dx[e - 1] + dx[e]);
+  const double xi = h * (s[R_SF] - sR * s[R_F]);
+  const double eh = (xi > 0.0 && s[R_ER] > 0.0) ? xi / (c * s[R_ER]) : 0.0;
+  const double ec = (xi < 0.0 && s[R_EL] > 0.0) ? -xi / (c * s[R_EL]) : 0.0;
+  o.a[pe + e] = abar + eh;
+  o.b[pe + e] = bbar + ec;
+  o.sigR[pe + e] = sR;
+  o.Fold[pe + e] = s[R_FOLD];
+  if (e == 0 || e == nx) {
+    const int side = (e == 0) ? 0 : 1;
+    o.C[p2 + side] = (s[R_EB] > 0.0) ? s[R_CEB] / s[R_EB] : s[R_C] * rinv;
+    o.Phi[p2 + side] = s[R_PHI];
+  }
+}
+
+__device__ inline SrcView make_src(const SlabDev &S, ProbDev pd, int from, const LoIn &in, const LoSol &sol, int g) {
+  SrcView s;
+  s.v = make_view(S, pd, from, in, g);
+  double *E, *F, *Eb;
+  level_out(S, from, g, sol, E, F, Eb);
+  s.E = E;
+  s.F = F;
+  s.Eb = Eb;
+  return s;
+}
+
+// Restriction with r <= 64 groups per coarse group: thread = (slab, p, e).
+// r > 64: first pass writes raw sums per 64-group chunk (FINAL = false), the
+// second pass (k_restrict_final) adds the chunks of each coarse group.
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                  const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
+                                                  int from, int to, LoIn in, LoSol sol, LoOut out,
+                                                  double *__restrict__ red) {
+  const Item it = tab[blockIdx.x];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ne = nx + 1;
+  const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
+  const int r = nfrom / nto;
+  const int rc = FINAL ? r : 64;
+  const int nout = nfrom / rc;  // coarse groups (FINAL) or chunks
+  const int idx = it.idx + threadIdx.x;
+  if (idx >= nout * ne) return;
+  const int q = idx / ne, e = idx - q * ne;
+  double acc[R_N];
+#pragma unroll
+  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
+  for (int g = q * rc; g < (q + 1) * rc; ++g) {
+    const SrcView s = make_src(S, pd, from, in, sol, g);
+    accumulate(s, e, acc);
+  }
+  if (FINAL) {
+    finalize(S, pd, to, q, e, r, acc, out);
+  } else {
+    double *rec = red + S.o_red + ((long long)q * ne + e) * R_N;
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) rec[k] = acc[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                        const Item *__restrict__ tab, const Ctl *ctl, int pmode,
+                                                        int lcyc, int from, int to, LoOut out,
+                                                        const double *__restrict__ red) {
+  const Item it = tab[blockIdx.x];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ne = nx + 1;
+  const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
+  const int r = nfrom / nto;
+  const int per = r / 64;
+  const int idx = it.idx + threadIdx.x;
+  if (idx >= nto * ne) return;
+  const int p = idx / ne, e = idx - p * ne;
+  double acc[R_N];
+#pragma unroll
+  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
+  for (int q = p * per; q < (p + 1) * per; ++q) {
+    const double *rec = red + S.o_red + ((long long)q * ne + e) * R_N;
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) acc[k] += rec[k];
+  }
+  finalize(S, pd, to, p, e, r, acc, out);
+}
+
+// ---------------------------------------------------------------------------
+// A7 + A8: grey LOQD + MEB (one Newton iteration) per slab, one thread block;
+// at the end of a cycle it also applies the inner / outer convergence tests.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void k_grey(const SlabDev *__restrict__ sd, ProbDev pd,
+                                              const Item *__restrict__ tab, Ctl *ctl, int pmode, int lcyc,
+                                              GreyArgs ga) {
+  __shared__ double lds[8 * 256];
+  __shared__ int s_flag[2];
+  const Item it = tab[blockIdx.x];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const int slab = it.slab;
+  const SlabDev &S = sd[slab];
+  const int nx = S.nx, t = threadIdx.x;
+  const int gl = S.nlev - 1;
+  const double c = S.c, dt = S.dt, cv = S.cv;
+  const double *Tst = ga.Tstar + S.o_cell;
+  const bool use_prev = ctl ? (ctl[slab].has_prev && ga.secant) : false;
+  // per-cell Newton coefficients for the cells of this thread's rows
+  double alpha[K], beta[K], se_eff[K], em_eff[K];
+  const long long pi = S.o_lpi[gl];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t * K + k - 1;
+    alpha[k] = beta[k] = se_eff[k] = em_eff[k] = 0.0;
+    if (i < 0 || i >= nx) continue;
+    double dS = 0.0;
+    if (ga.dS)
+      dS = ga.dS[S.o_cell + i];
+    else
+      for (int q = 0; q < S.nchunk; ++q) dS += ga.dSpart[S.o_chunk + (long long)q * nx + i];
+    const double Ts = Tst[i];
+    const double sig = ga.grey.sigE[pi + i];
+    const double Sst = ga.grey.emis[pi + i];
+    const double Es = ga.Estar[pi + i];
+    double D = 0.0;
+    if (ga.D) {
+      D = ga.D[S.o_cell + i];
+    } else if (use_prev) {
+      const double dT = Ts - ga.Tprev[S.o_cell + i];
+      if (fabs(dT) > 1e-8 * fabs(Ts)) D = (sig - ga.sigprev[S.o_cell + i]) / dT;
+      if (c * D * Es > 0.5 * (cv / dt + dS)) D = 0.0;
+    }
+    const double den = cv / dt + dS - c * D * Es;
+    const double al = (cv * (ga.Told[S.o_cell + i] - Ts) / dt - Sst) / den;
+    const double be = c * sig / den;
+    const double gg = c * D * Es - dS;
+    alpha[k] = al;
+    beta[k] = be;
+    se_eff[k] = sig + gg * be / c;
+    em_eff[k] = Sst - gg * al;
+  }
+  // rows: the grey level view with effective absorption / emission
+  LevelView v = make_view(S, pd, gl, ga.grey, 0);
+  double ra[K], rb[K], rc[K], rd[K], x[K], Ak[K + 1], ca[K + 1], cb[K + 1];
+  // row k of this thread is cell t K + k - 1: the Newton coefficients above
+  lo_rows<K>(v, c, dt, S.inv_cdt, true, se_eff, em_eff, ra, rb, rc, rd, Ak, ca, cb);
+  tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
+  double *E = ga.sol.E + pi, *F = ga.sol.F + S.o_lpe[gl], *Eb = ga.sol.Ebnd + S.o_lp2[gl];
+  lo_store<K>(nx, x, Ak, ca, cb, lds, E, F, Eb);
+  // temperature update, secant memory, norms
+  double dTc = 0.0, dEc = 0.0, dTs = 0.0, dEs = 0.0, Tmax = 0.0, Emax = 0.0;
+  int nfl = 0;
+  double *Tout = ga.Tout + S.o_cell;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t * K + k - 1;
+    if (i < 0 || i >= nx) continue;
+    const double Ts = Tst[i];
+    double Tn = Ts + alpha[k] + beta[k] * x[k];
+    if (Tn < 0.5 * Ts) {
+      Tn = 0.5 * Ts;
+      ++nfl;
+    }
+    if (ctl) {
+      ga.Tprev[S.o_cell + i] = Ts;
+      ga.sigprev[S.o_cell + i] = ga.grey.sigE[pi + i];
+    }
+    Tout[i] = Tn;
+    const double En = x[k];
+    if (ga.Egrey) ga.Egrey[S.o_cell + i] = En;
+    if (ga.end_cycle) {
+      dTc = fmax(dTc, fabs(Tn - ga.Tcyc[S.o_cell + i]));
+      dEc = fmax(dEc, fabs(En - ga.Ecyc[S.o_cell + i]));
+      dTs = fmax(dTs, fabs(Tn - ga.Ts[S.o_cell + i]));
+      dEs = fmax(dEs, fabs(En - ga.Es[S.o_cell + i]));
+      // NaN propagates through fmax as the other argument; flag it explicitly
+      Tmax = (Tn == Tn) ? fmax(Tmax, fabs(Tn)) : INFINITY;
+      Emax = (En == En) ? fmax(Emax, fabs(En)) : INFINITY;
+    }
+  }
+  if (!ctl) return;
+  // floor counter (exact integer sum through LDS)
+  {
+    int *il = reinterpret_cast<int *>(lds);
+    __syncthreads();
+    il[t] = nfl;
+    __syncthreads();
+    if (t == 0) {
+      long long sum = 0;
+      for (int q = 0; q < (int)blockDim.x; ++q) sum += il[q];
+      ctl[slab].n_floor += sum;
+      ctl[slab].has_prev = 1;
+    }
+    __syncthreads();
+  }
+  if (!ga.end_cycle) return;
+  dTc = block_max(dTc, lds);
+  dEc = block_max(dEc, lds);
+  dTs = block_max(dTs, lds);
+  dEs = block_max(dEs, lds);
+  Tmax = block_max(Tmax, lds);
+  Emax = block_max(Emax, lds);
+  if (t == 0) {
+    Ctl &cc = ctl[slab];
+    cc.ncyc += 1;
+    cc.n_c += 1;
+    cc.n_lo += ga.cyc_cost[slab];
+    int inner_done, outer_done = 0;
+    if (!isfinite(Tmax) || !isfinite(Emax)) {
+      cc.err = -5;
+      inner_done = 1;
+      outer_done = 1;
+    } else {
+      const bool conv_in = dTc <= ga.eps_inner * Tmax && dEc <= ga.eps_inner * Emax;
+      if (cc.n_replay > 0)
+        inner_done = cc.ncyc >= cc.replay[cc.s];
+      else
+        inner_done = conv_in || cc.ncyc >= ga.lmax;
+      if (inner_done) {
+        if (cc.s < TR_MAXOUT) cc.cycles[cc.s] = cc.ncyc;
+        const bool conv_out = cc.s >= 1 && dTs <= ga.eps * Tmax && dEs <= ga.eps * Emax;
+        outer_done = (cc.n_replay > 0) ? (cc.s + 1 >= cc.n_replay) : conv_out;
+      }
+    }
+    cc.inner_done = inner_done;
+    s_flag[0] = inner_done;
+    s_flag[1] = outer_done;
+  }
+  __syncthreads();
+  const int inner_done = s_flag[0];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t * K + k - 1;
+    if (i < 0 || i >= nx) continue;
+    const double Tn = Tout[i];
+    const double En = x[k];
+    ga.Tcyc[S.o_cell + i] = Tn;
+    ga.Ecyc[S.o_cell + i] = En;
+    if (inner_done) {
+      ga.Ts[S.o_cell + i] = Tn;
+      ga.Es[S.o_cell + i] = En;
+    }
+  }
+  // deactivation is published last so that the cell arrays above are final
+  __syncthreads();
+  if (t == 0 && s_flag[1]) ctl[slab].active = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Control and state kernels.
+// ---------------------------------------------------------------------------
+// Start of a transport iteration s >= 1 (one thread per slab).
+__global__ void k_outer_begin(Ctl *ctl, int nslab, int max_outer) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslab) return;
+  Ctl &c = ctl[s];
+  if (!c.active || !c.inner_done) return;
+  c.s += 1;
+  if (c.s > max_outer || (c.n_replay > 0 && c.s >= c.n_replay)) {
+    if (c.n_replay == 0) c.err = -4;
+    c.active = 0;
+    return;
+  }
+  c.inner_done = 0;
+  c.ncyc = 0;
+  c.n_ti += 1;
+}
+
+__global__ void k_count_active(const Ctl *ctl, int nslab, int *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int n = 0;
+  for (int s = 0; s < nslab; ++s) n += ctl[s].active;
+  *out = n;
+}
+
+// Elementwise copy over a pooled range.
+__global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src, double *__restrict__ dst, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// Fills a pooled cell array with a constant.
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ dst, double v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+
+// Initial state from the B table at T0: I^0 = B in every corner/direction,
+// E = sum w B / c, F = 0 (edges), synthetic sweep partials of I^0 for the
+// moments kernel.  Thread = (slab, g, i).
+__global__ __launch_bounds__(256) void k_init_state(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                    const Item *__restrict__ tab, const double *__restrict__ Bt,
+                                                    double *__restrict__ I, double *__restrict__ E,
+                                                    double *__restrict__ F, double *__restrict__ Ebnd,
+                                                    double *__restrict__ mom, double *__restrict__ bnd) {
+  const Item it = tab[blockIdx.x];
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ng = S.ng, M = S.nmu;
+  const int idx = it.idx + threadIdx.x;
+  if (idx >= ng * nx) return;
+  const int g = idx / nx, i = idx - g * nx;
+  const double b = Bt[S.o_gi + idx];
+  double *ip = I + S.o_I + ((long long)g * M * nx + i) * 2;
+  for (int m = 0; m < M; ++m) {
+    ip[(long long)m * nx * 2] = b;
+    ip[(long long)m * nx * 2 + 1] = b;
+  }
+  const double Ec = b * (S.wpos + S.wneg) / S.c;
+  E[S.o_gi + idx] = Ec;
+  F[S.o_ge + (long long)g * (nx + 1) + i] = 0.0;
+  if (i == nx - 1) F[S.o_ge + (long long)g * (nx + 1) + nx] = 0.0;
+  double *h0 = mom + 4 * S.o_gi + 2LL * idx;
+  double *h1 = h0 + 2LL * ng * nx;
+  h0[0] = b * S.wpos;
+  h0[1] = b * S.wmu2pos;
+  h1[0] = b * S.wneg;
+  h1[1] = b * S.wmu2neg;
+  if (i == 0) {
+    Ebnd[2 * S.o_g + 2 * g] = Ec;
+    double *b1 = bnd + 6 * S.o_g + 3 * ng + 3 * g;  // mu < 0 leaves at x = 0
+    b1[0] = b * S.wneg;
+    b1[1] = b * S.wmuneg;
+    b1[2] = b * S.wmu2neg;
+  }
+  if (i == nx - 1) {
+    Ebnd[2 * S.o_g + 2 * g + 1] = Ec;
+    double *b0 = bnd + 6 * S.o_g + 3 * g;  // mu > 0 leaves at x = X
+    b0[0] = b * S.wpos;
+    b0[1] = b * S.wmupos;
+    b0[2] = b * S.wmu2pos;
+  }
+}
+
+// Grey energy density of the fine spectrum: Egrey_i = sum_g E_g,i.  Thread = cell.
+__global__ __launch_bounds__(256) void k_group_sum(const SlabDev *__restrict__ sd, const Item *__restrict__ tab,
+                                                   const double *__restrict__ E, double *__restrict__ out) {
+  const Item it = tab[blockIdx.x];
+  const SlabDev &S = sd[it.slab];
+  const int i = it.idx + threadIdx.x;
+  if (i >= S.nx) return;
+  double acc = 0.0;
+  for (int g = 0; g < S.ng; ++g) acc += E[S.o_gi + (long long)g * S.nx + i];
+  out[S.o_cell + i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static inline dim3 blocks(int n) { return dim3((unsigned)n); }
+
+void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *T,
+                    double *kappa, double *B, double *dSpart) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_opacity, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, lcyc, T,
+                     kappa, B, dSpart);
+}
+
+void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart, double *dS) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_dS_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, dSpart, dS);
+}
+
+void launch_sweep(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *kappa,
+                  const double *B, const double *Ip, double *Io, double *mom, double *bnd) {
+  if (tab.n == 0) return;
+  const int waves = 2 * tab.n;
+  const int nb = (waves + 3) / 4;
+  hipLaunchKernelGGL(k_sweep<4>, blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n, ctl, pmode, lcyc,
+                     kappa, B, Ip, Io, mom, bnd);
+}
+
+void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
+                    const double *bnd, double *f, double *fbnd, double *C, double *Phi) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_moments, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, lcyc, mom,
+                     bnd, f, fbnd, C, Phi);
+}
+
+void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_phi, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, C, Phi);
+}
+
+void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
+               const LoIn &in, const LoSol &sol) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_lo<TR_LO_K>, blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
+                     lcyc, level, in, sol);
+}
+
+void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
+                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red) {
+  if (rt.single.n)
+    hipLaunchKernelGGL(k_restrict<true>, blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.single.d,
+                       ctl, pmode, lcyc, from, to, in, sol, out, red);
+  if (rt.part.n)
+    hipLaunchKernelGGL(k_restrict<false>, blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.part.d, ctl,
+                       pmode, lcyc, from, to, in, sol, out, red);
+  if (rt.fin.n)
+    hipLaunchKernelGGL(k_restrict_final, blocks(rt.fin.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.fin.d, ctl,
+                       pmode, lcyc, from, to, out, red);
+}
+
+void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
+                 const GreyArgs &ga) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_grey<TR_LO_K>, blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
+                     lcyc, ga);
+}
+
+void launch_outer_begin(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer) {
+  hipLaunchKernelGGL(k_outer_begin, dim3((nslab + 255) / 256), dim3(256), 0, env.stream, ctl, nslab, max_outer);
+}
+
+void launch_count_active(const LaunchEnv &env, const Ctl *ctl, int nslab, int *out) {
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, env.stream, ctl, nslab, out);
+}
+
+void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, src, dst, n);
+}
+
+void launch_fill(const LaunchEnv &env, double *dst, double v, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, dst, v, n);
+}
+
+void launch_init_state(const LaunchEnv &env, const Table &tab, const double *Bt, double *I, double *E, double *F,
+                       double *Ebnd, double *mom, double *bnd) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_init_state, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, Bt, I, E, F, Ebnd,
+                     mom, bnd);
+}
+
+void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, double *out) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_group_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, E, out);
+}
+
+int upload_head_coef(const double *coef) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(tr_head_coef), coef, sizeof(double) * TR_NHEAD) == hipSuccess ? 0 : -3;
+}
