@@ -1,0 +1,173 @@
+"""Benchmark: converged backward-Euler time steps of the MLQD method with
+multigrid in frequency on one MI355X.
+
+A "step" is one converged time step of the whole hot path (opacity/Planck
+tables, SCB transport sweeps with their moments, fine and coarse LO solves,
+restriction, grey LO + MEB Newton, cycle control) over the workload's slab.
+The default workload is the paper-scale problem: 200 cells, S16, 512 groups,
+V cycle on the hierarchy 512,128,32,8,1, dt = 0.002 ns; the timed region is
+the workload's 20 steps from the initial condition (inputs resident in HBM).
+
+Printed: one JSON line with the throughput in phase-space cell-updates per
+second (sweep cell-updates of the timed steps / wall time), ms per step,
+the live-measured roofline of the dominant kernel (the sweep) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    "paper": ("config_paper_scale",
+              "paper-scale slab: 200 cells, S16 Gauss-Legendre, 512 log groups on [0.01,100] keV, "
+              "V cycle on 512,128,32,8,1, dt=0.002 ns, eps=1e-10"),
+    "small": ("config_small",
+              "small slab: 50 cells, S8, 16 groups, two-grid V 16,1, dt=0.002 ns, eps=1e-10"),
+    "large": ("config_large",
+              "large slab: 2000 cells, S32, 4096 groups, F cycle on 4096,1024,256,64,16,1, dt=0.002 ns, "
+              "eps=1e-10"),
+}
+
+
+def sweep_bytes_per_cell_update(M):
+    """Algorithmic HBM bytes of one FP64 SCB cell-update: read I^{j-1} (two
+    corners, 16 B) and write I (16 B); plus the half-range moment partials
+    (two doubles per cell, group and half range, shared by M/2 directions)."""
+    return 32.0 + 16.0 * 2 / M
+
+
+def cpu_baseline(slab, cfg, budget_s=20.0):
+    """The CPU oracle (numpy, FP64) on the first time steps of the workload,
+    bounded to about budget_s seconds."""
+    import numpy as np  # noqa: F401
+
+    from oracle import mlqd
+
+    pb = mlqd.problem_from_slab(slab)
+    st = mlqd.initial_state(pb, slab.T0)
+    stats = mlqd.Stats()
+    t0 = time.perf_counter()
+    nsteps = 0
+    while True:
+        st = mlqd.step(pb, cfg.levels, cfg.schedule(), cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
+        nsteps += 1
+        if time.perf_counter() - t0 > budget_s * 0.5:
+            break
+    dt = time.perf_counter() - t0
+    cu = slab.cell_updates_per_sweep() * stats.n_ti
+    threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    return {
+        "value": cu / dt,
+        "unit": "cell-updates/s",
+        "cores": 1 if threads <= 1 else threads,
+        "kind": "oracle",
+        "ms_per_step": 1e3 * dt / nsteps,
+        "sample": f"first {nsteps} time step(s) of the same workload ({stats.n_ti} sweeps), numpy FP64, "
+                  f"{dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the design notes describe how the path would shard)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2011_05427_amd import binding, inputs
+
+    fn, desc = WORKLOADS[args.workload]
+    slabs, cfg, nsteps_cfg = getattr(inputs, fn)()
+    slab = slabs[0]
+    torch.cuda.set_device(0)
+    sv = binding.Solver([slab], [cfg.levels], cfg, timing=True)
+    st = sv.new_state()
+
+    # warmup from the initial condition
+    sv.state_init(st, slab.T0)
+    for _ in range(args.warmup):
+        sv.step(st)
+    torch.cuda.synchronize()
+
+    # timed: K steps from the initial condition
+    sv.state_init(st, slab.T0)
+    torch.cuda.synchronize()
+    acc = (binding.TrStats * 1)()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sv.step(st, stats=acc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    a = acc[0]
+    cu_sweep = slab.cell_updates_per_sweep()
+    sweeps = a.n_ti
+    value = cu_sweep * sweeps / wall
+    t_sweep_ms = a.t_ms[binding.T_SWEEP]
+    n_sweep = a.n_launch[binding.T_SWEEP]
+    avg_sweep_s = t_sweep_ms / max(n_sweep, 1) / 1e3
+    bytes_per_launch = sweep_bytes_per_cell_update(slab.nmu) * cu_sweep
+    achieved = bytes_per_launch / avg_sweep_s / 1e9 if avg_sweep_s > 0 else 0.0
+    kernel_ms = {name: a.t_ms[k] / max(args.steps, 1) for k, name in
+                 enumerate(["opacity", "sweep", "moments", "lo_fine", "restrict", "lo_coarse", "grey"])}
+
+    out = {
+        "metric": "phase-space cell-updates/s per sweep; ms per converged time step, learned vs plain",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "nx": slab.nx, "groups": slab.ng, "directions": slab.nmu,
+            "levels": cfg.levels, "cycle": "VWF"[cfg.cycle], "lmax": cfg.lmax,
+            "steps_timed": args.steps, "cell_updates_per_sweep": cu_sweep,
+            "sweeps": int(sweeps), "cycles": int(a.n_c), "lo_solves": int(a.n_lo),
+            "closure": "plain",
+        },
+        "kernel_ms_per_step": kernel_ms,
+        "sweep_kernel_cell_updates_per_s": cu_sweep / avg_sweep_s if avg_sweep_s > 0 else None,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_sweep",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": avg_sweep_s * 1e6,
+            "launches": int(n_sweep),
+        },
+    }
+    sv.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(slab, cfg, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,6 +103,8 @@ typedef struct tr_solver_cfg {
   int max_outer;    /* transport iterations before TR_ENOCONV */
   int secant;       /* 1: diagonal secant Frechet derivative of the grey
                        sigma_E (Eq. f-derivative-d); 0: D = 0 */
+  int timing;       /* 1: tr_step brackets its kernel groups with HIP events
+                       and accumulates their durations in tr_stats.t_ms */
 } tr_solver_cfg;
 
 typedef struct tr_ctx tr_ctx;
@@ -229,6 +231,9 @@ typedef struct tr_state {
  * (written to I_out; the caller uses I_out as I_prev of the first step). */
 int tr_state_init(tr_ctx *ctx, const tr_state *st, double T0, hipStream_t stream);
 
+enum { TR_T_OPACITY = 0, TR_T_SWEEP = 1, TR_T_MOMENTS = 2, TR_T_LO_FINE = 3, TR_T_RESTRICT = 4,
+       TR_T_LO_COARSE = 5, TR_T_GREY = 6, TR_T_N = 8 };
+
 typedef struct tr_stats {
   long long n_ti;  /* transport sweeps */
   long long n_c;   /* cycles */
@@ -236,6 +241,9 @@ typedef struct tr_stats {
   long long n_floor; /* temperature floor activations */
   int n_outer;     /* transport iterations of the last step incl. s = 0 */
   int cycles[64];  /* cycles per transport iteration of the last step */
+  double t_ms[TR_T_N];     /* with cfg.timing: summed kernel time per group
+                              (TR_T_*), over launches that did work */
+  long long n_launch[TR_T_N]; /* timed launch groups per TR_T_* */
 } tr_stats;
 
 /*

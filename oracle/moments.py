@@ -12,15 +12,21 @@ Edge intensities: at x = 0 the mu > 0 values are the incoming data and the mu < 
 values are the left corners of cell 1; at x = X the mu > 0 values are the right
 corners of cell nx and the mu < 0 values the incoming data.
 
-Zero or negative denominators (groups whose intensity underflowed) fall back to
-the isotropic values of the quadrature: f_iso = sum w mu^2 / sum w and
-C = -/+ sum_{mu>0} w mu / sum_{mu>0} w.
+A ratio whose denominator is below TINY = 1e-290 (zero, negative, or so close
+to the subnormal range that the intensity has lost its precision) falls back to
+the isotropic value of the quadrature: f_iso = sum w mu^2 / sum w and
+C = -/+ sum_{mu>0} w mu / sum_{mu>0} w.  Without the margin a boundary factor
+built from subnormal outgoing intensities jitters between sweeps, and because C
+multiplies E - E_in with a large incoming E_in the jitter keeps the transport
+iterations from converging below ~1e-9.
 """
 from __future__ import annotations
 
 import dataclasses
 
 import numpy as np
+
+TINY = 1e-290
 
 
 @dataclasses.dataclass
@@ -42,13 +48,13 @@ def iso_factors(mu, w):
 
 
 def _ratio(num, den, default):
-    ok = (den > 0) & (num > 0)
+    ok = (den > TINY) & (num > 0)
     out = np.where(ok, num / np.where(ok, den, 1.0), default)
     return out, int(np.count_nonzero(~ok))
 
 
 def _ratio_signed(num, den, default):
-    ok = den > 0
+    ok = den > TINY
     out = np.where(ok, num / np.where(ok, den, 1.0), default)
     return out, int(np.count_nonzero(~ok))
 

@@ -27,14 +27,16 @@ sum-over-groups property the paper states); the right/left coefficients are
 weighted separately by the energy density they multiply; the inhomogeneous part
 of the boundary condition is restricted additively.  With these choices the
 coarse equations are satisfied exactly by the block sums of a finer solution at
-the same temperature.  A weighted average whose weights sum to zero or less
-falls back to the plain block mean.
+the same temperature.  A weighted average whose weights sum to TINY = 1e-290
+or less falls back to the plain block mean, and a compensation term is dropped
+when the energy density it would divide by is that small.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .lo import Level, LOSolution, edge_lengths
+from .moments import TINY
 
 
 def _blocks(x, P):
@@ -52,7 +54,7 @@ def _wavg(psi, H, P):
     num = np.sum(pb * hb, axis=1)
     den = np.sum(hb, axis=1)
     mean = np.mean(pb, axis=1)
-    ok = den > 0
+    ok = den > TINY
     return np.where(ok, num / np.where(ok, den, 1.0), mean)
 
 
@@ -73,8 +75,8 @@ def restrict(lv: Level, sol: LOSolution, P: int, dx, c) -> Level:
     xi = h[None, :] * np.sum((_blocks(lv.sigR, P) - sigR[:, None, :]) * _blocks(sol.F, P), axis=1)
     ERp = np.sum(_blocks(ER, P), axis=1)
     ELp = np.sum(_blocks(EL, P), axis=1)
-    eta_hat = np.where((xi > 0) & (ERp > 0), xi / (c * np.where(ERp > 0, ERp, 1.0)), 0.0)
-    eta_chk = np.where((xi < 0) & (ELp > 0), -xi / (c * np.where(ELp > 0, ELp, 1.0)), 0.0)
+    eta_hat = np.where((xi > 0) & (ERp > TINY), xi / (c * np.where(ERp > TINY, ERp, 1.0)), 0.0)
+    eta_chk = np.where((xi < 0) & (ELp > TINY), -xi / (c * np.where(ELp > TINY, ELp, 1.0)), 0.0)
     C = np.stack([_wavg(lv.C[:, 0], sol.Ebnd[:, 0], P), _wavg(lv.C[:, 1], sol.Ebnd[:, 1], P)], axis=1)
     return Level(
         sigE=sigE,

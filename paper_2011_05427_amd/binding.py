@@ -34,7 +34,7 @@ class TrProblem(C.Structure):
 
 class TrSolverCfg(C.Structure):
     _fields_ = [("cycle", C.c_int), ("lmax", C.c_int), ("eps", C.c_double), ("eps_inner", C.c_double),
-                ("max_outer", C.c_int), ("secant", C.c_int)]
+                ("max_outer", C.c_int), ("secant", C.c_int), ("timing", C.c_int)]
 
 
 class TrLoCoeffs(C.Structure):
@@ -58,7 +58,11 @@ class TrState(C.Structure):
 
 class TrStats(C.Structure):
     _fields_ = [("n_ti", C.c_longlong), ("n_c", C.c_longlong), ("n_lo", C.c_longlong),
-                ("n_floor", C.c_longlong), ("n_outer", C.c_int), ("cycles", C.c_int * 64)]
+                ("n_floor", C.c_longlong), ("n_outer", C.c_int), ("cycles", C.c_int * 64),
+                ("t_ms", C.c_double * 8), ("n_launch", C.c_longlong * 8)]
+
+
+T_OPACITY, T_SWEEP, T_MOMENTS, T_LO_FINE, T_RESTRICT, T_LO_COARSE, T_GREY = range(7)
 
 
 EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_incoming", "tr_opacity",
@@ -123,7 +127,7 @@ class Solver:
     slabs: sequence of ``inputs.Slab``; levels: per-slab list of groups per
     frequency grid (fine first, grey last); cfg: ``inputs.SolverCfg``."""
 
-    def __init__(self, slabs: Sequence, levels: Sequence[Sequence[int]], cfg):
+    def __init__(self, slabs: Sequence, levels: Sequence[Sequence[int]], cfg, timing: bool = False):
         import torch
 
         if not torch.cuda.is_available():
@@ -147,7 +151,7 @@ class Solver:
         self.levels = [list(lv) for lv in levels]
         self.nlev = len(self.levels[0])
         c = TrSolverCfg(cycle=cfg.cycle, lmax=cfg.lmax, eps=cfg.eps, eps_inner=cfg.eps_inner,
-                        max_outer=cfg.max_outer, secant=1 if cfg.secant else 0)
+                        max_outer=cfg.max_outer, secant=1 if cfg.secant else 0, timing=1 if timing else 0)
         self._ctx = C.c_void_p()
         _check(self.lib.tr_create(C.byref(self._ctx), probs, len(self.slabs), C.byref(c)), "tr_create")
         self.n = len(self.slabs)

@@ -55,6 +55,13 @@ struct tr_ctx {
   Table t_opac{}, t_cell{}, t_sweep{}, t_gi{}, t_g{}, t_grey{};
   Table t_lo[TR_MAXLEV]{};
   std::map<std::pair<int, int>, RestrictTables> t_red;
+  // optional event timing of kernel groups inside tr_step
+  struct TimedGroup {
+    int cat, cycle, e0, e1;
+  };
+  std::vector<hipEvent_t> events;
+  int ev_used = 0;
+  std::vector<TimedGroup> groups;
 };
 
 namespace {
@@ -136,7 +143,7 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
     if (r <= 64) {
       for (int st = 0; st < nt * ne; st += 256) single.push_back({s, st});
     } else {
-      const int nchunk = nf / 64;
+      const int nchunk = nt * ((r + 63) / 64);
       for (int st = 0; st < nchunk * ne; st += 256) part.push_back({s, st});
       for (int st = 0; st < nt * ne; st += 256) fin.push_back({s, st});
     }
@@ -151,6 +158,49 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
 }
 
 LaunchEnv env_of(const tr_ctx *c, hipStream_t st) { return LaunchEnv{c->d_sd, c->pd, st}; }
+
+// Event marks around kernel groups (cfg.timing).  A group records its cycle
+// index (-1 outside the cycles) so that launches of cycles a slab skipped can
+// be left out of the sums.
+int tim_mark(tr_ctx *c, hipStream_t st) {
+  if (c->ev_used == (int)c->events.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    c->events.push_back(e);
+  }
+  const int k = c->ev_used++;
+  if (hipEventRecord(c->events[k], st) != hipSuccess) return -1;
+  return k;
+}
+
+struct TimedScope {
+  tr_ctx *c;
+  hipStream_t st;
+  int cat, cycle, e0;
+  TimedScope(tr_ctx *c_, hipStream_t st_, int cat_, int cycle_) : c(c_), st(st_), cat(cat_), cycle(cycle_), e0(-1) {
+    if (c->cfg.timing) e0 = tim_mark(c, st);
+  }
+  ~TimedScope() {
+    if (!c->cfg.timing || e0 < 0) return;
+    const int e1 = tim_mark(c, st);
+    if (e1 >= 0) c->groups.push_back({cat, cycle, e0, e1});
+  }
+};
+
+// After a synchronisation: adds the recorded durations of groups whose cycle
+// ran (cycle < ncyc_ran, or outside the cycles) to the stats of every slab.
+void tim_collect(tr_ctx *c, int ncyc_ran, double *t_ms, long long *n_launch) {
+  for (const auto &g : c->groups) {
+    if (g.cycle >= ncyc_ran) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->events[g.e0], c->events[g.e1]) == hipSuccess) {
+      t_ms[g.cat] += ms;
+      n_launch[g.cat] += 1;
+    }
+  }
+  c->groups.clear();
+  c->ev_used = 0;
+}
 
 LoIn fine_in(const tr_ctx *c, const double *kappa, const double *B, const double *f, const double *fbnd,
              const double *C, const double *Phi, const double *Eold, const double *Fold) {
@@ -227,6 +277,7 @@ const char *tr_error_string(int code) {
 
 int tr_destroy(tr_ctx *c) {
   if (!c) return TR_OK;
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->h_count) (void)hipHostFree(c->h_count);
   delete c;
@@ -252,13 +303,6 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     for (int l = 1; l < nlev; ++l) {
       const int a = P.level_ng[l - 1], b = P.level_ng[l];
       if (b < 1 || a % b) return TR_EINVAL;
-    }
-    // restriction chunks: every restriction ratio used is <= 64 or a multiple of 64
-    for (int l = 1; l < nlev; ++l) {
-      const int r0 = P.ng / P.level_ng[l];
-      if (r0 > 64 && r0 % 64) return TR_EINVAL;
-      const int r1 = P.level_ng[l];  // level l -> grey
-      if (l < nlev - 1 && r1 > 64 && r1 % 64) return TR_EINVAL;
     }
     for (int i = 0; i < P.nx; ++i)
       if (!(P.x_edges[i + 1] > P.x_edges[i])) return TR_EINVAL;
@@ -336,7 +380,16 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     c->n_nu += P.ng + 1;
     c->n_mu += P.nmu;
     c->n_chunk += (long long)S.nchunk * P.nx;
-    c->n_red += (long long)S.nchunk * (P.nx + 1) * 21;
+    {
+      // chunk records of the largest two-pass restriction between any two levels
+      long long worst = 0;
+      for (int a = 0; a < nlev; ++a)
+        for (int b = a + 1; b < nlev; ++b) {
+          const long long r = P.level_ng[a] / P.level_ng[b];
+          if (r > 64) worst = std::max(worst, (long long)P.level_ng[b] * ((r + 63) / 64));
+        }
+      c->n_red += worst * (P.nx + 1) * 21;
+    }
     S.o_lpi[0] = S.o_gi;
     S.o_lpe[0] = S.o_ge;
     S.o_lp2[0] = S.o_g2;
@@ -561,8 +614,7 @@ int tr_restrict(tr_ctx *c, int from, int to, const tr_lo_coeffs *in, const tr_lo
   if (!c || !in || !sol || !out || from < 0 || to <= from || to >= c->nlev) return TR_EINVAL;
   for (int s = 0; s < c->nslab; ++s) {
     const SlabDev &S = c->hs[s];
-    const int r = S.lev_ng[from] / S.lev_ng[to];
-    if (S.lev_ng[from] % S.lev_ng[to] || (r > 64 && r % 64)) return TR_EINVAL;
+    if (S.lev_ng[from] % S.lev_ng[to]) return TR_EINVAL;
   }
   int rc = build_restrict_tables(c, from, to);
   if (rc) return rc;
@@ -666,34 +718,78 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   ga.eps_inner = c->cfg.eps_inner;
 
   const int nsch = (int)c->sched.size();
+  double t_ms[TR_T_N] = {0};
+  long long n_launch[TR_T_N] = {0};
+  c->groups.clear();
+  c->ev_used = 0;
   for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
     if (outer > 0) {
       launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
-      launch_sweep(env, c->t_sweep, c->d_ctl, PRED_SWEEP, 0, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
-      launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
+      {
+        TimedScope ts(c, st, TR_T_SWEEP, -1);
+        launch_sweep(env, c->t_sweep, c->d_ctl, PRED_SWEEP, 0, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
+      }
+      {
+        TimedScope ts(c, st, TR_T_MOMENTS, -1);
+        launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
+      }
     }
     for (int l = 0; l < Lmax; ++l) {
-      launch_lo(env, c->t_lo[0], c->lo_threads, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
-      launch_restrict(env, c->t_red[std::make_pair(0, gl)], c->d_ctl, PRED_CYCLE, l, 0, gl, fine, fsol,
-                      level_out(c, gl), c->red);
+      {
+        TimedScope ts(c, st, TR_T_LO_FINE, l);
+        launch_lo(env, c->t_lo[0], c->lo_threads, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
+      }
+      {
+        TimedScope ts(c, st, TR_T_RESTRICT, l);
+        launch_restrict(env, c->t_red[std::make_pair(0, gl)], c->d_ctl, PRED_CYCLE, l, 0, gl, fine, fsol,
+                        level_out(c, gl), c->red);
+      }
       ga.end_cycle = nsch == 0;
-      launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
-      for (int q = 0; q < nsch; ++q) {
-        const int gm = c->sched[q];
-        launch_opacity(env, c->t_opac, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
-        launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
-                        level_out(c, gm), c->red);
-        launch_lo(env, c->t_lo[gm], c->lo_threads, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm), level_sol(c, gm));
-        launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
-                        level_sol(c, gm), level_out(c, gl), c->red);
-        ga.end_cycle = q == nsch - 1;
+      {
+        TimedScope ts(c, st, TR_T_GREY, l);
         launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
       }
-      launch_opacity(env, c->t_opac, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
+      for (int q = 0; q < nsch; ++q) {
+        const int gm = c->sched[q];
+        {
+          TimedScope ts(c, st, TR_T_OPACITY, l);
+          launch_opacity(env, c->t_opac, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
+        }
+        {
+          TimedScope ts(c, st, TR_T_RESTRICT, l);
+          launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
+                          level_out(c, gm), c->red);
+        }
+        {
+          TimedScope ts(c, st, TR_T_LO_COARSE, l);
+          launch_lo(env, c->t_lo[gm], c->lo_threads, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm),
+                    level_sol(c, gm));
+        }
+        {
+          TimedScope ts(c, st, TR_T_RESTRICT, l);
+          launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
+                          level_sol(c, gm), level_out(c, gl), c->red);
+        }
+        ga.end_cycle = q == nsch - 1;
+        {
+          TimedScope ts(c, st, TR_T_GREY, l);
+          launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
+        }
+      }
+      {
+        TimedScope ts(c, st, TR_T_OPACITY, l);
+        launch_opacity(env, c->t_opac, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
+      }
     }
     launch_count_active(env, c->d_ctl, ns, c->d_count);
     if (hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return TR_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return TR_EHIP;
+    if (c->cfg.timing) {
+      // cycles run by slab 0 in this transport iteration (exact for one slab)
+      Ctl k0;
+      if (hipMemcpy(&k0, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return TR_EHIP;
+      tim_collect(c, k0.ncyc, t_ms, n_launch);
+    }
     if (*c->h_count == 0) break;
   }
   launch_copy(env, c->Tstar, s->T, c->n_cell);
@@ -712,6 +808,10 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       o.n_floor += k.n_floor;
       o.n_outer = k.s + 1;
       for (int i = 0; i < 64; ++i) o.cycles[i] = i < TR_MAXOUT ? k.cycles[i] : 0;
+      for (int i = 0; i < TR_T_N; ++i) {
+        o.t_ms[i] += t_ms[i];
+        o.n_launch[i] += n_launch[i];
+      }
     }
   }
   return err;

@@ -8,6 +8,11 @@
 
 __constant__ double tr_head_coef[TR_NHEAD];
 
+// Ratios whose denominator is at or below this value (zero, negative, or close
+// to the subnormal range where intensities have lost their precision) use the
+// isotropic quadrature value or the unweighted mean instead.
+#define TR_TINY 1e-290
+
 // ---------------------------------------------------------------------------
 // predication
 // ---------------------------------------------------------------------------
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(256) void k_moments(const SlabDev *__restrict__ sd,
   const double *h1 = h0 + 2LL * ng * nx;
   const double phi = h0[0] + h1[0];
   const double chi = h0[1] + h1[1];
-  f[S.o_gi + idx] = (phi > 0.0 && chi > 0.0) ? chi / phi : S.f_iso;
+  f[S.o_gi + idx] = (phi > TR_TINY && chi > 0.0) ? chi / phi : S.f_iso;
   if (i != 0) return;
   const double inl = pd.inc[2 * S.o_g + g], inr = pd.inc[2 * S.o_g + ng + g];
   const double *b0 = bnd + 6 * S.o_g + 3 * g;            // mu > 0: leaves at x = X
@@ -269,16 +274,16 @@ __global__ __launch_bounds__(256) void k_moments(const SlabDev *__restrict__ sd,
   // x = 0
   {
     const double den = b1[0] + inl * S.wpos, num = b1[2] + inl * S.wmu2pos;
-    fbnd[o2] = (den > 0.0 && num > 0.0) ? num / den : S.f_iso;
-    const double Cm = (b1[0] > 0.0) ? b1[1] / b1[0] : -S.c_iso;
+    fbnd[o2] = (den > TR_TINY && num > 0.0) ? num / den : S.f_iso;
+    const double Cm = (b1[0] > TR_TINY) ? b1[1] / b1[0] : -S.c_iso;
     C[o2] = Cm;
     Phi[o2] = inl * S.wmupos - S.c * Cm * (inl * S.wpos / S.c);
   }
   // x = X
   {
     const double den = b0[0] + inr * S.wneg, num = b0[2] + inr * S.wmu2neg;
-    fbnd[o2 + 1] = (den > 0.0 && num > 0.0) ? num / den : S.f_iso;
-    const double Cp = (b0[0] > 0.0) ? b0[1] / b0[0] : S.c_iso;
+    fbnd[o2 + 1] = (den > TR_TINY && num > 0.0) ? num / den : S.f_iso;
+    const double Cp = (b0[0] > TR_TINY) ? b0[1] / b0[0] : S.c_iso;
     C[o2 + 1] = Cp;
     Phi[o2 + 1] = inr * S.wmuneg - S.c * Cp * (inr * S.wneg / S.c);
   }
@@ -573,26 +578,26 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   const long long pe = S.o_lpe[to] + (long long)p * (nx + 1);
   const long long p2 = S.o_lp2[to] + 2 * p;
   if (e < nx) {
-    o.sigE[pi + e] = (s[R_E] > 0.0) ? s[R_SEE] / s[R_E] : s[R_SE] * rinv;
+    o.sigE[pi + e] = (s[R_E] > TR_TINY) ? s[R_SEE] / s[R_E] : s[R_SE] * rinv;
     o.emis[pi + e] = s[R_EM];
     o.Eold[pi + e] = s[R_EOLD];
     o.Esum[pi + e] = s[R_E];
   }
-  const double abar = (s[R_ER] > 0.0) ? s[R_AER] / s[R_ER] : s[R_A] * rinv;
-  const double bbar = (s[R_EL] > 0.0) ? s[R_BEL] / s[R_EL] : s[R_B] * rinv;
-  const double sR = (s[R_AF] > 0.0) ? s[R_SAF] / s[R_AF] : s[R_S] * rinv;
+  const double abar = (s[R_ER] > TR_TINY) ? s[R_AER] / s[R_ER] : s[R_A] * rinv;
+  const double bbar = (s[R_EL] > TR_TINY) ? s[R_BEL] / s[R_EL] : s[R_B] * rinv;
+  const double sR = (s[R_AF] > TR_TINY) ? s[R_SAF] / s[R_AF] : s[R_S] * rinv;
   const double *dx = pd.dx + S.o_cell;
   const double h = (e == 0) ? 0.5 * dx[0] : (e == nx) ? 0.5 * dx[nx - 1] : 0.5 * (dx[e - 1] + dx[e]);
   const double xi = h * (s[R_SF] - sR * s[R_F]);
-  const double eh = (xi > 0.0 && s[R_ER] > 0.0) ? xi / (c * s[R_ER]) : 0.0;
-  const double ec = (xi < 0.0 && s[R_EL] > 0.0) ? -xi / (c * s[R_EL]) : 0.0;
+  const double eh = (xi > 0.0 && s[R_ER] > TR_TINY) ? xi / (c * s[R_ER]) : 0.0;
+  const double ec = (xi < 0.0 && s[R_EL] > TR_TINY) ? -xi / (c * s[R_EL]) : 0.0;
   o.a[pe + e] = abar + eh;
   o.b[pe + e] = bbar + ec;
   o.sigR[pe + e] = sR;
   o.Fold[pe + e] = s[R_FOLD];
   if (e == 0 || e == nx) {
     const int side = (e == 0) ? 0 : 1;
-    o.C[p2 + side] = (s[R_EB] > 0.0) ? s[R_CEB] / s[R_EB] : s[R_C] * rinv;
+    o.C[p2 + side] = (s[R_EB] > TR_TINY) ? s[R_CEB] / s[R_EB] : s[R_C] * rinv;
     o.Phi[p2 + side] = s[R_PHI];
   }
 }
@@ -609,8 +614,9 @@ __device__ inline SrcView make_src(const SlabDev &S, ProbDev pd, int from, const
 }
 
 // Restriction with r <= 64 groups per coarse group: thread = (slab, p, e).
-// r > 64: first pass writes raw sums per 64-group chunk (FINAL = false), the
-// second pass (k_restrict_final) adds the chunks of each coarse group.
+// r > 64: first pass writes raw sums per chunk of at most 64 groups (cpb =
+// ceil(r / 64) chunks per coarse group, FINAL = false); the second pass
+// (k_restrict_final) adds the chunks of each coarse group and finalises.
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd, ProbDev pd,
                                                   const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
@@ -622,22 +628,24 @@ __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd
   const int nx = S.nx, ne = nx + 1;
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
-  const int rc = FINAL ? r : 64;
-  const int nout = nfrom / rc;  // coarse groups (FINAL) or chunks
+  const int cpb = FINAL ? 1 : (r + 63) / 64;
   const int idx = it.idx + threadIdx.x;
-  if (idx >= nout * ne) return;
-  const int q = idx / ne, e = idx - q * ne;
+  if (idx >= nto * cpb * ne) return;
+  const int qq = idx / ne, e = idx - qq * ne;
+  const int p = qq / cpb, qc = qq - p * cpb;
+  const int g0 = p * r + (FINAL ? 0 : qc * 64);
+  const int g1 = FINAL ? (p + 1) * r : p * r + min(r, (qc + 1) * 64);
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  for (int g = q * rc; g < (q + 1) * rc; ++g) {
+  for (int g = g0; g < g1; ++g) {
     const SrcView s = make_src(S, pd, from, in, sol, g);
     accumulate(s, e, acc);
   }
   if (FINAL) {
-    finalize(S, pd, to, q, e, r, acc, out);
+    finalize(S, pd, to, p, e, r, acc, out);
   } else {
-    double *rec = red + S.o_red + ((long long)q * ne + e) * R_N;
+    double *rec = red + S.o_red + ((long long)qq * ne + e) * R_N;
 #pragma unroll
     for (int k = 0; k < R_N; ++k) rec[k] = acc[k];
   }
@@ -653,14 +661,14 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   const int nx = S.nx, ne = nx + 1;
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
-  const int per = r / 64;
+  const int cpb = (r + 63) / 64;
   const int idx = it.idx + threadIdx.x;
   if (idx >= nto * ne) return;
   const int p = idx / ne, e = idx - p * ne;
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  for (int q = p * per; q < (p + 1) * per; ++q) {
+  for (int q = p * cpb; q < (p + 1) * cpb; ++q) {
     const double *rec = red + S.o_red + ((long long)q * ne + e) * R_N;
 #pragma unroll
     for (int k = 0; k < R_N; ++k) acc[k] += rec[k];

@@ -158,7 +158,7 @@ def _cmp_level(name, out, ref, P, nx, Esum_ref):
     assert_close(f"{name}.Esum", to_np(out["Esum"], (P, nx)), Esum_ref, 1e-12)
 
 
-@pytest.mark.parametrize("ng,P,nx", [(16, 4, 11), (256, 2, 9), (128, 1, 300)])
+@pytest.mark.parametrize("ng,P,nx", [(16, 4, 11), (256, 2, 9), (128, 1, 300), (260, 2, 5)])
 def test_restriction(ng, P, nx):
     note(f"restrict ng={ng} P={P} nx={nx}")
     levels = [ng, P, 1] if P > 1 else [ng, 1]
