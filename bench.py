@@ -43,12 +43,29 @@ def sweep_bytes_per_cell_update(M):
     return 32.0 + 16.0 * 2 / M
 
 
-def cpu_baseline(slab, cfg, budget_s=20.0):
-    """The CPU oracle (numpy, FP64) on the first time steps of the workload,
-    bounded to about budget_s seconds."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(workload, budget_s=20.0):
+    """The CPU oracle (numpy, FP64, one thread) on the first time steps of the
+    workload, bounded to about budget_s seconds; run in a child process whose
+    BLAS / OpenMP pools are limited to one thread."""
+    import subprocess
 
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        env[k] = "1"
+    env["HIP_VISIBLE_DEVICES"] = ""
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", workload,
+                        "--cpu-budget", str(budget_s)], capture_output=True, text=True, env=env)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def _cpu_baseline_child(workload, budget_s):
     from oracle import mlqd
+    from paper_2011_05427_amd import inputs
+
+    slabs, cfg, _ = getattr(inputs, WORKLOADS[workload][0])()
+    slab = slabs[0]
 
     pb = mlqd.problem_from_slab(slab)
     st = mlqd.initial_state(pb, slab.T0)
@@ -62,11 +79,10 @@ def cpu_baseline(slab, cfg, budget_s=20.0):
             break
     dt = time.perf_counter() - t0
     cu = slab.cell_updates_per_sweep() * stats.n_ti
-    threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
     return {
         "value": cu / dt,
         "unit": "cell-updates/s",
-        "cores": 1 if threads <= 1 else threads,
+        "cores": 1,
         "kind": "oracle",
         "ms_per_step": 1e3 * dt / nsteps,
         "sample": f"first {nsteps} time step(s) of the same workload ({stats.n_ti} sweeps), numpy FP64, "
@@ -82,7 +98,11 @@ def main():
     ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget)))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the design notes describe how the path would shard)"}))
@@ -96,7 +116,7 @@ def main():
     slabs, cfg, nsteps_cfg = getattr(inputs, fn)()
     slab = slabs[0]
     torch.cuda.set_device(0)
-    sv = binding.Solver([slab], [cfg.levels], cfg, timing=True)
+    sv = binding.Solver([slab], [cfg.levels], cfg)
     st = sv.new_state()
 
     # warmup from the initial condition
@@ -116,15 +136,28 @@ def main():
     wall = time.perf_counter() - t0
 
     a = acc[0]
+    sv.close()
+
+    # per-kernel durations: the same steps again with HIP events around each
+    # kernel group (launched without graph replay; not part of the timed value)
+    svt = binding.Solver([slab], [cfg.levels], cfg, timing=True)
+    stt = svt.new_state()
+    svt.state_init(stt, slab.T0)
+    prof = (binding.TrStats * 1)()
+    for _ in range(args.steps):
+        svt.step(stt, stats=prof)
+    torch.cuda.synchronize()
+    svt.close()
+    p = prof[0]
     cu_sweep = slab.cell_updates_per_sweep()
     sweeps = a.n_ti
     value = cu_sweep * sweeps / wall
-    t_sweep_ms = a.t_ms[binding.T_SWEEP]
-    n_sweep = a.n_launch[binding.T_SWEEP]
+    t_sweep_ms = p.t_ms[binding.T_SWEEP]
+    n_sweep = p.n_launch[binding.T_SWEEP]
     avg_sweep_s = t_sweep_ms / max(n_sweep, 1) / 1e3
     bytes_per_launch = sweep_bytes_per_cell_update(slab.nmu) * cu_sweep
     achieved = bytes_per_launch / avg_sweep_s / 1e9 if avg_sweep_s > 0 else 0.0
-    kernel_ms = {name: a.t_ms[k] / max(args.steps, 1) for k, name in
+    kernel_ms = {name: p.t_ms[k] / max(args.steps, 1) for k, name in
                  enumerate(["opacity", "sweep", "moments", "lo_fine", "restrict", "lo_coarse", "grey"])}
 
     out = {
@@ -163,9 +196,8 @@ def main():
             "launches": int(n_sweep),
         },
     }
-    sv.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(slab, cfg, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

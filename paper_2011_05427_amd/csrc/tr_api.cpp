@@ -62,6 +62,15 @@ struct tr_ctx {
   std::vector<hipEvent_t> events;
   int ev_used = 0;
   std::vector<TimedGroup> groups;
+  // graph replay of one transport iteration (the launch sequence depends on
+  // the state pointers and on the number of cycles launched)
+  struct GraphEntry {
+    std::vector<const void *> key;
+    hipGraphExec_t first = nullptr, next = nullptr;  // s = 0 (no sweep) / s >= 1
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t gs = nullptr;  // library stream for graph replay
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 namespace {
@@ -140,12 +149,13 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
     const int ne = S.nx + 1;
     const int nf = S.lev_ng[from], nt = S.lev_ng[to];
     const int r = nf / nt;
-    if (r <= 64) {
+    const int cpb = restrict_cpb(r);
+    if (cpb == 1) {
       for (int st = 0; st < nt * ne; st += 256) single.push_back({s, st});
     } else {
-      const int nchunk = nt * ((r + 63) / 64);
-      for (int st = 0; st < nchunk * ne; st += 256) part.push_back({s, st});
-      for (int st = 0; st < nt * ne; st += 256) fin.push_back({s, st});
+      for (long long st = 0; st < (long long)nt * cpb * ne; st += 256) part.push_back({s, (int)st});
+      const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
+      for (int q = 0; q < nt * nb; ++q) fin.push_back({s, q});
     }
   }
   RestrictTables rt{};
@@ -278,6 +288,13 @@ const char *tr_error_string(int code) {
 int tr_destroy(tr_ctx *c) {
   if (!c) return TR_OK;
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  for (auto &g : c->graphs) {
+    if (g.first) (void)hipGraphExecDestroy(g.first);
+    if (g.next) (void)hipGraphExecDestroy(g.next);
+  }
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->gs) (void)hipStreamDestroy(c->gs);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->h_count) (void)hipHostFree(c->h_count);
   delete c;
@@ -385,8 +402,9 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       long long worst = 0;
       for (int a = 0; a < nlev; ++a)
         for (int b = a + 1; b < nlev; ++b) {
-          const long long r = P.level_ng[a] / P.level_ng[b];
-          if (r > 64) worst = std::max(worst, (long long)P.level_ng[b] * ((r + 63) / 64));
+          const int r = P.level_ng[a] / P.level_ng[b];
+          const int cpb = restrict_cpb(r);
+          if (cpb > 1) worst = std::max(worst, (long long)P.level_ng[b] * cpb);
         }
       c->n_red += worst * (P.nx + 1) * 21;
     }
@@ -465,6 +483,10 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   if ((rc = dalloc(c, &c->d_ctl, n_slab)) || (rc = dalloc(c, &c->d_cost, n_slab)) || (rc = dalloc(c, &c->d_count, 1)))
     return fail(rc);
   if (hipHostMalloc((void **)&c->h_count, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(TR_ENOMEM);
+  if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+    return fail(TR_EHIP);
   std::vector<int> cost(n_slab);
   for (int s = 0; s < n_slab; ++s) {
     const SlabDev &S = c->hs[s];
@@ -480,7 +502,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     std::vector<std::vector<Item>> lo(nlev);
     for (int s = 0; s < n_slab; ++s) {
       const SlabDev &S = c->hs[s];
-      const int ncb = (S.nx + 255) / 256;
+      const int ncb = (S.nx + 15) / 16;
       for (int q = 0; q < S.nchunk * ncb; ++q) opac.push_back({s, q});
       for (int st = 0; st < S.nx; st += 256) cell.push_back({s, st});
       for (int gg = 0; gg < S.ng; ++gg) sweep.push_back({s, gg});
@@ -654,11 +676,117 @@ int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
   return hip_err(hipGetLastError());
 }
 
+}  // extern "C"
+
+namespace {
+
+// Enqueues one transport iteration: (s >= 1) sweep and moments, then Lmax
+// predicated cycles; a slab whose inner loop has finished skips the rest.
+void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, bool with_sweep) {
+  const int ns = c->nslab, gl = c->nlev - 1;
+  LaunchEnv env = env_of(c, st);
+  const LoIn fine = fine_in(c, c->kappa, c->B, s->f, s->fbnd, s->C, c->Phi, c->Eold, c->Fold);
+  const LoSol fsol{s->E, s->F, s->Ebnd};
+  GreyArgs ga{};
+  ga.grey = level_in(c, gl);
+  ga.Estar = c->lev[gl].Esum;
+  ga.sol = level_sol(c, gl);
+  ga.Tstar = c->Tstar;
+  ga.Tout = c->Tstar;
+  ga.Told = c->Told;
+  ga.dSpart = c->dSpart;
+  ga.Tprev = c->Tprev;
+  ga.sigprev = c->sigprev;
+  ga.Egrey = s->Egrey;
+  ga.Tcyc = c->Tcyc;
+  ga.Ecyc = c->Ecyc;
+  ga.Ts = c->Ts;
+  ga.Es = c->Es;
+  ga.cyc_cost = c->d_cost;
+  ga.secant = c->cfg.secant;
+  ga.lmax = c->cfg.lmax;
+  ga.eps = c->cfg.eps;
+  ga.eps_inner = c->cfg.eps_inner;
+  const int nsch = (int)c->sched.size();
+  if (with_sweep) {
+    launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
+    {
+      TimedScope ts(c, st, TR_T_SWEEP, -1);
+      launch_sweep(env, c->t_sweep, c->d_ctl, PRED_SWEEP, 0, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
+    }
+    {
+      TimedScope ts(c, st, TR_T_MOMENTS, -1);
+      launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
+    }
+  }
+  for (int l = 0; l < Lmax; ++l) {
+    {
+      TimedScope ts(c, st, TR_T_LO_FINE, l);
+      launch_lo(env, c->t_lo[0], c->lo_threads, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
+    }
+    {
+      TimedScope ts(c, st, TR_T_RESTRICT, l);
+      launch_restrict(env, c->t_red[std::make_pair(0, gl)], c->d_ctl, PRED_CYCLE, l, 0, gl, fine, fsol,
+                      level_out(c, gl), c->red);
+    }
+    ga.end_cycle = nsch == 0;
+    {
+      TimedScope ts(c, st, TR_T_GREY, l);
+      launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
+    }
+    for (int q = 0; q < nsch; ++q) {
+      const int gm = c->sched[q];
+      {
+        TimedScope ts(c, st, TR_T_OPACITY, l);
+        launch_opacity(env, c->t_opac, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
+      }
+      {
+        TimedScope ts(c, st, TR_T_RESTRICT, l);
+        launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
+                        level_out(c, gm), c->red);
+      }
+      {
+        TimedScope ts(c, st, TR_T_LO_COARSE, l);
+        launch_lo(env, c->t_lo[gm], c->lo_threads, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm), level_sol(c, gm));
+      }
+      {
+        TimedScope ts(c, st, TR_T_RESTRICT, l);
+        launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
+                        level_sol(c, gm), level_out(c, gl), c->red);
+      }
+      ga.end_cycle = q == nsch - 1;
+      {
+        TimedScope ts(c, st, TR_T_GREY, l);
+        launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
+      }
+    }
+    {
+      TimedScope ts(c, st, TR_T_OPACITY, l);
+      launch_opacity(env, c->t_opac, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
+    }
+  }
+  launch_count_active(env, c->d_ctl, ns, c->d_count);
+}
+
+int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, hipGraphExec_t *out) {
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_EHIP;
+  enqueue_iteration(c, s, c->gs, Lmax, with_sweep);
+  if (hipStreamEndCapture(c->gs, &g) != hipSuccess || !g) return TR_EHIP;
+  const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e == hipSuccess ? TR_OK : TR_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
 int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st) {
   if (!c || !s || !s->T || !s->I_prev || !s->I_out || s->I_prev == s->I_out || !s->E || !s->F || !s->Ebnd ||
       !s->f || !s->fbnd || !s->C || !s->Egrey)
     return TR_EINVAL;
-  const int ns = c->nslab, nlev = c->nlev, gl = nlev - 1;
+  const int ns = c->nslab;
   // control records
   std::vector<Ctl> hc(ns);
   int Lmax = c->cfg.lmax;
@@ -678,8 +806,11 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       k.n_replay = n;
     }
   }
-  if (hipMemcpyAsync(c->d_ctl, hc.data(), sizeof(Ctl) * ns, hipMemcpyHostToDevice, st) != hipSuccess) return TR_EHIP;
-  LaunchEnv env = env_of(c, st);
+  // everything runs on the library stream, ordered after the caller's work
+  hipStream_t gs = c->gs;
+  if (hipEventRecord(c->ev_in, st) != hipSuccess || hipStreamWaitEvent(gs, c->ev_in, 0) != hipSuccess) return TR_EHIP;
+  if (hipMemcpyAsync(c->d_ctl, hc.data(), sizeof(Ctl) * ns, hipMemcpyHostToDevice, gs) != hipSuccess) return TR_EHIP;
+  LaunchEnv env = env_of(c, gs);
   // step start: old-time copies, convergence references, Phi with the current incoming
   launch_copy(env, s->T, c->Told, c->n_cell);
   launch_copy(env, s->T, c->Ts, c->n_cell);
@@ -692,98 +823,43 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   launch_phi(env, c->t_g, s->C, c->Phi);
   launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
 
-  const LoIn fine = fine_in(c, c->kappa, c->B, s->f, s->fbnd, s->C, c->Phi, c->Eold, c->Fold);
-  const LoSol fsol{s->E, s->F, s->Ebnd};
-  GreyArgs ga{};
-  ga.grey = level_in(c, gl);
-  ga.Estar = c->lev[gl].Esum;
-  ga.sol = level_sol(c, gl);
-  ga.Tstar = c->Tstar;
-  ga.Tout = c->Tstar;
-  ga.Told = c->Told;
-  ga.dS = nullptr;
-  ga.dSpart = c->dSpart;
-  ga.D = nullptr;
-  ga.Tprev = c->Tprev;
-  ga.sigprev = c->sigprev;
-  ga.Egrey = s->Egrey;
-  ga.Tcyc = c->Tcyc;
-  ga.Ecyc = c->Ecyc;
-  ga.Ts = c->Ts;
-  ga.Es = c->Es;
-  ga.cyc_cost = c->d_cost;
-  ga.secant = c->cfg.secant;
-  ga.lmax = c->cfg.lmax;
-  ga.eps = c->cfg.eps;
-  ga.eps_inner = c->cfg.eps_inner;
-
-  const int nsch = (int)c->sched.size();
+  // graphs for this state (ping-pong buffers give two keys per run)
+  tr_ctx::GraphEntry *ge = nullptr;
+  if (!c->cfg.timing) {
+    std::vector<const void *> key = {s->I_prev, s->I_out, s->E, s->F, s->Ebnd, s->f, s->fbnd, s->C, s->Egrey,
+                                     reinterpret_cast<const void *>((intptr_t)Lmax)};
+    for (auto &g : c->graphs)
+      if (g.key == key) ge = &g;
+    if (!ge) {
+      if (c->graphs.size() >= 4) {
+        auto &old = c->graphs.front();
+        (void)hipGraphExecDestroy(old.first);
+        (void)hipGraphExecDestroy(old.next);
+        c->graphs.erase(c->graphs.begin());
+      }
+      tr_ctx::GraphEntry e;
+      e.key = key;
+      // capture needs the stream idle of earlier uncaptured work ordering; the
+      // step-start work above is already enqueued and stays before replays
+      int rc = capture_iteration(c, s, Lmax, false, &e.first);
+      if (!rc) rc = capture_iteration(c, s, Lmax, true, &e.next);
+      if (rc) return rc;
+      c->graphs.push_back(e);
+      ge = &c->graphs.back();
+    }
+  }
   double t_ms[TR_T_N] = {0};
   long long n_launch[TR_T_N] = {0};
   c->groups.clear();
   c->ev_used = 0;
   for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
-    if (outer > 0) {
-      launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
-      {
-        TimedScope ts(c, st, TR_T_SWEEP, -1);
-        launch_sweep(env, c->t_sweep, c->d_ctl, PRED_SWEEP, 0, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
-      }
-      {
-        TimedScope ts(c, st, TR_T_MOMENTS, -1);
-        launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
-      }
+    if (ge) {
+      if (hipGraphLaunch(outer == 0 ? ge->first : ge->next, gs) != hipSuccess) return TR_EHIP;
+    } else {
+      enqueue_iteration(c, s, gs, Lmax, outer > 0);
     }
-    for (int l = 0; l < Lmax; ++l) {
-      {
-        TimedScope ts(c, st, TR_T_LO_FINE, l);
-        launch_lo(env, c->t_lo[0], c->lo_threads, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
-      }
-      {
-        TimedScope ts(c, st, TR_T_RESTRICT, l);
-        launch_restrict(env, c->t_red[std::make_pair(0, gl)], c->d_ctl, PRED_CYCLE, l, 0, gl, fine, fsol,
-                        level_out(c, gl), c->red);
-      }
-      ga.end_cycle = nsch == 0;
-      {
-        TimedScope ts(c, st, TR_T_GREY, l);
-        launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
-      }
-      for (int q = 0; q < nsch; ++q) {
-        const int gm = c->sched[q];
-        {
-          TimedScope ts(c, st, TR_T_OPACITY, l);
-          launch_opacity(env, c->t_opac, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
-        }
-        {
-          TimedScope ts(c, st, TR_T_RESTRICT, l);
-          launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
-                          level_out(c, gm), c->red);
-        }
-        {
-          TimedScope ts(c, st, TR_T_LO_COARSE, l);
-          launch_lo(env, c->t_lo[gm], c->lo_threads, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm),
-                    level_sol(c, gm));
-        }
-        {
-          TimedScope ts(c, st, TR_T_RESTRICT, l);
-          launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
-                          level_sol(c, gm), level_out(c, gl), c->red);
-        }
-        ga.end_cycle = q == nsch - 1;
-        {
-          TimedScope ts(c, st, TR_T_GREY, l);
-          launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
-        }
-      }
-      {
-        TimedScope ts(c, st, TR_T_OPACITY, l);
-        launch_opacity(env, c->t_opac, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
-      }
-    }
-    launch_count_active(env, c->d_ctl, ns, c->d_count);
-    if (hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return TR_EHIP;
-    if (hipStreamSynchronize(st) != hipSuccess) return TR_EHIP;
+    if (hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, gs) != hipSuccess) return TR_EHIP;
+    if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
     if (c->cfg.timing) {
       // cycles run by slab 0 in this transport iteration (exact for one slab)
       Ctl k0;
@@ -793,8 +869,10 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
     if (*c->h_count == 0) break;
   }
   launch_copy(env, c->Tstar, s->T, c->n_cell);
-  if (hipMemcpyAsync(hc.data(), c->d_ctl, sizeof(Ctl) * ns, hipMemcpyDeviceToHost, st) != hipSuccess) return TR_EHIP;
-  if (hipStreamSynchronize(st) != hipSuccess) return TR_EHIP;
+  if (hipMemcpyAsync(hc.data(), c->d_ctl, sizeof(Ctl) * ns, hipMemcpyDeviceToHost, gs) != hipSuccess) return TR_EHIP;
+  if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
+  if (hipEventRecord(c->ev_out, gs) != hipSuccess || hipStreamWaitEvent(st, c->ev_out, 0) != hipSuccess)
+    return TR_EHIP;
   int err = TR_OK;
   for (int q = 0; q < ns; ++q) {
     const Ctl &k = hc[q];

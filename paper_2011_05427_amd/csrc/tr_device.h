@@ -12,28 +12,33 @@
 // by the host at context creation.
 // ---------------------------------------------------------------------------
 #define TR_NHEAD 40
+#define TR_NRECIP 64
 extern __constant__ double tr_head_coef[TR_NHEAD];
+extern __constant__ double tr_recip[TR_NRECIP];  // 1/n, n < TR_NRECIP
 
 static constexpr double TR_PI4_15 = 6.4939394022668291491;  // pi^4 / 15
 static constexpr double TR_XSW = 2.0;
 
-// Head part int_0^x (x < 2).
+// Head part int_0^x (x < 2): x^3 (c_0 + c_1 x + sum_{j>=1} c_2j x^2j); the
+// odd coefficients beyond c_1 vanish, so the even part is a polynomial in x^2.
 __device__ inline double q_head(double x) {
-  double acc = tr_head_coef[TR_NHEAD - 1];
+  const double y = x * x;
+  double acc = tr_head_coef[TR_NHEAD - 2];
 #pragma unroll
-  for (int k = TR_NHEAD - 2; k >= 0; --k) acc = fma(acc, x, tr_head_coef[k]);
-  return acc * x * x * x;
+  for (int k = TR_NHEAD - 4; k >= 2; k -= 2) acc = fma(acc, y, tr_head_coef[k]);
+  acc = fma(acc, y, fma(tr_head_coef[1], x, tr_head_coef[0]));
+  return acc * y * x;
 }
 
 // Tail part int_x^inf (x >= 2), given ex = e^{-x}.  Terms decay like e^{-nx};
 // n_max = 40/x + 2 keeps the truncation below 1e-17 relative.
 __device__ inline double q_tail(double x, double ex) {
   if (!(ex > 0.0)) return 0.0;
-  int nmax = (int)(40.0 / x) + 2;
+  const int nmax = min(TR_NRECIP - 1, (int)(40.0 / x) + 2);
   double en = ex, acc = 0.0;
   double x2 = x * x, x3 = x2 * x;
   for (int n = 1; n <= nmax; ++n) {
-    double rn = 1.0 / n;
+    const double rn = tr_recip[n];
     // x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4 = (x^3 + (3x^2 + (6x + 6/n)/n)/n)/n
     double poly = fma(rn, fma(rn, fma(rn, 6.0, 6.0 * x), 3.0 * x2), x3);
     acc = fma(en * rn, poly, acc);
@@ -178,8 +183,27 @@ __device__ inline void tri_solve_block(const double (&a)[K], const double (&b)[K
 }
 
 // ---------------------------------------------------------------------------
-// Block-wide max reduction (exact, order independent).  lds: blockDim doubles.
+// Block-wide max reductions (exact, order independent).
 // ---------------------------------------------------------------------------
+// Six maxima at once; lds: 6 * blockDim doubles.
+__device__ inline void block_max6(double (&v)[6], double *lds) {
+  const int t = threadIdx.x, n = blockDim.x;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) lds[q * n + t] = v[q];
+  __syncthreads();
+  for (int st = n >> 1; st > 0; st >>= 1) {
+    if (t < st) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) lds[q * n + t] = fmax(lds[q * n + t], lds[q * n + t + st]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) v[q] = lds[q * n];
+  __syncthreads();
+}
+
+// lds: blockDim doubles.
 __device__ inline double block_max(double v, double *lds) {
   const int t = threadIdx.x;
   lds[t] = v;

@@ -61,8 +61,12 @@ void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int 
 void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi);
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
                const LoIn &in, const LoSol &sol);
-// Restriction work: slabs whose coarse groups hold <= 64 finer groups use one
-// pass; the others a chunk pass plus a final pass.
+// Restriction work: coarse groups of r <= 16 finer groups are done in one pass;
+// larger r in a chunk pass (cpb chunks per coarse group) plus a final pass over
+// blocks of TR_RFIN_E edges.
+#define TR_RFIN_E 12
+__host__ __device__ inline int restrict_cpb(int r) { return r <= 16 ? 1 : (r + 7) / 8 < 64 ? (r + 7) / 8 : 64; }
+
 struct RestrictTables {
   Table single, part, fin;
 };

@@ -7,6 +7,7 @@
 #include "tr_kernels.h"
 
 __constant__ double tr_head_coef[TR_NHEAD];
+__constant__ double tr_recip[TR_NRECIP];
 
 // Ratios whose denominator is at or below this value (zero, negative, or close
 // to the subnormal range where intensities have lost their precision) use the
@@ -33,46 +34,58 @@ __device__ inline bool pred_ok(const Ctl *ctl, int slab, int mode, int l) {
 }
 
 // ---------------------------------------------------------------------------
-// A1: opacity and group Planck tables at T, with the chunk partial sums of
-// dS = d/dT sum_g 2 kappa_g B_g.  Thread = (slab, 64-group chunk, cell).
+// A1: opacity and group Planck tables at T, with the 64-group chunk partial
+// sums of dS = d/dT sum_g 2 kappa_g B_g.  Block = one 64-group chunk x 16
+// cells; thread = (run of 4 consecutive groups, cell), so adjacent groups share
+// their common edge integral; the 16 run sums of a cell are added in LDS in a
+// fixed order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd, ProbDev pd,
                                                  const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
                                                  const double *__restrict__ T, double *__restrict__ kappa,
                                                  double *__restrict__ B, double *__restrict__ dSpart) {
+  __shared__ double part[16][17];
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   const int nx = S.nx, ng = S.ng;
-  const int ncb = (nx + 255) >> 8;
-  const int chunk = it.idx / ncb, cb = it.idx % ncb;
-  const int i = cb * 256 + threadIdx.x;
-  if (i >= nx) return;
-  const double Ti = T[S.o_cell + i];
-  const double Cc = pd.Ccell[S.o_cell + i];
-  const double T2 = Ti * Ti;
-  const double scale = S.aR * S.c * T2 * T2 * 0.5 / TR_PI4_15;
-  const double *nue = pd.nu_e + S.o_nu;
-  const double *nuc = pd.nu_c + S.o_g;
-  const int g0 = chunk * 64, g1 = min(ng, g0 + 64);
-  EdgeQ lo = edge_q(nue[g0], Ti);
+  const int ncb = (nx + 15) >> 4;
+  const int chunk = it.idx / ncb, cb = it.idx - chunk * ncb;
+  const int run = threadIdx.x >> 4, cl = threadIdx.x & 15;
+  const int i = cb * 16 + cl;
+  const int g0 = chunk * 64 + run * 4, g1 = min(ng, g0 + 4);
   double dS = 0.0;
-  for (int g = g0; g < g1; ++g) {
-    const EdgeQ hi = edge_q(nue[g + 1], Ti);
-    const double Bg = scale * q_interval(lo, hi);
-    const double dBg = 4.0 * Bg / Ti - scale / Ti * (hi.g4 - lo.g4);
-    const double nu = nuc[g];
-    const double y = nu / Ti;
-    const double nu3 = nu * nu * nu;
-    const double kap = Cc / nu3 * (-expm1(-y));
-    const double dkap = -Cc / (nu * nu) * exp(-y) / T2;
-    const long long o = S.o_gi + (long long)g * nx + i;
-    kappa[o] = kap;
-    B[o] = Bg;
-    dS += 2.0 * (dkap * Bg + kap * dBg);
-    lo = hi;
+  if (i < nx && g0 < ng) {
+    const double Ti = T[S.o_cell + i];
+    const double Cc = pd.Ccell[S.o_cell + i];
+    const double T2 = Ti * Ti;
+    const double scale = S.aR * S.c * T2 * T2 * 0.5 / TR_PI4_15;
+    const double *nue = pd.nu_e + S.o_nu;
+    const double *nuc = pd.nu_c + S.o_g;
+    EdgeQ lo = edge_q(nue[g0], Ti);
+    for (int g = g0; g < g1; ++g) {
+      const EdgeQ hi = edge_q(nue[g + 1], Ti);
+      const double Bg = scale * q_interval(lo, hi);
+      const double dBg = 4.0 * Bg / Ti - scale / Ti * (hi.g4 - lo.g4);
+      const double nu = nuc[g];
+      const double y = nu / Ti;
+      const double kap = Cc / (nu * nu * nu) * (-expm1(-y));
+      const double dkap = -Cc / (nu * nu) * exp(-y) / T2;
+      const long long o = S.o_gi + (long long)g * nx + i;
+      kappa[o] = kap;
+      B[o] = Bg;
+      dS += 2.0 * (dkap * Bg + kap * dBg);
+      lo = hi;
+    }
   }
-  dSpart[S.o_chunk + (long long)chunk * nx + i] = dS;
+  part[run][cl] = dS;
+  __syncthreads();
+  if (run == 0 && i < nx) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc += part[r][cl];
+    dSpart[S.o_chunk + (long long)chunk * nx + i] = acc;
+  }
 }
 
 // Sums the chunk partials of dS (standalone tr_opacity).  Thread = cell.
@@ -310,7 +323,6 @@ __global__ __launch_bounds__(256) void k_phi(const SlabDev *__restrict__ sd, Pro
 // MODE 0: fine grid from kappa/B tables and QD factors; MODE 1: level arrays.
 // ---------------------------------------------------------------------------
 struct LevelView {
-  int mode;
   int nx;
   const double *dx;
   // fine
@@ -327,9 +339,10 @@ __device__ inline double lv_h(const LevelView &v, int e) {
   return 0.5 * (v.dx[e - 1] + v.dx[e]);
 }
 
+template <bool FINE>
 __device__ inline void lv_edge(const LevelView &v, int e, double &ae, double &be, double &sr) {
   const int nx = v.nx;
-  if (v.mode == 0) {
+  if (FINE) {
     ae = (e < nx) ? v.f[e] : v.fbnd[1];
     be = (e > 0) ? v.f[e - 1] : v.fbnd[0];
     if (e == 0)
@@ -345,8 +358,9 @@ __device__ inline void lv_edge(const LevelView &v, int e, double &ae, double &be
   }
 }
 
+template <bool FINE>
 __device__ inline void lv_cell(const LevelView &v, int i, double &se, double &em) {
-  if (v.mode == 0) {
+  if (FINE) {
     se = v.kap[i];
     em = 2.0 * v.kap[i] * v.Bt[i];
   } else {
@@ -358,7 +372,7 @@ __device__ inline void lv_cell(const LevelView &v, int i, double &se, double &em
 // Builds the K rows of this thread; optional per-cell overrides (grey Newton).
 // With eff = true the absorption / emission of the cell of row k come from
 // se_eff[k] / em_eff[k] (the grey level coupled to the MEB).
-template <int K>
+template <int K, bool FINE>
 __device__ inline void lo_rows(const LevelView &v, double c, double dt, double inv_cdt, bool eff,
                                const double (&se_eff)[K], const double (&em_eff)[K], double (&ra)[K],
                                double (&rb)[K], double (&rc)[K], double (&rd)[K], double (&Ak)[K + 1],
@@ -374,7 +388,7 @@ __device__ inline void lo_rows(const LevelView &v, double c, double dt, double i
       continue;
     }
     double ae, be, sr;
-    lv_edge(v, e, ae, be, sr);
+    lv_edge<FINE>(v, e, ae, be, sr);
     const double h = lv_h(v, e);
     const double A = h * inv_cdt;
     const double ke = 1.0 / (A + sr * h);
@@ -397,7 +411,7 @@ __device__ inline void lo_rows(const LevelView &v, double c, double dt, double i
         se = se_eff[k];
         em = em_eff[k];
       } else {
-        lv_cell(v, i, se, em);
+        lv_cell<FINE>(v, i, se, em);
       }
       const double dxi = v.dx[i];
       ra[k] = -cb[k];
@@ -441,13 +455,13 @@ __device__ inline void lo_store(int nx, const double (&x)[K], const double (&Ak)
   }
 }
 
+template <bool FINE>
 __device__ inline LevelView make_view(const SlabDev &S, ProbDev pd, int level, const LoIn &in, int p) {
   LevelView v;
   v.nx = S.nx;
   v.dx = pd.dx + S.o_cell;
   const int nx = S.nx;
-  if (level == 0) {
-    v.mode = 0;
+  if (FINE) {
     const long long gi = S.o_gi + (long long)p * nx, g2 = 2 * S.o_g + 2 * p;
     v.kap = in.kappa + gi;
     v.Bt = in.B + gi;
@@ -459,7 +473,6 @@ __device__ inline LevelView make_view(const SlabDev &S, ProbDev pd, int level, c
     v.Fold = in.Fold + S.o_ge + (long long)p * (nx + 1);
     v.sigE = v.emis = v.a = v.b = v.sigR = nullptr;
   } else {
-    v.mode = 1;
     const long long pi = S.o_lpi[level] + (long long)p * nx;
     const long long pe = S.o_lpe[level] + (long long)p * (nx + 1);
     const long long p2 = S.o_lp2[level] + 2 * p;
@@ -477,10 +490,11 @@ __device__ inline LevelView make_view(const SlabDev &S, ProbDev pd, int level, c
   return v;
 }
 
+template <bool FINE>
 __device__ inline void level_out(const SlabDev &S, int level, int p, const LoSol &sol, double *&E, double *&F,
                                  double *&Eb) {
   const int nx = S.nx;
-  if (level == 0) {
+  if (FINE) {
     E = sol.E + S.o_gi + (long long)p * nx;
     F = sol.F + S.o_ge + (long long)p * (nx + 1);
     Eb = sol.Ebnd + 2 * S.o_g + 2 * p;
@@ -494,7 +508,7 @@ __device__ inline void level_out(const SlabDev &S, int level, int p, const LoSol
 // ---------------------------------------------------------------------------
 // A4 / A6: LO solve, one thread block per (slab, group of the level).
 // ---------------------------------------------------------------------------
-template <int K>
+template <int K, bool FINE>
 __global__ __launch_bounds__(256) void k_lo(const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab,
                                             const Ctl *ctl, int pmode, int lcyc, int level, LoIn in, LoSol sol) {
   __shared__ double lds[8 * 256];
@@ -502,12 +516,12 @@ __global__ __launch_bounds__(256) void k_lo(const SlabDev *__restrict__ sd, Prob
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   const int p = it.idx;
-  const LevelView v = make_view(S, pd, level, in, p);
+  const LevelView v = make_view<FINE>(S, pd, level, in, p);
   double ra[K], rb[K], rc[K], rd[K], x[K], Ak[K + 1], ca[K + 1], cb[K + 1], dummy[K];
-  lo_rows<K>(v, S.c, S.dt, S.inv_cdt, false, dummy, dummy, ra, rb, rc, rd, Ak, ca, cb);
+  lo_rows<K, FINE>(v, S.c, S.dt, S.inv_cdt, false, dummy, dummy, ra, rb, rc, rd, Ak, ca, cb);
   tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
   double *E, *F, *Eb;
-  level_out(S, level, p, sol, E, F, Eb);
+  level_out<FINE>(S, level, p, sol, E, F, Eb);
   lo_store<K>(S.nx, x, Ak, ca, cb, lds, E, F, Eb);
 }
 
@@ -528,11 +542,12 @@ struct SrcView {
   const double *E, *F, *Eb;  // solution of the source level (group p)
 };
 
+template <bool FINE>
 __device__ inline void accumulate(const SrcView &s, int e, double (&r)[R_N]) {
   const int nx = s.v.nx;
   if (e < nx) {
     double se, em;
-    lv_cell(s.v, e, se, em);
+    lv_cell<FINE>(s.v, e, se, em);
     const double E = s.E[e];
     r[R_E] += E;
     r[R_SEE] += se * E;
@@ -541,7 +556,7 @@ __device__ inline void accumulate(const SrcView &s, int e, double (&r)[R_N]) {
     r[R_EOLD] += s.v.Eold[e];
   }
   double ae, be, sr;
-  lv_edge(s.v, e, ae, be, sr);
+  lv_edge<FINE>(s.v, e, ae, be, sr);
   const double ER = (e < nx) ? s.E[e] : s.Eb[1];
   const double EL = (e > 0) ? s.E[e - 1] : s.Eb[0];
   const double F = s.F[e];
@@ -602,22 +617,24 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   }
 }
 
+template <bool FINE>
 __device__ inline SrcView make_src(const SlabDev &S, ProbDev pd, int from, const LoIn &in, const LoSol &sol, int g) {
   SrcView s;
-  s.v = make_view(S, pd, from, in, g);
+  s.v = make_view<FINE>(S, pd, from, in, g);
   double *E, *F, *Eb;
-  level_out(S, from, g, sol, E, F, Eb);
+  level_out<FINE>(S, from, g, sol, E, F, Eb);
   s.E = E;
   s.F = F;
   s.Eb = Eb;
   return s;
 }
 
-// Restriction with r <= 64 groups per coarse group: thread = (slab, p, e).
-// r > 64: first pass writes raw sums per chunk of at most 64 groups (cpb =
-// ceil(r / 64) chunks per coarse group, FINAL = false); the second pass
-// (k_restrict_final) adds the chunks of each coarse group and finalises.
-template <bool FINAL>
+// Restriction work split.  r finer groups per coarse group: r <= 16 is done in
+// one pass (thread = (slab, p, e) looping over the r groups); larger r in two:
+// cpb = min(64, ceil(r/8)) chunks of rc = ceil(r/cpb) groups write raw sums
+// (thread = (chunk, e)), then a final pass adds the chunks of each coarse group
+// (block = 12 edges x R_N sums) and finalises.
+template <bool FINAL, bool FINE>
 __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd, ProbDev pd,
                                                   const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
                                                   int from, int to, LoIn in, LoSol sol, LoOut out,
@@ -628,19 +645,20 @@ __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd
   const int nx = S.nx, ne = nx + 1;
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
-  const int cpb = FINAL ? 1 : (r + 63) / 64;
+  const int cpb = FINAL ? 1 : restrict_cpb(r);
+  const int rc = (r + cpb - 1) / cpb;
   const int idx = it.idx + threadIdx.x;
   if (idx >= nto * cpb * ne) return;
   const int qq = idx / ne, e = idx - qq * ne;
   const int p = qq / cpb, qc = qq - p * cpb;
-  const int g0 = p * r + (FINAL ? 0 : qc * 64);
-  const int g1 = FINAL ? (p + 1) * r : p * r + min(r, (qc + 1) * 64);
+  const int g0 = p * r + qc * rc;
+  const int g1 = min(g0 + rc, (p + 1) * r);
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
   for (int g = g0; g < g1; ++g) {
-    const SrcView s = make_src(S, pd, from, in, sol, g);
-    accumulate(s, e, acc);
+    const SrcView s = make_src<FINE>(S, pd, from, in, sol, g);
+    accumulate<FINE>(s, e, acc);
   }
   if (FINAL) {
     finalize(S, pd, to, p, e, r, acc, out);
@@ -655,25 +673,36 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
                                                         const Item *__restrict__ tab, const Ctl *ctl, int pmode,
                                                         int lcyc, int from, int to, LoOut out,
                                                         const double *__restrict__ red) {
+  __shared__ double sums[TR_RFIN_E][R_N];
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   const int nx = S.nx, ne = nx + 1;
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
-  const int cpb = (r + 63) / 64;
-  const int idx = it.idx + threadIdx.x;
-  if (idx >= nto * ne) return;
-  const int p = idx / ne, e = idx - p * ne;
-  double acc[R_N];
-#pragma unroll
-  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  for (int q = p * cpb; q < (p + 1) * cpb; ++q) {
-    const double *rec = red + S.o_red + ((long long)q * ne + e) * R_N;
-#pragma unroll
-    for (int k = 0; k < R_N; ++k) acc[k] += rec[k];
+  const int cpb = restrict_cpb(r);
+  const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
+  const int p = it.idx / nb, b = it.idx - p * nb;
+  const int t = threadIdx.x;
+  const int el = t / R_N, k = t - el * R_N;
+  const int e = b * TR_RFIN_E + el;
+  if (el < TR_RFIN_E) {
+    double acc = 0.0;
+    if (e < ne) {
+      const double *rec = red + S.o_red + ((long long)p * cpb * ne + e) * R_N + k;
+      const long long stride = (long long)ne * R_N;
+#pragma unroll 8
+      for (int q = 0; q < cpb; ++q) acc += rec[q * stride];
+    }
+    sums[el][k] = acc;
   }
-  finalize(S, pd, to, p, e, r, acc, out);
+  __syncthreads();
+  if (t < TR_RFIN_E && b * TR_RFIN_E + t < ne) {
+    double s[R_N];
+#pragma unroll
+    for (int q = 0; q < R_N; ++q) s[q] = sums[t][q];
+    finalize(S, pd, to, p, b * TR_RFIN_E + t, r, s, out);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -696,18 +725,34 @@ __global__ __launch_bounds__(256) void k_grey(const SlabDev *__restrict__ sd, Pr
   const double *Tst = ga.Tstar + S.o_cell;
   const bool use_prev = ctl ? (ctl[slab].has_prev && ga.secant) : false;
   // per-cell Newton coefficients for the cells of this thread's rows
-  double alpha[K], beta[K], se_eff[K], em_eff[K];
+  double alpha[K], beta[K], se_eff[K], em_eff[K], dSrow[K];
   const long long pi = S.o_lpi[gl];
+  // dS at the stage temperature: explicit, or the sum of the chunk partials
+  // (loop over chunks outside, rows inside, so the loads of a chunk overlap)
+#pragma unroll
+  for (int k = 0; k < K; ++k) dSrow[k] = 0.0;
+  if (ga.dS) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = t * K + k - 1;
+      if (i >= 0 && i < nx) dSrow[k] = ga.dS[S.o_cell + i];
+    }
+  } else {
+    for (int q = 0; q < S.nchunk; ++q) {
+      const double *row = ga.dSpart + S.o_chunk + (long long)q * nx;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = t * K + k - 1;
+        if (i >= 0 && i < nx) dSrow[k] += row[i];
+      }
+    }
+  }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int i = t * K + k - 1;
     alpha[k] = beta[k] = se_eff[k] = em_eff[k] = 0.0;
     if (i < 0 || i >= nx) continue;
-    double dS = 0.0;
-    if (ga.dS)
-      dS = ga.dS[S.o_cell + i];
-    else
-      for (int q = 0; q < S.nchunk; ++q) dS += ga.dSpart[S.o_chunk + (long long)q * nx + i];
+    const double dS = dSrow[k];
     const double Ts = Tst[i];
     const double sig = ga.grey.sigE[pi + i];
     const double Sst = ga.grey.emis[pi + i];
@@ -730,10 +775,10 @@ __global__ __launch_bounds__(256) void k_grey(const SlabDev *__restrict__ sd, Pr
     em_eff[k] = Sst - gg * al;
   }
   // rows: the grey level view with effective absorption / emission
-  LevelView v = make_view(S, pd, gl, ga.grey, 0);
+  LevelView v = make_view<false>(S, pd, gl, ga.grey, 0);
   double ra[K], rb[K], rc[K], rd[K], x[K], Ak[K + 1], ca[K + 1], cb[K + 1];
   // row k of this thread is cell t K + k - 1: the Newton coefficients above
-  lo_rows<K>(v, c, dt, S.inv_cdt, true, se_eff, em_eff, ra, rb, rc, rd, Ak, ca, cb);
+  lo_rows<K, false>(v, c, dt, S.inv_cdt, true, se_eff, em_eff, ra, rb, rc, rd, Ak, ca, cb);
   tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
   double *E = ga.sol.E + pi, *F = ga.sol.F + S.o_lpe[gl], *Eb = ga.sol.Ebnd + S.o_lp2[gl];
   lo_store<K>(nx, x, Ak, ca, cb, lds, E, F, Eb);
@@ -784,12 +829,16 @@ __global__ __launch_bounds__(256) void k_grey(const SlabDev *__restrict__ sd, Pr
     __syncthreads();
   }
   if (!ga.end_cycle) return;
-  dTc = block_max(dTc, lds);
-  dEc = block_max(dEc, lds);
-  dTs = block_max(dTs, lds);
-  dEs = block_max(dEs, lds);
-  Tmax = block_max(Tmax, lds);
-  Emax = block_max(Emax, lds);
+  {
+    double v[6] = {dTc, dEc, dTs, dEs, Tmax, Emax};
+    block_max6(v, lds);
+    dTc = v[0];
+    dEc = v[1];
+    dTs = v[2];
+    dEs = v[3];
+    Tmax = v[4];
+    Emax = v[5];
+  }
   if (t == 0) {
     Ctl &cc = ctl[slab];
     cc.ncyc += 1;
@@ -974,18 +1023,33 @@ void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double 
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
                const LoIn &in, const LoSol &sol) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_lo<TR_LO_K>, blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
-                     lcyc, level, in, sol);
+  if (level == 0)
+    hipLaunchKernelGGL((k_lo<TR_LO_K, true>), blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl,
+                       pmode, lcyc, level, in, sol);
+  else
+    hipLaunchKernelGGL((k_lo<TR_LO_K, false>), blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl,
+                       pmode, lcyc, level, in, sol);
 }
 
 void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
                      int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red) {
-  if (rt.single.n)
-    hipLaunchKernelGGL(k_restrict<true>, blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.single.d,
-                       ctl, pmode, lcyc, from, to, in, sol, out, red);
-  if (rt.part.n)
-    hipLaunchKernelGGL(k_restrict<false>, blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.part.d, ctl,
-                       pmode, lcyc, from, to, in, sol, out, red);
+  const bool fine = from == 0;
+  if (rt.single.n) {
+    if (fine)
+      hipLaunchKernelGGL((k_restrict<true, true>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+    else
+      hipLaunchKernelGGL((k_restrict<true, false>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+  }
+  if (rt.part.n) {
+    if (fine)
+      hipLaunchKernelGGL((k_restrict<false, true>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+    else
+      hipLaunchKernelGGL((k_restrict<false, false>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+  }
   if (rt.fin.n)
     hipLaunchKernelGGL(k_restrict_final, blocks(rt.fin.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.fin.d, ctl,
                        pmode, lcyc, from, to, out, red);
@@ -1029,5 +1093,9 @@ void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, d
 }
 
 int upload_head_coef(const double *coef) {
+  double rec[TR_NRECIP];
+  rec[0] = 0.0;
+  for (int n = 1; n < TR_NRECIP; ++n) rec[n] = 1.0 / n;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(tr_recip), rec, sizeof(double) * TR_NRECIP) != hipSuccess) return -3;
   return hipMemcpyToSymbol(HIP_SYMBOL(tr_head_coef), coef, sizeof(double) * TR_NHEAD) == hipSuccess ? 0 : -3;
 }

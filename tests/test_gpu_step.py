@@ -150,3 +150,24 @@ def test_paper_scale_one_step_replay():
     sv.step(st, replay=[stats.counts[0]])
     _compare_state("paper-scale step 0", sv, st, states[1])
     sv.close()
+
+
+def test_graph_replay_equals_eager_launches():
+    """tr_step replays captured graphs of a transport iteration (default) or
+    launches eagerly (timing mode); over several steps, with eager work and
+    synchronisations between replays, both give bitwise identical states."""
+    slab = inputs.make_slab(40, 32, 8, dt=0.004)
+    levels = [32, 4, 1]
+    cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_W, lmax=2)
+    note("graph vs eager, W cycle, 4 steps")
+    outs = []
+    for timing in (False, True):
+        sv = binding.Solver([slab], [levels], cfg, timing=timing)
+        st = sv.new_state()
+        sv.state_init(st, slab.T0)
+        for _ in range(4):
+            sv.step(st)
+        outs.append({k: to_np(v).copy() for k, v in st.items()})
+        sv.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
