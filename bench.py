@@ -103,6 +103,41 @@ def _cpu_baseline_child(workload, budget_s):
     }
 
 
+def learned_vs_plain(slab, cfg, args, plain_ms, plain_sweeps):
+    """Trains the closure on the plain solver's own steps of this workload (the
+    paper-scale sweeps), then times the same timed steps with the closure
+    seeding each step's factors.  The plain sweeps still decide convergence."""
+    import torch
+
+    from paper_2011_05427_amd import binding, closure
+
+    t0 = time.perf_counter()
+    ds = closure.generate(slab, cfg, cfg.levels, nsteps=args.steps, n_samples=args.train_samples, seed=0)
+    net, losses = closure.train(ds, epochs=args.train_epochs, batch=4096, lr=1e-3, seed=0)
+    train_s = time.perf_counter() - t0
+    sv = binding.Solver([slab], [cfg.levels], cfg)
+    sv.set_closure(net, ds.mean, ds.std)
+    st = sv.new_state()
+    sv.state_init(st, slab.T0)
+    for _ in range(args.warmup):
+        sv.step(st)
+    sv.state_init(st, slab.T0)
+    torch.cuda.synchronize()
+    acc = (binding.TrStats * 1)()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        sv.step(st, stats=acc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    sv.close()
+    ms = 1e3 * wall / args.steps
+    return {"ms_per_step": ms, "plain_ms_per_step": plain_ms, "speedup": plain_ms / ms,
+            "sweeps": int(acc[0].n_ti), "plain_sweeps": plain_sweeps, "seeded": int(acc[0].n_seeded),
+            "fallback": int(acc[0].n_fallback), "train_s": train_s, "samples": int(ds.X.shape[0]),
+            "epochs": args.train_epochs, "loss_first": losses[0], "loss_last": losses[-1],
+            "note": "network trained on the plain solver's steps of this workload; seeds s=0 cell factors"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +147,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
+    ap.add_argument("--train-samples", type=int, default=1000000)
+    ap.add_argument("--train-epochs", type=int, default=5)
     args = ap.parse_args()
     if args.cpu_baseline_child:
         print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget)))
@@ -209,6 +247,8 @@ def main():
             "launches": int(n_sweep),
         },
     }
+    if not args.no_learned:
+        out["learned"] = learned_vs_plain(slab, cfg, args, out["ms_per_step"], int(sweeps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -244,6 +244,8 @@ typedef struct tr_stats {
   double t_ms[TR_T_N];     /* with cfg.timing: summed kernel time per group
                               (TR_T_*), over launches that did work */
   long long n_launch[TR_T_N]; /* timed launch groups per TR_T_* */
+  long long n_seeded;   /* cell factors replaced by the closure */
+  long long n_fallback; /* closure predictions rejected (outside (0, 1)) */
 } tr_stats;
 
 /*
@@ -255,6 +257,65 @@ typedef struct tr_stats {
  * Errors: TR_ENOCONV, TR_ENAN, TR_EHIP.
  */
 int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats, hipStream_t stream);
+
+/*
+ * Learned closure (not part of the paper's method; its plain sweep stays the
+ * judge).  A multilayer perceptron 5 -> 128 -> 128 -> 128 -> 2 with ReLU
+ * hidden layers; output 0 through a logistic sigmoid predicts the group
+ * Eddington factor, output 1 is a prolongation correction.  Products run in
+ * bfloat16 on MFMA with float32 accumulation.  Parameters: float32 vector of
+ * tr_mlp_nparam() entries, row-major W1 [8][128] (input rows 5..7 unused), b1
+ * [128], W2 [128][128], b2, W3 [128][128], b3, W4 [128][2], b4 [2].  Inputs X
+ * [n][8] float32 standardised features (columns 5..7 ignored); targets Y
+ * [n][2] float32.  `work` is caller-owned device scratch of
+ * tr_mlp_work_bytes(n) (tr_mlp_train_work_bytes(batch) for training).
+ */
+int tr_mlp_nparam(void);
+size_t tr_mlp_work_bytes(long long n);
+size_t tr_mlp_train_work_bytes(int batch);
+/* out [n][2] = (sigmoid(o_0), o_1). */
+int tr_mlp_forward(const float *params, const float *X, long long n, float *out, void *work, hipStream_t stream);
+/* grad [nparam] of the mean-squared loss (1/n) sum (fhat-f)^2 + (rhat-r)^2 and
+ * the loss (device float). */
+int tr_mlp_grad(const float *params, const float *X, const float *Y, long long n, float *grad, float *loss,
+                void *work, hipStream_t stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected, t >= 1). */
+int tr_mlp_adam(float *params, float *m, float *v, const float *grad, int t, float lr, hipStream_t stream);
+/* One epoch of minibatch Adam in the order given by perm [n] (device ints);
+ * *t counts Adam steps (host), loss_sum (device float) accumulates the batch
+ * losses. */
+int tr_mlp_train_epoch(float *params, float *m, float *v, int *t, float lr, const float *X, const float *Y,
+                       long long n, const int *perm, int batch, void *work, float *loss_sum, hipStream_t stream);
+
+/*
+ * Closure inputs for every slab, group and cell (sample g * nx + i of each
+ * slab, pooled like gi): log T_i, log nu_g, log(kappa_g,i dx_i), log T_{i-1},
+ * log T_{i+1} (left neighbour of cell 0: T_left when positive, else T_0;
+ * right neighbour of the last cell: itself), standardised with mean/std
+ * (host [5] each).  X: [gi total][8] float32.
+ */
+int tr_mlp_features(tr_ctx *ctx, const double *T, const double *kappa, const float *mean, const float *std,
+                    float *X, hipStream_t stream);
+
+/*
+ * Training targets from two consecutive fine solutions (gi arrays): Y [gi][2]
+ * float32 = (f_g,i, r_g,i), r = log((E_g/E_p) / (E'_g/E'_p)) the change of
+ * the within-block spectral shape, E_p the sum over the `block` consecutive
+ * groups containing g (0 where a share is at or below 1e-290), clipped to
+ * [-2, 2].
+ */
+int tr_closure_targets(tr_ctx *ctx, const double *f, const double *E_new, const double *E_prev, int block, float *Y,
+                       hipStream_t stream);
+
+/*
+ * Attaches a trained closure to the context (params: device, kept by the
+ * caller; NULL detaches).  While attached, tr_step replaces the previous
+ * step's cell QD factors by the network's prediction at the start of every
+ * step (transport iteration s = 0); a prediction outside (0, 1) keeps the old
+ * factor.  All later transport iterations sweep and test convergence exactly
+ * as without the closure.
+ */
+int tr_set_closure(tr_ctx *ctx, const float *params, const float *mean, const float *std);
 
 #ifdef __cplusplus
 }

@@ -59,14 +59,17 @@ class TrState(C.Structure):
 class TrStats(C.Structure):
     _fields_ = [("n_ti", C.c_longlong), ("n_c", C.c_longlong), ("n_lo", C.c_longlong),
                 ("n_floor", C.c_longlong), ("n_outer", C.c_int), ("cycles", C.c_int * 64),
-                ("t_ms", C.c_double * 8), ("n_launch", C.c_longlong * 8)]
+                ("t_ms", C.c_double * 8), ("n_launch", C.c_longlong * 8),
+                ("n_seeded", C.c_longlong), ("n_fallback", C.c_longlong)]
 
 
 T_OPACITY, T_SWEEP, T_MOMENTS, T_LO_FINE, T_RESTRICT, T_LO_COARSE, T_GREY = range(7)
 
 
 EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_incoming", "tr_opacity",
-           "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step"]
+           "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step",
+           "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
+           "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure"]
 
 _lib = None
 
@@ -101,8 +104,20 @@ def load():
     lib.tr_grey_solve.argtypes = [vp, C.POINTER(TrLoCoeffs), vp, vp, vp, vp, vp, vp, C.POINTER(TrLoFields), vp]
     lib.tr_state_init.argtypes = [vp, C.POINTER(TrState), C.c_double, vp]
     lib.tr_step.argtypes = [vp, C.POINTER(TrState), _ip, C.POINTER(TrStats), vp]
+    lib.tr_mlp_nparam.argtypes = []
+    lib.tr_mlp_work_bytes.argtypes = [C.c_longlong]
+    lib.tr_mlp_work_bytes.restype = C.c_size_t
+    lib.tr_mlp_train_work_bytes.argtypes = [C.c_int]
+    lib.tr_mlp_train_work_bytes.restype = C.c_size_t
+    lib.tr_mlp_forward.argtypes = [vp, vp, C.c_longlong, vp, vp, vp]
+    lib.tr_mlp_grad.argtypes = [vp, vp, vp, C.c_longlong, vp, vp, vp, vp]
+    lib.tr_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp]
+    lib.tr_mlp_train_epoch.argtypes = [vp, vp, vp, _ip, C.c_float, vp, vp, C.c_longlong, vp, C.c_int, vp, vp, vp]
+    lib.tr_mlp_features.argtypes = [vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
+    lib.tr_closure_targets.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+    lib.tr_set_closure.argtypes = [vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
     for name in EXPORTS:
-        if name not in ("tr_error_string",):
+        if name not in ("tr_error_string", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -266,3 +281,96 @@ class Solver:
         if swap:
             st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
         return stats
+
+
+# ---------------------------------------------------------------------------
+# Learned closure network (MFMA kernels in the library)
+# ---------------------------------------------------------------------------
+def _stream():
+    import torch
+
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _f32(a):
+    return (C.c_float * len(a))(*[float(x) for x in a])
+
+
+class Mlp:
+    """Device-side network parameters and Adam state (float32, torch tensors)."""
+
+    def __init__(self, params):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        self.nparam = self.lib.tr_mlp_nparam()
+        p = torch.as_tensor(np.asarray(params, dtype=np.float32)).to("cuda")
+        assert p.numel() == self.nparam
+        self.params = p.contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = C.c_int(0)
+        self._work = {}
+
+    def _work_for(self, n, train=False):
+        key = (n, train)
+        if key not in self._work:
+            nb = self.lib.tr_mlp_train_work_bytes(n) if train else self.lib.tr_mlp_work_bytes(n)
+            self._work[key] = self.torch.empty(int(nb), dtype=self.torch.uint8, device="cuda")
+        return self._work[key]
+
+    def forward(self, X):
+        n = X.shape[0]
+        out = self.torch.empty((n, 2), dtype=self.torch.float32, device="cuda")
+        _check(self.lib.tr_mlp_forward(_ptr(self.params), _ptr(X), n, _ptr(out), _ptr(self._work_for(n)), _stream()),
+               "tr_mlp_forward")
+        return out
+
+    def grad(self, X, Y):
+        n = X.shape[0]
+        g = self.torch.empty(self.nparam, dtype=self.torch.float32, device="cuda")
+        loss = self.torch.empty(1, dtype=self.torch.float32, device="cuda")
+        _check(self.lib.tr_mlp_grad(_ptr(self.params), _ptr(X), _ptr(Y), n, _ptr(g), _ptr(loss),
+                                    _ptr(self._work_for(n)), _stream()), "tr_mlp_grad")
+        return g, loss
+
+    def adam(self, grad, lr):
+        self.t.value += 1
+        _check(self.lib.tr_mlp_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(grad), self.t.value,
+                                    C.c_float(lr), _stream()), "tr_mlp_adam")
+
+    def train_epoch(self, X, Y, perm, batch, lr):
+        """perm: device int32 tensor; returns the mean batch loss."""
+        n = X.shape[0]
+        loss = self.torch.zeros(1, dtype=self.torch.float32, device="cuda")
+        _check(self.lib.tr_mlp_train_epoch(_ptr(self.params), _ptr(self.m), _ptr(self.v), C.byref(self.t),
+                                           C.c_float(lr), _ptr(X), _ptr(Y), n, _ptr(perm), batch,
+                                           _ptr(self._work_for(batch, True)), _ptr(loss), _stream()),
+               "tr_mlp_train_epoch")
+        return float(loss.item()) / max(1, n // batch)
+
+
+def _solver_methods():
+    def mlp_features(self, T, kappa, mean, std, X):
+        _check(self.lib.tr_mlp_features(self._ctx, _ptr(T), _ptr(kappa), _f32(mean), _f32(std), _ptr(X),
+                                        self._stream()), "tr_mlp_features")
+
+    def closure_targets(self, f, E_new, E_prev, block, Y):
+        _check(self.lib.tr_closure_targets(self._ctx, _ptr(f), _ptr(E_new), _ptr(E_prev), int(block), _ptr(Y),
+                                           self._stream()), "tr_closure_targets")
+
+    def set_closure(self, mlp, mean=None, std=None):
+        if mlp is None:
+            _check(self.lib.tr_set_closure(self._ctx, None, None, None), "tr_set_closure")
+            self._closure = None
+            return
+        _check(self.lib.tr_set_closure(self._ctx, _ptr(mlp.params), _f32(mean), _f32(std)), "tr_set_closure")
+        self._closure = mlp
+
+    Solver.mlp_features = mlp_features
+    Solver.closure_targets = closure_targets
+    Solver.set_closure = set_closure
+
+
+_solver_methods()

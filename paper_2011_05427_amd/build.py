@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtr.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["tr_kernels.hip", "tr_api.cpp"]
+SOURCES = ["tr_kernels.hip", "tr_mlp.hip", "tr_api.cpp"]
 # Packed FP32 instructions are disabled for all device code; the host pass of
 # hipcc warns that it does not know the feature, which is harmless.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",

@@ -71,6 +71,13 @@ struct tr_ctx {
   std::vector<GraphEntry> graphs;
   hipStream_t gs = nullptr;  // library stream for graph replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // learned closure (seeding of the s = 0 cell factors)
+  const float *mlp_params = nullptr;
+  MlpStats mlp_stats{};
+  float *mlp_X = nullptr, *mlp_out = nullptr;
+  void *mlp_work = nullptr;
+  long long mlp_chunk = 0;
+  unsigned long long *d_seed_counts = nullptr;
 };
 
 namespace {
@@ -376,6 +383,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       }
     }
     S.f_iso = wmu2all / wall;
+    S.T_left = P.T_left;
     S.c_iso = S.wmupos / S.wpos;
     S.o_cell = c->n_cell;
     S.o_edge = c->n_edge;
@@ -663,6 +671,52 @@ int tr_grey_solve(tr_ctx *c, const tr_lo_coeffs *grey, const double *Tstar, cons
   return hip_err(hipGetLastError());
 }
 
+int tr_mlp_features(tr_ctx *c, const double *T, const double *kappa, const float *mean, const float *std, float *X,
+                    hipStream_t st) {
+  if (!c || !T || !kappa || !mean || !std || !X) return TR_EINVAL;
+  MlpStats ms;
+  for (int k = 0; k < 5; ++k) {
+    ms.mean[k] = mean[k];
+    ms.std[k] = std[k];
+    if (!(std[k] > 0)) return TR_EINVAL;
+  }
+  launch_mlp_features(env_of(c, st), c->t_gi, T, kappa, ms, X);
+  return hip_err(hipGetLastError());
+}
+
+int tr_closure_targets(tr_ctx *c, const double *f, const double *E_new, const double *E_prev, int block, float *Y,
+                       hipStream_t st) {
+  if (!c || !f || !E_new || !E_prev || !Y || block < 1) return TR_EINVAL;
+  launch_closure_targets(env_of(c, st), c->t_gi, f, E_new, E_prev, block, Y);
+  return hip_err(hipGetLastError());
+}
+
+int tr_set_closure(tr_ctx *c, const float *params, const float *mean, const float *std) {
+  if (!c) return TR_EINVAL;
+  if (!params) {
+    c->mlp_params = nullptr;
+    return TR_OK;
+  }
+  if (!mean || !std) return TR_EINVAL;
+  for (int k = 0; k < 5; ++k) {
+    if (!(std[k] > 0)) return TR_EINVAL;
+    c->mlp_stats.mean[k] = mean[k];
+    c->mlp_stats.std[k] = std[k];
+  }
+  if (!c->mlp_X) {
+    c->mlp_chunk = std::min<long long>(c->n_gi, 1LL << 20);
+    int rc;
+    if ((rc = dalloc(c, &c->mlp_X, 8 * c->n_gi)) || (rc = dalloc(c, &c->mlp_out, 2 * c->n_gi)) ||
+        (rc = dalloc(c, &c->d_seed_counts, 2)))
+      return rc;
+    char *w = nullptr;
+    if ((rc = dalloc(c, &w, (long long)tr_mlp_work_bytes(c->mlp_chunk)))) return rc;
+    c->mlp_work = w;
+  }
+  c->mlp_params = params;
+  return TR_OK;
+}
+
 int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
   if (!c || !s || !s->T || !s->I_out || !s->E || !s->F || !s->Ebnd || !s->f || !s->fbnd || !s->C || !s->Egrey ||
       !(T0 > 0))
@@ -822,6 +876,18 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   launch_copy(env, s->F, c->Fold, c->n_ge);
   launch_phi(env, c->t_g, s->C, c->Phi);
   launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
+  unsigned long long seed_counts[2] = {0, 0};
+  if (c->mlp_params) {
+    // learned closure: predicted cell factors replace the previous step's
+    if (hipMemsetAsync(c->d_seed_counts, 0, 2 * sizeof(unsigned long long), gs) != hipSuccess) return TR_EHIP;
+    launch_mlp_features(env, c->t_gi, c->Tstar, c->kappa, c->mlp_stats, c->mlp_X);
+    for (long long o = 0; o < c->n_gi; o += c->mlp_chunk) {
+      const long long n = std::min(c->mlp_chunk, c->n_gi - o);
+      int rc = tr_mlp_forward(c->mlp_params, c->mlp_X + 8 * o, n, c->mlp_out + 2 * o, c->mlp_work, gs);
+      if (rc) return rc;
+    }
+    launch_seed_f(env, c->mlp_out, s->f, c->n_gi, c->d_seed_counts);
+  }
 
   // graphs for this state (ping-pong buffers give two keys per run)
   tr_ctx::GraphEntry *ge = nullptr;
@@ -869,6 +935,9 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
     if (*c->h_count == 0) break;
   }
   launch_copy(env, c->Tstar, s->T, c->n_cell);
+  if (c->mlp_params &&
+      hipMemcpyAsync(seed_counts, c->d_seed_counts, sizeof(seed_counts), hipMemcpyDeviceToHost, gs) != hipSuccess)
+    return TR_EHIP;
   if (hipMemcpyAsync(hc.data(), c->d_ctl, sizeof(Ctl) * ns, hipMemcpyDeviceToHost, gs) != hipSuccess) return TR_EHIP;
   if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
   if (hipEventRecord(c->ev_out, gs) != hipSuccess || hipStreamWaitEvent(st, c->ev_out, 0) != hipSuccess)
@@ -889,6 +958,10 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       for (int i = 0; i < TR_T_N; ++i) {
         o.t_ms[i] += t_ms[i];
         o.n_launch[i] += n_launch[i];
+      }
+      if (q == 0) {  // closure counters cover the whole context
+        o.n_seeded += (long long)seed_counts[0];
+        o.n_fallback += (long long)seed_counts[1];
       }
     }
   }

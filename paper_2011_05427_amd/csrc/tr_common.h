@@ -19,6 +19,7 @@ struct SlabDev {
   double wpos, wmupos, wmu2pos;  // half-range quadrature sums over mu > 0
   double wneg, wmuneg, wmu2neg;  // over mu < 0 (wmuneg < 0)
   double f_iso, c_iso;
+  double T_left;  // incoming Planck temperature at x = 0 (<= 0: vacuum)
   long long o_cell, o_edge, o_I, o_gi, o_ge, o_g, o_g2, o_nu, o_mu, o_chunk;
   long long o_lpi[TR_MAXLEV], o_lpe[TR_MAXLEV], o_lp2[TR_MAXLEV];
   long long o_red;  // restriction scratch records (per slab)

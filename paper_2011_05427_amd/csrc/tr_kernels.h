@@ -81,4 +81,12 @@ void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
 void launch_init_state(const LaunchEnv &env, const Table &tab, const double *Bt, double *I, double *E, double *F,
                        double *Ebnd, double *mom, double *bnd);
 void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, double *out);
+struct MlpStats {
+  double mean[5], std[5];
+};
+void launch_mlp_features(const LaunchEnv &env, const Table &tab, const double *T, const double *kappa,
+                         const MlpStats &ms, float *X);
+void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double *f, const double *Enew,
+                            const double *Eprev, int blk, float *Y);
+void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts);
 int upload_head_coef(const double *coef);

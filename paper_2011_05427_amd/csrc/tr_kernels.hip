@@ -983,6 +983,82 @@ __global__ __launch_bounds__(256) void k_group_sum(const SlabDev *__restrict__ s
 }
 
 // ---------------------------------------------------------------------------
+// Learned closure: inputs per (g, i) and seeding of the cell QD factors.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_features(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                      const Item *__restrict__ tab, const double *__restrict__ T,
+                                                      const double *__restrict__ kappa, MlpStats ms,
+                                                      float *__restrict__ X) {
+  const Item it = tab[blockIdx.x];
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ng = S.ng;
+  const int idx = it.idx + threadIdx.x;
+  if (idx >= ng * nx) return;
+  const int g = idx / nx, i = idx - g * nx;
+  const double *Tc = T + S.o_cell;
+  const double Ti = Tc[i];
+  const double Tl = i > 0 ? Tc[i - 1] : (S.T_left > 0.0 ? S.T_left : Ti);
+  const double Tr = i < nx - 1 ? Tc[i + 1] : Ti;
+  const double f[5] = {log(Ti), log(pd.nu_c[S.o_g + g]), log(kappa[S.o_gi + idx] * pd.dx[S.o_cell + i]), log(Tl),
+                       log(Tr)};
+  float *x = X + (S.o_gi + idx) * 8;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) x[k] = (float)((f[k] - ms.mean[k]) / ms.std[k]);
+  x[5] = x[6] = x[7] = 0.0f;
+}
+
+// Training targets per (g, i): Y = (f_g,i, r_g,i) with r the log change of the
+// within-block spectral shape E_g / E_p between two fine solutions (blocks of
+// `blk` consecutive groups); 0 where a share is at or below TR_TINY; clipped to
+// [-2, 2] (shares near underflow move by orders of magnitude).
+__global__ __launch_bounds__(256) void k_closure_targets(const SlabDev *__restrict__ sd, const Item *__restrict__ tab,
+                                                         const double *__restrict__ f, const double *__restrict__ Enew,
+                                                         const double *__restrict__ Eprev, int blk,
+                                                         float *__restrict__ Y) {
+  const Item it = tab[blockIdx.x];
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ng = S.ng;
+  const int idx = it.idx + threadIdx.x;
+  if (idx >= ng * nx) return;
+  const int g = idx / nx, i = idx - g * nx;
+  const int g0 = (g / blk) * blk;
+  double sn = 0.0, sp = 0.0;
+  for (int q = g0; q < min(ng, g0 + blk); ++q) {
+    sn += Enew[S.o_gi + (long long)q * nx + i];
+    sp += Eprev[S.o_gi + (long long)q * nx + i];
+  }
+  const double en = Enew[S.o_gi + idx], ep = Eprev[S.o_gi + idx];
+  double r = 0.0;
+  if (sn > TR_TINY && sp > TR_TINY && en > TR_TINY && ep > TR_TINY) r = log((en / sn) / (ep / sp));
+  r = fmin(2.0, fmax(-2.0, r));
+  Y[2 * (S.o_gi + idx)] = (float)f[S.o_gi + idx];
+  Y[2 * (S.o_gi + idx) + 1] = (float)r;
+}
+
+// f <- fhat where 0 < fhat < 1 (counted), else the old factor stays (counted).
+__global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, double *__restrict__ f, long long n,
+                                                unsigned long long *__restrict__ counts) {
+  __shared__ unsigned int s_ok, s_bad;
+  if (threadIdx.x == 0) s_ok = s_bad = 0;
+  __syncthreads();
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const float fh = out[2 * i];
+    if (fh > 0.0f && fh < 1.0f) {
+      f[i] = (double)fh;
+      atomicAdd(&s_ok, 1u);
+    } else {
+      atomicAdd(&s_bad, 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&counts[0], (unsigned long long)s_ok);
+    atomicAdd(&counts[1], (unsigned long long)s_bad);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 static inline dim3 blocks(int n) { return dim3((unsigned)n); }
@@ -1090,6 +1166,24 @@ void launch_init_state(const LaunchEnv &env, const Table &tab, const double *Bt,
 void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, double *out) {
   if (tab.n == 0) return;
   hipLaunchKernelGGL(k_group_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, E, out);
+}
+
+void launch_mlp_features(const LaunchEnv &env, const Table &tab, const double *T, const double *kappa,
+                         const MlpStats &ms, float *X) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_mlp_features, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, T, kappa, ms, X);
+}
+
+void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double *f, const double *Enew,
+                            const double *Eprev, int blk, float *Y) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_closure_targets, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, f, Enew, Eprev, blk,
+                     Y);
+}
+
+void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_seed_f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, out, f, n, counts);
 }
 
 int upload_head_coef(const double *coef) {

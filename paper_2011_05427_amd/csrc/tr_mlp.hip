@@ -1,0 +1,390 @@
+// Learned closure network on MFMA (gfx950): 5 -> 128 -> 128 -> 128 -> 2, ReLU,
+// sigmoid on output 0.  Products run in bfloat16 with float32 accumulation on
+// v_mfma_f32_32x32x16_bf16; master weights, biases, gradients and the Adam
+// state are float32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "tr.h"
+
+namespace {
+
+constexpr int NH = 128, NINP = 8, NOUT = 2;
+// parameter vector offsets (float32): W1 [8][128], b1, W2 [128][128], b2, W3, b3, W4 [128][2], b4
+constexpr int OW1 = 0, OB1 = OW1 + NINP * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
+              OB3 = OW3 + NH * NH, OW4 = OB3 + NH, OB4 = OW4 + NH * NOUT, NPARAM = OB4 + NOUT;
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// float -> bfloat16 bits, round to nearest, ties to even
+__device__ inline uint16_t to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const uint32_t lsb = (u >> 16) & 1u;
+  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+__device__ inline float from_bf16(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+struct Gemm {
+  const uint16_t *A;  // [M x K], element (m, k) at A[m * am + k * ak]
+  long long am, ak;
+  const uint16_t *B;  // [K x N], element (k, n) at B[k * bk + n * bn]
+  long long bk, bn;
+  int M, N, K;
+  float *Cf;  // optional float32 output (m, n) at Cf[m * cm + n]
+  uint16_t *Cb;  // optional bfloat16 output (m, n) at Cb[m * cm + n]
+  long long cm;
+  const float *bias;  // optional, per column n
+  int relu;
+  const uint16_t *mask;  // optional: zero where mask(m, n) == 0 (ReLU derivative)
+  long long mm;
+};
+
+// C = epilogue(A B): one wavefront per 32 x 32 output tile, K in steps of 16.
+// Lane l holds A(m0 + l % 32, k0 + 8 (l / 32) + 0..7), B(k0 + 8 (l / 32) + 0..7,
+// n0 + l % 32) and accumulator element j of D(m0 + 8 (j / 4) + 4 (l / 32) +
+// j % 4, n0 + l % 32).  Out-of-range rows/columns read zeros and are not stored.
+__global__ __launch_bounds__(256) void k_gemm(Gemm g) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int m0 = (blockIdx.x * 2 + (wv >> 1)) * 32;
+  const int n0 = (blockIdx.y * 2 + (wv & 1)) * 32;
+  if (m0 >= g.M || n0 >= g.N) return;
+  const int r = lane & 31, hk = (lane >> 5) * 8;
+  const int m = m0 + r, n = n0 + r;
+  f32x16 acc;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + hk + i;
+      a[i] = (m < g.M && k < g.K) ? (short)g.A[m * g.am + k * g.ak] : (short)0;
+      b[i] = (n < g.N && k < g.K) ? (short)g.B[k * g.bk + n * g.bn] : (short)0;
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int nn = n0 + r;
+  if (nn >= g.N) return;
+  const float bias = g.bias ? g.bias[nn] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int mm = m0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    if (mm >= g.M) continue;
+    float v = acc[j] + bias;
+    if (g.relu) v = fmaxf(v, 0.0f);
+    if (g.mask && g.mask[mm * g.mm + nn] == 0) v = 0.0f;
+    if (g.Cf) g.Cf[mm * g.cm + nn] = v;
+    if (g.Cb) g.Cb[mm * g.cm + nn] = to_bf16(v);
+  }
+}
+
+// y[i * ldy + c] = bf16(x[i * ldx + c]) for c < ncol, zeros up to ldy.
+__global__ void k_to_bf16(const float *__restrict__ x, long long ldx, int ncol, uint16_t *__restrict__ y,
+                          long long ldy, long long nrow) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrow * ldy) return;
+  const long long i = t / ldy;
+  const int c = (int)(t - i * ldy);
+  y[t] = c < ncol ? to_bf16(x[i * ldx + c]) : (uint16_t)0;
+}
+
+// out[i] = (sigmoid(o[i][0]), o[i][1])
+__global__ void k_head(const float *__restrict__ o, float *__restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[2 * i] = 1.0f / (1.0f + expf(-o[2 * i]));
+  out[2 * i + 1] = o[2 * i + 1];
+}
+
+// dL/do for the mean-squared loss and per-block loss sums (fixed order).
+__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ o, const float *__restrict__ Y, int n,
+                                              float *__restrict__ dO, uint16_t *__restrict__ dOb,
+                                              float *__restrict__ part) {
+  __shared__ float red[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (i < n) {
+    const float fh = 1.0f / (1.0f + expf(-o[2 * i]));
+    const float d0 = fh - Y[2 * i], d1 = o[2 * i + 1] - Y[2 * i + 1];
+    l = d0 * d0 + d1 * d1;
+    const float g0 = 2.0f * d0 * fh * (1.0f - fh) / n, g1 = 2.0f * d1 / n;
+    dO[2 * i] = g0;
+    dO[2 * i + 1] = g1;
+    dOb[2 * i] = to_bf16(g0);
+    dOb[2 * i + 1] = to_bf16(g1);
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[c] = sum_i x[i * ld + c] (bias gradients), fixed summation order.
+__global__ void k_colsum(const float *__restrict__ x, long long ld, int ncol, int nrow, float *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  float acc = 0.0f;
+  for (int i = 0; i < nrow; ++i) acc += x[(long long)i * ld + c];
+  out[c] = acc;
+}
+
+__global__ void k_accum(float *__restrict__ dst, const float *__restrict__ src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
+}
+
+__global__ void k_sum(const float *__restrict__ part, int n, float *__restrict__ out, float scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float acc = 0.0f;
+  for (int i = 0; i < n; ++i) acc += part[i];
+  *out = acc * scale;
+}
+
+__global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_gather(const float *__restrict__ src, int w, const int *__restrict__ idx, int n,
+                         float *__restrict__ dst) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * w) return;
+  const long long i = t / w;
+  const int c = (int)(t - i * w);
+  dst[t] = src[(long long)idx[i] * w + c];
+}
+
+// work layout (bytes, 256-aligned pieces)
+struct Work {
+  uint16_t *Xb, *Wb, *H1, *H2, *H3, *dOb, *dZb;
+  float *O, *dO, *dZf, *part, *gtmp;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t work_bytes(long long n) {
+  size_t b = 0;
+  b += align256(n * NINP * 2);            // Xb
+  b += align256((size_t)NPARAM * 2);       // Wb (bf16 copy of the parameter vector)
+  b += 3 * align256(n * NH * 2);           // H1..H3
+  b += align256(n * NOUT * 2);             // dOb
+  b += align256(n * NH * 2);               // dZb
+  b += align256(n * NOUT * 4);             // O
+  b += align256(n * NOUT * 4);             // dO
+  b += align256(n * NH * 4);               // dZf
+  b += align256(((n + 255) / 256) * 4);    // loss partials
+  b += align256((size_t)NPARAM * 4);       // gradient scratch
+  return b;
+}
+
+Work carve(void *w, long long n) {
+  char *p = static_cast<char *>(w);
+  Work k;
+  auto take = [&](size_t bytes) {
+    char *q = p;
+    p += align256(bytes);
+    return q;
+  };
+  k.Xb = (uint16_t *)take(n * NINP * 2);
+  k.Wb = (uint16_t *)take((size_t)NPARAM * 2);
+  k.H1 = (uint16_t *)take(n * NH * 2);
+  k.H2 = (uint16_t *)take(n * NH * 2);
+  k.H3 = (uint16_t *)take(n * NH * 2);
+  k.dOb = (uint16_t *)take(n * NOUT * 2);
+  k.dZb = (uint16_t *)take(n * NH * 2);
+  k.O = (float *)take(n * NOUT * 4);
+  k.dO = (float *)take(n * NOUT * 4);
+  k.dZf = (float *)take(n * NH * 4);
+  k.part = (float *)take(((n + 255) / 256) * 4);
+  k.gtmp = (float *)take((size_t)NPARAM * 4);
+  return k;
+}
+
+void gemm(const Gemm &g, hipStream_t st) {
+  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+}
+
+Gemm gemm_nn(const uint16_t *A, long long am, long long ak, const uint16_t *B, long long bk, long long bn, int M,
+             int N, int K) {
+  Gemm g{};
+  g.A = A;
+  g.am = am;
+  g.ak = ak;
+  g.B = B;
+  g.bk = bk;
+  g.bn = bn;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  return g;
+}
+
+// forward pass; keeps the bf16 activations in the work area
+void forward(const float *params, const float *X, long long n, const Work &w, hipStream_t st) {
+  const int tb = 256;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPARAM + tb - 1) / tb)), dim3(tb), 0, st, params, 1LL, 1, w.Wb,
+                     1LL, (long long)NPARAM);
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * NINP + tb - 1) / tb)), dim3(tb), 0, st, X, (long long)NINP, 5,
+                     w.Xb, (long long)NINP, n);
+  const uint16_t *W1 = w.Wb + OW1, *W2 = w.Wb + OW2, *W3 = w.Wb + OW3, *W4 = w.Wb + OW4;
+  Gemm g = gemm_nn(w.Xb, NINP, 1, W1, NH, 1, (int)n, NH, NINP);
+  g.Cb = w.H1;
+  g.cm = NH;
+  g.bias = params + OB1;
+  g.relu = 1;
+  gemm(g, st);
+  g = gemm_nn(w.H1, NH, 1, W2, NH, 1, (int)n, NH, NH);
+  g.Cb = w.H2;
+  g.cm = NH;
+  g.bias = params + OB2;
+  g.relu = 1;
+  gemm(g, st);
+  g = gemm_nn(w.H2, NH, 1, W3, NH, 1, (int)n, NH, NH);
+  g.Cb = w.H3;
+  g.cm = NH;
+  g.bias = params + OB3;
+  g.relu = 1;
+  gemm(g, st);
+  g = gemm_nn(w.H3, NH, 1, W4, NOUT, 1, (int)n, NOUT, NH);
+  g.Cf = w.O;
+  g.cm = NOUT;
+  g.bias = params + OB4;
+  gemm(g, st);
+}
+
+// gradient of the mean-squared loss; grad [NPARAM], loss (device float)
+void backward(const float *params, const float *X, const float *Y, long long n, float *grad, float *loss,
+              const Work &w, hipStream_t st) {
+  forward(params, X, n, w, st);
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, st, w.O, Y, (int)n, w.dO, w.dOb, w.part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, st, w.part, nb, loss, 1.0f / (float)n);
+  const uint16_t *W2 = w.Wb + OW2, *W3 = w.Wb + OW3, *W4 = w.Wb + OW4;
+  // layer 4: dW4 = H3^T dO, db4 = sum dO, dZ3 = (dO W4^T) * [H3 > 0]
+  Gemm g = gemm_nn(w.H3, 1, NH, w.dOb, NOUT, 1, NH, NOUT, (int)n);
+  g.Cf = grad + OW4;
+  g.cm = NOUT;
+  gemm(g, st);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, st, w.dO, (long long)NOUT, NOUT, (int)n, grad + OB4);
+  g = gemm_nn(w.dOb, NOUT, 1, W4, 1, NOUT, (int)n, NH, NOUT);
+  g.Cf = w.dZf;
+  g.Cb = w.dZb;
+  g.cm = NH;
+  g.mask = w.H3;
+  g.mm = NH;
+  gemm(g, st);
+  // layer 3
+  g = gemm_nn(w.H2, 1, NH, w.dZb, NH, 1, NH, NH, (int)n);
+  g.Cf = grad + OW3;
+  g.cm = NH;
+  gemm(g, st);
+  hipLaunchKernelGGL(k_colsum, dim3(2), dim3(64), 0, st, w.dZf, (long long)NH, NH, (int)n, grad + OB3);
+  g = gemm_nn(w.dZb, NH, 1, W3, 1, NH, (int)n, NH, NH);
+  g.Cf = w.dZf;
+  g.Cb = w.dZb;
+  g.cm = NH;
+  g.mask = w.H2;
+  g.mm = NH;
+  gemm(g, st);
+  // layer 2
+  g = gemm_nn(w.H1, 1, NH, w.dZb, NH, 1, NH, NH, (int)n);
+  g.Cf = grad + OW2;
+  g.cm = NH;
+  gemm(g, st);
+  hipLaunchKernelGGL(k_colsum, dim3(2), dim3(64), 0, st, w.dZf, (long long)NH, NH, (int)n, grad + OB2);
+  g = gemm_nn(w.dZb, NH, 1, W2, 1, NH, (int)n, NH, NH);
+  g.Cf = w.dZf;
+  g.Cb = w.dZb;
+  g.cm = NH;
+  g.mask = w.H1;
+  g.mm = NH;
+  gemm(g, st);
+  // layer 1
+  g = gemm_nn(w.Xb, 1, NINP, w.dZb, NH, 1, NINP, NH, (int)n);
+  g.Cf = grad + OW1;
+  g.cm = NH;
+  gemm(g, st);
+  hipLaunchKernelGGL(k_colsum, dim3(2), dim3(64), 0, st, w.dZf, (long long)NH, NH, (int)n, grad + OB1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tr_mlp_nparam(void) { return NPARAM; }
+
+size_t tr_mlp_work_bytes(long long n) { return work_bytes(n); }
+
+int tr_mlp_forward(const float *params, const float *X, long long n, float *out, void *work, hipStream_t st) {
+  if (!params || !X || !out || !work || n <= 0) return TR_EINVAL;
+  const Work w = carve(work, n);
+  forward(params, X, n, w, st);
+  hipLaunchKernelGGL(k_head, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.O, out, (int)n);
+  return hipGetLastError() == hipSuccess ? TR_OK : TR_EHIP;
+}
+
+int tr_mlp_grad(const float *params, const float *X, const float *Y, long long n, float *grad, float *loss,
+                void *work, hipStream_t st) {
+  if (!params || !X || !Y || !grad || !loss || !work || n <= 0) return TR_EINVAL;
+  const Work w = carve(work, n);
+  backward(params, X, Y, n, grad, loss, w, st);
+  return hipGetLastError() == hipSuccess ? TR_OK : TR_EHIP;
+}
+
+int tr_mlp_adam(float *params, float *m, float *v, const float *grad, int t, float lr, hipStream_t st) {
+  if (!params || !m || !v || !grad || t < 1) return TR_EINVAL;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+  hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, params, m, v, grad, NPARAM, lr, b1, b2,
+                     1e-8f, c1, c2);
+  return hipGetLastError() == hipSuccess ? TR_OK : TR_EHIP;
+}
+
+int tr_mlp_train_epoch(float *params, float *m, float *v, int *t, float lr, const float *X, const float *Y,
+                       long long n, const int *perm, int batch, void *work, float *loss_sum, hipStream_t st) {
+  if (!params || !m || !v || !t || !X || !Y || !perm || batch <= 0 || !work || !loss_sum || n <= 0)
+    return TR_EINVAL;
+  // work holds: gathered X [batch][8], Y [batch][2], gradient, loss, then the pass work
+  char *p = static_cast<char *>(work);
+  float *Xg = (float *)p;
+  p += align256((size_t)batch * NINP * 4);
+  float *Yg = (float *)p;
+  p += align256((size_t)batch * NOUT * 4);
+  float *grad = (float *)p;
+  p += align256((size_t)NPARAM * 4);
+  float *lossb = (float *)p;
+  p += align256(4);
+  const Work w = carve(p, batch);
+  for (long long s = 0; s + batch <= n; s += batch) {
+    hipLaunchKernelGGL(k_gather, dim3((batch * NINP + 255) / 256), dim3(256), 0, st, X, NINP, perm + s, batch, Xg);
+    hipLaunchKernelGGL(k_gather, dim3((batch * NOUT + 255) / 256), dim3(256), 0, st, Y, NOUT, perm + s, batch, Yg);
+    backward(params, Xg, Yg, batch, grad, lossb, w, st);
+    *t += 1;
+    int rc = tr_mlp_adam(params, m, v, grad, *t, lr, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_accum, dim3(1), dim3(64), 0, st, loss_sum, lossb);
+  }
+  return hipGetLastError() == hipSuccess ? TR_OK : TR_EHIP;
+}
+
+size_t tr_mlp_train_work_bytes(int batch) {
+  return align256((size_t)batch * NINP * 4) + align256((size_t)batch * NOUT * 4) + align256((size_t)NPARAM * 4) +
+         align256(4) + work_bytes(batch);
+}
+
+}  // extern "C"

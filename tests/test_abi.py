@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "tr.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(tr_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*(tr_\w+)\s*\(", src, flags=re.M)))
 
 
 def test_header_declares_the_entry_points():

@@ -1,0 +1,133 @@
+"""GPU parity of the learned closure's MFMA kernels against the FP64 reference
+(same bfloat16 rounding points, float32 accumulation on the GPU): forward
+outputs and gradients per parameter tensor to relative Frobenius error 1e-2
+and cosine 0.9999, one Adam step, closure inputs and training targets; then
+training on the solver's own steps and a learned run that must converge to
+the plain method's answer."""
+import numpy as np
+import pytest
+
+from oracle import mlp, mlqd, planck
+from paper_2011_05427_amd import binding, closure, inputs
+
+from gpu_util import note, rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to("cuda")
+
+
+def _cos(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n, 8))
+    X[:, :5] = rng.normal(0, 1, (n, 5))
+    Y = np.stack([rng.uniform(0.2, 0.6, n), rng.normal(0, 0.2, n)], axis=1)
+    return X, Y
+
+
+@pytest.mark.parametrize("n", [1, 77, 1000])
+def test_forward_matches_reference(n):
+    note(f"mlp forward n={n}")
+    theta = mlp.init_params(3)
+    X, _ = _data(n, n)
+    net = binding.Mlp(theta)
+    out = to_np(net.forward(_f32(X))).reshape(n, 2)
+    ref, _ = mlp.forward(theta, X[:, :5], bf16=True)
+    assert rel_err(out, ref) < 1e-2
+    assert _cos(out[:, 1], ref[:, 1]) > 0.9999 or n == 1
+    assert np.max(np.abs(out[:, 0] - ref[:, 0])) < 1e-2
+
+
+@pytest.mark.parametrize("n", [64, 333])
+def test_gradients_match_reference(n):
+    note(f"mlp grad n={n}")
+    theta = mlp.init_params(4)
+    X, Y = _data(n, 10 + n)
+    net = binding.Mlp(theta)
+    g, loss = net.grad(_f32(X), _f32(Y))
+    g = to_np(g).astype(np.float64)
+    lref, gref = mlp.loss_and_grad(theta, X[:, :5], Y, bf16=True)
+    assert abs(float(to_np(loss)[0]) - lref) <= 1e-3 * lref
+    o = 0
+    for name, shp in mlp.SHAPES:
+        k = int(np.prod(shp))
+        a, b = g[o:o + k], gref[o:o + k]
+        if name == "W1":  # padded input rows carry no gradient
+            a, b = a[:mlp.NIN * mlp.NH], b[:mlp.NIN * mlp.NH]
+        assert rel_err(a, b) < 1e-2, name
+        assert _cos(a, b) > 0.9999, name
+        o += k
+
+
+def test_adam_step_matches_reference():
+    theta = mlp.init_params(5)
+    rng = np.random.default_rng(1)
+    grad = rng.normal(0, 1e-2, theta.size)
+    net = binding.Mlp(theta)
+    for _ in range(3):
+        net.adam(_f32(grad), 1e-3)
+    th, m, v = theta.copy(), np.zeros_like(theta), np.zeros_like(theta)
+    for t in range(1, 4):
+        th, m, v = mlp.adam_step(th, m, v, grad, t)
+    assert np.max(np.abs(to_np(net.params) - th)) < 1e-6
+
+
+def test_features_and_targets_match_reference():
+    slab = inputs.make_slab(37, 24, 4, T_left=0.9)
+    levels = [24, 6, 1]
+    sv = binding.Solver([slab], [levels], inputs.SolverCfg(levels=levels))
+    rng = np.random.default_rng(2)
+    T = 10 ** rng.uniform(-3, 0, slab.nx)
+    kap = planck.opacity(slab.nu_center, slab.C_cell, T)
+    mean, std = rng.normal(0, 1, 5), rng.uniform(0.5, 2, 5)
+    X = sv.empty(binding.TR_K_GI, 8).float()
+    sv.mlp_features(to_dev(T), to_dev(kap), mean, std, X)
+    ref = mlp.standardise(mlp.features(T, slab.nu_center, kap, np.diff(slab.x_edges), slab.T_left), mean, std)
+    got = to_np(X).reshape(-1, 8)
+    np.testing.assert_allclose(got[:, :5], ref, rtol=1e-5, atol=1e-5)
+    assert np.all(got[:, 5:] == 0)
+    f = rng.uniform(0.2, 0.6, (24, slab.nx))
+    En = 10 ** rng.uniform(-5, 0, (24, slab.nx))
+    Ep = 10 ** rng.uniform(-5, 0, (24, slab.nx))
+    Y = sv.empty(binding.TR_K_GI, 2).float()
+    sv.closure_targets(to_dev(f), to_dev(En), to_dev(Ep), 4, Y)
+    np.testing.assert_allclose(to_np(Y).reshape(-1, 2), mlp.targets(f, En, Ep, 4), rtol=2e-6, atol=1e-6)
+    sv.close()
+
+
+def test_training_and_learned_steps_converge_to_plain():
+    slab = inputs.make_slab(50, 32, 8, dt=0.004)
+    levels = [32, 8, 1]
+    cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_W, lmax=2, eps=1e-12, eps_inner=1e-13)
+    note("closure: data, training, learned vs plain")
+    ds = closure.generate(slab, cfg, levels, nsteps=8, n_samples=8 * 32 * 50, seed=0)
+    net, losses = closure.train(ds, epochs=30, batch=256, lr=2e-3, seed=0)
+    print("closure losses", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    runs = {}
+    for learned in (False, True):
+        sv = binding.Solver([slab], [levels], cfg)
+        if learned:
+            sv.set_closure(net, ds.mean, ds.std)
+        st = sv.new_state()
+        sv.state_init(st, slab.T0)
+        acc = (binding.TrStats * 1)()
+        for _ in range(8):
+            sv.step(st, stats=acc)
+        runs[learned] = (to_np(st["T"]).copy(), to_np(st["E"]).copy(), acc[0].n_ti, acc[0].n_seeded,
+                         acc[0].n_fallback)
+        sv.close()
+    print("sweeps plain", runs[False][2], "learned", runs[True][2], "seeded", runs[True][3], "fallback",
+          runs[True][4], flush=True)
+    assert runs[True][3] > 0
+    assert rel_err(runs[True][0], runs[False][0]) < 1e-9
+    assert rel_err(runs[True][1], runs[False][1]) < 1e-9
