@@ -3,15 +3,16 @@ multigrid in frequency on one MI355X.
 
 A "step" is one converged time step of the whole hot path (opacity/Planck
 tables, SCB transport sweeps with their moments, fine and coarse LO solves,
-restriction, grey LO + MEB Newton, cycle control) over the workload's slab.
+restriction, grey LO + MEB Newton, cycle control) over the workload's slabs.
 The default workload is the paper-scale problem: 200 cells, S16, 512 groups,
 V cycle on the hierarchy 512,128,32,8,1, dt = 0.002 ns; the timed region is
 the workload's 20 steps from the initial condition (inputs resident in HBM).
 
 Printed: one JSON line with the throughput in phase-space cell-updates per
-second (sweep cell-updates of the timed steps / wall time), ms per step,
-the live-measured roofline of the dominant kernel (the sweep) and the CPU
-oracle timed on a bounded sample of the same workload.
+second (sweep cell-updates of the timed steps / wall time), ms per step, the
+live-measured roofline of the sweep kernel (HIP events around its launches,
+algorithmic bytes per launch / average launch time), the learned closure vs
+the plain method, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -33,19 +34,24 @@ WORKLOADS = {
     "large": ("config_large",
               "large slab: 2000 cells, S32, 4096 groups, F cycle on 4096,1024,256,64,16,1, dt=0.002 ns, "
               "eps=1e-10"),
+    "batch": ("config_batch",
+              "batch of 256 uneven slabs (seed 201105427): nx in [50,400], groups in {64..1024}, S8/S16, "
+              "zone opacity constants log-uniform in [1,100], T_left in [0.5,1.5], W cycle G,G/8,1, "
+              "autotuned sweep tiles"),
 }
+KERNELS = ["opacity", "sweep", "moments", "lo_fine", "restrict", "lo_coarse", "grey"]
 
 
-def sweep_bytes_per_cell_update(M):
-    """Algorithmic HBM bytes of one FP64 SCB cell-update: read I^{j-1} (two
-    corners, 16 B) and write I (16 B); plus the half-range moment partials
-    (two doubles per cell, group and half range, shared by M/2 directions)."""
-    return 32.0 + 16.0 * 2 / M
+def sweep_bytes(slab):
+    """Algorithmic HBM bytes of one FP64 sweep of a slab: per cell-update read
+    the previous-time-level corner pair (16 B) and write the new one (16 B);
+    per (group, cell, half range) write the two moment partials (16 B)."""
+    return 32.0 * slab.cell_updates_per_sweep() + 32.0 * slab.ng * slab.nx
 
 
 def cpu_baseline(workload, budget_s=20.0):
     """The CPU oracle (numpy, FP64, one thread) on the first time steps of the
-    workload, bounded to about budget_s seconds; run in a child process whose
+    workload (bounded to about budget_s seconds); run in a child process whose
     BLAS / OpenMP pools are limited to one thread."""
     import subprocess
 
@@ -65,12 +71,28 @@ def _cpu_baseline_child(workload, budget_s):
     from paper_2011_05427_amd import inputs
 
     slabs, cfg, _ = getattr(inputs, WORKLOADS[workload][0])()
+    if workload == "batch":
+        # the oracle on the first slabs of the batch, one step each, within the budget
+        t0 = time.perf_counter()
+        cu, k = 0, 0
+        for slab in slabs:
+            pb = mlqd.problem_from_slab(slab)
+            st = mlqd.initial_state(pb, slab.T0)
+            stats = mlqd.Stats()
+            lv = inputs.levels_for(slab, cfg)
+            sched = inputs.SolverCfg(levels=lv, cycle=cfg.cycle).schedule()
+            mlqd.step(pb, lv, sched, cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
+            cu += slab.cell_updates_per_sweep() * stats.n_ti
+            k += 1
+            if time.perf_counter() - t0 > budget_s * 0.5:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": cu / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+                "sample": f"first time step of the first {k} slabs of the batch, numpy FP64, {dt:.1f} s"}
     slab = slabs[0]
-
     pb = mlqd.problem_from_slab(slab)
     if slab.cell_updates_per_sweep() > 5e7:
-        # large workload: a whole step exceeds the budget; time one transport
-        # sweep of the initial state (the dominant kernel) instead
+        # a whole step exceeds the budget: one transport sweep of the initial state
         from oracle.sweep import sweep
 
         st = mlqd.initial_state(pb, slab.T0)
@@ -91,45 +113,51 @@ def _cpu_baseline_child(workload, budget_s):
         if time.perf_counter() - t0 > budget_s * 0.5:
             break
     dt = time.perf_counter() - t0
-    cu = slab.cell_updates_per_sweep() * stats.n_ti
-    return {
-        "value": cu / dt,
-        "unit": "cell-updates/s",
-        "cores": 1,
-        "kind": "oracle",
-        "ms_per_step": 1e3 * dt / nsteps,
-        "sample": f"first {nsteps} time step(s) of the same workload ({stats.n_ti} sweeps), numpy FP64, "
-                  f"{dt:.1f} s",
-    }
+    return {"value": slab.cell_updates_per_sweep() * stats.n_ti / dt, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle", "ms_per_step": 1e3 * dt / nsteps,
+            "sample": f"first {nsteps} time step(s) of the same workload ({stats.n_ti} sweeps), numpy FP64, "
+                      f"{dt:.1f} s"}
+
+
+def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closure=None):
+    """Runs warmup steps, then `steps` steps from the initial condition; returns
+    (wall seconds, per-slab TrStats)."""
+    import torch
+
+    from paper_2011_05427_amd import binding
+
+    sv = binding.Solver(slabs, levels, cfg, timing=timing)
+    if tiles is not None:
+        sv.set_tiles(tiles)
+    if closure is not None:
+        sv.set_closure(*closure)
+    st = sv.new_state()
+    sv.state_init(st, slabs[0].T0)
+    for _ in range(warmup):
+        sv.step(st)
+    sv.state_init(st, slabs[0].T0)
+    torch.cuda.synchronize()
+    acc = (binding.TrStats * len(slabs))()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sv.step(st, stats=acc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sv.close()
+    return wall, acc
 
 
 def learned_vs_plain(slab, cfg, args, plain_ms, plain_sweeps):
-    """Trains the closure on the plain solver's own steps of this workload (the
-    paper-scale sweeps), then times the same timed steps with the closure
-    seeding each step's factors.  The plain sweeps still decide convergence."""
-    import torch
-
-    from paper_2011_05427_amd import binding, closure
+    """Trains the closure on the plain solver's own steps of this workload, then
+    times the same steps with the closure seeding each step's factors (the
+    plain sweeps still decide convergence)."""
+    from paper_2011_05427_amd import closure
 
     t0 = time.perf_counter()
     ds = closure.generate(slab, cfg, cfg.levels, nsteps=args.steps, n_samples=args.train_samples, seed=0)
     net, losses = closure.train(ds, epochs=args.train_epochs, batch=4096, lr=1e-3, seed=0)
     train_s = time.perf_counter() - t0
-    sv = binding.Solver([slab], [cfg.levels], cfg)
-    sv.set_closure(net, ds.mean, ds.std)
-    st = sv.new_state()
-    sv.state_init(st, slab.T0)
-    for _ in range(args.warmup):
-        sv.step(st)
-    sv.state_init(st, slab.T0)
-    torch.cuda.synchronize()
-    acc = (binding.TrStats * 1)()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        sv.step(st, stats=acc)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t1
-    sv.close()
+    wall, acc = run_steps([slab], [cfg.levels], cfg, args.steps, args.warmup, closure=(net, ds.mean, ds.std))
     ms = 1e3 * wall / args.steps
     return {"ms_per_step": ms, "plain_ms_per_step": plain_ms, "speedup": plain_ms / ms,
             "sweeps": int(acc[0].n_ti), "plain_sweeps": plain_sweeps, "seeded": int(acc[0].n_seeded),
@@ -141,7 +169,7 @@ def learned_vs_plain(slab, cfg, args, plain_ms, plain_sweeps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -161,56 +189,43 @@ def main():
 
     import torch
 
-    from paper_2011_05427_amd import binding, inputs
+    from paper_2011_05427_amd import binding, inputs, tuning
 
     fn, desc = WORKLOADS[args.workload]
     slabs, cfg, nsteps_cfg = getattr(inputs, fn)()
-    slab = slabs[0]
+    if args.steps is None:
+        args.steps = {"paper": 20, "small": 1, "large": 3, "batch": 2}[args.workload]
+    levels = [inputs.levels_for(s, cfg) for s in slabs]
     torch.cuda.set_device(0)
-    sv = binding.Solver([slab], [cfg.levels], cfg)
-    st = sv.new_state()
 
-    # warmup from the initial condition
-    sv.state_init(st, slab.T0)
-    for _ in range(args.warmup):
-        sv.step(st)
-    torch.cuda.synchronize()
+    tiles, tune_info = None, None
+    if args.workload == "batch":
+        sv = binding.Solver(slabs, levels, cfg)
+        st = sv.new_state()
+        sv.state_init(st, slabs[0].T0)
+        t0 = time.perf_counter()
+        tune_info = tuning.tune(sv, st, reps=3, path=None)
+        tune_info["tune_s"] = time.perf_counter() - t0
+        tiles = tune_info["K"]
+        sv.close()
+        del st
 
-    # timed: K steps from the initial condition
-    sv.state_init(st, slab.T0)
-    torch.cuda.synchronize()
-    acc = (binding.TrStats * 1)()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sv.step(st, stats=acc)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # timed: graph replay, no events
+    wall, acc = run_steps(slabs, levels, cfg, args.steps, args.warmup, tiles=tiles)
+    # per-kernel durations: the same steps with HIP events around each kernel group
+    # (eager launches, not part of the timed value)
+    _, prof = run_steps(slabs, levels, cfg, args.steps, 0, timing=True, tiles=tiles)
 
-    a = acc[0]
-    sv.close()
-
-    # per-kernel durations: the same steps again with HIP events around each
-    # kernel group (launched without graph replay; not part of the timed value)
-    svt = binding.Solver([slab], [cfg.levels], cfg, timing=True)
-    stt = svt.new_state()
-    svt.state_init(stt, slab.T0)
-    prof = (binding.TrStats * 1)()
-    for _ in range(args.steps):
-        svt.step(stt, stats=prof)
-    torch.cuda.synchronize()
-    svt.close()
-    p = prof[0]
-    cu_sweep = slab.cell_updates_per_sweep()
-    sweeps = a.n_ti
-    value = cu_sweep * sweeps / wall
-    t_sweep_ms = p.t_ms[binding.T_SWEEP]
+    sweeps = [int(acc[k].n_ti) for k in range(len(slabs))]
+    cu = sum(s.cell_updates_per_sweep() * n for s, n in zip(slabs, sweeps))
+    value = cu / wall
+    p = prof[0]  # kernel-group times cover the whole context
+    t_sweep_s = p.t_ms[binding.T_SWEEP] / 1e3
     n_sweep = p.n_launch[binding.T_SWEEP]
-    avg_sweep_s = t_sweep_ms / max(n_sweep, 1) / 1e3
-    bytes_per_launch = sweep_bytes_per_cell_update(slab.nmu) * cu_sweep
-    achieved = bytes_per_launch / avg_sweep_s / 1e9 if avg_sweep_s > 0 else 0.0
-    kernel_ms = {name: p.t_ms[k] / max(args.steps, 1) for k, name in
-                 enumerate(["opacity", "sweep", "moments", "lo_fine", "restrict", "lo_coarse", "grey"])}
-
+    bytes_total = sum(sweep_bytes(s) * int(prof[k].n_ti) for k, s in enumerate(slabs))
+    achieved = bytes_total / t_sweep_s / 1e9 if t_sweep_s > 0 else 0.0
+    kernel_ms = {name: p.t_ms[k] / max(args.steps, 1) for k, name in enumerate(KERNELS)}
+    ms_step = 1e3 * wall / args.steps
     out = {
         "metric": "phase-space cell-updates/s per sweep; ms per converged time step, learned vs plain",
         "value": value,
@@ -218,7 +233,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -226,14 +241,16 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc,
-            "nx": slab.nx, "groups": slab.ng, "directions": slab.nmu,
-            "levels": cfg.levels, "cycle": "VWF"[cfg.cycle], "lmax": cfg.lmax,
-            "steps_timed": args.steps, "cell_updates_per_sweep": cu_sweep,
-            "sweeps": int(sweeps), "cycles": int(a.n_c), "lo_solves": int(a.n_lo),
-            "closure": "plain",
+            "slabs": len(slabs),
+            "cell_updates_per_sweep": sum(s.cell_updates_per_sweep() for s in slabs),
+            "levels": levels[0] if len(slabs) == 1 else "per slab G,G/8,1",
+            "cycle": "VWF"[cfg.cycle], "lmax": cfg.lmax, "eps": cfg.eps,
+            "steps_timed": args.steps, "sweeps": sum(sweeps), "cycles": int(sum(a.n_c for a in acc)),
+            "lo_solves": int(sum(a.n_lo for a in acc)), "closure": "plain",
         },
         "kernel_ms_per_step": kernel_ms,
-        "sweep_kernel_cell_updates_per_s": cu_sweep / avg_sweep_s if avg_sweep_s > 0 else None,
+        "sweep_kernel_cell_updates_per_s": (sum(s.cell_updates_per_sweep() * int(prof[k].n_ti)
+                                                for k, s in enumerate(slabs)) / t_sweep_s) if t_sweep_s else None,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_sweep",
@@ -242,13 +259,16 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": avg_sweep_s * 1e6,
+            "bytes_per_launch": bytes_total / max(n_sweep, 1),
+            "avg_launch_us": 1e6 * t_sweep_s / max(n_sweep, 1),
             "launches": int(n_sweep),
         },
     }
-    if not args.no_learned:
-        out["learned"] = learned_vs_plain(slab, cfg, args, out["ms_per_step"], int(sweeps))
+    if tune_info is not None:
+        out["tiles"] = {"K_per_bucket": tune_info["K"], "us_per_K": tune_info["us"],
+                        "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}
+    if not args.no_learned and len(slabs) == 1 and slabs[0].cell_updates_per_sweep() < 5e7:
+        out["learned"] = learned_vs_plain(slabs[0], cfg, args, ms_step, sum(sweeps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -252,11 +252,29 @@ typedef struct tr_stats {
  * A8: one backward-Euler step of paper Alg. 3 for every slab (V/W/F cycles,
  * grid skipping, inner/outer infinity-norm tests, lmax cap).  replay (host,
  * nullable): per slab, a row of 64 ints = cycles per transport iteration
- * (0 terminates), executed instead of the convergence tests.  stats (host,
+ * (0 terminates; a row starting with 0 leaves that slab free-running),
+ * executed instead of the convergence tests.  stats (host,
  * nullable): [n_slab] counters accumulated over calls.
  * Errors: TR_ENOCONV, TR_ENAN, TR_EHIP.
  */
 int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats, hipStream_t stream);
+
+/*
+ * Batched launch tiles.  Sweep work is grouped by slab size into 6 buckets
+ * (nx <= 64, 128, 256, 512, 1024, larger), ordered longest slab first, and
+ * each bucket's wavefronts own K in {1, 2, 4, 8} consecutive cells per lane.
+ * tr_autotune times every K on each non-empty bucket (reps launches each, on
+ * the given I buffers and the context's current opacity tables) and keeps the
+ * fastest; K_out (host [6]) and us_out (host [6][4], microseconds per launch
+ * for K = 1, 2, 4, 8; nullable) report the result.  tr_set_tiles applies a
+ * cached choice; tr_get_tiles reads the current one and the items per bucket
+ * (host [6] each, items nullable).  Choosing tiles changes only the
+ * association of the sweep's prefix scan (results at roundoff).
+ */
+int tr_autotune(tr_ctx *ctx, const double *I_prev, double *I_out, int reps, int *K_out, double *us_out,
+                hipStream_t stream);
+int tr_set_tiles(tr_ctx *ctx, const int *K);
+int tr_get_tiles(const tr_ctx *ctx, int *K, int *items);
 
 /*
  * Learned closure (not part of the paper's method; its plain sweep stays the

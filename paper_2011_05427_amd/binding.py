@@ -69,7 +69,8 @@ T_OPACITY, T_SWEEP, T_MOMENTS, T_LO_FINE, T_RESTRICT, T_LO_COARSE, T_GREY = rang
 EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_incoming", "tr_opacity",
            "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step",
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
-           "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure"]
+           "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
+           "tr_autotune", "tr_set_tiles", "tr_get_tiles"]
 
 _lib = None
 
@@ -116,6 +117,9 @@ def load():
     lib.tr_mlp_features.argtypes = [vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
     lib.tr_closure_targets.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
     lib.tr_set_closure.argtypes = [vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    lib.tr_autotune.argtypes = [vp, vp, vp, C.c_int, _ip, _dp, vp]
+    lib.tr_set_tiles.argtypes = [vp, _ip]
+    lib.tr_get_tiles.argtypes = [vp, _ip, _ip]
     for name in EXPORTS:
         if name not in ("tr_error_string", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes"):
             getattr(lib, name).restype = C.c_int
@@ -368,6 +372,26 @@ def _solver_methods():
         _check(self.lib.tr_set_closure(self._ctx, _ptr(mlp.params), _f32(mean), _f32(std)), "tr_set_closure")
         self._closure = mlp
 
+    def autotune(self, st, reps=3):
+        """Times sweep tiles per slab-size bucket; returns (K[6], us[6][4])."""
+        K = (C.c_int * 6)()
+        us = (C.c_double * 24)()
+        _check(self.lib.tr_autotune(self._ctx, _ptr(st["I_prev"]), _ptr(st["I_out"]), reps, K, us, self._stream()),
+               "tr_autotune")
+        return list(K), [list(us[4 * b:4 * b + 4]) for b in range(6)]
+
+    def set_tiles(self, K):
+        arr = (C.c_int * 6)(*[int(k) for k in K])
+        _check(self.lib.tr_set_tiles(self._ctx, arr), "tr_set_tiles")
+
+    def get_tiles(self):
+        K, n = (C.c_int * 6)(), (C.c_int * 6)()
+        _check(self.lib.tr_get_tiles(self._ctx, K, n), "tr_get_tiles")
+        return list(K), list(n)
+
+    Solver.autotune = autotune
+    Solver.set_tiles = set_tiles
+    Solver.get_tiles = get_tiles
     Solver.mlp_features = mlp_features
     Solver.closure_targets = closure_targets
     Solver.set_closure = set_closure

@@ -14,6 +14,7 @@
 #include "tr_kernels.h"
 
 #define TR_NHEAD 40
+#define TR_NBUCKET 6
 
 namespace {
 
@@ -52,7 +53,11 @@ struct tr_ctx {
   int *d_count = nullptr;
   int *h_count = nullptr;  // pinned
   // work tables
-  Table t_opac{}, t_cell{}, t_sweep{}, t_gi{}, t_g{}, t_grey{};
+  Table t_opac{}, t_cell{}, t_gi{}, t_g{}, t_grey{};
+  // sweep work per slab-size bucket (nx <= 64, 128, 256, 512, 1024, more),
+  // longest slabs first; K = cells per lane of each bucket's launch
+  Table t_sweep_b[TR_NBUCKET]{};
+  int sweep_K[TR_NBUCKET] = {1, 2, 4, 4, 4, 4};
   Table t_lo[TR_MAXLEV]{};
   std::map<std::pair<int, int>, RestrictTables> t_red;
   // optional event timing of kernel groups inside tr_step
@@ -175,6 +180,21 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
 }
 
 LaunchEnv env_of(const tr_ctx *c, hipStream_t st) { return LaunchEnv{c->d_sd, c->pd, st}; }
+
+int sweep_bucket(int nx) {
+  int b = 0, lim = 64;
+  while (b < TR_NBUCKET - 1 && nx > lim) {
+    ++b;
+    lim *= 2;
+  }
+  return b;
+}
+
+void launch_sweeps(const tr_ctx *c, const LaunchEnv &env, const Ctl *ctl, int pmode, const double *kappa,
+                   const double *B, const double *Ip, double *Io, double *mom, double *bnd) {
+  for (int b = 0; b < TR_NBUCKET; ++b)
+    launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], ctl, pmode, 0, kappa, B, Ip, Io, mom, bnd);
+}
 
 // Event marks around kernel groups (cfg.timing).  A group records its cycle
 // index (-1 outside the cycles) so that launches of cycles a slab skipped can
@@ -506,14 +526,16 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
 
   // work tables
   {
-    std::vector<Item> opac, cell, sweep, gi, g, grey;
+    std::vector<Item> opac, cell, gi, g, grey;
+    std::vector<std::vector<std::pair<long long, Item>>> sweepb(TR_NBUCKET);
     std::vector<std::vector<Item>> lo(nlev);
     for (int s = 0; s < n_slab; ++s) {
       const SlabDev &S = c->hs[s];
       const int ncb = (S.nx + 15) / 16;
       for (int q = 0; q < S.nchunk * ncb; ++q) opac.push_back({s, q});
       for (int st = 0; st < S.nx; st += 256) cell.push_back({s, st});
-      for (int gg = 0; gg < S.ng; ++gg) sweep.push_back({s, gg});
+      const long long cost = (long long)S.nx * S.nmu;
+      for (int gg = 0; gg < S.ng; ++gg) sweepb[sweep_bucket(S.nx)].push_back({cost, Item{s, gg}});
       for (long long st = 0; st < (long long)S.ng * S.nx; st += 256) gi.push_back({s, (int)st});
       for (int st = 0; st < S.ng; st += 256) g.push_back({s, st});
       grey.push_back({s, 0});
@@ -521,11 +543,19 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
         for (int p = 0; p < S.lev_ng[l]; ++p) lo[l].push_back({s, p});
     }
     if ((rc = upload_table(c, opac, c->t_opac)) || (rc = upload_table(c, cell, c->t_cell)) ||
-        (rc = upload_table(c, sweep, c->t_sweep)) || (rc = upload_table(c, gi, c->t_gi)) ||
+        (rc = upload_table(c, gi, c->t_gi)) ||
         (rc = upload_table(c, g, c->t_g)) || (rc = upload_table(c, grey, c->t_grey)))
       return fail(rc);
     for (int l = 0; l < nlev; ++l)
       if ((rc = upload_table(c, lo[l], c->t_lo[l]))) return fail(rc);
+    for (int b = 0; b < TR_NBUCKET; ++b) {
+      // longest-processing-time order: the most expensive slabs start first
+      auto &v = sweepb[b];
+      std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+      std::vector<Item> items;
+      for (auto &e : v) items.push_back(e.second);
+      if ((rc = upload_table(c, items, c->t_sweep_b[b]))) return fail(rc);
+    }
     if ((rc = build_restrict_tables(c, 0, nlev - 1))) return fail(rc);
     for (int gsched : c->sched) {
       if ((rc = build_restrict_tables(c, 0, gsched)) || (rc = build_restrict_tables(c, gsched, nlev - 1)))
@@ -618,7 +648,7 @@ int tr_opacity(tr_ctx *c, const double *T, double *kappa, double *B, double *dS,
 int tr_sweep(tr_ctx *c, const double *kappa, const double *B, const double *I_prev, double *I_out, double *mom,
              double *bnd, hipStream_t st) {
   if (!c || !kappa || !B || !I_prev || !I_out || !mom || !bnd || I_prev == I_out) return TR_EINVAL;
-  launch_sweep(env_of(c, st), c->t_sweep, nullptr, PRED_ALL, 0, kappa, B, I_prev, I_out, mom, bnd);
+  launch_sweeps(c, env_of(c, st), nullptr, PRED_ALL, kappa, B, I_prev, I_out, mom, bnd);
   return hip_err(hipGetLastError());
 }
 
@@ -669,6 +699,72 @@ int tr_grey_solve(tr_ctx *c, const tr_lo_coeffs *grey, const double *Tstar, cons
   ga.D = D;
   launch_grey(env_of(c, st), c->t_grey, c->lo_threads, nullptr, PRED_ALL, 0, ga);
   return hip_err(hipGetLastError());
+}
+
+int tr_set_tiles(tr_ctx *c, const int *K) {
+  if (!c || !K) return TR_EINVAL;
+  for (int b = 0; b < TR_NBUCKET; ++b)
+    if (K[b] != 1 && K[b] != 2 && K[b] != 4 && K[b] != 8) return TR_EINVAL;
+  for (int b = 0; b < TR_NBUCKET; ++b) c->sweep_K[b] = K[b];
+  // captured launch sequences hold the old tiles
+  for (auto &g : c->graphs) {
+    if (g.first) (void)hipGraphExecDestroy(g.first);
+    if (g.next) (void)hipGraphExecDestroy(g.next);
+  }
+  c->graphs.clear();
+  return TR_OK;
+}
+
+int tr_get_tiles(const tr_ctx *c, int *K, int *items) {
+  if (!c || !K) return TR_EINVAL;
+  for (int b = 0; b < TR_NBUCKET; ++b) {
+    K[b] = c->sweep_K[b];
+    if (items) items[b] = c->t_sweep_b[b].n;
+  }
+  return TR_OK;
+}
+
+int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K_out, double *us_out,
+                hipStream_t st) {
+  if (!c || !I_prev || !I_out || I_prev == I_out || reps < 1) return TR_EINVAL;
+  static const int cand[4] = {1, 2, 4, 8};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TR_EHIP;
+  LaunchEnv env = env_of(c, st);
+  int K[TR_NBUCKET];
+  int rc = TR_OK;
+  for (int b = 0; b < TR_NBUCKET && !rc; ++b) {
+    K[b] = c->sweep_K[b];
+    if (c->t_sweep_b[b].n == 0) {
+      if (us_out)
+        for (int q = 0; q < 4; ++q) us_out[4 * b + q] = 0.0;
+      continue;
+    }
+    double best = 1e300;
+    for (int q = 0; q < 4 && !rc; ++q) {
+      launch_sweep(env, c->t_sweep_b[b], cand[q], nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom, c->bnd);
+      if (hipEventRecord(e0, st) != hipSuccess) rc = TR_EHIP;
+      for (int r = 0; r < reps; ++r)
+        launch_sweep(env, c->t_sweep_b[b], cand[q], nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
+                     c->bnd);
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = TR_EHIP;
+      const double us = 1e3 * ms / reps;
+      if (us_out) us_out[4 * b + q] = us;
+      if (us < best) {
+        best = us;
+        K[b] = cand[q];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (K_out)
+    for (int b = 0; b < TR_NBUCKET; ++b) K_out[b] = K[b];
+  return tr_set_tiles(c, K);
 }
 
 int tr_mlp_features(tr_ctx *c, const double *T, const double *kappa, const float *mean, const float *std, float *X,
@@ -766,7 +862,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
     {
       TimedScope ts(c, st, TR_T_SWEEP, -1);
-      launch_sweep(env, c->t_sweep, c->d_ctl, PRED_SWEEP, 0, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
+      launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
     }
     {
       TimedScope ts(c, st, TR_T_MOMENTS, -1);
@@ -850,14 +946,14 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
     k.active = 1;
     if (replay) {
       const int *row = replay + (size_t)q * TR_MAXOUT;
+      if (row[0] < 0) return TR_EINVAL;
       int n = 0;
       while (n < TR_MAXOUT && row[n] > 0) {
         k.replay[n] = row[n];
         Lmax = std::max(Lmax, row[n]);
         ++n;
       }
-      if (n == 0) return TR_EINVAL;
-      k.n_replay = n;
+      k.n_replay = n;  // 0: this slab runs its own convergence tests
     }
   }
   // everything runs on the library stream, ordered after the caller's work

@@ -54,8 +54,9 @@ struct Table {
 void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *T,
                     double *kappa, double *B, double *dSpart);
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart, double *dS);
-void launch_sweep(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *kappa,
-                  const double *B, const double *Ip, double *Io, double *mom, double *bnd);
+// Sweep tiles: K consecutive cells per lane (K in {1, 2, 4, 8}).
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, const Ctl *ctl, int pmode, int lcyc,
+                  const double *kappa, const double *B, const double *Ip, double *Io, double *mom, double *bnd);
 void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
                     const double *bnd, double *f, double *fbnd, double *C, double *Phi);
 void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi);

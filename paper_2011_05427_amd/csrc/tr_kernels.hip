@@ -1075,13 +1075,21 @@ void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart,
   hipLaunchKernelGGL(k_dS_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, dSpart, dS);
 }
 
-void launch_sweep(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *kappa,
-                  const double *B, const double *Ip, double *Io, double *mom, double *bnd) {
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, const Ctl *ctl, int pmode, int lcyc,
+                  const double *kappa, const double *B, const double *Ip, double *Io, double *mom, double *bnd) {
   if (tab.n == 0) return;
   const int waves = 2 * tab.n;
   const int nb = (waves + 3) / 4;
-  hipLaunchKernelGGL(k_sweep<4>, blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n, ctl, pmode, lcyc,
-                     kappa, B, Ip, Io, mom, bnd);
+#define TR_SWEEP_K(KK)                                                                                              \
+  hipLaunchKernelGGL(k_sweep<KK>, blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n, ctl, pmode, \
+                     lcyc, kappa, B, Ip, Io, mom, bnd)
+  switch (K) {
+    case 1: TR_SWEEP_K(1); break;
+    case 2: TR_SWEEP_K(2); break;
+    case 8: TR_SWEEP_K(8); break;
+    default: TR_SWEEP_K(4); break;
+  }
+#undef TR_SWEEP_K
 }
 
 void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,

@@ -1,0 +1,112 @@
+"""Batched path (many uneven slabs per launch) and its tiles: every sweep tile
+agrees with the oracle; a slab solved inside a batch equals the same slab
+solved alone bit for bit; sampled slabs of a batch match their own oracle
+runs; the autotuner keeps a valid tile per bucket."""
+import numpy as np
+import pytest
+
+from oracle import mlqd, planck
+from oracle.moments import factors
+from oracle.sweep import sweep
+from paper_2011_05427_amd import binding, inputs, tuning
+
+from gpu_util import assert_close, note, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def test_every_sweep_tile_matches_oracle(K):
+    note(f"sweep tile K={K}")
+    slab = inputs.make_slab(300, 3, 16, T_left=1.0, T_right=0.5)
+    sv = binding.Solver([slab], [[3, 1]], inputs.SolverCfg(levels=[3, 1]))
+    sv.set_tiles([K] * 6)
+    rng = np.random.default_rng(K)
+    kap = 10 ** rng.uniform(-2, 4, (3, 300))
+    B = rng.uniform(0, 1, (3, 300))
+    Ip = rng.uniform(0, 1, (3, 16, 300, 2))
+    Io = sv.empty(binding.TR_K_I)
+    mom, bnd = sv.empty(binding.TR_K_GI, 4), sv.empty(binding.TR_K_G, 6)
+    sv.sweep(to_dev(kap), to_dev(B), to_dev(Ip), Io, mom, bnd)
+    f, fb, Cb, Phi = (sv.empty(binding.TR_K_GI), sv.empty(binding.TR_K_G2), sv.empty(binding.TR_K_G2),
+                      sv.empty(binding.TR_K_G2))
+    sv.moments(mom, bnd, f, fb, Cb, Phi)
+    il = planck.boundary_intensity(slab.nu_edges, 1.0, slab.aR, slab.c)
+    ir = planck.boundary_intensity(slab.nu_edges, 0.5, slab.aR, slab.c)
+    ref = sweep(slab.mu, slab.x_edges, kap, B, Ip, il, ir, slab.c, slab.dt)
+    fac = factors(slab.mu, slab.w, ref, il, ir, slab.c)
+    got = to_np(Io, ref.shape)
+    for g in range(3):
+        assert_close(f"I g={g}", got[g], ref[g], 1e-12)
+    assert_close("f", to_np(f, (3, 300)), fac.f, 1e-12)
+    assert_close("C", to_np(Cb, (3, 2)), fac.C, 1e-12)
+    sv.close()
+
+
+def _batch(n):
+    slabs, cfg, _ = inputs.config_batch(n)
+    levels = [inputs.levels_for(s, cfg) for s in slabs]
+    return slabs, levels, cfg
+
+
+def _slab_view(sv, st, k):
+    s = sv.slabs[k]
+    oc = sv.layout(binding.TR_K_CELL, k)[0]
+    ogi = sv.layout(binding.TR_K_GI, k)[0]
+    oI = sv.layout(binding.TR_K_I, k)[0]
+    return (to_np(st["T"])[oc:oc + s.nx].copy(), to_np(st["E"])[ogi:ogi + s.ng * s.nx].copy(),
+            to_np(st["I_prev"])[oI:oI + s.ng * s.nmu * s.nx * 2].copy())
+
+
+def test_batched_equals_individual():
+    slabs, levels, cfg = _batch(20)
+    note("batch of 20 slabs from the uneven-batch distribution, one free-running step")
+    sv = binding.Solver(slabs, levels, cfg)
+    st = sv.new_state()
+    sv.state_init(st, 0.001)
+    sv.step(st)
+    batched = {k: _slab_view(sv, st, k) for k in (0, 7, 13)}
+    sv.close()
+    for k, ref in batched.items():
+        one = binding.Solver([slabs[k]], [levels[k]], cfg)
+        s1 = one.new_state()
+        one.state_init(s1, 0.001)
+        one.step(s1)
+        got = _slab_view(one, s1, 0)
+        one.close()
+        for a, b, name in zip(got, ref, ("T", "E", "I")):
+            assert np.array_equal(a, b), (k, name)
+
+
+def test_batch_sampled_slabs_match_oracle():
+    slabs, levels, cfg = _batch(20)
+    small = sorted(range(20), key=lambda k: slabs[k].ng * slabs[k].nx * slabs[k].nmu)[:2]
+    refs = {}
+    for k in small:
+        pb = mlqd.problem_from_slab(slabs[k])
+        st0 = mlqd.initial_state(pb, 0.001)
+        stats = mlqd.Stats()
+        sched = inputs.SolverCfg(levels=levels[k], cycle=cfg.cycle).schedule()
+        refs[k] = (mlqd.step(pb, levels[k], sched, cfg.lmax, cfg.eps, cfg.eps_inner, st0, stats=stats),
+                   stats.counts[0])
+    note(f"batch of 20, replay on slabs {small}")
+    sv = binding.Solver(slabs, levels, cfg)
+    tuning.tune(sv, _init(sv), reps=1, path=None)
+    st = _init(sv)
+    replay = [refs[k][1] if k in refs else [0] for k in range(20)]
+    sv.step(st, replay=replay)
+    for k, (ref, _) in refs.items():
+        T, E, I = _slab_view(sv, st, k)
+        assert_close(f"slab {k} T", T, ref.T, 1e-10, atol_scale=0.0)
+        assert_close(f"slab {k} E", E.reshape(ref.E.shape), ref.E, 1e-10)
+        assert_close(f"slab {k} I", I.reshape(ref.I.shape), ref.I, 1e-10)
+    K, items = sv.get_tiles()
+    assert all(k in (1, 2, 4, 8) for k in K)
+    assert sum(items) == sum(s.ng for s in slabs)
+    sv.close()
+
+
+def _init(sv):
+    st = sv.new_state()
+    sv.state_init(st, 0.001)
+    return st
