@@ -42,11 +42,12 @@ WORKLOADS = {
 KERNELS = ["opacity", "sweep", "moments", "lo_fine", "restrict", "lo_coarse", "grey"]
 
 
-def sweep_bytes(slab):
-    """Algorithmic HBM bytes of one FP64 sweep of a slab: per cell-update read
-    the previous-time-level corner pair (16 B) and write the new one (16 B);
-    per (group, cell, half range) write the two moment partials (16 B)."""
-    return 32.0 * slab.cell_updates_per_sweep() + 32.0 * slab.ng * slab.nx
+def sweep_bytes(slab, ibytes=8):
+    """Algorithmic HBM bytes of one sweep of a slab: per cell-update read the
+    previous-time-level corner pair and write the new one (2 x 2 values of
+    ibytes each: 32 B in binary64, 16 B with binary32 storage); per (group,
+    cell, half range) write the two binary64 moment partials (16 B)."""
+    return 4.0 * ibytes * slab.cell_updates_per_sweep() + 32.0 * slab.ng * slab.nx
 
 
 def cpu_baseline(workload, budget_s=20.0):
@@ -119,9 +120,10 @@ def _cpu_baseline_child(workload, budget_s):
                       f"{dt:.1f} s"}
 
 
-def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closure=None):
+def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closure=None, final=None):
     """Runs warmup steps, then `steps` steps from the initial condition; returns
-    (wall seconds, per-slab TrStats)."""
+    (wall seconds, per-slab TrStats); with a dict `final`, the final T and E
+    are copied into it."""
     import torch
 
     from paper_2011_05427_amd import binding
@@ -143,6 +145,9 @@ def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closu
         sv.step(st, stats=acc)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if final is not None:
+        final["T"] = st["T"].cpu().numpy()
+        final["E"] = st["E"].cpu().numpy()
     sv.close()
     return wall, acc
 
@@ -178,6 +183,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
     ap.add_argument("--train-samples", type=int, default=1000000)
     ap.add_argument("--train-epochs", type=int, default=5)
+    ap.add_argument("--fp32", action="store_true",
+                    help="also time the binary32-storage sweep variant and state its error vs binary64")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget)))
@@ -211,7 +218,8 @@ def main():
         del st
 
     # timed: graph replay, no events
-    wall, acc = run_steps(slabs, levels, cfg, args.steps, args.warmup, tiles=tiles)
+    fin64 = {}
+    wall, acc = run_steps(slabs, levels, cfg, args.steps, args.warmup, tiles=tiles, final=fin64)
     # per-kernel durations: the same steps with HIP events around each kernel group
     # (eager launches, not part of the timed value)
     _, prof = run_steps(slabs, levels, cfg, args.steps, 0, timing=True, tiles=tiles)
@@ -264,6 +272,28 @@ def main():
             "launches": int(n_sweep),
         },
     }
+    if args.fp32:
+        import dataclasses
+
+        import numpy as np
+
+        cfg32 = dataclasses.replace(cfg, precision=1)
+        fin32 = {}
+        wall32, acc32 = run_steps(slabs, levels, cfg32, args.steps, args.warmup, tiles=tiles, final=fin32)
+        _, prof32 = run_steps(slabs, levels, cfg32, args.steps, 0, timing=True, tiles=tiles)
+        t32 = prof32[0].t_ms[binding.T_SWEEP] / 1e3
+        b32 = sum(sweep_bytes(s, 4) * int(prof32[k].n_ti) for k, s in enumerate(slabs))
+        rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        out["fp32_storage"] = {
+            "ms_per_step": 1e3 * wall32 / args.steps,
+            "value": sum(s.cell_updates_per_sweep() * int(acc32[k].n_ti) for k, s in enumerate(slabs)) / wall32,
+            "sweeps": int(sum(a.n_ti for a in acc32)),
+            "sweep_achieved_GBs": b32 / t32 / 1e9 if t32 > 0 else None,
+            "sweep_frac_of_hbm": b32 / t32 / 1e9 / HBM_PEAK_GBS if t32 > 0 else None,
+            "max_rel_err_T_vs_f64": rel(fin32["T"], fin64["T"]),
+            "max_rel_err_E_vs_f64": rel(fin32["E"], fin64["E"]),
+            "note": "corner intensities stored in binary32; sweep arithmetic, moments, LO, grey and MEB in binary64",
+        }
     if tune_info is not None:
         out["tiles"] = {"K_per_bucket": tune_info["K"], "us_per_K": tune_info["us"],
                         "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}

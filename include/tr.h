@@ -105,7 +105,13 @@ typedef struct tr_solver_cfg {
                        sigma_E (Eq. f-derivative-d); 0: D = 0 */
   int timing;       /* 1: tr_step brackets its kernel groups with HIP events
                        and accumulates their durations in tr_stats.t_ms */
+  int precision;    /* TR_PREC_F64: corner intensities stored in binary64;
+                       TR_PREC_F32_STORAGE: stored in binary32 (I arrays are
+                       float), every sweep operation and all moments still in
+                       binary64 registers */
 } tr_solver_cfg;
+
+enum { TR_PREC_F64 = 0, TR_PREC_F32_STORAGE = 1 };
 
 typedef struct tr_ctx tr_ctx;
 
@@ -143,7 +149,7 @@ int tr_opacity(tr_ctx *ctx, const double *T, double *kappa, double *B, double *d
  *                     sum w mu^2 psi) of half h at its outflow boundary,
  * h = 0 for mu > 0, 1 for mu < 0.  mom has 4 * gi elements per slab, bnd
  * 6 * ng (offsets: 4 * gi offset, 6 * g offset).  I_prev and I_out must not
- * alias.
+ * alias.  With TR_PREC_F32_STORAGE, I_prev and I_out point to float arrays.
  */
 int tr_sweep(tr_ctx *ctx, const double *kappa, const double *B, const double *I_prev, double *I_out,
              double *mom, double *bnd, hipStream_t stream);
@@ -218,7 +224,8 @@ int tr_grey_solve(tr_ctx *ctx, const tr_lo_coeffs *grey, const double *Tstar, co
 /* Caller-owned step state (device, pooled). */
 typedef struct tr_state {
   double *T;       /* cell: material temperature */
-  const double *I_prev; /* I: corner intensities of the previous time level */
+  const double *I_prev; /* I: corner intensities of the previous time level
+                           (float with TR_PREC_F32_STORAGE) */
   double *I_out;   /* I: written by every sweep; holds I^j after the step */
   double *E, *F, *Ebnd; /* gi, ge, g2: fine LO solution (old-time values in,
                            new values out) */

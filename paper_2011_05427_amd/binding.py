@@ -34,7 +34,7 @@ class TrProblem(C.Structure):
 
 class TrSolverCfg(C.Structure):
     _fields_ = [("cycle", C.c_int), ("lmax", C.c_int), ("eps", C.c_double), ("eps_inner", C.c_double),
-                ("max_outer", C.c_int), ("secant", C.c_int), ("timing", C.c_int)]
+                ("max_outer", C.c_int), ("secant", C.c_int), ("timing", C.c_int), ("precision", C.c_int)]
 
 
 class TrLoCoeffs(C.Structure):
@@ -169,8 +169,10 @@ class Solver:
             p.level_ng = lvl.ctypes.data_as(_ip)
         self.levels = [list(lv) for lv in levels]
         self.nlev = len(self.levels[0])
+        self.precision = int(getattr(cfg, "precision", 0))
         c = TrSolverCfg(cycle=cfg.cycle, lmax=cfg.lmax, eps=cfg.eps, eps_inner=cfg.eps_inner,
-                        max_outer=cfg.max_outer, secant=1 if cfg.secant else 0, timing=1 if timing else 0)
+                        max_outer=cfg.max_outer, secant=1 if cfg.secant else 0, timing=1 if timing else 0,
+                        precision=self.precision)
         self._ctx = C.c_void_p()
         _check(self.lib.tr_create(C.byref(self._ctx), probs, len(self.slabs), C.byref(c)), "tr_create")
         self.n = len(self.slabs)
@@ -251,8 +253,13 @@ class Solver:
 
     # -- state and steps ----------------------------------------------------
     def new_state(self) -> Dict:
+        """Device state; the corner intensities are float32 when the context
+        stores them in binary32."""
         e = self.empty
-        return dict(T=e(TR_K_CELL), I_prev=e(TR_K_I), I_out=e(TR_K_I), E=e(TR_K_GI), F=e(TR_K_GE),
+        tI = self.torch.float32 if self.precision == 1 else self.torch.float64
+        nI = self.total(TR_K_I)
+        return dict(T=e(TR_K_CELL), I_prev=self.torch.zeros(nI, dtype=tI, device="cuda"),
+                    I_out=self.torch.zeros(nI, dtype=tI, device="cuda"), E=e(TR_K_GI), F=e(TR_K_GE),
                     Ebnd=e(TR_K_G2), f=e(TR_K_GI), fbnd=e(TR_K_G2), C=e(TR_K_G2), Egrey=e(TR_K_CELL))
 
     @staticmethod

@@ -191,9 +191,10 @@ int sweep_bucket(int nx) {
 }
 
 void launch_sweeps(const tr_ctx *c, const LaunchEnv &env, const Ctl *ctl, int pmode, const double *kappa,
-                   const double *B, const double *Ip, double *Io, double *mom, double *bnd) {
+                   const double *B, const void *Ip, void *Io, double *mom, double *bnd) {
   for (int b = 0; b < TR_NBUCKET; ++b)
-    launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], ctl, pmode, 0, kappa, B, Ip, Io, mom, bnd);
+    launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], c->cfg.precision == TR_PREC_F32_STORAGE, ctl, pmode, 0, kappa,
+                 B, Ip, Io, mom, bnd);
 }
 
 // Event marks around kernel groups (cfg.timing).  A group records its cycle
@@ -332,7 +333,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   if (!out || !probs || n_slab <= 0 || !cfg) return TR_EINVAL;
   *out = nullptr;
   if (cfg->lmax < 1 || cfg->lmax > TR_MAXOUT || cfg->max_outer < 1 || cfg->max_outer >= TR_MAXOUT ||
-      cfg->cycle < 0 || cfg->cycle > 2)
+      cfg->cycle < 0 || cfg->cycle > 2 || cfg->precision < 0 || cfg->precision > 1)
     return TR_EINVAL;
   const int nlev = probs[0].n_levels;
   if (nlev < 2 || nlev > TR_MAXLEV) return TR_EINVAL;
@@ -742,10 +743,12 @@ int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K
     }
     double best = 1e300;
     for (int q = 0; q < 4 && !rc; ++q) {
-      launch_sweep(env, c->t_sweep_b[b], cand[q], nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom, c->bnd);
+      const bool f32 = c->cfg.precision == TR_PREC_F32_STORAGE;
+      launch_sweep(env, c->t_sweep_b[b], cand[q], f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
+                   c->bnd);
       if (hipEventRecord(e0, st) != hipSuccess) rc = TR_EHIP;
       for (int r = 0; r < reps; ++r)
-        launch_sweep(env, c->t_sweep_b[b], cand[q], nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
+        launch_sweep(env, c->t_sweep_b[b], cand[q], f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
                      c->bnd);
       float ms = 0.f;
       if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -820,7 +823,8 @@ int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
   LaunchEnv env = env_of(c, st);
   launch_fill(env, s->T, T0, c->n_cell);
   launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, s->T, c->kappa, c->B, c->dSpart);
-  launch_init_state(env, c->t_gi, c->B, s->I_out, s->E, s->F, s->Ebnd, c->mom, c->bnd);
+  launch_init_state(env, c->t_gi, c->cfg.precision == TR_PREC_F32_STORAGE, c->B, s->I_out, s->E, s->F, s->Ebnd,
+                    c->mom, c->bnd);
   launch_moments(env, c->t_gi, nullptr, PRED_ALL, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
   launch_group_sum(env, c->t_cell, s->E, s->Egrey);
   return hip_err(hipGetLastError());

@@ -55,8 +55,9 @@ void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int 
                     double *kappa, double *B, double *dSpart);
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart, double *dS);
 // Sweep tiles: K consecutive cells per lane (K in {1, 2, 4, 8}).
-void launch_sweep(const LaunchEnv &env, const Table &tab, int K, const Ctl *ctl, int pmode, int lcyc,
-                  const double *kappa, const double *B, const double *Ip, double *Io, double *mom, double *bnd);
+// f32: corner intensities stored as float (binary64 arithmetic inside).
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
+                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd);
 void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
                     const double *bnd, double *f, double *fbnd, double *C, double *Phi);
 void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi);
@@ -79,8 +80,8 @@ void launch_outer_begin(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer
 void launch_count_active(const LaunchEnv &env, const Ctl *ctl, int nslab, int *out);
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n);
 void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
-void launch_init_state(const LaunchEnv &env, const Table &tab, const double *Bt, double *I, double *E, double *F,
-                       double *Ebnd, double *mom, double *bnd);
+void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,
+                       double *F, double *Ebnd, double *mom, double *bnd);
 void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, double *out);
 struct MlpStats {
   double mean[5], std[5];

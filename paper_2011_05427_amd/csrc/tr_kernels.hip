@@ -110,13 +110,27 @@ __global__ __launch_bounds__(256) void k_dS_sum(const SlabDev *__restrict__ sd, 
 // of the half range are processed in turn; the cell-average moments
 // sum w Ibar and sum w mu^2 Ibar accumulate in registers.
 // ---------------------------------------------------------------------------
-template <int K>
+// Corner-pair storage of the intensities: binary64 or binary32 (the sweep
+// computes in binary64 either way).
+template <typename TI>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double2 V;
+};
+template <>
+struct Pair<float> {
+  typedef float2 V;
+};
+
+template <int K, typename TI>
 __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, ProbDev pd,
                                                const Item *__restrict__ tab, int nitems, const Ctl *ctl, int pmode,
                                                int lcyc, const double *__restrict__ kappa,
-                                               const double *__restrict__ Bt, const double *__restrict__ Ip,
-                                               double *__restrict__ Io, double *__restrict__ mom,
+                                               const double *__restrict__ Bt, const TI *__restrict__ Ip,
+                                               TI *__restrict__ Io, double *__restrict__ mom,
                                                double *__restrict__ bnd) {
+  typedef typename Pair<TI>::V PV;
   const int lane = threadIdx.x & 63;
   const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int item = wv >> 1, half = wv & 1;
@@ -130,8 +144,8 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
   const double *dx = pd.dx + S.o_cell;
   const double *kp = kappa + S.o_gi + (long long)g * nx;
   const double *bp = Bt + S.o_gi + (long long)g * nx;
-  const double *ip = Ip + S.o_I + (long long)g * M * nx * 2;
-  double *io = Io + S.o_I + (long long)g * M * nx * 2;
+  const TI *ip = Ip + S.o_I + (long long)g * M * nx * 2;
+  TI *io = Io + S.o_I + (long long)g * M * nx * 2;
   const double *mu = pd.mu + S.o_mu;
   const double *w = pd.w + S.o_mu;
   double carry = pd.inc[2 * S.o_g + (half ? ng : 0) + g];  // lane j: inflow of direction m0 + j
@@ -165,14 +179,14 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
       const double mum = mu[m], wm = w[m];
       const double amu = fabs(mum), a = 0.5 * amu, a2 = a * a, aamu = a * amu;
       const double wmu2 = wm * mum * mum;
-      const double *row = ip + (long long)m * nx * 2;
+      const TI *row = ip + (long long)m * nx * 2;
       double al[K], be[K], ga[K], de[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (ok[k]) {
-          const double2 v = *reinterpret_cast<const double2 *>(row + 2 * cell[k]);
-          const double up = half ? v.y : v.x;
-          const double dn = half ? v.x : v.y;
+          const PV v = *reinterpret_cast<const PV *>(row + 2 * cell[k]);
+          const double up = half ? (double)v.y : (double)v.x;
+          const double dn = half ? (double)v.x : (double)v.y;
           const double s_up = fma(hh[k], up, ee[k]);
           const double s_dn = fma(hh[k], dn, ee[k]);
           const double apb = a + bb[k];
@@ -207,16 +221,16 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
       const double Be = __shfl_up(Bc, 1);
       const double cin = __shfl(carry, j);
       double Iin = (lane == 0) ? cin : fma(Ae, cin, Be);
-      double *orow = io + (long long)m * nx * 2;
+      TI *orow = io + (long long)m * nx * 2;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const double Iup = fma(ga[k], Iin, de[k]);
         const double Idn = fma(al[k], Iin, be[k]);
         if (ok[k]) {
-          double2 o;
-          o.x = half ? Idn : Iup;
-          o.y = half ? Iup : Idn;
-          *reinterpret_cast<double2 *>(orow + 2 * cell[k]) = o;
+          PV o;
+          o.x = (TI)(half ? Idn : Iup);
+          o.y = (TI)(half ? Iup : Idn);
+          *reinterpret_cast<PV *>(orow + 2 * cell[k]) = o;
           const double Ibar = 0.5 * (Iup + Idn);
           phi[k] = fma(wm, Ibar, phi[k]);
           chi[k] = fma(wmu2, Ibar, chi[k]);
@@ -927,9 +941,10 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ dst, double v
 // Initial state from the B table at T0: I^0 = B in every corner/direction,
 // E = sum w B / c, F = 0 (edges), synthetic sweep partials of I^0 for the
 // moments kernel.  Thread = (slab, g, i).
+template <typename TI>
 __global__ __launch_bounds__(256) void k_init_state(const SlabDev *__restrict__ sd, ProbDev pd,
                                                     const Item *__restrict__ tab, const double *__restrict__ Bt,
-                                                    double *__restrict__ I, double *__restrict__ E,
+                                                    TI *__restrict__ I, double *__restrict__ E,
                                                     double *__restrict__ F, double *__restrict__ Ebnd,
                                                     double *__restrict__ mom, double *__restrict__ bnd) {
   const Item it = tab[blockIdx.x];
@@ -939,10 +954,10 @@ __global__ __launch_bounds__(256) void k_init_state(const SlabDev *__restrict__ 
   if (idx >= ng * nx) return;
   const int g = idx / nx, i = idx - g * nx;
   const double b = Bt[S.o_gi + idx];
-  double *ip = I + S.o_I + ((long long)g * M * nx + i) * 2;
+  TI *ip = I + S.o_I + ((long long)g * M * nx + i) * 2;
   for (int m = 0; m < M; ++m) {
-    ip[(long long)m * nx * 2] = b;
-    ip[(long long)m * nx * 2 + 1] = b;
+    ip[(long long)m * nx * 2] = (TI)b;
+    ip[(long long)m * nx * 2 + 1] = (TI)b;
   }
   const double Ec = b * (S.wpos + S.wneg) / S.c;
   E[S.o_gi + idx] = Ec;
@@ -1075,19 +1090,28 @@ void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart,
   hipLaunchKernelGGL(k_dS_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, dSpart, dS);
 }
 
-void launch_sweep(const LaunchEnv &env, const Table &tab, int K, const Ctl *ctl, int pmode, int lcyc,
-                  const double *kappa, const double *B, const double *Ip, double *Io, double *mom, double *bnd) {
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
+                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd) {
   if (tab.n == 0) return;
   const int waves = 2 * tab.n;
   const int nb = (waves + 3) / 4;
-#define TR_SWEEP_K(KK)                                                                                              \
-  hipLaunchKernelGGL(k_sweep<KK>, blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n, ctl, pmode, \
-                     lcyc, kappa, B, Ip, Io, mom, bnd)
-  switch (K) {
-    case 1: TR_SWEEP_K(1); break;
-    case 2: TR_SWEEP_K(2); break;
-    case 8: TR_SWEEP_K(8); break;
-    default: TR_SWEEP_K(4); break;
+#define TR_SWEEP_K(KK, TT)                                                                                         \
+  hipLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n, ctl, \
+                     pmode, lcyc, kappa, B, static_cast<const TT *>(Ip), static_cast<TT *>(Io), mom, bnd)
+  if (f32) {
+    switch (K) {
+      case 1: TR_SWEEP_K(1, float); break;
+      case 2: TR_SWEEP_K(2, float); break;
+      case 8: TR_SWEEP_K(8, float); break;
+      default: TR_SWEEP_K(4, float); break;
+    }
+  } else {
+    switch (K) {
+      case 1: TR_SWEEP_K(1, double); break;
+      case 2: TR_SWEEP_K(2, double); break;
+      case 8: TR_SWEEP_K(8, double); break;
+      default: TR_SWEEP_K(4, double); break;
+    }
   }
 #undef TR_SWEEP_K
 }
@@ -1164,11 +1188,15 @@ void launch_fill(const LaunchEnv &env, double *dst, double v, long long n) {
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, dst, v, n);
 }
 
-void launch_init_state(const LaunchEnv &env, const Table &tab, const double *Bt, double *I, double *E, double *F,
-                       double *Ebnd, double *mom, double *bnd) {
+void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,
+                       double *F, double *Ebnd, double *mom, double *bnd) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_init_state, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, Bt, I, E, F, Ebnd,
-                     mom, bnd);
+  if (f32)
+    hipLaunchKernelGGL(k_init_state<float>, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, Bt,
+                       static_cast<float *>(I), E, F, Ebnd, mom, bnd);
+  else
+    hipLaunchKernelGGL(k_init_state<double>, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, Bt,
+                       static_cast<double *>(I), E, F, Ebnd, mom, bnd);
 }
 
 void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, double *out) {

@@ -84,6 +84,7 @@ class SolverCfg:
     eps_inner: float = 1e-11  # inner (low-order) tolerance
     max_outer: int = 50
     secant: bool = True  # diagonal secant Frechet derivative of grey sigma_E
+    precision: int = 0  # 0: binary64 intensities; 1: binary32 storage of the corner intensities
 
     def schedule(self) -> List[int]:
         """Grid indices (0-based into ``levels``) visited after each grey solve.
