@@ -30,7 +30,8 @@ struct tr_ctx {
   tr_solver_cfg cfg{};
   int nlev = 0;
   std::vector<int> sched;
-  int lo_threads = 64;
+  int lo_threads = 64;    // block size of the group LO solves
+  int grey_threads = 64;  // block size of the grey solve
   std::vector<SlabDev> hs;  // host copies of the slab descriptors
   std::vector<double> h_inc;
   // totals per kind
@@ -41,7 +42,7 @@ struct tr_ctx {
   ProbDev pd{};
   double *d_inc = nullptr;
   // workspace
-  double *kappa = nullptr, *B = nullptr, *dSpart = nullptr, *mom = nullptr, *bnd = nullptr, *Phi = nullptr;
+  double *kappa = nullptr, *B = nullptr, *dSpart = nullptr, *dS = nullptr, *mom = nullptr, *bnd = nullptr, *Phi = nullptr;
   double *Eold = nullptr, *Fold = nullptr, *red = nullptr;
   double *Told = nullptr, *Ts = nullptr, *Tcyc = nullptr, *Tstar = nullptr, *Tprev = nullptr, *sigprev = nullptr;
   double *Ecyc = nullptr, *Es = nullptr;
@@ -53,7 +54,7 @@ struct tr_ctx {
   int *d_count = nullptr;
   int *h_count = nullptr;  // pinned
   // work tables
-  Table t_opac{}, t_cell{}, t_gi{}, t_g{}, t_grey{};
+  Table t_opac{}, t_dS{}, t_cell{}, t_gi{}, t_g{}, t_grey{};
   // sweep work per slab-size bucket (nx <= 64, 128, 256, 512, 1024, more),
   // longest slabs first; K = cells per lane of each bucket's launch
   Table t_sweep_b[TR_NBUCKET]{};
@@ -161,11 +162,12 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
     const int ne = S.nx + 1;
     const int nf = S.lev_ng[from], nt = S.lev_ng[to];
     const int r = nf / nt;
-    const int cpb = restrict_cpb(r);
+    const int cpb = restrict_cpb(r, nt, ne);
     if (cpb == 1) {
       for (int st = 0; st < nt * ne; st += 256) single.push_back({s, st});
     } else {
-      for (long long st = 0; st < (long long)nt * cpb * ne; st += 256) part.push_back({s, (int)st});
+      const int ntile = (ne + 63) / 64;
+      for (long long q = 0; q < (long long)nt * cpb * ntile; ++q) part.push_back({s, (int)q});
       const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
       for (int q = 0; q < nt * nb; ++q) fin.push_back({s, q});
     }
@@ -359,7 +361,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   }
   const int rows = nx_max + 2;
   int T = ((rows + TR_LO_K - 1) / TR_LO_K + 63) / 64 * 64;
-  if (T > 256) return TR_EINVAL;  // nx <= 2046
+  if (T > 512) return TR_EINVAL;  // nx <= 2046
 
   tr_ctx *c = new (std::nothrow) tr_ctx();
   if (!c) return TR_ENOMEM;
@@ -368,6 +370,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   c->nlev = nlev;
   c->sched = schedule_for(cfg->cycle, nlev);
   c->lo_threads = T;
+  c->grey_threads = ((rows + TR_GREY_K - 1) / TR_GREY_K + 63) / 64 * 64;
   c->hs.resize(n_slab);
 
   std::vector<double> h_dx, h_C, h_mu, h_w, h_nue, h_nuc;
@@ -432,7 +435,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       for (int a = 0; a < nlev; ++a)
         for (int b = a + 1; b < nlev; ++b) {
           const int r = P.level_ng[a] / P.level_ng[b];
-          const int cpb = restrict_cpb(r);
+          const int cpb = restrict_cpb(r, P.level_ng[b], P.nx + 1);
           if (cpb > 1) worst = std::max(worst, (long long)P.level_ng[b] * cpb);
         }
       c->n_red += worst * (P.nx + 1) * 21;
@@ -494,7 +497,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       (rc = dalloc(c, &c->bnd, 6 * c->n_g)) || (rc = dalloc(c, &c->Phi, 2 * c->n_g)) ||
       (rc = dalloc(c, &c->Eold, c->n_gi)) || (rc = dalloc(c, &c->Fold, c->n_ge)) || (rc = dalloc(c, &c->red, c->n_red)))
     return fail(rc);
-  double **cells[] = {&c->Told, &c->Ts, &c->Tcyc, &c->Tstar, &c->Tprev, &c->sigprev, &c->Ecyc, &c->Es};
+  double **cells[] = {&c->dS, &c->Told, &c->Ts, &c->Tcyc, &c->Tstar, &c->Tprev, &c->sigprev, &c->Ecyc, &c->Es};
   for (double **p : cells)
     if ((rc = dalloc(c, p, c->n_cell))) return fail(rc);
   for (int l = 1; l < nlev; ++l) {
@@ -527,13 +530,14 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
 
   // work tables
   {
-    std::vector<Item> opac, cell, gi, g, grey;
+    std::vector<Item> opac, dsum, cell, gi, g, grey;
     std::vector<std::vector<std::pair<long long, Item>>> sweepb(TR_NBUCKET);
     std::vector<std::vector<Item>> lo(nlev);
     for (int s = 0; s < n_slab; ++s) {
       const SlabDev &S = c->hs[s];
       const int ncb = (S.nx + 15) / 16;
       for (int q = 0; q < S.nchunk * ncb; ++q) opac.push_back({s, q});
+      for (int st = 0; st < S.nx; st += 64) dsum.push_back({s, st});
       for (int st = 0; st < S.nx; st += 256) cell.push_back({s, st});
       const long long cost = (long long)S.nx * S.nmu;
       for (int gg = 0; gg < S.ng; ++gg) sweepb[sweep_bucket(S.nx)].push_back({cost, Item{s, gg}});
@@ -543,7 +547,8 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       for (int l = 0; l < nlev; ++l)
         for (int p = 0; p < S.lev_ng[l]; ++p) lo[l].push_back({s, p});
     }
-    if ((rc = upload_table(c, opac, c->t_opac)) || (rc = upload_table(c, cell, c->t_cell)) ||
+    if ((rc = upload_table(c, opac, c->t_opac)) || (rc = upload_table(c, dsum, c->t_dS)) ||
+        (rc = upload_table(c, cell, c->t_cell)) ||
         (rc = upload_table(c, gi, c->t_gi)) ||
         (rc = upload_table(c, g, c->t_g)) || (rc = upload_table(c, grey, c->t_grey)))
       return fail(rc);
@@ -642,7 +647,7 @@ int tr_opacity(tr_ctx *c, const double *T, double *kappa, double *B, double *dS,
   if (!c || !T || !kappa || !B) return TR_EINVAL;
   LaunchEnv env = env_of(c, st);
   launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, T, kappa, B, c->dSpart);
-  if (dS) launch_dS_sum(env, c->t_cell, c->dSpart, dS);
+  if (dS) launch_dS_sum(env, c->t_dS, nullptr, PRED_ALL, 0, c->dSpart, dS);
   return hip_err(hipGetLastError());
 }
 
@@ -698,7 +703,7 @@ int tr_grey_solve(tr_ctx *c, const tr_lo_coeffs *grey, const double *Tstar, cons
   ga.Told = Told;
   ga.dS = dS;
   ga.D = D;
-  launch_grey(env_of(c, st), c->t_grey, c->lo_threads, nullptr, PRED_ALL, 0, ga);
+  launch_grey(env_of(c, st), c->t_grey, c->grey_threads, nullptr, PRED_ALL, 0, ga);
   return hip_err(hipGetLastError());
 }
 
@@ -848,7 +853,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
   ga.Tstar = c->Tstar;
   ga.Tout = c->Tstar;
   ga.Told = c->Told;
-  ga.dSpart = c->dSpart;
+  ga.dS = c->dS;
   ga.Tprev = c->Tprev;
   ga.sigprev = c->sigprev;
   ga.Egrey = s->Egrey;
@@ -886,13 +891,14 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     ga.end_cycle = nsch == 0;
     {
       TimedScope ts(c, st, TR_T_GREY, l);
-      launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
+      launch_grey(env, c->t_grey, c->grey_threads, c->d_ctl, PRED_CYCLE, l, ga);
     }
     for (int q = 0; q < nsch; ++q) {
       const int gm = c->sched[q];
       {
         TimedScope ts(c, st, TR_T_OPACITY, l);
         launch_opacity(env, c->t_opac, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
+        launch_dS_sum(env, c->t_dS, c->d_ctl, PRED_CYCLE, l, c->dSpart, c->dS);
       }
       {
         TimedScope ts(c, st, TR_T_RESTRICT, l);
@@ -911,12 +917,13 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       ga.end_cycle = q == nsch - 1;
       {
         TimedScope ts(c, st, TR_T_GREY, l);
-        launch_grey(env, c->t_grey, c->lo_threads, c->d_ctl, PRED_CYCLE, l, ga);
+        launch_grey(env, c->t_grey, c->grey_threads, c->d_ctl, PRED_CYCLE, l, ga);
       }
     }
     {
       TimedScope ts(c, st, TR_T_OPACITY, l);
       launch_opacity(env, c->t_opac, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
+      launch_dS_sum(env, c->t_dS, c->d_ctl, PRED_DONECYC, l + 1, c->dSpart, c->dS);
     }
   }
   launch_count_active(env, c->d_ctl, ns, c->d_count);
@@ -976,6 +983,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   launch_copy(env, s->F, c->Fold, c->n_ge);
   launch_phi(env, c->t_g, s->C, c->Phi);
   launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
+  launch_dS_sum(env, c->t_dS, nullptr, PRED_ALL, 0, c->dSpart, c->dS);
   unsigned long long seed_counts[2] = {0, 0};
   if (c->mlp_params) {
     // learned closure: predicted cell factors replace the previous step's

@@ -85,6 +85,20 @@ __device__ inline double q_interval(const EdgeQ &lo, const EdgeQ &hi) {
 }
 
 // ---------------------------------------------------------------------------
+// 1/x from the hardware reciprocal estimate refined by two Newton steps,
+// which take the estimate's error to the binary64 rounding level.  For
+// normal, finite x of moderate exponent (what the low-order systems hold);
+// a * rcp_nr(b) then differs from a / b by a couple of ulps at most.
+// ---------------------------------------------------------------------------
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// ---------------------------------------------------------------------------
 // Partitioned tridiagonal solver for one system per thread block.
 //
 // Rows j = 0..N-1:  a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j  (a_0 = c_{N-1} = 0).
@@ -102,22 +116,24 @@ __device__ inline void tri_solve_block(const double (&a)[K], const double (&b)[K
                                        const double (&d)[K], double (&x)[K], double *lds, int T) {
   const int t = threadIdx.x;
   // downward: rows s+1..e in terms of x_s:  ah_i x_s + bh_i x_i + c_i x_{i+1} = dh_i
-  double ah[K], bh[K], dh[K];
+  double ah[K], bh[K], dh[K], ib[K];
   ah[1] = a[1];
   bh[1] = b[1];
   dh[1] = d[1];
+  ib[1] = rcp_nr(b[1]);
 #pragma unroll
   for (int i = 2; i < K; ++i) {
-    double r = a[i] / bh[i - 1];
+    const double r = a[i] * ib[i - 1];
     ah[i] = -r * ah[i - 1];
     bh[i] = b[i] - r * c[i - 1];
     dh[i] = d[i] - r * dh[i - 1];
+    ib[i] = rcp_nr(bh[i]);
   }
   // upward: rows e-1..s in terms of x_e:  a_i x_{i-1} + bv_i x_i + cv_i x_e = dv_i
   double bv = b[K - 2], cv = c[K - 2], dv = d[K - 2];
 #pragma unroll
   for (int i = K - 3; i >= 0; --i) {
-    double r = c[i] / bv;
+    const double r = c[i] * rcp_nr(bv);
     bv = b[i] - r * a[i + 1];
     cv = -r * cv;
     dv = d[i] - r * dv;
@@ -143,13 +159,13 @@ __device__ inline void tri_solve_block(const double (&a)[K], const double (&b)[K
       double al = 0.0, ga = 0.0;
       double am = 0.0, cm = 0.0, dm = 0.0, ap = 0.0, cp = 0.0, dp = 0.0;
       if (i - st >= 0) {
-        al = ai / rb[i - st];
+        al = ai * rcp_nr(rb[i - st]);
         am = ra[i - st];
         cm = rc[i - st];
         dm = rd[i - st];
       }
       if (i + st < R) {
-        ga = ci / rb[i + st];
+        ga = ci * rcp_nr(rb[i + st]);
         ap = ra[i + st];
         cp = rc[i + st];
         dp = rd[i + st];
@@ -170,12 +186,12 @@ __device__ inline void tri_solve_block(const double (&a)[K], const double (&b)[K
     }
     __syncthreads();
   }
-  const double xs = rd[2 * t] / rb[2 * t];
-  const double xe = rd[2 * t + 1] / rb[2 * t + 1];
+  const double xs = rd[2 * t] * rcp_nr(rb[2 * t]);
+  const double xe = rd[2 * t + 1] * rcp_nr(rb[2 * t + 1]);
   x[0] = xs;
   x[K - 1] = xe;
 #pragma unroll
-  for (int i = K - 2; i >= 1; --i) x[i] = (dh[i] - ah[i] * xs - c[i] * x[i + 1]) / bh[i];
+  for (int i = K - 2; i >= 1; --i) x[i] = (dh[i] - ah[i] * xs - c[i] * x[i + 1]) * ib[i];
   __syncthreads();
   // publish the first unknown of every partition for neighbours (reuse ra)
   ra[t] = xs;

@@ -3,7 +3,8 @@
 
 #include "tr_common.h"
 
-#define TR_LO_K 8  // rows per thread of the partitioned tridiagonal solver
+#define TR_LO_K 4    // rows per thread of the group LO solves (one block of up to 512 threads per system)
+#define TR_GREY_K 4  // rows per thread of the grey solve (one block of up to 512 threads per slab)
 
 enum { PRED_ALL = 0, PRED_CYCLE = 1, PRED_DONECYC = 2, PRED_SWEEP = 3, PRED_ACTIVE = 4 };
 
@@ -29,8 +30,7 @@ struct GreyArgs {
   const double *Tstar;   // cell: stage temperature
   double *Tout;          // cell: new temperature (may equal Tstar)
   const double *Told;    // cell: previous time level
-  const double *dS;      // cell: explicit dS (nullable)
-  const double *dSpart;  // chunk partials of dS (used when dS is null)
+  const double *dS;      // cell: d/dT of the emission sum_g 2 kappa_g B_g at Tstar
   const double *D;       // cell: explicit Frechet derivative (nullable)
   double *Tprev, *sigprev;         // secant memory (step mode)
   double *Egrey;                   // cell: grey E output (nullable)
@@ -53,7 +53,9 @@ struct Table {
 
 void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *T,
                     double *kappa, double *B, double *dSpart);
-void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart, double *dS);
+// dS per cell from the chunk partials; tab items = (slab, first of 64 cells).
+void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
+                   double *dS);
 // Sweep tiles: K consecutive cells per lane (K in {1, 2, 4, 8}).
 // f32: corner intensities stored as float (binary64 arithmetic inside).
 void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
@@ -64,10 +66,24 @@ void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double 
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
                const LoIn &in, const LoSol &sol);
 // Restriction work: coarse groups of r <= 16 finer groups are done in one pass;
-// larger r in a chunk pass (cpb chunks per coarse group) plus a final pass over
-// blocks of TR_RFIN_E edges.
+// larger r in a chunk pass plus a final pass over blocks of TR_RFIN_E edges.
+// In the chunk pass a block of 4 wavefronts covers 64 edges and 4 rcw finer
+// groups (rcw per wavefront), giving cpb chunk records per coarse group.  rcw
+// grows (fewer records to write and re-read) while the pass keeps at least
+// 4096 blocks, and so that cpb <= 64.
 #define TR_RFIN_E 12
-__host__ __device__ inline int restrict_cpb(int r) { return r <= 16 ? 1 : (r + 7) / 8 < 64 ? (r + 7) / 8 : 64; }
+__host__ __device__ inline int restrict_rcw(int r, int nto, int ne) {
+  const int ntile = (ne + 63) / 64;
+  int rcw = 1;
+  while (rcw < 32 && 4 * rcw < r && (long long)nto * ((r + 8 * rcw - 1) / (8 * rcw)) * ntile >= 4096) rcw *= 2;
+  while ((r + 4 * rcw - 1) / (4 * rcw) > 64) rcw *= 2;
+  return rcw;
+}
+__host__ __device__ inline int restrict_cpb(int r, int nto, int ne) {
+  if (r <= 16) return 1;
+  const int rcw = restrict_rcw(r, nto, ne);
+  return (r + 4 * rcw - 1) / (4 * rcw);
+}
 
 struct RestrictTables {
   Table single, part, fin;

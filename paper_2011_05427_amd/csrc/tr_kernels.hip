@@ -88,16 +88,38 @@ __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd,
   }
 }
 
-// Sums the chunk partials of dS (standalone tr_opacity).  Thread = cell.
+// Sums the 64-group chunk partials of dS for every cell.  Block = 64 cells
+// (lanes) x 4 wavefronts; wavefront w adds the chunks q = w, w + 4, ... and
+// the four partial sums are combined in a fixed order, so the result does not
+// depend on scheduling.
 __global__ __launch_bounds__(256) void k_dS_sum(const SlabDev *__restrict__ sd, const Item *__restrict__ tab,
-                                                const double *__restrict__ dSpart, double *__restrict__ dS) {
+                                                const Ctl *ctl, int pmode, int lcyc, const double *__restrict__ dSpart,
+                                                double *__restrict__ dS) {
+  __shared__ double part[4][64];
   const Item it = tab[blockIdx.x];
   const SlabDev &S = sd[it.slab];
-  const int i = it.idx + threadIdx.x;
-  if (i >= S.nx) return;
+  const int nx = S.nx, nchunk = S.nchunk;
+  const long long o_chunk = S.o_chunk, o_cell = S.o_cell;
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = it.idx + lane;
   double acc = 0.0;
-  for (int q = 0; q < S.nchunk; ++q) acc += dSpart[S.o_chunk + (long long)q * S.nx + i];
-  dS[S.o_cell + i] = acc;
+  if (i < nx) {
+    const double *row = dSpart + o_chunk + i;
+    int q = w;
+    for (; q + 12 < nchunk; q += 16) {
+      const double v0 = row[(long long)q * nx], v1 = row[(long long)(q + 4) * nx];
+      const double v2 = row[(long long)(q + 8) * nx], v3 = row[(long long)(q + 12) * nx];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+    }
+    for (; q < nchunk; q += 4) acc += row[(long long)q * nx];
+  }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < nx) dS[o_cell + i] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // ---------------------------------------------------------------------------
@@ -109,7 +131,24 @@ __global__ __launch_bounds__(256) void k_dS_sum(const SlabDev *__restrict__ sd, 
 // a row of nx cells advances 64 K cells per step instead of one.  Directions
 // of the half range are processed in turn; the cell-average moments
 // sum w Ibar and sum w mu^2 Ibar accumulate in registers.
+//
+// Memory: every intensity row is accessed through a raw buffer resource whose
+// range is the row, so lanes past the end of the slab load zeros and their
+// stores are dropped by the hardware; the loop body has no branches around
+// memory operations, and the corner pairs of the next direction are loaded
+// while the current one is scanned.  The scan uses DPP lane moves (row shifts
+// and row broadcasts), the carries between directions are lane reads.
 // ---------------------------------------------------------------------------
+typedef unsigned int tr_u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int tr_u32x2 __attribute__((ext_vector_type(2)));
+// Word 3 of a raw (unswizzled, range-checked) buffer resource on gfx9-family
+// targets: 32-bit data format.
+#define TR_BUF_WORD3 0x00020000
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, TR_BUF_WORD3);
+}
+
 // Corner-pair storage of the intensities: binary64 or binary32 (the sweep
 // computes in binary64 either way).
 template <typename TI>
@@ -117,10 +156,59 @@ struct Pair;
 template <>
 struct Pair<double> {
   typedef double2 V;
+  static __device__ inline V load(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  }
+  static __device__ inline void store(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, v), r, off, 0, 0);
+  }
 };
 template <>
 struct Pair<float> {
   typedef float2 V;
+  static __device__ inline V load(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  static __device__ inline void store(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tr_u32x2, v), r, off, 0, 0);
+  }
+};
+
+__device__ inline double buf_load_f64(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// DPP lane move of a binary64 value; lanes without a source (or in rows not
+// enabled by ROWM) keep `old`.
+template <int CTRL, int ROWM>
+__device__ inline double dpp_f64(double v, double old) {
+  const long long vi = __double_as_longlong(v), oi = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)vi, CTRL, ROWM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(vi >> 32), CTRL, ROWM, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long vi = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)vi, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(vi >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One step of the inclusive scan of affine maps x -> A x + B (composition
+// with the map of the source lane, applied first); the identity map is the
+// value for lanes without a source.
+template <int CTRL, int ROWM>
+__device__ inline void scan_step(double &A, double &B) {
+  const double Ap = dpp_f64<CTRL, ROWM>(A, 1.0);
+  const double Bp = dpp_f64<CTRL, ROWM>(B, 0.0);
+  B = fma(A, Bp, B);
+  A = A * Ap;
+}
+
+enum {
+  DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118,
+  DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143
 };
 
 template <int K, typename TI>
@@ -130,9 +218,12 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
                                                const double *__restrict__ Bt, const TI *__restrict__ Ip,
                                                TI *__restrict__ Io, double *__restrict__ mom,
                                                double *__restrict__ bnd) {
-  typedef typename Pair<TI>::V PV;
+  typedef Pair<TI> P;
+  typedef typename P::V PV;
   const int lane = threadIdx.x & 63;
-  const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // wavefront index, made visibly uniform so that the descriptors and the
+  // per-direction quantities live in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int item = wv >> 1, half = wv & 1;
   if (item >= nitems) return;
   const Item it = tab[item];
@@ -141,33 +232,42 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
   const int g = it.idx, nx = S.nx, ng = S.ng, M = S.nmu, Mh = M >> 1;
   const int m0 = half ? 0 : Mh;  // mu ascending: mu < 0 first
   const double inv_cdt = S.inv_cdt;
-  const double *dx = pd.dx + S.o_cell;
-  const double *kp = kappa + S.o_gi + (long long)g * nx;
-  const double *bp = Bt + S.o_gi + (long long)g * nx;
+  const __amdgpu_buffer_rsrc_t r_dx = buf_rsrc(pd.dx + S.o_cell, nx * 8);
+  const __amdgpu_buffer_rsrc_t r_kp = buf_rsrc(kappa + S.o_gi + (long long)g * nx, nx * 8);
+  const __amdgpu_buffer_rsrc_t r_bp = buf_rsrc(Bt + S.o_gi + (long long)g * nx, nx * 8);
   const TI *ip = Ip + S.o_I + (long long)g * M * nx * 2;
   TI *io = Io + S.o_I + (long long)g * M * nx * 2;
+  const int rowb = nx * 2 * (int)sizeof(TI);
   const double *mu = pd.mu + S.o_mu;
   const double *w = pd.w + S.o_mu;
   double carry = pd.inc[2 * S.o_g + (half ? ng : 0) + g];  // lane j: inflow of direction m0 + j
-  double *mp = mom + 4 * S.o_gi + (long long)half * 2 * ng * nx + (long long)g * nx * 2;
+  const __amdgpu_buffer_rsrc_t r_mp =
+      buf_rsrc(mom + 4 * S.o_gi + (long long)half * 2 * ng * nx + (long long)g * nx * 2, nx * 16);
   const int npass = (nx + 64 * K - 1) / (64 * K);
+  // byte offset of the corner pair of cell k of this lane in a pass; cells
+  // outside [0, nx) map to offsets outside the row's range
+  auto cell_of = [&](int pass, int k) {
+    const int q = pass * 64 * K + lane * K + k;
+    return half ? nx - 1 - q : q;
+  };
+  PV nxt[K];
+  {
+    const __amdgpu_buffer_rsrc_t r = buf_rsrc(ip + (long long)m0 * nx * 2, rowb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_of(0, k) * 2 * (int)sizeof(TI));
+  }
   for (int pass = 0; pass < npass; ++pass) {
-    double bb[K], ee[K], phi[K], chi[K];
-    int cell[K];
+    double bb[K], ee[K], phi[K], chi[K], hh[K];
+    int off[K];
     bool ok[K];
-    double hh[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int q = pass * 64 * K + lane * K + k;
-      ok[k] = q < nx;
-      const int i = half ? nx - 1 - q : q;
-      cell[k] = ok[k] ? i : 0;
-      double dxi = 0.0, kap = 0.0, bpl = 0.0;
-      if (ok[k]) {
-        dxi = dx[i];
-        kap = kp[i];
-        bpl = bp[i];
-      }
+      const int i = cell_of(pass, k);
+      ok[k] = i >= 0 && i < nx;
+      off[k] = i * 2 * (int)sizeof(TI);
+      const double dxi = buf_load_f64(r_dx, i * 8);
+      const double kap = buf_load_f64(r_kp, i * 8);
+      const double bpl = buf_load_f64(r_bp, i * 8);
       bb[k] = 0.5 * (kap + inv_cdt) * dxi;
       ee[k] = 0.5 * dxi * kap * bpl;
       hh[k] = 0.5 * dxi * inv_cdt;
@@ -176,31 +276,33 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
     }
     for (int j = 0; j < Mh; ++j) {
       const int m = m0 + j;
+      PV cur[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) cur[k] = nxt[k];
+      {
+        // next direction of this pass, else the first direction of the next
+        // pass (past the last pass every offset is out of range)
+        const bool same = j + 1 < Mh;
+        const __amdgpu_buffer_rsrc_t r = buf_rsrc(ip + (long long)(same ? m + 1 : m0) * nx * 2, rowb);
+#pragma unroll
+        for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_of(same ? pass : pass + 1, k) * 2 * (int)sizeof(TI));
+      }
       const double mum = mu[m], wm = w[m];
       const double amu = fabs(mum), a = 0.5 * amu, a2 = a * a, aamu = a * amu;
       const double wmu2 = wm * mum * mum;
-      const TI *row = ip + (long long)m * nx * 2;
       double al[K], be[K], ga[K], de[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (ok[k]) {
-          const PV v = *reinterpret_cast<const PV *>(row + 2 * cell[k]);
-          const double up = half ? (double)v.y : (double)v.x;
-          const double dn = half ? (double)v.x : (double)v.y;
-          const double s_up = fma(hh[k], up, ee[k]);
-          const double s_dn = fma(hh[k], dn, ee[k]);
-          const double apb = a + bb[k];
-          const double r = 1.0 / fma(apb, apb, a2);
-          al[k] = aamu * r;
-          ga[k] = apb * amu * r;
-          be[k] = fma(apb, s_dn, a * s_up) * r;
-          de[k] = fma(apb, s_up, -a * s_dn) * r;
-        } else {
-          al[k] = 1.0;
-          be[k] = 0.0;
-          ga[k] = 0.0;
-          de[k] = 0.0;
-        }
+        const double up = half ? (double)cur[k].y : (double)cur[k].x;
+        const double dn = half ? (double)cur[k].x : (double)cur[k].y;
+        const double s_up = fma(hh[k], up, ee[k]);
+        const double s_dn = fma(hh[k], dn, ee[k]);
+        const double apb = a + bb[k];
+        const double r = rcp_nr(fma(apb, apb, a2));
+        al[k] = ok[k] ? aamu * r : 1.0;
+        ga[k] = ok[k] ? apb * amu * r : 0.0;
+        be[k] = ok[k] ? fma(apb, s_dn, a * s_up) * r : 0.0;
+        de[k] = ok[k] ? fma(apb, s_up, -a * s_dn) * r : 0.0;
       }
       double A = al[0], Bc = be[0];
 #pragma unroll
@@ -208,46 +310,39 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
         Bc = fma(al[k], Bc, be[k]);
         A = al[k] * A;
       }
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const double Ap = __shfl_up(A, d);
-        const double Bp = __shfl_up(Bc, d);
-        if (lane >= d) {
-          Bc = fma(A, Bp, Bc);
-          A = A * Ap;
-        }
-      }
-      const double Ae = __shfl_up(A, 1);
-      const double Be = __shfl_up(Bc, 1);
-      const double cin = __shfl(carry, j);
-      double Iin = (lane == 0) ? cin : fma(Ae, cin, Be);
-      TI *orow = io + (long long)m * nx * 2;
+      scan_step<DPP_ROW_SHR1, 0xf>(A, Bc);
+      scan_step<DPP_ROW_SHR2, 0xf>(A, Bc);
+      scan_step<DPP_ROW_SHR4, 0xf>(A, Bc);
+      scan_step<DPP_ROW_SHR8, 0xf>(A, Bc);
+      scan_step<DPP_ROW_BCAST15, 0xa>(A, Bc);
+      scan_step<DPP_ROW_BCAST31, 0xc>(A, Bc);
+      const double Ae = dpp_f64<DPP_WAVE_SHR1, 0xf>(A, 1.0);
+      const double Be = dpp_f64<DPP_WAVE_SHR1, 0xf>(Bc, 0.0);
+      const double cin = readlane_f64(carry, j);
+      double Iin = fma(Ae, cin, Be);
+      const __amdgpu_buffer_rsrc_t ro = buf_rsrc(io + (long long)m * nx * 2, rowb);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const double Iup = fma(ga[k], Iin, de[k]);
         const double Idn = fma(al[k], Iin, be[k]);
-        if (ok[k]) {
-          PV o;
-          o.x = (TI)(half ? Idn : Iup);
-          o.y = (TI)(half ? Iup : Idn);
-          *reinterpret_cast<PV *>(orow + 2 * cell[k]) = o;
-          const double Ibar = 0.5 * (Iup + Idn);
-          phi[k] = fma(wm, Ibar, phi[k]);
-          chi[k] = fma(wmu2, Ibar, chi[k]);
-        }
+        PV o;
+        o.x = (TI)(half ? Idn : Iup);
+        o.y = (TI)(half ? Iup : Idn);
+        P::store(o, ro, off[k]);
+        const double Ibar = 0.5 * (Iup + Idn);
+        phi[k] = fma(wm, Ibar, phi[k]);
+        chi[k] = fma(wmu2, Ibar, chi[k]);
         Iin = Idn;
       }
-      const double cout = __shfl(Iin, 63);
+      const double cout = readlane_f64(Iin, 63);
       if (lane == j) carry = cout;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (ok[k]) {
-        double2 o;
-        o.x = phi[k];
-        o.y = chi[k];
-        *reinterpret_cast<double2 *>(mp + 2 * cell[k]) = o;
-      }
+      double2 o;
+      o.x = phi[k];
+      o.y = chi[k];
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, o), r_mp, cell_of(pass, k) * 16, 0, 0);
     }
   }
   // outflow-edge sums of this half range: carry = intensity leaving the slab
@@ -383,60 +478,84 @@ __device__ inline void lv_cell(const LevelView &v, int i, double &se, double &em
   }
 }
 
-// Builds the K rows of this thread; optional per-cell overrides (grey Newton).
-// With eff = true the absorption / emission of the cell of row k come from
-// se_eff[k] / em_eff[k] (the grey level coupled to the MEB).
+// Level data of the K rows of this thread (row k = unknown j = t K + k;
+// j = 0 and j = nx + 1 are the boundary unknowns, cell i = j - 1 otherwise):
+// edges e = t K - 1 .. t K + K - 1.  Loaded in one batch so that the loads
+// are in flight together.
+template <int K>
+struct RowData {
+  double ae[K + 1], be[K + 1], sr[K + 1], h[K + 1], Fo[K + 1];
+  double dx[K], Eo[K], se[K], em[K];
+  double C0, C1, P0, P1;
+};
+
 template <int K, bool FINE>
-__device__ inline void lo_rows(const LevelView &v, double c, double dt, double inv_cdt, bool eff,
-                               const double (&se_eff)[K], const double (&em_eff)[K], double (&ra)[K],
-                               double (&rb)[K], double (&rc)[K], double (&rd)[K], double (&Ak)[K + 1],
-                               double (&ca)[K + 1], double (&cb)[K + 1]) {
+__device__ inline void lo_load(const LevelView &v, RowData<K> &R) {
   const int t = threadIdx.x, nx = v.nx;
 #pragma unroll
   for (int q = 0; q <= K; ++q) {
     const int e = t * K - 1 + q;
-    if (e < 0 || e > nx) {
-      Ak[q] = 0.0;
-      ca[q] = 0.0;
-      cb[q] = 0.0;
-      continue;
-    }
-    double ae, be, sr;
-    lv_edge<FINE>(v, e, ae, be, sr);
-    const double h = lv_h(v, e);
-    const double A = h * inv_cdt;
-    const double ke = 1.0 / (A + sr * h);
-    Ak[q] = ke * A * v.Fold[e];
-    ca[q] = c * ke * ae;
-    cb[q] = c * ke * be;
+    R.ae[q] = R.be[q] = R.sr[q] = R.Fo[q] = 0.0;
+    R.h[q] = 1.0;
+    if (e < 0 || e > nx) continue;
+    lv_edge<FINE>(v, e, R.ae[q], R.be[q], R.sr[q]);
+    R.h[q] = lv_h(v, e);
+    R.Fo[q] = v.Fold[e];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t * K + k - 1;
+    R.dx[k] = R.Eo[k] = R.se[k] = R.em[k] = 0.0;
+    if (i < 0 || i >= nx) continue;
+    R.dx[k] = v.dx[i];
+    R.Eo[k] = v.Eold[i];
+    lv_cell<FINE>(v, i, R.se[k], R.em[k]);
+  }
+  R.C0 = v.C[0];
+  R.C1 = v.C[1];
+  R.P0 = v.Phi[0];
+  R.P1 = v.Phi[1];
+}
+
+// Builds the K rows of this thread from its level data; with eff = true the
+// absorption / emission of the cell of row k come from se_eff[k] / em_eff[k]
+// (the grey level coupled to the MEB).
+template <int K>
+__device__ inline void lo_build(const RowData<K> &R, int nx, double c, double dt, double inv_cdt, bool eff,
+                                const double (&se_eff)[K], const double (&em_eff)[K], double (&ra)[K],
+                                double (&rb)[K], double (&rc)[K], double (&rd)[K], double (&Ak)[K + 1],
+                                double (&ca)[K + 1], double (&cb)[K + 1]) {
+  const int t = threadIdx.x;
+  const double inv_dt = 1.0 / dt;
+#pragma unroll
+  for (int q = 0; q <= K; ++q) {
+    const double A = R.h[q] * inv_cdt;
+    const double ke = rcp_nr(A + R.sr[q] * R.h[q]);
+    Ak[q] = ke * A * R.Fo[q];
+    ca[q] = c * ke * R.ae[q];
+    cb[q] = c * ke * R.be[q];
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int j = t * K + k;
     if (j == 0) {
       ra[k] = 0.0;
-      rb[k] = cb[k + 1] - c * v.C[0];
+      rb[k] = cb[k + 1] - c * R.C0;
       rc[k] = -ca[k + 1];
-      rd[k] = v.Phi[0] - Ak[k + 1];
+      rd[k] = R.P0 - Ak[k + 1];
     } else if (j <= nx) {
-      const int i = j - 1;
-      double se, em;
-      if (eff) {
-        se = se_eff[k];
-        em = em_eff[k];
-      } else {
-        lv_cell<FINE>(v, i, se, em);
-      }
-      const double dxi = v.dx[i];
+      const double se = eff ? se_eff[k] : R.se[k];
+      const double em = eff ? em_eff[k] : R.em[k];
+      const double dxi = R.dx[k];
       ra[k] = -cb[k];
-      rb[k] = dxi / dt + c * se * dxi + cb[k + 1] + ca[k];
+      rb[k] = dxi * inv_dt + c * se * dxi + cb[k + 1] + ca[k];
       rc[k] = -ca[k + 1];
-      rd[k] = dxi * em + dxi / dt * v.Eold[i] - Ak[k + 1] + Ak[k];
+      rd[k] = dxi * em + dxi * inv_dt * R.Eo[k] - Ak[k + 1] + Ak[k];
     } else if (j == nx + 1) {
       ra[k] = -cb[k];
-      rb[k] = ca[k] + c * v.C[1];
+      rb[k] = ca[k] + c * R.C1;
       rc[k] = 0.0;
-      rd[k] = Ak[k] - v.Phi[1];
+      rd[k] = Ak[k] - R.P1;
     } else {
       ra[k] = 0.0;
       rb[k] = 1.0;
@@ -444,6 +563,17 @@ __device__ inline void lo_rows(const LevelView &v, double c, double dt, double i
       rd[k] = 0.0;
     }
   }
+}
+
+// Builds the K rows of this thread (load + build).
+template <int K, bool FINE>
+__device__ inline void lo_rows(const LevelView &v, double c, double dt, double inv_cdt, bool eff,
+                               const double (&se_eff)[K], const double (&em_eff)[K], double (&ra)[K],
+                               double (&rb)[K], double (&rc)[K], double (&rd)[K], double (&Ak)[K + 1],
+                               double (&ca)[K + 1], double (&cb)[K + 1]) {
+  RowData<K> R;
+  lo_load<K, FINE>(v, R);
+  lo_build<K>(R, v.nx, c, dt, inv_cdt, eff, se_eff, em_eff, ra, rb, rc, rd, Ak, ca, cb);
 }
 
 // Writes E, boundary E and F of one system after tri_solve_block.
@@ -523,9 +653,9 @@ __device__ inline void level_out(const SlabDev &S, int level, int p, const LoSol
 // A4 / A6: LO solve, one thread block per (slab, group of the level).
 // ---------------------------------------------------------------------------
 template <int K, bool FINE>
-__global__ __launch_bounds__(256) void k_lo(const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab,
+__global__ __launch_bounds__(512) void k_lo(const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab,
                                             const Ctl *ctl, int pmode, int lcyc, int level, LoIn in, LoSol sol) {
-  __shared__ double lds[8 * 256];
+  __shared__ double lds[8 * 512];
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
@@ -643,44 +773,90 @@ __device__ inline SrcView make_src(const SlabDev &S, ProbDev pd, int from, const
   return s;
 }
 
-// Restriction work split.  r finer groups per coarse group: r <= 16 is done in
-// one pass (thread = (slab, p, e) looping over the r groups); larger r in two:
-// cpb = min(64, ceil(r/8)) chunks of rc = ceil(r/cpb) groups write raw sums
-// (thread = (chunk, e)), then a final pass adds the chunks of each coarse group
-// (block = 12 edges x R_N sums) and finalises.
-template <bool FINAL, bool FINE>
+// One-pass restriction (r <= 16 finer groups per coarse group): thread =
+// (slab, p, e) looping over the r groups, writing the final coefficients.
+template <bool FINE>
 __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd, ProbDev pd,
                                                   const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
-                                                  int from, int to, LoIn in, LoSol sol, LoOut out,
-                                                  double *__restrict__ red) {
+                                                  int from, int to, LoIn in, LoSol sol, LoOut out) {
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   const int nx = S.nx, ne = nx + 1;
-  const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
-  const int r = nfrom / nto;
-  const int cpb = FINAL ? 1 : restrict_cpb(r);
-  const int rc = (r + cpb - 1) / cpb;
+  const int nto = S.lev_ng[to];
+  const int r = S.lev_ng[from] / nto;
   const int idx = it.idx + threadIdx.x;
-  if (idx >= nto * cpb * ne) return;
-  const int qq = idx / ne, e = idx - qq * ne;
-  const int p = qq / cpb, qc = qq - p * cpb;
-  const int g0 = p * r + qc * rc;
-  const int g1 = min(g0 + rc, (p + 1) * r);
+  if (idx >= nto * ne) return;
+  const int p = idx / ne, e = idx - p * ne;
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  for (int g = g0; g < g1; ++g) {
+  for (int g = p * r; g < (p + 1) * r; ++g) {
     const SrcView s = make_src<FINE>(S, pd, from, in, sol, g);
     accumulate<FINE>(s, e, acc);
   }
-  if (FINAL) {
-    finalize(S, pd, to, p, e, r, acc, out);
-  } else {
-    double *rec = red + S.o_red + ((long long)qq * ne + e) * R_N;
+  finalize(S, pd, to, p, e, r, acc, out);
+}
+
+// Chunk pass (r > 16): block = (slab, chunk record qq = p cpb + bc, tile of 64
+// edges); wavefront w adds groups p r + (4 bc + w) rcw + [0, rcw), lane =
+// edge.  The four wavefront sums are combined through LDS in a fixed order,
+// ((w0 + w2) + (w1 + w3)), and the record [64 edges][R_N] is written
+// contiguously.
+template <bool FINE>
+__global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                       const Item *__restrict__ tab, const Ctl *ctl, int pmode,
+                                                       int lcyc, int from, int to, LoIn in, LoSol sol,
+                                                       double *__restrict__ red) {
+  __shared__ double sh[2][64 * R_N];
+  const Item it = tab[blockIdx.x];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ne = nx + 1;
+  const int r = S.lev_ng[from] / S.lev_ng[to];
+  const int nto = S.lev_ng[to];
+  const int rcw = restrict_rcw(r, nto, ne), cpb = restrict_cpb(r, nto, ne);
+  const int ntile = (ne + 63) >> 6;
+  const int qq = it.idx / ntile, et = it.idx - qq * ntile;
+  const int p = qq / cpb, bc = qq - p * cpb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = et * 64 + lane;
+  const int g0 = p * r + (bc * 4 + w) * rcw;
+  const int g1 = min(g0 + rcw, (p + 1) * r);
+  double acc[R_N];
 #pragma unroll
-    for (int k = 0; k < R_N; ++k) rec[k] = acc[k];
+  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
+  if (e < ne) {
+    for (int g = g0; g < g1; ++g) {
+      const SrcView s = make_src<FINE>(S, pd, from, in, sol, g);
+      accumulate<FINE>(s, e, acc);
+    }
   }
+  double *slot = sh[w & 1] + lane * R_N;
+  if (w >= 2) {
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) slot[k] = acc[k];
+  }
+  __syncthreads();
+  if (w < 2) {
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) acc[k] += slot[k];
+  }
+  __syncthreads();
+  if (w == 1) {
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) slot[k] = acc[k];
+  }
+  __syncthreads();
+  if (w == 0) {
+    double *s1 = sh[1] + lane * R_N, *s0 = sh[0] + lane * R_N;
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) s0[k] = acc[k] + s1[k];
+  }
+  __syncthreads();
+  const int nval = min(64, ne - et * 64) * R_N;
+  double *rec = red + S.o_red + ((long long)qq * ne + et * 64) * R_N;
+  for (int j = threadIdx.x; j < nval; j += 256) rec[j] = sh[0][j];
 }
 
 __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restrict__ sd, ProbDev pd,
@@ -694,7 +870,7 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   const int nx = S.nx, ne = nx + 1;
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
-  const int cpb = restrict_cpb(r);
+  const int cpb = restrict_cpb(r, nto, ne);
   const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
   const int p = it.idx / nb, b = it.idx - p * nb;
   const int t = threadIdx.x;
@@ -722,142 +898,172 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
 // ---------------------------------------------------------------------------
 // A7 + A8: grey LOQD + MEB (one Newton iteration) per slab, one thread block;
 // at the end of a cycle it also applies the inner / outer convergence tests.
+// The kernel is a single block on the critical path of every cycle, so all of
+// its global loads (slab descriptor, control record, cell data, convergence
+// references) are issued before the first dependent computation, and the
+// block reductions use wavefront shuffles with one LDS exchange.
 // ---------------------------------------------------------------------------
+// Sums nfl and takes the maxima of v over the block (exact, order independent
+// for the maxima; the integer sum is exact).  Up to 16 wavefronts; lds: 7 * 16
+// doubles, which may still be read by other wavefronts on entry.
+__device__ inline void block_reduce_grey(double (&v)[6], int &nfl, double *lds) {
+  __syncthreads();
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = fmax(v[q], __shfl_xor(v[q], d));
+    nfl += __shfl_xor(nfl, d);
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) lds[q * 16 + w] = v[q];
+    lds[96 + w] = (double)nfl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double m = lds[q * 16];
+    for (int k = 1; k < nw; ++k) m = fmax(m, lds[q * 16 + k]);
+    v[q] = m;
+  }
+  double ns = lds[96];
+  for (int k = 1; k < nw; ++k) ns += lds[96 + k];
+  nfl = (int)ns;
+  __syncthreads();
+}
+
 template <int K>
-__global__ __launch_bounds__(256) void k_grey(const SlabDev *__restrict__ sd, ProbDev pd,
+__global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, ProbDev pd,
                                               const Item *__restrict__ tab, Ctl *ctl, int pmode, int lcyc,
                                               GreyArgs ga) {
-  __shared__ double lds[8 * 256];
+  __shared__ double lds[8 * 512];
   __shared__ int s_flag[2];
   const Item it = tab[blockIdx.x];
-  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const int slab = it.slab;
   const SlabDev &S = sd[slab];
-  const int nx = S.nx, t = threadIdx.x;
-  const int gl = S.nlev - 1;
+  // descriptor fields and control record are loaded together
+  const int nx = S.nx, gl = S.nlev - 1;
+  const long long o_cell = S.o_cell, pi = S.o_lpi[gl];
   const double c = S.c, dt = S.dt, cv = S.cv;
-  const double *Tst = ga.Tstar + S.o_cell;
-  const bool use_prev = ctl ? (ctl[slab].has_prev && ga.secant) : false;
-  // per-cell Newton coefficients for the cells of this thread's rows
-  double alpha[K], beta[K], se_eff[K], em_eff[K], dSrow[K];
-  const long long pi = S.o_lpi[gl];
-  // dS at the stage temperature: explicit, or the sum of the chunk partials
-  // (loop over chunks outside, rows inside, so the loads of a chunk overlap)
-#pragma unroll
-  for (int k = 0; k < K; ++k) dSrow[k] = 0.0;
-  if (ga.dS) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = t * K + k - 1;
-      if (i >= 0 && i < nx) dSrow[k] = ga.dS[S.o_cell + i];
-    }
-  } else {
-    for (int q = 0; q < S.nchunk; ++q) {
-      const double *row = ga.dSpart + S.o_chunk + (long long)q * nx;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int i = t * K + k - 1;
-        if (i >= 0 && i < nx) dSrow[k] += row[i];
-      }
-    }
+  int c_ncyc = 0, c_nrep = 0, c_s = 0, c_hasprev = 0, c_cost = 0;
+  if (ctl) {
+    c_ncyc = ctl[slab].ncyc;
+    c_nrep = ctl[slab].n_replay;
+    c_s = ctl[slab].s;
+    c_hasprev = ctl[slab].has_prev;
+    c_cost = ga.cyc_cost[slab];
   }
+  if (!pred_ok(ctl, slab, pmode, lcyc)) return;
+  const int c_rep = (ctl && c_nrep > 0) ? ctl[slab].replay[c_s] : 0;
+  const int t = threadIdx.x;
+  const bool use_prev = ctl ? (c_hasprev && ga.secant) : false;
+  // per-cell inputs of this thread's rows (row k is cell t K + k - 1)
+  double Ts[K], sig[K], Sst[K], Es[K], dS[K], Tol[K], Tpv[K], spv[K], Dx[K], rT[K], rE[K], sT[K], sE[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t * K + k - 1;
+    const bool ok = i >= 0 && i < nx;
+    const long long oc = o_cell + (ok ? i : 0), op = pi + (ok ? i : 0);
+    Ts[k] = ok ? ga.Tstar[oc] : 1.0;
+    sig[k] = ok ? ga.grey.sigE[op] : 0.0;
+    Sst[k] = ok ? ga.grey.emis[op] : 0.0;
+    Es[k] = ok ? ga.Estar[op] : 0.0;
+    dS[k] = ok ? ga.dS[oc] : 0.0;
+    Tol[k] = ok ? ga.Told[oc] : 0.0;
+    Dx[k] = (ok && ga.D) ? ga.D[oc] : 0.0;
+    Tpv[k] = (ok && use_prev) ? ga.Tprev[oc] : 0.0;
+    spv[k] = (ok && use_prev) ? ga.sigprev[oc] : 0.0;
+    const bool ref = ok && ga.end_cycle;
+    rT[k] = ref ? ga.Tcyc[oc] : 0.0;
+    rE[k] = ref ? ga.Ecyc[oc] : 0.0;
+    sT[k] = ref ? ga.Ts[oc] : 0.0;
+    sE[k] = ref ? ga.Es[oc] : 0.0;
+  }
+  // grey level coefficients of the rows (same batch of loads)
+  const LevelView v = make_view<false>(S, pd, gl, ga.grey, 0);
+  RowData<K> R;
+  lo_load<K, false>(v, R);
+  // Newton coefficients: T - T* = alpha + beta E per cell
+  double alpha[K], beta[K], se_eff[K], em_eff[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int i = t * K + k - 1;
     alpha[k] = beta[k] = se_eff[k] = em_eff[k] = 0.0;
     if (i < 0 || i >= nx) continue;
-    const double dS = dSrow[k];
-    const double Ts = Tst[i];
-    const double sig = ga.grey.sigE[pi + i];
-    const double Sst = ga.grey.emis[pi + i];
-    const double Es = ga.Estar[pi + i];
     double D = 0.0;
     if (ga.D) {
-      D = ga.D[S.o_cell + i];
+      D = Dx[k];
     } else if (use_prev) {
-      const double dT = Ts - ga.Tprev[S.o_cell + i];
-      if (fabs(dT) > 1e-8 * fabs(Ts)) D = (sig - ga.sigprev[S.o_cell + i]) / dT;
-      if (c * D * Es > 0.5 * (cv / dt + dS)) D = 0.0;
+      const double dT = Ts[k] - Tpv[k];
+      if (fabs(dT) > 1e-8 * fabs(Ts[k])) D = (sig[k] - spv[k]) / dT;
+      if (c * D * Es[k] > 0.5 * (cv / dt + dS[k])) D = 0.0;
     }
-    const double den = cv / dt + dS - c * D * Es;
-    const double al = (cv * (ga.Told[S.o_cell + i] - Ts) / dt - Sst) / den;
-    const double be = c * sig / den;
-    const double gg = c * D * Es - dS;
+    const double iden = rcp_nr(cv / dt + dS[k] - c * D * Es[k]);
+    const double al = (cv * (Tol[k] - Ts[k]) / dt - Sst[k]) * iden;
+    const double gg = c * D * Es[k] - dS[k];
     alpha[k] = al;
-    beta[k] = be;
-    se_eff[k] = sig + gg * be / c;
-    em_eff[k] = Sst - gg * al;
+    beta[k] = c * sig[k] * iden;
+    se_eff[k] = sig[k] + gg * sig[k] * iden;
+    em_eff[k] = Sst[k] - gg * al;
   }
-  // rows: the grey level view with effective absorption / emission
-  LevelView v = make_view<false>(S, pd, gl, ga.grey, 0);
+  // rows of the grey level with effective absorption / emission
   double ra[K], rb[K], rc[K], rd[K], x[K], Ak[K + 1], ca[K + 1], cb[K + 1];
-  // row k of this thread is cell t K + k - 1: the Newton coefficients above
-  lo_rows<K, false>(v, c, dt, S.inv_cdt, true, se_eff, em_eff, ra, rb, rc, rd, Ak, ca, cb);
+  lo_build<K>(R, nx, c, dt, S.inv_cdt, true, se_eff, em_eff, ra, rb, rc, rd, Ak, ca, cb);
   tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
   double *E = ga.sol.E + pi, *F = ga.sol.F + S.o_lpe[gl], *Eb = ga.sol.Ebnd + S.o_lp2[gl];
   lo_store<K>(nx, x, Ak, ca, cb, lds, E, F, Eb);
   // temperature update, secant memory, norms
-  double dTc = 0.0, dEc = 0.0, dTs = 0.0, dEs = 0.0, Tmax = 0.0, Emax = 0.0;
+  double red[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dTc, dEc, dTs, dEs, Tmax, Emax
+  double Tn[K];
   int nfl = 0;
-  double *Tout = ga.Tout + S.o_cell;
+  double *Tout = ga.Tout + o_cell;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int i = t * K + k - 1;
+    Tn[k] = 0.0;
     if (i < 0 || i >= nx) continue;
-    const double Ts = Tst[i];
-    double Tn = Ts + alpha[k] + beta[k] * x[k];
-    if (Tn < 0.5 * Ts) {
-      Tn = 0.5 * Ts;
+    double T1 = Ts[k] + alpha[k] + beta[k] * x[k];
+    if (T1 < 0.5 * Ts[k]) {
+      T1 = 0.5 * Ts[k];
       ++nfl;
     }
+    Tn[k] = T1;
     if (ctl) {
-      ga.Tprev[S.o_cell + i] = Ts;
-      ga.sigprev[S.o_cell + i] = ga.grey.sigE[pi + i];
+      ga.Tprev[o_cell + i] = Ts[k];
+      ga.sigprev[o_cell + i] = sig[k];
     }
-    Tout[i] = Tn;
+    Tout[i] = T1;
     const double En = x[k];
-    if (ga.Egrey) ga.Egrey[S.o_cell + i] = En;
+    if (ga.Egrey) ga.Egrey[o_cell + i] = En;
     if (ga.end_cycle) {
-      dTc = fmax(dTc, fabs(Tn - ga.Tcyc[S.o_cell + i]));
-      dEc = fmax(dEc, fabs(En - ga.Ecyc[S.o_cell + i]));
-      dTs = fmax(dTs, fabs(Tn - ga.Ts[S.o_cell + i]));
-      dEs = fmax(dEs, fabs(En - ga.Es[S.o_cell + i]));
+      red[0] = fmax(red[0], fabs(T1 - rT[k]));
+      red[1] = fmax(red[1], fabs(En - rE[k]));
+      red[2] = fmax(red[2], fabs(T1 - sT[k]));
+      red[3] = fmax(red[3], fabs(En - sE[k]));
       // NaN propagates through fmax as the other argument; flag it explicitly
-      Tmax = (Tn == Tn) ? fmax(Tmax, fabs(Tn)) : INFINITY;
-      Emax = (En == En) ? fmax(Emax, fabs(En)) : INFINITY;
+      red[4] = (T1 == T1) ? fmax(red[4], fabs(T1)) : INFINITY;
+      red[5] = (En == En) ? fmax(red[5], fabs(En)) : INFINITY;
     }
   }
   if (!ctl) return;
-  // floor counter (exact integer sum through LDS)
-  {
-    int *il = reinterpret_cast<int *>(lds);
-    __syncthreads();
-    il[t] = nfl;
-    __syncthreads();
+  block_reduce_grey(red, nfl, lds);
+  if (!ga.end_cycle) {
     if (t == 0) {
-      long long sum = 0;
-      for (int q = 0; q < (int)blockDim.x; ++q) sum += il[q];
-      ctl[slab].n_floor += sum;
+      ctl[slab].n_floor += nfl;
       ctl[slab].has_prev = 1;
     }
-    __syncthreads();
-  }
-  if (!ga.end_cycle) return;
-  {
-    double v[6] = {dTc, dEc, dTs, dEs, Tmax, Emax};
-    block_max6(v, lds);
-    dTc = v[0];
-    dEc = v[1];
-    dTs = v[2];
-    dEs = v[3];
-    Tmax = v[4];
-    Emax = v[5];
+    return;
   }
   if (t == 0) {
     Ctl &cc = ctl[slab];
-    cc.ncyc += 1;
+    const double dTc = red[0], dEc = red[1], dTs = red[2], dEs = red[3], Tmax = red[4], Emax = red[5];
+    const int ncyc = c_ncyc + 1;
+    cc.n_floor += nfl;
+    cc.has_prev = 1;
+    cc.ncyc = ncyc;
     cc.n_c += 1;
-    cc.n_lo += ga.cyc_cost[slab];
+    cc.n_lo += c_cost;
     int inner_done, outer_done = 0;
     if (!isfinite(Tmax) || !isfinite(Emax)) {
       cc.err = -5;
@@ -865,14 +1071,14 @@ __global__ __launch_bounds__(256) void k_grey(const SlabDev *__restrict__ sd, Pr
       outer_done = 1;
     } else {
       const bool conv_in = dTc <= ga.eps_inner * Tmax && dEc <= ga.eps_inner * Emax;
-      if (cc.n_replay > 0)
-        inner_done = cc.ncyc >= cc.replay[cc.s];
+      if (c_nrep > 0)
+        inner_done = ncyc >= c_rep;
       else
-        inner_done = conv_in || cc.ncyc >= ga.lmax;
+        inner_done = conv_in || ncyc >= ga.lmax;
       if (inner_done) {
-        if (cc.s < TR_MAXOUT) cc.cycles[cc.s] = cc.ncyc;
-        const bool conv_out = cc.s >= 1 && dTs <= ga.eps * Tmax && dEs <= ga.eps * Emax;
-        outer_done = (cc.n_replay > 0) ? (cc.s + 1 >= cc.n_replay) : conv_out;
+        if (c_s < TR_MAXOUT) cc.cycles[c_s] = ncyc;
+        const bool conv_out = c_s >= 1 && dTs <= ga.eps * Tmax && dEs <= ga.eps * Emax;
+        outer_done = (c_nrep > 0) ? (c_s + 1 >= c_nrep) : conv_out;
       }
     }
     cc.inner_done = inner_done;
@@ -885,13 +1091,11 @@ __global__ __launch_bounds__(256) void k_grey(const SlabDev *__restrict__ sd, Pr
   for (int k = 0; k < K; ++k) {
     const int i = t * K + k - 1;
     if (i < 0 || i >= nx) continue;
-    const double Tn = Tout[i];
-    const double En = x[k];
-    ga.Tcyc[S.o_cell + i] = Tn;
-    ga.Ecyc[S.o_cell + i] = En;
+    ga.Tcyc[o_cell + i] = Tn[k];
+    ga.Ecyc[o_cell + i] = x[k];
     if (inner_done) {
-      ga.Ts[S.o_cell + i] = Tn;
-      ga.Es[S.o_cell + i] = En;
+      ga.Ts[o_cell + i] = Tn[k];
+      ga.Es[o_cell + i] = x[k];
     }
   }
   // deactivation is published last so that the cell arrays above are final
@@ -1085,9 +1289,10 @@ void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int 
                      kappa, B, dSpart);
 }
 
-void launch_dS_sum(const LaunchEnv &env, const Table &tab, const double *dSpart, double *dS) {
+void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
+                   double *dS) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_dS_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, dSpart, dS);
+  hipLaunchKernelGGL(k_dS_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, ctl, pmode, lcyc, dSpart, dS);
 }
 
 void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
@@ -1144,19 +1349,19 @@ void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *
   const bool fine = from == 0;
   if (rt.single.n) {
     if (fine)
-      hipLaunchKernelGGL((k_restrict<true, true>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+      hipLaunchKernelGGL(k_restrict<true>, blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out);
     else
-      hipLaunchKernelGGL((k_restrict<true, false>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+      hipLaunchKernelGGL(k_restrict<false>, blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out);
   }
   if (rt.part.n) {
     if (fine)
-      hipLaunchKernelGGL((k_restrict<false, true>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+      hipLaunchKernelGGL(k_restrict_part<true>, blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, red);
     else
-      hipLaunchKernelGGL((k_restrict<false, false>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, out, red);
+      hipLaunchKernelGGL(k_restrict_part<false>, blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, red);
   }
   if (rt.fin.n)
     hipLaunchKernelGGL(k_restrict_final, blocks(rt.fin.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.fin.d, ctl,
@@ -1166,7 +1371,7 @@ void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_grey<TR_LO_K>, blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
+  hipLaunchKernelGGL(k_grey<TR_GREY_K>, blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
                      lcyc, ga);
 }
 
