@@ -123,14 +123,15 @@ __global__ __launch_bounds__(256) void k_dS_sum(const SlabDev *__restrict__ sd, 
 }
 
 // ---------------------------------------------------------------------------
-// A2 (+ partial A3): SCB sweep.  One wavefront per (slab, group, half range);
-// lanes own K consecutive cells along the sweep direction.  Per cell the 2x2
-// corner system makes the outflow an affine function of the inflow,
-// I_dn = al I_in + be and I_up = ga I_in + de; a lane composes its K maps and
-// a wavefront prefix scan of the composed maps gives every lane its inflow, so
-// a row of nx cells advances 64 K cells per step instead of one.  Directions
-// of the half range are processed in turn; the cell-average moments
-// sum w Ibar and sum w mu^2 Ibar accumulate in registers.
+// A2 (+ partial A3): SCB sweep.  One wavefront per (slab, group, half range).
+// Per cell the 2x2 corner system makes the outflow an affine function of the
+// inflow, I_dn = al I_in + be and I_up = ga I_in + de.  A pass covers 64 K
+// cells in K segments of 64 (lane l holds the l-th cell of every segment);
+// a wavefront prefix scan of the maps of each segment, chained by the
+// segments' total maps, gives every cell its inflow, so a row of nx cells
+// advances 64 K cells per pass instead of one.  Directions of the half range
+// are processed in turn; the cell-average moments sum w Ibar and
+// sum w mu^2 Ibar accumulate in registers.
 //
 // Memory: every intensity row is accessed through a raw buffer resource whose
 // range is the row, so lanes past the end of the slab load zeros and their
@@ -244,10 +245,12 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
   const __amdgpu_buffer_rsrc_t r_mp =
       buf_rsrc(mom + 4 * S.o_gi + (long long)half * 2 * ng * nx + (long long)g * nx * 2, nx * 16);
   const int npass = (nx + 64 * K - 1) / (64 * K);
-  // byte offset of the corner pair of cell k of this lane in a pass; cells
-  // outside [0, nx) map to offsets outside the row's range
+  // cell of segment k of a pass for this lane: the pass covers 64 K cells in
+  // sweep order, segment k the 64 consecutive cells k 64 .. k 64 + 63, lane l
+  // the l-th of them (so every load and store of a segment is one contiguous
+  // block); cells outside [0, nx) map to offsets outside the row's range
   auto cell_of = [&](int pass, int k) {
-    const int q = pass * 64 * K + lane * K + k;
+    const int q = pass * 64 * K + k * 64 + lane;
     return half ? nx - 1 - q : q;
   };
   PV nxt[K];
@@ -290,7 +293,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
       const double mum = mu[m], wm = w[m];
       const double amu = fabs(mum), a = 0.5 * amu, a2 = a * a, aamu = a * amu;
       const double wmu2 = wm * mum * mum;
-      double al[K], be[K], ga[K], de[K];
+      double al[K], be[K], ga[K], de[K], A[K], Bc[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const double up = half ? (double)cur[k].y : (double)cur[k].x;
@@ -303,26 +306,30 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
         ga[k] = ok[k] ? apb * amu * r : 0.0;
         be[k] = ok[k] ? fma(apb, s_dn, a * s_up) * r : 0.0;
         de[k] = ok[k] ? fma(apb, s_up, -a * s_dn) * r : 0.0;
+        A[k] = al[k];
+        Bc[k] = be[k];
       }
-      double A = al[0], Bc = be[0];
+      // inclusive scans of the K segments (independent chains)
 #pragma unroll
-      for (int k = 1; k < K; ++k) {
-        Bc = fma(al[k], Bc, be[k]);
-        A = al[k] * A;
-      }
-      scan_step<DPP_ROW_SHR1, 0xf>(A, Bc);
-      scan_step<DPP_ROW_SHR2, 0xf>(A, Bc);
-      scan_step<DPP_ROW_SHR4, 0xf>(A, Bc);
-      scan_step<DPP_ROW_SHR8, 0xf>(A, Bc);
-      scan_step<DPP_ROW_BCAST15, 0xa>(A, Bc);
-      scan_step<DPP_ROW_BCAST31, 0xc>(A, Bc);
-      const double Ae = dpp_f64<DPP_WAVE_SHR1, 0xf>(A, 1.0);
-      const double Be = dpp_f64<DPP_WAVE_SHR1, 0xf>(Bc, 0.0);
-      const double cin = readlane_f64(carry, j);
-      double Iin = fma(Ae, cin, Be);
+      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR1, 0xf>(A[k], Bc[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR2, 0xf>(A[k], Bc[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR4, 0xf>(A[k], Bc[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR8, 0xf>(A[k], Bc[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_BCAST15, 0xa>(A[k], Bc[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_BCAST31, 0xc>(A[k], Bc[k]);
+      // inflow of each segment: the previous segment's outflow
+      double cin = readlane_f64(carry, j);
       const __amdgpu_buffer_rsrc_t ro = buf_rsrc(io + (long long)m * nx * 2, rowb);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
+        const double Ae = dpp_f64<DPP_WAVE_SHR1, 0xf>(A[k], 1.0);
+        const double Be = dpp_f64<DPP_WAVE_SHR1, 0xf>(Bc[k], 0.0);
+        const double Iin = fma(Ae, cin, Be);
         const double Iup = fma(ga[k], Iin, de[k]);
         const double Idn = fma(al[k], Iin, be[k]);
         PV o;
@@ -332,10 +339,9 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
         const double Ibar = 0.5 * (Iup + Idn);
         phi[k] = fma(wm, Ibar, phi[k]);
         chi[k] = fma(wmu2, Ibar, chi[k]);
-        Iin = Idn;
+        cin = fma(readlane_f64(A[k], 63), cin, readlane_f64(Bc[k], 63));
       }
-      const double cout = readlane_f64(Iin, 63);
-      if (lane == j) carry = cout;
+      if (lane == j) carry = cin;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
