@@ -50,6 +50,47 @@ def sweep_bytes(slab, ibytes=8):
     return 4.0 * ibytes * slab.cell_updates_per_sweep() + 32.0 * slab.ng * slab.nx
 
 
+SWEEP_SOURCES = ["paper_2011_05427_amd/csrc/tr_kernels.hip", "paper_2011_05427_amd/csrc/tr_device.h",
+                 "paper_2011_05427_amd/csrc/tr_common.h"]
+
+
+def sweep_source_hash():
+    """sha256 over the sweep kernel's source text (its section of the kernel
+    file plus the device headers it includes)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        text = open(os.path.join(ROOT, rel)).read()
+        if rel.endswith("tr_kernels.hip"):
+            a = text.index("// A2 (+ partial A3): SCB sweep")
+            b = text.index("// A3: QD factors")
+            text = text[a:b]
+        h.update(text.encode())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, bytes_per_launch):
+    """HBM traffic of one sweep launch from the committed counter summary of
+    this workload (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when there is none or the sweep source changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_traffic.md")
+    try:
+        for line in open(path):
+            if line.startswith("traffic-json: "):
+                d = json.loads(line[len("traffic-json: "):])
+                if d.get("sweep_source_sha256") != sweep_source_hash():
+                    return None
+                t = d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
+                return {"bytes_per_launch": t, "fetch_bytes_per_launch": d["fetch_bytes_per_launch"],
+                        "write_bytes_per_launch": d["write_bytes_per_launch"],
+                        "ratio_to_algorithmic": t / bytes_per_launch, "source": os.path.relpath(path, ROOT)}
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
 def cpu_baseline(workload, budget_s=20.0):
     """The CPU oracle (numpy, FP64, one thread) on the first time steps of the
     workload (bounded to about budget_s seconds); run in a child process whose
@@ -120,10 +161,11 @@ def _cpu_baseline_child(workload, budget_s):
                       f"{dt:.1f} s"}
 
 
-def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closure=None, final=None):
+def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closure=None, final=None, sweep_ev=0):
     """Runs warmup steps, then `steps` steps from the initial condition; returns
     (wall seconds, per-slab TrStats); with a dict `final`, the final T and E
-    are copied into it."""
+    are copied into it.  The first `sweep_ev` timed steps launch their sweeps
+    with start / end events (the sweep kernel's duration, in TrStats.t_ms)."""
     import torch
 
     from paper_2011_05427_amd import binding
@@ -135,20 +177,40 @@ def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closu
         sv.set_closure(*closure)
     st = sv.new_state()
     sv.state_init(st, slabs[0].T0)
+    if sweep_ev:
+        sv.set_sweep_timing(True)  # warmup also builds the graphs of timed steps
     for _ in range(warmup):
         sv.step(st)
+    if sweep_ev:
+        sv.set_sweep_timing(False)
     sv.state_init(st, slabs[0].T0)
     torch.cuda.synchronize()
     acc = (binding.TrStats * len(slabs))()
+    acc_ev = (binding.TrStats * len(slabs))()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        sv.step(st, stats=acc)
+    for k in range(steps):
+        if k < sweep_ev:
+            # this step's sweeps are timed: its counters also go to acc_ev
+            sv.set_sweep_timing(True)
+            one = sv.step(st)
+            for q in range(len(slabs)):
+                for dst in (acc[q], acc_ev[q]):
+                    for f in ("n_ti", "n_c", "n_lo", "n_floor", "n_seeded", "n_fallback"):
+                        setattr(dst, f, getattr(dst, f) + getattr(one[q], f))
+                    for i in range(len(dst.t_ms)):
+                        dst.t_ms[i] += one[q].t_ms[i]
+                        dst.n_launch[i] += one[q].n_launch[i]
+            sv.set_sweep_timing(False)
+        else:
+            sv.step(st, stats=acc)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if final is not None:
         final["T"] = st["T"].cpu().numpy()
         final["E"] = st["E"].cpu().numpy()
     sv.close()
+    if sweep_ev:
+        return wall, acc, acc_ev
     return wall, acc
 
 
@@ -183,6 +245,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
     ap.add_argument("--train-samples", type=int, default=1000000)
     ap.add_argument("--train-epochs", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 1 GiB device copy (reference kernel for the HBM byte counters)")
     ap.add_argument("--fp32", action="store_true",
                     help="also time the binary32-storage sweep variant and state its error vs binary64")
     args = ap.parse_args()
@@ -219,7 +283,10 @@ def main():
 
     # timed: graph replay, no events
     fin64 = {}
-    wall, acc = run_steps(slabs, levels, cfg, args.steps, args.warmup, tiles=tiles, final=fin64)
+    # the first steps of the timed run also time their sweep launches
+    n_ev = max(1, args.steps // 10)
+    wall, acc, acc_ev = run_steps(slabs, levels, cfg, args.steps, args.warmup, tiles=tiles, final=fin64,
+                                  sweep_ev=n_ev)
     # per-kernel durations: the same steps with HIP events around each kernel group
     # (eager launches, not part of the timed value)
     _, prof = run_steps(slabs, levels, cfg, args.steps, 0, timing=True, tiles=tiles)
@@ -228,9 +295,11 @@ def main():
     cu = sum(s.cell_updates_per_sweep() * n for s, n in zip(slabs, sweeps))
     value = cu / wall
     p = prof[0]  # kernel-group times cover the whole context
-    t_sweep_s = p.t_ms[binding.T_SWEEP] / 1e3
-    n_sweep = p.n_launch[binding.T_SWEEP]
-    bytes_total = sum(sweep_bytes(s) * int(prof[k].n_ti) for k, s in enumerate(slabs))
+    # sweep kernel time inside the timed run: the launches of its first n_ev
+    # steps record their own start and end on HIP events
+    t_sweep_s = acc_ev[0].t_ms[binding.T_SWEEP] / 1e3
+    n_sweep = acc_ev[0].n_launch[binding.T_SWEEP]
+    bytes_total = sum(sweep_bytes(s) * int(acc_ev[k].n_ti) for k, s in enumerate(slabs))
     achieved = bytes_total / t_sweep_s / 1e9 if t_sweep_s > 0 else 0.0
     kernel_ms = {name: p.t_ms[k] / max(args.steps, 1) for k, name in enumerate(KERNELS)}
     ms_step = 1e3 * wall / args.steps
@@ -257,7 +326,7 @@ def main():
             "lo_solves": int(sum(a.n_lo for a in acc)), "closure": "plain",
         },
         "kernel_ms_per_step": kernel_ms,
-        "sweep_kernel_cell_updates_per_s": (sum(s.cell_updates_per_sweep() * int(prof[k].n_ti)
+        "sweep_kernel_cell_updates_per_s": (sum(s.cell_updates_per_sweep() * int(acc_ev[k].n_ti)
                                                 for k, s in enumerate(slabs)) / t_sweep_s) if t_sweep_s else None,
         "roofline": {
             "bound": "hbm",
@@ -270,6 +339,10 @@ def main():
             "bytes_per_launch": bytes_total / max(n_sweep, 1),
             "avg_launch_us": 1e6 * t_sweep_s / max(n_sweep, 1),
             "launches": int(n_sweep),
+            "timed_steps": n_ev,
+            "note": "kernel start/end events of the sweep launches in the first timed steps; "
+                    "achieved = algorithmic bytes (32 B per cell-update + 32 B per group-cell of moment "
+                    "partials) / kernel time",
         },
     }
     if args.fp32:
@@ -279,10 +352,10 @@ def main():
 
         cfg32 = dataclasses.replace(cfg, precision=1)
         fin32 = {}
-        wall32, acc32 = run_steps(slabs, levels, cfg32, args.steps, args.warmup, tiles=tiles, final=fin32)
-        _, prof32 = run_steps(slabs, levels, cfg32, args.steps, 0, timing=True, tiles=tiles)
-        t32 = prof32[0].t_ms[binding.T_SWEEP] / 1e3
-        b32 = sum(sweep_bytes(s, 4) * int(prof32[k].n_ti) for k, s in enumerate(slabs))
+        wall32, acc32, ev32 = run_steps(slabs, levels, cfg32, args.steps, args.warmup, tiles=tiles, final=fin32,
+                                        sweep_ev=n_ev)
+        t32 = ev32[0].t_ms[binding.T_SWEEP] / 1e3
+        b32 = sum(sweep_bytes(s, 4) * int(ev32[k].n_ti) for k, s in enumerate(slabs))
         rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
         out["fp32_storage"] = {
             "ms_per_step": 1e3 * wall32 / args.steps,
@@ -299,6 +372,20 @@ def main():
                         "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}
     if not args.no_learned and len(slabs) == 1 and slabs[0].cell_updates_per_sweep() < 5e7:
         out["learned"] = learned_vs_plain(slabs[0], cfg, args, ms_step, sum(sweeps))
+    tr = measured_traffic(args.workload, out["roofline"]["bytes_per_launch"])
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes_per_launch"]
+        out["roofline"]["traffic_detail"] = tr
+    if args.copy_calibration:
+        # a plain device copy of known size for the byte-counter calibration
+        # (outside every timed region)
+        n = 1 << 27
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 3}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
     print(json.dumps(out), flush=True)

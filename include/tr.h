@@ -249,8 +249,11 @@ typedef struct tr_stats {
   int n_outer;     /* transport iterations of the last step incl. s = 0 */
   int cycles[64];  /* cycles per transport iteration of the last step */
   double t_ms[TR_T_N];     /* with cfg.timing: summed kernel time per group
-                              (TR_T_*), over launches that did work */
-  long long n_launch[TR_T_N]; /* timed launch groups per TR_T_* */
+                              (TR_T_*), over launches that did work; with
+                              tr_set_sweep_timing only t_ms[TR_T_SWEEP] */
+  long long n_launch[TR_T_N]; /* timed launch groups per TR_T_* (sweep: kernel
+                                 launches, one per non-empty slab-size bucket
+                                 and transport iteration) */
   long long n_seeded;   /* cell factors replaced by the closure */
   long long n_fallback; /* closure predictions rejected (outside (0, 1)) */
 } tr_stats;
@@ -265,6 +268,16 @@ typedef struct tr_stats {
  * Errors: TR_ENOCONV, TR_ENAN, TR_EHIP.
  */
 int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats, hipStream_t stream);
+
+/*
+ * Sweep kernel timing inside tr_step.  on = 1: the transport sweeps of
+ * iterations s >= 1 are launched outside the replayed graphs, each launch
+ * recording its own start and end on HIP events, and their kernel time is
+ * added to tr_stats.t_ms[TR_T_SWEEP] (launches in n_launch[TR_T_SWEEP]);
+ * this costs one extra launch per transport iteration.  on = 0 (default):
+ * sweeps stay inside the graphs, untimed.  Errors: TR_EINVAL (on not 0/1).
+ */
+int tr_set_sweep_timing(tr_ctx *ctx, int on);
 
 /*
  * Batched launch tiles.  Sweep work is grouped by slab size into 6 buckets

@@ -70,7 +70,7 @@ EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_in
            "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step",
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
            "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
-           "tr_autotune", "tr_set_tiles", "tr_get_tiles"]
+           "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing"]
 
 _lib = None
 
@@ -105,6 +105,7 @@ def load():
     lib.tr_grey_solve.argtypes = [vp, C.POINTER(TrLoCoeffs), vp, vp, vp, vp, vp, vp, C.POINTER(TrLoFields), vp]
     lib.tr_state_init.argtypes = [vp, C.POINTER(TrState), C.c_double, vp]
     lib.tr_step.argtypes = [vp, C.POINTER(TrState), _ip, C.POINTER(TrStats), vp]
+    lib.tr_set_sweep_timing.argtypes = [vp, C.c_int]
     lib.tr_mlp_nparam.argtypes = []
     lib.tr_mlp_work_bytes.argtypes = [C.c_longlong]
     lib.tr_mlp_work_bytes.restype = C.c_size_t
@@ -292,6 +293,11 @@ class Solver:
         if swap:
             st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
         return stats
+
+    def set_sweep_timing(self, on: bool):
+        """Sweeps of tr_step launched with start / end events (kernel time in
+        TrStats.t_ms[T_SWEEP]) instead of inside the replayed graphs."""
+        _check(self.lib.tr_set_sweep_timing(self._ctx, 1 if on else 0), "tr_set_sweep_timing")
 
 
 # ---------------------------------------------------------------------------

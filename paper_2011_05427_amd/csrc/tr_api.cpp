@@ -72,11 +72,17 @@ struct tr_ctx {
   // the state pointers and on the number of cycles launched)
   struct GraphEntry {
     std::vector<const void *> key;
-    hipGraphExec_t first = nullptr, next = nullptr;  // s = 0 (no sweep) / s >= 1
+    // s = 0 (no sweep); s >= 1 with the sweep; s >= 1 without it (the sweep
+    // launched separately with its start / end events)
+    hipGraphExec_t first = nullptr, next = nullptr, rest = nullptr;
   };
   std::vector<GraphEntry> graphs;
   hipStream_t gs = nullptr;  // library stream for graph replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // start / end events of the sweep launches of tr_step (one pair per
+  // slab-size bucket): the sweep's kernel time is measured in every step
+  hipEvent_t ev_sw[TR_NBUCKET][2] = {};
+  int sweep_events = 0;  // tr_set_sweep_timing
   // learned closure (seeding of the s = 0 cell factors)
   const float *mlp_params = nullptr;
   MlpStats mlp_stats{};
@@ -192,11 +198,27 @@ int sweep_bucket(int nx) {
   return b;
 }
 
+// One sweep launch per non-empty slab-size bucket; with timed, each launch
+// records its start and end on the bucket's event pair.
 void launch_sweeps(const tr_ctx *c, const LaunchEnv &env, const Ctl *ctl, int pmode, const double *kappa,
-                   const double *B, const void *Ip, void *Io, double *mom, double *bnd) {
+                   const double *B, const void *Ip, void *Io, double *mom, double *bnd, bool timed = false) {
   for (int b = 0; b < TR_NBUCKET; ++b)
     launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], c->cfg.precision == TR_PREC_F32_STORAGE, ctl, pmode, 0, kappa,
-                 B, Ip, Io, mom, bnd);
+                 B, Ip, Io, mom, bnd, timed ? c->ev_sw[b][0] : nullptr, timed ? c->ev_sw[b][1] : nullptr);
+}
+
+// Kernel time of the last timed sweep launches (after a synchronisation).
+void sweep_time(const tr_ctx *c, double *t_ms, long long *n_launch) {
+  for (int b = 0; b < TR_NBUCKET; ++b) {
+    if (c->t_sweep_b[b].n == 0) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_sw[b][0], c->ev_sw[b][1]) == hipSuccess) {
+      t_ms[TR_T_SWEEP] += ms;
+      n_launch[TR_T_SWEEP] += 1;
+    } else {
+      (void)hipGetLastError();  // no timing for this launch; leave no error behind
+    }
+  }
 }
 
 // Event marks around kernel groups (cfg.timing).  A group records its cycle
@@ -321,9 +343,13 @@ int tr_destroy(tr_ctx *c) {
   for (auto &g : c->graphs) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
+    if (g.rest) (void)hipGraphExecDestroy(g.rest);
   }
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  for (int b = 0; b < TR_NBUCKET; ++b)
+    for (int q = 0; q < 2; ++q)
+      if (c->ev_sw[b][q]) (void)hipEventDestroy(c->ev_sw[b][q]);
   if (c->gs) (void)hipStreamDestroy(c->gs);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->h_count) (void)hipHostFree(c->h_count);
@@ -519,6 +545,9 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
     return fail(TR_EHIP);
+  for (int b = 0; b < TR_NBUCKET; ++b)
+    for (int q = 0; q < 2; ++q)
+      if (hipEventCreate(&c->ev_sw[b][q]) != hipSuccess) return fail(TR_EHIP);
   std::vector<int> cost(n_slab);
   for (int s = 0; s < n_slab; ++s) {
     const SlabDev &S = c->hs[s];
@@ -716,6 +745,7 @@ int tr_set_tiles(tr_ctx *c, const int *K) {
   for (auto &g : c->graphs) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
+    if (g.rest) (void)hipGraphExecDestroy(g.rest);
   }
   c->graphs.clear();
   return TR_OK;
@@ -841,7 +871,11 @@ namespace {
 
 // Enqueues one transport iteration: (s >= 1) sweep and moments, then Lmax
 // predicated cycles; a slab whose inner loop has finished skips the rest.
-void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, bool with_sweep) {
+// One transport iteration: (sweep + moments when with_sweep), Lmax predicated
+// cycles, the start of the next iteration and the active-slab count.  With
+// sweep_outside the sweep launches are left to the caller (timed launches).
+void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, bool with_sweep,
+                       bool sweep_outside) {
   const int ns = c->nslab, gl = c->nlev - 1;
   LaunchEnv env = env_of(c, st);
   const LoIn fine = fine_in(c, c->kappa, c->B, s->f, s->fbnd, s->C, c->Phi, c->Eold, c->Fold);
@@ -867,16 +901,11 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
   ga.eps = c->cfg.eps;
   ga.eps_inner = c->cfg.eps_inner;
   const int nsch = (int)c->sched.size();
+  if (with_sweep && !sweep_outside)
+    launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
   if (with_sweep) {
-    launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
-    {
-      TimedScope ts(c, st, TR_T_SWEEP, -1);
-      launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
-    }
-    {
-      TimedScope ts(c, st, TR_T_MOMENTS, -1);
-      launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
-    }
+    TimedScope ts(c, st, TR_T_MOMENTS, -1);
+    launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
   }
   for (int l = 0; l < Lmax; ++l) {
     {
@@ -926,13 +955,16 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       launch_dS_sum(env, c->t_dS, c->d_ctl, PRED_DONECYC, l + 1, c->dSpart, c->dS);
     }
   }
+  // start of the next transport iteration (s + 1) for slabs still iterating
+  launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
   launch_count_active(env, c->d_ctl, ns, c->d_count);
 }
 
-int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, hipGraphExec_t *out) {
+int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, bool sweep_outside,
+                      hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_EHIP;
-  enqueue_iteration(c, s, c->gs, Lmax, with_sweep);
+  enqueue_iteration(c, s, c->gs, Lmax, with_sweep, sweep_outside);
   if (hipStreamEndCapture(c->gs, &g) != hipSuccess || !g) return TR_EHIP;
   const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -942,6 +974,12 @@ int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, h
 }  // namespace
 
 extern "C" {
+
+int tr_set_sweep_timing(tr_ctx *c, int on) {
+  if (!c || (on != 0 && on != 1)) return TR_EINVAL;
+  c->sweep_events = on;
+  return TR_OK;
+}
 
 int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st) {
   if (!c || !s || !s->T || !s->I_prev || !s->I_out || s->I_prev == s->I_out || !s->E || !s->F || !s->Ebnd ||
@@ -1009,36 +1047,50 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
         auto &old = c->graphs.front();
         (void)hipGraphExecDestroy(old.first);
         (void)hipGraphExecDestroy(old.next);
+        if (old.rest) (void)hipGraphExecDestroy(old.rest);
         c->graphs.erase(c->graphs.begin());
       }
       tr_ctx::GraphEntry e;
       e.key = key;
       // capture needs the stream idle of earlier uncaptured work ordering; the
       // step-start work above is already enqueued and stays before replays
-      int rc = capture_iteration(c, s, Lmax, false, &e.first);
-      if (!rc) rc = capture_iteration(c, s, Lmax, true, &e.next);
+      int rc = capture_iteration(c, s, Lmax, false, false, &e.first);
+      if (!rc) rc = capture_iteration(c, s, Lmax, true, false, &e.next);
       if (rc) return rc;
       c->graphs.push_back(e);
       ge = &c->graphs.back();
     }
+    if (c->sweep_events && !ge->rest) {
+      const int rc = capture_iteration(c, s, Lmax, true, true, &ge->rest);
+      if (rc) return rc;
+    }
   }
+  // sweeps launched outside the graphs with their start / end events
+  const bool sweep_ev = c->cfg.timing || c->sweep_events;
   double t_ms[TR_T_N] = {0};
   long long n_launch[TR_T_N] = {0};
   c->groups.clear();
   c->ev_used = 0;
+  int s0 = 0;  // transport iteration of slab 0 (event timing mode)
   for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
+    // transport sweep of iteration s >= 1 (predicated per slab)
+    if (outer > 0 && sweep_ev)
+      launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd, true);
     if (ge) {
-      if (hipGraphLaunch(outer == 0 ? ge->first : ge->next, gs) != hipSuccess) return TR_EHIP;
+      hipGraphExec_t gx = outer == 0 ? ge->first : sweep_ev ? ge->rest : ge->next;
+      if (hipGraphLaunch(gx, gs) != hipSuccess) return TR_EHIP;
     } else {
-      enqueue_iteration(c, s, gs, Lmax, outer > 0);
+      enqueue_iteration(c, s, gs, Lmax, outer > 0, true);
     }
     if (hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, gs) != hipSuccess) return TR_EHIP;
     if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
+    if (outer > 0 && sweep_ev) sweep_time(c, t_ms, n_launch);
     if (c->cfg.timing) {
-      // cycles run by slab 0 in this transport iteration (exact for one slab)
+      // cycles run by slab 0 in the iteration just completed (exact for one slab)
       Ctl k0;
       if (hipMemcpy(&k0, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return TR_EHIP;
-      tim_collect(c, k0.ncyc, t_ms, n_launch);
+      tim_collect(c, s0 < TR_MAXOUT ? k0.cycles[s0] : 0, t_ms, n_launch);
+      s0 = k0.s;
     }
     if (*c->h_count == 0) break;
   }

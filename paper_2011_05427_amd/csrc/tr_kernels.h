@@ -58,8 +58,10 @@ void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int p
                    double *dS);
 // Sweep tiles: K consecutive cells per lane (K in {1, 2, 4, 8}).
 // f32: corner intensities stored as float (binary64 arithmetic inside).
+// With ev0 / ev1 the launch records the kernel's own start and end on them.
 void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
-                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd);
+                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
+                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
                     const double *bnd, double *f, double *fbnd, double *C, double *Phi);
 void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi);

@@ -3,6 +3,8 @@
 // Every kernel is batched over slabs through a work table (Item = slab, index)
 // and can be predicated on the per-slab iteration control, so one launch
 // sequence serves a batch of slabs that converge at different iterations.
+#include <hip/hip_ext.h>
+
 #include "tr_device.h"
 #include "tr_kernels.h"
 
@@ -1302,13 +1304,21 @@ void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int p
 }
 
 void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
-                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd) {
+                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
+                  hipEvent_t ev0, hipEvent_t ev1) {
   if (tab.n == 0) return;
   const int waves = 2 * tab.n;
   const int nb = (waves + 3) / 4;
-#define TR_SWEEP_K(KK, TT)                                                                                         \
-  hipLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n, ctl, \
-                     pmode, lcyc, kappa, B, static_cast<const TT *>(Ip), static_cast<TT *>(Io), mom, bnd)
+#define TR_SWEEP_K(KK, TT)                                                                                          \
+  do {                                                                                                              \
+    if (ev0)                                                                                                        \
+      hipExtLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(256), 0, env.stream, ev0, ev1, 0, env.sd, env.pd, \
+                            tab.d, tab.n, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip),               \
+                            static_cast<TT *>(Io), mom, bnd);                                                     \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n,   \
+                         ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip), static_cast<TT *>(Io), mom, bnd); \
+  } while (0)
   if (f32) {
     switch (K) {
       case 1: TR_SWEEP_K(1, float); break;

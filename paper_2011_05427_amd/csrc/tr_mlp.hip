@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "tr.h"
@@ -41,12 +42,25 @@ struct Gemm {
   int relu;
   const uint16_t *mask;  // optional: zero where mask(m, n) == 0 (ReLU derivative)
   long long mm;
+  float *split;  // optional scratch [64][M][N]: long reductions are split over K
+  int kc;        // split-K chunk length (set by gemm(); 0: the whole K)
 };
+
+// Epilogue of one output element.
+__device__ inline void gemm_store(const Gemm &g, int mm, int nn, float v) {
+  if (g.bias) v += g.bias[nn];
+  if (g.relu) v = fmaxf(v, 0.0f);
+  if (g.mask && g.mask[mm * g.mm + nn] == 0) v = 0.0f;
+  if (g.Cf) g.Cf[mm * g.cm + nn] = v;
+  if (g.Cb) g.Cb[mm * g.cm + nn] = to_bf16(v);
+}
 
 // C = epilogue(A B): one wavefront per 32 x 32 output tile, K in steps of 16.
 // Lane l holds A(m0 + l % 32, k0 + 8 (l / 32) + 0..7), B(k0 + 8 (l / 32) + 0..7,
 // n0 + l % 32) and accumulator element j of D(m0 + 8 (j / 4) + 4 (l / 32) +
 // j % 4, n0 + l % 32).  Out-of-range rows/columns read zeros and are not stored.
+// With g.kc > 0, block z covers K range [z kc, (z + 1) kc) and writes its raw
+// partial tile to g.split[z] (the epilogue follows in k_gemm_reduce).
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m0 = (blockIdx.x * 2 + (wv >> 1)) * 32;
@@ -54,32 +68,43 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   if (m0 >= g.M || n0 >= g.N) return;
   const int r = lane & 31, hk = (lane >> 5) * 8;
   const int m = m0 + r, n = n0 + r;
+  const int kb = g.kc ? blockIdx.z * g.kc : 0;
+  const int ke = g.kc ? min(g.K, kb + g.kc) : g.K;
   f32x16 acc;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     bf16x8 a, b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + hk + i;
-      a[i] = (m < g.M && k < g.K) ? (short)g.A[m * g.am + k * g.ak] : (short)0;
-      b[i] = (n < g.N && k < g.K) ? (short)g.B[k * g.bk + n * g.bn] : (short)0;
+      a[i] = (m < g.M && k < ke) ? (short)g.A[m * g.am + k * g.ak] : (short)0;
+      b[i] = (n < g.N && k < ke) ? (short)g.B[k * g.bk + n * g.bn] : (short)0;
     }
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
   const int nn = n0 + r;
   if (nn >= g.N) return;
-  const float bias = g.bias ? g.bias[nn] : 0.0f;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int mm = m0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
     if (mm >= g.M) continue;
-    float v = acc[j] + bias;
-    if (g.relu) v = fmaxf(v, 0.0f);
-    if (g.mask && g.mask[mm * g.mm + nn] == 0) v = 0.0f;
-    if (g.Cf) g.Cf[mm * g.cm + nn] = v;
-    if (g.Cb) g.Cb[mm * g.cm + nn] = to_bf16(v);
+    if (g.kc)
+      g.split[((long long)blockIdx.z * g.M + mm) * g.N + nn] = acc[j];
+    else
+      gemm_store(g, mm, nn, acc[j]);
   }
+}
+
+// Split-K reduction: element (m, n) adds the nz partial tiles in order, then
+// applies the epilogue.
+__global__ __launch_bounds__(256) void k_gemm_reduce(Gemm g, int nz) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)g.M * g.N) return;
+  const int mm = (int)(t / g.N), nn = (int)(t - (long long)mm * g.N);
+  float v = 0.0f;
+  for (int z = 0; z < nz; ++z) v += g.split[(long long)z * g.M * g.N + t];
+  gemm_store(g, mm, nn, v);
 }
 
 // y[i * ldy + c] = bf16(x[i * ldx + c]) for c < ncol, zeros up to ldy.
@@ -126,13 +151,40 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ o, const
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// out[c] = sum_i x[i * ld + c] (bias gradients), fixed summation order.
-__global__ void k_colsum(const float *__restrict__ x, long long ld, int ncol, int nrow, float *__restrict__ out) {
+// Column sums out[c] = sum_i x[i * ld + c] (bias gradients) in two passes
+// with a fixed summation order.  Pass 1: block = (tile of 64 columns, chunk q
+// of `rows` rows); its 4 wavefronts add the rows q rows + w, + 4, ... and are
+// combined in LDS in wavefront order.  Pass 2 adds the chunk partials in
+// chunk order.
+#define TR_COLSUM_CHUNKS 64
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ x, long long ld, int ncol, int nrow,
+                                                     int rows, float *__restrict__ part) {
+  __shared__ float sh[4][64];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, q = blockIdx.y;
+  const int c = blockIdx.x * 64 + l;
+  float acc = 0.0f;
+  if (c < ncol) {
+    const int i1 = min(nrow, (q + 1) * rows);
+    for (int i = q * rows + w; i < i1; i += 4) acc += x[(long long)i * ld + c];
+  }
+  sh[w][l] = acc;
+  __syncthreads();
+  if (w == 0 && c < ncol) part[(long long)q * ncol + c] = ((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l];
+}
+
+__global__ void k_colsum_fin(const float *__restrict__ part, int ncol, int nchunk, float *__restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   float acc = 0.0f;
-  for (int i = 0; i < nrow; ++i) acc += x[(long long)i * ld + c];
+  for (int q = 0; q < nchunk; ++q) acc += part[(long long)q * ncol + c];
   out[c] = acc;
+}
+
+void colsum(const float *x, long long ld, int ncol, int nrow, float *out, float *part, hipStream_t st) {
+  const int nchunk = std::max(1, std::min(TR_COLSUM_CHUNKS, (nrow + 63) / 64));
+  const int rows = (nrow + nchunk - 1) / nchunk;
+  hipLaunchKernelGGL(k_colsum_part, dim3((ncol + 63) / 64, nchunk), dim3(256), 0, st, x, ld, ncol, nrow, rows, part);
+  hipLaunchKernelGGL(k_colsum_fin, dim3((ncol + 63) / 64), dim3(64), 0, st, part, ncol, nchunk, out);
 }
 
 __global__ void k_accum(float *__restrict__ dst, const float *__restrict__ src) {
@@ -171,7 +223,7 @@ __global__ void k_gather(const float *__restrict__ src, int w, const int *__rest
 // work layout (bytes, 256-aligned pieces)
 struct Work {
   uint16_t *Xb, *Wb, *H1, *H2, *H3, *dOb, *dZb;
-  float *O, *dO, *dZf, *part, *gtmp;
+  float *O, *dO, *dZf, *part, *gtmp, *cpart, *split;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -188,6 +240,8 @@ size_t work_bytes(long long n) {
   b += align256(n * NH * 4);               // dZf
   b += align256(((n + 255) / 256) * 4);    // loss partials
   b += align256((size_t)NPARAM * 4);       // gradient scratch
+  b += align256((size_t)TR_COLSUM_CHUNKS * NH * 4);  // column-sum chunk partials
+  b += align256((size_t)64 * NH * NH * 4);            // split-K partial tiles
   return b;
 }
 
@@ -211,12 +265,31 @@ Work carve(void *w, long long n) {
   k.dZf = (float *)take(n * NH * 4);
   k.part = (float *)take(((n + 255) / 256) * 4);
   k.gtmp = (float *)take((size_t)NPARAM * 4);
+  k.cpart = (float *)take((size_t)TR_COLSUM_CHUNKS * NH * 4);
+  k.split = (float *)take((size_t)64 * NH * NH * 4);
   return k;
 }
 
-void gemm(const Gemm &g, hipStream_t st) {
+// Long reductions over few output tiles (the weight gradients, K = batch) are
+// split over K into up to 64 chunks of at least 128 so the chip fills.
+void gemm(const Gemm &g0, hipStream_t st) {
+  Gemm g = g0;
   dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
+  int nz = 1;
+  if (g.split && g.K >= 512 && (long long)g.M * g.N <= (long long)NH * NH) {
+    nz = std::min(64, g.K / 128);
+    g.kc = ((g.K + nz - 1) / nz + 15) / 16 * 16;
+    nz = (g.K + g.kc - 1) / g.kc;
+  }
+  if (nz == 1) {
+    g.kc = 0;
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+    return;
+  }
+  grid.z = nz;
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+  const long long n = (long long)g.M * g.N;
+  hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, nz);
 }
 
 Gemm gemm_nn(const uint16_t *A, long long am, long long ak, const uint16_t *B, long long bk, long long bn, int M,
@@ -278,9 +351,10 @@ void backward(const float *params, const float *X, const float *Y, long long n, 
   // layer 4: dW4 = H3^T dO, db4 = sum dO, dZ3 = (dO W4^T) * [H3 > 0]
   Gemm g = gemm_nn(w.H3, 1, NH, w.dOb, NOUT, 1, NH, NOUT, (int)n);
   g.Cf = grad + OW4;
+  g.split = w.split;
   g.cm = NOUT;
   gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, st, w.dO, (long long)NOUT, NOUT, (int)n, grad + OB4);
+  colsum(w.dO, (long long)NOUT, NOUT, (int)n, grad + OB4, w.cpart, st);
   g = gemm_nn(w.dOb, NOUT, 1, W4, 1, NOUT, (int)n, NH, NOUT);
   g.Cf = w.dZf;
   g.Cb = w.dZb;
@@ -291,9 +365,10 @@ void backward(const float *params, const float *X, const float *Y, long long n, 
   // layer 3
   g = gemm_nn(w.H2, 1, NH, w.dZb, NH, 1, NH, NH, (int)n);
   g.Cf = grad + OW3;
+  g.split = w.split;
   g.cm = NH;
   gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3(2), dim3(64), 0, st, w.dZf, (long long)NH, NH, (int)n, grad + OB3);
+  colsum(w.dZf, (long long)NH, NH, (int)n, grad + OB3, w.cpart, st);
   g = gemm_nn(w.dZb, NH, 1, W3, 1, NH, (int)n, NH, NH);
   g.Cf = w.dZf;
   g.Cb = w.dZb;
@@ -304,9 +379,10 @@ void backward(const float *params, const float *X, const float *Y, long long n, 
   // layer 2
   g = gemm_nn(w.H1, 1, NH, w.dZb, NH, 1, NH, NH, (int)n);
   g.Cf = grad + OW2;
+  g.split = w.split;
   g.cm = NH;
   gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3(2), dim3(64), 0, st, w.dZf, (long long)NH, NH, (int)n, grad + OB2);
+  colsum(w.dZf, (long long)NH, NH, (int)n, grad + OB2, w.cpart, st);
   g = gemm_nn(w.dZb, NH, 1, W2, 1, NH, (int)n, NH, NH);
   g.Cf = w.dZf;
   g.Cb = w.dZb;
@@ -317,9 +393,10 @@ void backward(const float *params, const float *X, const float *Y, long long n, 
   // layer 1
   g = gemm_nn(w.Xb, 1, NINP, w.dZb, NH, 1, NINP, NH, (int)n);
   g.Cf = grad + OW1;
+  g.split = w.split;
   g.cm = NH;
   gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3(2), dim3(64), 0, st, w.dZf, (long long)NH, NH, (int)n, grad + OB1);
+  colsum(w.dZf, (long long)NH, NH, (int)n, grad + OB1, w.cpart, st);
 }
 
 }  // namespace

@@ -171,3 +171,31 @@ def test_graph_replay_equals_eager_launches():
         sv.close()
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.gpu
+def test_timed_sweep_launches_equal_graph_replay():
+    """With sweep timing on, tr_step launches the sweeps outside its graphs
+    with start / end events; the states stay bitwise identical to the plain
+    graph replay, and the sweep kernel time is reported for every launch."""
+    slab = inputs.make_slab(40, 32, 8, dt=0.004)
+    levels = [32, 4, 1]
+    cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_W, lmax=2)
+    note("graph replay vs timed sweep launches, W cycle, 4 steps (timing on in steps 1 and 3)")
+    outs = []
+    for mode in (0, 1):
+        sv = binding.Solver([slab], [levels], cfg)
+        st = sv.new_state()
+        sv.state_init(st, slab.T0)
+        for k in range(4):
+            sv.set_sweep_timing(mode == 1 and k % 2 == 1)
+            stats = sv.step(st)
+            if mode == 1 and k % 2 == 1:
+                assert stats[0].n_launch[binding.T_SWEEP] == stats[0].n_ti > 0
+                assert stats[0].t_ms[binding.T_SWEEP] > 0.0
+            else:
+                assert stats[0].n_launch[binding.T_SWEEP] == 0
+        outs.append({k: to_np(v).copy() for k, v in st.items()})
+        sv.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
