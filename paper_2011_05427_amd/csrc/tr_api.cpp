@@ -32,6 +32,7 @@ struct tr_ctx {
   std::vector<int> sched;
   int lo_threads = 64;    // block size of the group LO solves
   int grey_threads = 64;  // block size of the grey solve
+  int opac_run = 4;       // groups per thread of the opacity kernel (1 or 4)
   std::vector<SlabDev> hs;  // host copies of the slab descriptors
   std::vector<double> h_inc;
   // totals per kind
@@ -559,12 +560,15 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
 
   // work tables
   {
+    // small tables: one group per opacity thread (shortest chains); large
+    // ones: runs of 4 groups sharing their edge integrals
+    c->opac_run = c->n_gi <= (1LL << 21) ? 1 : 4;
     std::vector<Item> opac, dsum, cell, gi, g, grey;
     std::vector<std::vector<std::pair<long long, Item>>> sweepb(TR_NBUCKET);
     std::vector<std::vector<Item>> lo(nlev);
     for (int s = 0; s < n_slab; ++s) {
       const SlabDev &S = c->hs[s];
-      const int ncb = (S.nx + 15) / 16;
+      const int ncb = (S.nx + 4 * c->opac_run - 1) / (4 * c->opac_run);
       for (int q = 0; q < S.nchunk * ncb; ++q) opac.push_back({s, q});
       for (int st = 0; st < S.nx; st += 64) dsum.push_back({s, st});
       for (int st = 0; st < S.nx; st += 256) cell.push_back({s, st});
@@ -612,7 +616,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       }
       if (up(c->Told, Tb.data(), 8 * Tb.size())) return fail(TR_EHIP);
       LaunchEnv env = env_of(c, 0);
-      launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, c->Told, c->kappa, c->B, c->dSpart);
+      launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, c->Told, c->kappa, c->B, c->dSpart);
       if (hipDeviceSynchronize() != hipSuccess) return fail(TR_EHIP);
       std::vector<double> hB(c->n_gi);
       if (hipMemcpy(hB.data(), c->B, 8 * hB.size(), hipMemcpyDeviceToHost) != hipSuccess) return fail(TR_EHIP);
@@ -675,7 +679,7 @@ int tr_set_incoming(tr_ctx *c, int slab, const double *inc_left, const double *i
 int tr_opacity(tr_ctx *c, const double *T, double *kappa, double *B, double *dS, hipStream_t st) {
   if (!c || !T || !kappa || !B) return TR_EINVAL;
   LaunchEnv env = env_of(c, st);
-  launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, T, kappa, B, c->dSpart);
+  launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, T, kappa, B, c->dSpart);
   if (dS) launch_dS_sum(env, c->t_dS, nullptr, PRED_ALL, 0, c->dSpart, dS);
   return hip_err(hipGetLastError());
 }
@@ -857,7 +861,7 @@ int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
     return TR_EINVAL;
   LaunchEnv env = env_of(c, st);
   launch_fill(env, s->T, T0, c->n_cell);
-  launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, s->T, c->kappa, c->B, c->dSpart);
+  launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, s->T, c->kappa, c->B, c->dSpart);
   launch_init_state(env, c->t_gi, c->cfg.precision == TR_PREC_F32_STORAGE, c->B, s->I_out, s->E, s->F, s->Ebnd,
                     c->mom, c->bnd);
   launch_moments(env, c->t_gi, nullptr, PRED_ALL, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
@@ -926,7 +930,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       const int gm = c->sched[q];
       {
         TimedScope ts(c, st, TR_T_OPACITY, l);
-        launch_opacity(env, c->t_opac, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
+        launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
         launch_dS_sum(env, c->t_dS, c->d_ctl, PRED_CYCLE, l, c->dSpart, c->dS);
       }
       {
@@ -951,7 +955,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     }
     {
       TimedScope ts(c, st, TR_T_OPACITY, l);
-      launch_opacity(env, c->t_opac, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
+      launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
       launch_dS_sum(env, c->t_dS, c->d_ctl, PRED_DONECYC, l + 1, c->dSpart, c->dS);
     }
   }
@@ -1020,7 +1024,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   launch_copy(env, s->E, c->Eold, c->n_gi);
   launch_copy(env, s->F, c->Fold, c->n_ge);
   launch_phi(env, c->t_g, s->C, c->Phi);
-  launch_opacity(env, c->t_opac, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
+  launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
   launch_dS_sum(env, c->t_dS, nullptr, PRED_ALL, 0, c->dSpart, c->dS);
   unsigned long long seed_counts[2] = {0, 0};
   if (c->mlp_params) {

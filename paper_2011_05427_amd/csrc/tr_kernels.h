@@ -51,8 +51,10 @@ struct Table {
   int n;
 };
 
-void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *T,
-                    double *kappa, double *B, double *dSpart);
+// run = 1 or 4 groups per thread; tab items = (slab, chunk * ncb + cell block)
+// with ncb = ceil(nx / (4 run)).
+void launch_opacity(const LaunchEnv &env, const Table &tab, int run, const Ctl *ctl, int pmode, int lcyc,
+                    const double *T, double *kappa, double *B, double *dSpart);
 // dS per cell from the chunk partials; tab items = (slab, first of 64 cells).
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
                    double *dS);

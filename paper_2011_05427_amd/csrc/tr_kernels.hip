@@ -37,25 +37,28 @@ __device__ inline bool pred_ok(const Ctl *ctl, int slab, int mode, int l) {
 
 // ---------------------------------------------------------------------------
 // A1: opacity and group Planck tables at T, with the 64-group chunk partial
-// sums of dS = d/dT sum_g 2 kappa_g B_g.  Block = one 64-group chunk x 16
-// cells; thread = (run of 4 consecutive groups, cell), so adjacent groups share
-// their common edge integral; the 16 run sums of a cell are added in LDS in a
-// fixed order.
+// sums of dS = d/dT sum_g 2 kappa_g B_g.  Block = one 64-group chunk x 4 RUN
+// cells; thread = (run of RUN consecutive groups, cell): adjacent groups of a
+// run share their common edge integral.  RUN = 4 saves edge work on large
+// tables; RUN = 1 gives the shortest dependent chain per thread for small
+// ones.  The 64 / RUN run sums of a cell are added in LDS in a fixed order.
 // ---------------------------------------------------------------------------
+template <int RUN>
 __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd, ProbDev pd,
                                                  const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
                                                  const double *__restrict__ T, double *__restrict__ kappa,
                                                  double *__restrict__ B, double *__restrict__ dSpart) {
-  __shared__ double part[16][17];
+  constexpr int CB = 4 * RUN, NR = 64 / RUN;  // cells per block, runs per chunk
+  __shared__ double part[NR][CB + 1];
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   const int nx = S.nx, ng = S.ng;
-  const int ncb = (nx + 15) >> 4;
+  const int ncb = (nx + CB - 1) / CB;
   const int chunk = it.idx / ncb, cb = it.idx - chunk * ncb;
-  const int run = threadIdx.x >> 4, cl = threadIdx.x & 15;
-  const int i = cb * 16 + cl;
-  const int g0 = chunk * 64 + run * 4, g1 = min(ng, g0 + 4);
+  const int run = threadIdx.x / CB, cl = threadIdx.x - run * CB;
+  const int i = cb * CB + cl;
+  const int g0 = chunk * 64 + run * RUN, g1 = min(ng, g0 + RUN);
   double dS = 0.0;
   if (i < nx && g0 < ng) {
     const double Ti = T[S.o_cell + i];
@@ -65,7 +68,10 @@ __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd,
     const double *nue = pd.nu_e + S.o_nu;
     const double *nuc = pd.nu_c + S.o_g;
     EdgeQ lo = edge_q(nue[g0], Ti);
-    for (int g = g0; g < g1; ++g) {
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+      const int g = g0 + q;
+      if (g >= g1) break;
       const EdgeQ hi = edge_q(nue[g + 1], Ti);
       const double Bg = scale * q_interval(lo, hi);
       const double dBg = 4.0 * Bg / Ti - scale / Ti * (hi.g4 - lo.g4);
@@ -82,10 +88,18 @@ __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd,
   }
   part[run][cl] = dS;
   __syncthreads();
+  // runs r = run, run + 8, ... by the first 8 runs, then the 8 partials
+  if (run < 8) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = run; r < NR; r += 8) acc += part[r][cl];
+    part[run][cl] = acc;
+  }
+  __syncthreads();
   if (run == 0 && i < nx) {
     double acc = 0.0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc += part[r][cl];
+    for (int r = 0; r < 8; ++r) acc += part[r][cl];
     dSpart[S.o_chunk + (long long)chunk * nx + i] = acc;
   }
 }
@@ -663,7 +677,7 @@ __device__ inline void level_out(const SlabDev &S, int level, int p, const LoSol
 template <int K, bool FINE>
 __global__ __launch_bounds__(512) void k_lo(const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab,
                                             const Ctl *ctl, int pmode, int lcyc, int level, LoIn in, LoSol sol) {
-  __shared__ double lds[8 * 512];
+  extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
@@ -945,7 +959,7 @@ template <int K>
 __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, ProbDev pd,
                                               const Item *__restrict__ tab, Ctl *ctl, int pmode, int lcyc,
                                               GreyArgs ga) {
-  __shared__ double lds[8 * 512];
+  extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
   __shared__ int s_flag[2];
   const Item it = tab[blockIdx.x];
   const int slab = it.slab;
@@ -1290,11 +1304,15 @@ __global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, d
 // ---------------------------------------------------------------------------
 static inline dim3 blocks(int n) { return dim3((unsigned)n); }
 
-void launch_opacity(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *T,
-                    double *kappa, double *B, double *dSpart) {
+void launch_opacity(const LaunchEnv &env, const Table &tab, int run, const Ctl *ctl, int pmode, int lcyc,
+                    const double *T, double *kappa, double *B, double *dSpart) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_opacity, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, lcyc, T,
-                     kappa, B, dSpart);
+  if (run == 1)
+    hipLaunchKernelGGL(k_opacity<1>, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, lcyc,
+                       T, kappa, B, dSpart);
+  else
+    hipLaunchKernelGGL(k_opacity<4>, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, lcyc,
+                       T, kappa, B, dSpart);
 }
 
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
@@ -1353,10 +1371,10 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
                const LoIn &in, const LoSol &sol) {
   if (tab.n == 0) return;
   if (level == 0)
-    hipLaunchKernelGGL((k_lo<TR_LO_K, true>), blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl,
+    hipLaunchKernelGGL((k_lo<TR_LO_K, true>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
                        pmode, lcyc, level, in, sol);
   else
-    hipLaunchKernelGGL((k_lo<TR_LO_K, false>), blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl,
+    hipLaunchKernelGGL((k_lo<TR_LO_K, false>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
                        pmode, lcyc, level, in, sol);
 }
 
@@ -1387,7 +1405,7 @@ void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_grey<TR_GREY_K>, blocks(tab.n), dim3(threads), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
+  hipLaunchKernelGGL(k_grey<TR_GREY_K>, blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
                      lcyc, ga);
 }
 
