@@ -346,6 +346,22 @@ int tr_closure_targets(tr_ctx *ctx, const double *f, const double *E_new, const 
                        hipStream_t stream);
 
 /*
+ * Prolongation with the learned shape correction (the paper's method moves
+ * coarse-grid information back to the fine grid through T only; prolongation
+ * between frequency grids appears there as a general multigrid operator).
+ * For every slab, coarse group p of level `level` (>= 1) and cell i, the fine
+ * groups g of p get E_fine = E_p,i w_g,i / sum_{g' in p} w_g',i with
+ * w = E_prev exp(r), r the closure's second output (r: [gi][2] float32 as
+ * written by tr_mlp_forward on tr_mlp_features rows; column 1 is read; NULL
+ * means r = 0); a block whose weights sum to 1e-290 or less is split evenly.
+ * E_coarse: pooled like kind TR_K_LEV_PI + level; E_prev, E_fine: gi arrays
+ * (distinct).  Prolonged groups of a block sum to E_p.
+ * Errors: TR_EINVAL (level out of range, ng not a multiple of the level).
+ */
+int tr_prolong(tr_ctx *ctx, int level, const double *E_coarse, const double *E_prev, const float *r, double *E_fine,
+               hipStream_t stream);
+
+/*
  * Attaches a trained closure to the context (params: device, kept by the
  * caller; NULL detaches).  While attached, tr_step replaces the previous
  * step's cell QD factors by the network's prediction at the start of every

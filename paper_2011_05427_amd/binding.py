@@ -70,7 +70,8 @@ EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_in
            "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step",
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
            "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
-           "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing"]
+           "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing",
+           "tr_prolong"]
 
 _lib = None
 
@@ -106,6 +107,7 @@ def load():
     lib.tr_state_init.argtypes = [vp, C.POINTER(TrState), C.c_double, vp]
     lib.tr_step.argtypes = [vp, C.POINTER(TrState), _ip, C.POINTER(TrStats), vp]
     lib.tr_set_sweep_timing.argtypes = [vp, C.c_int]
+    lib.tr_prolong.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.tr_mlp_nparam.argtypes = []
     lib.tr_mlp_work_bytes.argtypes = [C.c_longlong]
     lib.tr_mlp_work_bytes.restype = C.c_size_t
@@ -293,6 +295,12 @@ class Solver:
         if swap:
             st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
         return stats
+
+    def prolong(self, level, E_coarse, E_prev, r, E_fine):
+        """tr_prolong: E_fine from level `level` energy densities (r: closure
+        output [gi][2] float32 or None)."""
+        _check(self.lib.tr_prolong(self._ctx, int(level), _ptr(E_coarse), _ptr(E_prev),
+                                   _ptr(r) if r is not None else None, _ptr(E_fine), self._stream()), "tr_prolong")
 
     def set_sweep_timing(self, on: bool):
         """Sweeps of tr_step launched with start / end events (kernel time in

@@ -62,6 +62,7 @@ struct tr_ctx {
   int sweep_K[TR_NBUCKET] = {1, 2, 4, 4, 4, 4};
   Table t_lo[TR_MAXLEV]{};
   std::map<std::pair<int, int>, RestrictTables> t_red;
+  std::map<int, Table> t_pro;  // prolongation work per level
   // optional event timing of kernel groups inside tr_step
   struct TimedGroup {
     int cat, cycle, e0, e1;
@@ -826,6 +827,25 @@ int tr_closure_targets(tr_ctx *c, const double *f, const double *E_new, const do
                        hipStream_t st) {
   if (!c || !f || !E_new || !E_prev || !Y || block < 1) return TR_EINVAL;
   launch_closure_targets(env_of(c, st), c->t_gi, f, E_new, E_prev, block, Y);
+  return hip_err(hipGetLastError());
+}
+
+int tr_prolong(tr_ctx *c, int level, const double *E_coarse, const double *E_prev, const float *r, double *E_fine,
+               hipStream_t st) {
+  if (!c || level < 1 || level >= c->nlev || !E_coarse || !E_prev || !E_fine || E_prev == E_fine) return TR_EINVAL;
+  if (!c->t_pro.count(level)) {
+    std::vector<Item> items;
+    for (int s = 0; s < c->nslab; ++s) {
+      const SlabDev &S = c->hs[s];
+      if (S.ng % S.lev_ng[level]) return TR_EINVAL;
+      for (int q = 0; q < S.lev_ng[level] * S.nx; q += 256) items.push_back({s, q});
+    }
+    Table t{};
+    const int rc = upload_table(c, items, t);
+    if (rc) return rc;
+    c->t_pro[level] = t;
+  }
+  launch_prolong(env_of(c, st), c->t_pro[level], level, E_coarse, E_prev, r, E_fine);
   return hip_err(hipGetLastError());
 }
 

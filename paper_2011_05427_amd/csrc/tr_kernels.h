@@ -110,5 +110,8 @@ void launch_mlp_features(const LaunchEnv &env, const Table &tab, const double *T
                          const MlpStats &ms, float *X);
 void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double *f, const double *Enew,
                             const double *Eprev, int blk, float *Y);
+// tab items = (slab, first (p, i) of 256) over the level's n_p nx cells.
+void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const double *Ec, const double *Eprev,
+                    const float *r, double *Ef);
 void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts);
 int upload_head_coef(const double *coef);

@@ -1276,6 +1276,34 @@ __global__ __launch_bounds__(256) void k_closure_targets(const SlabDev *__restri
   Y[2 * (S.o_gi + idx) + 1] = (float)r;
 }
 
+// Prolongation of level `lev` energy densities to the fine groups with the
+// closure's shape correction: thread = (slab, coarse group p, cell i); the
+// fine groups g of p get E_p w_g / sum w over the block, w = E_prev exp(r_g)
+// (r_g = 0 without a prediction); an empty block is split evenly.
+__global__ __launch_bounds__(256) void k_prolong(const SlabDev *__restrict__ sd, const Item *__restrict__ tab, int lev,
+                                                 const double *__restrict__ Ec, const double *__restrict__ Eprev,
+                                                 const float *__restrict__ r, double *__restrict__ Ef) {
+  const Item it = tab[blockIdx.x];
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, np = S.lev_ng[lev];
+  const int blk = S.ng / np;
+  const int idx = it.idx + threadIdx.x;
+  if (idx >= np * nx) return;
+  const int p = idx / nx, i = idx - p * nx;
+  const double Ep = Ec[S.o_lpi[lev] + idx];
+  const long long o0 = S.o_gi + (long long)p * blk * nx + i;
+  double W = 0.0;
+  for (int q = 0; q < blk; ++q) {
+    const long long o = o0 + (long long)q * nx;
+    W += Eprev[o] * (r ? exp((double)r[2 * o + 1]) : 1.0);
+  }
+  for (int q = 0; q < blk; ++q) {
+    const long long o = o0 + (long long)q * nx;
+    const double w = Eprev[o] * (r ? exp((double)r[2 * o + 1]) : 1.0);
+    Ef[o] = W > TR_TINY ? Ep * w / W : Ep / blk;
+  }
+}
+
 // f <- fhat where 0 < fhat < 1 (counted), else the old factor stays (counted).
 __global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, double *__restrict__ f, long long n,
                                                 unsigned long long *__restrict__ counts) {
@@ -1454,6 +1482,12 @@ void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double
   if (tab.n == 0) return;
   hipLaunchKernelGGL(k_closure_targets, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, f, Enew, Eprev, blk,
                      Y);
+}
+
+void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const double *Ec, const double *Eprev,
+                    const float *r, double *Ef) {
+  if (tab.n == 0) return;
+  hipLaunchKernelGGL(k_prolong, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, lev, Ec, Eprev, r, Ef);
 }
 
 void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts) {

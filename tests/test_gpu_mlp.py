@@ -131,3 +131,47 @@ def test_training_and_learned_steps_converge_to_plain():
     assert runs[True][3] > 0
     assert rel_err(runs[True][0], runs[False][0]) < 1e-9
     assert rel_err(runs[True][1], runs[False][1]) < 1e-9
+
+
+@pytest.mark.parametrize("with_r", [False, True])
+def test_prolong_matches_oracle(with_r):
+    """tr_prolong on a batch of two slabs (levels G, G/8, 1), every coarse level,
+    against the oracle prolongation; includes a cell whose block is empty."""
+    from oracle.prolong import prolong
+
+    slabs = [inputs.make_slab(37, 32, 8), inputs.make_slab(70, 64, 8, C1=5.0)]
+    levels = [[s.ng, s.ng // 8, 1] for s in slabs]
+    cfg = inputs.SolverCfg(levels=[0, 0, 1], cycle=inputs.CYCLE_W, lmax=2)
+    note(f"prolong, r={'closure output' if with_r else 'none'}")
+    sv = binding.Solver(slabs, levels, cfg)
+    rng = np.random.default_rng(11)
+    n_gi = sv.total(binding.TR_K_GI)
+    Eprev = 10.0 ** rng.uniform(-9, 1, size=n_gi)
+    o1 = sv.layout(binding.TR_K_GI, 1)[0]
+    Eprev[o1 + 5 * 70 + 3: o1 + 5 * 70 + 4] = 0.0  # one cell of one fine group
+    Eprev_blk = Eprev.copy()
+    for g in range(8):  # block 0 of level 1 in cell 11 of slab 1: empty
+        Eprev_blk[o1 + g * 70 + 11] = 0.0
+    r = rng.uniform(-2, 2, size=(n_gi, 2)).astype(np.float32) if with_r else None
+    for lev in (1, 2):
+        n_pi = sv.total(binding.TR_K_LEV_PI + lev)
+        Ec = 10.0 ** rng.uniform(-4, 0, size=n_pi)
+        out = sv.empty(binding.TR_K_GI)
+        rd = None
+        if r is not None:
+            import torch
+
+            rd = torch.as_tensor(np.ascontiguousarray(r).ravel()).to("cuda")  # float32 [gi][2]
+        sv.prolong(lev, to_dev(Ec), to_dev(Eprev_blk), rd, out)
+        got = to_np(out)
+        for k, s in enumerate(slabs):
+            og = sv.layout(binding.TR_K_GI, k)[0]
+            op = sv.layout(binding.TR_K_LEV_PI + lev, k)[0]
+            npl = levels[k][lev]
+            Ep = Ec[op:op + npl * s.nx].reshape(npl, s.nx)
+            Epr = Eprev_blk[og:og + s.ng * s.nx].reshape(s.ng, s.nx)
+            rr = None if r is None else r[og:og + s.ng * s.nx, 1].astype(np.float64).reshape(s.ng, s.nx)
+            want = prolong(Ep, Epr, rr)
+            have = got[og:og + s.ng * s.nx].reshape(s.ng, s.nx)
+            assert rel_err(have, want) < 1e-13, (lev, k, rel_err(have, want))
+    sv.close()
