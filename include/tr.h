@@ -298,15 +298,17 @@ int tr_get_tiles(const tr_ctx *ctx, int *K, int *items);
 
 /*
  * Learned closure (not part of the paper's method; its plain sweep stays the
- * judge).  A multilayer perceptron 5 -> 128 -> 128 -> 128 -> 2 with ReLU
- * hidden layers; output 0 through a logistic sigmoid predicts the group
- * Eddington factor, output 1 is a prolongation correction.  Products run in
- * bfloat16 on MFMA with float32 accumulation.  Parameters: float32 vector of
- * tr_mlp_nparam() entries, row-major W1 [8][128] (input rows 5..7 unused), b1
- * [128], W2 [128][128], b2, W3 [128][128], b3, W4 [128][2], b4 [2].  Inputs X
- * [n][8] float32 standardised features (columns 5..7 ignored); targets Y
- * [n][2] float32.  `work` is caller-owned device scratch of
- * tr_mlp_work_bytes(n) (tr_mlp_train_work_bytes(batch) for training).
+ * judge).  A multilayer perceptron 7 -> 128 -> 128 -> 128 -> 2 with ReLU
+ * hidden layers; output 0 through a logistic sigmoid s predicts the change of
+ * the group Eddington factor over a time step, f_seed = f + 0.05 (2 s - 1);
+ * output 1 is a prolongation correction (log change of the within-block
+ * spectral shape).  Products run in bfloat16 on MFMA with float32
+ * accumulation.  Parameters: float32 vector of tr_mlp_nparam() entries,
+ * row-major W1 [8][128] (input row 7 unused), b1 [128], W2 [128][128], b2, W3
+ * [128][128], b3, W4 [128][2], b4 [2].  Inputs X [n][8] float32 standardised
+ * features (column 7 ignored); targets Y [n][2] float32.  `work` is
+ * caller-owned device scratch of tr_mlp_work_bytes(n)
+ * (tr_mlp_train_work_bytes(batch) for training).
  */
 int tr_mlp_nparam(void);
 size_t tr_mlp_work_bytes(long long n);
@@ -329,21 +331,24 @@ int tr_mlp_train_epoch(float *params, float *m, float *v, int *t, float lr, cons
  * Closure inputs for every slab, group and cell (sample g * nx + i of each
  * slab, pooled like gi): log T_i, log nu_g, log(kappa_g,i dx_i), log T_{i-1},
  * log T_{i+1} (left neighbour of cell 0: T_left when positive, else T_0;
- * right neighbour of the last cell: itself), standardised with mean/std
- * (host [5] each).  X: [gi total][8] float32.
+ * right neighbour of the last cell: itself), the factor f_g,i, and
+ * log(T_i / T_prev_i) (T_prev: cell array of the previous time step's start,
+ * nullable = no change), standardised with mean/std (host [7] each).
+ * X: [gi total][8] float32 (column 7 zero).
  */
-int tr_mlp_features(tr_ctx *ctx, const double *T, const double *kappa, const float *mean, const float *std,
-                    float *X, hipStream_t stream);
+int tr_mlp_features(tr_ctx *ctx, const double *T, const double *T_prev, const double *kappa, const double *f,
+                    const float *mean, const float *std, float *X, hipStream_t stream);
 
 /*
- * Training targets from two consecutive fine solutions (gi arrays): Y [gi][2]
- * float32 = (f_g,i, r_g,i), r = log((E_g/E_p) / (E'_g/E'_p)) the change of
- * the within-block spectral shape, E_p the sum over the `block` consecutive
- * groups containing g (0 where a share is at or below 1e-290), clipped to
- * [-2, 2].
+ * Training targets from two consecutive converged steps (gi arrays): Y [gi][2]
+ * float32 = (s_g,i, r_g,i), s = 1/2 + (f - f_prev) / 0.1 clipped to
+ * [0.01, 0.99] (the sigmoid value that reproduces the factor change), r =
+ * log((E_g/E_p) / (E'_g/E'_p)) the change of the within-block spectral shape,
+ * E_p the sum over the `block` consecutive groups containing g (0 where a
+ * share is at or below 1e-290), clipped to [-2, 2].
  */
-int tr_closure_targets(tr_ctx *ctx, const double *f, const double *E_new, const double *E_prev, int block, float *Y,
-                       hipStream_t stream);
+int tr_closure_targets(tr_ctx *ctx, const double *f, const double *f_prev, const double *E_new, const double *E_prev,
+                       int block, float *Y, hipStream_t stream);
 
 /*
  * Prolongation with the learned shape correction (the paper's method moves
@@ -363,11 +368,12 @@ int tr_prolong(tr_ctx *ctx, int level, const double *E_coarse, const double *E_p
 
 /*
  * Attaches a trained closure to the context (params: device, kept by the
- * caller; NULL detaches).  While attached, tr_step replaces the previous
- * step's cell QD factors by the network's prediction at the start of every
- * step (transport iteration s = 0); a prediction outside (0, 1) keeps the old
- * factor.  All later transport iterations sweep and test convergence exactly
- * as without the closure.
+ * caller; mean/std: host [7]; NULL params detaches).  While attached, tr_step
+ * adds the network's predicted factor change to the previous step's cell QD
+ * factors at the start of every step (transport iteration s = 0); a seeded
+ * factor outside (0, 1) keeps the old one.  The temperature history the
+ * inputs use restarts with tr_state_init.  All later transport iterations
+ * sweep and test convergence exactly as without the closure.
  */
 int tr_set_closure(tr_ctx *ctx, const float *params, const float *mean, const float *std);
 

@@ -1,10 +1,12 @@
 """FP64 reference of the learned closure network (oracle; test infrastructure only).
 
-The closure is a multilayer perceptron 5 -> 128 -> 128 -> 128 -> 2 with ReLU
-hidden layers.  Output 0 passes through a logistic sigmoid and predicts the
-group Eddington factor f_g,i in (0, 1); output 1 is a linear prolongation
-correction r_g,i (the log change of the within-block spectral shape).  The
-loss of a batch of n samples is  (1/n) sum [(fhat - f)^2 + (rhat - r)^2].
+The closure is a multilayer perceptron 7 -> 128 -> 128 -> 128 -> 2 with ReLU
+hidden layers.  Output 0 passes through a logistic sigmoid s and predicts the
+change of the group Eddington factor over a time step as a residual on the
+previous factor: f_seed = f^{j-1} + DF (2 s - 1), DF = 0.05; output 1 is a
+linear prolongation correction r_g,i (the log change of the within-block
+spectral shape).  The loss of a batch of n samples is
+(1/n) sum [(shat - s)^2 + (rhat - r)^2].
 
 The GPU runs the products in bfloat16 with float32 accumulation: the weights
 and each layer's input activations are rounded to bfloat16 (round to nearest,
@@ -14,7 +16,7 @@ differ only by the float32 accumulation.  The pure float64 path
 (``bf16=False``) is pinned by central finite differences.
 
 Parameter vector layout (float32 on the GPU, float64 here), row-major:
-  W1 [8][128]  (input features padded from 5 to 8 with zero rows)
+  W1 [8][128]  (input features padded from 7 to 8 with a zero row)
   b1 [128]
   W2 [128][128], b2 [128], W3 [128][128], b3 [128]
   W4 [128][2], b4 [2]
@@ -23,7 +25,8 @@ from __future__ import annotations
 
 import numpy as np
 
-NIN, NIN_PAD, NH, NOUT = 5, 8, 128, 2
+NIN, NIN_PAD, NH, NOUT = 7, 8, 128, 2
+DF = 0.05  # scale of the predicted factor change
 SHAPES = [("W1", (NIN_PAD, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)),
           ("W3", (NH, NH)), ("b3", (NH,)), ("W4", (NH, NOUT)), ("b4", (NOUT,))]
 NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -131,11 +134,13 @@ def adam_step(theta, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def features(T, nu_center, kappa, dx, T_left):
+def features(T, nu_center, kappa, dx, T_left, f_prev, T_prev=None):
     """Closure inputs per (group g, cell i), sample index g * nx + i:
-    log T_i, log nu_g, log(kappa_g,i dx_i), log T_{i-1}, log T_{i+1}; the left
-    neighbour of cell 0 is the incoming Planck temperature when positive (else
-    T_0), the right neighbour of the last cell is the cell itself."""
+    log T_i, log nu_g, log(kappa_g,i dx_i), log T_{i-1}, log T_{i+1}, the
+    current factor f_g,i, and log(T_i / T_i^prev), the temperature change of
+    the last time step (0 without a previous step).  The left neighbour of
+    cell 0 is the incoming Planck temperature when positive (else T_0), the
+    right neighbour of the last cell is the cell itself."""
     T = np.asarray(T, dtype=np.float64)
     G, nx = kappa.shape
     Tl = np.concatenate([[T_left if T_left > 0 else T[0]], T[:-1]])
@@ -146,6 +151,8 @@ def features(T, nu_center, kappa, dx, T_left):
     f[:, :, 2] = np.log(kappa * np.asarray(dx)[None, :])
     f[:, :, 3] = np.log(Tl)[None, :]
     f[:, :, 4] = np.log(Tr)[None, :]
+    f[:, :, 5] = np.asarray(f_prev, dtype=np.float64).reshape(G, nx)
+    f[:, :, 6] = 0.0 if T_prev is None else np.log(T / np.asarray(T_prev, dtype=np.float64))[None, :]
     return f.reshape(G * nx, NIN)
 
 
@@ -153,13 +160,14 @@ def standardise(F, mean, std):
     return (np.asarray(F) - np.asarray(mean)[None, :]) / np.asarray(std)[None, :]
 
 
-def targets(f, E_new, E_prev, block, tiny=1e-290):
-    """Training targets per (g, i): (f_g,i, r_g,i) with r the log change of the
-    within-block spectral shape, r = log((E_g/E_p) / (E'_g/E'_p)), E_p the sum
-    over the `block` consecutive groups containing g; 0 where a share is not
-    above tiny; clipped to [-2, 2] (groups near underflow change their share by
-    orders of magnitude and would otherwise dominate the loss).
-    Arrays [G, nx] -> [G * nx, 2]."""
+def targets(f, f_prev, E_new, E_prev, block, tiny=1e-290):
+    """Training targets per (g, i): (s, r) with s = 1/2 + (f - f_prev) / (2 DF)
+    clipped to [0.01, 0.99] (the sigmoid value that reproduces the factor
+    change) and r the log change of the within-block spectral shape,
+    r = log((E_g/E_p) / (E'_g/E'_p)), E_p the sum over the `block` consecutive
+    groups containing g; 0 where a share is not above tiny; clipped to [-2, 2]
+    (groups near underflow change their share by orders of magnitude and would
+    otherwise dominate the loss).  Arrays [G, nx] -> [G * nx, 2]."""
     E_new = np.asarray(E_new, dtype=np.float64)
     E_prev = np.asarray(E_prev, dtype=np.float64)
     G, nx = E_new.shape
@@ -173,4 +181,15 @@ def targets(f, E_new, E_prev, block, tiny=1e-290):
             r[g] = np.where(ok, np.log(np.where(ok, (E_new[g] / np.where(ok, sn, 1)) /
                                                  (E_prev[g] / np.where(ok, sp, 1)), 1.0)), 0.0)
     r = np.clip(r, -2.0, 2.0)
-    return np.stack([np.asarray(f, dtype=np.float64).ravel(), r.ravel()], axis=1)
+    df = np.asarray(f, dtype=np.float64).ravel() - np.asarray(f_prev, dtype=np.float64).ravel()
+    s = np.clip(0.5 + df / (2.0 * DF), 0.01, 0.99)
+    return np.stack([s, r.ravel()], axis=1)
+
+
+def seed(f_prev, s_hat):
+    """Seeded factor f_prev + DF (2 s_hat - 1), kept only inside (0, 1)
+    (else f_prev); returns (factors, accepted mask)."""
+    f_prev = np.asarray(f_prev, dtype=np.float64)
+    cand = f_prev + DF * (2.0 * np.asarray(s_hat, dtype=np.float64) - 1.0)
+    ok = (cand > 0.0) & (cand < 1.0)
+    return np.where(ok, cand, f_prev), ok

@@ -117,8 +117,8 @@ def load():
     lib.tr_mlp_grad.argtypes = [vp, vp, vp, C.c_longlong, vp, vp, vp, vp]
     lib.tr_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp]
     lib.tr_mlp_train_epoch.argtypes = [vp, vp, vp, _ip, C.c_float, vp, vp, C.c_longlong, vp, C.c_int, vp, vp, vp]
-    lib.tr_mlp_features.argtypes = [vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
-    lib.tr_closure_targets.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+    lib.tr_mlp_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
+    lib.tr_closure_targets.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp]
     lib.tr_set_closure.argtypes = [vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
     lib.tr_autotune.argtypes = [vp, vp, vp, C.c_int, _ip, _dp, vp]
     lib.tr_set_tiles.argtypes = [vp, _ip]
@@ -377,13 +377,14 @@ class Mlp:
 
 
 def _solver_methods():
-    def mlp_features(self, T, kappa, mean, std, X):
-        _check(self.lib.tr_mlp_features(self._ctx, _ptr(T), _ptr(kappa), _f32(mean), _f32(std), _ptr(X),
-                                        self._stream()), "tr_mlp_features")
+    def mlp_features(self, T, T_prev, kappa, f, mean, std, X):
+        """Closure inputs (T_prev may be None: no temperature change)."""
+        _check(self.lib.tr_mlp_features(self._ctx, _ptr(T), _ptr(T_prev), _ptr(kappa), _ptr(f), _f32(mean),
+                                        _f32(std), _ptr(X), self._stream()), "tr_mlp_features")
 
-    def closure_targets(self, f, E_new, E_prev, block, Y):
-        _check(self.lib.tr_closure_targets(self._ctx, _ptr(f), _ptr(E_new), _ptr(E_prev), int(block), _ptr(Y),
-                                           self._stream()), "tr_closure_targets")
+    def closure_targets(self, f, f_prev, E_new, E_prev, block, Y):
+        _check(self.lib.tr_closure_targets(self._ctx, _ptr(f), _ptr(f_prev), _ptr(E_new), _ptr(E_prev), int(block),
+                                           _ptr(Y), self._stream()), "tr_closure_targets")
 
     def set_closure(self, mlp, mean=None, std=None):
         if mlp is None:

@@ -2,13 +2,14 @@
 on the GPU with the library's MFMA kernels.
 
 Samples are (group, cell) pairs.  Inputs: the closure features at the start
-of a time step (temperature profile T^{j-1}, group centre, optical depth of the
-cell at T^{j-1}).  Targets: the cell Eddington factor f^j the plain method
-converges to in that step, and the change of the within-block spectral shape
-over the step (blocks of the first coarse frequency grid).  A network trained
-this way predicts, at the start of a step, the factors the step will end with;
-the solver uses the prediction only to seed transport iteration s = 0, and the
-plain sweeps decide convergence.
+of a time step (temperature profile T^{j-1} and its neighbours, group centre,
+optical depth of the cell at T^{j-1}, the current factor f^{j-1} and the
+temperature change of the previous step).  Targets: the change of the cell
+Eddington factor over the step, f^j - f^{j-1}, as the sigmoid value
+1/2 + (f^j - f^{j-1}) / (2 DF), and the change of the within-block spectral
+shape (blocks of the first coarse frequency grid).  The solver adds the
+predicted change to f^{j-1} only to seed transport iteration s = 0; the plain
+sweeps decide convergence.
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ import numpy as np
 
 from . import binding
 
-NIN, NIN_PAD, NH, NOUT = 5, 8, 128, 2
+NIN, NIN_PAD, NH, NOUT = 7, 8, 128, 2
 
 
 def init_params(seed: int = 0) -> np.ndarray:
@@ -57,17 +58,20 @@ def generate(slab, cfg, levels: Sequence[int], nsteps: int, n_samples: int, seed
     block = max(1, slab.ng // levels[1]) if len(levels) > 2 else slab.ng
     xs, ys = [], []
     stats = (binding.TrStats * 1)()
+    T_hist = None
     for _ in range(nsteps):
         T0 = st["T"].clone()
         E0 = st["E"].clone()
+        f0 = st["f"].clone()
         sv.opacity(T0, kappa, B)
         X = torch.empty((n, NIN_PAD), dtype=torch.float32, device="cuda")
-        sv.mlp_features(T0, kappa, zero, one, X)
+        sv.mlp_features(T0, T_hist, kappa, f0, zero, one, X)
         sv.step(st, stats=stats)
         Y = torch.empty((n, NOUT), dtype=torch.float32, device="cuda")
-        sv.closure_targets(st["f"], st["E"], E0, block, Y)
+        sv.closure_targets(st["f"], f0, st["E"], E0, block, Y)
         xs.append(X)
         ys.append(Y)
+        T_hist = T0
     torch.cuda.synchronize()
     sv.close()
     Xa = torch.cat(xs).cpu().numpy()

@@ -92,6 +92,8 @@ struct tr_ctx {
   void *mlp_work = nullptr;
   long long mlp_chunk = 0;
   unsigned long long *d_seed_counts = nullptr;
+  double *T_hist = nullptr;  // temperature at the start of the previous closure step
+  int have_hist = 0;
 };
 
 namespace {
@@ -810,23 +812,23 @@ int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K
   return tr_set_tiles(c, K);
 }
 
-int tr_mlp_features(tr_ctx *c, const double *T, const double *kappa, const float *mean, const float *std, float *X,
-                    hipStream_t st) {
-  if (!c || !T || !kappa || !mean || !std || !X) return TR_EINVAL;
+int tr_mlp_features(tr_ctx *c, const double *T, const double *T_prev, const double *kappa, const double *f,
+                    const float *mean, const float *std, float *X, hipStream_t st) {
+  if (!c || !T || !kappa || !f || !mean || !std || !X) return TR_EINVAL;
   MlpStats ms;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < TR_MLP_NFEAT; ++k) {
     ms.mean[k] = mean[k];
     ms.std[k] = std[k];
     if (!(std[k] > 0)) return TR_EINVAL;
   }
-  launch_mlp_features(env_of(c, st), c->t_gi, T, kappa, ms, X);
+  launch_mlp_features(env_of(c, st), c->t_gi, T, T_prev, kappa, f, ms, X);
   return hip_err(hipGetLastError());
 }
 
-int tr_closure_targets(tr_ctx *c, const double *f, const double *E_new, const double *E_prev, int block, float *Y,
-                       hipStream_t st) {
-  if (!c || !f || !E_new || !E_prev || !Y || block < 1) return TR_EINVAL;
-  launch_closure_targets(env_of(c, st), c->t_gi, f, E_new, E_prev, block, Y);
+int tr_closure_targets(tr_ctx *c, const double *f, const double *f_prev, const double *E_new, const double *E_prev,
+                       int block, float *Y, hipStream_t st) {
+  if (!c || !f || !f_prev || !E_new || !E_prev || !Y || block < 1) return TR_EINVAL;
+  launch_closure_targets(env_of(c, st), c->t_gi, f, f_prev, E_new, E_prev, block, Y);
   return hip_err(hipGetLastError());
 }
 
@@ -856,7 +858,7 @@ int tr_set_closure(tr_ctx *c, const float *params, const float *mean, const floa
     return TR_OK;
   }
   if (!mean || !std) return TR_EINVAL;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < TR_MLP_NFEAT; ++k) {
     if (!(std[k] > 0)) return TR_EINVAL;
     c->mlp_stats.mean[k] = mean[k];
     c->mlp_stats.std[k] = std[k];
@@ -865,7 +867,7 @@ int tr_set_closure(tr_ctx *c, const float *params, const float *mean, const floa
     c->mlp_chunk = std::min<long long>(c->n_gi, 1LL << 20);
     int rc;
     if ((rc = dalloc(c, &c->mlp_X, 8 * c->n_gi)) || (rc = dalloc(c, &c->mlp_out, 2 * c->n_gi)) ||
-        (rc = dalloc(c, &c->d_seed_counts, 2)))
+        (rc = dalloc(c, &c->d_seed_counts, 2)) || (rc = dalloc(c, &c->T_hist, c->n_cell)))
       return rc;
     char *w = nullptr;
     if ((rc = dalloc(c, &w, (long long)tr_mlp_work_bytes(c->mlp_chunk)))) return rc;
@@ -879,6 +881,7 @@ int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
   if (!c || !s || !s->T || !s->I_out || !s->E || !s->F || !s->Ebnd || !s->f || !s->fbnd || !s->C || !s->Egrey ||
       !(T0 > 0))
     return TR_EINVAL;
+  c->have_hist = 0;  // a new run: no temperature history for the closure
   LaunchEnv env = env_of(c, st);
   launch_fill(env, s->T, T0, c->n_cell);
   launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, s->T, c->kappa, c->B, c->dSpart);
@@ -1050,7 +1053,12 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   if (c->mlp_params) {
     // learned closure: predicted cell factors replace the previous step's
     if (hipMemsetAsync(c->d_seed_counts, 0, 2 * sizeof(unsigned long long), gs) != hipSuccess) return TR_EHIP;
-    launch_mlp_features(env, c->t_gi, c->Tstar, c->kappa, c->mlp_stats, c->mlp_X);
+    // inputs at the step start: T^{j-1}, the previous step's T (after a
+    // first closure step), the current factors
+    launch_mlp_features(env, c->t_gi, c->Tstar, c->have_hist ? c->T_hist : nullptr, c->kappa, s->f, c->mlp_stats,
+                        c->mlp_X);
+    launch_copy(env, c->Tstar, c->T_hist, c->n_cell);
+    c->have_hist = 1;
     for (long long o = 0; o < c->n_gi; o += c->mlp_chunk) {
       const long long n = std::min(c->mlp_chunk, c->n_gi - o);
       int rc = tr_mlp_forward(c->mlp_params, c->mlp_X + 8 * o, n, c->mlp_out + 2 * o, c->mlp_work, gs);

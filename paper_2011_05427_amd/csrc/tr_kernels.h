@@ -103,13 +103,15 @@ void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
 void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,
                        double *F, double *Ebnd, double *mom, double *bnd);
 void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, double *out);
+#define TR_MLP_NFEAT 7   // closure inputs per sample (8 columns, the last zero)
+#define TR_MLP_DF 0.05   // scale of the predicted factor change per time step
 struct MlpStats {
-  double mean[5], std[5];
+  double mean[TR_MLP_NFEAT], std[TR_MLP_NFEAT];
 };
-void launch_mlp_features(const LaunchEnv &env, const Table &tab, const double *T, const double *kappa,
-                         const MlpStats &ms, float *X);
-void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double *f, const double *Enew,
-                            const double *Eprev, int blk, float *Y);
+void launch_mlp_features(const LaunchEnv &env, const Table &tab, const double *T, const double *Tprev,
+                         const double *kappa, const double *f, const MlpStats &ms, float *X);
+void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double *f, const double *fprev,
+                            const double *Enew, const double *Eprev, int blk, float *Y);
 // tab items = (slab, first (p, i) of 256) over the level's n_p nx cells.
 void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const double *Ec, const double *Eprev,
                     const float *r, double *Ef);

@@ -1228,8 +1228,9 @@ __global__ __launch_bounds__(256) void k_group_sum(const SlabDev *__restrict__ s
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mlp_features(const SlabDev *__restrict__ sd, ProbDev pd,
                                                       const Item *__restrict__ tab, const double *__restrict__ T,
-                                                      const double *__restrict__ kappa, MlpStats ms,
-                                                      float *__restrict__ X) {
+                                                      const double *__restrict__ Tprev,
+                                                      const double *__restrict__ kappa, const double *__restrict__ fc,
+                                                      MlpStats ms, float *__restrict__ X) {
   const Item it = tab[blockIdx.x];
   const SlabDev &S = sd[it.slab];
   const int nx = S.nx, ng = S.ng;
@@ -1240,20 +1241,28 @@ __global__ __launch_bounds__(256) void k_mlp_features(const SlabDev *__restrict_
   const double Ti = Tc[i];
   const double Tl = i > 0 ? Tc[i - 1] : (S.T_left > 0.0 ? S.T_left : Ti);
   const double Tr = i < nx - 1 ? Tc[i + 1] : Ti;
-  const double f[5] = {log(Ti), log(pd.nu_c[S.o_g + g]), log(kappa[S.o_gi + idx] * pd.dx[S.o_cell + i]), log(Tl),
-                       log(Tr)};
+  const double f[TR_MLP_NFEAT] = {log(Ti),
+                                  log(pd.nu_c[S.o_g + g]),
+                                  log(kappa[S.o_gi + idx] * pd.dx[S.o_cell + i]),
+                                  log(Tl),
+                                  log(Tr),
+                                  fc[S.o_gi + idx],
+                                  Tprev ? log(Ti / Tprev[S.o_cell + i]) : 0.0};
   float *x = X + (S.o_gi + idx) * 8;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) x[k] = (float)((f[k] - ms.mean[k]) / ms.std[k]);
-  x[5] = x[6] = x[7] = 0.0f;
+  for (int k = 0; k < TR_MLP_NFEAT; ++k) x[k] = (float)((f[k] - ms.mean[k]) / ms.std[k]);
+  x[7] = 0.0f;
 }
 
-// Training targets per (g, i): Y = (f_g,i, r_g,i) with r the log change of the
-// within-block spectral shape E_g / E_p between two fine solutions (blocks of
-// `blk` consecutive groups); 0 where a share is at or below TR_TINY; clipped to
+// Training targets per (g, i): Y = (s_g,i, r_g,i) with s = 1/2 + (f - f_prev) /
+// (2 DF) clipped to [0.01, 0.99] (the sigmoid value that reproduces the
+// factor change of the step) and r the log change of the within-block
+// spectral shape E_g / E_p between two fine solutions (blocks of `blk`
+// consecutive groups); 0 where a share is at or below TR_TINY; clipped to
 // [-2, 2] (shares near underflow move by orders of magnitude).
 __global__ __launch_bounds__(256) void k_closure_targets(const SlabDev *__restrict__ sd, const Item *__restrict__ tab,
-                                                         const double *__restrict__ f, const double *__restrict__ Enew,
+                                                         const double *__restrict__ f, const double *__restrict__ fprev,
+                                                         const double *__restrict__ Enew,
                                                          const double *__restrict__ Eprev, int blk,
                                                          float *__restrict__ Y) {
   const Item it = tab[blockIdx.x];
@@ -1272,7 +1281,8 @@ __global__ __launch_bounds__(256) void k_closure_targets(const SlabDev *__restri
   double r = 0.0;
   if (sn > TR_TINY && sp > TR_TINY && en > TR_TINY && ep > TR_TINY) r = log((en / sn) / (ep / sp));
   r = fmin(2.0, fmax(-2.0, r));
-  Y[2 * (S.o_gi + idx)] = (float)f[S.o_gi + idx];
+  const double sv = 0.5 + (f[S.o_gi + idx] - fprev[S.o_gi + idx]) / (2.0 * TR_MLP_DF);
+  Y[2 * (S.o_gi + idx)] = (float)fmin(0.99, fmax(0.01, sv));
   Y[2 * (S.o_gi + idx) + 1] = (float)r;
 }
 
@@ -1304,7 +1314,8 @@ __global__ __launch_bounds__(256) void k_prolong(const SlabDev *__restrict__ sd,
   }
 }
 
-// f <- fhat where 0 < fhat < 1 (counted), else the old factor stays (counted).
+// f <- f + DF (2 s_hat - 1) where the result lies in (0, 1) (counted), else
+// the old factor stays (counted).
 __global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, double *__restrict__ f, long long n,
                                                 unsigned long long *__restrict__ counts) {
   __shared__ unsigned int s_ok, s_bad;
@@ -1312,9 +1323,9 @@ __global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, d
   __syncthreads();
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    const float fh = out[2 * i];
-    if (fh > 0.0f && fh < 1.0f) {
-      f[i] = (double)fh;
+    const double cand = f[i] + TR_MLP_DF * (2.0 * (double)out[2 * i] - 1.0);
+    if (cand > 0.0 && cand < 1.0) {
+      f[i] = cand;
       atomicAdd(&s_ok, 1u);
     } else {
       atomicAdd(&s_bad, 1u);
@@ -1471,17 +1482,18 @@ void launch_group_sum(const LaunchEnv &env, const Table &tab, const double *E, d
   hipLaunchKernelGGL(k_group_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, E, out);
 }
 
-void launch_mlp_features(const LaunchEnv &env, const Table &tab, const double *T, const double *kappa,
-                         const MlpStats &ms, float *X) {
+void launch_mlp_features(const LaunchEnv &env, const Table &tab, const double *T, const double *Tprev,
+                         const double *kappa, const double *f, const MlpStats &ms, float *X) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_mlp_features, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, T, kappa, ms, X);
+  hipLaunchKernelGGL(k_mlp_features, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, T, Tprev, kappa,
+                     f, ms, X);
 }
 
-void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double *f, const double *Enew,
-                            const double *Eprev, int blk, float *Y) {
+void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double *f, const double *fprev,
+                            const double *Enew, const double *Eprev, int blk, float *Y) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_closure_targets, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, f, Enew, Eprev, blk,
-                     Y);
+  hipLaunchKernelGGL(k_closure_targets, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, f, fprev, Enew, Eprev,
+                     blk, Y);
 }
 
 void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const double *Ec, const double *Eprev,

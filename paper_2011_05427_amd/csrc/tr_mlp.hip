@@ -12,7 +12,7 @@
 
 namespace {
 
-constexpr int NH = 128, NINP = 8, NOUT = 2;
+constexpr int NH = 128, NINP = 8, NOUT = 2, NFEAT = 7;  // NFEAT of the NINP input columns are used
 // parameter vector offsets (float32): W1 [8][128], b1, W2 [128][128], b2, W3, b3, W4 [128][2], b4
 constexpr int OW1 = 0, OB1 = OW1 + NINP * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
               OB3 = OW3 + NH * NH, OW4 = OB3 + NH, OB4 = OW4 + NH * NOUT, NPARAM = OB4 + NOUT;
@@ -44,13 +44,19 @@ struct Gemm {
   long long mm;
   float *split;  // optional scratch [64][M][N]: long reductions are split over K
   int kc;        // split-K chunk length (set by gemm(); 0: the whole K)
+  int panels;    // k_gemm_rows: 32-row panels per wavefront (set by gemm())
 };
 
 // Epilogue of one output element.
-__device__ inline void gemm_store(const Gemm &g, int mm, int nn, float v) {
+__device__ inline float gemm_value(const Gemm &g, int mm, int nn, float v) {
   if (g.bias) v += g.bias[nn];
   if (g.relu) v = fmaxf(v, 0.0f);
   if (g.mask && g.mask[mm * g.mm + nn] == 0) v = 0.0f;
+  return v;
+}
+
+__device__ inline void gemm_store(const Gemm &g, int mm, int nn, float v) {
+  v = gemm_value(g, mm, nn, v);
   if (g.Cf) g.Cf[mm * g.cm + nn] = v;
   if (g.Cb) g.Cb[mm * g.cm + nn] = to_bf16(v);
 }
@@ -93,6 +99,106 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
       g.split[((long long)blockIdx.z * g.M + mm) * g.N + nn] = acc[j];
     else
       gemm_store(g, mm, nn, acc[j]);
+  }
+}
+
+// Row-panel GEMM for A contiguous in k (ak == 1) with K, N <= 128: the whole
+// B is staged once per block in LDS as B^T (k contiguous, rows padded to 136
+// bf16 against bank conflicts), each wavefront computes 32-row panels across
+// all N columns (up to four 32 x 32 accumulators), so every A fragment is one
+// 16-byte load reused for all column tiles.  Lane layout as in k_gemm.
+#define TR_GEMM_ROWS_LD 136
+__global__ __launch_bounds__(256) void k_gemm_rows(Gemm g) {
+  __shared__ uint16_t Bt[128 * TR_GEMM_ROWS_LD];
+  __shared__ uint16_t Pb[4][32 * 128];  // bf16 output panel of each wavefront
+  const int Kp = (g.K + 15) & ~15;
+  // consecutive threads read consecutive n (row-major B: 8 at a time, 16 B),
+  // then write the transposed elements; k in [K, Kp) is zero
+  if (g.bn == 1 && (g.N & 7) == 0 && (g.bk & 7) == 0) {
+    const int n8 = g.N >> 3;
+    for (int idx = threadIdx.x; idx < n8 * Kp; idx += 256) {
+      const int k = idx / n8, n = 8 * (idx - k * n8);
+      bf16x8 v;
+      if (k < g.K)
+        v = *reinterpret_cast<const bf16x8 *>(g.B + (long long)k * g.bk + n);
+      else
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Bt[(n + q) * TR_GEMM_ROWS_LD + k] = (uint16_t)v[q];
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < g.N * Kp; idx += 256) {
+      const int k = idx / g.N, n = idx - k * g.N;
+      Bt[n * TR_GEMM_ROWS_LD + k] = (k < g.K) ? g.B[k * g.bk + n * g.bn] : (uint16_t)0;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int ntile = (g.N + 31) >> 5;
+  for (int pnl = 0; pnl < g.panels; ++pnl) {
+    const int m0 = ((blockIdx.x * g.panels + pnl) * 4 + wv) * 32;
+    if (m0 >= g.M) break;
+    const int m = m0 + r;
+    f32x16 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+    for (int k0 = 0; k0 < Kp; k0 += 16) {
+      const int kk = k0 + 8 * h;
+      bf16x8 a;
+      if (m < g.M && kk + 8 <= g.K) {
+        a = *reinterpret_cast<const bf16x8 *>(g.A + (long long)m * g.am + kk);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = (m < g.M && kk + i < g.K) ? (short)g.A[(long long)m * g.am + kk + i] : (short)0;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < ntile) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt + (t * 32 + r) * TR_GEMM_ROWS_LD + kk);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+    // bf16 output rows with a width of a multiple of 8 go through the
+    // wavefront's LDS panel and leave as contiguous 16-byte row pieces
+    const bool panel = g.Cb && (g.N & 7) == 0 && g.cm == g.N;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int nn = t * 32 + r;
+      if (t >= ntile || nn >= g.N) continue;
+      const float bias = g.bias ? g.bias[nn] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int rr = 8 * (j >> 2) + 4 * h + (j & 3);
+        const int mm = m0 + rr;
+        if (mm >= g.M) continue;
+        float v = acc[t][j] + bias;
+        if (g.relu) v = fmaxf(v, 0.0f);
+        if (g.mask && g.mask[mm * g.mm + nn] == 0) v = 0.0f;
+        if (g.Cf) g.Cf[mm * g.cm + nn] = v;
+        if (panel)
+          Pb[wv][rr * g.N + nn] = to_bf16(v);
+        else if (g.Cb)
+          g.Cb[mm * g.cm + nn] = to_bf16(v);
+      }
+    }
+    if (panel) {
+      // the panel is written and read by this wavefront only
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const int pieces = g.N / 8;  // 16-byte pieces per row
+      for (int q = lane; q < 32 * pieces; q += 64) {
+        const int rr = q / pieces, c8 = q - rr * pieces;
+        if (m0 + rr < g.M)
+          *reinterpret_cast<bf16x8 *>(g.Cb + (long long)(m0 + rr) * g.cm + 8 * c8) =
+              *reinterpret_cast<const bf16x8 *>(&Pb[wv][rr * g.N + 8 * c8]);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
   }
 }
 
@@ -283,7 +389,14 @@ void gemm(const Gemm &g0, hipStream_t st) {
   }
   if (nz == 1) {
     g.kc = 0;
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+    if (g.ak == 1 && g.K <= 128 && g.N <= 128) {
+      // enough panels per block to amortise staging B, while keeping >= 512 blocks
+      g.panels = std::max(1, std::min(32, g.M / (128 * 512)));
+      const int rows = 4 * 32 * g.panels;
+      hipLaunchKernelGGL(k_gemm_rows, dim3((unsigned)((g.M + rows - 1) / rows)), dim3(256), 0, st, g);
+    } else {
+      hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+    }
     return;
   }
   grid.z = nz;
@@ -312,7 +425,7 @@ void forward(const float *params, const float *X, long long n, const Work &w, hi
   const int tb = 256;
   hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((NPARAM + tb - 1) / tb)), dim3(tb), 0, st, params, 1LL, 1, w.Wb,
                      1LL, (long long)NPARAM);
-  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * NINP + tb - 1) / tb)), dim3(tb), 0, st, X, (long long)NINP, 5,
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * NINP + tb - 1) / tb)), dim3(tb), 0, st, X, (long long)NINP, NFEAT,
                      w.Xb, (long long)NINP, n);
   const uint16_t *W1 = w.Wb + OW1, *W2 = w.Wb + OW2, *W3 = w.Wb + OW3, *W4 = w.Wb + OW4;
   Gemm g = gemm_nn(w.Xb, NINP, 1, W1, NH, 1, (int)n, NH, NINP);

@@ -29,7 +29,7 @@ def _cos(a, b):
 def _data(n, seed):
     rng = np.random.default_rng(seed)
     X = np.zeros((n, 8))
-    X[:, :5] = rng.normal(0, 1, (n, 5))
+    X[:, :mlp.NIN] = rng.normal(0, 1, (n, mlp.NIN))
     Y = np.stack([rng.uniform(0.2, 0.6, n), rng.normal(0, 0.2, n)], axis=1)
     return X, Y
 
@@ -41,7 +41,7 @@ def test_forward_matches_reference(n):
     X, _ = _data(n, n)
     net = binding.Mlp(theta)
     out = to_np(net.forward(_f32(X))).reshape(n, 2)
-    ref, _ = mlp.forward(theta, X[:, :5], bf16=True)
+    ref, _ = mlp.forward(theta, X[:, :mlp.NIN], bf16=True)
     assert rel_err(out, ref) < 1e-2
     assert _cos(out[:, 1], ref[:, 1]) > 0.9999 or n == 1
     assert np.max(np.abs(out[:, 0] - ref[:, 0])) < 1e-2
@@ -55,7 +55,7 @@ def test_gradients_match_reference(n):
     net = binding.Mlp(theta)
     g, loss = net.grad(_f32(X), _f32(Y))
     g = to_np(g).astype(np.float64)
-    lref, gref = mlp.loss_and_grad(theta, X[:, :5], Y, bf16=True)
+    lref, gref = mlp.loss_and_grad(theta, X[:, :mlp.NIN], Y, bf16=True)
     assert abs(float(to_np(loss)[0]) - lref) <= 1e-3 * lref
     o = 0
     for name, shp in mlp.SHAPES:
@@ -87,20 +87,24 @@ def test_features_and_targets_match_reference():
     sv = binding.Solver([slab], [levels], inputs.SolverCfg(levels=levels))
     rng = np.random.default_rng(2)
     T = 10 ** rng.uniform(-3, 0, slab.nx)
+    Tp = T * rng.uniform(0.7, 1.3, slab.nx)
     kap = planck.opacity(slab.nu_center, slab.C_cell, T)
-    mean, std = rng.normal(0, 1, 5), rng.uniform(0.5, 2, 5)
-    X = sv.empty(binding.TR_K_GI, 8).float()
-    sv.mlp_features(to_dev(T), to_dev(kap), mean, std, X)
-    ref = mlp.standardise(mlp.features(T, slab.nu_center, kap, np.diff(slab.x_edges), slab.T_left), mean, std)
-    got = to_np(X).reshape(-1, 8)
-    np.testing.assert_allclose(got[:, :5], ref, rtol=1e-5, atol=1e-5)
-    assert np.all(got[:, 5:] == 0)
-    f = rng.uniform(0.2, 0.6, (24, slab.nx))
+    fp = rng.uniform(0.2, 0.6, (24, slab.nx))
+    mean, std = rng.normal(0, 1, mlp.NIN), rng.uniform(0.5, 2, mlp.NIN)
+    for T_prev in (None, Tp):
+        X = sv.empty(binding.TR_K_GI, 8).float()
+        sv.mlp_features(to_dev(T), None if T_prev is None else to_dev(T_prev), to_dev(kap), to_dev(fp), mean, std, X)
+        ref = mlp.standardise(mlp.features(T, slab.nu_center, kap, np.diff(slab.x_edges), slab.T_left, fp, T_prev),
+                              mean, std)
+        got = to_np(X).reshape(-1, 8)
+        np.testing.assert_allclose(got[:, :mlp.NIN], ref, rtol=1e-5, atol=1e-5)
+        assert np.all(got[:, mlp.NIN:] == 0)
+    f = fp + rng.uniform(-0.08, 0.08, (24, slab.nx))
     En = 10 ** rng.uniform(-5, 0, (24, slab.nx))
     Ep = 10 ** rng.uniform(-5, 0, (24, slab.nx))
     Y = sv.empty(binding.TR_K_GI, 2).float()
-    sv.closure_targets(to_dev(f), to_dev(En), to_dev(Ep), 4, Y)
-    np.testing.assert_allclose(to_np(Y).reshape(-1, 2), mlp.targets(f, En, Ep, 4), rtol=2e-6, atol=1e-6)
+    sv.closure_targets(to_dev(f), to_dev(fp), to_dev(En), to_dev(Ep), 4, Y)
+    np.testing.assert_allclose(to_np(Y).reshape(-1, 2), mlp.targets(f, fp, En, Ep, 4), rtol=2e-6, atol=1e-6)
     sv.close()
 
 

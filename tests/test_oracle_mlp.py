@@ -67,3 +67,38 @@ def test_sigmoid_output_in_unit_interval():
     X, _ = _batch(64)
     out, _ = mlp.forward(theta, X)
     assert np.all((out[:, 0] > 0) & (out[:, 0] < 1))
+
+
+def test_residual_targets_and_seed_round_trip():
+    """The factor-change target and the seeding rule invert each other inside
+    the representable range, and an unchanged factor maps to s = 1/2."""
+    rng = np.random.default_rng(9)
+    G, nx = 6, 5
+    fp = rng.uniform(0.2, 0.8, (G, nx))
+    f = fp + rng.uniform(-0.9, 0.9, (G, nx)) * mlp.DF
+    E = 10 ** rng.uniform(-3, 0, (G, nx))
+    Y = mlp.targets(f, fp, E, E, 3)
+    got, ok = mlp.seed(fp.ravel(), Y[:, 0])
+    assert ok.all()
+    np.testing.assert_allclose(got, f.ravel(), rtol=0, atol=1e-14)
+    Y0 = mlp.targets(fp, fp, E, E, 3)
+    assert np.all(Y0[:, 0] == 0.5) and np.all(Y0[:, 1] == 0.0)
+    # a change beyond the range saturates; a seed outside (0, 1) keeps the old factor
+    Yc = mlp.targets(fp + 3 * mlp.DF, fp, E, E, 3)
+    assert np.all(Yc[:, 0] == 0.99)
+    s, ok = mlp.seed(np.array([0.01, 0.5]), np.array([0.0, 1.0]))
+    assert not ok[0] and ok[1] and s[0] == 0.01 and abs(s[1] - 0.55) < 1e-15
+
+
+def test_features_temperature_change_column():
+    rng = np.random.default_rng(4)
+    G, nx = 3, 4
+    T = 10 ** rng.uniform(-2, 0, nx)
+    Tp = T * rng.uniform(0.5, 1.5, nx)
+    kap = 10 ** rng.uniform(-1, 2, (G, nx))
+    fp = rng.uniform(0.3, 0.6, (G, nx))
+    F = mlp.features(T, np.array([0.1, 1.0, 10.0]), kap, np.full(nx, 0.5), 1.0, fp, Tp).reshape(G, nx, mlp.NIN)
+    np.testing.assert_allclose(F[:, :, 6], np.log(T / Tp)[None, :].repeat(G, 0), rtol=1e-15)
+    np.testing.assert_array_equal(F[:, :, 5], fp)
+    F0 = mlp.features(T, np.array([0.1, 1.0, 10.0]), kap, np.full(nx, 0.5), 1.0, fp).reshape(G, nx, mlp.NIN)
+    assert np.all(F0[:, :, 6] == 0.0)
