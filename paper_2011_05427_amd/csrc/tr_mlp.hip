@@ -202,6 +202,122 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Gemm g) {
   }
 }
 
+// Fused inference: all four layers of the network for panels of 32 samples
+// per wavefront, the weights staged once per block in LDS as bf16 B^T
+// (W1 with K padded from 8 to 16, W4 with N padded from 2 to 32), the
+// activations of a panel kept in a per-wavefront LDS panel between layers.
+// The rounding points and the order of the MFMA accumulation are those of
+// the layer-by-layer kernels (fp32 bias + ReLU, then bf16), so the outputs
+// are identical to forward() + k_head.  Block = 8 wavefronts (two per SIMD),
+// one block per CU: 153 KB of LDS (gfx950).
+#define TR_FUSED_LD 136
+#define TR_FUSED_WAVES 8
+__global__ __launch_bounds__(64 * TR_FUSED_WAVES) void k_mlp_fused(const float *__restrict__ params, const float *__restrict__ X,
+                                                   long long n, float *__restrict__ out) {
+  __shared__ uint16_t W1t[NH * 24];
+  __shared__ uint16_t W2t[NH * TR_FUSED_LD];
+  __shared__ uint16_t W3t[NH * TR_FUSED_LD];
+  __shared__ uint16_t W4t[32 * TR_FUSED_LD];
+  __shared__ float bias[3 * NH + NOUT];
+  __shared__ uint16_t Pn[TR_FUSED_WAVES][32 * TR_FUSED_LD];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < NH * 24; i += nt) {
+    const int nn = i / 24, k = i - nn * 24;
+    W1t[i] = k < NINP ? to_bf16(params[OW1 + k * NH + nn]) : (uint16_t)0;
+  }
+  for (int i = tid; i < NH * NH; i += nt) {
+    const int k = i / NH, nn = i - k * NH;  // coalesced reads along n
+    W2t[nn * TR_FUSED_LD + k] = to_bf16(params[OW2 + i]);
+    W3t[nn * TR_FUSED_LD + k] = to_bf16(params[OW3 + i]);
+  }
+  for (int i = tid; i < 32 * NH; i += nt) {
+    const int nn = i / NH, k = i - nn * NH;
+    W4t[nn * TR_FUSED_LD + k] = nn < NOUT ? to_bf16(params[OW4 + k * NOUT + nn]) : (uint16_t)0;
+  }
+  for (int i = tid; i < NH; i += nt) {
+    bias[i] = params[OB1 + i];
+    bias[NH + i] = params[OB2 + i];
+    bias[2 * NH + i] = params[OB3 + i];
+  }
+  if (tid < NOUT) bias[3 * NH + tid] = params[OB4 + tid];
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  uint16_t *P = Pn[wv];
+  const long long npanel = (n + 31) / 32;
+  for (long long pnl = (long long)blockIdx.x * TR_FUSED_WAVES + wv; pnl < npanel;
+       pnl += (long long)gridDim.x * TR_FUSED_WAVES) {
+    const long long m0 = pnl * 32;
+    const long long m = m0 + r;
+    f32x16 acc[4];
+    // layer 1: K = 8 (second half of the 16-wide k step is zero)
+    bf16x8 a;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = (h == 0 && m < n && i < NFEAT) ? (short)to_bf16(X[m * NINP + i]) : (short)0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(W1t + (t * 32 + r) * 24 + 8 * h);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+    }
+    // hidden layers: bias + ReLU -> bf16 panel -> next product
+#pragma unroll
+    for (int layer = 0; layer < 3; ++layer) {
+      const float *bl = bias + layer * NH;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float bv = bl[t * 32 + r];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int rr = 8 * (j >> 2) + 4 * h + (j & 3);
+          P[rr * TR_FUSED_LD + t * 32 + r] = to_bf16(fmaxf(acc[t][j] + bv, 0.0f));
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      bf16x8 af[8];
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) af[ks] = *reinterpret_cast<const bf16x8 *>(P + r * TR_FUSED_LD + ks * 16 + 8 * h);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      if (layer < 2) {
+        const uint16_t *Wt = layer == 0 ? W2t : W3t;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Wt + (t * 32 + r) * TR_FUSED_LD + ks * 16 + 8 * h);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks], b, acc[t], 0, 0, 0);
+          }
+        }
+      } else {
+        // output layer: one 32-wide tile, columns 0 and 1 are the outputs
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[0][j] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8 *>(W4t + r * TR_FUSED_LD + ks * 16 + 8 * h);
+          acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks], b, acc[0], 0, 0, 0);
+        }
+        if (r < NOUT) {
+          const float bv = bias[3 * NH + r];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const long long mm = m0 + 8 * (j >> 2) + 4 * h + (j & 3);
+            if (mm < n) {
+              const float o = acc[0][j] + bv;
+              out[2 * mm + r] = r == 0 ? 1.0f / (1.0f + expf(-o)) : o;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Split-K reduction: element (m, n) adds the nz partial tiles in order, then
 // applies the epilogue.
 __global__ __launch_bounds__(256) void k_gemm_reduce(Gemm g, int nz) {
@@ -522,9 +638,11 @@ size_t tr_mlp_work_bytes(long long n) { return work_bytes(n); }
 
 int tr_mlp_forward(const float *params, const float *X, long long n, float *out, void *work, hipStream_t st) {
   if (!params || !X || !out || !work || n <= 0) return TR_EINVAL;
-  const Work w = carve(work, n);
-  forward(params, X, n, w, st);
-  hipLaunchKernelGGL(k_head, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.O, out, (int)n);
+  // fused inference: at most one block per CU (the weights are staged once
+  // per block), wavefronts loop over the 32-sample panels
+  const long long npanel = (n + 31) / 32;
+  const unsigned nb = (unsigned)std::min<long long>(256, (npanel + TR_FUSED_WAVES - 1) / TR_FUSED_WAVES);
+  hipLaunchKernelGGL(k_mlp_fused, dim3(nb), dim3(64 * TR_FUSED_WAVES), 0, st, params, X, n, out);
   return hipGetLastError() == hipSuccess ? TR_OK : TR_EHIP;
 }
 
