@@ -52,8 +52,7 @@ struct tr_ctx {
   } lev[TR_MAXLEV]{};
   Ctl *d_ctl = nullptr;
   int *d_cost = nullptr;
-  int *d_count = nullptr;
-  int *h_count = nullptr;  // pinned
+  int *h_count = nullptr;  // pinned, coherent: active slabs after a transport iteration
   // work tables
   Table t_opac{}, t_dS{}, t_cell{}, t_gi{}, t_g{}, t_grey{};
   // sweep work per slab-size bucket (nx <= 64, 128, 256, 512, 1024, more),
@@ -304,7 +303,16 @@ LoSol level_sol(const tr_ctx *c, int l) {
 
 LoOut level_out(const tr_ctx *c, int l) {
   const auto &L = c->lev[l];
-  return LoOut{L.sigE, L.emis, L.a, L.b, L.sigR, L.C, L.Phi, L.Eold, L.Fold, L.Esum};
+  return LoOut{L.sigE, L.emis, L.a, L.b, L.sigR, L.C, L.Phi, L.Eold, L.Fold, L.Esum, nullptr, nullptr};
+}
+
+// Grey-level output of a restriction inside a step: it also reduces the dS
+// chunk partials of the current opacity tables for the grey solve.
+LoOut grey_out(const tr_ctx *c) {
+  LoOut o = level_out(c, c->nlev - 1);
+  o.dSpart = c->dSpart;
+  o.dS = c->dS;
+  return o;
 }
 
 LoIn coeffs_in(const tr_lo_coeffs *in) {
@@ -542,9 +550,11 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     for (double **p : p2)
       if ((rc = dalloc(c, p, c->n_lp2[l]))) return fail(rc);
   }
-  if ((rc = dalloc(c, &c->d_ctl, n_slab)) || (rc = dalloc(c, &c->d_cost, n_slab)) || (rc = dalloc(c, &c->d_count, 1)))
+  if ((rc = dalloc(c, &c->d_ctl, n_slab)) || (rc = dalloc(c, &c->d_cost, n_slab)))
     return fail(rc);
-  if (hipHostMalloc((void **)&c->h_count, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(TR_ENOMEM);
+  // the active-slab count is written by the GPU straight into coherent pinned
+  // host memory (read after the synchronisation of every transport iteration)
+  if (hipHostMalloc((void **)&c->h_count, sizeof(int), hipHostMallocCoherent) != hipSuccess) return fail(TR_ENOMEM);
   if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -942,7 +952,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     {
       TimedScope ts(c, st, TR_T_RESTRICT, l);
       launch_restrict(env, c->t_red[std::make_pair(0, gl)], c->d_ctl, PRED_CYCLE, l, 0, gl, fine, fsol,
-                      level_out(c, gl), c->red);
+                      grey_out(c), c->red);
     }
     ga.end_cycle = nsch == 0;
     {
@@ -954,7 +964,6 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       {
         TimedScope ts(c, st, TR_T_OPACITY, l);
         launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
-        launch_dS_sum(env, c->t_dS, c->d_ctl, PRED_CYCLE, l, c->dSpart, c->dS);
       }
       {
         TimedScope ts(c, st, TR_T_RESTRICT, l);
@@ -968,7 +977,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       {
         TimedScope ts(c, st, TR_T_RESTRICT, l);
         launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
-                        level_sol(c, gm), level_out(c, gl), c->red);
+                        level_sol(c, gm), grey_out(c), c->red);
       }
       ga.end_cycle = q == nsch - 1;
       {
@@ -979,12 +988,11 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     {
       TimedScope ts(c, st, TR_T_OPACITY, l);
       launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
-      launch_dS_sum(env, c->t_dS, c->d_ctl, PRED_DONECYC, l + 1, c->dSpart, c->dS);
     }
   }
   // start of the next transport iteration (s + 1) for slabs still iterating
   launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
-  launch_count_active(env, c->d_ctl, ns, c->d_count);
+  launch_count_active(env, c->d_ctl, ns, c->h_count);
 }
 
 int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, bool sweep_outside,
@@ -1048,7 +1056,6 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   launch_copy(env, s->F, c->Fold, c->n_ge);
   launch_phi(env, c->t_g, s->C, c->Phi);
   launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
-  launch_dS_sum(env, c->t_dS, nullptr, PRED_ALL, 0, c->dSpart, c->dS);
   unsigned long long seed_counts[2] = {0, 0};
   if (c->mlp_params) {
     // learned closure: predicted cell factors replace the previous step's
@@ -1114,7 +1121,6 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
     } else {
       enqueue_iteration(c, s, gs, Lmax, outer > 0, true);
     }
-    if (hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, gs) != hipSuccess) return TR_EHIP;
     if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
     if (outer > 0 && sweep_ev) sweep_time(c, t_ms, n_launch);
     if (c->cfg.timing) {
@@ -1124,7 +1130,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       tim_collect(c, s0 < TR_MAXOUT ? k0.cycles[s0] : 0, t_ms, n_launch);
       s0 = k0.s;
     }
-    if (*c->h_count == 0) break;
+    if (*static_cast<volatile int *>(c->h_count) == 0) break;
   }
   launch_copy(env, c->Tstar, s->T, c->n_cell);
   if (c->mlp_params &&

@@ -56,9 +56,11 @@ struct EdgeQ {
   int is_tail;
 };
 
-__device__ inline EdgeQ edge_q(double nu, double T) {
+// inv_T = 1 / T (one reciprocal per cell, shared by its edges).  In the tail
+// range 1 - e^{-x} >= 0.86 is computed directly (no cancellation).
+__device__ inline EdgeQ edge_q(double nu, double inv_T) {
   EdgeQ e;
-  double x = nu / T;
+  double x = nu * inv_T;
   e.x = x;
   if (nu == 0.0) {
     e.head = 0.0; e.tail = 0.0; e.g4 = 0.0; e.is_tail = 0;
@@ -72,7 +74,7 @@ __device__ inline EdgeQ edge_q(double nu, double T) {
     double ex = exp(-x);
     e.head = 0.0; e.tail = q_tail(x, ex); e.is_tail = 1;
     double x2 = x * x;
-    e.g4 = (ex > 0.0) ? x2 * x2 * ex / (-expm1(-x)) : 0.0;
+    e.g4 = (ex > 0.0) ? x2 * x2 * ex / (1.0 - ex) : 0.0;
   }
   return e;
 }

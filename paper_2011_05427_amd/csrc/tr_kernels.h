@@ -21,6 +21,10 @@ struct LoSol {
 
 struct LoOut {
   double *sigE, *emis, *a, *b, *sigR, *C, *Phi, *Eold, *Fold, *Esum;
+  // restriction to the grey level in a step: also reduce the 64-group chunk
+  // partials of dS into the cell array (both null otherwise)
+  const double *dSpart;
+  double *dS;
 };
 
 struct GreyArgs {

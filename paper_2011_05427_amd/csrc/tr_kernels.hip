@@ -63,22 +63,27 @@ __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd,
   if (i < nx && g0 < ng) {
     const double Ti = T[S.o_cell + i];
     const double Cc = pd.Ccell[S.o_cell + i];
+    const double iT = 1.0 / Ti;
     const double T2 = Ti * Ti;
     const double scale = S.aR * S.c * T2 * T2 * 0.5 / TR_PI4_15;
     const double *nue = pd.nu_e + S.o_nu;
     const double *nuc = pd.nu_c + S.o_g;
-    EdgeQ lo = edge_q(nue[g0], Ti);
+    EdgeQ lo = edge_q(nue[g0], iT);
 #pragma unroll
     for (int q = 0; q < RUN; ++q) {
       const int g = g0 + q;
       if (g >= g1) break;
-      const EdgeQ hi = edge_q(nue[g + 1], Ti);
+      const EdgeQ hi = edge_q(nue[g + 1], iT);
       const double Bg = scale * q_interval(lo, hi);
-      const double dBg = 4.0 * Bg / Ti - scale / Ti * (hi.g4 - lo.g4);
+      const double dBg = (4.0 * Bg - scale * (hi.g4 - lo.g4)) * iT;
       const double nu = nuc[g];
-      const double y = nu / Ti;
-      const double kap = Cc / (nu * nu * nu) * (-expm1(-y));
-      const double dkap = -Cc / (nu * nu) * exp(-y) / T2;
+      const double y = nu * iT;
+      // 1 - e^{-y} from the same exponential unless y is small (cancellation)
+      const double ey = exp(-y);
+      const double om = y > 0.5 ? 1.0 - ey : -expm1(-y);
+      const double cn = Cc / (nu * nu);
+      const double kap = cn / nu * om;
+      const double dkap = -cn * ey * iT * iT;
       const long long o = S.o_gi + (long long)g * nx + i;
       kappa[o] = kap;
       B[o] = Bg;
@@ -750,9 +755,29 @@ __device__ inline void accumulate(const SrcView &s, int e, double (&r)[R_N]) {
 }
 
 // Final coefficients of coarse group p at edge e from the block sums.
+// dS of cell i from the chunk partials, for the grey restriction: eight
+// interleaved partial sums (chunks q = k mod 8) keep eight loads in flight and
+// are combined in a fixed order.
+__device__ inline void finalize_dS(const SlabDev &S, int i, const LoOut &o) {
+  if (!o.dS || i >= S.nx) return;
+  const double *row = o.dSpart + S.o_chunk + i;
+  const long long nx = S.nx;
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  int q = 0;
+  for (; q + 8 <= S.nchunk; q += 8) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += row[(q + k) * nx];
+  }
+  for (int k = 0; q + k < S.nchunk; ++k) acc[k] += row[(q + k) * nx];
+  o.dS[S.o_cell + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int e, int r, const double (&s)[R_N],
                                 const LoOut &o) {
   const int nx = S.nx;
+  if (p == 0) finalize_dS(S, e, o);
   const double rinv = 1.0 / r;
   const double c = S.c;
   const long long pi = S.o_lpi[to] + (long long)p * nx;
