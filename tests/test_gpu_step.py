@@ -61,7 +61,8 @@ def _compare_state(tag, sv, st, ref, slab_idx=0):
     assert_close(f"{tag} C", C, ref.fac.C, TOL)
 
 
-@pytest.mark.parametrize("case", ["small_V", "W3", "F4", "vacuum_both"])
+@pytest.mark.parametrize("case", ["small_V", "W3", "F4", "vacuum_both", "two_cells_S2", "max_cells",
+                                  "thin", "thick"])
 def test_step_replay(case):
     if case == "small_V":
         slabs, cfg, nsteps = inputs.config_small()
@@ -77,10 +78,30 @@ def test_step_replay(case):
         levels = [64, 16, 4, 1]
         cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_F, lmax=2)
         nsteps = 2
-    else:
+    elif case == "vacuum_both":
         slab = inputs.make_slab(20, 8, 4, T_left=0.0, T_right=0.0, T0=0.05)
         levels = [8, 1]
         cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_V, lmax=3)
+        nsteps = 2
+    elif case == "two_cells_S2":  # smallest slab, two groups, two directions
+        slab = inputs.make_slab(2, 2, 2)
+        levels = [2, 1]
+        cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_V, lmax=4)
+        nsteps = 2
+    elif case == "max_cells":  # the largest slab the LO block solver takes (2046 cells)
+        slab = inputs.make_slab(2046, 4, 2)
+        levels = [4, 1]
+        cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_V, lmax=4)
+        nsteps = 1
+    elif case == "thin":  # optically thin everywhere
+        slab = inputs.make_slab(30, 16, 8, C1=0.01, C2=0.001)
+        levels = [16, 4, 1]
+        cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_W, lmax=2)
+        nsteps = 2
+    else:  # optically thick everywhere (diffusive, near-isotropic factors)
+        slab = inputs.make_slab(30, 16, 8, C1=3.0e4, C2=1.0e4)
+        levels = [16, 4, 1]
+        cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_W, lmax=2)
         nsteps = 2
     note(f"step replay {case} nx={slab.nx} ng={slab.ng} nmu={slab.nmu} levels={levels}")
     states, stats = _oracle_run(slab, cfg, levels, nsteps)
