@@ -171,7 +171,7 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
     const int ne = S.nx + 1;
     const int nf = S.lev_ng[from], nt = S.lev_ng[to];
     const int r = nf / nt;
-    const int cpb = restrict_cpb(r, nt, ne);
+    const int cpb = restrict_cpb(r, nt, ne, S.rtarget);
     if (cpb == 1) {
       for (int st = 0; st < nt * ne; st += 256) single.push_back({s, st});
     } else {
@@ -424,6 +424,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     S.nsched = (int)c->sched.size();
     for (size_t q = 0; q < c->sched.size(); ++q) S.sched[q] = c->sched[q];
     S.nchunk = (P.ng + 63) / 64;
+    S.rtarget = std::max(16, 4096 / n_slab);
     S.cv = P.cv;
     S.dt = P.dt;
     S.c = P.c;
@@ -473,7 +474,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       for (int a = 0; a < nlev; ++a)
         for (int b = a + 1; b < nlev; ++b) {
           const int r = P.level_ng[a] / P.level_ng[b];
-          const int cpb = restrict_cpb(r, P.level_ng[b], P.nx + 1);
+          const int cpb = restrict_cpb(r, P.level_ng[b], P.nx + 1, S.rtarget);
           if (cpb > 1) worst = std::max(worst, (long long)P.level_ng[b] * cpb);
         }
       c->n_red += worst * (P.nx + 1) * 21;

@@ -15,6 +15,7 @@ struct SlabDev {
   int nsched;
   int sched[TR_MAXLEV];  // level indices visited after each grey solve
   int nchunk;            // 64-group chunks of the fine grid (opacity partials)
+  int rtarget;           // restriction chunk pass: blocks aimed at per slab
   double cv, dt, c, aR, inv_cdt;
   double wpos, wmupos, wmu2pos;  // half-range quadrature sums over mu > 0
   double wneg, wmuneg, wmu2neg;  // over mu < 0 (wmuneg < 0)

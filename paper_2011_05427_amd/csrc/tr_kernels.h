@@ -77,19 +77,20 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
 // larger r in a chunk pass plus a final pass over blocks of TR_RFIN_E edges.
 // In the chunk pass a block of 4 wavefronts covers 64 edges and 4 rcw finer
 // groups (rcw per wavefront), giving cpb chunk records per coarse group.  rcw
-// grows (fewer records to write and re-read) while the pass keeps at least
-// 4096 blocks, and so that cpb <= 64.
+// grows (fewer records to write and re-read) while a slab's pass keeps at
+// least `target` blocks (4096 over the slabs of a context), and so that
+// cpb <= 64.
 #define TR_RFIN_E 12
-__host__ __device__ inline int restrict_rcw(int r, int nto, int ne) {
+__host__ __device__ inline int restrict_rcw(int r, int nto, int ne, int target) {
   const int ntile = (ne + 63) / 64;
   int rcw = 1;
-  while (rcw < 32 && 4 * rcw < r && (long long)nto * ((r + 8 * rcw - 1) / (8 * rcw)) * ntile >= 4096) rcw *= 2;
+  while (rcw < 32 && 4 * rcw < r && (long long)nto * ((r + 8 * rcw - 1) / (8 * rcw)) * ntile >= target) rcw *= 2;
   while ((r + 4 * rcw - 1) / (4 * rcw) > 64) rcw *= 2;
   return rcw;
 }
-__host__ __device__ inline int restrict_cpb(int r, int nto, int ne) {
+__host__ __device__ inline int restrict_cpb(int r, int nto, int ne, int target) {
   if (r <= 16) return 1;
-  const int rcw = restrict_rcw(r, nto, ne);
+  const int rcw = restrict_rcw(r, nto, ne, target);
   return (r + 4 * rcw - 1) / (4 * rcw);
 }
 

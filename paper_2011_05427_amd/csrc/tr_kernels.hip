@@ -862,7 +862,7 @@ __global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict
   const int nx = S.nx, ne = nx + 1;
   const int r = S.lev_ng[from] / S.lev_ng[to];
   const int nto = S.lev_ng[to];
-  const int rcw = restrict_rcw(r, nto, ne), cpb = restrict_cpb(r, nto, ne);
+  const int rcw = restrict_rcw(r, nto, ne, S.rtarget), cpb = restrict_cpb(r, nto, ne, S.rtarget);
   const int ntile = (ne + 63) >> 6;
   const int qq = it.idx / ntile, et = it.idx - qq * ntile;
   const int p = qq / cpb, bc = qq - p * cpb;
@@ -917,7 +917,7 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   const int nx = S.nx, ne = nx + 1;
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
-  const int cpb = restrict_cpb(r, nto, ne);
+  const int cpb = restrict_cpb(r, nto, ne, S.rtarget);
   const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
   const int p = it.idx / nb, b = it.idx - p * nb;
   const int t = threadIdx.x;
