@@ -76,6 +76,9 @@ struct tr_ctx {
     // s = 0 (no sweep); s >= 1 with the sweep; s >= 1 without it (the sweep
     // launched separately with its start / end events)
     hipGraphExec_t first = nullptr, next = nullptr, rest = nullptr;
+    // chains of L iterations in one graph (s = 0 and L - 1 sweeping ones):
+    // one host synchronisation for the iterations a step usually needs
+    std::map<int, hipGraphExec_t> chain;
   };
   std::vector<GraphEntry> graphs;
   hipStream_t gs = nullptr;  // library stream for graph replay
@@ -84,6 +87,7 @@ struct tr_ctx {
   // slab-size bucket): the sweep's kernel time is measured in every step
   hipEvent_t ev_sw[TR_NBUCKET][2] = {};
   int sweep_events = 0;  // tr_set_sweep_timing
+  int last_iters = 0;    // transport iterations (incl. s = 0) of the previous step's slowest slab
   // learned closure (seeding of the s = 0 cell factors)
   const float *mlp_params = nullptr;
   MlpStats mlp_stats{};
@@ -356,6 +360,7 @@ int tr_destroy(tr_ctx *c) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
     if (g.rest) (void)hipGraphExecDestroy(g.rest);
+    for (auto &kv : g.chain) (void)hipGraphExecDestroy(kv.second);
   }
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -764,6 +769,7 @@ int tr_set_tiles(tr_ctx *c, const int *K) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
     if (g.rest) (void)hipGraphExecDestroy(g.rest);
+    for (auto &kv : g.chain) (void)hipGraphExecDestroy(kv.second);
   }
   c->graphs.clear();
   return TR_OK;
@@ -1007,6 +1013,17 @@ int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, b
   return e == hipSuccess ? TR_OK : TR_EHIP;
 }
 
+// One graph holding L transport iterations: s = 0, then L - 1 with sweeps.
+int capture_chain(tr_ctx *c, const tr_state *s, int Lmax, int L, hipGraphExec_t *out) {
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_EHIP;
+  for (int q = 0; q < L; ++q) enqueue_iteration(c, s, c->gs, Lmax, q > 0, false);
+  if (hipStreamEndCapture(c->gs, &g) != hipSuccess || !g) return TR_EHIP;
+  const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e == hipSuccess ? TR_OK : TR_EHIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1088,6 +1105,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
         (void)hipGraphExecDestroy(old.first);
         (void)hipGraphExecDestroy(old.next);
         if (old.rest) (void)hipGraphExecDestroy(old.rest);
+        for (auto &kv : old.chain) (void)hipGraphExecDestroy(kv.second);
         c->graphs.erase(c->graphs.begin());
       }
       tr_ctx::GraphEntry e;
@@ -1112,11 +1130,23 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   c->groups.clear();
   c->ev_used = 0;
   int s0 = 0;  // transport iteration of slab 0 (event timing mode)
+  // graph replay without timed sweeps: the iterations the previous step needed
+  // run as one chained graph (iterations past convergence are predicated off)
+  const int chain = (ge && !sweep_ev) ? std::min(8, std::min(c->last_iters, c->cfg.max_outer + 2)) : 0;
+  if (chain >= 2 && !ge->chain.count(chain)) {
+    hipGraphExec_t x = nullptr;
+    const int rc = capture_chain(c, s, Lmax, chain, &x);
+    if (rc) return rc;
+    ge->chain[chain] = x;
+  }
   for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
     // transport sweep of iteration s >= 1 (predicated per slab)
     if (outer > 0 && sweep_ev)
       launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd, true);
-    if (ge) {
+    if (ge && outer == 0 && chain >= 2) {
+      if (hipGraphLaunch(ge->chain[chain], gs) != hipSuccess) return TR_EHIP;
+      outer += chain - 1;
+    } else if (ge) {
       hipGraphExec_t gx = outer == 0 ? ge->first : sweep_ev ? ge->rest : ge->next;
       if (hipGraphLaunch(gx, gs) != hipSuccess) return TR_EHIP;
     } else {
@@ -1142,8 +1172,10 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   if (hipEventRecord(c->ev_out, gs) != hipSuccess || hipStreamWaitEvent(st, c->ev_out, 0) != hipSuccess)
     return TR_EHIP;
   int err = TR_OK;
+  c->last_iters = 0;
   for (int q = 0; q < ns; ++q) {
     const Ctl &k = hc[q];
+    c->last_iters = std::max(c->last_iters, k.s + 1);
     if (k.active) err = TR_ENOCONV;
     if (k.err) err = k.err;
     if (stats) {
