@@ -177,7 +177,9 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
     const int r = nf / nt;
     const int cpb = restrict_cpb(r, nt, ne, S.rtarget);
     if (cpb == 1) {
-      for (int st = 0; st < nt * ne; st += 256) single.push_back({s, st});
+      // four wavefront items (coarse group, tile of 64 edges) per block
+      const int nwi = nt * ((ne + 63) / 64);
+      for (int q = 0; 4 * q < nwi; ++q) single.push_back({s, q});
     } else {
       const int ntile = (ne + 63) / 64;
       for (long long q = 0; q < (long long)nt * cpb * ntile; ++q) part.push_back({s, (int)q});
@@ -739,7 +741,7 @@ int tr_restrict(tr_ctx *c, int from, int to, const tr_lo_coeffs *in, const tr_lo
   LoSol s{sol->E, sol->F, sol->Ebnd};
   LoOut o{out->sigE, out->emis, out->a, out->b, out->sigR, out->C, out->Phi, out->Eold, out->Fold, out->Esum};
   launch_restrict(env_of(c, st), c->t_red[std::make_pair(from, to)], nullptr, PRED_ALL, 0, from, to, coeffs_in(in), s,
-                  o, c->red);
+                  o, c->red, true);
   return hip_err(hipGetLastError());
 }
 
@@ -952,6 +954,9 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
   }
   for (int l = 0; l < Lmax; ++l) {
+    // old-time sums are constant during the step: restricted in its first
+    // cycle only (every slab runs cycle 0 of iteration s = 0)
+    const bool old = !with_sweep && l == 0;
     {
       TimedScope ts(c, st, TR_T_LO_FINE, l);
       launch_lo(env, c->t_lo[0], c->lo_threads, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
@@ -959,7 +964,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     {
       TimedScope ts(c, st, TR_T_RESTRICT, l);
       launch_restrict(env, c->t_red[std::make_pair(0, gl)], c->d_ctl, PRED_CYCLE, l, 0, gl, fine, fsol,
-                      grey_out(c), c->red);
+                      grey_out(c), c->red, old);
     }
     ga.end_cycle = nsch == 0;
     {
@@ -975,7 +980,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       {
         TimedScope ts(c, st, TR_T_RESTRICT, l);
         launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
-                        level_out(c, gm), c->red);
+                        level_out(c, gm), c->red, old);
       }
       {
         TimedScope ts(c, st, TR_T_LO_COARSE, l);
@@ -984,7 +989,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       {
         TimedScope ts(c, st, TR_T_RESTRICT, l);
         launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
-                        level_sol(c, gm), grey_out(c), c->red);
+                        level_sol(c, gm), grey_out(c), c->red, old);
       }
       ga.end_cycle = q == nsch - 1;
       {

@@ -75,6 +75,8 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
                const LoIn &in, const LoSol &sol);
 // Restriction work: coarse groups of r <= 16 finer groups are done in one pass;
 // larger r in a chunk pass plus a final pass over blocks of TR_RFIN_E edges.
+// old: also restrict the old-time E and F (out.Eold / out.Fold are written
+// only then).
 // In the chunk pass a block of 4 wavefronts covers 64 edges and 4 rcw finer
 // groups (rcw per wavefront), giving cpb chunk records per coarse group.  rcw
 // grows (fewer records to write and re-read) while a slab's pass keeps at
@@ -98,7 +100,7 @@ struct RestrictTables {
   Table single, part, fin;
 };
 void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
-                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red);
+                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, bool old);
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga);
 void launch_outer_begin(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer);

@@ -700,57 +700,160 @@ __global__ __launch_bounds__(512) void k_lo(const SlabDev *__restrict__ sd, Prob
 // A5: restriction.  Sum records per (block of finer groups, edge e): e < nx
 // also carries the sums of cell e, e = 0 / nx the boundary sums of side 0 / 1.
 // ---------------------------------------------------------------------------
+// The old-time sums (last two fields) are constant during a time step: a
+// step restricts them in its first cycle only (OLD), records without them
+// hold R_NC fields.
 enum {
-  R_E = 0, R_SEE, R_SE, R_EM, R_EOLD,       // cell
+  R_E = 0, R_SEE, R_SE, R_EM,               // cell
   R_ER, R_AER, R_A, R_EL, R_BEL, R_B,       // edge: right / left weights
-  R_AF, R_SAF, R_S, R_SF, R_F, R_FOLD,      // edge: |F| weights, flux sums
+  R_AF, R_SAF, R_S, R_SF, R_F,              // edge: |F| weights, flux sums
   R_EB, R_CEB, R_C, R_PHI,                  // boundary side
+  R_EOLD, R_FOLD,                           // old-time cell / edge sums
   R_N
 };
+constexpr int R_NC = R_EOLD;
+template <bool OLD>
+constexpr int rec_fields() { return OLD ? R_N : R_NC; }
 
-struct SrcView {
-  LevelView v;
-  const double *E, *F, *Eb;  // solution of the source level (group p)
+// Values of one finer group at edge e (lane), loaded without branches:
+// buffer loads out of a row's range (cell e = nx, cell e - 1 = -1, lanes past
+// the last edge) return zero, and boundary values are selected per lane.
+struct EdgeVals {
+  double se, em;           // cell e (zero for e = nx)
+  double ae, be, sr;       // edge e
+  double ER, EL, F;        // E right / left of the edge, flux
+  double Eo, Fo;           // old-time cell / edge values (OLD only)
+  double Eb0, Eb1, C0, C1, P0, P1;  // group boundary values (wave-uniform)
 };
 
-template <bool FINE>
-__device__ inline void accumulate(const SrcView &s, int e, double (&r)[R_N]) {
-  const int nx = s.v.nx;
-  if (e < nx) {
-    double se, em;
-    lv_cell<FINE>(s.v, e, se, em);
-    const double E = s.E[e];
-    r[R_E] += E;
-    r[R_SEE] += se * E;
-    r[R_SE] += se;
-    r[R_EM] += em;
-    r[R_EOLD] += s.v.Eold[e];
+// Per-lane geometry of edge e: weights of the left / right cell in the
+// width-weighted fine sigma_R average (0 / 1 and 1 / 0 on the boundary edges).
+struct EdgeGeo {
+  int e, nx;
+  double wm, we;
+};
+
+__device__ inline EdgeGeo edge_geo(const SlabDev &S, ProbDev pd, int e) {
+  EdgeGeo q;
+  q.e = e;
+  q.nx = S.nx;
+  const __amdgpu_buffer_rsrc_t r = buf_rsrc(pd.dx + S.o_cell, S.nx * 8);
+  const double dm = buf_load_f64(r, (e - 1) * 8), de = buf_load_f64(r, e * 8);
+  const double id = (e > 0 && e < S.nx) ? 1.0 / (dm + de) : 0.0;
+  q.wm = (e == S.nx) ? 1.0 : dm * id;
+  q.we = (e == 0) ? 1.0 : de * id;
+  return q;
+}
+
+// Loads group g of level `from` at edge q.e (g wave-uniform).  With valid
+// false every value is zero (empty buffer ranges, boundary values times 0),
+// so that the caller can add it without a branch.
+template <bool FINE, bool OLD>
+__device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, const LoSol &sol, int g, bool valid,
+                                  const EdgeGeo &q, EdgeVals &v) {
+  const int nx = S.nx, e = q.e;
+  const int oe = e * 8, om = (e - 1) * 8;
+  const int cb = valid ? nx * 8 : 0, eb = valid ? (nx + 1) * 8 : 0;
+  const double m = valid ? 1.0 : 0.0;
+  if (FINE) {
+    const long long gi = S.o_gi + (long long)g * nx, ge = S.o_ge + (long long)g * (nx + 1);
+    const long long g2 = 2 * S.o_g + 2 * (long long)g;
+    const __amdgpu_buffer_rsrc_t rk = buf_rsrc(in.kappa + gi, cb), rb = buf_rsrc(in.B + gi, cb);
+    const __amdgpu_buffer_rsrc_t rf = buf_rsrc(in.f + gi, cb), rE = buf_rsrc(sol.E + gi, cb);
+    const __amdgpu_buffer_rsrc_t rF = buf_rsrc(sol.F + ge, eb);
+    const double ke = buf_load_f64(rk, oe), km = buf_load_f64(rk, om);
+    const double Be = buf_load_f64(rb, oe);
+    const double fe = buf_load_f64(rf, oe), fm = buf_load_f64(rf, om);
+    const double Ee = buf_load_f64(rE, oe), Em = buf_load_f64(rE, om);
+    v.F = buf_load_f64(rF, oe);
+    if (OLD) {
+      v.Eo = buf_load_f64(buf_rsrc(in.Eold + gi, cb), oe);
+      v.Fo = buf_load_f64(buf_rsrc(in.Fold + ge, eb), oe);
+    }
+    const double fb0 = m * in.fbnd[g2], fb1 = m * in.fbnd[g2 + 1];
+    v.Eb0 = m * sol.Ebnd[g2];
+    v.Eb1 = m * sol.Ebnd[g2 + 1];
+    v.C0 = m * in.C[g2];
+    v.C1 = m * in.C[g2 + 1];
+    v.P0 = m * in.Phi[g2];
+    v.P1 = m * in.Phi[g2 + 1];
+    v.se = ke;
+    v.em = 2.0 * ke * Be;
+    // out-of-range loads are zero: boundary values are added, not selected,
+    // so that every load is used on every lane (no branch around a load)
+    v.ae = fe + (e == nx ? fb1 : 0.0);
+    v.be = fm + (e == 0 ? fb0 : 0.0);
+    v.sr = km * q.wm + ke * q.we;
+    v.ER = Ee + (e == nx ? v.Eb1 : 0.0);
+    v.EL = Em + (e == 0 ? v.Eb0 : 0.0);
+  } else {
+    const long long pi = S.o_lpi[from] + (long long)g * nx, pe = S.o_lpe[from] + (long long)g * (nx + 1);
+    const long long p2 = S.o_lp2[from] + 2 * (long long)g;
+    v.se = buf_load_f64(buf_rsrc(in.sigE + pi, cb), oe);
+    v.em = buf_load_f64(buf_rsrc(in.emis + pi, cb), oe);
+    v.ae = buf_load_f64(buf_rsrc(in.a + pe, eb), oe);
+    v.be = buf_load_f64(buf_rsrc(in.b + pe, eb), oe);
+    v.sr = buf_load_f64(buf_rsrc(in.sigR + pe, eb), oe);
+    const __amdgpu_buffer_rsrc_t rE = buf_rsrc(sol.E + pi, cb);
+    const double Ee = buf_load_f64(rE, oe), Em = buf_load_f64(rE, om);
+    v.F = buf_load_f64(buf_rsrc(sol.F + pe, eb), oe);
+    if (OLD) {
+      v.Eo = buf_load_f64(buf_rsrc(in.Eold + pi, cb), oe);
+      v.Fo = buf_load_f64(buf_rsrc(in.Fold + pe, eb), oe);
+    }
+    v.Eb0 = m * sol.Ebnd[p2];
+    v.Eb1 = m * sol.Ebnd[p2 + 1];
+    v.C0 = m * in.C[p2];
+    v.C1 = m * in.C[p2 + 1];
+    v.P0 = m * in.Phi[p2];
+    v.P1 = m * in.Phi[p2 + 1];
+    v.ER = Ee + (e == nx ? v.Eb1 : 0.0);
+    v.EL = Em + (e == 0 ? v.Eb0 : 0.0);
   }
-  double ae, be, sr;
-  lv_edge<FINE>(s.v, e, ae, be, sr);
-  const double ER = (e < nx) ? s.E[e] : s.Eb[1];
-  const double EL = (e > 0) ? s.E[e - 1] : s.Eb[0];
-  const double F = s.F[e];
-  r[R_ER] += ER;
-  r[R_AER] += ae * ER;
-  r[R_A] += ae;
-  r[R_EL] += EL;
-  r[R_BEL] += be * EL;
-  r[R_B] += be;
-  r[R_AF] += fabs(F);
-  r[R_SAF] += sr * fabs(F);
-  r[R_S] += sr;
-  r[R_SF] += sr * F;
-  r[R_F] += F;
-  r[R_FOLD] += s.v.Fold[e];
-  if (e == 0 || e == nx) {
-    const int side = (e == 0) ? 0 : 1;
-    const double Eb = s.Eb[side];
-    const double Cs = s.v.C[side];
-    r[R_EB] += Eb;
-    r[R_CEB] += Cs * Eb;
-    r[R_C] += Cs;
-    r[R_PHI] += s.v.Phi[side];
+}
+
+template <bool OLD>
+__device__ inline void add_group(const EdgeVals &v, const EdgeGeo &q, double (&r)[R_N]) {
+  r[R_E] += v.ER;  // cell sums of e = nx are not used
+  r[R_SEE] += v.se * v.ER;
+  r[R_SE] += v.se;
+  r[R_EM] += v.em;
+  if (OLD) r[R_EOLD] += v.Eo;
+  r[R_ER] += v.ER;
+  r[R_AER] += v.ae * v.ER;
+  r[R_A] += v.ae;
+  r[R_EL] += v.EL;
+  r[R_BEL] += v.be * v.EL;
+  r[R_B] += v.be;
+  const double aF = fabs(v.F);
+  r[R_AF] += aF;
+  r[R_SAF] += v.sr * aF;
+  r[R_S] += v.sr;
+  r[R_SF] += v.sr * v.F;
+  r[R_F] += v.F;
+  if (OLD) r[R_FOLD] += v.Fo;
+  const bool b0 = q.e == 0, b1 = q.e == q.nx;
+  const double Eb = b0 ? v.Eb0 : b1 ? v.Eb1 : 0.0;
+  const double Cs = b0 ? v.C0 : b1 ? v.C1 : 0.0;
+  r[R_EB] += Eb;
+  r[R_CEB] += Cs * Eb;
+  r[R_C] += Cs;
+  r[R_PHI] += b0 ? v.P0 : b1 ? v.P1 : 0.0;
+}
+
+// Adds finer groups [g0, g1) (wave-uniform) at this lane's edge, two groups'
+// loads in flight per step, in ascending group order (a missing second group
+// of an odd count adds zeros, which leaves the sums unchanged).
+template <bool FINE, bool OLD>
+__device__ inline void acc_groups(const SlabDev &S, int from, const LoIn &in, const LoSol &sol, int g0, int g1,
+                                  const EdgeGeo &q, double (&acc)[R_N]) {
+  for (int g = g0; g < g1; g += 2) {
+    const bool two = g + 1 < g1;
+    EdgeVals a, b;
+    load_group<FINE, OLD>(S, from, in, sol, g, true, q, a);
+    load_group<FINE, OLD>(S, from, in, sol, two ? g + 1 : g, two, q, b);
+    add_group<OLD>(a, q, acc);
+    add_group<OLD>(b, q, acc);
   }
 }
 
@@ -774,6 +877,7 @@ __device__ inline void finalize_dS(const SlabDev &S, int i, const LoOut &o) {
   o.dS[S.o_cell + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
+template <bool OLD>
 __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int e, int r, const double (&s)[R_N],
                                 const LoOut &o) {
   const int nx = S.nx;
@@ -786,7 +890,7 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   if (e < nx) {
     o.sigE[pi + e] = (s[R_E] > TR_TINY) ? s[R_SEE] / s[R_E] : s[R_SE] * rinv;
     o.emis[pi + e] = s[R_EM];
-    o.Eold[pi + e] = s[R_EOLD];
+    if (OLD) o.Eold[pi + e] = s[R_EOLD];
     o.Esum[pi + e] = s[R_E];
   }
   const double abar = (s[R_ER] > TR_TINY) ? s[R_AER] / s[R_ER] : s[R_A] * rinv;
@@ -800,7 +904,7 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   o.a[pe + e] = abar + eh;
   o.b[pe + e] = bbar + ec;
   o.sigR[pe + e] = sR;
-  o.Fold[pe + e] = s[R_FOLD];
+  if (OLD) o.Fold[pe + e] = s[R_FOLD];
   if (e == 0 || e == nx) {
     const int side = (e == 0) ? 0 : 1;
     o.C[p2 + side] = (s[R_EB] > TR_TINY) ? s[R_CEB] / s[R_EB] : s[R_C] * rinv;
@@ -808,21 +912,10 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   }
 }
 
-template <bool FINE>
-__device__ inline SrcView make_src(const SlabDev &S, ProbDev pd, int from, const LoIn &in, const LoSol &sol, int g) {
-  SrcView s;
-  s.v = make_view<FINE>(S, pd, from, in, g);
-  double *E, *F, *Eb;
-  level_out<FINE>(S, from, g, sol, E, F, Eb);
-  s.E = E;
-  s.F = F;
-  s.Eb = Eb;
-  return s;
-}
-
-// One-pass restriction (r <= 16 finer groups per coarse group): thread =
-// (slab, p, e) looping over the r groups, writing the final coefficients.
-template <bool FINE>
+// One-pass restriction (r <= 16 finer groups per coarse group): wavefront =
+// (coarse group p, tile of 64 edges), lane = edge; block = 4 consecutive
+// wavefront items of a slab (item index 4 it.idx + w).
+template <bool FINE, bool OLD>
 __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd, ProbDev pd,
                                                   const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
                                                   int from, int to, LoIn in, LoSol sol, LoOut out) {
@@ -832,17 +925,17 @@ __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd
   const int nx = S.nx, ne = nx + 1;
   const int nto = S.lev_ng[to];
   const int r = S.lev_ng[from] / nto;
-  const int idx = it.idx + threadIdx.x;
-  if (idx >= nto * ne) return;
-  const int p = idx / ne, e = idx - p * ne;
+  const int ntile = (ne + 63) >> 6;
+  const int wi = 4 * it.idx + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wi >= nto * ntile) return;
+  const int p = wi / ntile, et = wi - p * ntile;
+  const int e = et * 64 + (threadIdx.x & 63);
+  const EdgeGeo q = edge_geo(S, pd, e);
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  for (int g = p * r; g < (p + 1) * r; ++g) {
-    const SrcView s = make_src<FINE>(S, pd, from, in, sol, g);
-    accumulate<FINE>(s, e, acc);
-  }
-  finalize(S, pd, to, p, e, r, acc, out);
+  acc_groups<FINE, OLD>(S, from, in, sol, p * r, (p + 1) * r, q, acc);
+  if (e < ne) finalize<OLD>(S, pd, to, p, e, r, acc, out);
 }
 
 // Chunk pass (r > 16): block = (slab, chunk record qq = p cpb + bc, tile of 64
@@ -850,7 +943,7 @@ __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd
 // edge.  The four wavefront sums are combined through LDS in a fixed order,
 // ((w0 + w2) + (w1 + w3)), and the record [64 edges][R_N] is written
 // contiguously.
-template <bool FINE>
+template <bool FINE, bool OLD>
 __global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict__ sd, ProbDev pd,
                                                        const Item *__restrict__ tab, const Ctl *ctl, int pmode,
                                                        int lcyc, int from, int to, LoIn in, LoSol sol,
@@ -866,46 +959,44 @@ __global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict
   const int ntile = (ne + 63) >> 6;
   const int qq = it.idx / ntile, et = it.idx - qq * ntile;
   const int p = qq / cpb, bc = qq - p * cpb;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int e = et * 64 + lane;
   const int g0 = p * r + (bc * 4 + w) * rcw;
   const int g1 = min(g0 + rcw, (p + 1) * r);
+  const EdgeGeo q = edge_geo(S, pd, e);
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  if (e < ne) {
-    for (int g = g0; g < g1; ++g) {
-      const SrcView s = make_src<FINE>(S, pd, from, in, sol, g);
-      accumulate<FINE>(s, e, acc);
-    }
-  }
-  double *slot = sh[w & 1] + lane * R_N;
+  acc_groups<FINE, OLD>(S, from, in, sol, g0, g1, q, acc);
+  constexpr int NF = rec_fields<OLD>();
+  double *slot = sh[w & 1] + lane * NF;
   if (w >= 2) {
 #pragma unroll
-    for (int k = 0; k < R_N; ++k) slot[k] = acc[k];
+    for (int k = 0; k < NF; ++k) slot[k] = acc[k];
   }
   __syncthreads();
   if (w < 2) {
 #pragma unroll
-    for (int k = 0; k < R_N; ++k) acc[k] += slot[k];
+    for (int k = 0; k < NF; ++k) acc[k] += slot[k];
   }
   __syncthreads();
   if (w == 1) {
 #pragma unroll
-    for (int k = 0; k < R_N; ++k) slot[k] = acc[k];
+    for (int k = 0; k < NF; ++k) slot[k] = acc[k];
   }
   __syncthreads();
   if (w == 0) {
-    double *s1 = sh[1] + lane * R_N, *s0 = sh[0] + lane * R_N;
+    double *s1 = sh[1] + lane * NF, *s0 = sh[0] + lane * NF;
 #pragma unroll
-    for (int k = 0; k < R_N; ++k) s0[k] = acc[k] + s1[k];
+    for (int k = 0; k < NF; ++k) s0[k] = acc[k] + s1[k];
   }
   __syncthreads();
-  const int nval = min(64, ne - et * 64) * R_N;
-  double *rec = red + S.o_red + ((long long)qq * ne + et * 64) * R_N;
+  const int nval = min(64, ne - et * 64) * NF;
+  double *rec = red + S.o_red + ((long long)qq * ne + et * 64) * NF;
   for (int j = threadIdx.x; j < nval; j += 256) rec[j] = sh[0][j];
 }
 
+template <bool OLD>
 __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restrict__ sd, ProbDev pd,
                                                         const Item *__restrict__ tab, const Ctl *ctl, int pmode,
                                                         int lcyc, int from, int to, LoOut out,
@@ -921,13 +1012,14 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
   const int p = it.idx / nb, b = it.idx - p * nb;
   const int t = threadIdx.x;
-  const int el = t / R_N, k = t - el * R_N;
+  constexpr int NF = rec_fields<OLD>();
+  const int el = t / NF, k = t - el * NF;
   const int e = b * TR_RFIN_E + el;
   if (el < TR_RFIN_E) {
     double acc = 0.0;
     if (e < ne) {
-      const double *rec = red + S.o_red + ((long long)p * cpb * ne + e) * R_N + k;
-      const long long stride = (long long)ne * R_N;
+      const double *rec = red + S.o_red + ((long long)p * cpb * ne + e) * NF + k;
+      const long long stride = (long long)ne * NF;
 #pragma unroll 8
       for (int q = 0; q < cpb; ++q) acc += rec[q * stride];
     }
@@ -937,8 +1029,8 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   if (t < TR_RFIN_E && b * TR_RFIN_E + t < ne) {
     double s[R_N];
 #pragma unroll
-    for (int q = 0; q < R_N; ++q) s[q] = sums[t][q];
-    finalize(S, pd, to, p, b * TR_RFIN_E + t, r, s, out);
+    for (int q = 0; q < R_N; ++q) s[q] = q < NF ? sums[t][q] : 0.0;
+    finalize<OLD>(S, pd, to, p, b * TR_RFIN_E + t, r, s, out);
   }
 }
 
@@ -1442,28 +1534,37 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
                        pmode, lcyc, level, in, sol);
 }
 
-void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
-                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red) {
+template <bool OLD>
+void launch_restrict_t(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
+                       int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red) {
   const bool fine = from == 0;
   if (rt.single.n) {
     if (fine)
-      hipLaunchKernelGGL(k_restrict<true>, blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
+      hipLaunchKernelGGL((k_restrict<true, OLD>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
                          rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out);
     else
-      hipLaunchKernelGGL(k_restrict<false>, blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
+      hipLaunchKernelGGL((k_restrict<false, OLD>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
                          rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out);
   }
   if (rt.part.n) {
     if (fine)
-      hipLaunchKernelGGL(k_restrict_part<true>, blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
+      hipLaunchKernelGGL((k_restrict_part<true, OLD>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
                          rt.part.d, ctl, pmode, lcyc, from, to, in, sol, red);
     else
-      hipLaunchKernelGGL(k_restrict_part<false>, blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
+      hipLaunchKernelGGL((k_restrict_part<false, OLD>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
                          rt.part.d, ctl, pmode, lcyc, from, to, in, sol, red);
   }
   if (rt.fin.n)
-    hipLaunchKernelGGL(k_restrict_final, blocks(rt.fin.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.fin.d, ctl,
-                       pmode, lcyc, from, to, out, red);
+    hipLaunchKernelGGL(k_restrict_final<OLD>, blocks(rt.fin.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.fin.d,
+                       ctl, pmode, lcyc, from, to, out, red);
+}
+
+void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
+                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, bool old) {
+  if (old)
+    launch_restrict_t<true>(env, rt, ctl, pmode, lcyc, from, to, in, sol, out, red);
+  else
+    launch_restrict_t<false>(env, rt, ctl, pmode, lcyc, from, to, in, sol, out, red);
 }
 
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
