@@ -172,7 +172,7 @@ def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closu
 
     sv = binding.Solver(slabs, levels, cfg, timing=timing)
     if tiles is not None:
-        sv.set_tiles(tiles)
+        sv.set_tiles(*tiles)
     if closure is not None:
         sv.set_closure(*closure)
     st = sv.new_state()
@@ -273,17 +273,17 @@ def main():
     levels = [inputs.levels_for(s, cfg) for s in slabs]
     torch.cuda.set_device(0)
 
-    tiles, tune_info = None, None
-    if args.workload == "batch":
-        sv = binding.Solver(slabs, levels, cfg)
-        st = sv.new_state()
-        sv.state_init(st, slabs[0].T0)
-        t0 = time.perf_counter()
-        tune_info = tuning.tune(sv, st, reps=3, path=None)
-        tune_info["tune_s"] = time.perf_counter() - t0
-        tiles = tune_info["K"]
-        sv.close()
-        del st
+    # sweep tiles (cells per lane, wavefronts per group and half range) chosen
+    # by the autotuner on this workload's first state (untimed set-up)
+    sv = binding.Solver(slabs, levels, cfg)
+    st = sv.new_state()
+    sv.state_init(st, slabs[0].T0)
+    t0 = time.perf_counter()
+    tune_info = tuning.tune(sv, st, reps=3, path=None)
+    tune_info["tune_s"] = time.perf_counter() - t0
+    tiles = (tune_info["K"], tune_info["split"])
+    sv.close()
+    del st
 
     # timed: graph replay, no events
     fin64 = {}
@@ -371,9 +371,9 @@ def main():
             "max_rel_err_E_vs_f64": rel(fin32["E"], fin64["E"]),
             "note": "corner intensities stored in binary32; sweep arithmetic, moments, LO, grey and MEB in binary64",
         }
-    if tune_info is not None:
-        out["tiles"] = {"K_per_bucket": tune_info["K"], "us_per_K": tune_info["us"],
-                        "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}
+    out["tiles"] = {"K_per_bucket": tune_info["K"], "split_per_bucket": tune_info["split"],
+                    "us_per_tile": tune_info["us"], "tile_order": "q = (K in 1,2,4,8)[q // 3], (split in 1,2,4)[q % 3]",
+                    "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}
     if not args.no_learned:
         out["learned"] = learned_vs_plain(slabs, levels, cfg, tiles, args, ms_step, sum(sweeps))
     tr = measured_traffic(args.workload, out["roofline"]["bytes_per_launch"])

@@ -281,20 +281,24 @@ int tr_set_sweep_timing(tr_ctx *ctx, int on);
 
 /*
  * Batched launch tiles.  Sweep work is grouped by slab size into 6 buckets
- * (nx <= 64, 128, 256, 512, 1024, larger), ordered longest slab first, and
- * each bucket's wavefronts own K in {1, 2, 4, 8} consecutive cells per lane.
- * tr_autotune times every K on each non-empty bucket (reps launches each, on
- * the given I buffers and the context's current opacity tables) and keeps the
- * fastest; K_out (host [6]) and us_out (host [6][4], microseconds per launch
- * for K = 1, 2, 4, 8; nullable) report the result.  tr_set_tiles applies a
- * cached choice; tr_get_tiles reads the current one and the items per bucket
- * (host [6] each, items nullable).  Choosing tiles changes only the
- * association of the sweep's prefix scan (results at roundoff).
+ * (nx <= 64, 128, 256, 512, 1024, larger), ordered longest slab first.  A
+ * bucket's tile is (K, split): its wavefronts own K in {1, 2, 4, 8} cells per
+ * lane and pass, and split in {1, 2, 4} wavefronts share the directions of
+ * one (group, half range) (more wavefronts in flight for small problems).
+ * tr_autotune times the 12 tiles on each non-empty bucket (reps launches
+ * each, on the given I buffers and the context's current opacity tables) and
+ * keeps the fastest; K_out, split_out (host [6]) and us_out (host [6][12],
+ * microseconds per launch, tile q = (K index q / 3, split index q % 3)) report
+ * the result (each nullable).  tr_set_tiles applies a cached choice (split
+ * nullable: 1); tr_get_tiles reads the current one and the items per bucket
+ * (host [6] each; split, items nullable).  Tiles change only the association
+ * of the sweep's prefix scan and of its direction sums (results at roundoff).
+ * Errors: TR_EINVAL (K or split outside the sets above).
  */
-int tr_autotune(tr_ctx *ctx, const double *I_prev, double *I_out, int reps, int *K_out, double *us_out,
-                hipStream_t stream);
-int tr_set_tiles(tr_ctx *ctx, const int *K);
-int tr_get_tiles(const tr_ctx *ctx, int *K, int *items);
+int tr_autotune(tr_ctx *ctx, const double *I_prev, double *I_out, int reps, int *K_out, int *split_out,
+                double *us_out, hipStream_t stream);
+int tr_set_tiles(tr_ctx *ctx, const int *K, const int *split);
+int tr_get_tiles(const tr_ctx *ctx, int *K, int *split, int *items);
 
 /*
  * Learned closure (not part of the paper's method; its plain sweep stays the

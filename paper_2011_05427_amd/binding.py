@@ -120,9 +120,9 @@ def load():
     lib.tr_mlp_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
     lib.tr_closure_targets.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp]
     lib.tr_set_closure.argtypes = [vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
-    lib.tr_autotune.argtypes = [vp, vp, vp, C.c_int, _ip, _dp, vp]
-    lib.tr_set_tiles.argtypes = [vp, _ip]
-    lib.tr_get_tiles.argtypes = [vp, _ip, _ip]
+    lib.tr_autotune.argtypes = [vp, vp, vp, C.c_int, _ip, _ip, _dp, vp]
+    lib.tr_set_tiles.argtypes = [vp, _ip, _ip]
+    lib.tr_get_tiles.argtypes = [vp, _ip, _ip, _ip]
     for name in EXPORTS:
         if name not in ("tr_error_string", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes"):
             getattr(lib, name).restype = C.c_int
@@ -395,21 +395,24 @@ def _solver_methods():
         self._closure = mlp
 
     def autotune(self, st, reps=3):
-        """Times sweep tiles per slab-size bucket; returns (K[6], us[6][4])."""
-        K = (C.c_int * 6)()
-        us = (C.c_double * 24)()
-        _check(self.lib.tr_autotune(self._ctx, _ptr(st["I_prev"]), _ptr(st["I_out"]), reps, K, us, self._stream()),
-               "tr_autotune")
-        return list(K), [list(us[4 * b:4 * b + 4]) for b in range(6)]
+        """Times the sweep tiles (K, split) per slab-size bucket; returns
+        (K[6], split[6], us[6][12]) with tile q = (K index q // 3, split index q % 3)."""
+        K, S = (C.c_int * 6)(), (C.c_int * 6)()
+        us = (C.c_double * 72)()
+        _check(self.lib.tr_autotune(self._ctx, _ptr(st["I_prev"]), _ptr(st["I_out"]), reps, K, S, us,
+                                    self._stream()), "tr_autotune")
+        return list(K), list(S), [list(us[12 * b:12 * b + 12]) for b in range(6)]
 
-    def set_tiles(self, K):
+    def set_tiles(self, K, split=None):
         arr = (C.c_int * 6)(*[int(k) for k in K])
-        _check(self.lib.tr_set_tiles(self._ctx, arr), "tr_set_tiles")
+        sp = None if split is None else (C.c_int * 6)(*[int(k) for k in split])
+        _check(self.lib.tr_set_tiles(self._ctx, arr, sp), "tr_set_tiles")
 
     def get_tiles(self):
-        K, n = (C.c_int * 6)(), (C.c_int * 6)()
-        _check(self.lib.tr_get_tiles(self._ctx, K, n), "tr_get_tiles")
-        return list(K), list(n)
+        """(K[6], split[6], items[6]) of the current sweep tiles."""
+        K, S, n = (C.c_int * 6)(), (C.c_int * 6)(), (C.c_int * 6)()
+        _check(self.lib.tr_get_tiles(self._ctx, K, S, n), "tr_get_tiles")
+        return list(K), list(S), list(n)
 
     Solver.autotune = autotune
     Solver.set_tiles = set_tiles

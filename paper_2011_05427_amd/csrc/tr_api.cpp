@@ -59,6 +59,7 @@ struct tr_ctx {
   // longest slabs first; K = cells per lane of each bucket's launch
   Table t_sweep_b[TR_NBUCKET]{};
   int sweep_K[TR_NBUCKET] = {1, 2, 4, 4, 4, 4};
+  int sweep_S[TR_NBUCKET] = {1, 1, 1, 1, 1, 1};  // wavefronts sharing a (group, half range)
   Table t_lo[TR_MAXLEV]{};
   std::map<std::pair<int, int>, RestrictTables> t_red;
   std::map<int, Table> t_pro;  // prolongation work per level
@@ -212,8 +213,9 @@ int sweep_bucket(int nx) {
 void launch_sweeps(const tr_ctx *c, const LaunchEnv &env, const Ctl *ctl, int pmode, const double *kappa,
                    const double *B, const void *Ip, void *Io, double *mom, double *bnd, bool timed = false) {
   for (int b = 0; b < TR_NBUCKET; ++b)
-    launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], c->cfg.precision == TR_PREC_F32_STORAGE, ctl, pmode, 0, kappa,
-                 B, Ip, Io, mom, bnd, timed ? c->ev_sw[b][0] : nullptr, timed ? c->ev_sw[b][1] : nullptr);
+    launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], c->sweep_S[b], c->cfg.precision == TR_PREC_F32_STORAGE, ctl,
+                 pmode, 0, kappa, B, Ip, Io, mom, bnd, timed ? c->ev_sw[b][0] : nullptr,
+                 timed ? c->ev_sw[b][1] : nullptr);
 }
 
 // Kernel time of the last timed sweep launches (after a synchronisation).
@@ -761,11 +763,16 @@ int tr_grey_solve(tr_ctx *c, const tr_lo_coeffs *grey, const double *Tstar, cons
   return hip_err(hipGetLastError());
 }
 
-int tr_set_tiles(tr_ctx *c, const int *K) {
+int tr_set_tiles(tr_ctx *c, const int *K, const int *split) {
   if (!c || !K) return TR_EINVAL;
-  for (int b = 0; b < TR_NBUCKET; ++b)
+  for (int b = 0; b < TR_NBUCKET; ++b) {
     if (K[b] != 1 && K[b] != 2 && K[b] != 4 && K[b] != 8) return TR_EINVAL;
-  for (int b = 0; b < TR_NBUCKET; ++b) c->sweep_K[b] = K[b];
+    if (split && split[b] != 1 && split[b] != 2 && split[b] != 4) return TR_EINVAL;
+  }
+  for (int b = 0; b < TR_NBUCKET; ++b) {
+    c->sweep_K[b] = K[b];
+    c->sweep_S[b] = split ? split[b] : 1;
+  }
   // captured launch sequences hold the old tiles
   for (auto &g : c->graphs) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
@@ -777,49 +784,55 @@ int tr_set_tiles(tr_ctx *c, const int *K) {
   return TR_OK;
 }
 
-int tr_get_tiles(const tr_ctx *c, int *K, int *items) {
+int tr_get_tiles(const tr_ctx *c, int *K, int *split, int *items) {
   if (!c || !K) return TR_EINVAL;
   for (int b = 0; b < TR_NBUCKET; ++b) {
     K[b] = c->sweep_K[b];
+    if (split) split[b] = c->sweep_S[b];
     if (items) items[b] = c->t_sweep_b[b].n;
   }
   return TR_OK;
 }
 
-int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K_out, double *us_out,
-                hipStream_t st) {
+int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K_out, int *split_out,
+                double *us_out, hipStream_t st) {
   if (!c || !I_prev || !I_out || I_prev == I_out || reps < 1) return TR_EINVAL;
-  static const int cand[4] = {1, 2, 4, 8};
+  static const int candK[4] = {1, 2, 4, 8}, candS[3] = {1, 2, 4};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TR_EHIP;
   LaunchEnv env = env_of(c, st);
-  int K[TR_NBUCKET];
+  const bool f32 = c->cfg.precision == TR_PREC_F32_STORAGE;
+  int K[TR_NBUCKET], Sp[TR_NBUCKET];
   int rc = TR_OK;
   for (int b = 0; b < TR_NBUCKET && !rc; ++b) {
     K[b] = c->sweep_K[b];
+    Sp[b] = c->sweep_S[b];
     if (c->t_sweep_b[b].n == 0) {
       if (us_out)
-        for (int q = 0; q < 4; ++q) us_out[4 * b + q] = 0.0;
+        for (int q = 0; q < 12; ++q) us_out[12 * b + q] = 0.0;
       continue;
     }
     double best = 1e300;
-    for (int q = 0; q < 4 && !rc; ++q) {
-      const bool f32 = c->cfg.precision == TR_PREC_F32_STORAGE;
-      launch_sweep(env, c->t_sweep_b[b], cand[q], f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
+    for (int q = 0; q < 12 && !rc; ++q) {
+      const int kk = candK[q / 3], ss = candS[q % 3];
+      launch_sweep(env, c->t_sweep_b[b], kk, ss, f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
                    c->bnd);
       if (hipEventRecord(e0, st) != hipSuccess) rc = TR_EHIP;
       for (int r = 0; r < reps; ++r)
-        launch_sweep(env, c->t_sweep_b[b], cand[q], f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
+        launch_sweep(env, c->t_sweep_b[b], kk, ss, f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
                      c->bnd);
       float ms = 0.f;
       if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
         rc = TR_EHIP;
-      const double us = 1e3 * ms / reps;
-      if (us_out) us_out[4 * b + q] = us;
-      if (us < best) {
+      // a tile whose launch was refused (resources) is not a candidate
+      const bool launched = hipGetLastError() == hipSuccess;
+      const double us = launched ? 1e3 * ms / reps : 0.0;
+      if (us_out) us_out[12 * b + q] = us;
+      if (launched && us < best) {
         best = us;
-        K[b] = cand[q];
+        K[b] = kk;
+        Sp[b] = ss;
       }
     }
   }
@@ -828,7 +841,9 @@ int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K
   if (rc) return rc;
   if (K_out)
     for (int b = 0; b < TR_NBUCKET; ++b) K_out[b] = K[b];
-  return tr_set_tiles(c, K);
+  if (split_out)
+    for (int b = 0; b < TR_NBUCKET; ++b) split_out[b] = Sp[b];
+  return tr_set_tiles(c, K, Sp);
 }
 
 int tr_mlp_features(tr_ctx *c, const double *T, const double *T_prev, const double *kappa, const double *f,

@@ -62,11 +62,12 @@ void launch_opacity(const LaunchEnv &env, const Table &tab, int run, const Ctl *
 // dS per cell from the chunk partials; tab items = (slab, first of 64 cells).
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
                    double *dS);
-// Sweep tiles: K consecutive cells per lane (K in {1, 2, 4, 8}).
+// Sweep tiles: K cells per lane and pass (K in {1, 2, 4, 8}); split in
+// {1, 2, 4} wavefronts share the directions of one (group, half range).
 // f32: corner intensities stored as float (binary64 arithmetic inside).
 // With ev0 / ev1 the launch records the kernel's own start and end on them.
-void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
-                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool f32, const Ctl *ctl, int pmode,
+                  int lcyc, const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
                     const double *bnd, double *f, double *fbnd, double *C, double *Phi);

@@ -144,22 +144,22 @@ __global__ __launch_bounds__(256) void k_dS_sum(const SlabDev *__restrict__ sd, 
 }
 
 // ---------------------------------------------------------------------------
-// A2 (+ partial A3): SCB sweep.  One wavefront per (slab, group, half range).
+// A2 (+ partial A3): SCB sweep.  Work unit = (slab, group, half range).
 // Per cell the 2x2 corner system makes the outflow an affine function of the
 // inflow, I_dn = al I_in + be and I_up = ga I_in + de.  A pass covers 64 K
-// cells in K segments of 64 (lane l holds the l-th cell of every segment);
-// a wavefront prefix scan of the maps of each segment, chained by the
-// segments' total maps, gives every cell its inflow, so a row of nx cells
-// advances 64 K cells per pass instead of one.  Directions of the half range
-// are processed in turn; the cell-average moments sum w Ibar and
-// sum w mu^2 Ibar accumulate in registers.
+// cells in sweep order; lane l owns K consecutive of them.  A lane first
+// composes its K maps in turn, one wavefront prefix scan of the 64 lane maps
+// then gives every lane its inflow, and the lane applies its maps in turn;
+// passes are chained by the total map of the previous pass.  Directions of
+// the half range are processed in turn; the cell-average moments sum w Ibar
+// and sum w mu^2 Ibar accumulate in registers.
 //
 // Memory: every intensity row is accessed through a raw buffer resource whose
 // range is the row, so lanes past the end of the slab load zeros and their
 // stores are dropped by the hardware; the loop body has no branches around
 // memory operations, and the corner pairs of the next direction are loaded
-// while the current one is scanned.  The scan uses DPP lane moves (row shifts
-// and row broadcasts), the carries between directions are lane reads.
+// while the current one is computed.  The scan uses DPP lane moves (row
+// shifts and row broadcasts), the carries between passes are lane reads.
 // ---------------------------------------------------------------------------
 typedef unsigned int tr_u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int tr_u32x2 __attribute__((ext_vector_type(2)));
@@ -233,26 +233,46 @@ enum {
   DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143
 };
 
-template <int K, typename TI>
-__global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, ProbDev pd,
-                                               const Item *__restrict__ tab, int nitems, const Ctl *ctl, int pmode,
-                                               int lcyc, const double *__restrict__ kappa,
-                                               const double *__restrict__ Bt, const TI *__restrict__ Ip,
-                                               TI *__restrict__ Io, double *__restrict__ mom,
-                                               double *__restrict__ bnd) {
+// LDS transposition buffer of a wavefront (K > 1): pass position p (sweep
+// order, 0 <= p < 64 K) lives in slot p + p / K, one pad slot after every K
+// positions, so that both the segment-major accesses (lane l, position
+// 64 k + l) and the lane-serial ones (lane l, position K l + k, slot
+// (K + 1) l + k) spread over the banks.
+template <int K>
+__device__ inline int tr_slot(int p) {
+  return p + p / K;
+}
+
+// Doubles of LDS a sweep block needs (launch argument).
+__host__ __device__ inline int sweep_lds_doubles(int K, int split) {
+  const int nw = split == 1 ? 4 : split;
+  const int tcol = K > 1 ? 128 * (K + 1) : 0;  // transposition buffer per wavefront
+  return nw * tcol + (split == 1 ? 0 : split * (K * 128 + 3));
+}
+
+// One work unit's share of directions, sweeping in the direction of
+// decreasing x (REV, mu < 0) or increasing x.
+template <int K, typename TI, bool REV>
+__device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, int split,
+                                  const double *__restrict__ kappa, const double *__restrict__ Bt,
+                                  const TI *__restrict__ Ip, TI *__restrict__ Io, double *__restrict__ mom,
+                                  double *__restrict__ bnd, double *sred) {
   typedef Pair<TI> P;
   typedef typename P::V PV;
   const int lane = threadIdx.x & 63;
-  // wavefront index, made visibly uniform so that the descriptors and the
-  // per-direction quantities live in scalar registers
-  const int wv = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-  const int item = wv >> 1, half = wv & 1;
-  if (item >= nitems) return;
-  const Item it = tab[item];
-  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
-  const SlabDev &S = sd[it.slab];
-  const int g = it.idx, nx = S.nx, ng = S.ng, M = S.nmu, Mh = M >> 1;
-  const int m0 = half ? 0 : Mh;  // mu ascending: mu < 0 first
+  const int half = REV ? 1 : 0;
+  const int nx = S.nx, ng = S.ng, M = S.nmu, Mh = M >> 1;
+  const int m0 = REV ? 0 : Mh;  // mu ascending: mu < 0 first
+  // this wavefront's directions m0 + [j0, j1)
+  const int dw = (Mh + split - 1) / split;
+  const int j0 = min(Mh, sub * dw), j1 = min(Mh, j0 + dw);
+  // LDS: transposition buffers of the block's wavefronts, then (split > 1)
+  // the partial moments [split][K][64] (phi, chi) and outflow sums [split][3]
+  const int nw = split == 1 ? 4 : split;
+  const int wslot = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double2 *tb = reinterpret_cast<double2 *>(sred) + (K > 1 ? wslot * 64 * (K + 1) : 0);
+  double2 *red = reinterpret_cast<double2 *>(sred) + (K > 1 ? nw * 64 * (K + 1) : 0);
+  double *sb = reinterpret_cast<double *>(red + split * K * 64);
   const double inv_cdt = S.inv_cdt;
   const __amdgpu_buffer_rsrc_t r_dx = buf_rsrc(pd.dx + S.o_cell, nx * 8);
   const __amdgpu_buffer_rsrc_t r_kp = buf_rsrc(kappa + S.o_gi + (long long)g * nx, nx * 8);
@@ -262,23 +282,27 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
   const int rowb = nx * 2 * (int)sizeof(TI);
   const double *mu = pd.mu + S.o_mu;
   const double *w = pd.w + S.o_mu;
-  double carry = pd.inc[2 * S.o_g + (half ? ng : 0) + g];  // lane j: inflow of direction m0 + j
+  double carry = pd.inc[2 * S.o_g + half * ng + g];  // lane j: inflow of direction m0 + j
   const __amdgpu_buffer_rsrc_t r_mp =
       buf_rsrc(mom + 4 * S.o_gi + (long long)half * 2 * ng * nx + (long long)g * nx * 2, nx * 16);
   const int npass = (nx + 64 * K - 1) / (64 * K);
-  // cell of segment k of a pass for this lane: the pass covers 64 K cells in
-  // sweep order, segment k the 64 consecutive cells k 64 .. k 64 + 63, lane l
-  // the l-th of them (so every load and store of a segment is one contiguous
-  // block); cells outside [0, nx) map to offsets outside the row's range
-  auto cell_of = [&](int pass, int k) {
-    const int q = pass * 64 * K + k * 64 + lane;
-    return half ? nx - 1 - q : q;
+  // cells of a pass: position q in sweep order; lane l computes positions
+  // K l .. K l + K - 1 (lane-serial) and moves positions 64 k + l to and from
+  // memory (segment-major: each access is one contiguous block); cells
+  // outside [0, nx) map to offsets outside the row's range
+  auto cell_at = [&](int pass, int q) {
+    const int c = pass * 64 * K + q;
+    return REV ? nx - 1 - c : c;
   };
+  auto cell_mem = [&](int pass, int k) { return cell_at(pass, K > 1 ? k * 64 + lane : lane); };
+  auto cell_own = [&](int pass, int k) { return cell_at(pass, lane * K + k); };
   PV nxt[K];
   {
-    const __amdgpu_buffer_rsrc_t r = buf_rsrc(ip + (long long)m0 * nx * 2, rowb);
+    // a wavefront without directions reads nothing (empty range)
+    const __amdgpu_buffer_rsrc_t r =
+        buf_rsrc(ip + (long long)(m0 + (j0 < j1 ? j0 : 0)) * nx * 2, j0 < j1 ? rowb : 0);
 #pragma unroll
-    for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_of(0, k) * 2 * (int)sizeof(TI));
+    for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_mem(0, k) * 2 * (int)sizeof(TI));
   }
   for (int pass = 0; pass < npass; ++pass) {
     double bb[K], ee[K], phi[K], chi[K], hh[K];
@@ -286,9 +310,9 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
     bool ok[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int i = cell_of(pass, k);
+      const int i = cell_own(pass, k);
       ok[k] = i >= 0 && i < nx;
-      off[k] = i * 2 * (int)sizeof(TI);
+      off[k] = cell_mem(pass, k) * 2 * (int)sizeof(TI);
       const double dxi = buf_load_f64(r_dx, i * 8);
       const double kap = buf_load_f64(r_kp, i * 8);
       const double bpl = buf_load_f64(r_bp, i * 8);
@@ -298,27 +322,39 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
       phi[k] = 0.0;
       chi[k] = 0.0;
     }
-    for (int j = 0; j < Mh; ++j) {
+    for (int j = j0; j < j1; ++j) {
       const int m = m0 + j;
-      PV cur[K];
+      double cx[K], cy[K];  // corner pair of the lane's cells (left, right)
+      if (K > 1) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) cur[k] = nxt[k];
+        for (int k = 0; k < K; ++k) tb[tr_slot<K>(k * 64 + lane)] = make_double2((double)nxt[k].x, (double)nxt[k].y);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double2 v = tb[(K + 1) * lane + k];
+          cx[k] = v.x;
+          cy[k] = v.y;
+        }
+      } else {
+        cx[0] = (double)nxt[0].x;
+        cy[0] = (double)nxt[0].y;
+      }
       {
         // next direction of this pass, else the first direction of the next
         // pass (past the last pass every offset is out of range)
-        const bool same = j + 1 < Mh;
-        const __amdgpu_buffer_rsrc_t r = buf_rsrc(ip + (long long)(same ? m + 1 : m0) * nx * 2, rowb);
+        const bool same = j + 1 < j1;
+        const __amdgpu_buffer_rsrc_t r = buf_rsrc(ip + (long long)(same ? m + 1 : m0 + j0) * nx * 2, rowb);
 #pragma unroll
-        for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_of(same ? pass : pass + 1, k) * 2 * (int)sizeof(TI));
+        for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_mem(same ? pass : pass + 1, k) * 2 * (int)sizeof(TI));
       }
       const double mum = mu[m], wm = w[m];
       const double amu = fabs(mum), a = 0.5 * amu, a2 = a * a, aamu = a * amu;
       const double wmu2 = wm * mum * mum;
-      double al[K], be[K], ga[K], de[K], A[K], Bc[K];
+      double al[K], be[K], ga[K], de[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double up = half ? (double)cur[k].y : (double)cur[k].x;
-        const double dn = half ? (double)cur[k].x : (double)cur[k].y;
+        const double up = REV ? cy[k] : cx[k];
+        const double dn = REV ? cx[k] : cy[k];
         const double s_up = fma(hh[k], up, ee[k]);
         const double s_dn = fma(hh[k], dn, ee[k]);
         const double apb = a + bb[k];
@@ -327,54 +363,101 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
         ga[k] = ok[k] ? apb * amu * r : 0.0;
         be[k] = ok[k] ? fma(apb, s_dn, a * s_up) * r : 0.0;
         de[k] = ok[k] ? fma(apb, s_up, -a * s_dn) * r : 0.0;
-        A[k] = al[k];
-        Bc[k] = be[k];
       }
-      // inclusive scans of the K segments (independent chains)
+      // the lane's map: its K cell maps composed in sweep order
+      double A = al[0], Bc = be[0];
 #pragma unroll
-      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR1, 0xf>(A[k], Bc[k]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR2, 0xf>(A[k], Bc[k]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR4, 0xf>(A[k], Bc[k]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_SHR8, 0xf>(A[k], Bc[k]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_BCAST15, 0xa>(A[k], Bc[k]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) scan_step<DPP_ROW_BCAST31, 0xc>(A[k], Bc[k]);
-      // inflow of each segment: the previous segment's outflow
-      double cin = readlane_f64(carry, j);
-      const __amdgpu_buffer_rsrc_t ro = buf_rsrc(io + (long long)m * nx * 2, rowb);
+      for (int k = 1; k < K; ++k) {
+        Bc = fma(al[k], Bc, be[k]);
+        A = A * al[k];
+      }
+      // inclusive scan of the lane maps
+      scan_step<DPP_ROW_SHR1, 0xf>(A, Bc);
+      scan_step<DPP_ROW_SHR2, 0xf>(A, Bc);
+      scan_step<DPP_ROW_SHR4, 0xf>(A, Bc);
+      scan_step<DPP_ROW_SHR8, 0xf>(A, Bc);
+      scan_step<DPP_ROW_BCAST15, 0xa>(A, Bc);
+      scan_step<DPP_ROW_BCAST31, 0xc>(A, Bc);
+      // inflow of the lane: the maps of the lanes before it applied to the
+      // pass inflow
+      const double cin = readlane_f64(carry, j);
+      const double Ae = dpp_f64<DPP_WAVE_SHR1, 0xf>(A, 1.0);
+      const double Be = dpp_f64<DPP_WAVE_SHR1, 0xf>(Bc, 0.0);
+      double Iin = fma(Ae, cin, Be);
+      double ox[K], oy[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double Ae = dpp_f64<DPP_WAVE_SHR1, 0xf>(A[k], 1.0);
-        const double Be = dpp_f64<DPP_WAVE_SHR1, 0xf>(Bc[k], 0.0);
-        const double Iin = fma(Ae, cin, Be);
         const double Iup = fma(ga[k], Iin, de[k]);
         const double Idn = fma(al[k], Iin, be[k]);
-        PV o;
-        o.x = (TI)(half ? Idn : Iup);
-        o.y = (TI)(half ? Iup : Idn);
-        P::store(o, ro, off[k]);
+        ox[k] = REV ? Idn : Iup;
+        oy[k] = REV ? Iup : Idn;
         const double Ibar = 0.5 * (Iup + Idn);
         phi[k] = fma(wm, Ibar, phi[k]);
         chi[k] = fma(wmu2, Ibar, chi[k]);
-        cin = fma(readlane_f64(A[k], 63), cin, readlane_f64(Bc[k], 63));
+        Iin = Idn;
       }
-      if (lane == j) carry = cin;
-    }
+      const __amdgpu_buffer_rsrc_t ro = buf_rsrc(io + (long long)m * nx * 2, rowb);
+      if (K > 1) {
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double2 o;
-      o.x = phi[k];
-      o.y = chi[k];
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, o), r_mp, cell_of(pass, k) * 16, 0, 0);
+        for (int k = 0; k < K; ++k) tb[(K + 1) * lane + k] = make_double2(ox[k], oy[k]);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double2 v = tb[tr_slot<K>(k * 64 + lane)];
+          PV o;
+          o.x = (TI)v.x;
+          o.y = (TI)v.y;
+          P::store(o, ro, off[k]);
+        }
+        __builtin_amdgcn_wave_barrier();
+      } else {
+        PV o;
+        o.x = (TI)ox[0];
+        o.y = (TI)oy[0];
+        P::store(o, ro, off[0]);
+      }
+      const double cout = fma(readlane_f64(A, 63), cin, readlane_f64(Bc, 63));
+      if (lane == j) carry = cout;
     }
+    // cell moments of the pass (lane-serial) to memory (segment-major)
+    if (split > 1) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) red[(sub * K + k) * 64 + lane] = make_double2(phi[k], chi[k]);
+      __syncthreads();
+      if (sub == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          for (int q = 1; q < split; ++q) {
+            const double2 v = red[(q * K + k) * 64 + lane];
+            phi[k] += v.x;
+            chi[k] += v.y;
+          }
+        }
+      }
+    }
+    if (sub == 0) {
+      if (K > 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) tb[(K + 1) * lane + k] = make_double2(phi[k], chi[k]);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double2 o = tb[tr_slot<K>(k * 64 + lane)];
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, o), r_mp, cell_mem(pass, k) * 16, 0,
+                                                 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+      } else {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, make_double2(phi[0], chi[0])), r_mp,
+                                               cell_mem(pass, 0) * 16, 0, 0);
+      }
+    }
+    if (split > 1) __syncthreads();
   }
   // outflow-edge sums of this half range: carry = intensity leaving the slab
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (lane < Mh) {
+  if (lane >= j0 && lane < j1) {
     const double wl = w[m0 + lane], ml = mu[m0 + lane];
     s0 = wl * carry;
     s1 = wl * ml * carry;
@@ -386,12 +469,57 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
     s1 += __shfl_xor(s1, d);
     s2 += __shfl_xor(s2, d);
   }
-  if (lane == 0) {
-    double *bo = bnd + 6 * S.o_g + (long long)half * 3 * ng + 3 * g;
-    bo[0] = s0;
-    bo[1] = s1;
-    bo[2] = s2;
+  double *bo = bnd + 6 * S.o_g + (long long)half * 3 * ng + 3 * g;
+  if (split == 1) {
+    if (lane == 0) {
+      bo[0] = s0;
+      bo[1] = s1;
+      bo[2] = s2;
+    }
+    return;
   }
+  if (lane == 0) {
+    sb[3 * sub] = s0;
+    sb[3 * sub + 1] = s1;
+    sb[3 * sub + 2] = s2;
+  }
+  __syncthreads();
+  if (sub == 0 && lane < 3) {
+    double t = sb[lane];
+    for (int q = 1; q < split; ++q) t += sb[3 * q + lane];
+    bo[lane] = t;
+  }
+}
+
+// split = 1: a wavefront sweeps all directions of one (group, half range);
+// blocks of 4 such wavefronts.  split = 2 or 4: a block of split wavefronts
+// shares one (group, half range), wavefront `sub` taking a contiguous share
+// of its directions; the moment and outflow partials are added through LDS
+// in wavefront order (more wavefronts in flight for small problems).
+template <int K, typename TI>
+__global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, ProbDev pd,
+                                               const Item *__restrict__ tab, int nitems, int split, const Ctl *ctl,
+                                               int pmode, int lcyc, const double *__restrict__ kappa,
+                                               const double *__restrict__ Bt, const TI *__restrict__ Ip,
+                                               TI *__restrict__ Io, double *__restrict__ mom,
+                                               double *__restrict__ bnd) {
+  extern __shared__ double sred[];  // split > 1: [split][K][64] (phi, chi), then [split][3]
+  // wavefront indices, made visibly uniform so that the descriptors and the
+  // per-direction quantities live in scalar registers (split is uniform: the
+  // whole block of a split sweep exits together)
+  const int unit = split == 1
+                       ? __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6))
+                       : (int)blockIdx.x;
+  const int sub = split == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int item = unit >> 1, half = unit & 1;
+  if (item >= nitems) return;
+  const Item it = tab[item];
+  if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
+  const SlabDev &S = sd[it.slab];
+  if (half)
+    sweep_unit<K, TI, true>(S, pd, it.idx, sub, split, kappa, Bt, Ip, Io, mom, bnd, sred);
+  else
+    sweep_unit<K, TI, false>(S, pd, it.idx, sub, split, kappa, Bt, Ip, Io, mom, bnd, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -1477,21 +1605,24 @@ void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int p
   hipLaunchKernelGGL(k_dS_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, ctl, pmode, lcyc, dSpart, dS);
 }
 
-void launch_sweep(const LaunchEnv &env, const Table &tab, int K, bool f32, const Ctl *ctl, int pmode, int lcyc,
-                  const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool f32, const Ctl *ctl, int pmode,
+                  int lcyc, const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
                   hipEvent_t ev0, hipEvent_t ev1) {
   if (tab.n == 0) return;
   const int waves = 2 * tab.n;
-  const int nb = (waves + 3) / 4;
+  const int nb = split == 1 ? (waves + 3) / 4 : waves;
+  const int nt = split == 1 ? 256 : 64 * split;
+  const size_t lds = (size_t)sweep_lds_doubles(K, split) * sizeof(double);
 #define TR_SWEEP_K(KK, TT)                                                                                          \
   do {                                                                                                              \
     if (ev0)                                                                                                        \
-      hipExtLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(256), 0, env.stream, ev0, ev1, 0, env.sd, env.pd, \
-                            tab.d, tab.n, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip),               \
+      hipExtLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(nt), lds, env.stream, ev0, ev1, 0, env.sd, env.pd, \
+                            tab.d, tab.n, split, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip),        \
                             static_cast<TT *>(Io), mom, bnd);                                                     \
     else                                                                                                            \
-      hipLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, tab.n,   \
-                         ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip), static_cast<TT *>(Io), mom, bnd); \
+      hipLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(nt), lds, env.stream, env.sd, env.pd, tab.d, tab.n,  \
+                         split, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip), static_cast<TT *>(Io), mom, \
+                         bnd);                                                                                      \
   } while (0)
   if (f32) {
     switch (K) {

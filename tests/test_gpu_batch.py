@@ -15,16 +15,23 @@ from gpu_util import assert_close, note, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8])
-def test_every_sweep_tile_matches_oracle(K):
-    note(f"sweep tile K={K}")
-    slab = inputs.make_slab(300, 3, 16, T_left=1.0, T_right=0.5)
+TILES = [(K, S, 16) for K in (1, 2, 4, 8) for S in (1, 2, 4)] + [(2, 2, 6), (4, 4, 6), (1, 4, 2), (8, 2, 2)]
+
+
+@pytest.mark.parametrize("K,S,nmu", TILES)
+def test_every_sweep_tile_matches_oracle(K, S, nmu):
+    """Every tile (K cells per lane, S wavefronts sharing a group's half range)
+    against the oracle sweep, incl. direction counts that S does not divide
+    (wavefronts with one or no direction)."""
+    note(f"sweep tile K={K} split={S} nmu={nmu}")
+    slab = inputs.make_slab(300, 3, nmu, T_left=1.0, T_right=0.5)
     sv = binding.Solver([slab], [[3, 1]], inputs.SolverCfg(levels=[3, 1]))
-    sv.set_tiles([K] * 6)
-    rng = np.random.default_rng(K)
+    sv.set_tiles([K] * 6, [S] * 6)
+    assert sv.get_tiles()[:2] == ([K] * 6, [S] * 6)
+    rng = np.random.default_rng(K + 10 * S + nmu)
     kap = 10 ** rng.uniform(-2, 4, (3, 300))
     B = rng.uniform(0, 1, (3, 300))
-    Ip = rng.uniform(0, 1, (3, 16, 300, 2))
+    Ip = rng.uniform(0, 1, (3, nmu, 300, 2))
     Io = sv.empty(binding.TR_K_I)
     mom, bnd = sv.empty(binding.TR_K_GI, 4), sv.empty(binding.TR_K_G, 6)
     sv.sweep(to_dev(kap), to_dev(B), to_dev(Ip), Io, mom, bnd)
@@ -100,8 +107,9 @@ def test_batch_sampled_slabs_match_oracle():
         assert_close(f"slab {k} T", T, ref.T, 1e-10, atol_scale=0.0)
         assert_close(f"slab {k} E", E.reshape(ref.E.shape), ref.E, 1e-10)
         assert_close(f"slab {k} I", I.reshape(ref.I.shape), ref.I, 1e-10)
-    K, items = sv.get_tiles()
+    K, S, items = sv.get_tiles()
     assert all(k in (1, 2, 4, 8) for k in K)
+    assert all(k in (1, 2, 4) for k in S)
     assert sum(items) == sum(s.ng for s in slabs)
     sv.close()
 
