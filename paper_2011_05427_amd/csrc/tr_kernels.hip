@@ -646,25 +646,49 @@ struct RowData {
 
 template <int K, bool FINE>
 __device__ inline void lo_load(const LevelView &v, RowData<K> &R) {
+  // branch-free: buffer loads outside a row's range return zero, so every
+  // load of the thread is issued before the first use
   const int t = threadIdx.x, nx = v.nx;
+  const int cb = nx * 8, eb = (nx + 1) * 8;
+  const __amdgpu_buffer_rsrc_t r_dx = buf_rsrc(v.dx, cb), r_Fo = buf_rsrc(v.Fold, eb), r_Eo = buf_rsrc(v.Eold, cb);
 #pragma unroll
   for (int q = 0; q <= K; ++q) {
     const int e = t * K - 1 + q;
-    R.ae[q] = R.be[q] = R.sr[q] = R.Fo[q] = 0.0;
-    R.h[q] = 1.0;
-    if (e < 0 || e > nx) continue;
-    lv_edge<FINE>(v, e, R.ae[q], R.be[q], R.sr[q]);
-    R.h[q] = lv_h(v, e);
-    R.Fo[q] = v.Fold[e];
+    const bool in = e >= 0 && e <= nx;
+    const double dxm = buf_load_f64(r_dx, (e - 1) * 8), dxe = buf_load_f64(r_dx, e * 8);
+    R.h[q] = in ? 0.5 * (dxm + dxe) : 1.0;
+    R.Fo[q] = buf_load_f64(r_Fo, e * 8);
+    if (FINE) {
+      const __amdgpu_buffer_rsrc_t r_f = buf_rsrc(v.f, cb), r_k = buf_rsrc(v.kap, cb);
+      const double fe = buf_load_f64(r_f, e * 8), fm = buf_load_f64(r_f, (e - 1) * 8);
+      const double ke = buf_load_f64(r_k, e * 8), km = buf_load_f64(r_k, (e - 1) * 8);
+      // boundary factors are added (the cell loads are zero there), so that
+      // no load is conditional
+      R.ae[q] = fe + (e == nx ? v.fbnd[1] : 0.0);
+      R.be[q] = fm + (e == 0 ? v.fbnd[0] : 0.0);
+      // width-weighted sigma_R of the two cells (one cell on the boundary)
+      const double id = (e > 0 && e < nx) ? 1.0 / (dxm + dxe) : 0.0;
+      const double wm = (e == nx) ? 1.0 : dxm * id, we = (e == 0) ? 1.0 : dxe * id;
+      R.sr[q] = km * wm + ke * we;
+    } else {
+      R.ae[q] = buf_load_f64(buf_rsrc(v.a, eb), e * 8);
+      R.be[q] = buf_load_f64(buf_rsrc(v.b, eb), e * 8);
+      R.sr[q] = buf_load_f64(buf_rsrc(v.sigR, eb), e * 8);
+    }
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int i = t * K + k - 1;
-    R.dx[k] = R.Eo[k] = R.se[k] = R.em[k] = 0.0;
-    if (i < 0 || i >= nx) continue;
-    R.dx[k] = v.dx[i];
-    R.Eo[k] = v.Eold[i];
-    lv_cell<FINE>(v, i, R.se[k], R.em[k]);
+    R.dx[k] = buf_load_f64(r_dx, i * 8);
+    R.Eo[k] = buf_load_f64(r_Eo, i * 8);
+    if (FINE) {
+      const double kap = buf_load_f64(buf_rsrc(v.kap, cb), i * 8);
+      R.se[k] = kap;
+      R.em[k] = 2.0 * kap * buf_load_f64(buf_rsrc(v.Bt, cb), i * 8);
+    } else {
+      R.se[k] = buf_load_f64(buf_rsrc(v.sigE, cb), i * 8);
+      R.em[k] = buf_load_f64(buf_rsrc(v.emis, cb), i * 8);
+    }
   }
   R.C0 = v.C[0];
   R.C1 = v.C[1];
