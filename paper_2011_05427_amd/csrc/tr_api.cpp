@@ -184,7 +184,8 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
     } else {
       const int ntile = (ne + 63) / 64;
       for (long long q = 0; q < (long long)nt * cpb * ntile; ++q) part.push_back({s, (int)q});
-      const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
+      const int RE = restrict_fin_edges(cpb);
+      const int nb = (ne + RE - 1) / RE;
       for (int q = 0; q < nt * nb; ++q) fin.push_back({s, q});
     }
   }

@@ -96,6 +96,9 @@ __host__ __device__ inline int restrict_cpb(int r, int nto, int ne, int target) 
   const int rcw = restrict_rcw(r, nto, ne, target);
   return (r + 4 * rcw - 1) / (4 * rcw);
 }
+// Edges per block of the final pass: TR_RFIN_E, or a quarter of it when 16
+// or more chunk records per edge are split over four parts.
+__host__ __device__ inline int restrict_fin_edges(int cpb) { return cpb >= 16 ? TR_RFIN_E / 4 : TR_RFIN_E; }
 
 struct RestrictTables {
   Table single, part, fin;

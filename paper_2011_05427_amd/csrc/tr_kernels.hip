@@ -1148,12 +1148,18 @@ __global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict
   for (int j = threadIdx.x; j < nval; j += 256) rec[j] = sh[0][j];
 }
 
+// Final pass: block = restrict_fin_edges(cpb) edges of one coarse group;
+// thread = (part u, edge, field) adds the chunk records q = u, u + U, ...
+// (U = 4 parts for 16 or more records, else 1); the parts are combined in a
+// fixed order, ((u0 + u1) + (u2 + u3)).
 template <bool OLD>
 __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restrict__ sd, ProbDev pd,
                                                         const Item *__restrict__ tab, const Ctl *ctl, int pmode,
                                                         int lcyc, int from, int to, LoOut out,
                                                         const double *__restrict__ red) {
-  __shared__ double sums[TR_RFIN_E][R_N];
+  constexpr int NF = rec_fields<OLD>();
+  static_assert(TR_RFIN_E * R_N <= 256, "final pass block");
+  __shared__ double sums[TR_RFIN_E * R_N];
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
@@ -1161,28 +1167,35 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
   const int cpb = restrict_cpb(r, nto, ne, S.rtarget);
-  const int nb = (ne + TR_RFIN_E - 1) / TR_RFIN_E;
+  const int RE = restrict_fin_edges(cpb), U = TR_RFIN_E / RE;
+  const int NP = RE * NF;  // (edge, field) pairs of the block
+  const int nb = (ne + RE - 1) / RE;
   const int p = it.idx / nb, b = it.idx - p * nb;
   const int t = threadIdx.x;
-  constexpr int NF = rec_fields<OLD>();
-  const int el = t / NF, k = t - el * NF;
-  const int e = b * TR_RFIN_E + el;
-  if (el < TR_RFIN_E) {
+  const int u = t / NP, pr = t - u * NP;
+  const int el = pr / NF, k = pr - el * NF;
+  const int e = b * RE + el;
+  if (u < U) {
     double acc = 0.0;
     if (e < ne) {
-      const double *rec = red + S.o_red + ((long long)p * cpb * ne + e) * NF + k;
       const long long stride = (long long)ne * NF;
-#pragma unroll 8
-      for (int q = 0; q < cpb; ++q) acc += rec[q * stride];
+      const double *rec = red + S.o_red + ((long long)p * cpb * ne + e) * NF + k + u * stride;
+#pragma unroll 4
+      for (int q = u; q < cpb; q += U, rec += U * stride) acc += *rec;
     }
-    sums[el][k] = acc;
+    sums[u * NP + pr] = acc;
   }
   __syncthreads();
-  if (t < TR_RFIN_E && b * TR_RFIN_E + t < ne) {
+  if (t < RE && b * RE + t < ne) {
     double s[R_N];
 #pragma unroll
-    for (int q = 0; q < R_N; ++q) s[q] = q < NF ? sums[t][q] : 0.0;
-    finalize<OLD>(S, pd, to, p, b * TR_RFIN_E + t, r, s, out);
+    for (int q = 0; q < R_N; ++q) {
+      const int j = t * NF + q;
+      double v = 0.0;
+      if (q < NF) v = U == 4 ? (sums[j] + sums[NP + j]) + (sums[2 * NP + j] + sums[3 * NP + j]) : sums[j];
+      s[q] = v;
+    }
+    finalize<OLD>(S, pd, to, p, b * RE + t, r, s, out);
   }
 }
 
