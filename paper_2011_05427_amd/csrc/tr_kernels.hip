@@ -233,20 +233,17 @@ enum {
   DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143
 };
 
-// LDS transposition buffer of a wavefront (K > 1): pass position p (sweep
-// order, 0 <= p < 64 K) lives in slot p + p / K, one pad slot after every K
-// positions, so that both the segment-major accesses (lane l, position
-// 64 k + l) and the lane-serial ones (lane l, position K l + k, slot
-// (K + 1) l + k) spread over the banks.
-template <int K>
-__device__ inline int tr_slot(int p) {
-  return p + p / K;
-}
+// LDS transposition buffer of a wavefront (K > 1): 64 K slots of 16 bytes;
+// pass position p (sweep order) lives in slot p ^ ((p >> 3) & 7), so that
+// any 8 consecutive lanes of both the segment-major accesses (lane l,
+// position 64 k + l) and the lane-serial ones (lane l, position K l + k)
+// touch 8 different 16-byte bank groups.
+__device__ inline int tr_slot(int p) { return p ^ ((p >> 3) & 7); }
 
 // Doubles of LDS a sweep block needs (launch argument).
 __host__ __device__ inline int sweep_lds_doubles(int K, int split) {
   const int nw = split == 1 ? 4 : split;
-  const int tcol = K > 1 ? 128 * (K + 1) : 0;  // transposition buffer per wavefront
+  const int tcol = K > 1 ? 128 * K : 0;  // transposition buffer per wavefront
   return nw * tcol + (split == 1 ? 0 : split * (K * 128 + 3));
 }
 
@@ -270,8 +267,8 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
   // the partial moments [split][K][64] (phi, chi) and outflow sums [split][3]
   const int nw = split == 1 ? 4 : split;
   const int wslot = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double2 *tb = reinterpret_cast<double2 *>(sred) + (K > 1 ? wslot * 64 * (K + 1) : 0);
-  double2 *red = reinterpret_cast<double2 *>(sred) + (K > 1 ? nw * 64 * (K + 1) : 0);
+  double2 *tb = reinterpret_cast<double2 *>(sred) + (K > 1 ? wslot * 64 * K : 0);
+  double2 *red = reinterpret_cast<double2 *>(sred) + (K > 1 ? nw * 64 * K : 0);
   double *sb = reinterpret_cast<double *>(red + split * K * 64);
   const double inv_cdt = S.inv_cdt;
   const __amdgpu_buffer_rsrc_t r_dx = buf_rsrc(pd.dx + S.o_cell, nx * 8);
@@ -327,11 +324,11 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
       double cx[K], cy[K];  // corner pair of the lane's cells (left, right)
       if (K > 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) tb[tr_slot<K>(k * 64 + lane)] = make_double2((double)nxt[k].x, (double)nxt[k].y);
+        for (int k = 0; k < K; ++k) tb[tr_slot(k * 64 + lane)] = make_double2((double)nxt[k].x, (double)nxt[k].y);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const double2 v = tb[(K + 1) * lane + k];
+          const double2 v = tb[tr_slot(K * lane + k)];
           cx[k] = v.x;
           cy[k] = v.y;
         }
@@ -400,11 +397,11 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
       if (K > 1) {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < K; ++k) tb[(K + 1) * lane + k] = make_double2(ox[k], oy[k]);
+        for (int k = 0; k < K; ++k) tb[tr_slot(K * lane + k)] = make_double2(ox[k], oy[k]);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const double2 v = tb[tr_slot<K>(k * 64 + lane)];
+          const double2 v = tb[tr_slot(k * 64 + lane)];
           PV o;
           o.x = (TI)v.x;
           o.y = (TI)v.y;
@@ -439,11 +436,11 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
     if (sub == 0) {
       if (K > 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) tb[(K + 1) * lane + k] = make_double2(phi[k], chi[k]);
+        for (int k = 0; k < K; ++k) tb[tr_slot(K * lane + k)] = make_double2(phi[k], chi[k]);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const double2 o = tb[tr_slot<K>(k * 64 + lane)];
+          const double2 o = tb[tr_slot(k * 64 + lane)];
           __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, o), r_mp, cell_mem(pass, k) * 16, 0,
                                                  0);
         }
