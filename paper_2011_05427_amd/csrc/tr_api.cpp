@@ -30,7 +30,6 @@ struct tr_ctx {
   tr_solver_cfg cfg{};
   int nlev = 0;
   std::vector<int> sched;
-  int lo_threads = 64;    // block size of the group LO solves
   int grey_threads = 64;  // block size of the grey solve
   int opac_run = 4;       // groups per thread of the opacity kernel (1 or 4)
   std::vector<SlabDev> hs;  // host copies of the slab descriptors
@@ -60,7 +59,9 @@ struct tr_ctx {
   Table t_sweep_b[TR_NBUCKET]{};
   int sweep_K[TR_NBUCKET] = {1, 2, 4, 4, 4, 4};
   int sweep_S[TR_NBUCKET] = {1, 1, 1, 1, 1, 1};  // wavefronts sharing a (group, half range)
-  Table t_lo[TR_MAXLEV]{};
+  // group LO solves per level, by block size 64 << kb (kb = 0..3): a slab's
+  // systems take the smallest block that covers them with 4 rows per thread
+  Table t_lo[4][TR_MAXLEV]{};
   std::map<std::pair<int, int>, RestrictTables> t_red;
   std::map<int, Table> t_pro;  // prolongation work per level
   // optional event timing of kernel groups inside tr_step
@@ -167,6 +168,16 @@ std::vector<int> schedule_for(int cycle, int nlev) {
   return s;
 }
 
+// Block size class of a slab's LO systems (4 rows per thread): 64 << kb
+// threads, the smallest that covers nx + 2 rows.  The padding rows of a
+// larger block do not change the arithmetic of the system's rows.
+int lo_block(int nx) {
+  const int need = (nx + 2 + TR_LO_K - 1) / TR_LO_K;
+  int kb = 0;
+  while ((64 << kb) < need) ++kb;
+  return kb;
+}
+
 int build_restrict_tables(tr_ctx *c, int from, int to) {
   auto key = std::make_pair(from, to);
   if (c->t_red.count(key)) return TR_OK;
@@ -199,6 +210,12 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
 }
 
 LaunchEnv env_of(const tr_ctx *c, hipStream_t st) { return LaunchEnv{c->d_sd, c->pd, st}; }
+
+// LO solves of a level, one launch per block size in use.
+void launch_lo_all(const tr_ctx *c, const LaunchEnv &env, const Ctl *ctl, int pmode, int lcyc, int level,
+                   const LoIn &in, const LoSol &sol) {
+  for (int kb = 0; kb < 4; ++kb) launch_lo(env, c->t_lo[kb][level], 64 << kb, ctl, pmode, lcyc, level, in, sol);
+}
 
 int sweep_bucket(int nx) {
   int b = 0, lim = 64;
@@ -417,7 +434,6 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   c->cfg = *cfg;
   c->nlev = nlev;
   c->sched = schedule_for(cfg->cycle, nlev);
-  c->lo_threads = T;
   c->grey_threads = ((rows + TR_GREY_K - 1) / TR_GREY_K + 63) / 64 * 64;
   c->hs.resize(n_slab);
 
@@ -589,7 +605,8 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     c->opac_run = c->n_gi <= (1LL << 21) ? 1 : 4;
     std::vector<Item> opac, dsum, cell, gi, g, grey;
     std::vector<std::vector<std::pair<long long, Item>>> sweepb(TR_NBUCKET);
-    std::vector<std::vector<Item>> lo(nlev);
+    std::vector<std::vector<Item>> lo[4];
+    for (int kb = 0; kb < 4; ++kb) lo[kb].resize(nlev);
     for (int s = 0; s < n_slab; ++s) {
       const SlabDev &S = c->hs[s];
       const int ncb = (S.nx + 4 * c->opac_run - 1) / (4 * c->opac_run);
@@ -602,7 +619,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       for (int st = 0; st < S.ng; st += 256) g.push_back({s, st});
       grey.push_back({s, 0});
       for (int l = 0; l < nlev; ++l)
-        for (int p = 0; p < S.lev_ng[l]; ++p) lo[l].push_back({s, p});
+        for (int p = 0; p < S.lev_ng[l]; ++p) lo[lo_block(S.nx)][l].push_back({s, p});
     }
     if ((rc = upload_table(c, opac, c->t_opac)) || (rc = upload_table(c, dsum, c->t_dS)) ||
         (rc = upload_table(c, cell, c->t_cell)) ||
@@ -610,7 +627,8 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
         (rc = upload_table(c, g, c->t_g)) || (rc = upload_table(c, grey, c->t_grey)))
       return fail(rc);
     for (int l = 0; l < nlev; ++l)
-      if ((rc = upload_table(c, lo[l], c->t_lo[l]))) return fail(rc);
+      for (int kb = 0; kb < 4; ++kb)
+        if ((rc = upload_table(c, lo[kb][l], c->t_lo[kb][l]))) return fail(rc);
     for (int b = 0; b < TR_NBUCKET; ++b) {
       // longest-processing-time order: the most expensive slabs start first
       auto &v = sweepb[b];
@@ -728,7 +746,7 @@ int tr_lo_solve(tr_ctx *c, int level, const tr_lo_coeffs *in, const tr_lo_fields
   if (level > 0 && (!in->sigE || !in->emis || !in->a || !in->b || !in->sigR)) return TR_EINVAL;
   if (!in->C || !in->Phi || !in->Eold || !in->Fold) return TR_EINVAL;
   LoSol sol{out->E, out->F, out->Ebnd};
-  launch_lo(env_of(c, st), c->t_lo[level], c->lo_threads, nullptr, PRED_ALL, 0, level, coeffs_in(in), sol);
+  launch_lo_all(c, env_of(c, st), nullptr, PRED_ALL, 0, level, coeffs_in(in), sol);
   return hip_err(hipGetLastError());
 }
 
@@ -975,7 +993,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     const bool old = !with_sweep && l == 0;
     {
       TimedScope ts(c, st, TR_T_LO_FINE, l);
-      launch_lo(env, c->t_lo[0], c->lo_threads, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
+      launch_lo_all(c, env, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
     }
     {
       TimedScope ts(c, st, TR_T_RESTRICT, l);
@@ -1000,7 +1018,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       }
       {
         TimedScope ts(c, st, TR_T_LO_COARSE, l);
-        launch_lo(env, c->t_lo[gm], c->lo_threads, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm), level_sol(c, gm));
+        launch_lo_all(c, env, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm), level_sol(c, gm));
       }
       {
         TimedScope ts(c, st, TR_T_RESTRICT, l);
