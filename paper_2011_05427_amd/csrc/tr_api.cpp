@@ -1037,8 +1037,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     }
   }
   // start of the next transport iteration (s + 1) for slabs still iterating
-  launch_outer_begin(env, c->d_ctl, ns, c->cfg.max_outer);
-  launch_count_active(env, c->d_ctl, ns, c->h_count);
+  launch_outer_end(env, c->d_ctl, ns, c->cfg.max_outer, c->h_count);
 }
 
 int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, bool sweep_outside,
@@ -1103,14 +1102,8 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   if (hipMemcpyAsync(c->d_ctl, hc.data(), sizeof(Ctl) * ns, hipMemcpyHostToDevice, gs) != hipSuccess) return TR_EHIP;
   LaunchEnv env = env_of(c, gs);
   // step start: old-time copies, convergence references, Phi with the current incoming
-  launch_copy(env, s->T, c->Told, c->n_cell);
-  launch_copy(env, s->T, c->Ts, c->n_cell);
-  launch_copy(env, s->T, c->Tcyc, c->n_cell);
-  launch_copy(env, s->T, c->Tstar, c->n_cell);
-  launch_copy(env, s->Egrey, c->Es, c->n_cell);
-  launch_copy(env, s->Egrey, c->Ecyc, c->n_cell);
-  launch_copy(env, s->E, c->Eold, c->n_gi);
-  launch_copy(env, s->F, c->Fold, c->n_ge);
+  launch_step_start(env, s->T, s->Egrey, s->E, s->F, c->n_cell, c->n_gi, c->n_ge, c->Told, c->Ts, c->Tcyc, c->Tstar,
+                    c->Es, c->Ecyc, c->Eold, c->Fold);
   launch_phi(env, c->t_g, s->C, c->Phi);
   launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
   unsigned long long seed_counts[2] = {0, 0};

@@ -107,8 +107,13 @@ void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *
                      int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, bool old);
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga);
-void launch_outer_begin(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer);
-void launch_count_active(const LaunchEnv &env, const Ctl *ctl, int nslab, int *out);
+// End of a transport iteration (start of s + 1 where the inner iteration is
+// done) and the count of slabs still active into *out (one launch).
+void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out);
+// Step-start copies of T, Egrey, E, F into the step's reference arrays.
+void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
+                       long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
+                       double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold);
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n);
 void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
 void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,

@@ -5,6 +5,8 @@
 // sequence serves a batch of slabs that converge at different iterations.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "tr_device.h"
 #include "tr_kernels.h"
 
@@ -1407,28 +1409,56 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
 // ---------------------------------------------------------------------------
 // Control and state kernels.
 // ---------------------------------------------------------------------------
-// Start of a transport iteration s >= 1 (one thread per slab).
-__global__ void k_outer_begin(Ctl *ctl, int nslab, int max_outer) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nslab) return;
-  Ctl &c = ctl[s];
-  if (!c.active || !c.inner_done) return;
-  c.s += 1;
-  if (c.s > max_outer || (c.n_replay > 0 && c.s >= c.n_replay)) {
-    if (c.n_replay == 0) c.err = -4;
-    c.active = 0;
-    return;
+// End of a transport iteration: slabs whose inner iteration finished start
+// iteration s + 1 (or stop at the iteration limit / replay length), and the
+// number of slabs still active is written to *out.  One block of 256
+// threads; slabs s = t, t + 256, ...; the count is summed exactly.
+__global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_outer, int *out) {
+  __shared__ int part[4];
+  int n = 0;
+  for (int s = threadIdx.x; s < nslab; s += blockDim.x) {
+    Ctl &c = ctl[s];
+    if (c.active && c.inner_done) {
+      c.s += 1;
+      if (c.s > max_outer || (c.n_replay > 0 && c.s >= c.n_replay)) {
+        if (c.n_replay == 0) c.err = -4;
+        c.active = 0;
+      } else {
+        c.inner_done = 0;
+        c.ncyc = 0;
+        c.n_ti += 1;
+      }
+    }
+    n += c.active;
   }
-  c.inner_done = 0;
-  c.ncyc = 0;
-  c.n_ti += 1;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) n += __shfl_xor(n, d);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
-__global__ void k_count_active(const Ctl *ctl, int nslab, int *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int n = 0;
-  for (int s = 0; s < nslab; ++s) n += ctl[s].active;
-  *out = n;
+// Step start: copies of the state into the step's references (T into Told,
+// Ts, Tcyc, Tstar; Egrey into Es, Ecyc; E into Eold; F into Fold).
+struct StepCopies {
+  const double *T, *Egrey, *E, *F;
+  double *Told, *Ts, *Tcyc, *Tstar, *Es, *Ecyc, *Eold, *Fold;
+  long long n_cell, n_gi, n_ge;
+};
+
+__global__ __launch_bounds__(256) void k_step_start(StepCopies a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n_cell) {
+    const double t = a.T[i], e = a.Egrey[i];
+    a.Told[i] = t;
+    a.Ts[i] = t;
+    a.Tcyc[i] = t;
+    a.Tstar[i] = t;
+    a.Es[i] = e;
+    a.Ecyc[i] = e;
+  }
+  if (i < a.n_gi) a.Eold[i] = a.E[i];
+  if (i < a.n_ge) a.Fold[i] = a.F[i];
 }
 
 // Elementwise copy over a pooled range.
@@ -1739,12 +1769,17 @@ void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, 
                      lcyc, ga);
 }
 
-void launch_outer_begin(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer) {
-  hipLaunchKernelGGL(k_outer_begin, dim3((nslab + 255) / 256), dim3(256), 0, env.stream, ctl, nslab, max_outer);
+void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out) {
+  hipLaunchKernelGGL(k_outer_end, dim3(1), dim3(256), 0, env.stream, ctl, nslab, max_outer, out);
 }
 
-void launch_count_active(const LaunchEnv &env, const Ctl *ctl, int nslab, int *out) {
-  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, env.stream, ctl, nslab, out);
+void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
+                       long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
+                       double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold) {
+  const StepCopies a{T, Egrey, E, F, Told, Ts, Tcyc, Tstar, Es, Ecyc, Eold, Fold, n_cell, n_gi, n_ge};
+  const long long n = std::max(n_cell, std::max(n_gi, n_ge));
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_step_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, a);
 }
 
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n) {
