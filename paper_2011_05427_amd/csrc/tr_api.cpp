@@ -63,6 +63,11 @@ struct tr_ctx {
   // systems take the smallest block that covers them with 4 rows per thread
   Table t_lo[4][TR_MAXLEV]{};
   std::map<std::pair<int, int>, RestrictTables> t_red;
+  // stage restrictions fine -> level computing kappa / B themselves (tiles of
+  // 63 edges) and their dS partials
+  std::map<int, RestrictTables> t_red_op;
+  double *dsop = nullptr;
+  long long n_dsop = 0;
   std::map<int, Table> t_pro;  // prolongation work per level
   // optional event timing of kernel groups inside tr_step
   struct TimedGroup {
@@ -178,9 +183,12 @@ int lo_block(int nx) {
   return kb;
 }
 
-int build_restrict_tables(tr_ctx *c, int from, int to) {
+// Work tables of the restriction from -> to; mode 1 = the stage restriction
+// fine -> level computing the tables itself (tiles of 63 edges).
+int build_restrict_tables(tr_ctx *c, int from, int to, int mode = 0) {
   auto key = std::make_pair(from, to);
-  if (c->t_red.count(key)) return TR_OK;
+  if (mode == 0 ? c->t_red.count(key) != 0 : c->t_red_op.count(to) != 0) return TR_OK;
+  const int TE = restrict_tile(mode);
   std::vector<Item> single, part, fin;
   for (int s = 0; s < c->nslab; ++s) {
     const SlabDev &S = c->hs[s];
@@ -189,11 +197,11 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
     const int r = nf / nt;
     const int cpb = restrict_cpb(r, nt, ne, S.rtarget);
     if (cpb == 1) {
-      // four wavefront items (coarse group, tile of 64 edges) per block
-      const int nwi = nt * ((ne + 63) / 64);
+      // four wavefront items (coarse group, tile of edges) per block
+      const int nwi = nt * ((ne + TE - 1) / TE);
       for (int q = 0; 4 * q < nwi; ++q) single.push_back({s, q});
     } else {
-      const int ntile = (ne + 63) / 64;
+      const int ntile = (ne + TE - 1) / TE;
       for (long long q = 0; q < (long long)nt * cpb * ntile; ++q) part.push_back({s, (int)q});
       const int RE = restrict_fin_edges(cpb);
       const int nb = (ne + RE - 1) / RE;
@@ -205,7 +213,10 @@ int build_restrict_tables(tr_ctx *c, int from, int to) {
   if (!rc) rc = upload_table(c, part, rt.part);
   if (!rc) rc = upload_table(c, fin, rt.fin);
   if (rc) return rc;
-  c->t_red[key] = rt;
+  if (mode == 0)
+    c->t_red[key] = rt;
+  else
+    c->t_red_op[to] = rt;
   return TR_OK;
 }
 
@@ -503,7 +514,18 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
           const int cpb = restrict_cpb(r, P.level_ng[b], P.nx + 1, S.rtarget);
           if (cpb > 1) worst = std::max(worst, (long long)P.level_ng[b] * cpb);
         }
-      c->n_red += worst * (P.nx + 1) * 21;
+      c->n_red += worst * (P.nx + 1) * 22;  // up to 22 fields per record
+    }
+    {
+      // stage dS partials: rows per cell of the fused restriction fine -> gm
+      long long worst = 0;
+      for (int gm : c->sched) {
+        const int r = P.level_ng[0] / P.level_ng[gm];
+        S.dsnp[gm] = P.level_ng[gm] * restrict_cpb(r, P.level_ng[gm], P.nx + 1, S.rtarget);
+        worst = std::max(worst, (long long)S.dsnp[gm]);
+      }
+      S.o_dsop = c->n_dsop;
+      c->n_dsop += worst * P.nx;
     }
     S.o_lpi[0] = S.o_gi;
     S.o_lpe[0] = S.o_ge;
@@ -560,7 +582,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   if ((rc = dalloc(c, &c->kappa, c->n_gi)) || (rc = dalloc(c, &c->B, c->n_gi)) ||
       (rc = dalloc(c, &c->dSpart, c->n_chunk)) || (rc = dalloc(c, &c->mom, 4 * c->n_gi)) ||
       (rc = dalloc(c, &c->bnd, 6 * c->n_g)) || (rc = dalloc(c, &c->Phi, 2 * c->n_g)) ||
-      (rc = dalloc(c, &c->Eold, c->n_gi)) || (rc = dalloc(c, &c->Fold, c->n_ge)) || (rc = dalloc(c, &c->red, c->n_red)))
+      (rc = dalloc(c, &c->Eold, c->n_gi)) || (rc = dalloc(c, &c->Fold, c->n_ge)) || (rc = dalloc(c, &c->red, c->n_red)) || (rc = dalloc(c, &c->dsop, c->n_dsop)))
     return fail(rc);
   double **cells[] = {&c->dS, &c->Told, &c->Ts, &c->Tcyc, &c->Tstar, &c->Tprev, &c->sigprev, &c->Ecyc, &c->Es};
   for (double **p : cells)
@@ -639,7 +661,8 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     }
     if ((rc = build_restrict_tables(c, 0, nlev - 1))) return fail(rc);
     for (int gsched : c->sched) {
-      if ((rc = build_restrict_tables(c, 0, gsched)) || (rc = build_restrict_tables(c, gsched, nlev - 1)))
+      if ((rc = build_restrict_tables(c, 0, gsched)) || (rc = build_restrict_tables(c, 0, gsched, 1)) ||
+          (rc = build_restrict_tables(c, gsched, nlev - 1)))
         return fail(rc);
     }
   }
@@ -1008,13 +1031,11 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     for (int q = 0; q < nsch; ++q) {
       const int gm = c->sched[q];
       {
-        TimedScope ts(c, st, TR_T_OPACITY, l);
-        launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart);
-      }
-      {
+        // the stage's kappa, B at T* are evaluated inside the restriction
+        // (not written to the tables), with the stage dS partials
         TimedScope ts(c, st, TR_T_RESTRICT, l);
-        launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
-                        level_out(c, gm), c->red, old);
+        launch_restrict(env, c->t_red_op[gm], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol, level_out(c, gm), c->red,
+                        old, 1, c->Tstar, c->dsop);
       }
       {
         TimedScope ts(c, st, TR_T_LO_COARSE, l);
@@ -1023,7 +1044,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
       {
         TimedScope ts(c, st, TR_T_RESTRICT, l);
         launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
-                        level_sol(c, gm), grey_out(c), c->red, old);
+                        level_sol(c, gm), grey_out(c), c->red, old, 2, nullptr, c->dsop);
       }
       ga.end_cycle = q == nsch - 1;
       {

@@ -24,6 +24,8 @@ struct SlabDev {
   long long o_cell, o_edge, o_I, o_gi, o_ge, o_g, o_g2, o_nu, o_mu, o_chunk;
   long long o_lpi[TR_MAXLEV], o_lpe[TR_MAXLEV], o_lp2[TR_MAXLEV];
   long long o_red;  // restriction scratch records (per slab)
+  long long o_dsop;          // stage dS partials (per slab)
+  int dsnp[TR_MAXLEV];       // stage dS partial rows of the restriction fine -> level
 };
 
 // Problem constants (device, pooled).

@@ -77,13 +77,18 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
 // Restriction work: coarse groups of r <= 16 finer groups are done in one pass;
 // larger r in a chunk pass plus a final pass over blocks of TR_RFIN_E edges.
 // old: also restrict the old-time E and F (out.Eold / out.Fold are written
-// only then).
+// only then).  mode 1 (fine to a stage level): kappa and B are computed at
+// the cell temperatures T instead of read, in tiles of 63 edges (tables from
+// build with restrict_tile(1)), and the stage dS partials of every cell go to
+// dsop (S.dsnp[to] rows of nx per slab at S.o_dsop); mode 2 (stage level to
+// grey): those partials are added into out.dS.
+inline int restrict_tile(int mode) { return mode == 1 ? 63 : 64; }
 // In the chunk pass a block of 4 wavefronts covers 64 edges and 4 rcw finer
 // groups (rcw per wavefront), giving cpb chunk records per coarse group.  rcw
 // grows (fewer records to write and re-read) while a slab's pass keeps at
 // least `target` blocks (4096 over the slabs of a context), and so that
 // cpb <= 64.
-#define TR_RFIN_E 12
+#define TR_RFIN_E 11
 __host__ __device__ inline int restrict_rcw(int r, int nto, int ne, int target) {
   const int ntile = (ne + 63) / 64;
   int rcw = 1;
@@ -96,15 +101,16 @@ __host__ __device__ inline int restrict_cpb(int r, int nto, int ne, int target) 
   const int rcw = restrict_rcw(r, nto, ne, target);
   return (r + 4 * rcw - 1) / (4 * rcw);
 }
-// Edges per block of the final pass: TR_RFIN_E, or a quarter of it when 16
-// or more chunk records per edge are split over four parts.
+// Edges per block of the final pass: TR_RFIN_E, or a quarter of it (rounded
+// down) when 16 or more chunk records per edge are split over four parts.
 __host__ __device__ inline int restrict_fin_edges(int cpb) { return cpb >= 16 ? TR_RFIN_E / 4 : TR_RFIN_E; }
 
 struct RestrictTables {
   Table single, part, fin;
 };
 void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
-                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, bool old);
+                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, bool old,
+                     int mode = 0, const double *T = nullptr, double *dsop = nullptr);
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga);
 // End of a transport iteration (start of s + 1 where the inner iteration is

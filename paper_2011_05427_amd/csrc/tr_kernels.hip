@@ -37,6 +37,24 @@ __device__ inline bool pred_ok(const Ctl *ctl, int slab, int mode, int l) {
   return true;
 }
 
+// Opacity and group Planck function of group g (centre nu, edge integrals
+// lo / hi) in a cell (1/T = iT, opacity constant Cc, scale = a_R c T^4 / 2 /
+// (pi^4 / 15)); returns the group's term of dS = d/dT sum 2 kappa B.  Shared
+// by the table kernel and the stage restriction, so both give the same bits.
+__device__ inline double planck_group(double nu, const EdgeQ &lo, const EdgeQ &hi, double iT, double Cc,
+                                      double scale, double &kap, double &Bg) {
+  Bg = scale * q_interval(lo, hi);
+  const double dBg = (4.0 * Bg - scale * (hi.g4 - lo.g4)) * iT;
+  const double y = nu * iT;
+  // 1 - e^{-y} from the same exponential unless y is small (cancellation)
+  const double ey = exp(-y);
+  const double om = y > 0.5 ? 1.0 - ey : -expm1(-y);
+  const double cn = Cc / (nu * nu);
+  kap = cn / nu * om;
+  const double dkap = -cn * ey * iT * iT;
+  return 2.0 * (dkap * Bg + kap * dBg);
+}
+
 // ---------------------------------------------------------------------------
 // A1: opacity and group Planck tables at T, with the 64-group chunk partial
 // sums of dS = d/dT sum_g 2 kappa_g B_g.  Block = one 64-group chunk x 4 RUN
@@ -76,20 +94,11 @@ __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd,
       const int g = g0 + q;
       if (g >= g1) break;
       const EdgeQ hi = edge_q(nue[g + 1], iT);
-      const double Bg = scale * q_interval(lo, hi);
-      const double dBg = (4.0 * Bg - scale * (hi.g4 - lo.g4)) * iT;
-      const double nu = nuc[g];
-      const double y = nu * iT;
-      // 1 - e^{-y} from the same exponential unless y is small (cancellation)
-      const double ey = exp(-y);
-      const double om = y > 0.5 ? 1.0 - ey : -expm1(-y);
-      const double cn = Cc / (nu * nu);
-      const double kap = cn / nu * om;
-      const double dkap = -cn * ey * iT * iT;
+      double kap, Bg;
+      dS += planck_group(nuc[g], lo, hi, iT, Cc, scale, kap, Bg);
       const long long o = S.o_gi + (long long)g * nx + i;
       kappa[o] = kap;
       B[o] = Bg;
-      dS += 2.0 * (dkap * Bg + kap * dBg);
       lo = hi;
     }
   }
@@ -232,7 +241,7 @@ __device__ inline void scan_step(double &A, double &B) {
 
 enum {
   DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118,
-  DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143
+  DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143
 };
 
 // LDS transposition buffer of a wavefront (K > 1): 64 K slots of 16 bytes;
@@ -851,20 +860,31 @@ __global__ __launch_bounds__(512) void k_lo(const SlabDev *__restrict__ sd, Prob
 // A5: restriction.  Sum records per (block of finer groups, edge e): e < nx
 // also carries the sums of cell e, e = 0 / nx the boundary sums of side 0 / 1.
 // ---------------------------------------------------------------------------
-// The old-time sums (last two fields) are constant during a time step: a
-// step restricts them in its first cycle only (OLD), records without them
-// hold R_NC fields.
+// The old-time sums (R_EOLD, R_FOLD) are constant during a time step: a step
+// restricts them in its first cycle only (OLD); records without them hold
+// R_NC fields.  In a grey stage (Alg. 3) the fine-to-coarse restriction
+// computes kappa and B at the stage temperature itself (mode RM_OPAC) and
+// leaves per-cell partial sums of dS; the coarse-to-grey restriction of the
+// same stage adds them up as one more record field, R_DS (mode RM_DSF).
 enum {
   R_E = 0, R_SEE, R_SE, R_EM,               // cell
   R_ER, R_AER, R_A, R_EL, R_BEL, R_B,       // edge: right / left weights
   R_AF, R_SAF, R_S, R_SF, R_F,              // edge: |F| weights, flux sums
   R_EB, R_CEB, R_C, R_PHI,                  // boundary side
   R_EOLD, R_FOLD,                           // old-time cell / edge sums
-  R_N
+  R_N,
+  R_DS = R_N,                               // stage dS of cell e (RM_DSF)
+  R_NA                                      // accumulator size
 };
 constexpr int R_NC = R_EOLD;
+enum { RM_PLAIN = 0, RM_OPAC = 1, RM_DSF = 2 };
+// Fields of a record: the present sums in enum order, then R_DS (RM_DSF).
+template <bool OLD, int MODE>
+constexpr int rec_fields() { return (OLD ? R_N : R_NC) + (MODE == RM_DSF ? 1 : 0); }
 template <bool OLD>
-constexpr int rec_fields() { return OLD ? R_N : R_NC; }
+__device__ inline int rec_src(int k) {  // accumulator index of record field k
+  return k < (OLD ? R_N : R_NC) ? k : R_DS;
+}
 
 // Values of one finer group at edge e (lane), loaded without branches:
 // buffer loads out of a row's range (cell e = nx, cell e - 1 = -1, lanes past
@@ -874,6 +894,7 @@ struct EdgeVals {
   double ae, be, sr;       // edge e
   double ER, EL, F;        // E right / left of the edge, flux
   double Eo, Fo;           // old-time cell / edge values (OLD only)
+  double ds;               // stage dS partials of cell e (RM_DSF only)
   double Eb0, Eb1, C0, C1, P0, P1;  // group boundary values (wave-uniform)
 };
 
@@ -896,12 +917,36 @@ __device__ inline EdgeGeo edge_geo(const SlabDev &S, ProbDev pd, int e) {
   return q;
 }
 
+// Stage opacity of the lane's own cell c = e - 1 (RM_OPAC): 1 / T, the
+// opacity constant and the Planck scale, zero for cells outside the slab.
+struct CellOpac {
+  double iT, Cc, scale;
+  const double *nue, *nuc;
+};
+
+__device__ inline CellOpac cell_opac(const SlabDev &S, ProbDev pd, const double *T, int c) {
+  CellOpac o;
+  const bool in = c >= 0 && c < S.nx;
+  const double Tc = in ? buf_load_f64(buf_rsrc(T + S.o_cell, S.nx * 8), c * 8) : 1.0;
+  o.Cc = buf_load_f64(buf_rsrc(pd.Ccell + S.o_cell, S.nx * 8), c * 8);
+  o.iT = 1.0 / Tc;
+  const double T2 = Tc * Tc;
+  o.scale = in ? S.aR * S.c * T2 * T2 * 0.5 / TR_PI4_15 : 0.0;
+  o.nue = pd.nu_e + S.o_nu;
+  o.nuc = pd.nu_c + S.o_g;
+  return o;
+}
+
 // Loads group g of level `from` at edge q.e (g wave-uniform).  With valid
 // false every value is zero (empty buffer ranges, boundary values times 0),
-// so that the caller can add it without a branch.
-template <bool FINE, bool OLD>
+// so that the caller can add it without a branch.  RM_OPAC: the cell values
+// kappa / B come from the caller (km, ke: cells e - 1, e; Be: cell e).
+// RM_DSF: v.ds = the dS partials of coarse group g at cell e (dsp partials
+// per coarse group, row stride nx).
+template <bool FINE, bool OLD, int MODE>
 __device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, const LoSol &sol, int g, bool valid,
-                                  const EdgeGeo &q, EdgeVals &v) {
+                                  const EdgeGeo &q, double km, double ke, double Be, const double *dsop, int dsp,
+                                  EdgeVals &v) {
   const int nx = S.nx, e = q.e;
   const int oe = e * 8, om = (e - 1) * 8;
   const int cb = valid ? nx * 8 : 0, eb = valid ? (nx + 1) * 8 : 0;
@@ -909,11 +954,14 @@ __device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, co
   if (FINE) {
     const long long gi = S.o_gi + (long long)g * nx, ge = S.o_ge + (long long)g * (nx + 1);
     const long long g2 = 2 * S.o_g + 2 * (long long)g;
-    const __amdgpu_buffer_rsrc_t rk = buf_rsrc(in.kappa + gi, cb), rb = buf_rsrc(in.B + gi, cb);
+    if (MODE != RM_OPAC) {
+      const __amdgpu_buffer_rsrc_t rk = buf_rsrc(in.kappa + gi, cb), rb = buf_rsrc(in.B + gi, cb);
+      ke = buf_load_f64(rk, oe);
+      km = buf_load_f64(rk, om);
+      Be = buf_load_f64(rb, oe);
+    }
     const __amdgpu_buffer_rsrc_t rf = buf_rsrc(in.f + gi, cb), rE = buf_rsrc(sol.E + gi, cb);
     const __amdgpu_buffer_rsrc_t rF = buf_rsrc(sol.F + ge, eb);
-    const double ke = buf_load_f64(rk, oe), km = buf_load_f64(rk, om);
-    const double Be = buf_load_f64(rb, oe);
     const double fe = buf_load_f64(rf, oe), fm = buf_load_f64(rf, om);
     const double Ee = buf_load_f64(rE, oe), Em = buf_load_f64(rE, om);
     v.F = buf_load_f64(rF, oe);
@@ -928,13 +976,13 @@ __device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, co
     v.C1 = m * in.C[g2 + 1];
     v.P0 = m * in.Phi[g2];
     v.P1 = m * in.Phi[g2 + 1];
-    v.se = ke;
-    v.em = 2.0 * ke * Be;
+    v.se = m * ke;
+    v.em = m * (2.0 * ke * Be);
     // out-of-range loads are zero: boundary values are added, not selected,
     // so that every load is used on every lane (no branch around a load)
     v.ae = fe + (e == nx ? fb1 : 0.0);
     v.be = fm + (e == 0 ? fb0 : 0.0);
-    v.sr = km * q.wm + ke * q.we;
+    v.sr = m * (km * q.wm + ke * q.we);
     v.ER = Ee + (e == nx ? v.Eb1 : 0.0);
     v.EL = Em + (e == 0 ? v.Eb0 : 0.0);
   } else {
@@ -952,6 +1000,12 @@ __device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, co
       v.Eo = buf_load_f64(buf_rsrc(in.Eold + pi, cb), oe);
       v.Fo = buf_load_f64(buf_rsrc(in.Fold + pe, eb), oe);
     }
+    if (MODE == RM_DSF) {
+      const double *row = dsop + S.o_dsop + (long long)g * dsp * nx;
+      double t = 0.0;
+      for (int b = 0; b < dsp; ++b) t += buf_load_f64(buf_rsrc(row + (long long)b * nx, cb), oe);
+      v.ds = t;
+    }
     v.Eb0 = m * sol.Ebnd[p2];
     v.Eb1 = m * sol.Ebnd[p2 + 1];
     v.C0 = m * in.C[p2];
@@ -963,8 +1017,8 @@ __device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, co
   }
 }
 
-template <bool OLD>
-__device__ inline void add_group(const EdgeVals &v, const EdgeGeo &q, double (&r)[R_N]) {
+template <bool OLD, int MODE>
+__device__ inline void add_group(const EdgeVals &v, const EdgeGeo &q, double (&r)[R_NA]) {
   r[R_E] += v.ER;  // cell sums of e = nx are not used
   r[R_SEE] += v.se * v.ER;
   r[R_SE] += v.se;
@@ -983,6 +1037,7 @@ __device__ inline void add_group(const EdgeVals &v, const EdgeGeo &q, double (&r
   r[R_SF] += v.sr * v.F;
   r[R_F] += v.F;
   if (OLD) r[R_FOLD] += v.Fo;
+  if (MODE == RM_DSF) r[R_DS] += v.ds;
   const bool b0 = q.e == 0, b1 = q.e == q.nx;
   const double Eb = b0 ? v.Eb0 : b1 ? v.Eb1 : 0.0;
   const double Cs = b0 ? v.C0 : b1 ? v.C1 : 0.0;
@@ -994,24 +1049,51 @@ __device__ inline void add_group(const EdgeVals &v, const EdgeGeo &q, double (&r
 
 // Adds finer groups [g0, g1) (wave-uniform) at this lane's edge, two groups'
 // loads in flight per step, in ascending group order (a missing second group
-// of an odd count adds zeros, which leaves the sums unchanged).
-template <bool FINE, bool OLD>
-__device__ inline void acc_groups(const SlabDev &S, int from, const LoIn &in, const LoSol &sol, int g0, int g1,
-                                  const EdgeGeo &q, double (&acc)[R_N]) {
-  for (int g = g0; g < g1; g += 2) {
-    const bool two = g + 1 < g1;
-    EdgeVals a, b;
-    load_group<FINE, OLD>(S, from, in, sol, g, true, q, a);
-    load_group<FINE, OLD>(S, from, in, sol, two ? g + 1 : g, two, q, b);
-    add_group<OLD>(a, q, acc);
-    add_group<OLD>(b, q, acc);
+// of an odd count adds zeros, which leaves the sums unchanged).  RM_OPAC:
+// the lane also evaluates kappa, B of its own cell c = e - 1 for every group
+// (the right cell's values come from the next lane) and returns the cell's
+// dS partial sum over the groups.
+template <bool FINE, bool OLD, int MODE>
+__device__ inline double acc_groups(const SlabDev &S, ProbDev pd, int from, const LoIn &in, const LoSol &sol,
+                                    int g0, int g1, const EdgeGeo &q, const double *T, const double *dsop,
+                                    double (&acc)[R_NA]) {
+  double dS = 0.0;
+  if (MODE == RM_OPAC) {
+    // one group per step: its loads are issued first and are in flight while
+    // the group's opacity and Planck integrals are evaluated
+    const CellOpac co = cell_opac(S, pd, T, q.e - 1);
+    EdgeQ lo = edge_q(co.nue[g0], co.iT);
+    for (int g = g0; g < g1; ++g) {
+      EdgeVals a;
+      load_group<FINE, OLD, RM_OPAC>(S, from, in, sol, g, true, q, 0.0, 0.0, 0.0, dsop, 0, a);
+      double ka, Ba;
+      const EdgeQ hi = edge_q(co.nue[g + 1], co.iT);
+      dS += planck_group(co.nuc[g], lo, hi, co.iT, co.Cc, co.scale, ka, Ba);
+      lo = hi;
+      // right cell of the edge = own cell of the next lane
+      const double ke = dpp_f64<DPP_WAVE_SHL1, 0xf>(ka, 0.0), Be = dpp_f64<DPP_WAVE_SHL1, 0xf>(Ba, 0.0);
+      a.se = ke;
+      a.em = 2.0 * ke * Be;
+      a.sr = ka * q.wm + ke * q.we;
+      add_group<OLD, MODE>(a, q, acc);
+    }
+  } else {
+    const int dsp = MODE == RM_DSF ? S.dsnp[from] / S.lev_ng[from] : 0;
+    for (int g = g0; g < g1; g += 2) {
+      const bool two = g + 1 < g1;
+      EdgeVals a, b;
+      load_group<FINE, OLD, MODE>(S, from, in, sol, g, true, q, 0.0, 0.0, 0.0, dsop, dsp, a);
+      load_group<FINE, OLD, MODE>(S, from, in, sol, two ? g + 1 : g, two, q, 0.0, 0.0, 0.0, dsop, dsp, b);
+      add_group<OLD, MODE>(a, q, acc);
+      add_group<OLD, MODE>(b, q, acc);
+    }
   }
+  return dS;
 }
 
-// Final coefficients of coarse group p at edge e from the block sums.
-// dS of cell i from the chunk partials, for the grey restriction: eight
-// interleaved partial sums (chunks q = k mod 8) keep eight loads in flight and
-// are combined in a fixed order.
+// dS of cell i from the chunk partials of the opacity tables, for the grey
+// restriction: eight interleaved partial sums (chunks q = k mod 8) keep
+// eight loads in flight and are combined in a fixed order.
 __device__ inline void finalize_dS(const SlabDev &S, int i, const LoOut &o) {
   if (!o.dS || i >= S.nx) return;
   const double *row = o.dSpart + S.o_chunk + i;
@@ -1028,11 +1110,16 @@ __device__ inline void finalize_dS(const SlabDev &S, int i, const LoOut &o) {
   o.dS[S.o_cell + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
-template <bool OLD>
-__device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int e, int r, const double (&s)[R_N],
+// Final coefficients of coarse group p at edge e from the block sums.
+template <bool OLD, int MODE>
+__device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int e, int r, const double (&s)[R_NA],
                                 const LoOut &o) {
   const int nx = S.nx;
-  if (p == 0) finalize_dS(S, e, o);
+  if (MODE == RM_DSF) {
+    if (o.dS && e < nx) o.dS[S.o_cell + e] = s[R_DS];
+  } else if (p == 0) {
+    finalize_dS(S, e, o);
+  }
   const double rinv = 1.0 / r;
   const double c = S.c;
   const long long pi = S.o_lpi[to] + (long long)p * nx;
@@ -1063,43 +1150,61 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   }
 }
 
+// Edges per wavefront tile: 64, or 63 in RM_OPAC (lane l owns cell
+// 63 t + l - 1 and edge 63 t + l; lane 63 only supplies its cell's values).
+template <int MODE>
+__device__ __host__ constexpr int rtile() { return MODE == RM_OPAC ? 63 : 64; }
+
+// Stage dS partials of the lanes' own cells (RM_OPAC): lanes 1..63 write
+// cells 63 t .. 63 t + 62 of partial row `row`.
+__device__ inline void store_dS_part(const SlabDev &S, double *dsop, long long row, int c, double v) {
+  if ((threadIdx.x & 63) >= 1 && c >= 0 && c < S.nx) dsop[S.o_dsop + row * S.nx + c] = v;
+}
+
 // One-pass restriction (r <= 16 finer groups per coarse group): wavefront =
-// (coarse group p, tile of 64 edges), lane = edge; block = 4 consecutive
+// (coarse group p, tile of edges), lane = edge; block = 4 consecutive
 // wavefront items of a slab (item index 4 it.idx + w).
-template <bool FINE, bool OLD>
+template <bool FINE, bool OLD, int MODE>
 __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd, ProbDev pd,
                                                   const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
-                                                  int from, int to, LoIn in, LoSol sol, LoOut out) {
+                                                  int from, int to, LoIn in, LoSol sol, LoOut out,
+                                                  const double *T, double *dsop) {
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   const int nx = S.nx, ne = nx + 1;
   const int nto = S.lev_ng[to];
   const int r = S.lev_ng[from] / nto;
-  const int ntile = (ne + 63) >> 6;
+  constexpr int TE = rtile<MODE>();
+  const int ntile = (ne + TE - 1) / TE;
   const int wi = 4 * it.idx + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wi >= nto * ntile) return;
   const int p = wi / ntile, et = wi - p * ntile;
-  const int e = et * 64 + (threadIdx.x & 63);
+  const int lane = threadIdx.x & 63;
+  const int e = et * TE + lane;
   const EdgeGeo q = edge_geo(S, pd, e);
-  double acc[R_N];
+  double acc[R_NA];
 #pragma unroll
-  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  acc_groups<FINE, OLD>(S, from, in, sol, p * r, (p + 1) * r, q, acc);
-  if (e < ne) finalize<OLD>(S, pd, to, p, e, r, acc, out);
+  for (int k = 0; k < R_NA; ++k) acc[k] = 0.0;
+  const double dS = acc_groups<FINE, OLD, MODE>(S, pd, from, in, sol, p * r, (p + 1) * r, q, T, dsop, acc);
+  if (MODE == RM_OPAC) store_dS_part(S, dsop, p, e - 1, dS);
+  if (e < ne && lane < TE) finalize<OLD, MODE>(S, pd, to, p, e, r, acc, out);
 }
 
-// Chunk pass (r > 16): block = (slab, chunk record qq = p cpb + bc, tile of 64
+// Chunk pass (r > 16): block = (slab, chunk record qq = p cpb + bc, tile of
 // edges); wavefront w adds groups p r + (4 bc + w) rcw + [0, rcw), lane =
 // edge.  The four wavefront sums are combined through LDS in a fixed order,
-// ((w0 + w2) + (w1 + w3)), and the record [64 edges][R_N] is written
-// contiguously.
-template <bool FINE, bool OLD>
+// ((w0 + w2) + (w1 + w3)), and the record [edges][fields] is written
+// contiguously.  RM_OPAC: the dS partials of the four wavefronts are
+// combined the same way into partial row qq.
+template <bool FINE, bool OLD, int MODE>
 __global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict__ sd, ProbDev pd,
                                                        const Item *__restrict__ tab, const Ctl *ctl, int pmode,
                                                        int lcyc, int from, int to, LoIn in, LoSol sol,
-                                                       double *__restrict__ red) {
-  __shared__ double sh[2][64 * R_N];
+                                                       double *__restrict__ red, const double *T, double *dsop) {
+  constexpr int NF = rec_fields<OLD, MODE>();
+  __shared__ double sh[2][64 * NF];
+  __shared__ double sds[4][64];
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
@@ -1107,43 +1212,46 @@ __global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict
   const int r = S.lev_ng[from] / S.lev_ng[to];
   const int nto = S.lev_ng[to];
   const int rcw = restrict_rcw(r, nto, ne, S.rtarget), cpb = restrict_cpb(r, nto, ne, S.rtarget);
-  const int ntile = (ne + 63) >> 6;
+  constexpr int TE = rtile<MODE>();
+  const int ntile = (ne + TE - 1) / TE;
   const int qq = it.idx / ntile, et = it.idx - qq * ntile;
   const int p = qq / cpb, bc = qq - p * cpb;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int e = et * 64 + lane;
+  const int e = et * TE + lane;
   const int g0 = p * r + (bc * 4 + w) * rcw;
   const int g1 = min(g0 + rcw, (p + 1) * r);
   const EdgeGeo q = edge_geo(S, pd, e);
-  double acc[R_N];
+  double acc[R_NA];
 #pragma unroll
-  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  acc_groups<FINE, OLD>(S, from, in, sol, g0, g1, q, acc);
-  constexpr int NF = rec_fields<OLD>();
+  for (int k = 0; k < R_NA; ++k) acc[k] = 0.0;
+  const double dS = acc_groups<FINE, OLD, MODE>(S, pd, from, in, sol, g0, g1, q, T, dsop, acc);
+  if (MODE == RM_OPAC) sds[w][lane] = dS;
   double *slot = sh[w & 1] + lane * NF;
   if (w >= 2) {
 #pragma unroll
-    for (int k = 0; k < NF; ++k) slot[k] = acc[k];
+    for (int k = 0; k < NF; ++k) slot[k] = acc[rec_src<OLD>(k)];
   }
   __syncthreads();
   if (w < 2) {
 #pragma unroll
-    for (int k = 0; k < NF; ++k) acc[k] += slot[k];
+    for (int k = 0; k < NF; ++k) acc[rec_src<OLD>(k)] += slot[k];
   }
   __syncthreads();
   if (w == 1) {
 #pragma unroll
-    for (int k = 0; k < NF; ++k) slot[k] = acc[k];
+    for (int k = 0; k < NF; ++k) slot[k] = acc[rec_src<OLD>(k)];
   }
   __syncthreads();
   if (w == 0) {
     double *s1 = sh[1] + lane * NF, *s0 = sh[0] + lane * NF;
 #pragma unroll
-    for (int k = 0; k < NF; ++k) s0[k] = acc[k] + s1[k];
+    for (int k = 0; k < NF; ++k) s0[k] = acc[rec_src<OLD>(k)] + s1[k];
+    if (MODE == RM_OPAC)
+      store_dS_part(S, dsop, qq, e - 1, (sds[0][lane] + sds[2][lane]) + (sds[1][lane] + sds[3][lane]));
   }
   __syncthreads();
-  const int nval = min(64, ne - et * 64) * NF;
-  double *rec = red + S.o_red + ((long long)qq * ne + et * 64) * NF;
+  const int nval = min(TE, ne - et * TE) * NF;
+  double *rec = red + S.o_red + ((long long)qq * ne + et * TE) * NF;
   for (int j = threadIdx.x; j < nval; j += 256) rec[j] = sh[0][j];
 }
 
@@ -1151,14 +1259,14 @@ __global__ __launch_bounds__(256) void k_restrict_part(const SlabDev *__restrict
 // thread = (part u, edge, field) adds the chunk records q = u, u + U, ...
 // (U = 4 parts for 16 or more records, else 1); the parts are combined in a
 // fixed order, ((u0 + u1) + (u2 + u3)).
-template <bool OLD>
+template <bool OLD, int MODE>
 __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restrict__ sd, ProbDev pd,
                                                         const Item *__restrict__ tab, const Ctl *ctl, int pmode,
                                                         int lcyc, int from, int to, LoOut out,
                                                         const double *__restrict__ red) {
-  constexpr int NF = rec_fields<OLD>();
-  static_assert(TR_RFIN_E * R_N <= 256, "final pass block");
-  __shared__ double sums[TR_RFIN_E * R_N];
+  constexpr int NF = rec_fields<OLD, MODE>();
+  static_assert(TR_RFIN_E * (R_NA) <= 256 && 4 * (TR_RFIN_E / 4) * R_NA <= 256, "final pass block");
+  __shared__ double sums[TR_RFIN_E * R_NA];
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
@@ -1166,7 +1274,7 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   const int nfrom = S.lev_ng[from], nto = S.lev_ng[to];
   const int r = nfrom / nto;
   const int cpb = restrict_cpb(r, nto, ne, S.rtarget);
-  const int RE = restrict_fin_edges(cpb), U = TR_RFIN_E / RE;
+  const int RE = restrict_fin_edges(cpb), U = cpb >= 16 ? 4 : 1;
   const int NP = RE * NF;  // (edge, field) pairs of the block
   const int nb = (ne + RE - 1) / RE;
   const int p = it.idx / nb, b = it.idx - p * nb;
@@ -1186,15 +1294,14 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
   }
   __syncthreads();
   if (t < RE && b * RE + t < ne) {
-    double s[R_N];
+    double s[R_NA];
 #pragma unroll
-    for (int q = 0; q < R_N; ++q) {
+    for (int q = 0; q < R_NA; ++q) s[q] = 0.0;
+    for (int q = 0; q < NF; ++q) {
       const int j = t * NF + q;
-      double v = 0.0;
-      if (q < NF) v = U == 4 ? (sums[j] + sums[NP + j]) + (sums[2 * NP + j] + sums[3 * NP + j]) : sums[j];
-      s[q] = v;
+      s[rec_src<OLD>(q)] = U == 4 ? (sums[j] + sums[NP + j]) + (sums[2 * NP + j] + sums[3 * NP + j]) : sums[j];
     }
-    finalize<OLD>(S, pd, to, p, b * RE + t, r, s, out);
+    finalize<OLD, MODE>(S, pd, to, p, b * RE + t, r, s, out);
   }
 }
 
@@ -1729,37 +1836,40 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
                        pmode, lcyc, level, in, sol);
 }
 
-template <bool OLD>
+template <bool FINE, bool OLD, int MODE>
 void launch_restrict_t(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
-                       int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red) {
-  const bool fine = from == 0;
-  if (rt.single.n) {
-    if (fine)
-      hipLaunchKernelGGL((k_restrict<true, OLD>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out);
-    else
-      hipLaunchKernelGGL((k_restrict<false, OLD>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out);
-  }
-  if (rt.part.n) {
-    if (fine)
-      hipLaunchKernelGGL((k_restrict_part<true, OLD>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, red);
-    else
-      hipLaunchKernelGGL((k_restrict_part<false, OLD>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd, env.pd,
-                         rt.part.d, ctl, pmode, lcyc, from, to, in, sol, red);
-  }
+                       int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, const double *T,
+                       double *dsop) {
+  if (rt.single.n)
+    hipLaunchKernelGGL((k_restrict<FINE, OLD, MODE>), blocks(rt.single.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                       rt.single.d, ctl, pmode, lcyc, from, to, in, sol, out, T, dsop);
+  if (rt.part.n)
+    hipLaunchKernelGGL((k_restrict_part<FINE, OLD, MODE>), blocks(rt.part.n), dim3(256), 0, env.stream, env.sd,
+                       env.pd, rt.part.d, ctl, pmode, lcyc, from, to, in, sol, red, T, dsop);
   if (rt.fin.n)
-    hipLaunchKernelGGL(k_restrict_final<OLD>, blocks(rt.fin.n), dim3(256), 0, env.stream, env.sd, env.pd, rt.fin.d,
-                       ctl, pmode, lcyc, from, to, out, red);
+    hipLaunchKernelGGL((k_restrict_final<OLD, MODE>), blocks(rt.fin.n), dim3(256), 0, env.stream, env.sd, env.pd,
+                       rt.fin.d, ctl, pmode, lcyc, from, to, out, red);
 }
 
 void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *ctl, int pmode, int lcyc, int from,
-                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, bool old) {
-  if (old)
-    launch_restrict_t<true>(env, rt, ctl, pmode, lcyc, from, to, in, sol, out, red);
-  else
-    launch_restrict_t<false>(env, rt, ctl, pmode, lcyc, from, to, in, sol, out, red);
+                     int to, const LoIn &in, const LoSol &sol, const LoOut &out, double *red, bool old, int mode,
+                     const double *T, double *dsop) {
+  const bool fine = from == 0;
+#define TR_RL(F, O, M) launch_restrict_t<F, O, M>(env, rt, ctl, pmode, lcyc, from, to, in, sol, out, red, T, dsop)
+  if (fine) {
+    if (mode == RM_OPAC) {
+      if (old) TR_RL(true, true, RM_OPAC); else TR_RL(true, false, RM_OPAC);
+    } else {
+      if (old) TR_RL(true, true, RM_PLAIN); else TR_RL(true, false, RM_PLAIN);
+    }
+  } else {
+    if (mode == RM_DSF) {
+      if (old) TR_RL(false, true, RM_DSF); else TR_RL(false, false, RM_DSF);
+    } else {
+      if (old) TR_RL(false, true, RM_PLAIN); else TR_RL(false, false, RM_PLAIN);
+    }
+  }
+#undef TR_RL
 }
 
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,

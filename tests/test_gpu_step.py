@@ -61,7 +61,7 @@ def _compare_state(tag, sv, st, ref, slab_idx=0):
     assert_close(f"{tag} C", C, ref.fac.C, TOL)
 
 
-@pytest.mark.parametrize("case", ["small_V", "W3", "F4", "vacuum_both", "two_cells_S2", "max_cells",
+@pytest.mark.parametrize("case", ["small_V", "W3", "F4", "W_r32", "vacuum_both", "two_cells_S2", "max_cells",
                                   "thin", "thick"])
 def test_step_replay(case):
     if case == "small_V":
@@ -77,6 +77,11 @@ def test_step_replay(case):
         slab = inputs.make_slab(70, 64, 16, dt=0.002)
         levels = [64, 16, 4, 1]
         cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_F, lmax=2)
+        nsteps = 2
+    elif case == "W_r32":  # stage level of 32 fine groups per coarse group (two-pass stage restriction)
+        slab = inputs.make_slab(70, 64, 8, dt=0.004)
+        levels = [64, 2, 1]
+        cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_W, lmax=2)
         nsteps = 2
     elif case == "vacuum_both":
         slab = inputs.make_slab(20, 8, 4, T_left=0.0, T_right=0.0, T0=0.05)
