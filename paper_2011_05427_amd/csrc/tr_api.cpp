@@ -52,6 +52,8 @@ struct tr_ctx {
   Ctl *d_ctl = nullptr;
   int *d_cost = nullptr;
   int *h_count = nullptr;  // pinned, coherent: active slabs after a transport iteration
+  Ctl *h_ctl_out = nullptr;  // pinned, coherent: control records once every slab stopped
+  Ctl *h_ctl_in = nullptr;   // pinned: control records uploaded at the step start
   // work tables
   Table t_opac{}, t_dS{}, t_cell{}, t_gi{}, t_g{}, t_grey{};
   // sweep work per slab-size bucket (nx <= 64, 128, 256, 512, 1024, more),
@@ -403,6 +405,8 @@ int tr_destroy(tr_ctx *c) {
   if (c->gs) (void)hipStreamDestroy(c->gs);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->h_count) (void)hipHostFree(c->h_count);
+  if (c->h_ctl_out) (void)hipHostFree(c->h_ctl_out);
+  if (c->h_ctl_in) (void)hipHostFree(c->h_ctl_in);
   delete c;
   return TR_OK;
 }
@@ -603,7 +607,10 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     return fail(rc);
   // the active-slab count is written by the GPU straight into coherent pinned
   // host memory (read after the synchronisation of every transport iteration)
-  if (hipHostMalloc((void **)&c->h_count, sizeof(int), hipHostMallocCoherent) != hipSuccess) return fail(TR_ENOMEM);
+  if (hipHostMalloc((void **)&c->h_count, sizeof(int), hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_ctl_out, sizeof(Ctl) * n_slab, hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_ctl_in, sizeof(Ctl) * n_slab, hipHostMallocDefault) != hipSuccess)
+    return fail(TR_ENOMEM);
   if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -1058,7 +1065,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     }
   }
   // start of the next transport iteration (s + 1) for slabs still iterating
-  launch_outer_end(env, c->d_ctl, ns, c->cfg.max_outer, c->h_count);
+  launch_outer_end(env, c->d_ctl, ns, c->cfg.max_outer, c->h_count, c->h_ctl_out);
 }
 
 int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, bool sweep_outside,
@@ -1120,7 +1127,11 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   // everything runs on the library stream, ordered after the caller's work
   hipStream_t gs = c->gs;
   if (hipEventRecord(c->ev_in, st) != hipSuccess || hipStreamWaitEvent(gs, c->ev_in, 0) != hipSuccess) return TR_EHIP;
-  if (hipMemcpyAsync(c->d_ctl, hc.data(), sizeof(Ctl) * ns, hipMemcpyHostToDevice, gs) != hipSuccess) return TR_EHIP;
+  // (from pinned memory: the copy is asynchronous; the previous step has
+  // finished with the buffer)
+  std::memcpy(c->h_ctl_in, hc.data(), sizeof(Ctl) * ns);
+  if (hipMemcpyAsync(c->d_ctl, c->h_ctl_in, sizeof(Ctl) * ns, hipMemcpyHostToDevice, gs) != hipSuccess)
+    return TR_EHIP;
   LaunchEnv env = env_of(c, gs);
   // step start: old-time copies, convergence references, Phi with the current incoming
   launch_step_start(env, s->T, s->Egrey, s->E, s->F, c->n_cell, c->n_gi, c->n_ge, c->Told, c->Ts, c->Tcyc, c->Tstar,
@@ -1192,6 +1203,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
     if (rc) return rc;
     ge->chain[chain] = x;
   }
+  bool done = false;  // every slab stopped (seen on the host)
   for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
     // transport sweep of iteration s >= 1 (predicated per slab)
     if (outer > 0 && sweep_ev)
@@ -1214,14 +1226,23 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       tim_collect(c, s0 < TR_MAXOUT ? k0.cycles[s0] : 0, t_ms, n_launch);
       s0 = k0.s;
     }
-    if (*static_cast<volatile int *>(c->h_count) == 0) break;
+    if (*static_cast<volatile int *>(c->h_count) == 0) {
+      done = true;
+      break;
+    }
   }
   launch_copy(env, c->Tstar, s->T, c->n_cell);
+  if (done) {
+    // the last iteration's end kernel wrote the final records to host memory
+    // before the synchronisation above
+    std::memcpy(hc.data(), c->h_ctl_out, sizeof(Ctl) * ns);
+  } else if (hipMemcpyAsync(hc.data(), c->d_ctl, sizeof(Ctl) * ns, hipMemcpyDeviceToHost, gs) != hipSuccess) {
+    return TR_EHIP;
+  }
   if (c->mlp_params &&
       hipMemcpyAsync(seed_counts, c->d_seed_counts, sizeof(seed_counts), hipMemcpyDeviceToHost, gs) != hipSuccess)
     return TR_EHIP;
-  if (hipMemcpyAsync(hc.data(), c->d_ctl, sizeof(Ctl) * ns, hipMemcpyDeviceToHost, gs) != hipSuccess) return TR_EHIP;
-  if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
+  if ((!done || c->mlp_params) && hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
   if (hipEventRecord(c->ev_out, gs) != hipSuccess || hipStreamWaitEvent(st, c->ev_out, 0) != hipSuccess)
     return TR_EHIP;
   int err = TR_OK;

@@ -114,8 +114,9 @@ void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga);
 // End of a transport iteration (start of s + 1 where the inner iteration is
-// done) and the count of slabs still active into *out (one launch).
-void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out);
+// done) and the count of slabs still active into *out (one launch); with no
+// slab left active the control records are copied to hout.
+void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout);
 // Step-start copies of T, Egrey, E, F into the step's reference arrays.
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,

@@ -6,6 +6,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <cstddef>
 
 #include "tr_device.h"
 #include "tr_kernels.h"
@@ -21,18 +22,25 @@ __constant__ double tr_recip[TR_NRECIP];
 // ---------------------------------------------------------------------------
 // predication
 // ---------------------------------------------------------------------------
+// The four leading fields of the control record (active, s, ncyc,
+// inner_done) are read with one 16-byte load and combined without
+// short-circuit evaluation, so a predicated kernel waits for one round trip.
+static_assert(offsetof(Ctl, active) == 0 && offsetof(Ctl, s) == 4 && offsetof(Ctl, ncyc) == 8 &&
+                  offsetof(Ctl, inner_done) == 12 && sizeof(Ctl) % 16 == 0,
+              "control record header");
 __device__ inline bool pred_ok(const Ctl *ctl, int slab, int mode, int l) {
   if (ctl == nullptr || mode == PRED_ALL) return true;
-  const Ctl &c = ctl[slab];
+  const int4 h = *reinterpret_cast<const int4 *>(ctl + slab);
+  const bool active = h.x != 0, s_pos = h.y > 0, at_l = h.z == l, running = h.w == 0;
   switch (mode) {
     case PRED_CYCLE:  // body of cycle l+1 of the current transport iteration
-      return c.active && !c.inner_done && c.ncyc == l;
+      return active & running & at_l;
     case PRED_DONECYC:  // the slab has just completed cycle l
-      return c.active && c.ncyc == l;
+      return active & at_l;
     case PRED_SWEEP:  // start of a transport iteration s >= 1
-      return c.active && !c.inner_done && c.ncyc == 0 && c.s > 0;
+      return active & running & (h.z == 0) & s_pos;
     case PRED_ACTIVE:
-      return c.active;
+      return active;
   }
   return true;
 }
@@ -1518,9 +1526,10 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
 // ---------------------------------------------------------------------------
 // End of a transport iteration: slabs whose inner iteration finished start
 // iteration s + 1 (or stop at the iteration limit / replay length), and the
-// number of slabs still active is written to *out.  One block of 256
+// number of slabs still active is written to *out; when it is zero the
+// control records are also copied to hout (host memory).  One block of 256
 // threads; slabs s = t, t + 256, ...; the count is summed exactly.
-__global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_outer, int *out) {
+__global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout) {
   __shared__ int part[4];
   int n = 0;
   for (int s = threadIdx.x; s < nslab; s += blockDim.x) {
@@ -1542,7 +1551,12 @@ __global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_
   for (int d = 32; d > 0; d >>= 1) n += __shfl_xor(n, d);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = n;
   __syncthreads();
-  if (threadIdx.x == 0) *out = (part[0] + part[1]) + (part[2] + part[3]);
+  const int total = (part[0] + part[1]) + (part[2] + part[3]);
+  // once every slab has stopped, the final control records go straight to
+  // the host copy (read there after the stream synchronisation)
+  if (total == 0)
+    for (int s = threadIdx.x; s < nslab; s += blockDim.x) hout[s] = ctl[s];
+  if (threadIdx.x == 0) *out = total;
 }
 
 // Step start: copies of the state into the step's references (T into Told,
@@ -1879,8 +1893,8 @@ void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, 
                      lcyc, ga);
 }
 
-void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out) {
-  hipLaunchKernelGGL(k_outer_end, dim3(1), dim3(256), 0, env.stream, ctl, nslab, max_outer, out);
+void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout) {
+  hipLaunchKernelGGL(k_outer_end, dim3(1), dim3(256), 0, env.stream, ctl, nslab, max_outer, out, hout);
 }
 
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
