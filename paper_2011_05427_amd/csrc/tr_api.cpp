@@ -50,7 +50,6 @@ struct tr_ctx {
     double *sigE, *emis, *a, *b, *sigR, *C, *Phi, *Eold, *Fold, *E, *F, *Ebnd, *Esum;
   } lev[TR_MAXLEV]{};
   Ctl *d_ctl = nullptr;
-  int *d_cost = nullptr;
   int *h_count = nullptr;  // pinned, coherent: active slabs after a transport iteration
   Ctl *h_ctl_out = nullptr;  // pinned, coherent: control records once every slab stopped
   Ctl *h_ctl_in = nullptr;   // pinned: control records uploaded at the step start
@@ -542,6 +541,14 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       c->n_lpe[l] += (long long)S.lev_ng[l] * (P.nx + 1);
       c->n_lp2[l] += 2LL * S.lev_ng[l];
     }
+    S.o_gpi = S.o_lpi[nlev - 1];
+    S.o_gpe = S.o_lpe[nlev - 1];
+    S.o_gp2 = S.o_lp2[nlev - 1];
+    {
+      int k = S.lev_ng[0] + 1;
+      for (int q = 0; q < S.nsched; ++q) k += S.lev_ng[S.sched[q]] + 1;
+      S.cyc_cost = k;
+    }
     for (int i = 0; i < P.nx; ++i) {
       h_dx.push_back(P.x_edges[i + 1] - P.x_edges[i]);
       h_C.push_back(P.C_cell[i]);
@@ -603,7 +610,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     for (double **p : p2)
       if ((rc = dalloc(c, p, c->n_lp2[l]))) return fail(rc);
   }
-  if ((rc = dalloc(c, &c->d_ctl, n_slab)) || (rc = dalloc(c, &c->d_cost, n_slab)))
+  if ((rc = dalloc(c, &c->d_ctl, n_slab)))
     return fail(rc);
   // the active-slab count is written by the GPU straight into coherent pinned
   // host memory (read after the synchronisation of every transport iteration)
@@ -618,14 +625,6 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   for (int b = 0; b < TR_NBUCKET; ++b)
     for (int q = 0; q < 2; ++q)
       if (hipEventCreate(&c->ev_sw[b][q]) != hipSuccess) return fail(TR_EHIP);
-  std::vector<int> cost(n_slab);
-  for (int s = 0; s < n_slab; ++s) {
-    const SlabDev &S = c->hs[s];
-    int k = S.lev_ng[0] + 1;
-    for (int q = 0; q < S.nsched; ++q) k += S.lev_ng[S.sched[q]] + 1;
-    cost[s] = k;
-  }
-  if (up(c->d_cost, cost.data(), sizeof(int) * n_slab)) return fail(TR_EHIP);
 
   // work tables
   {
@@ -808,6 +807,7 @@ int tr_grey_solve(tr_ctx *c, const tr_lo_coeffs *grey, const double *Tstar, cons
   ga.Told = Told;
   ga.dS = dS;
   ga.D = D;
+  ga.ctl_dummy = c->d_ctl;
   launch_grey(env_of(c, st), c->t_grey, c->grey_threads, nullptr, PRED_ALL, 0, ga);
   return hip_err(hipGetLastError());
 }
@@ -1005,7 +1005,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
   ga.Ecyc = c->Ecyc;
   ga.Ts = c->Ts;
   ga.Es = c->Es;
-  ga.cyc_cost = c->d_cost;
+  ga.ctl_dummy = c->d_ctl;
   ga.secant = c->cfg.secant;
   ga.lmax = c->cfg.lmax;
   ga.eps = c->cfg.eps;

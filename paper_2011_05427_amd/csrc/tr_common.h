@@ -24,6 +24,8 @@ struct SlabDev {
   long long o_cell, o_edge, o_I, o_gi, o_ge, o_g, o_g2, o_nu, o_mu, o_chunk;
   long long o_lpi[TR_MAXLEV], o_lpe[TR_MAXLEV], o_lp2[TR_MAXLEV];
   long long o_red;  // restriction scratch records (per slab)
+  long long o_gpi, o_gpe, o_gp2;  // grey level offsets (= o_lpi / o_lpe / o_lp2 of the last level)
+  int cyc_cost;              // LO solves per cycle
   long long o_dsop;          // stage dS partials (per slab)
   int dsnp[TR_MAXLEV];       // stage dS partial rows of the restriction fine -> level
 };

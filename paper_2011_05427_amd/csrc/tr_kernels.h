@@ -39,7 +39,7 @@ struct GreyArgs {
   double *Tprev, *sigprev;         // secant memory (step mode)
   double *Egrey;                   // cell: grey E output (nullable)
   double *Tcyc, *Ecyc, *Ts, *Es;   // convergence references (step mode)
-  const int *cyc_cost;             // per slab: LO solves per cycle
+  const Ctl *ctl_dummy;             // any valid control record (read, unused, without control)
   int secant, end_cycle, lmax;
   double eps, eps_inner;
 };

@@ -1357,25 +1357,23 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
                                               GreyArgs ga) {
   extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
   __shared__ int s_flag[2];
+  // every scalar input (work item, descriptor, control record) is read
+  // without branches so that the loads overlap: the control record is read
+  // from slot 0 of a valid array even without control (then unused)
   const Item it = tab[blockIdx.x];
   const int slab = it.slab;
   const SlabDev &S = sd[slab];
-  // descriptor fields and control record are loaded together
-  const int nx = S.nx, gl = S.nlev - 1;
-  const long long o_cell = S.o_cell, pi = S.o_lpi[gl];
+  const int nx = S.nx;
+  const long long o_cell = S.o_cell, pi = S.o_gpi;
   const double c = S.c, dt = S.dt, cv = S.cv;
-  int c_ncyc = 0, c_nrep = 0, c_s = 0, c_hasprev = 0, c_cost = 0;
-  if (ctl) {
-    c_ncyc = ctl[slab].ncyc;
-    c_nrep = ctl[slab].n_replay;
-    c_s = ctl[slab].s;
-    c_hasprev = ctl[slab].has_prev;
-    c_cost = ga.cyc_cost[slab];
-  }
-  if (!pred_ok(ctl, slab, pmode, lcyc)) return;
-  const int c_rep = (ctl && c_nrep > 0) ? ctl[slab].replay[c_s] : 0;
+  const bool has_ctl = ctl != nullptr;
+  const Ctl &kc = has_ctl ? ctl[slab] : *ga.ctl_dummy;
+  const int4 hd = *reinterpret_cast<const int4 *>(&kc);  // active, s, ncyc, inner_done
+  const int c_ncyc = hd.z, c_s = hd.y, c_nrep = kc.n_replay, c_hasprev = kc.has_prev, c_cost = S.cyc_cost;
+  if (has_ctl && !pred_ok(ctl, slab, pmode, lcyc)) return;
+  const int c_rep = (has_ctl && c_nrep > 0) ? kc.replay[c_s] : 0;
   const int t = threadIdx.x;
-  const bool use_prev = ctl ? (c_hasprev && ga.secant) : false;
+  const bool use_prev = has_ctl && c_hasprev && ga.secant;
   // per-cell inputs of this thread's rows (row k is cell t K + k - 1)
   double Ts[K], sig[K], Sst[K], Es[K], dS[K], Tol[K], Tpv[K], spv[K], Dx[K], rT[K], rE[K], sT[K], sE[K];
 #pragma unroll
@@ -1399,7 +1397,19 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
     sE[k] = ref ? ga.Es[oc] : 0.0;
   }
   // grey level coefficients of the rows (same batch of loads)
-  const LevelView v = make_view<false>(S, pd, gl, ga.grey, 0);
+  LevelView v;
+  v.nx = nx;
+  v.dx = pd.dx + o_cell;
+  v.sigE = ga.grey.sigE + pi;
+  v.emis = ga.grey.emis + pi;
+  v.a = ga.grey.a + S.o_gpe;
+  v.b = ga.grey.b + S.o_gpe;
+  v.sigR = ga.grey.sigR + S.o_gpe;
+  v.C = ga.grey.C + S.o_gp2;
+  v.Phi = ga.grey.Phi + S.o_gp2;
+  v.Eold = ga.grey.Eold + pi;
+  v.Fold = ga.grey.Fold + S.o_gpe;
+  v.kap = v.Bt = v.f = v.fbnd = nullptr;
   RowData<K> R;
   lo_load<K, false>(v, R);
   // Newton coefficients: T - T* = alpha + beta E per cell
@@ -1429,7 +1439,7 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
   double ra[K], rb[K], rc[K], rd[K], x[K], Ak[K + 1], ca[K + 1], cb[K + 1];
   lo_build<K>(R, nx, c, dt, S.inv_cdt, true, se_eff, em_eff, ra, rb, rc, rd, Ak, ca, cb);
   tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
-  double *E = ga.sol.E + pi, *F = ga.sol.F + S.o_lpe[gl], *Eb = ga.sol.Ebnd + S.o_lp2[gl];
+  double *E = ga.sol.E + pi, *F = ga.sol.F + S.o_gpe, *Eb = ga.sol.Ebnd + S.o_gp2;
   lo_store<K>(nx, x, Ak, ca, cb, lds, E, F, Eb);
   // temperature update, secant memory, norms
   double red[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dTc, dEc, dTs, dEs, Tmax, Emax
@@ -1447,7 +1457,7 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
       ++nfl;
     }
     Tn[k] = T1;
-    if (ctl) {
+    if (has_ctl) {
       ga.Tprev[o_cell + i] = Ts[k];
       ga.sigprev[o_cell + i] = sig[k];
     }
@@ -1464,7 +1474,7 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
       red[5] = (En == En) ? fmax(red[5], fabs(En)) : INFINITY;
     }
   }
-  if (!ctl) return;
+  if (!has_ctl) return;
   block_reduce_grey(red, nfl, lds);
   if (!ga.end_cycle) {
     if (t == 0) {
