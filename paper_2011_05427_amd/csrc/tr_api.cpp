@@ -84,9 +84,6 @@ struct tr_ctx {
     // s = 0 (no sweep); s >= 1 with the sweep; s >= 1 without it (the sweep
     // launched separately with its start / end events)
     hipGraphExec_t first = nullptr, next = nullptr, rest = nullptr;
-    // chains of L iterations in one graph (s = 0 and L - 1 sweeping ones):
-    // one host synchronisation for the iterations a step usually needs
-    std::map<int, hipGraphExec_t> chain;
   };
   std::vector<GraphEntry> graphs;
   hipStream_t gs = nullptr;  // library stream for graph replay
@@ -394,7 +391,6 @@ int tr_destroy(tr_ctx *c) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
     if (g.rest) (void)hipGraphExecDestroy(g.rest);
-    for (auto &kv : g.chain) (void)hipGraphExecDestroy(kv.second);
   }
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -827,7 +823,6 @@ int tr_set_tiles(tr_ctx *c, const int *K, const int *split) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
     if (g.rest) (void)hipGraphExecDestroy(g.rest);
-    for (auto &kv : g.chain) (void)hipGraphExecDestroy(kv.second);
   }
   c->graphs.clear();
   return TR_OK;
@@ -1079,16 +1074,6 @@ int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, b
   return e == hipSuccess ? TR_OK : TR_EHIP;
 }
 
-// One graph holding L transport iterations: s = 0, then L - 1 with sweeps.
-int capture_chain(tr_ctx *c, const tr_state *s, int Lmax, int L, hipGraphExec_t *out) {
-  hipGraph_t g = nullptr;
-  if (hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_EHIP;
-  for (int q = 0; q < L; ++q) enqueue_iteration(c, s, c->gs, Lmax, q > 0, false);
-  if (hipStreamEndCapture(c->gs, &g) != hipSuccess || !g) return TR_EHIP;
-  const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  return e == hipSuccess ? TR_OK : TR_EHIP;
-}
 
 }  // namespace
 
@@ -1169,7 +1154,6 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
         (void)hipGraphExecDestroy(old.first);
         (void)hipGraphExecDestroy(old.next);
         if (old.rest) (void)hipGraphExecDestroy(old.rest);
-        for (auto &kv : old.chain) (void)hipGraphExecDestroy(kv.second);
         c->graphs.erase(c->graphs.begin());
       }
       tr_ctx::GraphEntry e;
@@ -1195,21 +1179,18 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   c->ev_used = 0;
   int s0 = 0;  // transport iteration of slab 0 (event timing mode)
   // graph replay without timed sweeps: the iterations the previous step needed
-  // run as one chained graph (iterations past convergence are predicated off)
-  const int chain = (ge && !sweep_ev) ? std::min(8, std::min(c->last_iters, c->cfg.max_outer + 2)) : 0;
-  if (chain >= 2 && !ge->chain.count(chain)) {
-    hipGraphExec_t x = nullptr;
-    const int rc = capture_chain(c, s, Lmax, chain, &x);
-    if (rc) return rc;
-    ge->chain[chain] = x;
-  }
+  // are launched back to back (one host synchronisation for all of them);
+  // iterations past convergence are predicated off on the device
+  const int chain = (ge && !sweep_ev) ? std::min(c->last_iters, c->cfg.max_outer + 2) : 0;
   bool done = false;  // every slab stopped (seen on the host)
   for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
     // transport sweep of iteration s >= 1 (predicated per slab)
     if (outer > 0 && sweep_ev)
       launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd, true);
     if (ge && outer == 0 && chain >= 2) {
-      if (hipGraphLaunch(ge->chain[chain], gs) != hipSuccess) return TR_EHIP;
+      if (hipGraphLaunch(ge->first, gs) != hipSuccess) return TR_EHIP;
+      for (int q = 1; q < chain; ++q)
+        if (hipGraphLaunch(ge->next, gs) != hipSuccess) return TR_EHIP;
       outer += chain - 1;
     } else if (ge) {
       hipGraphExec_t gx = outer == 0 ? ge->first : sweep_ev ? ge->rest : ge->next;
