@@ -50,7 +50,7 @@ struct tr_ctx {
     double *sigE, *emis, *a, *b, *sigR, *C, *Phi, *Eold, *Fold, *E, *F, *Ebnd, *Esum;
   } lev[TR_MAXLEV]{};
   Ctl *d_ctl = nullptr;
-  int *h_count = nullptr;  // pinned, coherent: active slabs after a transport iteration
+  int *h_count = nullptr;  // pinned, coherent: [active slabs, slabs in mid-iteration] after an iteration graph
   Ctl *h_ctl_out = nullptr;  // pinned, coherent: control records once every slab stopped
   Ctl *h_ctl_in = nullptr;   // pinned: control records uploaded at the step start
   // work tables
@@ -84,6 +84,9 @@ struct tr_ctx {
     // s = 0 (no sweep); s >= 1 with the sweep; s >= 1 without it (the sweep
     // launched separately with its start / end events)
     hipGraphExec_t first = nullptr, next = nullptr, rest = nullptr;
+    // s >= 1 with its first cycle only, and the remaining cycles of an
+    // iteration (no sweep): the last iteration of a step usually needs one
+    hipGraphExec_t next1 = nullptr, tail = nullptr;
   };
   std::vector<GraphEntry> graphs;
   hipStream_t gs = nullptr;  // library stream for graph replay
@@ -391,6 +394,8 @@ int tr_destroy(tr_ctx *c) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
     if (g.rest) (void)hipGraphExecDestroy(g.rest);
+    if (g.next1) (void)hipGraphExecDestroy(g.next1);
+    if (g.tail) (void)hipGraphExecDestroy(g.tail);
   }
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -610,7 +615,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     return fail(rc);
   // the active-slab count is written by the GPU straight into coherent pinned
   // host memory (read after the synchronisation of every transport iteration)
-  if (hipHostMalloc((void **)&c->h_count, sizeof(int), hipHostMallocCoherent) != hipSuccess ||
+  if (hipHostMalloc((void **)&c->h_count, 2 * sizeof(int), hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void **)&c->h_ctl_out, sizeof(Ctl) * n_slab, hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void **)&c->h_ctl_in, sizeof(Ctl) * n_slab, hipHostMallocDefault) != hipSuccess)
     return fail(TR_ENOMEM);
@@ -823,6 +828,8 @@ int tr_set_tiles(tr_ctx *c, const int *K, const int *split) {
     if (g.first) (void)hipGraphExecDestroy(g.first);
     if (g.next) (void)hipGraphExecDestroy(g.next);
     if (g.rest) (void)hipGraphExecDestroy(g.rest);
+    if (g.next1) (void)hipGraphExecDestroy(g.next1);
+    if (g.tail) (void)hipGraphExecDestroy(g.tail);
   }
   c->graphs.clear();
   return TR_OK;
@@ -974,13 +981,14 @@ int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
 
 namespace {
 
-// Enqueues one transport iteration: (s >= 1) sweep and moments, then Lmax
-// predicated cycles; a slab whose inner loop has finished skips the rest.
-// One transport iteration: (sweep + moments when with_sweep), Lmax predicated
-// cycles, the start of the next iteration and the active-slab count.  With
-// sweep_outside the sweep launches are left to the caller (timed launches).
+// One transport iteration: (sweep + moments when with_sweep), the predicated
+// cycles l in [lbeg, lend) (default all Lmax; a slab whose inner loop has
+// finished skips the rest), the start of the next iteration and the
+// active-slab count.  With sweep_outside the sweep launches are left to the
+// caller (timed launches).
 void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, bool with_sweep,
-                       bool sweep_outside) {
+                       bool sweep_outside, int lbeg = 0, int lend = -1) {
+  if (lend < 0) lend = Lmax;
   const int ns = c->nslab, gl = c->nlev - 1;
   LaunchEnv env = env_of(c, st);
   const LoIn fine = fine_in(c, c->kappa, c->B, s->f, s->fbnd, s->C, c->Phi, c->Eold, c->Fold);
@@ -1012,7 +1020,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     TimedScope ts(c, st, TR_T_MOMENTS, -1);
     launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
   }
-  for (int l = 0; l < Lmax; ++l) {
+  for (int l = lbeg; l < lend; ++l) {
     // old-time sums are constant during the step: restricted in its first
     // cycle only (every slab runs cycle 0 of iteration s = 0)
     const bool old = !with_sweep && l == 0;
@@ -1064,10 +1072,10 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
 }
 
 int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, bool sweep_outside,
-                      hipGraphExec_t *out) {
+                      hipGraphExec_t *out, int lbeg = 0, int lend = -1) {
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_EHIP;
-  enqueue_iteration(c, s, c->gs, Lmax, with_sweep, sweep_outside);
+  enqueue_iteration(c, s, c->gs, Lmax, with_sweep, sweep_outside, lbeg, lend);
   if (hipStreamEndCapture(c->gs, &g) != hipSuccess || !g) return TR_EHIP;
   const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -1154,6 +1162,8 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
         (void)hipGraphExecDestroy(old.first);
         (void)hipGraphExecDestroy(old.next);
         if (old.rest) (void)hipGraphExecDestroy(old.rest);
+        if (old.next1) (void)hipGraphExecDestroy(old.next1);
+        if (old.tail) (void)hipGraphExecDestroy(old.tail);
         c->graphs.erase(c->graphs.begin());
       }
       tr_ctx::GraphEntry e;
@@ -1162,6 +1172,8 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       // step-start work above is already enqueued and stays before replays
       int rc = capture_iteration(c, s, Lmax, false, false, &e.first);
       if (!rc) rc = capture_iteration(c, s, Lmax, true, false, &e.next);
+      if (!rc && Lmax > 1) rc = capture_iteration(c, s, Lmax, true, false, &e.next1, 0, 1);
+      if (!rc && Lmax > 1) rc = capture_iteration(c, s, Lmax, false, false, &e.tail, 1, Lmax);
       if (rc) return rc;
       c->graphs.push_back(e);
       ge = &c->graphs.back();
@@ -1183,33 +1195,60 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   // iterations past convergence are predicated off on the device
   const int chain = (ge && !sweep_ev) ? std::min(c->last_iters, c->cfg.max_outer + 2) : 0;
   bool done = false;  // every slab stopped (seen on the host)
-  for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
-    // transport sweep of iteration s >= 1 (predicated per slab)
-    if (outer > 0 && sweep_ev)
-      launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd, true);
-    if (ge && outer == 0 && chain >= 2) {
-      if (hipGraphLaunch(ge->first, gs) != hipSuccess) return TR_EHIP;
-      for (int q = 1; q < chain; ++q)
-        if (hipGraphLaunch(ge->next, gs) != hipSuccess) return TR_EHIP;
-      outer += chain - 1;
-    } else if (ge) {
-      hipGraphExec_t gx = outer == 0 ? ge->first : sweep_ev ? ge->rest : ge->next;
-      if (hipGraphLaunch(gx, gs) != hipSuccess) return TR_EHIP;
-    } else {
-      enqueue_iteration(c, s, gs, Lmax, outer > 0, true);
+  volatile const int *hc_active = c->h_count, *hc_mid = c->h_count + 1;
+  if (ge && !sweep_ev) {
+    // graph replay: the iterations the previous step needed are launched back
+    // to back, the last of them with its first cycle only; a slab still in
+    // the middle of that iteration then gets the remaining cycles (tail)
+    const int L = std::max(1, chain), cap = c->cfg.max_outer + 2;
+    const bool one = ge->next1 != nullptr;
+    int launched = 1;
+    bool part = false;
+    if (hipGraphLaunch(ge->first, gs) != hipSuccess) return TR_EHIP;
+    for (int q = 1; q < L; ++q, ++launched) {
+      part = one && q == L - 1;
+      if (hipGraphLaunch(part ? ge->next1 : ge->next, gs) != hipSuccess) return TR_EHIP;
     }
-    if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
-    if (outer > 0 && sweep_ev) sweep_time(c, t_ms, n_launch);
-    if (c->cfg.timing) {
-      // cycles run by slab 0 in the iteration just completed (exact for one slab)
-      Ctl k0;
-      if (hipMemcpy(&k0, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return TR_EHIP;
-      tim_collect(c, s0 < TR_MAXOUT ? k0.cycles[s0] : 0, t_ms, n_launch);
-      s0 = k0.s;
+    for (;;) {
+      if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
+      if (*hc_active == 0) {
+        done = true;
+        break;
+      }
+      if (part && *hc_mid > 0) {
+        part = false;
+        if (hipGraphLaunch(ge->tail, gs) != hipSuccess) return TR_EHIP;
+        continue;
+      }
+      if (launched >= cap) break;
+      part = false;
+      ++launched;
+      if (hipGraphLaunch(ge->next, gs) != hipSuccess) return TR_EHIP;
     }
-    if (*static_cast<volatile int *>(c->h_count) == 0) {
-      done = true;
-      break;
+  } else {
+    for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
+      // transport sweep of iteration s >= 1 (predicated per slab)
+      if (outer > 0 && sweep_ev)
+        launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd, true);
+      if (ge) {
+        hipGraphExec_t gx = outer == 0 ? ge->first : ge->rest;
+        if (hipGraphLaunch(gx, gs) != hipSuccess) return TR_EHIP;
+      } else {
+        enqueue_iteration(c, s, gs, Lmax, outer > 0, true);
+      }
+      if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
+      if (outer > 0 && sweep_ev) sweep_time(c, t_ms, n_launch);
+      if (c->cfg.timing) {
+        // cycles run by slab 0 in the iteration just completed (exact for one slab)
+        Ctl k0;
+        if (hipMemcpy(&k0, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return TR_EHIP;
+        tim_collect(c, s0 < TR_MAXOUT ? k0.cycles[s0] : 0, t_ms, n_launch);
+        s0 = k0.s;
+      }
+      if (*hc_active == 0) {
+        done = true;
+        break;
+      }
     }
   }
   launch_copy(env, c->Tstar, s->T, c->n_cell);

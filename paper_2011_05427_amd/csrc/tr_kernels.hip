@@ -1536,12 +1536,13 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
 // ---------------------------------------------------------------------------
 // End of a transport iteration: slabs whose inner iteration finished start
 // iteration s + 1 (or stop at the iteration limit / replay length), and the
-// number of slabs still active is written to *out; when it is zero the
+// number of slabs still active is written to out[0] (out[1]: those in the
+// middle of an inner iteration, ncyc > 0); when no slab is active the
 // control records are also copied to hout (host memory).  One block of 256
 // threads; slabs s = t, t + 256, ...; the count is summed exactly.
 __global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout) {
-  __shared__ int part[4];
-  int n = 0;
+  __shared__ int part[4], partm[4];
+  int n = 0, nm = 0;
   for (int s = threadIdx.x; s < nslab; s += blockDim.x) {
     Ctl &c = ctl[s];
     if (c.active && c.inner_done) {
@@ -1556,17 +1557,27 @@ __global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_
       }
     }
     n += c.active;
+    nm += (c.active && c.ncyc > 0) ? 1 : 0;  // inner iteration not finished by the graph
   }
 #pragma unroll
-  for (int d = 32; d > 0; d >>= 1) n += __shfl_xor(n, d);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = n;
+  for (int d = 32; d > 0; d >>= 1) {
+    n += __shfl_xor(n, d);
+    nm += __shfl_xor(nm, d);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[threadIdx.x >> 6] = n;
+    partm[threadIdx.x >> 6] = nm;
+  }
   __syncthreads();
   const int total = (part[0] + part[1]) + (part[2] + part[3]);
   // once every slab has stopped, the final control records go straight to
   // the host copy (read there after the stream synchronisation)
   if (total == 0)
     for (int s = threadIdx.x; s < nslab; s += blockDim.x) hout[s] = ctl[s];
-  if (threadIdx.x == 0) *out = total;
+  if (threadIdx.x == 0) {
+    out[0] = total;
+    out[1] = (partm[0] + partm[1]) + (partm[2] + partm[3]);
+  }
 }
 
 // Step start: copies of the state into the step's references (T into Told,
