@@ -264,7 +264,12 @@ typedef struct tr_stats {
  * nullable): per slab, a row of 64 ints = cycles per transport iteration
  * (0 terminates; a row starting with 0 leaves that slab free-running),
  * executed instead of the convergence tests.  stats (host,
- * nullable): [n_slab] counters accumulated over calls.
+ * nullable): [n_slab] counters accumulated over calls.  The step runs on
+ * the library's stream after the work already queued on `stream`, and
+ * `stream` waits for it; the call returns once the host has seen every slab
+ * stop (the stats are final), while the last copy into st->T may still be
+ * in flight: work queued on `stream` afterwards sees the results, the host
+ * synchronises `stream` before reading device memory directly.
  * Errors: TR_ENOCONV, TR_ENAN, TR_EHIP.
  */
 int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats, hipStream_t stream);
