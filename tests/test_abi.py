@@ -100,3 +100,18 @@ def test_create_rejects_invalid_problems():
     assert _create([], [], cfg) == EINVAL
     # a batch whose slabs disagree on the number of levels
     assert _create([ok, ok], [[8, 1], [8, 4, 1]], cfg) == EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(binding.LIB_PATH), reason="libtr.so not built (run __graft_entry__.build())")
+def test_calls_without_a_context_are_rejected():
+    """Every entry point taking a context returns TR_EINVAL for a null one
+    before touching the device (tile, timing and closure calls here)."""
+    lib = binding.load()
+    EINVAL = -1
+    K = (ctypes.c_int * 6)(4, 4, 4, 4, 4, 4)
+    S = (ctypes.c_int * 6)(1, 2, 4, 1, 2, 4)
+    assert lib.tr_set_tiles(None, K, S) == EINVAL
+    assert lib.tr_get_tiles(None, K, S, None) == EINVAL
+    assert lib.tr_autotune(None, None, None, 1, K, S, None, None) == EINVAL
+    assert lib.tr_set_sweep_timing(None, 1) == EINVAL
+    assert lib.tr_step(None, None, None, None, None) == EINVAL
