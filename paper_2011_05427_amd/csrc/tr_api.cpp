@@ -262,13 +262,18 @@ void sweep_time(const tr_ctx *c, double *t_ms, long long *n_launch) {
   }
 }
 
+// Events that only time work read after a stream synchronisation: without
+// the system-scope fence of a default event, recording them does not add a
+// cache writeback and invalidation to the timed interval.
+hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 // Event marks around kernel groups (cfg.timing).  A group records its cycle
 // index (-1 outside the cycles) so that launches of cycles a slab skipped can
 // be left out of the sums.
 int tim_mark(tr_ctx *c, hipStream_t st) {
   if (c->ev_used == (int)c->events.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return -1;
+    if (timing_event(&e) != hipSuccess) return -1;
     c->events.push_back(e);
   }
   const int k = c->ev_used++;
@@ -625,7 +630,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     return fail(TR_EHIP);
   for (int b = 0; b < TR_NBUCKET; ++b)
     for (int q = 0; q < 2; ++q)
-      if (hipEventCreate(&c->ev_sw[b][q]) != hipSuccess) return fail(TR_EHIP);
+      if (timing_event(&c->ev_sw[b][q]) != hipSuccess) return fail(TR_EHIP);
 
   // work tables
   {
@@ -850,7 +855,7 @@ int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K
   if (!c || !I_prev || !I_out || I_prev == I_out || reps < 1) return TR_EINVAL;
   static const int candK[4] = {1, 2, 4, 8}, candS[3] = {1, 2, 4};
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TR_EHIP;
+  if (timing_event(&e0) != hipSuccess || timing_event(&e1) != hipSuccess) return TR_EHIP;
   LaunchEnv env = env_of(c, st);
   const bool f32 = c->cfg.precision == TR_PREC_F32_STORAGE;
   int K[TR_NBUCKET], Sp[TR_NBUCKET];
