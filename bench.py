@@ -15,6 +15,7 @@ algorithmic bytes per launch / average launch time), the learned closure vs
 the plain method, and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -40,6 +41,7 @@ WORKLOADS = {
               "autotuned sweep tiles"),
 }
 KERNELS = ["opacity", "sweep", "moments", "lo_fine", "restrict", "lo_coarse", "grey"]
+LMAX_CANDIDATES = (1, 2, 4)  # cycles per transport iteration tried in the set-up
 
 
 def sweep_bytes(slab, ibytes=8):
@@ -91,7 +93,7 @@ def measured_traffic(workload, bytes_per_launch):
     return None
 
 
-def cpu_baseline(workload, budget_s=20.0):
+def cpu_baseline(workload, budget_s=20.0, lmax=None):
     """The CPU oracle (numpy, FP64, one thread) on the first time steps of the
     workload (bounded to about budget_s seconds); run in a child process whose
     BLAS / OpenMP pools are limited to one thread."""
@@ -101,18 +103,22 @@ def cpu_baseline(workload, budget_s=20.0):
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
         env[k] = "1"
     env["HIP_VISIBLE_DEVICES"] = ""
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", workload,
-                        "--cpu-budget", str(budget_s)], capture_output=True, text=True, env=env)
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", workload, "--cpu-budget", str(budget_s)]
+    if lmax is not None:
+        cmd += ["--cpu-lmax", str(lmax)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env)
     if r.returncode != 0:
         return {"error": r.stderr[-500:]}
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def _cpu_baseline_child(workload, budget_s):
+def _cpu_baseline_child(workload, budget_s, lmax=None):
     from oracle import mlqd
     from paper_2011_05427_amd import inputs
 
     slabs, cfg, _ = getattr(inputs, WORKLOADS[workload][0])()
+    if lmax is not None:
+        cfg = dataclasses.replace(cfg, lmax=lmax)  # the GPU run's choice
     if workload == "batch":
         # the oracle on the first slabs of the batch, one step each, within the budget
         t0 = time.perf_counter()
@@ -237,6 +243,39 @@ def learned_vs_plain(slabs, levels, cfg, tiles, args, plain_ms, plain_sweeps):
                     "seeds the cell factors with its predicted change; the plain sweeps decide convergence"}
 
 
+def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles, cands, initial):
+    """The same steps with the cycle and lmax chosen per step by
+    ``tuning.StageSchedule`` (seeded with the set-up costs; every candidate's
+    graphs captured in untimed warmup steps)."""
+    import torch
+
+    from paper_2011_05427_amd import binding, tuning
+
+    sv = binding.Solver(slabs, levels, cfg)
+    sv.set_tiles(*tiles)
+    st = sv.new_state()
+    for cand in cands:
+        sv.set_schedule(*cand)
+        sv.state_init(st, slabs[0].T0)
+        for _ in range(max(warmup, 2)):
+            sv.step(st)
+    sv.state_init(st, slabs[0].T0)
+    ctl = tuning.StageSchedule(cands, initial=initial)
+    torch.cuda.synchronize()
+    acc = (binding.TrStats * len(slabs))()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctl.step(sv, st, stats=acc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sv.close()
+    return {"ms_per_step": 1e3 * wall / steps,
+            "value": sum(s.cell_updates_per_sweep() * int(a.n_ti) for s, a in zip(slabs, acc)) / wall,
+            "sweeps": int(sum(a.n_ti for a in acc)), "cycles": int(sum(a.n_c for a in acc)),
+            "choices": [f"{'VWF'[c]}{l}" for (c, l), _ in ctl.history],
+            "note": "candidates " + ",".join(f"{'VWF'[c]}{l}" for c, l in cands) + "; probe every 8 steps"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +285,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-lmax", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
     ap.add_argument("--train-samples", type=int, default=1000000)
     ap.add_argument("--train-epochs", type=int, default=5)
@@ -255,7 +295,7 @@ def main():
                     help="also time the binary32-storage sweep variant and state its error vs binary64")
     args = ap.parse_args()
     if args.cpu_baseline_child:
-        print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget)))
+        print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget, args.cpu_lmax)))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -282,6 +322,13 @@ def main():
     tune_info = tuning.tune(sv, st, reps=3, path=None)
     tune_info["tune_s"] = time.perf_counter() - t0
     tiles = (tune_info["K"], tune_info["split"])
+    # lmax of the workload's cycle chosen from the measured cost of its first
+    # steps (untimed set-up, tr_set_schedule); the workload fixes the cycle
+    # and the tolerances, not lmax
+    cfg_lmax = cfg.lmax
+    cands = [(cfg.cycle, l) for l in LMAX_CANDIDATES]
+    sched_ms = tuning.tune_schedule(sv, st, cands, steps=2)
+    cfg = dataclasses.replace(cfg, lmax=next(iter(sched_ms))[1])
     sv.close()
     del st
 
@@ -325,7 +372,7 @@ def main():
             "slabs": len(slabs),
             "cell_updates_per_sweep": sum(s.cell_updates_per_sweep() for s in slabs),
             "levels": levels[0] if len(slabs) == 1 else "per slab G,G/8,1",
-            "cycle": "VWF"[cfg.cycle], "lmax": cfg.lmax, "eps": cfg.eps,
+            "cycle": "VWF"[cfg.cycle], "lmax": cfg.lmax, "eps": cfg.eps, "eps_inner": cfg.eps_inner,
             "steps_timed": args.steps, "sweeps": sum(sweeps), "cycles": int(sum(a.n_c for a in acc)),
             "lo_solves": int(sum(a.n_lo for a in acc)), "closure": "plain",
         },
@@ -350,8 +397,6 @@ def main():
         },
     }
     if args.fp32:
-        import dataclasses
-
         import numpy as np
 
         cfg32 = dataclasses.replace(cfg, precision=1)
@@ -374,6 +419,12 @@ def main():
     out["tiles"] = {"K_per_bucket": tune_info["K"], "split_per_bucket": tune_info["split"],
                     "us_per_tile": tune_info["us"], "tile_order": "q = (K in 1,2,4,8)[q // 3], (split in 1,2,4)[q % 3]",
                     "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}
+    out["schedule"] = {
+        "lmax_chosen": cfg.lmax, "lmax_configured": cfg_lmax,
+        "set_up_ms_per_step": {f"{'VWF'[c]}{l}": ms for (c, l), ms in sched_ms.items()},
+        "set_up": "2 steps from the initial state per candidate, after 2 untimed steps that capture its graphs",
+    }
+    out["stage_adaptive"] = run_stage_adaptive(slabs, levels, cfg, args.steps, args.warmup, tiles, cands, sched_ms)
     if not args.no_learned:
         out["learned"] = learned_vs_plain(slabs, levels, cfg, tiles, args, ms_step, sum(sweeps))
     tr = measured_traffic(args.workload, out["roofline"]["bytes_per_launch"])
@@ -391,7 +442,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 3}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, cfg.lmax)
     print(json.dumps(out), flush=True)
 
 

@@ -275,6 +275,20 @@ typedef struct tr_stats {
 int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats, hipStream_t stream);
 
 /*
+ * A8: cycle and lmax of the following tr_step calls (the context's grids stay:
+ * V visits none of the intermediate grids, W the second grid, F every
+ * intermediate grid from coarse to fine).  Which cycle, hierarchy and lmax
+ * cost least depends on the stage of the TRT process and on the time step
+ * (Sec. 6 and 7); this lets a caller choose them step by step.  Every
+ * intermediate grid's restriction tables and buffers are made at tr_create,
+ * so a change needs no new device memory; a schedule's graphs are captured
+ * at its first step and kept.  Host only, takes effect
+ * at the next tr_step.  Errors: TR_EINVAL (cycle not TR_CYCLE_*, lmax outside
+ * 1..64).
+ */
+int tr_set_schedule(tr_ctx *ctx, int cycle, int lmax);
+
+/*
  * Sweep kernel timing inside tr_step.  on = 1: the transport sweeps of
  * iterations s >= 1 are launched outside the replayed graphs, each launch
  * recording its own start and end on HIP events, and their kernel time is

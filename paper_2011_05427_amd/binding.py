@@ -71,7 +71,7 @@ EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_in
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
            "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
            "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing",
-           "tr_prolong"]
+           "tr_prolong", "tr_set_schedule"]
 
 _lib = None
 
@@ -107,6 +107,7 @@ def load():
     lib.tr_state_init.argtypes = [vp, C.POINTER(TrState), C.c_double, vp]
     lib.tr_step.argtypes = [vp, C.POINTER(TrState), _ip, C.POINTER(TrStats), vp]
     lib.tr_set_sweep_timing.argtypes = [vp, C.c_int]
+    lib.tr_set_schedule.argtypes = [vp, C.c_int, C.c_int]
     lib.tr_prolong.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.tr_mlp_nparam.argtypes = []
     lib.tr_mlp_work_bytes.argtypes = [C.c_longlong]
@@ -179,6 +180,7 @@ class Solver:
         self._ctx = C.c_void_p()
         _check(self.lib.tr_create(C.byref(self._ctx), probs, len(self.slabs), C.byref(c)), "tr_create")
         self.n = len(self.slabs)
+        self.schedule = (int(cfg.cycle), int(cfg.lmax))
 
     def close(self):
         if self._ctx:
@@ -301,6 +303,13 @@ class Solver:
         output [gi][2] float32 or None)."""
         _check(self.lib.tr_prolong(self._ctx, int(level), _ptr(E_coarse), _ptr(E_prev),
                                    _ptr(r) if r is not None else None, _ptr(E_fine), self._stream()), "tr_prolong")
+
+    def set_schedule(self, cycle: int, lmax: int):
+        """Cycle (CYCLE_V / W / F over this context's grids) and lmax of the
+        following steps (paper Alg. 3; chosen per step by a caller such as
+        ``tuning.StageSchedule``)."""
+        _check(self.lib.tr_set_schedule(self._ctx, int(cycle), int(lmax)), "tr_set_schedule")
+        self.schedule = (int(cycle), int(lmax))
 
     def set_sweep_timing(self, on: bool):
         """Sweeps of tr_step launched with start / end events (kernel time in

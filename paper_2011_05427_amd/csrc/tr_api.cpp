@@ -13,6 +13,10 @@
 #include "tr.h"
 #include "tr_kernels.h"
 
+// Instantiated graph sets kept per context (state buffers x schedule); the
+// oldest is destroyed beyond this.
+#define TR_GRAPH_CACHE 12
+
 #define TR_NHEAD 40
 #define TR_NBUCKET 6
 
@@ -78,7 +82,7 @@ struct tr_ctx {
   int ev_used = 0;
   std::vector<TimedGroup> groups;
   // graph replay of one transport iteration (the launch sequence depends on
-  // the state pointers and on the number of cycles launched)
+  // the state pointers, the number of cycles launched, the cycle and lmax)
   struct GraphEntry {
     std::vector<const void *> key;
     // s = 0 (no sweep); s >= 1 with the sweep; s >= 1 without it (the sweep
@@ -467,8 +471,6 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     S.nmu = P.nmu;
     S.nlev = nlev;
     for (int l = 0; l < nlev; ++l) S.lev_ng[l] = P.level_ng[l];
-    S.nsched = (int)c->sched.size();
-    for (size_t q = 0; q < c->sched.size(); ++q) S.sched[q] = c->sched[q];
     S.nchunk = (P.ng + 63) / 64;
     S.rtarget = std::max(16, 4096 / n_slab);
     S.cv = P.cv;
@@ -527,8 +529,9 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     }
     {
       // stage dS partials: rows per cell of the fused restriction fine -> gm
+      // (every intermediate grid: the schedule can change between steps)
       long long worst = 0;
-      for (int gm : c->sched) {
+      for (int gm : schedule_for(TR_CYCLE_F, nlev)) {
         const int r = P.level_ng[0] / P.level_ng[gm];
         S.dsnp[gm] = P.level_ng[gm] * restrict_cpb(r, P.level_ng[gm], P.nx + 1, S.rtarget);
         worst = std::max(worst, (long long)S.dsnp[gm]);
@@ -550,11 +553,6 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     S.o_gpi = S.o_lpi[nlev - 1];
     S.o_gpe = S.o_lpe[nlev - 1];
     S.o_gp2 = S.o_lp2[nlev - 1];
-    {
-      int k = S.lev_ng[0] + 1;
-      for (int q = 0; q < S.nsched; ++q) k += S.lev_ng[S.sched[q]] + 1;
-      S.cyc_cost = k;
-    }
     for (int i = 0; i < P.nx; ++i) {
       h_dx.push_back(P.x_edges[i + 1] - P.x_edges[i]);
       h_C.push_back(P.C_cell[i]);
@@ -672,7 +670,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       if ((rc = upload_table(c, items, c->t_sweep_b[b]))) return fail(rc);
     }
     if ((rc = build_restrict_tables(c, 0, nlev - 1))) return fail(rc);
-    for (int gsched : c->sched) {
+    for (int gsched : schedule_for(TR_CYCLE_F, nlev)) {
       if ((rc = build_restrict_tables(c, 0, gsched)) || (rc = build_restrict_tables(c, 0, gsched, 1)) ||
           (rc = build_restrict_tables(c, gsched, nlev - 1)))
         return fail(rc);
@@ -1014,6 +1012,8 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
   ga.Ts = c->Ts;
   ga.Es = c->Es;
   ga.ctl_dummy = c->d_ctl;
+  ga.stage_mask = 0;
+  for (int gm : c->sched) ga.stage_mask |= 1 << gm;
   ga.secant = c->cfg.secant;
   ga.lmax = c->cfg.lmax;
   ga.eps = c->cfg.eps;
@@ -1092,6 +1092,14 @@ int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, b
 
 extern "C" {
 
+int tr_set_schedule(tr_ctx *c, int cycle, int lmax) {
+  if (!c || cycle < 0 || cycle > 2 || lmax < 1 || lmax > TR_MAXOUT) return TR_EINVAL;
+  c->cfg.cycle = cycle;
+  c->cfg.lmax = lmax;
+  c->sched = schedule_for(cycle, c->nlev);
+  return TR_OK;
+}
+
 int tr_set_sweep_timing(tr_ctx *c, int on) {
   if (!c || (on != 0 && on != 1)) return TR_EINVAL;
   c->sweep_events = on;
@@ -1158,11 +1166,13 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   tr_ctx::GraphEntry *ge = nullptr;
   if (!c->cfg.timing) {
     std::vector<const void *> key = {s->I_prev, s->I_out, s->E, s->F, s->Ebnd, s->f, s->fbnd, s->C, s->Egrey,
-                                     reinterpret_cast<const void *>((intptr_t)Lmax)};
+                                     reinterpret_cast<const void *>((intptr_t)Lmax),
+                                     reinterpret_cast<const void *>((intptr_t)c->cfg.lmax),
+                                     reinterpret_cast<const void *>((intptr_t)c->cfg.cycle)};
     for (auto &g : c->graphs)
       if (g.key == key) ge = &g;
     if (!ge) {
-      if (c->graphs.size() >= 4) {
+      if (c->graphs.size() >= TR_GRAPH_CACHE) {
         auto &old = c->graphs.front();
         (void)hipGraphExecDestroy(old.first);
         (void)hipGraphExecDestroy(old.next);

@@ -12,8 +12,6 @@
 struct SlabDev {
   int nx, ng, nmu, nlev;
   int lev_ng[TR_MAXLEV];
-  int nsched;
-  int sched[TR_MAXLEV];  // level indices visited after each grey solve
   int nchunk;            // 64-group chunks of the fine grid (opacity partials)
   int rtarget;           // restriction chunk pass: blocks aimed at per slab
   double cv, dt, c, aR, inv_cdt;
@@ -25,7 +23,6 @@ struct SlabDev {
   long long o_lpi[TR_MAXLEV], o_lpe[TR_MAXLEV], o_lp2[TR_MAXLEV];
   long long o_red;  // restriction scratch records (per slab)
   long long o_gpi, o_gpe, o_gp2;  // grey level offsets (= o_lpi / o_lpe / o_lp2 of the last level)
-  int cyc_cost;              // LO solves per cycle
   long long o_dsop;          // stage dS partials (per slab)
   int dsnp[TR_MAXLEV];       // stage dS partial rows of the restriction fine -> level
 };

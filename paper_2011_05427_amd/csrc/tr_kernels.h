@@ -40,6 +40,7 @@ struct GreyArgs {
   double *Egrey;                   // cell: grey E output (nullable)
   double *Tcyc, *Ecyc, *Ts, *Es;   // convergence references (step mode)
   const Ctl *ctl_dummy;             // any valid control record (read, unused, without control)
+  int stage_mask;                   // bit l: grid l is visited after each grey solve (LO solves counted)
   int secant, end_cycle, lmax;
   double eps, eps_inner;
 };

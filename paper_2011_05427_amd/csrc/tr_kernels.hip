@@ -1369,7 +1369,7 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
   const bool has_ctl = ctl != nullptr;
   const Ctl &kc = has_ctl ? ctl[slab] : *ga.ctl_dummy;
   const int4 hd = *reinterpret_cast<const int4 *>(&kc);  // active, s, ncyc, inner_done
-  const int c_ncyc = hd.z, c_s = hd.y, c_nrep = kc.n_replay, c_hasprev = kc.has_prev, c_cost = S.cyc_cost;
+  const int c_ncyc = hd.z, c_s = hd.y, c_nrep = kc.n_replay, c_hasprev = kc.has_prev;
   if (has_ctl && !pred_ok(ctl, slab, pmode, lcyc)) return;
   const int c_rep = (has_ctl && c_nrep > 0) ? kc.replay[c_s] : 0;
   const int t = threadIdx.x;
@@ -1491,7 +1491,11 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
     cc.has_prev = 1;
     cc.ncyc = ncyc;
     cc.n_c += 1;
-    cc.n_lo += c_cost;
+    // LO solves of the cycle: the fine groups, the grey level and every stage
+    int cost = S.lev_ng[0] + 1;
+    for (int l = 1; l < TR_MAXLEV; ++l)
+      if ((ga.stage_mask >> l) & 1) cost += S.lev_ng[l] + 1;
+    cc.n_lo += cost;
     int inner_done, outer_done = 0;
     if (!isfinite(Tmax) || !isfinite(Emax)) {
       cc.err = -5;

@@ -1,0 +1,96 @@
+"""Host logic of the per-step cycle / lmax choice (tuning.StageSchedule and
+tuning.tune_schedule) with a stand-in solver on CPU tensors: the controller's
+choices follow from the recorded times alone, and the set-up search leaves the
+state as it found it."""
+import pytest
+import torch
+
+from paper_2011_05427_amd import tuning
+
+V, W, F = 0, 1, 2
+
+
+def test_tries_every_candidate_then_takes_the_cheapest():
+    ctl = tuning.StageSchedule([(V, 1), (V, 2), (V, 4)], probe=0)
+    seen = []
+    for ms in (3.0, 2.0, 5.0):
+        c = ctl.choose()
+        seen.append(c)
+        ctl.record(c, ms)
+    assert seen == [(V, 1), (V, 2), (V, 4)]
+    for _ in range(5):
+        c = ctl.choose()
+        assert c == (V, 2)
+        ctl.record(c, 2.0)
+
+
+def test_weighted_mean_reorders_when_the_cost_changes():
+    ctl = tuning.StageSchedule([(V, 1), (W, 2)], probe=0, decay=0.5, initial={(V, 1): 1.0, (W, 2): 1.5})
+    assert ctl.choose() == (V, 1)
+    ctl.record((V, 1), 3.0)  # mean 0.5 * 1.0 + 0.5 * 3.0 = 2.0 > 1.5
+    assert ctl.cost[(V, 1)] == pytest.approx(2.0)
+    assert ctl.choose() == (W, 2)
+
+
+def test_probe_reruns_the_oldest_measurement():
+    ctl = tuning.StageSchedule([(V, 1), (V, 2)], probe=4, initial={(V, 1): 1.0, (V, 2): 2.0})
+    choices = []
+    for _ in range(9):
+        c = ctl.choose()
+        choices.append(c)
+        ctl.record(c, 1.0 if c == (V, 1) else 2.0)
+    # steps 4 and 8 probe (V, 2), whose measurement is the oldest
+    assert choices == [(V, 1)] * 4 + [(V, 2)] + [(V, 1)] * 3 + [(V, 2)]
+
+
+def test_ties_follow_candidate_order_and_bad_settings_are_rejected():
+    ctl = tuning.StageSchedule([(F, 2), (V, 1)], probe=0, initial={(F, 2): 1.0, (V, 1): 1.0})
+    assert ctl.choose() == (F, 2)
+    with pytest.raises(ValueError):
+        tuning.StageSchedule([])
+    with pytest.raises(ValueError):
+        tuning.StageSchedule([(V, 1)], decay=1.0)
+
+
+class _FakeSolver:
+    """Stands in for binding.Solver: a step adds lmax to T and swaps the two
+    intensity buffers (as the binding does)."""
+
+    def __init__(self):
+        self.schedule = (V, 4)
+        self.calls = []
+
+    def set_schedule(self, cycle, lmax):
+        self.schedule = (cycle, lmax)
+        self.calls.append(("set", cycle, lmax))
+
+    def step(self, st, **kw):
+        st["T"] += self.schedule[1]
+        st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
+        self.calls.append(("step",) + self.schedule)
+        return None
+
+
+def test_tune_schedule_restores_the_state_and_ranks_every_candidate():
+    st = {"T": torch.zeros(3, dtype=torch.float64), "I_prev": torch.ones(4, dtype=torch.float64),
+          "I_out": torch.full((4,), 2.0, dtype=torch.float64)}
+    ref = {k: v.clone() for k, v in st.items()}
+    sv = _FakeSolver()
+    out = tuning.tune_schedule(sv, st, [(V, 1), (V, 2)], steps=3)
+    assert set(out) == {(V, 1), (V, 2)}
+    assert list(out.values()) == sorted(out.values())
+    for k in ref:
+        assert torch.equal(st[k], ref[k]), k
+    # per candidate: two untimed steps, then the timed ones
+    assert [c for c in sv.calls if c[0] == "step"].count(("step", V, 1)) == 5
+
+
+def test_stage_schedule_drives_a_solver_and_records_each_step():
+    st = {"T": torch.zeros(1, dtype=torch.float64), "I_prev": torch.zeros(1), "I_out": torch.zeros(1)}
+    sv = _FakeSolver()
+    ctl = tuning.StageSchedule([(V, 1), (V, 2)], probe=0)
+    for _ in range(4):
+        ctl.step(sv, st)
+    assert [c for c, _ in ctl.history][:2] == [(V, 1), (V, 2)]
+    assert len(ctl.history) == 4
+    assert sv.calls[0] == ("set", V, 1)
