@@ -129,9 +129,44 @@ def make_slab(nx: int, ng: int, nmu: int, *, C1: float = 27.0, C2: float = 2.7,
                 T_left=T_left, T_right=T_right, cv=cv, dt=dt, T0=T0)
 
 
+def double_gauss_legendre(n: int):
+    """Double S_n: the n-point Gauss-Legendre rule mapped to each half range
+    [-1, 0] and [0, 1] (2 n directions, ascending, weights summing to 2)."""
+    x, w = gauss_legendre(n)
+    mp, wp = 0.5 * (x + 1.0), 0.5 * w
+    return np.concatenate([-mp[::-1], mp]), np.concatenate([wp[::-1], wp])
+
+
 # ---------------------------------------------------------------------------
 # Named workloads
 # ---------------------------------------------------------------------------
+
+FC_DT = (0.02, 0.04)  # ns: the two time steps of the Fleck-Cummings runs (150 and 75 steps to 3 ns)
+
+
+def fc_slab(dt: float = 0.02) -> Slab:
+    """The paper's Fleck-Cummings set-up (Sec. 6): [0, 4] cm in 10 uniform
+    cells, one material (C = 27), black-body incoming at 1 keV on the left,
+    vacuum on the right, T0 = 1e-3 keV, c_v = 0.5917 a_R T_b^3 with T_b = 1
+    keV, 256 groups: 254 log-spaced between 1e-4 and 10 keV and the two end
+    groups [0, 1e-4] and [10, inf) (the paper's 1e7 keV bound carries no
+    Planck energy in binary64), double S8.  The end groups' opacity centres
+    extend the log spacing by one ratio (reading: the paper averages over
+    the spectrum, this build evaluates kappa at a group centre)."""
+    r = (10.0 / 1e-4) ** (1.0 / 254)
+    x = np.linspace(0.0, 4.0, 11)
+    edges, centre = log_groups(256, 1e-4 / r, 10.0 * r)
+    mu, w = double_gauss_legendre(8)
+    return Slab(x_edges=x, nu_edges=edges, nu_center=centre, mu=mu, w=w, C_cell=np.full(10, 27.0),
+                T_left=1.0, T_right=0.0, cv=0.5917 * A_RAD, dt=dt, T0=0.001)
+
+
+def config_fc(dt: float = 0.02, levels=(256, 1), cycle: int = CYCLE_V, lmax: int = 4):
+    """Fleck-Cummings runs of Tables 1 (dt = 0.02 ns) and 2 (0.04 ns): eps =
+    1e-6, inner eps = 1e-7, to t = 3 ns."""
+    cfg = SolverCfg(levels=list(levels), cycle=cycle, lmax=lmax, eps=1e-6, eps_inner=1e-7)
+    return [fc_slab(dt)], cfg, int(round(3.0 / dt))
+
 
 def config_small():
     """50 cells, S8, 16 groups, two-grid V (16 -> 1), one step dt=0.002."""
