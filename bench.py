@@ -286,6 +286,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-lmax", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--lmax", type=int, default=None,
+                    help="use this lmax instead of the set-up choice (e.g. to profile a plain run's choice)")
+    ap.add_argument("--tiles", default=None,
+                    help="sweep tiles 'K1,..,K6:S1,..,S6' per slab-size bucket instead of the autotuner's")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
     ap.add_argument("--train-samples", type=int, default=1000000)
     ap.add_argument("--train-epochs", type=int, default=5)
@@ -319,16 +323,26 @@ def main():
     st = sv.new_state()
     sv.state_init(st, slabs[0].T0)
     t0 = time.perf_counter()
-    tune_info = tuning.tune(sv, st, reps=3, path=None)
+    if args.tiles:
+        ks, ss = args.tiles.split(":")
+        tiles = ([int(v) for v in ks.split(",")], [int(v) for v in ss.split(",")])
+        sv.set_tiles(*tiles)
+        tune_info = {"K": tiles[0], "split": tiles[1], "us": None, "fixed": True}
+    else:
+        tune_info = tuning.tune(sv, st, reps=3, path=None)
+        tiles = (tune_info["K"], tune_info["split"])
     tune_info["tune_s"] = time.perf_counter() - t0
-    tiles = (tune_info["K"], tune_info["split"])
     # lmax of the workload's cycle chosen from the measured cost of its first
     # steps (untimed set-up, tr_set_schedule); the workload fixes the cycle
     # and the tolerances, not lmax
     cfg_lmax = cfg.lmax
     cands = [(cfg.cycle, l) for l in LMAX_CANDIDATES]
-    sched_ms = tuning.tune_schedule(sv, st, cands, steps=2)
-    cfg = dataclasses.replace(cfg, lmax=next(iter(sched_ms))[1])
+    if args.lmax is not None:
+        sched_ms = None
+        cfg = dataclasses.replace(cfg, lmax=args.lmax)
+    else:
+        sched_ms = tuning.tune_schedule(sv, st, cands, steps=2)
+        cfg = dataclasses.replace(cfg, lmax=next(iter(sched_ms))[1])
     sv.close()
     del st
 
@@ -417,12 +431,13 @@ def main():
             "note": "corner intensities stored in binary32; sweep arithmetic, moments, LO, grey and MEB in binary64",
         }
     out["tiles"] = {"K_per_bucket": tune_info["K"], "split_per_bucket": tune_info["split"],
-                    "us_per_tile": tune_info["us"], "tile_order": "q = (K in 1,2,4,8)[q // 3], (split in 1,2,4)[q % 3]",
+                    "us_per_tile": tune_info["us"], "fixed_by_option": bool(tune_info.get("fixed")), "tile_order": "q = (K in 1,2,4,8)[q // 3], (split in 1,2,4)[q % 3]",
                     "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}
     out["schedule"] = {
         "lmax_chosen": cfg.lmax, "lmax_configured": cfg_lmax,
-        "set_up_ms_per_step": {f"{'VWF'[c]}{l}": ms for (c, l), ms in sched_ms.items()},
-        "set_up": "2 steps from the initial state per candidate, after 2 untimed steps that capture its graphs",
+        "set_up_ms_per_step": ({f"{'VWF'[c]}{l}": ms for (c, l), ms in sched_ms.items()} if sched_ms else None),
+        "set_up": ("2 steps from the initial state per candidate, after 2 untimed steps that capture its graphs"
+                   if sched_ms else "fixed by --lmax"),
     }
     out["stage_adaptive"] = run_stage_adaptive(slabs, levels, cfg, args.steps, args.warmup, tiles, cands, sched_ms)
     if not args.no_learned:
