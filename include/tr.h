@@ -250,7 +250,10 @@ typedef struct tr_stats {
   int cycles[64];  /* cycles per transport iteration of the last step */
   double t_ms[TR_T_N];     /* with cfg.timing: summed kernel time per group
                               (TR_T_*), over launches that did work; with
-                              tr_set_sweep_timing only t_ms[TR_T_SWEEP] */
+                              tr_set_sweep_timing only t_ms[TR_T_SWEEP].
+                              Inside tr_step the QD factors after a sweep are
+                              formed by the first fine LO solve (time under
+                              TR_T_LO_FINE; TR_T_MOMENTS stays 0) */
   long long n_launch[TR_T_N]; /* timed launch groups per TR_T_* (sweep: kernel
                                  launches, one per non-empty slab-size bucket
                                  and transport iteration) */

@@ -1021,9 +1021,17 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
   const int nsch = (int)c->sched.size();
   if (with_sweep && !sweep_outside)
     launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
+  // after a sweep the first fine solve forms the QD factors from the sweep's
+  // partials (its slabs are exactly those that swept: every slab leaves the
+  // s = 0 iteration at s >= 1, and an iteration with a sweep starts at cycle 0)
+  LoIn fine0 = fine;
   if (with_sweep) {
-    TimedScope ts(c, st, TR_T_MOMENTS, -1);
-    launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
+    fine0.mom = c->mom;
+    fine0.bnd = c->bnd;
+    fine0.f_out = s->f;
+    fine0.fbnd_out = s->fbnd;
+    fine0.C_out = s->C;
+    fine0.Phi_out = c->Phi;
   }
   for (int l = lbeg; l < lend; ++l) {
     // old-time sums are constant during the step: restricted in its first
@@ -1031,7 +1039,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     const bool old = !with_sweep && l == 0;
     {
       TimedScope ts(c, st, TR_T_LO_FINE, l);
-      launch_lo_all(c, env, c->d_ctl, PRED_CYCLE, l, 0, fine, fsol);
+      launch_lo_all(c, env, c->d_ctl, PRED_CYCLE, l, 0, l == 0 ? fine0 : fine, fsol);
     }
     {
       TimedScope ts(c, st, TR_T_RESTRICT, l);

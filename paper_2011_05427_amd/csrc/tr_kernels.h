@@ -13,6 +13,11 @@ struct LoIn {
   const double *kappa, *B, *f, *fbnd;
   const double *sigE, *emis, *a, *b, *sigR;
   const double *C, *Phi, *Eold, *Fold;
+  // fine level, first cycle of an iteration with a sweep: the QD factors are
+  // formed from the sweep's half-range partials (mom, bnd) inside the solve
+  // and written to f_out, fbnd_out, C_out, Phi_out (all null otherwise)
+  const double *mom, *bnd;
+  double *f_out, *fbnd_out, *C_out, *Phi_out;
 };
 
 struct LoSol {

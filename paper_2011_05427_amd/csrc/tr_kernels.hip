@@ -542,6 +542,36 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
 // A3: QD factors from the half-range partials.  Thread = (slab, g, i); the
 // i = 0 thread of each group also forms the boundary factors.
 // ---------------------------------------------------------------------------
+// Cell factor f = chi / phi of the summed half-range moments (the isotropic
+// value where phi underflows).
+__device__ inline double cell_factor(double phi, double chi, double f_iso) {
+  return (phi > TR_TINY && chi > 0.0) ? chi / phi : f_iso;
+}
+
+// Boundary factors of a group from the outflow sums of the half range
+// leaving at x = 0 (b1: mu < 0) and at x = X (b0: mu > 0) and the incoming
+// intensities inl / inr: edge factors, C and Phi = F_in - c C E_in per side.
+struct BndFac {
+  double fb0, fb1, C0, C1, P0, P1;
+};
+__device__ inline BndFac boundary_factors(const SlabDev &S, double inl, double inr, const double *b0,
+                                          const double *b1) {
+  BndFac o;
+  {
+    const double den = b1[0] + inl * S.wpos, num = b1[2] + inl * S.wmu2pos;
+    o.fb0 = (den > TR_TINY && num > 0.0) ? num / den : S.f_iso;
+    o.C0 = (b1[0] > TR_TINY) ? b1[1] / b1[0] : -S.c_iso;
+    o.P0 = inl * S.wmupos - S.c * o.C0 * (inl * S.wpos / S.c);
+  }
+  {
+    const double den = b0[0] + inr * S.wneg, num = b0[2] + inr * S.wmu2neg;
+    o.fb1 = (den > TR_TINY && num > 0.0) ? num / den : S.f_iso;
+    o.C1 = (b0[0] > TR_TINY) ? b0[1] / b0[0] : S.c_iso;
+    o.P1 = inr * S.wmuneg - S.c * o.C1 * (inr * S.wneg / S.c);
+  }
+  return o;
+}
+
 __global__ __launch_bounds__(256) void k_moments(const SlabDev *__restrict__ sd, ProbDev pd,
                                                  const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
                                                  const double *__restrict__ mom, const double *__restrict__ bnd,
@@ -558,28 +588,19 @@ __global__ __launch_bounds__(256) void k_moments(const SlabDev *__restrict__ sd,
   const double *h1 = h0 + 2LL * ng * nx;
   const double phi = h0[0] + h1[0];
   const double chi = h0[1] + h1[1];
-  f[S.o_gi + idx] = (phi > TR_TINY && chi > 0.0) ? chi / phi : S.f_iso;
+  f[S.o_gi + idx] = cell_factor(phi, chi, S.f_iso);
   if (i != 0) return;
   const double inl = pd.inc[2 * S.o_g + g], inr = pd.inc[2 * S.o_g + ng + g];
   const double *b0 = bnd + 6 * S.o_g + 3 * g;            // mu > 0: leaves at x = X
   const double *b1 = bnd + 6 * S.o_g + 3 * ng + 3 * g;   // mu < 0: leaves at x = 0
   const long long o2 = 2 * S.o_g + 2 * g;
-  // x = 0
-  {
-    const double den = b1[0] + inl * S.wpos, num = b1[2] + inl * S.wmu2pos;
-    fbnd[o2] = (den > TR_TINY && num > 0.0) ? num / den : S.f_iso;
-    const double Cm = (b1[0] > TR_TINY) ? b1[1] / b1[0] : -S.c_iso;
-    C[o2] = Cm;
-    Phi[o2] = inl * S.wmupos - S.c * Cm * (inl * S.wpos / S.c);
-  }
-  // x = X
-  {
-    const double den = b0[0] + inr * S.wneg, num = b0[2] + inr * S.wmu2neg;
-    fbnd[o2 + 1] = (den > TR_TINY && num > 0.0) ? num / den : S.f_iso;
-    const double Cp = (b0[0] > TR_TINY) ? b0[1] / b0[0] : S.c_iso;
-    C[o2 + 1] = Cp;
-    Phi[o2 + 1] = inr * S.wmuneg - S.c * Cp * (inr * S.wneg / S.c);
-  }
+  const BndFac o = boundary_factors(S, inl, inr, b0, b1);
+  fbnd[o2] = o.fb0;
+  C[o2] = o.C0;
+  Phi[o2] = o.P0;
+  fbnd[o2 + 1] = o.fb1;
+  C[o2 + 1] = o.C1;
+  Phi[o2 + 1] = o.P1;
 }
 
 // Phi = F_in - c C E_in from given C and the current incoming (step start).
@@ -660,13 +681,38 @@ struct RowData {
   double C0, C1, P0, P1;
 };
 
-template <int K, bool FINE>
-__device__ inline void lo_load(const LevelView &v, RowData<K> &R) {
+// Factor source of the first fine solve of an iteration with a sweep: the
+// group's half-range partial rows (phi, chi per cell), its boundary factors
+// and the row its cell factors are written to.
+struct FacSrc {
+  __amdgpu_buffer_rsrc_t r0, r1, rf;
+  double f_iso;
+  BndFac bf;
+};
+
+template <int K, bool FINE, bool MOM = false>
+__device__ inline void lo_load(const LevelView &v, RowData<K> &R, const FacSrc *fs = nullptr) {
   // branch-free: buffer loads outside a row's range return zero, so every
   // load of the thread is issued before the first use
   const int t = threadIdx.x, nx = v.nx;
   const int cb = nx * 8, eb = (nx + 1) * 8;
   const __amdgpu_buffer_rsrc_t r_dx = buf_rsrc(v.dx, cb), r_Fo = buf_rsrc(v.Fold, eb), r_Eo = buf_rsrc(v.Eold, cb);
+  // MOM: factors of cells t K - 2 .. t K + K - 1 from the partials (zero
+  // outside the slab, as the factor loads are); the thread's own cells
+  // t K - 1 .. t K + K - 2 are written (stores outside the row are dropped)
+  double fc[K + 2];
+  if (MOM) {
+#pragma unroll
+    for (int j = 0; j < K + 2; ++j) {
+      const int i = t * K - 2 + j;
+      const double2 h0 = Pair<double>::load(fs->r0, i * 16), h1 = Pair<double>::load(fs->r1, i * 16);
+      fc[j] = (i >= 0 && i < nx) ? cell_factor(h0.x + h1.x, h0.y + h1.y, fs->f_iso) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tr_u32x2, fc[k + 1]), fs->rf, (t * K - 1 + k) * 8, 0,
+                                            0);
+  }
 #pragma unroll
   for (int q = 0; q <= K; ++q) {
     const int e = t * K - 1 + q;
@@ -676,12 +722,13 @@ __device__ inline void lo_load(const LevelView &v, RowData<K> &R) {
     R.Fo[q] = buf_load_f64(r_Fo, e * 8);
     if (FINE) {
       const __amdgpu_buffer_rsrc_t r_f = buf_rsrc(v.f, cb), r_k = buf_rsrc(v.kap, cb);
-      const double fe = buf_load_f64(r_f, e * 8), fm = buf_load_f64(r_f, (e - 1) * 8);
+      const double fe = MOM ? fc[q + 1] : buf_load_f64(r_f, e * 8);
+      const double fm = MOM ? fc[q] : buf_load_f64(r_f, (e - 1) * 8);
       const double ke = buf_load_f64(r_k, e * 8), km = buf_load_f64(r_k, (e - 1) * 8);
       // boundary factors are added (the cell loads are zero there), so that
       // no load is conditional
-      R.ae[q] = fe + (e == nx ? v.fbnd[1] : 0.0);
-      R.be[q] = fm + (e == 0 ? v.fbnd[0] : 0.0);
+      R.ae[q] = fe + (e == nx ? (MOM ? fs->bf.fb1 : v.fbnd[1]) : 0.0);
+      R.be[q] = fm + (e == 0 ? (MOM ? fs->bf.fb0 : v.fbnd[0]) : 0.0);
       // width-weighted sigma_R of the two cells (one cell on the boundary)
       const double id = (e > 0 && e < nx) ? 1.0 / (dxm + dxe) : 0.0;
       const double wm = (e == nx) ? 1.0 : dxm * id, we = (e == 0) ? 1.0 : dxe * id;
@@ -706,10 +753,17 @@ __device__ inline void lo_load(const LevelView &v, RowData<K> &R) {
       R.em[k] = buf_load_f64(buf_rsrc(v.emis, cb), i * 8);
     }
   }
-  R.C0 = v.C[0];
-  R.C1 = v.C[1];
-  R.P0 = v.Phi[0];
-  R.P1 = v.Phi[1];
+  if (MOM) {
+    R.C0 = fs->bf.C0;
+    R.C1 = fs->bf.C1;
+    R.P0 = fs->bf.P0;
+    R.P1 = fs->bf.P1;
+  } else {
+    R.C0 = v.C[0];
+    R.C1 = v.C[1];
+    R.P0 = v.Phi[0];
+    R.P1 = v.Phi[1];
+  }
 }
 
 // Builds the K rows of this thread from its level data; with eff = true the
@@ -847,7 +901,10 @@ __device__ inline void level_out(const SlabDev &S, int level, int p, const LoSol
 // ---------------------------------------------------------------------------
 // A4 / A6: LO solve, one thread block per (slab, group of the level).
 // ---------------------------------------------------------------------------
-template <int K, bool FINE>
+// MOM (fine level, first cycle of an iteration with a sweep): the group's QD
+// factors are formed here from the sweep's half-range partials, with the
+// arithmetic of k_moments, and written for the restriction and later cycles.
+template <int K, bool FINE, bool MOM>
 __global__ __launch_bounds__(512) void k_lo(const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab,
                                             const Ctl *ctl, int pmode, int lcyc, int level, LoIn in, LoSol sol) {
   extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
@@ -857,7 +914,30 @@ __global__ __launch_bounds__(512) void k_lo(const SlabDev *__restrict__ sd, Prob
   const int p = it.idx;
   const LevelView v = make_view<FINE>(S, pd, level, in, p);
   double ra[K], rb[K], rc[K], rd[K], x[K], Ak[K + 1], ca[K + 1], cb[K + 1], dummy[K];
-  lo_rows<K, FINE>(v, S.c, S.dt, S.inv_cdt, false, dummy, dummy, ra, rb, rc, rd, Ak, ca, cb);
+  if (MOM) {
+    const int nx = S.nx, ng = S.ng;
+    FacSrc fs;
+    fs.r0 = buf_rsrc(in.mom + 4 * S.o_gi + 2LL * p * nx, nx * 16);
+    fs.r1 = buf_rsrc(in.mom + 4 * S.o_gi + 2LL * ng * nx + 2LL * p * nx, nx * 16);
+    fs.rf = buf_rsrc(in.f_out + S.o_gi + (long long)p * nx, nx * 8);
+    fs.f_iso = S.f_iso;
+    const double inl = pd.inc[2 * S.o_g + p], inr = pd.inc[2 * S.o_g + ng + p];
+    fs.bf = boundary_factors(S, inl, inr, in.bnd + 6 * S.o_g + 3 * p, in.bnd + 6 * S.o_g + 3 * ng + 3 * p);
+    if (threadIdx.x == 0) {
+      const long long o2 = 2 * S.o_g + 2 * p;
+      in.fbnd_out[o2] = fs.bf.fb0;
+      in.fbnd_out[o2 + 1] = fs.bf.fb1;
+      in.C_out[o2] = fs.bf.C0;
+      in.C_out[o2 + 1] = fs.bf.C1;
+      in.Phi_out[o2] = fs.bf.P0;
+      in.Phi_out[o2 + 1] = fs.bf.P1;
+    }
+    RowData<K> R;
+    lo_load<K, true, true>(v, R, &fs);
+    lo_build<K>(R, nx, S.c, S.dt, S.inv_cdt, false, dummy, dummy, ra, rb, rc, rd, Ak, ca, cb);
+  } else {
+    lo_rows<K, FINE>(v, S.c, S.dt, S.inv_cdt, false, dummy, dummy, ra, rb, rc, rd, Ak, ca, cb);
+  }
   tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
   double *E, *F, *Eb;
   level_out<FINE>(S, level, p, sol, E, F, Eb);
@@ -1867,11 +1947,14 @@ void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double 
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
                const LoIn &in, const LoSol &sol) {
   if (tab.n == 0) return;
-  if (level == 0)
-    hipLaunchKernelGGL((k_lo<TR_LO_K, true>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
+  if (level == 0 && in.mom)
+    hipLaunchKernelGGL((k_lo<TR_LO_K, true, true>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd,
+                       tab.d, ctl, pmode, lcyc, level, in, sol);
+  else if (level == 0)
+    hipLaunchKernelGGL((k_lo<TR_LO_K, true, false>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
                        pmode, lcyc, level, in, sol);
   else
-    hipLaunchKernelGGL((k_lo<TR_LO_K, false>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
+    hipLaunchKernelGGL((k_lo<TR_LO_K, false, false>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
                        pmode, lcyc, level, in, sol);
 }
 
