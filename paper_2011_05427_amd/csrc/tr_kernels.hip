@@ -1450,6 +1450,9 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
   const Ctl &kc = has_ctl ? ctl[slab] : *ga.ctl_dummy;
   const int4 hd = *reinterpret_cast<const int4 *>(&kc);  // active, s, ncyc, inner_done
   const int c_ncyc = hd.z, c_s = hd.y, c_nrep = kc.n_replay, c_hasprev = kc.has_prev;
+  // counters updated at the end, read with the other control fields so that
+  // the update is no further round trip
+  const long long c_nfloor = kc.n_floor, c_nc = kc.n_c, c_nlo = kc.n_lo;
   if (has_ctl && !pred_ok(ctl, slab, pmode, lcyc)) return;
   const int c_rep = (has_ctl && c_nrep > 0) ? kc.replay[c_s] : 0;
   const int t = threadIdx.x;
@@ -1558,7 +1561,7 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
   block_reduce_grey(red, nfl, lds);
   if (!ga.end_cycle) {
     if (t == 0) {
-      ctl[slab].n_floor += nfl;
+      ctl[slab].n_floor = c_nfloor + nfl;
       ctl[slab].has_prev = 1;
     }
     return;
@@ -1567,15 +1570,15 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
     Ctl &cc = ctl[slab];
     const double dTc = red[0], dEc = red[1], dTs = red[2], dEs = red[3], Tmax = red[4], Emax = red[5];
     const int ncyc = c_ncyc + 1;
-    cc.n_floor += nfl;
+    cc.n_floor = c_nfloor + nfl;
     cc.has_prev = 1;
     cc.ncyc = ncyc;
-    cc.n_c += 1;
+    cc.n_c = c_nc + 1;
     // LO solves of the cycle: the fine groups, the grey level and every stage
     int cost = S.lev_ng[0] + 1;
     for (int l = 1; l < TR_MAXLEV; ++l)
       if ((ga.stage_mask >> l) & 1) cost += S.lev_ng[l] + 1;
-    cc.n_lo += cost;
+    cc.n_lo = c_nlo + cost;
     int inner_done, outer_done = 0;
     if (!isfinite(Tmax) || !isfinite(Emax)) {
       cc.err = -5;
