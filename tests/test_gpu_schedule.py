@@ -99,3 +99,34 @@ def test_stage_adaptive_run_reaches_the_fixed_schedule_solution():
         sv.close()
     assert rel_err(res[1][0], res[0][0]) < 1e-8
     assert rel_err(res[1][1], res[0][1]) < 1e-8
+
+
+def test_batch_schedule_changes_replay_each_slab():
+    """Three uneven slabs in one context switch schedule together; each slab
+    replays its own oracle run (its LO solve count follows its own grids)."""
+    slabs = [inputs.make_slab(30, 16, 8, C1=5.0, C2=40.0, T_left=0.8),
+             inputs.make_slab(50, 64, 16, C1=60.0, C2=2.0, T_left=1.3),
+             inputs.make_slab(12, 128, 8, C1=1.5, C2=9.0, T_left=0.6)]
+    levels = [[s.ng, s.ng // 8, 1] for s in slabs]
+    plan = [(W, 2), (V, 1), (W, 1), (V, 3)]
+    base = inputs.SolverCfg(levels=[0, 0, 1], cycle=W, lmax=2)
+    pbs = [mlqd.problem_from_slab(s) for s in slabs]
+    osts = [mlqd.initial_state(pb, s.T0) for pb, s in zip(pbs, slabs)]
+    sv = binding.Solver(slabs, levels, base)
+    st = sv.new_state()
+    sv.state_init(st, 0.001)
+    for j, (cyc, lmax) in enumerate(plan):
+        counts, nlo = [], []
+        for k in range(len(slabs)):
+            stats = mlqd.Stats()
+            osts[k] = mlqd.step(pbs[k], levels[k], _sched(levels[k], cyc), lmax, base.eps, base.eps_inner, osts[k],
+                                stats=stats)
+            counts.append(stats.counts[0])
+            nlo.append(stats.n_lo)
+        note(f"batch step {j}: cycle {'VWF'[cyc]} lmax {lmax}")
+        sv.set_schedule(cyc, lmax)
+        gs = sv.step(st, replay=counts)
+        for k in range(len(slabs)):
+            assert gs[k].n_lo == nlo[k], (j, k)
+            _compare_state(f"batch schedule step {j} slab {k}", sv, st, osts[k], slab_idx=k)
+    sv.close()
