@@ -14,7 +14,9 @@
  *    gives a message.  Nothing throws across the ABI.
  *  - One context serves one stream at a time; calls on one context are not
  *    thread-safe.
- *  - Floating point is IEEE binary64 throughout.
+ *  - Floating point is IEEE binary64 throughout, except the corner intensities
+ *    of a context created with TR_PREC_F32_STORAGE (binary32 storage) and the
+ *    closure network calls (float32 parameters, bfloat16 products).
  *
  * Batched layout ("pooled" arrays).  A context holds n_slab independent slab
  * problems.  Every per-slab array is stored slab after slab in creation order;
