@@ -620,7 +620,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
   // host memory (read after the synchronisation of every transport iteration)
   if (hipHostMalloc((void **)&c->h_count, 2 * sizeof(int), hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void **)&c->h_ctl_out, sizeof(Ctl) * n_slab, hipHostMallocCoherent) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_ctl_in, sizeof(Ctl) * n_slab, hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc((void **)&c->h_ctl_in, sizeof(Ctl) * n_slab, hipHostMallocCoherent) != hipSuccess)
     return fail(TR_ENOMEM);
   if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -1141,15 +1141,15 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   // everything runs on the library stream, ordered after the caller's work
   hipStream_t gs = c->gs;
   if (hipEventRecord(c->ev_in, st) != hipSuccess || hipStreamWaitEvent(gs, c->ev_in, 0) != hipSuccess) return TR_EHIP;
-  // (from pinned memory: the copy is asynchronous; the previous step has
-  // finished with the buffer)
+  // (coherent pinned memory, read by the step-start kernel; the previous
+  // step has finished with the buffer)
+  static_assert(sizeof(Ctl) % sizeof(int) == 0, "control records are copied as ints");
   std::memcpy(c->h_ctl_in, hc.data(), sizeof(Ctl) * ns);
-  if (hipMemcpyAsync(c->d_ctl, c->h_ctl_in, sizeof(Ctl) * ns, hipMemcpyHostToDevice, gs) != hipSuccess)
-    return TR_EHIP;
   LaunchEnv env = env_of(c, gs);
-  // step start: old-time copies, convergence references, Phi with the current incoming
+  // step start: control records, old-time copies, convergence references,
+  // Phi with the current incoming
   launch_step_start(env, s->T, s->Egrey, s->E, s->F, c->n_cell, c->n_gi, c->n_ge, c->Told, c->Ts, c->Tcyc, c->Tstar,
-                    c->Es, c->Ecyc, c->Eold, c->Fold);
+                    c->Es, c->Ecyc, c->Eold, c->Fold, c->h_ctl_in, c->d_ctl, ns);
   launch_phi(env, c->t_g, s->C, c->Phi);
   launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
   unsigned long long seed_counts[2] = {0, 0};
@@ -1227,11 +1227,15 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
     const bool one = ge->next1 != nullptr;
     int launched = 1;
     bool part = false;
+    // the new temperature goes to the state after every launched chain,
+    // ahead of the synchronisation (a later chain copies it again), so a
+    // converged step needs no launch after it
     if (hipGraphLaunch(ge->first, gs) != hipSuccess) return TR_EHIP;
     for (int q = 1; q < L; ++q, ++launched) {
       part = one && q == L - 1;
       if (hipGraphLaunch(part ? ge->next1 : ge->next, gs) != hipSuccess) return TR_EHIP;
     }
+    launch_copy(env, c->Tstar, s->T, c->n_cell);
     for (;;) {
       if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
       if (*hc_active == 0) {
@@ -1241,12 +1245,14 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       if (part && *hc_mid > 0) {
         part = false;
         if (hipGraphLaunch(ge->tail, gs) != hipSuccess) return TR_EHIP;
+        launch_copy(env, c->Tstar, s->T, c->n_cell);
         continue;
       }
       if (launched >= cap) break;
       part = false;
       ++launched;
       if (hipGraphLaunch(ge->next, gs) != hipSuccess) return TR_EHIP;
+      launch_copy(env, c->Tstar, s->T, c->n_cell);
     }
   } else {
     for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
@@ -1274,7 +1280,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       }
     }
   }
-  launch_copy(env, c->Tstar, s->T, c->n_cell);
+  if (!(ge && !sweep_ev)) launch_copy(env, c->Tstar, s->T, c->n_cell);
   if (done) {
     // the last iteration's end kernel wrote the final records to host memory
     // before the synchronisation above

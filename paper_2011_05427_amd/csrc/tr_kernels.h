@@ -123,10 +123,12 @@ void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, 
 // done) and the count of slabs still active into *out (one launch); with no
 // slab left active the control records are copied to hout.
 void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout);
-// Step-start copies of T, Egrey, E, F into the step's reference arrays.
+// Step-start copies of T, Egrey, E, F into the step's reference arrays, and
+// of the nslab control records from (coherent pinned) host memory ctl_in.
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
-                       double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold);
+                       double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
+                       Ctl *ctl, int nslab);
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n);
 void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
 void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,

@@ -1673,6 +1673,9 @@ struct StepCopies {
   const double *T, *Egrey, *E, *F;
   double *Told, *Ts, *Tcyc, *Tstar, *Es, *Ecyc, *Eold, *Fold;
   long long n_cell, n_gi, n_ge;
+  const int *ctl_in;  // control records in coherent pinned host memory (n_ctl words)
+  int *ctl;
+  long long n_ctl;
 };
 
 __global__ __launch_bounds__(256) void k_step_start(StepCopies a) {
@@ -1688,6 +1691,7 @@ __global__ __launch_bounds__(256) void k_step_start(StepCopies a) {
   }
   if (i < a.n_gi) a.Eold[i] = a.E[i];
   if (i < a.n_ge) a.Fold[i] = a.F[i];
+  if (i < a.n_ctl) a.ctl[i] = a.ctl_in[i];
 }
 
 // Elementwise copy over a pooled range.
@@ -2010,9 +2014,12 @@ void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, 
 
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
-                       double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold) {
-  const StepCopies a{T, Egrey, E, F, Told, Ts, Tcyc, Tstar, Es, Ecyc, Eold, Fold, n_cell, n_gi, n_ge};
-  const long long n = std::max(n_cell, std::max(n_gi, n_ge));
+                       double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
+                       Ctl *ctl, int nslab) {
+  const long long n_ctl = (long long)nslab * (long long)(sizeof(Ctl) / sizeof(int));
+  const StepCopies a{T,  Egrey, E,  F,    Told,  Ts,   Tcyc,  Tstar, Es, Ecyc, Eold, Fold, n_cell, n_gi, n_ge,
+                     reinterpret_cast<const int *>(ctl_in), reinterpret_cast<int *>(ctl), n_ctl};
+  const long long n = std::max(std::max(n_cell, n_ctl), std::max(n_gi, n_ge));
   if (n <= 0) return;
   hipLaunchKernelGGL(k_step_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, a);
 }
