@@ -194,21 +194,20 @@ def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closu
     acc = (binding.TrStats * len(slabs))()
     acc_ev = (binding.TrStats * len(slabs))()
     t0 = time.perf_counter()
-    for k in range(steps):
-        if k < sweep_ev:
-            # this step's sweeps are timed: its counters also go to acc_ev
-            sv.set_sweep_timing(True)
-            one = sv.step(st)
-            for q in range(len(slabs)):
-                for dst in (acc[q], acc_ev[q]):
-                    for f in ("n_ti", "n_c", "n_lo", "n_floor", "n_seeded", "n_fallback"):
-                        setattr(dst, f, getattr(dst, f) + getattr(one[q], f))
-                    for i in range(len(dst.t_ms)):
-                        dst.t_ms[i] += one[q].t_ms[i]
-                        dst.n_launch[i] += one[q].n_launch[i]
-            sv.set_sweep_timing(False)
-        else:
-            sv.step(st, stats=acc)
+    for _ in range(min(steps, sweep_ev)):
+        # this step's sweeps are timed: its counters also go to acc_ev
+        sv.set_sweep_timing(True)
+        one = sv.step(st)
+        for q in range(len(slabs)):
+            for dst in (acc[q], acc_ev[q]):
+                for f in ("n_ti", "n_c", "n_lo", "n_floor", "n_seeded", "n_fallback"):
+                    setattr(dst, f, getattr(dst, f) + getattr(one[q], f))
+                for i in range(len(dst.t_ms)):
+                    dst.t_ms[i] += one[q].t_ms[i]
+                    dst.n_launch[i] += one[q].n_launch[i]
+        sv.set_sweep_timing(False)
+    if steps > sweep_ev:
+        sv.run(st, steps - sweep_ev, stats=acc)  # the remaining steps in one library call
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if final is not None:

@@ -280,6 +280,19 @@ typedef struct tr_stats {
 int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats, hipStream_t stream);
 
 /*
+ * A8: nsteps consecutive free-running steps (as nsteps calls of tr_step
+ * without replay, with no return to the caller in between).  Step k uses the
+ * state with I_prev and I_out exchanged k times, as a caller of tr_step
+ * exchanges them after each step (so both buffers must be writable); after
+ * the call the caller exchanges its two pointers once more when nsteps is
+ * odd.  stats (host, nullable) as in
+ * tr_step, accumulated over the steps.  The call stops at the first failing
+ * step and returns its error; *done (host, nullable) receives the number of
+ * steps completed.  Errors: TR_EINVAL (nsteps < 0) and those of tr_step.
+ */
+int tr_run(tr_ctx *ctx, const tr_state *st, int nsteps, tr_stats *stats, int *done, hipStream_t stream);
+
+/*
  * A8: cycle and lmax of the following tr_step calls (the context's grids stay:
  * V visits none of the intermediate grids, W the second grid, F every
  * intermediate grid from coarse to fine).  Which cycle, hierarchy and lmax

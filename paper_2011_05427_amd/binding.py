@@ -71,7 +71,7 @@ EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_in
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
            "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
            "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing",
-           "tr_prolong", "tr_set_schedule"]
+           "tr_prolong", "tr_set_schedule", "tr_run"]
 
 _lib = None
 
@@ -108,6 +108,7 @@ def load():
     lib.tr_step.argtypes = [vp, C.POINTER(TrState), _ip, C.POINTER(TrStats), vp]
     lib.tr_set_sweep_timing.argtypes = [vp, C.c_int]
     lib.tr_set_schedule.argtypes = [vp, C.c_int, C.c_int]
+    lib.tr_run.argtypes = [vp, C.POINTER(TrState), C.c_int, C.POINTER(TrStats), _ip, vp]
     lib.tr_prolong.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.tr_mlp_nparam.argtypes = []
     lib.tr_mlp_work_bytes.argtypes = [C.c_longlong]
@@ -296,6 +297,19 @@ class Solver:
         _check(code, "tr_step")
         if swap:
             st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
+        return stats
+
+    def run(self, st: Dict, nsteps: int, stats=None):
+        """tr_run: nsteps free-running steps in one call; the dict's
+        intensity buffers end exchanged as after nsteps calls of step()."""
+        if stats is None:
+            stats = (TrStats * self.n)()
+        done = C.c_int(0)
+        code = self.lib.tr_run(self._ctx, C.byref(self._state(st)), int(nsteps), stats,
+                               C.cast(C.byref(done), _ip), self._stream())
+        if done.value % 2 == 1:
+            st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
+        _check(code, "tr_run")
         return stats
 
     def prolong(self, level, E_coarse, E_prev, r, E_fine):

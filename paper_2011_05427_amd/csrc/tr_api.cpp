@@ -1100,6 +1100,22 @@ int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, b
 
 extern "C" {
 
+int tr_run(tr_ctx *c, const tr_state *s, int nsteps, tr_stats *stats, int *done, hipStream_t st) {
+  if (done) *done = 0;
+  if (!c || !s || nsteps < 0) return TR_EINVAL;
+  tr_state w = *s;
+  for (int k = 0; k < nsteps; ++k) {
+    const int rc = tr_step(c, &w, nullptr, stats, st);
+    if (rc) return rc;
+    if (done) *done = k + 1;
+    // the two buffers exchange roles (both are the caller's writable arrays)
+    double *prev = const_cast<double *>(w.I_prev);
+    w.I_prev = w.I_out;
+    w.I_out = prev;
+  }
+  return TR_OK;
+}
+
 int tr_set_schedule(tr_ctx *c, int cycle, int lmax) {
   if (!c || cycle < 0 || cycle > 2 || lmax < 1 || lmax > TR_MAXOUT) return TR_EINVAL;
   c->cfg.cycle = cycle;

@@ -115,4 +115,5 @@ def test_calls_without_a_context_are_rejected():
     assert lib.tr_autotune(None, None, None, 1, K, S, None, None) == EINVAL
     assert lib.tr_set_sweep_timing(None, 1) == EINVAL
     assert lib.tr_set_schedule(None, 0, 1) == EINVAL
+    assert lib.tr_run(None, None, 1, None, None, None) == EINVAL
     assert lib.tr_step(None, None, None, None, None) == EINVAL

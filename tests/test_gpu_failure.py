@@ -106,3 +106,25 @@ def test_two_runs_and_a_resumed_run_are_bitwise_identical():
     sv.close()
     for k in runs[0]:
         assert np.array_equal(res[k], runs[0][k]), k
+
+
+def test_run_equals_single_steps():
+    """tr_run of n steps (no return to the caller between steps) leaves the
+    same state and counters as n calls of tr_step, bitwise, for an odd and an
+    even n."""
+    slab = _slab()
+    for n in (3, 4):
+        outs = []
+        for multi in (False, True):
+            sv, st = _solver(slab)
+            acc = (binding.TrStats * 1)()
+            if multi:
+                sv.run(st, n, stats=acc)
+            else:
+                for _ in range(n):
+                    sv.step(st, stats=acc)
+            outs.append(({k: to_np(v).copy() for k, v in st.items()}, (acc[0].n_ti, acc[0].n_c, acc[0].n_lo)))
+            sv.close()
+        assert outs[0][1] == outs[1][1]
+        for k in outs[0][0]:
+            assert np.array_equal(outs[0][0][k], outs[1][0][k]), (n, k)
