@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -54,7 +55,8 @@ struct tr_ctx {
     double *sigE, *emis, *a, *b, *sigR, *C, *Phi, *Eold, *Fold, *E, *F, *Ebnd, *Esum;
   } lev[TR_MAXLEV]{};
   Ctl *d_ctl = nullptr;
-  int *h_count = nullptr;  // pinned, coherent: [active slabs, slabs in mid-iteration] after an iteration graph
+  int *h_count = nullptr;  // pinned, coherent: [active slabs, slabs in mid-iteration, iteration serial]
+  int *d_serial = nullptr;  // iterations ended so far (device)
   Ctl *h_ctl_out = nullptr;  // pinned, coherent: control records once every slab stopped
   Ctl *h_ctl_in = nullptr;   // pinned: control records uploaded at the step start
   // work tables
@@ -270,6 +272,24 @@ void sweep_time(const tr_ctx *c, double *t_ms, long long *n_launch) {
 // the system-scope fence of a default event, recording them does not add a
 // cache writeback and invalidation to the timed interval.
 hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
+// Waits until the end kernel of the iteration with serial number `expect`
+// has published its counts (h_count[2]), spinning on the coherent host word
+// instead of a stream synchronisation; after about a second without it the
+// stream is synchronised (that also reports a failed launch).
+int wait_iteration(tr_ctx *c, int expect) {
+  volatile const int *ser = c->h_count + 2;
+  for (long long k = 0; *ser != expect; ++k) {
+    if ((k & 4095) == 4095) {
+      static const double limit_s = 1.0;
+      static thread_local std::chrono::steady_clock::time_point t0;
+      if (k == 4095) t0 = std::chrono::steady_clock::now();
+      if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit_s)
+        return hip_err(hipStreamSynchronize(c->gs));
+    }
+  }
+  return TR_OK;
+}
 
 // Event marks around kernel groups (cfg.timing).  A group records its cycle
 // index (-1 outside the cycles) so that launches of cycles a slab skipped can
@@ -614,14 +634,16 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     for (double **p : p2)
       if ((rc = dalloc(c, p, c->n_lp2[l]))) return fail(rc);
   }
-  if ((rc = dalloc(c, &c->d_ctl, n_slab)))
+  if ((rc = dalloc(c, &c->d_ctl, n_slab)) || (rc = dalloc(c, &c->d_serial, 1)))
     return fail(rc);
+  if (hipMemset(c->d_serial, 0, sizeof(int)) != hipSuccess) return fail(TR_EHIP);
   // the active-slab count is written by the GPU straight into coherent pinned
   // host memory (read after the synchronisation of every transport iteration)
-  if (hipHostMalloc((void **)&c->h_count, 2 * sizeof(int), hipHostMallocCoherent) != hipSuccess ||
+  if (hipHostMalloc((void **)&c->h_count, 3 * sizeof(int), hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void **)&c->h_ctl_out, sizeof(Ctl) * n_slab, hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void **)&c->h_ctl_in, sizeof(Ctl) * n_slab, hipHostMallocCoherent) != hipSuccess)
     return fail(TR_ENOMEM);
+  c->h_count[0] = c->h_count[1] = c->h_count[2] = 0;
   if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -1081,7 +1103,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     }
   }
   // start of the next transport iteration (s + 1) for slabs still iterating
-  launch_outer_end(env, c->d_ctl, ns, c->cfg.max_outer, c->h_count, c->h_ctl_out);
+  launch_outer_end(env, c->d_ctl, ns, c->cfg.max_outer, c->h_count, c->h_ctl_out, c->d_serial);
 }
 
 int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, bool sweep_outside,
@@ -1246,14 +1268,19 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
     // the new temperature goes to the state after every launched chain,
     // ahead of the synchronisation (a later chain copies it again), so a
     // converged step needs no launch after it
+    // every iteration graph ends with the end kernel, which publishes its
+    // serial number: the host waits for the serial of the last one launched
+    int expect = *(c->h_count + 2);
     if (hipGraphLaunch(ge->first, gs) != hipSuccess) return TR_EHIP;
     for (int q = 1; q < L; ++q, ++launched) {
       part = one && q == L - 1;
       if (hipGraphLaunch(part ? ge->next1 : ge->next, gs) != hipSuccess) return TR_EHIP;
     }
+    expect += L;
     launch_copy(env, c->Tstar, s->T, c->n_cell);
     for (;;) {
-      if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
+      const int rc = wait_iteration(c, expect);
+      if (rc) return rc;
       if (*hc_active == 0) {
         done = true;
         break;
@@ -1261,6 +1288,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       if (part && *hc_mid > 0) {
         part = false;
         if (hipGraphLaunch(ge->tail, gs) != hipSuccess) return TR_EHIP;
+        ++expect;
         launch_copy(env, c->Tstar, s->T, c->n_cell);
         continue;
       }
@@ -1268,6 +1296,7 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       part = false;
       ++launched;
       if (hipGraphLaunch(ge->next, gs) != hipSuccess) return TR_EHIP;
+      ++expect;
       launch_copy(env, c->Tstar, s->T, c->n_cell);
     }
   } else {

@@ -120,9 +120,11 @@ void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga);
 // End of a transport iteration (start of s + 1 where the inner iteration is
-// done) and the count of slabs still active into *out (one launch); with no
-// slab left active the control records are copied to hout.
-void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout);
+// done) and the count of slabs still active into out[0] (out[1]: slabs in
+// the middle of an inner iteration), one launch; with no slab left active
+// the control records are copied to hout.  Then *serial (device) is
+// incremented and written to out[2], after the other host writes.
+void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout, int *serial);
 // Step-start copies of T, Egrey, E, F into the step's reference arrays, and
 // of the nslab control records from (coherent pinned) host memory ctl_in.
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,

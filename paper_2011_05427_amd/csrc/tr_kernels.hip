@@ -1627,7 +1627,8 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
 // middle of an inner iteration, ncyc > 0); when no slab is active the
 // control records are also copied to hout (host memory).  One block of 256
 // threads; slabs s = t, t + 256, ...; the count is summed exactly.
-__global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout) {
+__global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout,
+                                                   int *serial) {
   __shared__ int part[4], partm[4];
   int n = 0, nm = 0;
   for (int s = threadIdx.x; s < nslab; s += blockDim.x) {
@@ -1658,12 +1659,20 @@ __global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_
   __syncthreads();
   const int total = (part[0] + part[1]) + (part[2] + part[3]);
   // once every slab has stopped, the final control records go straight to
-  // the host copy (read there after the stream synchronisation)
+  // the host copy
   if (total == 0)
     for (int s = threadIdx.x; s < nslab; s += blockDim.x) hout[s] = ctl[s];
+  __threadfence_system();
+  __syncthreads();
   if (threadIdx.x == 0) {
     out[0] = total;
     out[1] = (partm[0] + partm[1]) + (partm[2] + partm[3]);
+    // the iteration's serial number last: a host that sees it also sees the
+    // counts and records written above
+    const int ser = *serial + 1;
+    *serial = ser;
+    __threadfence_system();
+    out[2] = ser;
   }
 }
 
@@ -2008,8 +2017,8 @@ void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, 
                      lcyc, ga);
 }
 
-void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout) {
-  hipLaunchKernelGGL(k_outer_end, dim3(1), dim3(256), 0, env.stream, ctl, nslab, max_outer, out, hout);
+void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout, int *serial) {
+  hipLaunchKernelGGL(k_outer_end, dim3(1), dim3(256), 0, env.stream, ctl, nslab, max_outer, out, hout, serial);
 }
 
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
