@@ -1122,22 +1122,6 @@ int capture_iteration(tr_ctx *c, const tr_state *s, int Lmax, bool with_sweep, b
 
 extern "C" {
 
-int tr_run(tr_ctx *c, const tr_state *s, int nsteps, tr_stats *stats, int *done, hipStream_t st) {
-  if (done) *done = 0;
-  if (!c || !s || nsteps < 0) return TR_EINVAL;
-  tr_state w = *s;
-  for (int k = 0; k < nsteps; ++k) {
-    const int rc = tr_step(c, &w, nullptr, stats, st);
-    if (rc) return rc;
-    if (done) *done = k + 1;
-    // the two buffers exchange roles (both are the caller's writable arrays)
-    double *prev = const_cast<double *>(w.I_prev);
-    w.I_prev = w.I_out;
-    w.I_out = prev;
-  }
-  return TR_OK;
-}
-
 int tr_set_schedule(tr_ctx *c, int cycle, int lmax) {
   if (!c || cycle < 0 || cycle > 2 || lmax < 1 || lmax > TR_MAXOUT) return TR_EINVAL;
   c->cfg.cycle = cycle;
@@ -1152,7 +1136,12 @@ int tr_set_sweep_timing(tr_ctx *c, int on) {
   return TR_OK;
 }
 
-int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st) {
+}  // extern "C"
+
+namespace {
+
+int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st, bool order_in,
+              bool order_out) {
   if (!c || !s || !s->T || !s->I_prev || !s->I_out || s->I_prev == s->I_out || !s->E || !s->F || !s->Ebnd ||
       !s->f || !s->fbnd || !s->C || !s->Egrey)
     return TR_EINVAL;
@@ -1178,7 +1167,9 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   }
   // everything runs on the library stream, ordered after the caller's work
   hipStream_t gs = c->gs;
-  if (hipEventRecord(c->ev_in, st) != hipSuccess || hipStreamWaitEvent(gs, c->ev_in, 0) != hipSuccess) return TR_EHIP;
+  if (order_in &&
+      (hipEventRecord(c->ev_in, st) != hipSuccess || hipStreamWaitEvent(gs, c->ev_in, 0) != hipSuccess))
+    return TR_EHIP;
   // (coherent pinned memory, read by the step-start kernel; the previous
   // step has finished with the buffer)
   static_assert(sizeof(Ctl) % sizeof(int) == 0, "control records are copied as ints");
@@ -1337,7 +1328,8 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
       hipMemcpyAsync(seed_counts, c->d_seed_counts, sizeof(seed_counts), hipMemcpyDeviceToHost, gs) != hipSuccess)
     return TR_EHIP;
   if ((!done || c->mlp_params) && hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
-  if (hipEventRecord(c->ev_out, gs) != hipSuccess || hipStreamWaitEvent(st, c->ev_out, 0) != hipSuccess)
+  if (order_out &&
+      (hipEventRecord(c->ev_out, gs) != hipSuccess || hipStreamWaitEvent(st, c->ev_out, 0) != hipSuccess))
     return TR_EHIP;
   int err = TR_OK;
   c->last_iters = 0;
@@ -1367,4 +1359,33 @@ int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hi
   return err;
 }
 
+}  // namespace
+
+extern "C" {
+
+int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st) {
+  return step_impl(c, s, replay, stats, st, true, true);
+}
+
+int tr_run(tr_ctx *c, const tr_state *s, int nsteps, tr_stats *stats, int *done, hipStream_t st) {
+  if (done) *done = 0;
+  if (!c || !s || nsteps < 0) return TR_EINVAL;
+  tr_state w = *s;
+  for (int k = 0; k < nsteps; ++k) {
+    // between the steps of one call everything stays on the library stream:
+    // the caller's stream is waited for before the first and waits after the last
+    const bool last = k == nsteps - 1;
+    int rc = step_impl(c, &w, nullptr, stats, st, k == 0, last);
+    if (rc && !last && hipEventRecord(c->ev_out, c->gs) == hipSuccess) (void)hipStreamWaitEvent(st, c->ev_out, 0);
+    if (rc) return rc;
+    if (done) *done = k + 1;
+    // the two buffers exchange roles (both are the caller's writable arrays)
+    double *prev = const_cast<double *>(w.I_prev);
+    w.I_prev = w.I_out;
+    w.I_out = prev;
+  }
+  return TR_OK;
+}
+
 }  // extern "C"
+
