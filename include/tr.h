@@ -285,8 +285,9 @@ int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats,
  * state with I_prev and I_out exchanged k times, as a caller of tr_step
  * exchanges them after each step (so both buffers must be writable); after
  * the call the caller exchanges its two pointers once more when nsteps is
- * odd.  stats (host, nullable) as in
- * tr_step, accumulated over the steps.  The call stops at the first failing
+ * odd.  The library stream is ordered after `stream` before the first step
+ * and `stream` after the last (not between steps).  stats (host, nullable)
+ * as in tr_step, accumulated over the steps.  The call stops at the first failing
  * step and returns its error; *done (host, nullable) receives the number of
  * steps completed.  Errors: TR_EINVAL (nsteps < 0) and those of tr_step.
  */
