@@ -270,8 +270,9 @@ typedef struct tr_stats {
  * (0 terminates; a row starting with 0 leaves that slab free-running),
  * executed instead of the convergence tests.  stats (host,
  * nullable): [n_slab] counters accumulated over calls.  The step runs on
- * the library's stream after the work already queued on `stream`, and
- * `stream` waits for it; the call returns once the host has seen every slab
+ * `stream` after the work already queued there (its graphs are captured on a
+ * stream of the library's own and launched on `stream`); the call returns
+ * once the host has seen every slab
  * stop (the stats are final), while the last copy into st->T may still be
  * in flight: work queued on `stream` afterwards sees the results, the host
  * synchronises `stream` before reading device memory directly.
@@ -285,8 +286,7 @@ int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats,
  * state with I_prev and I_out exchanged k times, as a caller of tr_step
  * exchanges them after each step (so both buffers must be writable); after
  * the call the caller exchanges its two pointers once more when nsteps is
- * odd.  The library stream is ordered after `stream` before the first step
- * and `stream` after the last (not between steps).  stats (host, nullable)
+ * odd.  Every step runs on `stream`.  stats (host, nullable)
  * as in tr_step, accumulated over the steps.  The call stops at the first failing
  * step and returns its error; *done (host, nullable) receives the number of
  * steps completed.  Errors: TR_EINVAL (nsteps < 0) and those of tr_step.

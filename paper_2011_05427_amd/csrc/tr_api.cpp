@@ -95,8 +95,7 @@ struct tr_ctx {
     hipGraphExec_t next1 = nullptr, tail = nullptr;
   };
   std::vector<GraphEntry> graphs;
-  hipStream_t gs = nullptr;  // library stream for graph replay
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t gs = nullptr;  // library stream for graph capture (replays run on the caller's stream)
   // start / end events of the sweep launches of tr_step (one pair per
   // slab-size bucket): the sweep's kernel time is measured in every step
   hipEvent_t ev_sw[TR_NBUCKET][2] = {};
@@ -277,7 +276,7 @@ hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEv
 // has published its counts (h_count[2]), spinning on the coherent host word
 // instead of a stream synchronisation; after about a second without it the
 // stream is synchronised (that also reports a failed launch).
-int wait_iteration(tr_ctx *c, int expect) {
+int wait_iteration(tr_ctx *c, int expect, hipStream_t st) {
   volatile const int *ser = c->h_count + 2;
   for (long long k = 0; *ser != expect; ++k) {
     if ((k & 4095) == 4095) {
@@ -285,7 +284,7 @@ int wait_iteration(tr_ctx *c, int expect) {
       static thread_local std::chrono::steady_clock::time_point t0;
       if (k == 4095) t0 = std::chrono::steady_clock::now();
       if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit_s)
-        return hip_err(hipStreamSynchronize(c->gs));
+        return hip_err(hipStreamSynchronize(st));
     }
   }
   return TR_OK;
@@ -426,8 +425,6 @@ int tr_destroy(tr_ctx *c) {
     if (g.next1) (void)hipGraphExecDestroy(g.next1);
     if (g.tail) (void)hipGraphExecDestroy(g.tail);
   }
-  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
-  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   for (int b = 0; b < TR_NBUCKET; ++b)
     for (int q = 0; q < 2; ++q)
       if (c->ev_sw[b][q]) (void)hipEventDestroy(c->ev_sw[b][q]);
@@ -644,10 +641,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       hipHostMalloc((void **)&c->h_ctl_in, sizeof(Ctl) * n_slab, hipHostMallocCoherent) != hipSuccess)
     return fail(TR_ENOMEM);
   c->h_count[0] = c->h_count[1] = c->h_count[2] = 0;
-  if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
-    return fail(TR_EHIP);
+  if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess) return fail(TR_EHIP);
   for (int b = 0; b < TR_NBUCKET; ++b)
     for (int q = 0; q < 2; ++q)
       if (timing_event(&c->ev_sw[b][q]) != hipSuccess) return fail(TR_EHIP);
@@ -1140,8 +1134,7 @@ int tr_set_sweep_timing(tr_ctx *c, int on) {
 
 namespace {
 
-int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st, bool order_in,
-              bool order_out) {
+int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st) {
   if (!c || !s || !s->T || !s->I_prev || !s->I_out || s->I_prev == s->I_out || !s->E || !s->F || !s->Ebnd ||
       !s->f || !s->fbnd || !s->C || !s->Egrey)
     return TR_EINVAL;
@@ -1165,11 +1158,9 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
       k.n_replay = n;  // 0: this slab runs its own convergence tests
     }
   }
-  // everything runs on the library stream, ordered after the caller's work
-  hipStream_t gs = c->gs;
-  if (order_in &&
-      (hipEventRecord(c->ev_in, st) != hipSuccess || hipStreamWaitEvent(gs, c->ev_in, 0) != hipSuccess))
-    return TR_EHIP;
+  // everything runs on the caller's stream (graphs are captured on the
+  // library's own stream and replayed here), so no ordering between streams
+  hipStream_t gs = st;
   // (coherent pinned memory, read by the step-start kernel; the previous
   // step has finished with the buffer)
   static_assert(sizeof(Ctl) % sizeof(int) == 0, "control records are copied as ints");
@@ -1270,7 +1261,7 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
     expect += L;
     launch_copy(env, c->Tstar, s->T, c->n_cell);
     for (;;) {
-      const int rc = wait_iteration(c, expect);
+      const int rc = wait_iteration(c, expect, gs);
       if (rc) return rc;
       if (*hc_active == 0) {
         done = true;
@@ -1328,9 +1319,6 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
       hipMemcpyAsync(seed_counts, c->d_seed_counts, sizeof(seed_counts), hipMemcpyDeviceToHost, gs) != hipSuccess)
     return TR_EHIP;
   if ((!done || c->mlp_params) && hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
-  if (order_out &&
-      (hipEventRecord(c->ev_out, gs) != hipSuccess || hipStreamWaitEvent(st, c->ev_out, 0) != hipSuccess))
-    return TR_EHIP;
   int err = TR_OK;
   c->last_iters = 0;
   for (int q = 0; q < ns; ++q) {
@@ -1364,7 +1352,7 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
 extern "C" {
 
 int tr_step(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, hipStream_t st) {
-  return step_impl(c, s, replay, stats, st, true, true);
+  return step_impl(c, s, replay, stats, st);
 }
 
 int tr_run(tr_ctx *c, const tr_state *s, int nsteps, tr_stats *stats, int *done, hipStream_t st) {
@@ -1372,11 +1360,7 @@ int tr_run(tr_ctx *c, const tr_state *s, int nsteps, tr_stats *stats, int *done,
   if (!c || !s || nsteps < 0) return TR_EINVAL;
   tr_state w = *s;
   for (int k = 0; k < nsteps; ++k) {
-    // between the steps of one call everything stays on the library stream:
-    // the caller's stream is waited for before the first and waits after the last
-    const bool last = k == nsteps - 1;
-    int rc = step_impl(c, &w, nullptr, stats, st, k == 0, last);
-    if (rc && !last && hipEventRecord(c->ev_out, c->gs) == hipSuccess) (void)hipStreamWaitEvent(st, c->ev_out, 0);
+    const int rc = step_impl(c, &w, nullptr, stats, st);
     if (rc) return rc;
     if (done) *done = k + 1;
     // the two buffers exchange roles (both are the caller's writable arrays)
