@@ -1630,6 +1630,8 @@ __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, Pr
 __global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout,
                                                    int *serial) {
   __shared__ int part[4], partm[4];
+  // only this kernel writes the serial: read it now, with the records
+  const int ser0 = threadIdx.x == 0 ? *serial : 0;
   int n = 0, nm = 0;
   for (int s = threadIdx.x; s < nslab; s += blockDim.x) {
     Ctl &c = ctl[s];
@@ -1660,16 +1662,17 @@ __global__ __launch_bounds__(256) void k_outer_end(Ctl *ctl, int nslab, int max_
   const int total = (part[0] + part[1]) + (part[2] + part[3]);
   // once every slab has stopped, the final control records go straight to
   // the host copy
-  if (total == 0)
+  if (total == 0) {
     for (int s = threadIdx.x; s < nslab; s += blockDim.x) hout[s] = ctl[s];
-  __threadfence_system();
-  __syncthreads();
+    __threadfence_system();
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     out[0] = total;
     out[1] = (partm[0] + partm[1]) + (partm[2] + partm[3]);
     // the iteration's serial number last: a host that sees it also sees the
     // counts and records written above
-    const int ser = *serial + 1;
+    const int ser = ser0 + 1;
     *serial = ser;
     __threadfence_system();
     out[2] = ser;
