@@ -1282,9 +1282,15 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
       launch_copy(env, c->Tstar, s->T, c->n_cell);
     }
   } else {
+    // timed sweeps without per-group timing: the sweep of iteration s + 1 is
+    // queued behind iteration s before the host waits for it (it sweeps only
+    // the slabs still active then, as a launch after the wait would), so its
+    // start event is not recorded on an idle stream ahead of the kernel's
+    // submission; a launch that found no active slab is not counted
+    const bool ahead = sweep_ev && !c->cfg.timing;
     for (int outer = 0; outer <= c->cfg.max_outer + 1; ++outer) {
       // transport sweep of iteration s >= 1 (predicated per slab)
-      if (outer > 0 && sweep_ev)
+      if (outer > 0 && sweep_ev && !ahead)
         launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd, true);
       if (ge) {
         hipGraphExec_t gx = outer == 0 ? ge->first : ge->rest;
@@ -1292,8 +1298,11 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
       } else {
         enqueue_iteration(c, s, gs, Lmax, outer > 0, true);
       }
+      const bool next = ahead && outer < c->cfg.max_outer + 1;
+      if (next)
+        launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd, true);
       if (hipStreamSynchronize(gs) != hipSuccess) return TR_EHIP;
-      if (outer > 0 && sweep_ev) sweep_time(c, t_ms, n_launch);
+      if (ahead ? (next && *hc_active > 0) : (outer > 0 && sweep_ev)) sweep_time(c, t_ms, n_launch);
       if (c->cfg.timing) {
         // cycles run by slab 0 in the iteration just completed (exact for one slab)
         Ctl k0;
