@@ -311,8 +311,10 @@ int tr_set_schedule(tr_ctx *ctx, int cycle, int lmax);
  * Sweep kernel timing inside tr_step.  on = 1: the transport sweeps of
  * iterations s >= 1 are launched outside the replayed graphs, each launch
  * recording its own start and end on HIP events, and their kernel time is
- * added to tr_stats.t_ms[TR_T_SWEEP] (launches in n_launch[TR_T_SWEEP]);
- * this costs one extra launch per transport iteration.  on = 0 (default):
+ * added to tr_stats.t_ms[TR_T_SWEEP] (launches in n_launch[TR_T_SWEEP]).
+ * Each is queued behind the previous iteration before the host waits for
+ * it, so one more launch at the end of a step finds no slab active (it
+ * does nothing and is not counted).  on = 0 (default):
  * sweeps stay inside the graphs, untimed.  Errors: TR_EINVAL (on not 0/1).
  */
 int tr_set_sweep_timing(tr_ctx *ctx, int on);
