@@ -225,3 +225,34 @@ def test_timed_sweep_launches_equal_graph_replay():
         sv.close()
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.gpu
+def test_steps_on_a_side_stream_equal_the_default_stream():
+    """tr_step and tr_run run on the caller's stream (the library only
+    captures its graphs on a stream of its own): the same steps queued on a
+    side stream give bitwise the state they give on the default stream, with
+    the same counters."""
+    import torch
+
+    slab = inputs.make_slab(40, 32, 8, dt=0.004)
+    levels = [32, 4, 1]
+    cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_V, lmax=2)
+    note("V cycle, 1 tr_step + 3 steps of tr_run, default stream vs a side stream")
+    outs, counts = [], []
+    for side in (False, True):
+        sv = binding.Solver([slab], [levels], cfg)
+        st = sv.new_state()
+        sv.state_init(st, slab.T0)
+        torch.cuda.synchronize()
+        stream = torch.cuda.Stream() if side else torch.cuda.current_stream()
+        with torch.cuda.stream(stream):
+            a = sv.step(st)
+            b = sv.run(st, 3)
+        stream.synchronize()
+        counts.append((a[0].n_ti, a[0].n_c, b[0].n_ti, b[0].n_c))
+        outs.append({k: to_np(v).copy() for k, v in st.items()})
+        sv.close()
+    assert counts[0] == counts[1] and counts[0][2] > 0
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
