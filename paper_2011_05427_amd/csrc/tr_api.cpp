@@ -275,7 +275,8 @@ hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEv
 // Waits until the end kernel of the iteration with serial number `expect`
 // has published its counts (h_count[2]), spinning on the coherent host word
 // instead of a stream synchronisation; after about a second without it the
-// stream is synchronised (that also reports a failed launch).
+// stream is synchronised (that also reports a failed launch), and a serial
+// still missing after that is an error.
 int wait_iteration(tr_ctx *c, int expect, hipStream_t st) {
   volatile const int *ser = c->h_count + 2;
   for (long long k = 0; *ser != expect; ++k) {
@@ -283,8 +284,11 @@ int wait_iteration(tr_ctx *c, int expect, hipStream_t st) {
       static const double limit_s = 1.0;
       static thread_local std::chrono::steady_clock::time_point t0;
       if (k == 4095) t0 = std::chrono::steady_clock::now();
-      if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit_s)
-        return hip_err(hipStreamSynchronize(st));
+      if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit_s) {
+        const int rc = hip_err(hipStreamSynchronize(st));
+        if (rc) return rc;
+        return *ser == expect ? TR_OK : TR_EHIP;
+      }
     }
   }
   return TR_OK;
