@@ -256,3 +256,34 @@ def test_steps_on_a_side_stream_equal_the_default_stream():
     assert counts[0] == counts[1] and counts[0][2] > 0
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("cycle,levels", [
+    (inputs.CYCLE_V, [8, 1]),
+    (inputs.CYCLE_W, [8, 4, 1]),
+    (inputs.CYCLE_F, [8, 4, 2, 1]),
+])
+def test_steps_reach_the_single_grid_solution(cycle, levels):
+    """Paper Alg. 1 solves the multigroup LOQD equations and the energy
+    balance as one nonlinear system on the fine frequency grid (the oracle:
+    a global root find in T around the multigroup LO solve).  At tight
+    tolerances the multigrid steps on the GPU converge to the same solution,
+    for every cycle shape."""
+    slab = inputs.make_slab(6, 8, 4, dt=0.004, T0=0.01, C1=4.0, C2=1.0)
+    pb = mlqd.problem_from_slab(slab)
+    ref = mlqd.initial_state(pb, slab.T0)
+    for _ in range(2):
+        ref = mlqd.alg1_step(pb, ref, eps=1e-14)
+    cfg = inputs.SolverCfg(levels=levels, cycle=cycle, lmax=4, eps=1e-13, eps_inner=1e-14, max_outer=60)
+    note(f"cycle {cycle} levels {levels}: 2 GPU steps against 2 single-grid oracle steps")
+    sv = binding.Solver([slab], [levels], cfg)
+    st = sv.new_state()
+    sv.state_init(st, slab.T0)
+    for _ in range(2):
+        sv.step(st)
+    T = to_np(st["T"])
+    E = to_np(st["E"]).reshape(slab.ng, slab.nx)
+    np.testing.assert_allclose(T, ref.T, rtol=1e-10)
+    np.testing.assert_allclose(E, ref.E, rtol=1e-9, atol=1e-12 * ref.E.max())
+    sv.close()
