@@ -1173,8 +1173,7 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
   // step start: control records, old-time copies, convergence references,
   // Phi with the current incoming
   launch_step_start(env, s->T, s->Egrey, s->E, s->F, c->n_cell, c->n_gi, c->n_ge, c->Told, c->Ts, c->Tcyc, c->Tstar,
-                    c->Es, c->Ecyc, c->Eold, c->Fold, c->h_ctl_in, c->d_ctl, ns);
-  launch_phi(env, c->t_g, s->C, c->Phi);
+                    c->Es, c->Ecyc, c->Eold, c->Fold, c->h_ctl_in, c->d_ctl, ns, c->t_g, s->C, c->Phi);
   launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
   unsigned long long seed_counts[2] = {0, 0};
   if (c->mlp_params) {

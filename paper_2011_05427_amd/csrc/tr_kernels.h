@@ -77,7 +77,6 @@ void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool
                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
                     const double *bnd, double *f, double *fbnd, double *C, double *Phi);
-void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi);
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
                const LoIn &in, const LoSol &sol);
 // Restriction work: coarse groups of r <= 16 finer groups are done in one pass;
@@ -125,12 +124,14 @@ void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, 
 // the control records are copied to hout.  Then *serial (device) is
 // incremented and written to out[2], after the other host writes.
 void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout, int *serial);
-// Step-start copies of T, Egrey, E, F into the step's reference arrays, and
-// of the nslab control records from (coherent pinned) host memory ctl_in.
+// Step-start copies of T, Egrey, E, F into the step's reference arrays, of
+// the nslab control records from (coherent pinned) host memory ctl_in, and
+// Phi from C and the incoming intensities (tab_g items = (slab, first of 256
+// groups)), in one launch.
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
                        double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
-                       Ctl *ctl, int nslab);
+                       Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi);
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n);
 void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
 void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,

@@ -604,10 +604,8 @@ __global__ __launch_bounds__(256) void k_moments(const SlabDev *__restrict__ sd,
 }
 
 // Phi = F_in - c C E_in from given C and the current incoming (step start).
-__global__ __launch_bounds__(256) void k_phi(const SlabDev *__restrict__ sd, ProbDev pd,
-                                             const Item *__restrict__ tab, const double *__restrict__ C,
-                                             double *__restrict__ Phi) {
-  const Item it = tab[blockIdx.x];
+__device__ inline void phi_groups(const SlabDev *__restrict__ sd, const ProbDev &pd, const Item it,
+                                  const double *__restrict__ C, double *__restrict__ Phi) {
   const SlabDev &S = sd[it.slab];
   const int g = it.idx + threadIdx.x;
   if (g >= S.ng) return;
@@ -1688,9 +1686,20 @@ struct StepCopies {
   const int *ctl_in;  // control records in coherent pinned host memory (n_ctl words)
   int *ctl;
   long long n_ctl;
+  // blocks from copy_blocks on: Phi of 256 groups per work item of tab_g
+  unsigned copy_blocks;
+  const SlabDev *sd;
+  ProbDev pd;
+  const Item *tab_g;
+  const double *C;
+  double *Phi;
 };
 
 __global__ __launch_bounds__(256) void k_step_start(StepCopies a) {
+  if (blockIdx.x >= a.copy_blocks) {
+    phi_groups(a.sd, a.pd, a.tab_g[blockIdx.x - a.copy_blocks], a.C, a.Phi);
+    return;
+  }
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.n_cell) {
     const double t = a.T[i], e = a.Egrey[i];
@@ -1958,10 +1967,6 @@ void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int 
                      bnd, f, fbnd, C, Phi);
 }
 
-void launch_phi(const LaunchEnv &env, const Table &tab, const double *C, double *Phi) {
-  if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_phi, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, C, Phi);
-}
 
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
                const LoIn &in, const LoSol &sol) {
@@ -2027,13 +2032,17 @@ void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, 
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
                        double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
-                       Ctl *ctl, int nslab) {
+                       Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi) {
   const long long n_ctl = (long long)nslab * (long long)(sizeof(Ctl) / sizeof(int));
-  const StepCopies a{T,  Egrey, E,  F,    Told,  Ts,   Tcyc,  Tstar, Es, Ecyc, Eold, Fold, n_cell, n_gi, n_ge,
-                     reinterpret_cast<const int *>(ctl_in), reinterpret_cast<int *>(ctl), n_ctl};
   const long long n = std::max(std::max(n_cell, n_ctl), std::max(n_gi, n_ge));
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_step_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, a);
+  const unsigned copy_blocks = (unsigned)((n + 255) / 256);
+  const StepCopies a{T,      Egrey, E,      F,      Told,        Ts,
+                     Tcyc,   Tstar, Es,     Ecyc,   Eold,        Fold,
+                     n_cell, n_gi,  n_ge,   reinterpret_cast<const int *>(ctl_in), reinterpret_cast<int *>(ctl), n_ctl,
+                     copy_blocks, env.sd, env.pd, tab_g.d, C,  Phi};
+  const unsigned nb = copy_blocks + (unsigned)tab_g.n;
+  if (nb == 0) return;
+  hipLaunchKernelGGL(k_step_start, dim3(nb), dim3(256), 0, env.stream, a);
 }
 
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n) {
