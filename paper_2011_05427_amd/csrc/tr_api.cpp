@@ -1171,10 +1171,10 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
   std::memcpy(c->h_ctl_in, hc.data(), sizeof(Ctl) * ns);
   LaunchEnv env = env_of(c, gs);
   // step start: control records, old-time copies, convergence references,
-  // Phi with the current incoming
+  // Phi with the current incoming, the opacity tables at T
   launch_step_start(env, s->T, s->Egrey, s->E, s->F, c->n_cell, c->n_gi, c->n_ge, c->Told, c->Ts, c->Tcyc, c->Tstar,
-                    c->Es, c->Ecyc, c->Eold, c->Fold, c->h_ctl_in, c->d_ctl, ns, c->t_g, s->C, c->Phi);
-  launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, c->Tstar, c->kappa, c->B, c->dSpart);
+                    c->Es, c->Ecyc, c->Eold, c->Fold, c->h_ctl_in, c->d_ctl, ns, c->t_g, s->C, c->Phi, c->t_opac,
+                    c->opac_run, c->kappa, c->B, c->dSpart);
   unsigned long long seed_counts[2] = {0, 0};
   if (c->mlp_params) {
     // learned closure: predicted cell factors replace the previous step's

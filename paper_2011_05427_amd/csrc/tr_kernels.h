@@ -125,13 +125,15 @@ void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, 
 // incremented and written to out[2], after the other host writes.
 void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, int *out, Ctl *hout, int *serial);
 // Step-start copies of T, Egrey, E, F into the step's reference arrays, of
-// the nslab control records from (coherent pinned) host memory ctl_in, and
-// Phi from C and the incoming intensities (tab_g items = (slab, first of 256
-// groups)), in one launch.
+// the nslab control records from (coherent pinned) host memory ctl_in, Phi
+// from C and the incoming intensities (tab_g items = (slab, first of 256
+// groups)), and the opacity tables kappa, B, dSpart at T (tab_op and run as
+// for launch_opacity, every slab), in one launch.
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
                        double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
-                       Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi);
+                       Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi, const Table &tab_op,
+                       int run, double *kappa, double *B, double *dSpart);
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n);
 void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
 void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,

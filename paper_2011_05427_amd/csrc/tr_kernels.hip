@@ -71,14 +71,13 @@ __device__ inline double planck_group(double nu, const EdgeQ &lo, const EdgeQ &h
 // tables; RUN = 1 gives the shortest dependent chain per thread for small
 // ones.  The 64 / RUN run sums of a cell are added in LDS in a fixed order.
 // ---------------------------------------------------------------------------
+// One block (256 threads) of the opacity work: work item `it`.
 template <int RUN>
-__global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd, ProbDev pd,
-                                                 const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
-                                                 const double *__restrict__ T, double *__restrict__ kappa,
-                                                 double *__restrict__ B, double *__restrict__ dSpart) {
+__device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbDev &pd, const Item it, const Ctl *ctl,
+                                     int pmode, int lcyc, const double *__restrict__ T, double *__restrict__ kappa,
+                                     double *__restrict__ B, double *__restrict__ dSpart) {
   constexpr int CB = 4 * RUN, NR = 64 / RUN;  // cells per block, runs per chunk
   __shared__ double part[NR][CB + 1];
-  const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   const int nx = S.nx, ng = S.ng;
@@ -126,6 +125,14 @@ __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd,
     for (int r = 0; r < 8; ++r) acc += part[r][cl];
     dSpart[S.o_chunk + (long long)chunk * nx + i] = acc;
   }
+}
+
+template <int RUN>
+__global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                 const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
+                                                 const double *__restrict__ T, double *__restrict__ kappa,
+                                                 double *__restrict__ B, double *__restrict__ dSpart) {
+  opacity_block<RUN>(sd, pd, tab[blockIdx.x], ctl, pmode, lcyc, T, kappa, B, dSpart);
 }
 
 // Sums the 64-group chunk partials of dS for every cell.  Block = 64 cells
@@ -1686,16 +1693,25 @@ struct StepCopies {
   const int *ctl_in;  // control records in coherent pinned host memory (n_ctl words)
   int *ctl;
   long long n_ctl;
-  // blocks from copy_blocks on: Phi of 256 groups per work item of tab_g
-  unsigned copy_blocks;
+  // blocks from copy_blocks on: Phi of 256 groups per work item of tab_g;
+  // from phi_end on: the opacity tables at T, one work item of tab_op each
+  unsigned copy_blocks, phi_end;
   const SlabDev *sd;
   ProbDev pd;
   const Item *tab_g;
   const double *C;
   double *Phi;
+  const Item *tab_op;
+  double *kappa, *B, *dSpart;
 };
 
+template <int RUN>
 __global__ __launch_bounds__(256) void k_step_start(StepCopies a) {
+  if (blockIdx.x >= a.phi_end) {
+    opacity_block<RUN>(a.sd, a.pd, a.tab_op[blockIdx.x - a.phi_end], nullptr, PRED_ALL, 0, a.T, a.kappa, a.B,
+                       a.dSpart);
+    return;
+  }
   if (blockIdx.x >= a.copy_blocks) {
     phi_groups(a.sd, a.pd, a.tab_g[blockIdx.x - a.copy_blocks], a.C, a.Phi);
     return;
@@ -2032,17 +2048,21 @@ void launch_outer_end(const LaunchEnv &env, Ctl *ctl, int nslab, int max_outer, 
 void launch_step_start(const LaunchEnv &env, const double *T, const double *Egrey, const double *E, const double *F,
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
                        double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
-                       Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi) {
+                       Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi, const Table &tab_op,
+                       int run, double *kappa, double *B, double *dSpart) {
   const long long n_ctl = (long long)nslab * (long long)(sizeof(Ctl) / sizeof(int));
   const long long n = std::max(std::max(n_cell, n_ctl), std::max(n_gi, n_ge));
-  const unsigned copy_blocks = (unsigned)((n + 255) / 256);
-  const StepCopies a{T,      Egrey, E,      F,      Told,        Ts,
-                     Tcyc,   Tstar, Es,     Ecyc,   Eold,        Fold,
-                     n_cell, n_gi,  n_ge,   reinterpret_cast<const int *>(ctl_in), reinterpret_cast<int *>(ctl), n_ctl,
-                     copy_blocks, env.sd, env.pd, tab_g.d, C,  Phi};
-  const unsigned nb = copy_blocks + (unsigned)tab_g.n;
+  const unsigned copy_blocks = (unsigned)((n + 255) / 256), phi_end = copy_blocks + (unsigned)tab_g.n;
+  const StepCopies a{T,       Egrey,  E,       F,      Told,        Ts,
+                     Tcyc,    Tstar,  Es,      Ecyc,   Eold,        Fold,
+                     n_cell,  n_gi,   n_ge,    reinterpret_cast<const int *>(ctl_in), reinterpret_cast<int *>(ctl), n_ctl,
+                     copy_blocks, phi_end, env.sd, env.pd, tab_g.d, C, Phi, tab_op.d, kappa, B, dSpart};
+  const unsigned nb = phi_end + (unsigned)tab_op.n;
   if (nb == 0) return;
-  hipLaunchKernelGGL(k_step_start, dim3(nb), dim3(256), 0, env.stream, a);
+  if (run == 1)
+    hipLaunchKernelGGL(k_step_start<1>, dim3(nb), dim3(256), 0, env.stream, a);
+  else
+    hipLaunchKernelGGL(k_step_start<4>, dim3(nb), dim3(256), 0, env.stream, a);
 }
 
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n) {
