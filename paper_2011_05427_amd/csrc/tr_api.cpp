@@ -813,7 +813,8 @@ int tr_restrict(tr_ctx *c, int from, int to, const tr_lo_coeffs *in, const tr_lo
   int rc = build_restrict_tables(c, from, to);
   if (rc) return rc;
   LoSol s{sol->E, sol->F, sol->Ebnd};
-  LoOut o{out->sigE, out->emis, out->a, out->b, out->sigR, out->C, out->Phi, out->Eold, out->Fold, out->Esum};
+  LoOut o{out->sigE, out->emis, out->a, out->b, out->sigR, out->C, out->Phi, out->Eold, out->Fold, out->Esum,
+          nullptr, nullptr};
   launch_restrict(env_of(c, st), c->t_red[std::make_pair(from, to)], nullptr, PRED_ALL, 0, from, to, coeffs_in(in), s,
                   o, c->red, true);
   return hip_err(hipGetLastError());
