@@ -1380,7 +1380,9 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
     if (e < ne) {
       const long long stride = (long long)ne * NF;
       const double *rec = red + S.o_red + ((long long)p * cpb * ne + e) * NF + k + u * stride;
-#pragma unroll 4
+      // unrolled so that a part's records (16 at 64 records and 4 parts) are
+      // all loaded before the first add; the adds keep their order
+#pragma unroll 16
       for (int q = u; q < cpb; q += U, rec += U * stride) acc += *rec;
     }
     sums[u * NP + pr] = acc;
