@@ -128,7 +128,7 @@ def _cpu_baseline_child(workload, budget_s, lmax=None):
             st = mlqd.initial_state(pb, slab.T0)
             stats = mlqd.Stats()
             lv = inputs.levels_for(slab, cfg)
-            sched = inputs.SolverCfg(levels=lv, cycle=cfg.cycle).schedule()
+            sched = mlqd.schedule(len(lv), cfg.cycle)
             mlqd.step(pb, lv, sched, cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
             cu += slab.cell_updates_per_sweep() * stats.n_ti
             k += 1
@@ -156,7 +156,7 @@ def _cpu_baseline_child(workload, budget_s, lmax=None):
     t0 = time.perf_counter()
     nsteps = 0
     while True:
-        st = mlqd.step(pb, cfg.levels, cfg.schedule(), cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
+        st = mlqd.step(pb, cfg.levels, mlqd.schedule(len(cfg.levels), cfg.cycle), cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
         nsteps += 1
         if time.perf_counter() - t0 > budget_s * 0.5:
             break

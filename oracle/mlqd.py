@@ -156,6 +156,23 @@ def initial_state(pb: Problem, T0: float, M: Optional[int] = None) -> State:
                  Egrey=E.sum(axis=0), j=0)
 
 
+CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
+
+
+def schedule(n_levels: int, cycle: int) -> List[int]:
+    """Grids (0-based indices into the hierarchy, fine = 0, grey = n_levels - 1)
+    visited after each grey solve in one cycle (paper Sec. 4, Fig. 1): the
+    V cycle (Alg. 2) visits none; the W cycle (three grids) the middle one; the
+    F cycle every intermediate grid, from the coarsest non-grey one up to the
+    second finest (Fig. 1 draws Gamma = 4, S = (3, 2); the low-order solve
+    counts of Tables 1-2 fix S = (Gamma - 1, ..., 2) for the larger Gamma)."""
+    if cycle == CYCLE_V or n_levels <= 2:
+        return []
+    if cycle == CYCLE_W:
+        return [1]
+    return list(range(n_levels - 2, 0, -1))
+
+
 def _norm(x):
     return float(np.max(np.abs(x)))
 

@@ -86,19 +86,6 @@ class SolverCfg:
     secant: bool = True  # diagonal secant Frechet derivative of grey sigma_E
     precision: int = 0  # 0: binary64 intensities; 1: binary32 storage of the corner intensities
 
-    def schedule(self) -> List[int]:
-        """Grid indices (0-based into ``levels``) visited after each grey solve.
-
-        V: none.  W (3 grids): the middle grid.  F: every intermediate grid from
-        the coarsest non-grey one up to the second finest (paper Fig. 1).
-        """
-        n = len(self.levels)
-        if self.cycle == CYCLE_V or n <= 2:
-            return []
-        if self.cycle == CYCLE_W:
-            return [1]
-        return list(range(n - 2, 0, -1))
-
 
 def gauss_legendre(n: int):
     mu, w = np.polynomial.legendre.leggauss(n)

@@ -36,7 +36,7 @@ def test_fc_first_step_heats_from_the_left():
     pb = mlqd.problem_from_slab(s)
     st = mlqd.initial_state(pb, s.T0)
     stats = mlqd.Stats()
-    new = mlqd.step(pb, cfg.levels, cfg.schedule(), cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
+    new = mlqd.step(pb, cfg.levels, mlqd.schedule(len(cfg.levels), cfg.cycle), cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
     # radiation enters at x = 0: temperature falls off monotonically into the slab
     assert np.all(np.diff(new.T) < 0) and new.T[0] > 0.05 and new.T.min() >= s.T0
     assert all(1 <= c <= cfg.lmax for c in stats.counts[0])

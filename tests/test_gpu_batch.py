@@ -93,7 +93,7 @@ def test_batch_sampled_slabs_match_oracle():
         pb = mlqd.problem_from_slab(slabs[k])
         st0 = mlqd.initial_state(pb, 0.001)
         stats = mlqd.Stats()
-        sched = inputs.SolverCfg(levels=levels[k], cycle=cfg.cycle).schedule()
+        sched = mlqd.schedule(len(levels[k]), cfg.cycle)
         refs[k] = (mlqd.step(pb, levels[k], sched, cfg.lmax, cfg.eps, cfg.eps_inner, st0, stats=stats),
                    stats.counts[0])
     note(f"batch of 20, replay on slabs {small}")

@@ -29,7 +29,7 @@ def test_fc_steps_replay_the_oracle(row):
     sv.state_init(st, s.T0)
     for j in range(2):
         stats = mlqd.Stats()
-        ost = mlqd.step(pb, levels, cfg.schedule(), lmax, cfg.eps, cfg.eps_inner, ost, stats=stats)
+        ost = mlqd.step(pb, levels, mlqd.schedule(len(levels), cfg.cycle), lmax, cfg.eps, cfg.eps_inner, ost, stats=stats)
         gs = sv.step(st, replay=[stats.counts[0]])
         assert gs[0].n_lo == stats.n_lo
         _compare_state(f"FC row {row} step {j}", sv, st, ost)
@@ -49,7 +49,7 @@ def test_fc_free_running_counts_match_the_oracle():
     sv.state_init(st, s.T0)
     acc = (binding.TrStats * 1)()
     for _ in range(3):
-        ost = mlqd.step(pb, levels, cfg.schedule(), lmax, cfg.eps, cfg.eps_inner, ost, stats=stats)
+        ost = mlqd.step(pb, levels, mlqd.schedule(len(levels), cfg.cycle), lmax, cfg.eps, cfg.eps_inner, ost, stats=stats)
         sv.step(st, stats=acc)
     assert (acc[0].n_ti, acc[0].n_c, acc[0].n_lo) == (stats.n_ti, stats.n_c, stats.n_lo)
     assert rel_err(to_np(st["T"]), ost.T) < 1e-10

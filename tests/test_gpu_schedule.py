@@ -23,7 +23,7 @@ V, W, F = inputs.CYCLE_V, inputs.CYCLE_W, inputs.CYCLE_F
 
 
 def _sched(levels, cycle):
-    return inputs.SolverCfg(levels=levels, cycle=cycle).schedule()
+    return mlqd.schedule(len(levels), cycle)
 
 
 def test_schedule_changes_replay_the_oracle():

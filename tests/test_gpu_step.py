@@ -30,8 +30,7 @@ def _oracle_run(slab, cfg, levels, nsteps):
 
 
 def _sched(cfg, levels):
-    c = inputs.SolverCfg(levels=levels, cycle=cfg.cycle)
-    return c.schedule()
+    return mlqd.schedule(len(levels), cfg.cycle)
 
 
 def _compare_state(tag, sv, st, ref, slab_idx=0):

@@ -157,3 +157,44 @@ def test_grey_newton_conserves_energy():
     dT = gr.T - Tstar
     meb = cv * (gr.T - Told) / dt - (C * grey.sigE[0] * E + C * D * Estar * dT - S - dS * dT)
     assert np.max(np.abs(meb)) < 1e-12 * np.max(cv * np.abs(gr.T) / dt)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_steady_source_free_slab_matches_closed_form(seed):
+    """Steady state (1/dt = 0), no absorption or emission, QD factors that vary
+    from cell to cell and opacities that vary from cell to cell on a
+    non-uniform mesh.  The continuous equations then give a constant flux F and
+    c d(f E)/dx = -sigma F, so f E at a cell centre x_i is f_{1/2} E_{1/2} -
+    (F/c) tau(x_i) with tau the optical depth from x = 0, and the two boundary
+    conditions fix E_{1/2} and F.  The discrete first moment integrated
+    between neighbouring cell centres with the dx-weighted edge opacity, and
+    over the boundary half cells, reproduces this solution exactly at every
+    cell centre and boundary; an edge length of dx_i, the arithmetic mean of
+    the two opacities, or the QD factors attached to the wrong side of an
+    edge do not."""
+    from oracle.moments import Factors
+
+    rng = np.random.default_rng(seed)
+    nx = 9
+    dx = rng.uniform(0.05, 0.5, nx)
+    sig = 10 ** rng.uniform(-1, 1, nx)
+    f = rng.uniform(0.25, 0.6, nx)
+    fb = rng.uniform(0.3, 0.6, 2)
+    Cm, Cp, Phim, Phip = -0.45, 0.55, 2.0, -0.3
+    fac = Factors(f=f[None], f_bnd=fb[None], C=np.array([[Cm, Cp]]), Phi=np.array([[Phim, Phip]]))
+    lv = lo.fine_level(sig[None], np.zeros((1, nx)), fac, np.zeros((1, nx)), np.zeros((1, nx + 1)), dx)
+    lv = dataclasses.replace(lv, sigE=np.zeros((1, nx)), emis=np.zeros((1, nx)))
+    sol = lo.solve_level(lv, dx, C, np.inf)
+
+    tau_edge = np.concatenate([[0.0], np.cumsum(sig * dx)])
+    tau_centre = tau_edge[:-1] + sig * dx / 2
+    tauX = tau_edge[-1]
+    # unknowns (E_{1/2}, F): F - c C^- E_{1/2} = Phi^-,
+    # F - c C^+ E_{nx+1/2} = Phi^+ with f_{nx+1/2} E_{nx+1/2} = f_{1/2} E_{1/2} - F tau_X / c
+    A = np.array([[-C * Cm, 1.0], [-C * Cp * fb[0] / fb[1], 1.0 + Cp * tauX / fb[1]]])
+    E0, F = np.linalg.solve(A, [Phim, Phip])
+    E_centre = (fb[0] * E0 - F * tau_centre / C) / f
+    EX = (fb[0] * E0 - F * tauX / C) / fb[1]
+    np.testing.assert_allclose(sol.E[0], E_centre, rtol=1e-12)
+    np.testing.assert_allclose(sol.Ebnd[0], [E0, EX], rtol=1e-12)
+    np.testing.assert_allclose(sol.F[0], np.full(nx + 1, F), rtol=1e-11)

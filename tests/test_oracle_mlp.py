@@ -102,3 +102,20 @@ def test_features_temperature_change_column():
     np.testing.assert_array_equal(F[:, :, 5], fp)
     F0 = mlp.features(T, np.array([0.1, 1.0, 10.0]), kap, np.full(nx, 0.5), 1.0, fp).reshape(G, nx, mlp.NIN)
     assert np.all(F0[:, :, 6] == 0.0)
+
+
+def test_adam_bias_correction_gives_scaled_sign_steps():
+    """With the bias-corrected moments, a constant gradient g moves every
+    parameter by -lr g / (|g| + eps) at every step, the first one included
+    (m_hat = g, v_hat = g^2 exactly); without the correction the first step
+    would be sqrt(1 - beta2) / (1 - beta1) = 0.316 times that."""
+    rng = np.random.default_rng(12)
+    n = 64
+    theta0 = rng.normal(0, 1, n)
+    g = rng.normal(0, 1, n) * 10.0 ** rng.integers(-6, 3, n)
+    lr, eps = 1e-3, 1e-8
+    theta, m, v = theta0.copy(), np.zeros(n), np.zeros(n)
+    for t in range(1, 4):
+        prev = theta
+        theta, m, v = mlp.adam_step(theta, m, v, g, t, lr=lr, eps=eps)
+        np.testing.assert_allclose(theta - prev, -lr * g / (np.abs(g) + eps), rtol=1e-9, atol=1e-18)

@@ -117,8 +117,7 @@ def test_multigrid_matches_single_grid(cycle, levels, sched):
 
 
 def _per_cycle_cost(levels, cycle):
-    cfg = inputs.SolverCfg(levels=levels, cycle={"V": 0, "W": 1, "F": 2}[cycle])
-    return levels[0] + 1 + sum(levels[g] + 1 for g in cfg.schedule())
+    return levels[0] + 1 + sum(levels[g] + 1 for g in mlqd.schedule(len(levels), {"V": 0, "W": 1, "F": 2}[cycle]))
 
 
 def test_paper_table_arithmetic():
@@ -138,7 +137,7 @@ def test_oracle_counters_follow_cycle_law():
     slab, pb = tiny_problem(nx=8, ng=16, nmu=4, dt=0.004)
     for levels, cyc, lmax in (([16, 1], "V", 3), ([16, 4, 1], "W", 2), ([16, 8, 4, 1], "F", 1)):
         cfg = inputs.SolverCfg(levels=levels, cycle={"V": 0, "W": 1, "F": 2}[cyc], lmax=lmax)
-        st, stats = mlqd.run(pb, slab.T0, levels, cfg.schedule(), lmax, 1e-10, 1e-11, 2)
+        st, stats = mlqd.run(pb, slab.T0, levels, mlqd.schedule(len(levels), cfg.cycle), lmax, 1e-10, 1e-11, 2)
         assert stats.n_lo == stats.n_c * _per_cycle_cost(levels, cyc)
         if lmax == 1:
             assert stats.n_c == stats.n_ti + 2
@@ -162,3 +161,89 @@ def test_subnormal_boundary_factor_guard_converges():
     for _ in range(2):
         st = mlqd.step(pb, [64, 8, 1], [1], 2, 1e-10, 1e-11, st, stats=stats, max_outer=10)
     assert all(len(c) <= 4 for c in stats.counts)
+
+
+def test_secant_derivative_of_a_linear_opacity_is_its_slope():
+    """Eq. f-derivative-d: D_i = (sigma(T~[k]) - sigma(T~[k-1])) / (T~[k] - T~[k-1])
+    per cell.  For a grey opacity linear in T it is the slope exactly; it is 0
+    at the first grey stage of a step (no earlier stage), where the stage
+    temperature moved by 1e-8 relative or less, and where c D E* would exceed
+    half of c_v/dt + S' (the guard that keeps the Newton denominator
+    positive)."""
+    slab, pb = tiny_problem(nx=6, ng=4, nmu=4, dt=0.01)
+    rng = np.random.default_rng(8)
+    s0, k = rng.uniform(1, 5, 6), rng.uniform(1, 30, 6) * np.array([1, -1, 1, -1, 1, 1])
+    sigma = lambda T: s0 + k * T
+    T1 = rng.uniform(0.2, 0.4, 6)
+    T2 = T1 * rng.uniform(1.05, 1.3, 6)
+    Estar = np.full(6, 1e-6)
+    dS = np.full(6, 1.0)
+    D = mlqd._secant(T2, sigma(T2), (T1, sigma(T1)), Estar, dS, pb)
+    np.testing.assert_allclose(D, k, rtol=1e-10)
+    assert np.all(mlqd._secant(T2, sigma(T2), None, Estar, dS, pb) == 0.0)
+    T3 = T2 * 1.1
+    T3[2] = T2[2] * (1 + 5e-9)
+    D3 = mlqd._secant(T3, sigma(T3), (T2, sigma(T2)), Estar, dS, pb)
+    assert D3[2] == 0.0 and np.all(D3[[0, 1, 3, 4, 5]] != 0.0)
+    big = 0.75 * (pb.cv / pb.dt + dS) / (pb.c * np.abs(k))  # c |D| E* at 1.5 times the bound
+    Dg = mlqd._secant(T2, sigma(T2), (T1, sigma(T1)), big, dS, pb)
+    np.testing.assert_array_equal(Dg, np.where(k > 0, 0.0, D))
+    ok = 0.25 * (pb.cv / pb.dt + dS) / (pb.c * np.abs(k))  # c |D| E* at half the bound
+    np.testing.assert_array_equal(mlqd._secant(T2, sigma(T2), (T1, sigma(T1)), ok, dS, pb), D)
+
+
+def test_secant_derivative_makes_the_grey_newton_cycles_superlinear():
+    """Within one transport iteration (fixed QD factors) every V cycle ends
+    with a Newton update of the grey LOQD + MEB system.  Its only
+    approximation is the diagonal derivative of the grey sigma_E; with the
+    secant estimate taken between consecutive grey stages the temperature
+    change collapses superlinearly (cycle 3 moves T less than 1e-4 times what
+    cycle 2 did), while D = 0 leaves a linear rate (here about 0.02)."""
+    slab = inputs.make_slab(10, 16, 8, dt=0.01, T0=0.05)
+    pb = mlqd.problem_from_slab(slab)
+    st = mlqd.initial_state(pb, slab.T0)
+    rates = {}
+    for secant in (True, False):
+        stats = mlqd.Stats()
+        mlqd.step(pb, [16, 1], [], 40, 1e-14, 1e-15, st, stats=stats, replay=[4], secant=secant)
+        d = stats.dT_cycle
+        rates[secant] = d[2] / d[1]
+    assert rates[True] < 1e-4 < 1e-3 < rates[False], rates
+
+
+@pytest.mark.parametrize("levels,sched", [([1, 1], []), ([1, 1, 1], [1]), ([1, 1, 1, 1], [2, 1])])
+def test_secant_pairs_consecutive_grey_stages(monkeypatch, levels, sched):
+    """With a single frequency group the grey sigma_E of every stage is the
+    group opacity kappa(T) itself, so Eq. f-derivative-d can be evaluated
+    from the opacity law: the D handed to each grey Newton update must be
+    (kappa(T~[k]) - kappa(T~[k-1])) / (T~[k] - T~[k-1]) between the stage
+    temperatures of consecutive grey stages of the step (over cycles, grids
+    of the schedule and transport iterations alike), 0 at the step's first
+    stage."""
+    slab = inputs.make_slab(8, 1, 4, C1=1.0, C2=0.5, dt=0.1, T0=0.1)
+    pb = mlqd.problem_from_slab(slab)
+    st = mlqd.initial_state(pb, slab.T0)
+    calls = []
+    real = mlqd.grey_newton
+
+    def spy(grey, Tstar, Told, S, dS, Estar, D, *rest):
+        calls.append((np.array(Tstar), np.array(D), np.array(dS), np.array(Estar)))
+        return real(grey, Tstar, Told, S, dS, Estar, D, *rest)
+
+    monkeypatch.setattr(mlqd, "grey_newton", spy)
+    mlqd.step(pb, levels, sched, 40, 1e-14, 1e-15, st, replay=[2, 2])
+    assert len(calls) == 4 * (1 + len(sched))
+    assert np.all(calls[0][1] == 0.0)
+    kap = lambda T: planck.opacity(pb.nu_center, pb.C_cell, T)[0]
+    checked = 0
+    for (Tp, _, _, _), (T, D, dS, Estar) in zip(calls[:-1], calls[1:]):
+        dT = T - Tp
+        expect = (kap(T) - kap(Tp)) / np.where(dT != 0, dT, 1.0)
+        live = (np.abs(dT) > 1e-8 * np.abs(T)) & (pb.c * expect * Estar <= 0.5 * (pb.cv / pb.dt + dS))
+        # the grey opacity carries roundoff of a few ulps, which the secant
+        # divides by the stage change
+        tol = 1e-9 * np.abs(expect) + 1e-15 * kap(T) / np.where(dT != 0, np.abs(dT), 1.0)
+        assert np.all(np.abs(D - expect)[live] <= tol[live]), (D, expect)
+        assert np.all(D[~live] == 0.0)
+        checked += np.count_nonzero(live)
+    assert checked >= 24

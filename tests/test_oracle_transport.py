@@ -132,3 +132,36 @@ def test_boundary_condition_identity():
         F_edge = psi @ (w * mu)
         np.testing.assert_allclose(F_edge, C * fac.C[:, side] * E_edge + fac.Phi[:, side], rtol=1e-13)
         np.testing.assert_allclose(fac.f_bnd[:, side], psi @ (w * mu * mu) / (psi @ w), rtol=1e-14)
+
+
+def test_cell_factor_converges_at_second_order_to_exact_eddington_factor():
+    """Pure absorber lit from the left by unit isotropic radiation: the exact
+    intensity is exp(-sigma x / mu) for mu > 0 and 0 for mu < 0, so the exact
+    Eddington factor at x is sum_{mu>0} w mu^2 e^(-sigma x/mu) / sum_{mu>0} w
+    e^(-sigma x/mu), and the outgoing boundary factor at X is the same ratio
+    with mu instead of mu^2.  The discrete factors (cell average of the two
+    corner values) converge to them at second order under refinement; any
+    other corner weighting of the cell value converges only at first order."""
+    mu, w = inputs.gauss_legendre(8)
+    pos = mu > 0
+    sig, X = 2.0, 1.0
+
+    def errors(nx):
+        x = _uniform(nx, X)
+        xc = 0.5 * (x[:-1] + x[1:])
+        I = sweep(mu, x, np.full((1, nx), sig), np.zeros((1, nx)), np.zeros((1, 8, nx, 2)),
+                  np.ones(1), np.zeros(1), C, np.inf)
+        fac = moments.factors(mu, w, I, np.ones(1), np.zeros(1), C)
+        att = np.exp(-sig * xc[None, :] / mu[pos][:, None])
+        f_exact = (w[pos] * mu[pos] ** 2) @ att / (w[pos] @ att)
+        attX = np.exp(-sig * X / mu[pos])
+        C_exact = (w[pos] * mu[pos]) @ attX / (w[pos] @ attX)
+        fX_exact = (w[pos] * mu[pos] ** 2) @ attX / (w[pos] @ attX)
+        return (np.max(np.abs(fac.f[0] - f_exact)), abs(fac.C[0, 1] - C_exact),
+                abs(fac.f_bnd[0, 1] - fX_exact))
+
+    e80, e160 = errors(80), errors(160)
+    orders = [np.log2(a / b) for a, b in zip(e80, e160)]
+    assert e160[0] < 1e-4 and orders[0] > 1.8, (e160, orders)
+    assert e160[1] < 5e-5 and orders[1] > 1.8, (e160, orders)
+    assert e160[2] < 5e-5 and orders[2] > 1.8, (e160, orders)
