@@ -363,6 +363,24 @@ int tr_mlp_forward(const float *params, const float *X, long long n, float *out,
  * the loss (device float). */
 int tr_mlp_grad(const float *params, const float *X, const float *Y, long long n, float *grad, float *loss,
                 void *work, hipStream_t stream);
+/*
+ * tr_mlp_grad without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  It allocates nothing: its pass work lives in a
+ * file-scope device array of the library (10.4 MiB, held by every GPU the
+ * library runs on until the process ends), sized for at most
+ * TR_MLP_NOALLOC_MAX_N samples.  The array's address on the current device
+ * (the device of `stream`, which must be current) is looked up on the first
+ * call on that device.  Results equal tr_mlp_grad's bit for bit.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads) race and give wrong gradients; the caller orders them.
+ * No state carries over between calls (each writes every word it reads).
+ * Errors: TR_EINVAL (a null pointer, n < 1 or n > TR_MLP_NOALLOC_MAX_N),
+ * TR_EHIP.
+ */
+enum { TR_MLP_NOALLOC_MAX_N = 4096 };
+int tr_mlp_grad_noalloc(const float *params, const float *X, const float *Y, long long n, float *grad, float *loss,
+                        hipStream_t stream);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected, t >= 1). */
 int tr_mlp_adam(float *params, float *m, float *v, const float *grad, int t, float lr, hipStream_t stream);
 /* One epoch of minibatch Adam in the order given by perm [n] (device ints);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libtr.so")
 TR_OK, TR_EINVAL, TR_ENOMEM, TR_EHIP, TR_ENOCONV, TR_ENAN = 0, -1, -2, -3, -4, -5
 TR_K_CELL, TR_K_EDGE, TR_K_I, TR_K_GI, TR_K_GE, TR_K_G2, TR_K_G = 0, 1, 2, 3, 4, 5, 6
 TR_K_LEV_PI, TR_K_LEV_PE, TR_K_LEV_P2 = 8, 16, 24
+TR_MLP_NOALLOC_MAX_N = 4096  # samples per tr_mlp_grad_noalloc call (size of its device scratch)
 MAXOUT = 64
 
 _dp = C.POINTER(C.c_double)
@@ -69,7 +70,7 @@ T_OPACITY, T_SWEEP, T_MOMENTS, T_LO_FINE, T_RESTRICT, T_LO_COARSE, T_GREY = rang
 EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_incoming", "tr_opacity",
            "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step",
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
-           "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
+           "tr_mlp_grad_noalloc", "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
            "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing",
            "tr_prolong", "tr_set_schedule", "tr_run"]
 
@@ -117,6 +118,7 @@ def load():
     lib.tr_mlp_train_work_bytes.restype = C.c_size_t
     lib.tr_mlp_forward.argtypes = [vp, vp, C.c_longlong, vp, vp, vp]
     lib.tr_mlp_grad.argtypes = [vp, vp, vp, C.c_longlong, vp, vp, vp, vp]
+    lib.tr_mlp_grad_noalloc.argtypes = [vp, vp, vp, C.c_longlong, vp, vp, vp]
     lib.tr_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp]
     lib.tr_mlp_train_epoch.argtypes = [vp, vp, vp, _ip, C.c_float, vp, vp, C.c_longlong, vp, C.c_int, vp, vp, vp]
     lib.tr_mlp_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
@@ -382,6 +384,11 @@ class Mlp:
         _check(self.lib.tr_mlp_grad(_ptr(self.params), _ptr(X), _ptr(Y), n, _ptr(g), _ptr(loss),
                                     _ptr(self._work_for(n)), _stream()), "tr_mlp_grad")
         return g, loss
+
+    def grad_noalloc(self, X, Y, g, loss):
+        """tr_mlp_grad_noalloc into caller tensors g [nparam], loss [1]."""
+        _check(self.lib.tr_mlp_grad_noalloc(_ptr(self.params), _ptr(X), _ptr(Y), X.shape[0], _ptr(g), _ptr(loss),
+                                            _stream()), "tr_mlp_grad_noalloc")
 
     def adam(self, grad, lr):
         self.t.value += 1

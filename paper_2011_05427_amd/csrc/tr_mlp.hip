@@ -1,4 +1,4 @@
-// Learned closure network on MFMA (gfx950): 5 -> 128 -> 128 -> 128 -> 2, ReLU,
+// Learned closure network on MFMA (gfx950): 7 -> 128 -> 128 -> 128 -> 2, ReLU,
 // sigmoid on output 0.  Products run in bfloat16 with float32 accumulation on
 // v_mfma_f32_32x32x16_bf16; master weights, biases, gradients and the Adam
 // state are float32.
@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "tr.h"
@@ -448,9 +449,9 @@ struct Work {
   float *O, *dO, *dZf, *part, *gtmp, *cpart, *split;
 };
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-size_t work_bytes(long long n) {
+constexpr size_t work_bytes(long long n) {
   size_t b = 0;
   b += align256(n * NINP * 2);            // Xb
   b += align256((size_t)NPARAM * 2);       // Wb (bf16 copy of the parameter vector)
@@ -628,6 +629,33 @@ void backward(const float *params, const float *X, const float *Y, long long n, 
   colsum(w.dZf, (long long)NH, NH, (int)n, grad + OB1, w.cpart, st);
 }
 
+// Scratch of the allocation-free gradient entry point: the pass work of
+// TR_MLP_NOALLOC_MAX_N samples in one file-scope array.  Every GPU the library
+// runs on holds its own copy at its own address (found once per device with
+// hipGetSymbolAddress); host code passes that address, never the array's name.
+constexpr size_t kNoAllocBytes = work_bytes(TR_MLP_NOALLOC_MAX_N);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (resolved on the
+// first call per device).
+int scratch_address(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return TR_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return TR_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TR_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -649,6 +677,18 @@ int tr_mlp_forward(const float *params, const float *X, long long n, float *out,
 int tr_mlp_grad(const float *params, const float *X, const float *Y, long long n, float *grad, float *loss,
                 void *work, hipStream_t st) {
   if (!params || !X || !Y || !grad || !loss || !work || n <= 0) return TR_EINVAL;
+  const Work w = carve(work, n);
+  backward(params, X, Y, n, grad, loss, w, st);
+  return hipGetLastError() == hipSuccess ? TR_OK : TR_EHIP;
+}
+
+int tr_mlp_grad_noalloc(const float *params, const float *X, const float *Y, long long n, float *grad, float *loss,
+                        hipStream_t st) {
+  if (!params || !X || !Y || !grad || !loss || n <= 0 || n > TR_MLP_NOALLOC_MAX_N) return TR_EINVAL;
+  void *work = nullptr;
+  const int rc = scratch_address(&work);
+  if (rc != TR_OK) return rc;
+  // every word of the pass work is written before it is read within one call
   const Work w = carve(work, n);
   backward(params, X, Y, n, grad, loss, w, st);
   return hipGetLastError() == hipSuccess ? TR_OK : TR_EHIP;
