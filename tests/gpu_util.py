@@ -23,14 +23,30 @@ def to_np(t, shape=None):
     return a if shape is None else a.reshape(shape)
 
 
+FLOOR = 1e-290  # values at or below this carry no relative precision (subnormal range nearby)
+
+
 def assert_close(name, got, ref, rtol, atol_scale=None):
-    """Elementwise |got - ref| <= rtol |ref| + rtol * max|ref| (the second term
-    admits the roundoff of entries far below the array's scale)."""
+    """Elementwise |got - ref| <= rtol |ref| + rtol * scale + FLOOR, where the
+    scale is the largest |ref| of the element's own row: a group's values
+    ([G, n] arrays: per group), a group-direction's corner values ([G, M, n, 2]
+    intensities: per (g, m); [M, n, 2]: per m), the whole array for 1-D
+    arrays.  So a cold group many decades below the hot ones is held to its
+    own scale, and only entries near zero inside a row (sign changes,
+    attenuation across the slab) get the row's absolute slack.  atol_scale
+    overrides the row scale (0: purely relative)."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     assert got.shape == ref.shape, (name, got.shape, ref.shape)
-    scale = np.max(np.abs(ref)) if atol_scale is None else atol_scale
-    tol = rtol * np.abs(ref) + rtol * scale
+    if atol_scale is not None:
+        scale = atol_scale
+    elif ref.ndim <= 1:
+        scale = np.max(np.abs(ref)) if ref.size else 0.0
+    else:
+        lead = ref.ndim - 1 if ref.ndim == 2 else ref.ndim - 2
+        axes = tuple(range(lead, ref.ndim))
+        scale = np.max(np.abs(ref), axis=axes, keepdims=True)
+    tol = rtol * np.abs(ref) + rtol * scale + FLOOR
     bad = ~(np.abs(got - ref) <= tol)
     if np.any(bad):
         idx = np.argwhere(bad)[0]

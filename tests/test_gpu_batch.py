@@ -18,20 +18,40 @@ pytestmark = pytest.mark.gpu
 TILES = [(K, S, 16) for K in (1, 2, 4, 8) for S in (1, 2, 4)] + [(2, 2, 6), (4, 4, 6), (1, 4, 2), (8, 2, 2)]
 
 
+# (K, split, nmu, nx): several passes of 64 K cells per wavefront with a
+# partial last pass, up to the large workload's 2000 cells and 32 directions
+MULTI_PASS = [(8, 1, 32, 1300), (8, 2, 32, 1300), (8, 4, 32, 1300), (4, 4, 32, 1100), (8, 4, 32, 2000),
+              (8, 2, 16, 1100), (2, 1, 8, 1100)]
+
+
 @pytest.mark.parametrize("K,S,nmu", TILES)
 def test_every_sweep_tile_matches_oracle(K, S, nmu):
     """Every tile (K cells per lane, S wavefronts sharing a group's half range)
     against the oracle sweep, incl. direction counts that S does not divide
     (wavefronts with one or no direction)."""
-    note(f"sweep tile K={K} split={S} nmu={nmu}")
-    slab = inputs.make_slab(300, 3, nmu, T_left=1.0, T_right=0.5)
+    _tile_case(K, S, nmu, 300)
+
+
+@pytest.mark.parametrize("K,S,nmu,nx", MULTI_PASS)
+def test_multi_pass_sweep_tiles_match_oracle(K, S, nmu, nx):
+    """Tiles whose wavefronts cross the slab in several passes (the carry of
+    the inflow from one pass to the next), incl. the tile the autotuner picks
+    for slabs above 1024 cells."""
+    _tile_case(K, S, nmu, nx)
+
+
+def _tile_case(K, S, nmu, nx):
+    note(f"sweep tile K={K} split={S} nmu={nmu} nx={nx}")
+    slab = inputs.make_slab(nx, 3, nmu, T_left=1.0, T_right=0.5)
     sv = binding.Solver([slab], [[3, 1]], inputs.SolverCfg(levels=[3, 1]))
     sv.set_tiles([K] * 6, [S] * 6)
     assert sv.get_tiles()[:2] == ([K] * 6, [S] * 6)
-    rng = np.random.default_rng(K + 10 * S + nmu)
-    kap = 10 ** rng.uniform(-2, 4, (3, 300))
-    B = rng.uniform(0, 1, (3, 300))
-    Ip = rng.uniform(0, 1, (3, nmu, 300, 2))
+    rng = np.random.default_rng(K + 10 * S + nmu + nx)
+    kap = 10 ** rng.uniform(-2, 4, (3, nx))
+    # the first group optically thin everywhere: its inflow crosses every pass
+    kap[0] = 10 ** rng.uniform(-3, -1, nx)
+    B = rng.uniform(0, 1, (3, nx))
+    Ip = rng.uniform(0, 1, (3, nmu, nx, 2))
     Io = sv.empty(binding.TR_K_I)
     mom, bnd = sv.empty(binding.TR_K_GI, 4), sv.empty(binding.TR_K_G, 6)
     sv.sweep(to_dev(kap), to_dev(B), to_dev(Ip), Io, mom, bnd)
@@ -45,7 +65,7 @@ def test_every_sweep_tile_matches_oracle(K, S, nmu):
     got = to_np(Io, ref.shape)
     for g in range(3):
         assert_close(f"I g={g}", got[g], ref[g], 1e-12)
-    assert_close("f", to_np(f, (3, 300)), fac.f, 1e-12)
+    assert_close("f", to_np(f, (3, nx)), fac.f, 1e-12)
     assert_close("C", to_np(Cb, (3, 2)), fac.C, 1e-12)
     sv.close()
 
@@ -111,6 +131,61 @@ def test_batch_sampled_slabs_match_oracle():
     assert all(k in (1, 2, 4, 8) for k in K)
     assert all(k in (1, 2, 4) for k in S)
     assert sum(items) == sum(s.ng for s in slabs)
+    sv.close()
+
+
+def _bucket_cover(instances):
+    """Indices of batch instances that cover every populated slab-size bucket
+    of the sweep (nx <= 64, 128, 256, 512) and every group count, the
+    1024-group slabs among them: per bucket the instance with the most
+    groups, plus the smallest and the largest slab of the batch."""
+    bounds = [64, 128, 256, 512]
+    pick = set()
+    for lo, hi in zip([0] + bounds[:-1], bounds):
+        inb = [k for k, d in enumerate(instances) if lo < d["nx"] <= hi]
+        if inb:
+            pick.add(max(inb, key=lambda k: (instances[k]["ng"], instances[k]["nx"])))
+    for G in (64, 128, 256, 512, 1024):
+        ing = [k for k, d in enumerate(instances) if d["ng"] == G]
+        if ing and not any(instances[k]["ng"] == G for k in pick):
+            pick.add(min(ing, key=lambda k: instances[k]["nx"]))
+    cost = lambda k: instances[k]["nx"] * instances[k]["ng"] * instances[k]["nmu"]
+    pick.add(min(range(len(instances)), key=cost))
+    pick.add(max(range(len(instances)), key=cost))
+    return sorted(pick)
+
+
+def test_batch_replay_covers_every_bucket_and_group_count():
+    """One replayed step of slabs that cover every populated size bucket and
+    every group count of the uneven-batch distribution (incl. 1024 groups and
+    the largest slab), solved together in one batch with the autotuned tiles,
+    each against its own oracle run at 1e-10."""
+    inst = inputs.batch_instances(256)
+    ks = _bucket_cover(inst)
+    slabs, cfg, _ = inputs.config_batch(256)
+    slabs = [slabs[k] for k in ks]
+    levels = [inputs.levels_for(s, cfg) for s in slabs]
+    assert {s.ng for s in slabs} == {64, 128, 256, 512, 1024}
+    assert len({min(4, max(0, (s.nx - 1).bit_length() - 6)) for s in slabs}) == 4
+    refs = []
+    for s, lv in zip(slabs, levels):
+        pb = mlqd.problem_from_slab(s)
+        stats = mlqd.Stats()
+        ref = mlqd.step(pb, lv, mlqd.schedule(len(lv), cfg.cycle), cfg.lmax, cfg.eps, cfg.eps_inner,
+                        mlqd.initial_state(pb, 0.001), stats=stats)
+        refs.append((ref, stats.counts[0]))
+    note(f"batch of instances {ks}: nx={[s.nx for s in slabs]} ng={[s.ng for s in slabs]}, one replayed step")
+    sv = binding.Solver(slabs, levels, cfg)
+    tuning.tune(sv, _init(sv), reps=1, path=None)
+    note(f"  tiles {sv.get_tiles()}")
+    st = _init(sv)
+    stats = sv.step(st, replay=[c for _, c in refs])
+    for k, (ref, counts) in enumerate(refs):
+        assert list(stats[k].cycles[:len(counts)]) == counts
+        T, E, I = _slab_view(sv, st, k)
+        assert_close(f"slab {ks[k]} T", T, ref.T, 1e-10, atol_scale=0.0)
+        assert_close(f"slab {ks[k]} E", E.reshape(ref.E.shape), ref.E, 1e-10)
+        assert_close(f"slab {ks[k]} I", I.reshape(ref.I.shape), ref.I, 1e-10)
     sv.close()
 
 
