@@ -4,15 +4,20 @@ multigrid in frequency on one MI355X.
 A "step" is one converged time step of the whole hot path (opacity/Planck
 tables, SCB transport sweeps with their moments, fine and coarse LO solves,
 restriction, grey LO + MEB Newton, cycle control) over the workload's slabs.
-The default workload is the paper-scale problem: 200 cells, S16, 512 groups,
-V cycle on the hierarchy 512,128,32,8,1, dt = 0.002 ns; the timed region is
-the workload's 20 steps from the initial condition (inputs resident in HBM).
+The default (headline) workload is the large single problem: 2000 cells, S32,
+4096 log groups, F cycle on the hierarchy 4096,1024,256,64,16,1, dt = 0.002
+ns; the timed region is --steps steps from the initial condition (inputs
+resident in HBM).  The paper-scale slab (200 cells, S16, 512 groups, V cycle)
+and the batch of 256 uneven slabs are measured in the same run and reported
+under their own keys.
 
 Printed: one JSON line with the throughput in phase-space cell-updates per
 second (sweep cell-updates of the timed steps / wall time), ms per step, the
 live-measured roofline of the sweep kernel (HIP events around its launches,
-algorithmic bytes per launch / average launch time), the learned closure vs
-the plain method, and the CPU oracle timed on a bounded sample.
+algorithmic bytes per launch / average launch time), the fraction of the HBM
+peak of the restriction and fine LO kernel groups, the learned closure vs the
+plain method, and the CPU oracle timed on a bounded sample (one thread and all
+cores).
 """
 import argparse
 import dataclasses
@@ -42,6 +47,28 @@ WORKLOADS = {
 }
 KERNELS = ["opacity", "sweep", "moments", "lo_fine", "restrict", "lo_coarse", "grey"]
 LMAX_CANDIDATES = (1, 2, 4)  # cycles per transport iteration tried in the set-up
+
+
+def lo_fine_bytes(slab, n_cycles, n_sweeps):
+    """Algorithmic HBM bytes of the fine LO solves: per (group, cell) and
+    solve read the QD factor, kappa, B, E_old and F_old and write E and F (56
+    B); the first solve after each sweep reads the two half-range moment
+    partial pairs instead of the factor (32 B instead of 8) and writes the
+    factor (8 B)."""
+    gi = slab.ng * slab.nx
+    return 56.0 * gi * n_cycles + 32.0 * gi * n_sweeps
+
+
+def restrict_bytes(slab, n_stage_levels, n_cycles, n_steps):
+    """Algorithmic HBM bytes of the fine-grid restrictions: per (group, edge)
+    and cycle the fine-to-grey pass reads the QD factor, kappa, B, E and F (40
+    B) and every stage of the schedule reads the factor, E and F (24 B; kappa
+    and B at the stage temperature are recomputed); the first cycle of a step
+    also reads E_old and F_old (16 B) once per target grid.  The coarse-to-grey
+    passes read the coarse levels (under 1/4 of the fine bytes) and are not
+    counted."""
+    ge = slab.ng * (slab.nx + 1)
+    return (40.0 + 24.0 * n_stage_levels) * ge * n_cycles + 16.0 * (1 + n_stage_levels) * ge * n_steps
 
 
 def sweep_bytes(slab, ibytes=8):
@@ -94,9 +121,9 @@ def measured_traffic(workload, bytes_per_launch):
 
 
 def cpu_baseline(workload, budget_s=20.0, lmax=None):
-    """The CPU oracle (numpy, FP64, one thread) on the first time steps of the
-    workload (bounded to about budget_s seconds); run in a child process whose
-    BLAS / OpenMP pools are limited to one thread."""
+    """The CPU oracle (numpy, FP64) on a bounded sample of the workload, in a
+    child process that never touches the GPU (BLAS / OpenMP pools limited to
+    one thread per process)."""
     import subprocess
 
     env = dict(os.environ)
@@ -112,6 +139,36 @@ def cpu_baseline(workload, budget_s=20.0, lmax=None):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def _host_cpus():
+    """(usable cores, cores reported by the OS, model name) of this host."""
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return usable, os.cpu_count() or usable, model
+
+
+_SWEEP_JOB = {}
+
+
+def _sweep_chunk(bounds):
+    """Oracle sweep of groups [g0, g1) of the prepared initial state (worker
+    of the all-cores baseline; the inputs are inherited from the parent)."""
+    from oracle.sweep import sweep
+
+    g0, g1 = bounds
+    j = _SWEEP_JOB
+    t0 = time.perf_counter()
+    out = sweep(j["mu"], j["x"], j["kappa"][g0:g1], j["B"][g0:g1], j["I"][g0:g1], j["il"][g0:g1], j["ir"][g0:g1],
+                j["c"], j["dt"])
+    return time.perf_counter() - t0, float(out[:, :, -1, 1].sum())
+
+
 def _cpu_baseline_child(workload, budget_s, lmax=None):
     from oracle import mlqd
     from paper_2011_05427_amd import inputs
@@ -119,6 +176,8 @@ def _cpu_baseline_child(workload, budget_s, lmax=None):
     slabs, cfg, _ = getattr(inputs, WORKLOADS[workload][0])()
     if lmax is not None:
         cfg = dataclasses.replace(cfg, lmax=lmax)  # the GPU run's choice
+    usable, nproc, model = _host_cpus()
+    host = {"nproc": nproc, "usable_cores": usable, "cpu_model": model}
     if workload == "batch":
         # the oracle on the first slabs of the batch, one step each, within the budget
         t0 = time.perf_counter()
@@ -135,36 +194,50 @@ def _cpu_baseline_child(workload, budget_s, lmax=None):
             if time.perf_counter() - t0 > budget_s * 0.5:
                 break
         dt = time.perf_counter() - t0
-        return {"value": cu / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-                "sample": f"first time step of the first {k} slabs of the batch, numpy FP64, {dt:.1f} s"}
+        return dict(host, value=cu / dt, unit="cell-updates/s", cores=1, kind="oracle",
+                    sample=f"first time step of the first {k} slabs of the batch, numpy FP64, one thread, {dt:.1f} s")
     slab = slabs[0]
     pb = mlqd.problem_from_slab(slab)
     if slab.cell_updates_per_sweep() > 5e7:
-        # a whole step exceeds the budget: one transport sweep of the initial state
-        from oracle.sweep import sweep
+        # a whole step of this size takes minutes in the oracle: one transport
+        # sweep of the initial state (every group and direction), on one thread
+        # and split over processes by group (the sweep of a group is
+        # independent of the others given the tables)
+        import multiprocessing as mp
 
         st = mlqd.initial_state(pb, slab.T0)
         kappa, B = pb.tables(st.T)
+        _SWEEP_JOB.update(mu=pb.mu, x=pb.x_edges, kappa=kappa, B=B, I=st.I, il=pb.inc_left, ir=pb.inc_right,
+                          c=pb.c, dt=pb.dt)
+        t1, _ = _sweep_chunk((0, slab.ng))
+        workers = max(1, min(usable, 16))
+        cuts = [round(k * slab.ng / workers) for k in range(workers + 1)]
         t0 = time.perf_counter()
-        sweep(pb.mu, pb.x_edges, kappa, B, st.I, pb.inc_left, pb.inc_right, pb.c, pb.dt)
-        dt = time.perf_counter() - t0
-        return {"value": slab.cell_updates_per_sweep() / dt, "unit": "cell-updates/s", "cores": 1,
-                "kind": "oracle", "sample": f"one transport sweep of the workload's initial state, numpy FP64, "
-                                            f"{dt:.1f} s"}
+        with mp.get_context("fork").Pool(workers) as pool:
+            pool.map(_sweep_chunk, list(zip(cuts[:-1], cuts[1:])))
+        tn = time.perf_counter() - t0
+        cu = slab.cell_updates_per_sweep()
+        return dict(host, value=cu / tn, unit="cell-updates/s", cores=workers, kind="oracle",
+                    sample=f"one transport sweep of the workload's initial state (all {slab.ng} groups x "
+                           f"{slab.nmu} directions x {slab.nx} cells), numpy FP64: {tn:.1f} s on {workers} "
+                           f"processes over group ranges (incl. pool start-up), {t1:.1f} s on one thread; "
+                           f"a whole oracle step of this size is not timed (minutes)",
+                    one_thread={"value": cu / t1, "unit": "cell-updates/s", "cores": 1, "seconds": t1})
     st = mlqd.initial_state(pb, slab.T0)
     stats = mlqd.Stats()
     t0 = time.perf_counter()
     nsteps = 0
     while True:
-        st = mlqd.step(pb, cfg.levels, mlqd.schedule(len(cfg.levels), cfg.cycle), cfg.lmax, cfg.eps, cfg.eps_inner, st, stats=stats)
+        st = mlqd.step(pb, cfg.levels, mlqd.schedule(len(cfg.levels), cfg.cycle), cfg.lmax, cfg.eps,
+                       cfg.eps_inner, st, stats=stats)
         nsteps += 1
         if time.perf_counter() - t0 > budget_s * 0.5:
             break
     dt = time.perf_counter() - t0
-    return {"value": slab.cell_updates_per_sweep() * stats.n_ti / dt, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle", "ms_per_step": 1e3 * dt / nsteps,
-            "sample": f"first {nsteps} time step(s) of the same workload ({stats.n_ti} sweeps), numpy FP64, "
-                      f"{dt:.1f} s"}
+    return dict(host, value=slab.cell_updates_per_sweep() * stats.n_ti / dt, unit="cell-updates/s", cores=1,
+                kind="oracle", ms_per_step=1e3 * dt / nsteps,
+                sample=f"first {nsteps} time step(s) of the same workload ({stats.n_ti} sweeps), numpy FP64, "
+                       f"one thread, {dt:.1f} s")
 
 
 def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closure=None, final=None, sweep_ev=0):
@@ -275,46 +348,16 @@ def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles, cands, initial)
             "note": "candidates " + ",".join(f"{'VWF'[c]}{l}" for c, l in cands) + "; probe every 8 steps"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
-    ap.add_argument("--cpu-lmax", type=int, default=None, help=argparse.SUPPRESS)
-    ap.add_argument("--lmax", type=int, default=None,
-                    help="use this lmax instead of the set-up choice (e.g. to profile a plain run's choice)")
-    ap.add_argument("--tiles", default=None,
-                    help="sweep tiles 'K1,..,K6:S1,..,S6' per slab-size bucket instead of the autotuner's")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
-    ap.add_argument("--train-samples", type=int, default=1000000)
-    ap.add_argument("--train-epochs", type=int, default=5)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="end with a 1 GiB device copy (reference kernel for the HBM byte counters)")
-    ap.add_argument("--fp32", action="store_true",
-                    help="also time the binary32-storage sweep variant and state its error vs binary64")
-    args = ap.parse_args()
-    if args.cpu_baseline_child:
-        print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget, args.cpu_lmax)))
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the design notes describe how the path would shard)"}))
-        sys.exit(2)
-
+def measure(workload, steps, warmup, tiles_opt=None, lmax_opt=None, fp32=False):
+    """Set-up (sweep tiles, lmax), the timed steps and an event-timed rerun of
+    the same steps for one workload; returns (result dict, internals)."""
     import torch
 
     from paper_2011_05427_amd import binding, inputs, tuning
 
-    fn, desc = WORKLOADS[args.workload]
-    slabs, cfg, nsteps_cfg = getattr(inputs, fn)()
-    if args.steps is None:
-        args.steps = {"paper": 20, "small": 1, "large": 3, "batch": 2}[args.workload]
+    fn, desc = WORKLOADS[workload]
+    slabs, cfg, _ = getattr(inputs, fn)()
     levels = [inputs.levels_for(s, cfg) for s in slabs]
-    torch.cuda.set_device(0)
 
     # sweep tiles (cells per lane, wavefronts per group and half range) chosen
     # by the autotuner on this workload's first state (untimed set-up)
@@ -322,8 +365,8 @@ def main():
     st = sv.new_state()
     sv.state_init(st, slabs[0].T0)
     t0 = time.perf_counter()
-    if args.tiles:
-        ks, ss = args.tiles.split(":")
+    if tiles_opt:
+        ks, ss = tiles_opt.split(":")
         tiles = ([int(v) for v in ks.split(",")], [int(v) for v in ss.split(",")])
         sv.set_tiles(*tiles)
         tune_info = {"K": tiles[0], "split": tiles[1], "us": None, "fixed": True}
@@ -336,60 +379,59 @@ def main():
     # and the tolerances, not lmax
     cfg_lmax = cfg.lmax
     cands = [(cfg.cycle, l) for l in LMAX_CANDIDATES]
-    if args.lmax is not None:
+    if lmax_opt is not None:
         sched_ms = None
-        cfg = dataclasses.replace(cfg, lmax=args.lmax)
+        cfg = dataclasses.replace(cfg, lmax=lmax_opt)
     else:
         sched_ms = tuning.tune_schedule(sv, st, cands, steps=2)
         cfg = dataclasses.replace(cfg, lmax=next(iter(sched_ms))[1])
     sv.close()
     del st
+    torch.cuda.empty_cache()
 
-    # timed: graph replay, no events
+    # timed: graph replay, no events, except that the first steps also time
+    # their sweep launches
     fin64 = {}
-    # the first steps of the timed run also time their sweep launches
-    n_ev = max(1, args.steps // 10)
-    wall, acc, acc_ev = run_steps(slabs, levels, cfg, args.steps, args.warmup, tiles=tiles, final=fin64,
-                                  sweep_ev=n_ev)
-    # per-kernel durations: the same steps with HIP events around each kernel group
-    # (eager launches, not part of the timed value)
-    _, prof = run_steps(slabs, levels, cfg, args.steps, 0, timing=True, tiles=tiles)
+    n_ev = max(1, steps // 10)
+    wall, acc, acc_ev = run_steps(slabs, levels, cfg, steps, warmup, tiles=tiles, final=fin64, sweep_ev=n_ev)
+    # per-kernel durations: the same steps with HIP events around each kernel
+    # group (eager launches, not part of the timed value)
+    _, prof = run_steps(slabs, levels, cfg, steps, 0, timing=True, tiles=tiles)
 
     sweeps = [int(acc[k].n_ti) for k in range(len(slabs))]
     cu = sum(s.cell_updates_per_sweep() * n for s, n in zip(slabs, sweeps))
-    value = cu / wall
     p = prof[0]  # kernel-group times cover the whole context
-    # sweep kernel time inside the timed run: the launches of its first n_ev
-    # steps record their own start and end on HIP events
     t_sweep_s = acc_ev[0].t_ms[binding.T_SWEEP] / 1e3
     n_sweep = acc_ev[0].n_launch[binding.T_SWEEP]
     bytes_total = sum(sweep_bytes(s) * int(acc_ev[k].n_ti) for k, s in enumerate(slabs))
     achieved = bytes_total / t_sweep_s / 1e9 if t_sweep_s > 0 else 0.0
-    kernel_ms = {name: p.t_ms[k] / max(args.steps, 1) for k, name in enumerate(KERNELS)}
-    ms_step = 1e3 * wall / args.steps
-    out = {
-        "metric": "phase-space cell-updates/s per sweep; ms per converged time step, learned vs plain",
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    kernel_ms = {name: p.t_ms[k] / max(steps, 1) for k, name in enumerate(KERNELS)}
+    # HBM fractions of the restriction and fine LO kernel groups over the
+    # event-timed steps (algorithmic bytes from the per-slab counts)
+    nstage = [len(mlqd_schedule(len(lv), cfg.cycle)) for lv in levels]
+    rb = sum(restrict_bytes(s, ns, int(a.n_c), steps) for s, ns, a in zip(slabs, nstage, prof))
+    lb = sum(lo_fine_bytes(s, int(a.n_c), int(a.n_ti)) for s, a in zip(slabs, prof))
+    groups = {}
+    for name, idx, nbytes in (("restrict", binding.T_RESTRICT, rb), ("lo_fine", binding.T_LO_FINE, lb)):
+        t = p.t_ms[idx] / 1e3
+        gbs = nbytes / t / 1e9 if t > 0 else None
+        groups[name] = {"bytes_per_step": nbytes / steps, "ms_per_step": 1e3 * t / steps, "achieved_GBs": gbs,
+                        "frac": gbs / HBM_PEAK_GBS if gbs else None, "launches": int(p.n_launch[idx])}
+    ms_step = 1e3 * wall / steps
+    res = {
+        "value": cu / wall,
         "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
         "config": {
             "workload": desc,
             "slabs": len(slabs),
             "cell_updates_per_sweep": sum(s.cell_updates_per_sweep() for s in slabs),
             "levels": levels[0] if len(slabs) == 1 else "per slab G,G/8,1",
             "cycle": "VWF"[cfg.cycle], "lmax": cfg.lmax, "eps": cfg.eps, "eps_inner": cfg.eps_inner,
-            "steps_timed": args.steps, "sweeps": sum(sweeps), "cycles": int(sum(a.n_c for a in acc)),
+            "steps_timed": steps, "sweeps": sum(sweeps), "cycles": int(sum(a.n_c for a in acc)),
             "lo_solves": int(sum(a.n_lo for a in acc)), "closure": "plain",
         },
         "kernel_ms_per_step": kernel_ms,
+        "kernel_groups_hbm": groups,
         "sweep_kernel_cell_updates_per_s": (sum(s.cell_updates_per_sweep() * int(acc_ev[k].n_ti)
                                                 for k, s in enumerate(slabs)) / t_sweep_s) if t_sweep_s else None,
         "roofline": {
@@ -408,19 +450,33 @@ def main():
                     "achieved = algorithmic bytes (32 B per cell-update + 32 B per group-cell of moment "
                     "partials) / kernel time",
         },
+        "tiles": {"K_per_bucket": tune_info["K"], "split_per_bucket": tune_info["split"],
+                  "us_per_tile": tune_info["us"], "fixed_by_option": bool(tune_info.get("fixed")),
+                  "tile_order": "q = (K in 1,2,4,8)[q // 3], (split in 1,2,4)[q % 3]",
+                  "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]},
+        "schedule": {
+            "lmax_chosen": cfg.lmax, "lmax_configured": cfg_lmax,
+            "set_up_ms_per_step": ({f"{'VWF'[c]}{l}": ms for (c, l), ms in sched_ms.items()} if sched_ms else None),
+            "set_up": ("2 steps from the initial state per candidate, after 2 untimed steps that capture its graphs"
+                       if sched_ms else "fixed by --lmax"),
+        },
     }
-    if args.fp32:
+    tr = measured_traffic(workload, res["roofline"]["bytes_per_launch"])
+    if tr is not None:
+        res["roofline"]["traffic"] = tr["bytes_per_launch"]
+        res["roofline"]["traffic_detail"] = tr
+    if fp32:
         import numpy as np
 
         cfg32 = dataclasses.replace(cfg, precision=1)
         fin32 = {}
-        wall32, acc32, ev32 = run_steps(slabs, levels, cfg32, args.steps, args.warmup, tiles=tiles, final=fin32,
+        wall32, acc32, ev32 = run_steps(slabs, levels, cfg32, steps, warmup, tiles=tiles, final=fin32,
                                         sweep_ev=n_ev)
         t32 = ev32[0].t_ms[binding.T_SWEEP] / 1e3
         b32 = sum(sweep_bytes(s, 4) * int(ev32[k].n_ti) for k, s in enumerate(slabs))
         rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
-        out["fp32_storage"] = {
-            "ms_per_step": 1e3 * wall32 / args.steps,
+        res["fp32_storage"] = {
+            "ms_per_step": 1e3 * wall32 / steps,
             "value": sum(s.cell_updates_per_sweep() * int(acc32[k].n_ti) for k, s in enumerate(slabs)) / wall32,
             "sweeps": int(sum(a.n_ti for a in acc32)),
             "sweep_achieved_GBs": b32 / t32 / 1e9 if t32 > 0 else None,
@@ -429,22 +485,93 @@ def main():
             "max_rel_err_E_vs_f64": rel(fin32["E"], fin64["E"]),
             "note": "corner intensities stored in binary32; sweep arithmetic, moments, LO, grey and MEB in binary64",
         }
-    out["tiles"] = {"K_per_bucket": tune_info["K"], "split_per_bucket": tune_info["split"],
-                    "us_per_tile": tune_info["us"], "fixed_by_option": bool(tune_info.get("fixed")), "tile_order": "q = (K in 1,2,4,8)[q // 3], (split in 1,2,4)[q % 3]",
-                    "buckets": tuning.BUCKETS, "tune_s": tune_info["tune_s"]}
-    out["schedule"] = {
-        "lmax_chosen": cfg.lmax, "lmax_configured": cfg_lmax,
-        "set_up_ms_per_step": ({f"{'VWF'[c]}{l}": ms for (c, l), ms in sched_ms.items()} if sched_ms else None),
-        "set_up": ("2 steps from the initial state per candidate, after 2 untimed steps that capture its graphs"
-                   if sched_ms else "fixed by --lmax"),
+    internals = dict(slabs=slabs, levels=levels, cfg=cfg, tiles=tiles, cands=cands, sched_ms=sched_ms,
+                     sweeps=sum(sweeps))
+    return res, internals
+
+
+def mlqd_schedule(n_levels, cycle):
+    """Grids visited after each grey solve in one cycle (the library's own
+    rule: V none, W the second grid, F every intermediate grid); used only to
+    count the restriction passes of the byte model."""
+    if cycle == 0 or n_levels <= 2:
+        return []
+    if cycle == 1:
+        return [1]
+    return list(range(n_levels - 2, 0, -1))
+
+
+EXTRA_STEPS = {"paper": 20, "batch": 4}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--extras", default="paper,batch",
+                    help="other workloads measured in the same run (comma list, '' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-lmax", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--lmax", type=int, default=None,
+                    help="use this lmax instead of the set-up choice (e.g. to profile a plain run's choice)")
+    ap.add_argument("--tiles", default=None,
+                    help="sweep tiles 'K1,..,K6:S1,..,S6' per slab-size bucket instead of the autotuner's")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the stage-adaptive schedule run")
+    ap.add_argument("--train-samples", type=int, default=1000000)
+    ap.add_argument("--train-epochs", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 1 GiB device copy (reference kernel for the HBM byte counters)")
+    ap.add_argument("--fp32", action="store_true",
+                    help="also time the binary32-storage sweep variant and state its error vs binary64")
+    args = ap.parse_args()
+    if args.cpu_baseline_child:
+        print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget, args.cpu_lmax)))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the design notes describe how the path would shard)"}))
+        sys.exit(2)
+
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.steps is None:
+        args.steps = {"paper": 20, "small": 1, "large": 50, "batch": 4}[args.workload]
+    res, ins = measure(args.workload, args.steps, args.warmup, args.tiles, args.lmax, args.fp32)
+    out = {
+        "metric": "phase-space cell-updates/s per sweep; ms per converged time step, learned vs plain",
+        "value": res.pop("value"),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
     }
-    out["stage_adaptive"] = run_stage_adaptive(slabs, levels, cfg, args.steps, args.warmup, tiles, cands, sched_ms)
+    out.update(res)
+    if not args.no_adaptive:
+        out["stage_adaptive"] = run_stage_adaptive(ins["slabs"], ins["levels"], ins["cfg"], args.steps, args.warmup,
+                                                   ins["tiles"], ins["cands"], ins["sched_ms"])
     if not args.no_learned:
-        out["learned"] = learned_vs_plain(slabs, levels, cfg, tiles, args, ms_step, sum(sweeps))
-    tr = measured_traffic(args.workload, out["roofline"]["bytes_per_launch"])
-    if tr is not None:
-        out["roofline"]["traffic"] = tr["bytes_per_launch"]
-        out["roofline"]["traffic_detail"] = tr
+        out["learned"] = learned_vs_plain(ins["slabs"], ins["levels"], ins["cfg"], ins["tiles"], args,
+                                          out["ms_per_step"], ins["sweeps"])
+    torch.cuda.empty_cache()
+    for extra in [e for e in args.extras.split(",") if e and e != args.workload]:
+        r, xi = measure(extra, EXTRA_STEPS.get(extra, 4), args.warmup)
+        r["steps"] = EXTRA_STEPS.get(extra, 4)
+        if not args.no_cpu_baseline:
+            r["cpu_baseline"] = cpu_baseline(extra, args.cpu_budget, xi["cfg"].lmax)
+        out[{"paper": "paper_scale"}.get(extra, extra)] = r
+        torch.cuda.empty_cache()
     if args.copy_calibration:
         # a plain device copy of known size for the byte-counter calibration
         # (outside every timed region)
@@ -456,7 +583,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 3}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, cfg.lmax)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, ins["cfg"].lmax)
     print(json.dumps(out), flush=True)
 
 
