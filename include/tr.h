@@ -69,10 +69,21 @@ enum {
 
 /*
  * One slab problem (all pointers HOST, copied at tr_create).  Paper Sec. 2
- * (Eqs. rt-nu, eb-nu, rt-nu-bc and the multigroup Eqs. rt, rt-bc, rt-ic) with
- * the opacity law kappa_g(T) = C_cell / nu_c^3 (1 - exp(-nu_c / T)) at the
- * group centre nu_c (sigma_E = sigma_B = sigma_R = kappa_g) and eps = cv T.
+ * (Eqs. rt-nu, eb-nu, rt-nu-bc and the multigroup Eqs. rt, rt-bc, rt-ic),
+ * eps = cv T, and the spectral opacity sigma(nu, T) = C_cell / nu^3 (1 -
+ * exp(-nu / T)) of Sec. 6, entering the group equations either
+ *  - TR_OPAC_POINT: as the point law kappa_g(T) = C_cell / nu_c^3 (1 -
+ *    exp(-nu_c / T)) at the group centre nu_c, sigma_E = sigma_B = sigma_R =
+ *    kappa_g; or
+ *  - TR_OPAC_SPECTRAL: as the paper's group averages (Sec. 2 after Eq. rt,
+ *    Sec. 3.1 with Eq. mloqd-2): sigma_B,g(T) Planck-weighted at T (only the
+ *    emission sigma_B,g B_g enters; closed form), sigma_E,g(T, T_r)
+ *    Planck-weighted at the radiation temperature T_r = (E / a_R)^(1/4) of the
+ *    cell's latest grey energy density E, sigma_R,g(T, T_r) the dB/dT-weighted
+ *    harmonic mean at T_r (Gauss-Legendre panels in nu / T_r).  nu_center is
+ *    not used.
  */
+enum { TR_OPAC_POINT = 0, TR_OPAC_SPECTRAL = 1 };
 typedef struct tr_problem {
   int nx;                  /* cells, >= 2 */
   int ng;                  /* fine groups, >= 1 */
@@ -92,6 +103,7 @@ typedef struct tr_problem {
   int n_levels;            /* frequency grids incl. fine and grey, 2..8 */
   const int *level_ng;     /* [n_levels] groups per grid: ng, ..., 1; each
                               divides the previous (uniform coarsening) */
+  int opacity;             /* TR_OPAC_POINT or TR_OPAC_SPECTRAL */
 } tr_problem;
 
 /* Iteration settings shared by all slabs of a context (paper Alg. 3). */
@@ -133,13 +145,22 @@ int tr_layout(const tr_ctx *ctx, int kind, int slab, long long *offset, long lon
 int tr_set_incoming(tr_ctx *ctx, int slab, const double *inc_left, const double *inc_right);
 
 /*
- * A1 (paper Sec. 2 opacity/Planck; config law).  For every slab, cell and
- * group: kappa[g][i] = kappa_g(T_i), B[g][i] = group Planck integral
- *   B_g = (aR c T^4 / 2) (15/pi^4) int_{nu_g/T}^{nu_{g+1}/T} t^3/(e^t-1) dt
- * and dS[i] = d/dT sum_g 2 kappa_g B_g at T_i.
- * T: cell (pooled); kappa, B: gi (pooled); dS: cell (pooled).
+ * A1 (paper Sec. 2 group opacities and Planck function).  For every slab,
+ * cell and group, at T_i:
+ *  - point slabs: kappa[g][i] = kappa_g(T_i), B[g][i] = group Planck integral
+ *      B_g = (aR c T^4 / 2) (15/pi^4) int_{nu_g/T}^{nu_{g+1}/T} t^3/(e^t-1) dt;
+ *  - spectral slabs: kappa[g][i] = sigma_E,g(T_i, T_r,i), B[g][i] =
+ *    sigma_B,g B_g / sigma_E,g (so that kappa B is the group emission), and
+ *    sigR[g][i] = sigma_R,g(T_i, T_r,i), with T_r = (Egrey / aR)^(1/4)
+ *    (Egrey NULL: T_r = T);
+ * and dS[i] = d/dT sum_g 2 sigma_B,g B_g at T_i.  The sweep and the LO
+ * solves take kappa as the absorption opacity and kappa B as the emission.
+ * T, Egrey: cell (pooled); kappa, B, sigR: gi (pooled); dS: cell (pooled,
+ * nullable); sigR is written for spectral slabs only (nullable when no slab
+ * is spectral).  Errors: TR_EINVAL (sigR NULL with a spectral slab).
  */
-int tr_opacity(tr_ctx *ctx, const double *T, double *kappa, double *B, double *dS, hipStream_t stream);
+int tr_opacity(tr_ctx *ctx, const double *T, const double *Egrey, double *kappa, double *B, double *sigR,
+               double *dS, hipStream_t stream);
 
 /*
  * A2 + partial A3: one transport sweep (paper Sec. 5: implicit Euler, simple
@@ -171,6 +192,8 @@ typedef struct tr_lo_coeffs {
   /* level 0 (fine): */
   const double *kappa, *B;   /* gi, tables at the level's temperature */
   const double *f, *fbnd;    /* gi, g2 QD factors */
+  const double *sigRc;       /* gi, cell values of sigma_R,g (spectral
+                                slabs); NULL: kappa (point law) */
   /* levels >= 1: */
   const double *sigE, *emis; /* [n][nx] absorption, emission e = sum 2 kappa B */
   const double *a, *b;       /* [n][nx+1] coefficients of E right / left of edge */

@@ -89,17 +89,20 @@ def edge_opacity(sig_cell, dx):
     return out
 
 
-def fine_level(kappa, B, fac, Eold, Fold, dx):
+def fine_level(kappa, B, fac, Eold, Fold, dx, emis=None, sigR=None):
     """Fine-grid (Omega^1) coefficients from the opacity / Planck tables at the
-    current temperature and the QD factors of the last sweep."""
+    current temperature and the QD factors of the last sweep.  Point law
+    (default): sigma_E = sigma_R = kappa and emission 2 kappa B.  With the
+    group averages of the spectral opacity, kappa is sigma_E,g, `emis` the
+    emission 2 sigma_B,g B_g and `sigR` the cell values of sigma_R,g."""
     G, nx = kappa.shape
     f_ext = np.concatenate([fac.f_bnd[:, :1], fac.f, fac.f_bnd[:, 1:]], axis=1)  # [G, nx+2]
     return Level(
         sigE=kappa.copy(),
-        emis=2.0 * kappa * B,
+        emis=2.0 * kappa * B if emis is None else np.array(emis, dtype=np.float64),
         a=f_ext[:, 1:].copy(),
         b=f_ext[:, :-1].copy(),
-        sigR=edge_opacity(kappa, dx),
+        sigR=edge_opacity(kappa if sigR is None else np.asarray(sigR, dtype=np.float64), dx),
         C=fac.C.copy(),
         Phi=fac.Phi.copy(),
         Eold=np.array(Eold, dtype=np.float64),

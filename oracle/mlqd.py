@@ -44,7 +44,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import planck
+from . import opacity, planck
 from .lo import Level, LOSolution, fine_level, grey_newton, solve_level
 from .moments import Factors, energy_flux, factors
 from .restrict import restrict
@@ -71,6 +71,7 @@ class Problem:
     dt: float
     c: float
     aR: float
+    opacity: int = 0  # 0: point law at the group centre; 1: group averages of the spectral law
 
     @property
     def dx(self):
@@ -89,8 +90,21 @@ class Problem:
         B = planck.planck_groups(self.nu_edges, T, self.aR, self.c)
         return kappa, B
 
+    def coeffs(self, T, Egrey):
+        """Group coefficients at the material temperature T (cell array) and
+        the grey energy density Egrey of the same grey solve (radiation
+        temperature of the spectral averages): (sigma_E, emission source
+        sigma_B B, sigma_R), each [G, nx].  Point law: (kappa, kappa B, kappa)."""
+        if self.opacity == 1:
+            Tr = opacity.radiation_temperature(Egrey, self.aR)
+            return opacity.spectral_tables(self.nu_edges, self.C_cell, T, Tr, self.aR, self.c)
+        kappa, B = self.tables(T)
+        return kappa, kappa * B, kappa
+
     def emission_dT(self, T):
-        """S'(T) = d/dT sum_g 2 kappa_g B_g  -> [nx]"""
+        """S'(T) = d/dT sum_g 2 sigma_B,g B_g  -> [nx]"""
+        if self.opacity == 1:
+            return 2.0 * np.sum(opacity.emission_dT(self.nu_edges, self.C_cell, T, self.aR, self.c), axis=0)
         kappa, B = self.tables(T)
         dk = planck.opacity_dT(self.nu_center, self.C_cell, T)
         dB = planck.planck_groups_dT(self.nu_edges, T, self.aR, self.c)
@@ -110,6 +124,7 @@ def problem_from_slab(slab) -> Problem:
         inc_left=planck.boundary_intensity(slab.nu_edges, slab.T_left, slab.aR, slab.c),
         inc_right=planck.boundary_intensity(slab.nu_edges, slab.T_right, slab.aR, slab.c),
         cv=float(slab.cv), dt=float(slab.dt), c=float(slab.c), aR=float(slab.aR),
+        opacity=int(getattr(slab, "opacity", 0)),
     )
 
 
@@ -226,8 +241,8 @@ def step(pb: Problem, levels: List[int], schedule: List[int], lmax: int, eps: fl
     s = 0
     while True:
         if s > 0:
-            kappa, B = pb.tables(T_s)
-            I = sweep(pb.mu, pb.x_edges, kappa, B, st.I, pb.inc_left, pb.inc_right, c, dt)
+            sig, src, _ = pb.coeffs(T_s, E_s)
+            I = sweep(pb.mu, pb.x_edges, sig, None, st.I, pb.inc_left, pb.inc_right, c, dt, source=src)
             fac = factors(pb.mu, pb.w, I, pb.inc_left, pb.inc_right, c)
             stats.n_ti += 1
         T_cur, E_cur = T_s, E_s
@@ -235,8 +250,8 @@ def step(pb: Problem, levels: List[int], schedule: List[int], lmax: int, eps: fl
         while True:
             ncyc += 1
             # fine spectrum at T^(l,s)
-            kappa, B = pb.tables(T_cur)
-            fine = fine_level(kappa, B, fac, Eold, Fold, dx)
+            sig, src, sR = pb.coeffs(T_cur, E_cur)
+            fine = fine_level(sig, None, fac, Eold, Fold, dx, emis=2.0 * src, sigR=sR)
             fsol = solve_level(fine, dx, c, dt)
             stats.n_lo += levels[0]
             # stage k = 0: grey from the fine spectrum
@@ -251,8 +266,8 @@ def step(pb: Problem, levels: List[int], schedule: List[int], lmax: int, eps: fl
             prev = (Tst, gr.sigE)
             Tt, Eg = gr.T, gr.sol.E[0]
             for gam in schedule:
-                kap2, B2 = pb.tables(Tt)
-                fine2 = fine_level(kap2, B2, fac, Eold, Fold, dx)
+                sig2, src2, sR2 = pb.coeffs(Tt, Eg)
+                fine2 = fine_level(sig2, None, fac, Eold, Fold, dx, emis=2.0 * src2, sigR=sR2)
                 lv = restrict(fine2, fsol, levels[gam], dx, c)
                 csol = solve_level(lv, dx, c, dt)
                 stats.n_lo += levels[gam]
@@ -315,26 +330,32 @@ def alg1_step(pb: Problem, st: State, eps: float = 1e-13, max_outer: int = 200) 
     I = st.I
     T = Told.copy()
 
+    # radiation temperature of the spectral averages: from the total energy
+    # density of the previous outer iteration's solution (held during the
+    # nonlinear solve); at the fixed point it is that of the solution itself
+    Er = st.Egrey.copy()
+
     def lo_at(Tv, fac_):
-        kappa, B = pb.tables(Tv)
-        sol = solve_level(fine_level(kappa, B, fac_, Eold, Fold, dx), dx, c, dt)
-        return kappa, B, sol
+        sig, src, sR = pb.coeffs(Tv, Er)
+        sol = solve_level(fine_level(sig, None, fac_, Eold, Fold, dx, emis=2.0 * src, sigR=sR), dx, c, dt)
+        return sig, src, sol
 
     def meb_residual(Tv, fac_):
-        kappa, B, sol = lo_at(Tv, fac_)
-        return cv * (Tv - Told) / dt - np.sum(c * kappa * sol.E - 2.0 * kappa * B, axis=0)
+        sig, src, sol = lo_at(Tv, fac_)
+        return cv * (Tv - Told) / dt - np.sum(c * sig * sol.E - 2.0 * src, axis=0)
 
     sol = None
     for s in range(max_outer):
         if s > 0:
-            kappa, B = pb.tables(T)
-            I = sweep(pb.mu, pb.x_edges, kappa, B, st.I, pb.inc_left, pb.inc_right, c, dt)
+            sig, src, _ = pb.coeffs(T, Er)
+            I = sweep(pb.mu, pb.x_edges, sig, None, st.I, pb.inc_left, pb.inc_right, c, dt, source=src)
             fac = factors(pb.mu, pb.w, I, pb.inc_left, pb.inc_right, c)
         r = root(meb_residual, T, args=(fac,), method="hybr", tol=1e-15)
         Tn = r.x
         _, _, sol = lo_at(Tn, fac)
-        done = s >= 1 and _norm(Tn - T) <= eps * _norm(Tn)
-        T = Tn
+        En = sol.E.sum(axis=0)
+        done = s >= 1 and _norm(Tn - T) <= eps * _norm(Tn) and _norm(En - Er) <= eps * _norm(En)
+        T, Er = Tn, En
         if done:
             break
     else:

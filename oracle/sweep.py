@@ -25,7 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def sweep(mu, x_edges, kappa, B, I_prev, inc_left, inc_right, c, dt):
+def sweep(mu, x_edges, kappa, B, I_prev, inc_left, inc_right, c, dt, source=None):
     """One transport sweep over every group and direction.
 
     mu        [M] direction cosines
@@ -35,6 +35,9 @@ def sweep(mu, x_edges, kappa, B, I_prev, inc_left, inc_right, c, dt):
               (corner 0 = left corner, corner 1 = right corner)
     inc_left  [G] isotropic incoming intensity at x = 0 (used for mu > 0)
     inc_right [G] isotropic incoming intensity at x = X (used for mu < 0)
+    source    [G, nx] emission sigma_B,g B_g of the group (default kappa B,
+              the point law where sigma_B = sigma_E = kappa); kappa is then
+              the absorption opacity sigma_E,g and B is not used
     returns I [G, M, nx, 2]
     """
     mu = np.asarray(mu, dtype=np.float64)
@@ -43,6 +46,7 @@ def sweep(mu, x_edges, kappa, B, I_prev, inc_left, inc_right, c, dt):
     M = len(mu)
     inv_cdt = 1.0 / (c * dt)
     sig = kappa + inv_cdt
+    src = kappa * B if source is None else np.asarray(source, dtype=np.float64)
     I = np.empty((G, M, nx, 2))
     for m in range(M):
         amu = abs(mu[m])
@@ -60,8 +64,8 @@ def sweep(mu, x_edges, kappa, B, I_prev, inc_left, inc_right, c, dt):
             #   -a I_up + (a + b) I_dn = s_dn
             a = amu / 2.0
             b = sig[:, i] * dx[i] / 2.0
-            s_up = dx[i] / 2.0 * (kappa[:, i] * B[:, i] + inv_cdt * I_prev[:, m, i, up])
-            s_dn = dx[i] / 2.0 * (kappa[:, i] * B[:, i] + inv_cdt * I_prev[:, m, i, dn])
+            s_up = dx[i] / 2.0 * (src[:, i] + inv_cdt * I_prev[:, m, i, up])
+            s_dn = dx[i] / 2.0 * (src[:, i] + inv_cdt * I_prev[:, m, i, dn])
             r1 = s_up + amu * I_in
             r2 = s_dn
             det = (a + b) * (a + b) + a * a

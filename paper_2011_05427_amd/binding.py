@@ -30,7 +30,7 @@ class TrProblem(C.Structure):
                 ("x_edges", _dp), ("nu_edges", _dp), ("nu_center", _dp), ("mu", _dp), ("w", _dp),
                 ("C_cell", _dp), ("T_left", C.c_double), ("T_right", C.c_double), ("cv", C.c_double),
                 ("dt", C.c_double), ("c", C.c_double), ("aR", C.c_double), ("n_levels", C.c_int),
-                ("level_ng", _ip)]
+                ("level_ng", _ip), ("opacity", C.c_int)]
 
 
 class TrSolverCfg(C.Structure):
@@ -40,7 +40,8 @@ class TrSolverCfg(C.Structure):
 
 class TrLoCoeffs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in
-                ("kappa", "B", "f", "fbnd", "sigE", "emis", "a", "b", "sigR", "C", "Phi", "Eold", "Fold")]
+                ("kappa", "B", "f", "fbnd", "sigRc", "sigE", "emis", "a", "b", "sigR", "C", "Phi", "Eold",
+                 "Fold")]
 
 
 class TrLoFields(C.Structure):
@@ -98,7 +99,7 @@ def load():
     lib.tr_error_string.restype = C.c_char_p
     lib.tr_layout.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
     lib.tr_set_incoming.argtypes = [vp, C.c_int, _dp, _dp]
-    lib.tr_opacity.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tr_opacity.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.tr_sweep.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.tr_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.tr_lo_solve.argtypes = [vp, C.c_int, C.POINTER(TrLoCoeffs), C.POINTER(TrLoFields), vp]
@@ -174,6 +175,7 @@ class Solver:
             p.T_left, p.T_right, p.cv, p.dt, p.c, p.aR = s.T_left, s.T_right, s.cv, s.dt, s.c, s.aR
             p.n_levels = len(lv)
             p.level_ng = lvl.ctypes.data_as(_ip)
+            p.opacity = int(getattr(s, "opacity", 0))
         self.levels = [list(lv) for lv in levels]
         self.nlev = len(self.levels[0])
         self.precision = int(getattr(cfg, "precision", 0))
@@ -221,9 +223,9 @@ class Solver:
         _check(self.lib.tr_set_incoming(self._ctx, slab, None if l is None else _as_dp(l),
                                         None if r is None else _as_dp(r)), "tr_set_incoming")
 
-    def opacity(self, T, kappa, B, dS=None):
-        _check(self.lib.tr_opacity(self._ctx, _ptr(T), _ptr(kappa), _ptr(B), _ptr(dS), self._stream()),
-               "tr_opacity")
+    def opacity(self, T, kappa, B, dS=None, Egrey=None, sigR=None):
+        _check(self.lib.tr_opacity(self._ctx, _ptr(T), _ptr(Egrey), _ptr(kappa), _ptr(B), _ptr(sigR), _ptr(dS),
+                                   self._stream()), "tr_opacity")
 
     def sweep(self, kappa, B, I_prev, I_out, mom, bnd):
         _check(self.lib.tr_sweep(self._ctx, _ptr(kappa), _ptr(B), _ptr(I_prev), _ptr(I_out), _ptr(mom),

@@ -37,6 +37,10 @@ struct tr_ctx {
   std::vector<int> sched;
   int grey_threads = 64;  // block size of the grey solve
   int opac_run = 4;       // groups per thread of the opacity kernel (1 or 4)
+  // some slab has the spectral opacity model: the opacity launches evaluate
+  // the group averages (radiation temperature from the grey E) and write the
+  // sigma_R table; grey stages take tables at T~ and the plain restriction
+  bool spectral = false;
   std::vector<SlabDev> hs;  // host copies of the slab descriptors
   std::vector<double> h_inc;
   // totals per kind
@@ -47,6 +51,7 @@ struct tr_ctx {
   ProbDev pd{};
   double *d_inc = nullptr;
   // workspace
+  double *sigR = nullptr;  // cell sigma_R table (spectral); = kappa otherwise
   double *kappa = nullptr, *B = nullptr, *dSpart = nullptr, *dS = nullptr, *mom = nullptr, *bnd = nullptr, *Phi = nullptr;
   double *Eold = nullptr, *Fold = nullptr, *red = nullptr;
   double *Told = nullptr, *Ts = nullptr, *Tcyc = nullptr, *Tstar = nullptr, *Tprev = nullptr, *sigprev = nullptr;
@@ -342,6 +347,7 @@ LoIn fine_in(const tr_ctx *c, const double *kappa, const double *B, const double
   LoIn in{};
   in.kappa = kappa;
   in.B = B;
+  in.sgr = c->sigR;
   in.f = f;
   in.fbnd = fbnd;
   in.C = C;
@@ -389,6 +395,7 @@ LoIn coeffs_in(const tr_lo_coeffs *in) {
   LoIn r{};
   r.kappa = in->kappa;
   r.B = in->B;
+  r.sgr = in->sigRc;
   r.f = in->f;
   r.fbnd = in->fbnd;
   r.sigE = in->sigE;
@@ -456,6 +463,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
         !P.x_edges || !P.nu_edges || !P.nu_center || !P.mu || !P.w || !P.C_cell)
       return TR_EINVAL;
     if (!(P.dt > 0) || !(P.cv > 0) || !(P.c > 0) || !(P.aR > 0)) return TR_EINVAL;
+    if (P.opacity != TR_OPAC_POINT && P.opacity != TR_OPAC_SPECTRAL) return TR_EINVAL;
     if (P.level_ng[0] != P.ng || P.level_ng[nlev - 1] != 1) return TR_EINVAL;
     for (int l = 1; l < nlev; ++l) {
       const int a = P.level_ng[l - 1], b = P.level_ng[l];
@@ -493,6 +501,8 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     S.nlev = nlev;
     for (int l = 0; l < nlev; ++l) S.lev_ng[l] = P.level_ng[l];
     S.nchunk = (P.ng + 63) / 64;
+    S.opac = P.opacity;
+    if (P.opacity == TR_OPAC_SPECTRAL) c->spectral = true;
     S.rtarget = std::max(16, 4096 / n_slab);
     S.cv = P.cv;
     S.dt = P.dt;
@@ -620,6 +630,13 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
       (rc = dalloc(c, &c->bnd, 6 * c->n_g)) || (rc = dalloc(c, &c->Phi, 2 * c->n_g)) ||
       (rc = dalloc(c, &c->Eold, c->n_gi)) || (rc = dalloc(c, &c->Fold, c->n_ge)) || (rc = dalloc(c, &c->red, c->n_red)) || (rc = dalloc(c, &c->dsop, c->n_dsop)))
     return fail(rc);
+  // sigma_R of spectral slabs has a table of its own; under the point law it
+  // is the kappa table (same addresses, no extra traffic)
+  if (c->spectral) {
+    if ((rc = dalloc(c, &c->sigR, c->n_gi))) return fail(rc);
+  } else {
+    c->sigR = c->kappa;
+  }
   double **cells[] = {&c->dS, &c->Told, &c->Ts, &c->Tcyc, &c->Tstar, &c->Tprev, &c->sigprev, &c->Ecyc, &c->Es};
   for (double **p : cells)
     if ((rc = dalloc(c, p, c->n_cell))) return fail(rc);
@@ -771,10 +788,12 @@ int tr_set_incoming(tr_ctx *c, int slab, const double *inc_left, const double *i
   return hip_err(hipMemcpy(c->d_inc, c->h_inc.data(), 8 * c->h_inc.size(), hipMemcpyHostToDevice));
 }
 
-int tr_opacity(tr_ctx *c, const double *T, double *kappa, double *B, double *dS, hipStream_t st) {
-  if (!c || !T || !kappa || !B) return TR_EINVAL;
+int tr_opacity(tr_ctx *c, const double *T, const double *Egrey, double *kappa, double *B, double *sigR, double *dS,
+               hipStream_t st) {
+  if (!c || !T || !kappa || !B || (c->spectral && !sigR)) return TR_EINVAL;
   LaunchEnv env = env_of(c, st);
-  launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, T, kappa, B, c->dSpart);
+  launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, T, kappa, B, c->dSpart, c->spectral, Egrey,
+                 sigR);
   if (dS) launch_dS_sum(env, c->t_dS, nullptr, PRED_ALL, 0, c->dSpart, dS);
   return hip_err(hipGetLastError());
 }
@@ -1074,6 +1093,32 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     }
     for (int q = 0; q < nsch; ++q) {
       const int gm = c->sched[q];
+      if (c->spectral) {
+        // group averages at the stage temperature and the radiation
+        // temperature of the grey E just solved, into the tables (the fine
+        // solve of this cycle is done with them; the end of the cycle
+        // evaluates them again at its final T), then the plain restriction;
+        // the stage-to-grey restriction reduces dS from the tables' partials
+        {
+          TimedScope ts(c, st, TR_T_OPACITY, l);
+          launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_CYCLE, l, c->Tstar, c->kappa, c->B, c->dSpart,
+                         true, s->Egrey, c->sigR);
+        }
+        {
+          TimedScope ts(c, st, TR_T_RESTRICT, l);
+          launch_restrict(env, c->t_red[std::make_pair(0, gm)], c->d_ctl, PRED_CYCLE, l, 0, gm, fine, fsol,
+                          level_out(c, gm), c->red, old);
+        }
+        {
+          TimedScope ts(c, st, TR_T_LO_COARSE, l);
+          launch_lo_all(c, env, c->d_ctl, PRED_CYCLE, l, gm, level_in(c, gm), level_sol(c, gm));
+        }
+        {
+          TimedScope ts(c, st, TR_T_RESTRICT, l);
+          launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
+                          level_sol(c, gm), grey_out(c), c->red, old);
+        }
+      } else {
       {
         // the stage's kappa, B at T* are evaluated inside the restriction
         // (not written to the tables), with the stage dS partials
@@ -1090,6 +1135,7 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
         launch_restrict(env, c->t_red[std::make_pair(gm, gl)], c->d_ctl, PRED_CYCLE, l, gm, gl, level_in(c, gm),
                         level_sol(c, gm), grey_out(c), c->red, old, 2, nullptr, c->dsop);
       }
+      }
       ga.end_cycle = q == nsch - 1;
       {
         TimedScope ts(c, st, TR_T_GREY, l);
@@ -1098,7 +1144,8 @@ void enqueue_iteration(tr_ctx *c, const tr_state *s, hipStream_t st, int Lmax, b
     }
     {
       TimedScope ts(c, st, TR_T_OPACITY, l);
-      launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart);
+      launch_opacity(env, c->t_opac, c->opac_run, c->d_ctl, PRED_DONECYC, l + 1, c->Tstar, c->kappa, c->B, c->dSpart,
+                     c->spectral, s->Egrey, c->sigR);
     }
   }
   // start of the next transport iteration (s + 1) for slabs still iterating
@@ -1175,7 +1222,7 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
   // Phi with the current incoming, the opacity tables at T
   launch_step_start(env, s->T, s->Egrey, s->E, s->F, c->n_cell, c->n_gi, c->n_ge, c->Told, c->Ts, c->Tcyc, c->Tstar,
                     c->Es, c->Ecyc, c->Eold, c->Fold, c->h_ctl_in, c->d_ctl, ns, c->t_g, s->C, c->Phi, c->t_opac,
-                    c->opac_run, c->kappa, c->B, c->dSpart);
+                    c->opac_run, c->kappa, c->B, c->dSpart, c->spectral, c->sigR);
   unsigned long long seed_counts[2] = {0, 0};
   if (c->mlp_params) {
     // learned closure: predicted cell factors replace the previous step's

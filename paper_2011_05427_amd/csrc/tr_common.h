@@ -14,6 +14,7 @@ struct SlabDev {
   int lev_ng[TR_MAXLEV];
   int nchunk;            // 64-group chunks of the fine grid (opacity partials)
   int rtarget;           // restriction chunk pass: blocks aimed at per slab
+  int opac;              // TR_OPAC_POINT / TR_OPAC_SPECTRAL
   double cv, dt, c, aR, inv_cdt;
   double wpos, wmupos, wmu2pos;  // half-range quadrature sums over mu > 0
   double wneg, wmuneg, wmu2neg;  // over mu < 0 (wmuneg < 0)

@@ -11,6 +11,7 @@ enum { PRED_ALL = 0, PRED_CYCLE = 1, PRED_DONECYC = 2, PRED_SWEEP = 3, PRED_ACTI
 // Coefficients of a level (fine: kappa/B/f/fbnd; coarse: level arrays).
 struct LoIn {
   const double *kappa, *B, *f, *fbnd;
+  const double *sgr;  // fine level: cell sigma_R table (spectral slabs); null: kappa
   const double *sigE, *emis, *a, *b, *sigR;
   const double *C, *Phi, *Eold, *Fold;
   // fine level, first cycle of an iteration with a sweep: the QD factors are
@@ -62,9 +63,13 @@ struct Table {
 };
 
 // run = 1 or 4 groups per thread; tab items = (slab, chunk * ncb + cell block)
-// with ncb = ceil(nx / (4 run)).
+// with ncb = ceil(nx / (4 run)).  spec: slabs with the spectral opacity model
+// get the group averages at (T, T_r from Eg; Eg null: T_r = T) and their
+// sigma_R in sgr; without spec every slab gets the point law and the group
+// Planck integrals (the initial state and the incoming radiation use B_g).
 void launch_opacity(const LaunchEnv &env, const Table &tab, int run, const Ctl *ctl, int pmode, int lcyc,
-                    const double *T, double *kappa, double *B, double *dSpart);
+                    const double *T, double *kappa, double *B, double *dSpart, bool spec = false,
+                    const double *Eg = nullptr, double *sgr = nullptr);
 // dS per cell from the chunk partials; tab items = (slab, first of 64 cells).
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
                    double *dS);
@@ -133,7 +138,8 @@ void launch_step_start(const LaunchEnv &env, const double *T, const double *Egre
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
                        double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
                        Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi, const Table &tab_op,
-                       int run, double *kappa, double *B, double *dSpart);
+                       int run, double *kappa, double *B, double *dSpart, bool spec = false,
+                       double *sgr = nullptr);
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n);
 void launch_fill(const LaunchEnv &env, double *dst, double v, long long n);
 void launch_init_state(const LaunchEnv &env, const Table &tab, bool f32, const double *Bt, void *I, double *E,

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstddef>
 
+#include "tr.h"
 #include "tr_device.h"
 #include "tr_kernels.h"
 
@@ -63,6 +64,66 @@ __device__ inline double planck_group(double nu, const EdgeQ &lo, const EdgeQ &h
   return 2.0 * (dkap * Bg + kap * dBg);
 }
 
+// Group averages of the spectral opacity sigma(nu, T) = Cc / nu^3 (1 -
+// e^{-nu/T}) over the group [a, b] (b may be +inf), paper Sec. 2 and Sec. 3.1:
+//  - src = sigma_B,g B_g = int sigma B(nu, T) dnu, closed form (the factor
+//    1 - e^{-nu/T} cancels the Planck denominator): Cc K T e^{-a/T} (1 -
+//    e^{-(b-a)/T}), K = a_R c / 2 / (pi^4 / 15); returns its dS term
+//    2 d(src)/dT = 2 Cc K e^{-a/T} ((1 + a/T)(1 - e^{-d}) - d e^{-d}), d = (b-a)/T;
+//  - sE = sigma_E,g(T, T_r), sR = sigma_R,g(T, T_r) from Gauss-Legendre
+//    panels (8 nodes) in y = nu / T_r over [a/T_r, min(b/T_r, max(a/T_r, 8) +
+//    64)]: panel width 1, or with rho = T_r / T > 1 min(1, max(1/rho, y/2))
+//    from the panel's start y.  The factor e^{-y rho} grows off the real axis
+//    at the rate rho, so panels close to y = 0 must be short on the scale
+//    1/rho and may grow geometrically away from it (their width then stays
+//    below half their distance to the imaginary axis, where the poles of
+//    1/(1 - e^{-y rho}) lie; those of 1/(1 - e^{-y}) are at 2 pi i k).  Both
+//    integrals of a ratio carry the common factor e^{a/T_r}, so no weight
+//    over- or underflows in the Wien tail.
+__device__ inline double spectral_group(double a, double b, double T, double Tr, double Cc, double K, double &sE,
+                                        double &src, double &sR) {
+  constexpr double gx[4] = {0.18343464249564978, 0.525532409916329, 0.7966664774136267, 0.9602898564975362};
+  constexpr double gw[4] = {0.36268378337836177, 0.31370664587788705, 0.22238103445337434, 0.10122853629037669};
+  const double iT = 1.0 / T;
+  const double xa = a * iT, d = (b - a) * iT;
+  const double ea = exp(-xa);
+  const double omd = -expm1(-d);  // 1 for the open group
+  src = Cc * K * T * ea * omd;
+  const double tl = isinf(d) ? 0.0 : d * exp(-d);
+  const double dS = 2.0 * Cc * K * ea * ((1.0 + xa) * omd - tl);
+  const double iTr = 1.0 / Tr, rho = Tr * iT;
+  const double ya = a * iTr;
+  const double ytop = fmin(b * iTr, fmax(ya, 8.0) + 64.0);
+  const double hs = rho > 1.0 ? 1.0 / rho : 1.0;
+  double nE = 0.0, dE = 0.0, nR = 0.0, dR = 0.0;
+  double y0 = ya;
+  for (int panel = 0; y0 < ytop && panel < 4096; ++panel) {
+    const double y1 = fmin(ytop, y0 + fmin(1.0, fmax(hs, 0.5 * y0)));
+    const double hm = 0.5 * (y1 - y0), cm = 0.5 * (y1 + y0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = q < 4 ? 3 - q : q - 4;
+      const double y = cm + (q < 4 ? -hm : hm) * gx[k];
+      const double wq = hm * gw[k];
+      const double e1 = exp(ya - y);
+      const double io = 1.0 / (-expm1(-y));
+      const double oz = -expm1(-y * rho);
+      const double y3 = y * y * y;
+      const double bw = e1 * io;           // B(nu, T_r) e^{a/T_r} / (K T_r^3 y^3)
+      const double rw = y3 * y * bw * io;  // dB/dT'(nu, T_r) e^{a/T_r} / (K T_r^2)
+      nE += wq * oz * bw;
+      dE += wq * y3 * bw;
+      nR += wq * rw;
+      dR += wq * rw * y3 / oz;
+    }
+    y0 = y1;
+  }
+  const double sc = Cc * iTr * iTr * iTr;
+  sE = sc * nE / dE;
+  sR = sc * nR / dR;
+  return dS;
+}
+
 // ---------------------------------------------------------------------------
 // A1: opacity and group Planck tables at T, with the 64-group chunk partial
 // sums of dS = d/dT sum_g 2 kappa_g B_g.  Block = one 64-group chunk x 4 RUN
@@ -72,10 +133,14 @@ __device__ inline double planck_group(double nu, const EdgeQ &lo, const EdgeQ &h
 // ones.  The 64 / RUN run sums of a cell are added in LDS in a fixed order.
 // ---------------------------------------------------------------------------
 // One block (256 threads) of the opacity work: work item `it`.
-template <int RUN>
+// SPEC: slabs of the spectral model get the group averages at (T, T_r =
+// (Eg / a_R)^(1/4); Eg null: T_r = T) with sigma_R in sgr (one group per step:
+// the panel sums do not share edge work).
+template <int RUN, bool SPEC>
 __device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbDev &pd, const Item it, const Ctl *ctl,
                                      int pmode, int lcyc, const double *__restrict__ T, double *__restrict__ kappa,
-                                     double *__restrict__ B, double *__restrict__ dSpart) {
+                                     double *__restrict__ B, double *__restrict__ dSpart,
+                                     const double *__restrict__ Eg = nullptr, double *__restrict__ sgr = nullptr) {
   constexpr int CB = 4 * RUN, NR = 64 / RUN;  // cells per block, runs per chunk
   __shared__ double part[NR][CB + 1];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
@@ -95,18 +160,31 @@ __device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbD
     const double scale = S.aR * S.c * T2 * T2 * 0.5 / TR_PI4_15;
     const double *nue = pd.nu_e + S.o_nu;
     const double *nuc = pd.nu_c + S.o_g;
-    EdgeQ lo = edge_q(nue[g0], iT);
+    if (SPEC && S.opac == TR_OPAC_SPECTRAL) {
+      const double Tr = Eg ? sqrt(sqrt(fmax(Eg[S.o_cell + i], 1e-300) / S.aR)) : Ti;
+      const double K = S.aR * S.c * 0.5 / TR_PI4_15;
+      for (int g = g0; g < g1; ++g) {
+        double sE, src, sR;
+        dS += spectral_group(nue[g], nue[g + 1], Ti, Tr, Cc, K, sE, src, sR);
+        const long long o = S.o_gi + (long long)g * nx + i;
+        kappa[o] = sE;
+        B[o] = src / sE;
+        sgr[o] = sR;
+      }
+    } else {
+      EdgeQ lo = edge_q(nue[g0], iT);
 #pragma unroll
-    for (int q = 0; q < RUN; ++q) {
-      const int g = g0 + q;
-      if (g >= g1) break;
-      const EdgeQ hi = edge_q(nue[g + 1], iT);
-      double kap, Bg;
-      dS += planck_group(nuc[g], lo, hi, iT, Cc, scale, kap, Bg);
-      const long long o = S.o_gi + (long long)g * nx + i;
-      kappa[o] = kap;
-      B[o] = Bg;
-      lo = hi;
+      for (int q = 0; q < RUN; ++q) {
+        const int g = g0 + q;
+        if (g >= g1) break;
+        const EdgeQ hi = edge_q(nue[g + 1], iT);
+        double kap, Bg;
+        dS += planck_group(nuc[g], lo, hi, iT, Cc, scale, kap, Bg);
+        const long long o = S.o_gi + (long long)g * nx + i;
+        kappa[o] = kap;
+        B[o] = Bg;
+        lo = hi;
+      }
     }
   }
   part[run][cl] = dS;
@@ -127,12 +205,13 @@ __device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbD
   }
 }
 
-template <int RUN>
+template <int RUN, bool SPEC>
 __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd, ProbDev pd,
                                                  const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
                                                  const double *__restrict__ T, double *__restrict__ kappa,
-                                                 double *__restrict__ B, double *__restrict__ dSpart) {
-  opacity_block<RUN>(sd, pd, tab[blockIdx.x], ctl, pmode, lcyc, T, kappa, B, dSpart);
+                                                 double *__restrict__ B, double *__restrict__ dSpart,
+                                                 const double *__restrict__ Eg, double *__restrict__ sgr) {
+  opacity_block<RUN, SPEC>(sd, pd, tab[blockIdx.x], ctl, pmode, lcyc, T, kappa, B, dSpart, Eg, sgr);
 }
 
 // Sums the 64-group chunk partials of dS for every cell.  Block = 64 cells
@@ -631,8 +710,8 @@ __device__ inline void phi_groups(const SlabDev *__restrict__ sd, const ProbDev 
 struct LevelView {
   int nx;
   const double *dx;
-  // fine
-  const double *kap, *Bt, *f, *fbnd;
+  // fine (sgr: cell sigma_R, the kappa table under the point law)
+  const double *kap, *Bt, *f, *fbnd, *sgr;
   // coarse
   const double *sigE, *emis, *a, *b, *sigR;
   // both
@@ -652,11 +731,11 @@ __device__ inline void lv_edge(const LevelView &v, int e, double &ae, double &be
     ae = (e < nx) ? v.f[e] : v.fbnd[1];
     be = (e > 0) ? v.f[e - 1] : v.fbnd[0];
     if (e == 0)
-      sr = v.kap[0];
+      sr = v.sgr[0];
     else if (e == nx)
-      sr = v.kap[nx - 1];
+      sr = v.sgr[nx - 1];
     else
-      sr = (v.kap[e - 1] * v.dx[e - 1] + v.kap[e] * v.dx[e]) / (v.dx[e - 1] + v.dx[e]);
+      sr = (v.sgr[e - 1] * v.dx[e - 1] + v.sgr[e] * v.dx[e]) / (v.dx[e - 1] + v.dx[e]);
   } else {
     ae = v.a[e];
     be = v.b[e];
@@ -726,7 +805,8 @@ __device__ inline void lo_load(const LevelView &v, RowData<K> &R, const FacSrc *
     R.h[q] = in ? 0.5 * (dxm + dxe) : 1.0;
     R.Fo[q] = buf_load_f64(r_Fo, e * 8);
     if (FINE) {
-      const __amdgpu_buffer_rsrc_t r_f = buf_rsrc(v.f, cb), r_k = buf_rsrc(v.kap, cb);
+      // cell sigma_R of the edge's two cells (the kappa table under the point law)
+      const __amdgpu_buffer_rsrc_t r_f = buf_rsrc(v.f, cb), r_k = buf_rsrc(v.sgr, cb);
       const double fe = MOM ? fc[q + 1] : buf_load_f64(r_f, e * 8);
       const double fm = MOM ? fc[q] : buf_load_f64(r_f, (e - 1) * 8);
       const double ke = buf_load_f64(r_k, e * 8), km = buf_load_f64(r_k, (e - 1) * 8);
@@ -862,6 +942,7 @@ __device__ inline LevelView make_view(const SlabDev &S, ProbDev pd, int level, c
   if (FINE) {
     const long long gi = S.o_gi + (long long)p * nx, g2 = 2 * S.o_g + 2 * p;
     v.kap = in.kappa + gi;
+    v.sgr = (in.sgr ? in.sgr : in.kappa) + gi;
     v.Bt = in.B + gi;
     v.f = in.f + gi;
     v.fbnd = in.fbnd + g2;
@@ -883,7 +964,7 @@ __device__ inline LevelView make_view(const SlabDev &S, ProbDev pd, int level, c
     v.Phi = in.Phi + p2;
     v.Eold = in.Eold + pi;
     v.Fold = in.Fold + pe;
-    v.kap = v.Bt = v.f = v.fbnd = nullptr;
+    v.kap = v.Bt = v.f = v.fbnd = v.sgr = nullptr;
   }
   return v;
 }
@@ -1047,11 +1128,23 @@ __device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, co
   if (FINE) {
     const long long gi = S.o_gi + (long long)g * nx, ge = S.o_ge + (long long)g * (nx + 1);
     const long long g2 = 2 * S.o_g + 2 * (long long)g;
+    double sre, srm;  // cell sigma_R right / left of the edge
     if (MODE != RM_OPAC) {
       const __amdgpu_buffer_rsrc_t rk = buf_rsrc(in.kappa + gi, cb), rb = buf_rsrc(in.B + gi, cb);
       ke = buf_load_f64(rk, oe);
       km = buf_load_f64(rk, om);
       Be = buf_load_f64(rb, oe);
+      if (in.sgr && in.sgr != in.kappa) {  // spectral slabs: a table of its own
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(in.sgr + gi, cb);
+        sre = buf_load_f64(rs, oe);
+        srm = buf_load_f64(rs, om);
+      } else {
+        sre = ke;
+        srm = km;
+      }
+    } else {
+      sre = ke;
+      srm = km;
     }
     const __amdgpu_buffer_rsrc_t rf = buf_rsrc(in.f + gi, cb), rE = buf_rsrc(sol.E + gi, cb);
     const __amdgpu_buffer_rsrc_t rF = buf_rsrc(sol.F + ge, eb);
@@ -1075,7 +1168,7 @@ __device__ inline void load_group(const SlabDev &S, int from, const LoIn &in, co
     // so that every load is used on every lane (no branch around a load)
     v.ae = fe + (e == nx ? fb1 : 0.0);
     v.be = fm + (e == 0 ? fb0 : 0.0);
-    v.sr = m * (km * q.wm + ke * q.we);
+    v.sr = m * (srm * q.wm + sre * q.we);
     v.ER = Ee + (e == nx ? v.Eb1 : 0.0);
     v.EL = Em + (e == 0 ? v.Eb0 : 0.0);
   } else {
@@ -1705,13 +1798,16 @@ struct StepCopies {
   double *Phi;
   const Item *tab_op;
   double *kappa, *B, *dSpart;
+  double *sgr;  // sigma_R table of spectral slabs (SPEC)
 };
 
-template <int RUN>
+template <int RUN, bool SPEC>
 __global__ __launch_bounds__(256) void k_step_start(StepCopies a) {
   if (blockIdx.x >= a.phi_end) {
-    opacity_block<RUN>(a.sd, a.pd, a.tab_op[blockIdx.x - a.phi_end], nullptr, PRED_ALL, 0, a.T, a.kappa, a.B,
-                       a.dSpart);
+    // the group averages of spectral slabs at the radiation temperature of
+    // the state's grey energy density (read here, copied by other blocks)
+    opacity_block<RUN, SPEC>(a.sd, a.pd, a.tab_op[blockIdx.x - a.phi_end], nullptr, PRED_ALL, 0, a.T, a.kappa, a.B,
+                             a.dSpart, a.Egrey, a.sgr);
     return;
   }
   if (blockIdx.x >= a.copy_blocks) {
@@ -1925,14 +2021,18 @@ __global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, d
 static inline dim3 blocks(int n) { return dim3((unsigned)n); }
 
 void launch_opacity(const LaunchEnv &env, const Table &tab, int run, const Ctl *ctl, int pmode, int lcyc,
-                    const double *T, double *kappa, double *B, double *dSpart) {
+                    const double *T, double *kappa, double *B, double *dSpart, bool spec, const double *Eg,
+                    double *sgr) {
   if (tab.n == 0) return;
-  if (run == 1)
-    hipLaunchKernelGGL(k_opacity<1>, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, lcyc,
-                       T, kappa, B, dSpart);
-  else
-    hipLaunchKernelGGL(k_opacity<4>, blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, lcyc,
-                       T, kappa, B, dSpart);
+#define TR_OP(R, SP)                                                                                                 \
+  hipLaunchKernelGGL((k_opacity<R, SP>), blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, \
+                     lcyc, T, kappa, B, dSpart, Eg, sgr)
+  if (spec) {
+    if (run == 1) TR_OP(1, true); else TR_OP(4, true);
+  } else {
+    if (run == 1) TR_OP(1, false); else TR_OP(4, false);
+  }
+#undef TR_OP
 }
 
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
@@ -2051,20 +2151,27 @@ void launch_step_start(const LaunchEnv &env, const double *T, const double *Egre
                        long long n_cell, long long n_gi, long long n_ge, double *Told, double *Ts, double *Tcyc,
                        double *Tstar, double *Es, double *Ecyc, double *Eold, double *Fold, const Ctl *ctl_in,
                        Ctl *ctl, int nslab, const Table &tab_g, const double *C, double *Phi, const Table &tab_op,
-                       int run, double *kappa, double *B, double *dSpart) {
+                       int run, double *kappa, double *B, double *dSpart, bool spec, double *sgr) {
   const long long n_ctl = (long long)nslab * (long long)(sizeof(Ctl) / sizeof(int));
   const long long n = std::max(std::max(n_cell, n_ctl), std::max(n_gi, n_ge));
   const unsigned copy_blocks = (unsigned)((n + 255) / 256), phi_end = copy_blocks + (unsigned)tab_g.n;
   const StepCopies a{T,       Egrey,  E,       F,      Told,        Ts,
                      Tcyc,    Tstar,  Es,      Ecyc,   Eold,        Fold,
                      n_cell,  n_gi,   n_ge,    reinterpret_cast<const int *>(ctl_in), reinterpret_cast<int *>(ctl), n_ctl,
-                     copy_blocks, phi_end, env.sd, env.pd, tab_g.d, C, Phi, tab_op.d, kappa, B, dSpart};
+                     copy_blocks, phi_end, env.sd, env.pd, tab_g.d, C, Phi, tab_op.d, kappa, B, dSpart, sgr};
   const unsigned nb = phi_end + (unsigned)tab_op.n;
   if (nb == 0) return;
-  if (run == 1)
-    hipLaunchKernelGGL(k_step_start<1>, dim3(nb), dim3(256), 0, env.stream, a);
-  else
-    hipLaunchKernelGGL(k_step_start<4>, dim3(nb), dim3(256), 0, env.stream, a);
+  if (spec) {
+    if (run == 1)
+      hipLaunchKernelGGL((k_step_start<1, true>), dim3(nb), dim3(256), 0, env.stream, a);
+    else
+      hipLaunchKernelGGL((k_step_start<4, true>), dim3(nb), dim3(256), 0, env.stream, a);
+  } else {
+    if (run == 1)
+      hipLaunchKernelGGL((k_step_start<1, false>), dim3(nb), dim3(256), 0, env.stream, a);
+    else
+      hipLaunchKernelGGL((k_step_start<4, false>), dim3(nb), dim3(256), 0, env.stream, a);
+  }
 }
 
 void launch_copy(const LaunchEnv &env, const double *src, double *dst, long long n) {

@@ -36,6 +36,11 @@ C_LIGHT = 29.9792458  # cm / ns
 A_RAD = 0.01372  # GJ / (cm^3 keV^4)
 
 CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
+# Opacity model of a slab: the point law kappa_g(T) = C / nu_c^3 (1 - exp(-nu_c / T))
+# at the group centre for sigma_E = sigma_B = sigma_R, or the paper's group
+# averages (Planck-weighted sigma_B,g at T, sigma_E,g at T and the radiation
+# temperature, Rosseland sigma_R,g) of the spectral law C / nu^3 (1 - exp(-nu / T)).
+OPAC_POINT, OPAC_SPECTRAL = 0, 1
 _CYCLE_NAMES = {"V": CYCLE_V, "W": CYCLE_W, "F": CYCLE_F}
 
 
@@ -56,6 +61,7 @@ class Slab:
     T0: float
     c: float = C_LIGHT
     aR: float = A_RAD
+    opacity: int = 0  # OPAC_POINT / OPAC_SPECTRAL
 
     @property
     def nx(self) -> int:
@@ -106,14 +112,14 @@ def log_groups(ng: int, lo: float, hi: float):
 def make_slab(nx: int, ng: int, nmu: int, *, C1: float = 27.0, C2: float = 2.7,
               X: float = 4.0, nu_lo: float = 0.01, nu_hi: float = 100.0,
               T_left: float = 1.0, T_right: float = 0.0, cv: float = 0.5,
-              dt: float = 0.002, T0: float = 0.001) -> Slab:
+              dt: float = 0.002, T0: float = 0.001, opacity: int = OPAC_POINT) -> Slab:
     """Two-zone slab: cells [0, nx//2) use C1, the rest C2."""
     x = np.linspace(0.0, X, nx + 1)
     edges, centre = log_groups(ng, nu_lo, nu_hi)
     mu, w = gauss_legendre(nmu)
     C = np.where(np.arange(nx) < nx // 2, C1, C2).astype(np.float64)
     return Slab(x_edges=x, nu_edges=edges, nu_center=centre, mu=mu, w=w, C_cell=C,
-                T_left=T_left, T_right=T_right, cv=cv, dt=dt, T0=T0)
+                T_left=T_left, T_right=T_right, cv=cv, dt=dt, T0=T0, opacity=opacity)
 
 
 def double_gauss_legendre(n: int):
@@ -131,28 +137,30 @@ def double_gauss_legendre(n: int):
 FC_DT = (0.02, 0.04)  # ns: the two time steps of the Fleck-Cummings runs (150 and 75 steps to 3 ns)
 
 
-def fc_slab(dt: float = 0.02) -> Slab:
+def fc_slab(dt: float = 0.02, opacity: int = OPAC_SPECTRAL) -> Slab:
     """The paper's Fleck-Cummings set-up (Sec. 6): [0, 4] cm in 10 uniform
-    cells, one material (C = 27), black-body incoming at 1 keV on the left,
-    vacuum on the right, T0 = 1e-3 keV, c_v = 0.5917 a_R T_b^3 with T_b = 1
-    keV, 256 groups: 254 log-spaced between 1e-4 and 10 keV and the two end
-    groups [0, 1e-4] and [10, inf) (the paper's 1e7 keV bound carries no
-    Planck energy in binary64), double S8.  The end groups' opacity centres
-    extend the log spacing by one ratio (reading: the paper averages over
-    the spectrum, this build evaluates kappa at a group centre)."""
+    cells, one material with the spectral opacity 27 / nu^3 (1 - exp(-nu / T)),
+    black-body incoming at 1 keV on the left, vacuum on the right, T0 = 1e-3
+    keV, c_v = 0.5917 a_R T_b^3 with T_b = 1 keV, 256 groups: 254 log-spaced
+    between 1e-4 and 10 keV and the two end groups [0, 1e-4] and [10, inf)
+    (the paper's 1e7 keV bound carries no Planck energy in binary64), double
+    S8.  The group opacities are the paper's spectral averages (default) or,
+    with opacity=OPAC_POINT, the point law at a group centre; the end groups'
+    centres (point law only) extend the log spacing by one ratio."""
     r = (10.0 / 1e-4) ** (1.0 / 254)
     x = np.linspace(0.0, 4.0, 11)
     edges, centre = log_groups(256, 1e-4 / r, 10.0 * r)
     mu, w = double_gauss_legendre(8)
     return Slab(x_edges=x, nu_edges=edges, nu_center=centre, mu=mu, w=w, C_cell=np.full(10, 27.0),
-                T_left=1.0, T_right=0.0, cv=0.5917 * A_RAD, dt=dt, T0=0.001)
+                T_left=1.0, T_right=0.0, cv=0.5917 * A_RAD, dt=dt, T0=0.001, opacity=opacity)
 
 
-def config_fc(dt: float = 0.02, levels=(256, 1), cycle: int = CYCLE_V, lmax: int = 4):
+def config_fc(dt: float = 0.02, levels=(256, 1), cycle: int = CYCLE_V, lmax: int = 4,
+              opacity: int = OPAC_SPECTRAL):
     """Fleck-Cummings runs of Tables 1 (dt = 0.02 ns) and 2 (0.04 ns): eps =
     1e-6, inner eps = 1e-7, to t = 3 ns."""
     cfg = SolverCfg(levels=list(levels), cycle=cycle, lmax=lmax, eps=1e-6, eps_inner=1e-7)
-    return [fc_slab(dt)], cfg, int(round(3.0 / dt))
+    return [fc_slab(dt, opacity)], cfg, int(round(3.0 / dt))
 
 
 def config_small():

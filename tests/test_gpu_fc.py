@@ -1,6 +1,7 @@
 """GPU parity on the paper's Fleck-Cummings set-up (10 cells, 256 groups,
-double S8, eps = 1e-6): steps of three of the Tables 1-2 algorithms replayed
-against the oracle (1e-10), and free-running steps reaching the oracle's
+double S8, eps = 1e-6, the group averages of the spectral opacity): steps of
+three of the Tables 1-2 algorithms replayed against the oracle (1e-10), one
+with the point opacity law, and free-running steps reaching the oracle's
 iteration counts."""
 import pytest
 
@@ -16,12 +17,13 @@ ROWS = [(0.02, [256, 32, 1], inputs.CYCLE_W, 2), (0.02, [256, 32, 16, 4, 1], inp
         (0.04, [256, 1], inputs.CYCLE_V, 6)]
 
 
-@pytest.mark.parametrize("row", range(len(ROWS)))
-def test_fc_steps_replay_the_oracle(row):
+@pytest.mark.parametrize("row,opac", [(0, inputs.OPAC_SPECTRAL), (1, inputs.OPAC_SPECTRAL),
+                                      (2, inputs.OPAC_SPECTRAL), (1, inputs.OPAC_POINT)])
+def test_fc_steps_replay_the_oracle(row, opac):
     dt, levels, cyc, lmax = ROWS[row]
-    slabs, cfg, _ = inputs.config_fc(dt, levels, cyc, lmax)
+    slabs, cfg, _ = inputs.config_fc(dt, levels, cyc, lmax, opacity=opac)
     s = slabs[0]
-    note(f"FC dt={dt} grids={levels} cycle={'VWF'[cyc]} lmax={lmax}")
+    note(f"FC dt={dt} grids={levels} cycle={'VWF'[cyc]} lmax={lmax} opacity={'point spectral'.split()[opac]}")
     pb = mlqd.problem_from_slab(s)
     ost = mlqd.initial_state(pb, s.T0)
     sv = binding.Solver(slabs, [levels], cfg)
@@ -32,7 +34,7 @@ def test_fc_steps_replay_the_oracle(row):
         ost = mlqd.step(pb, levels, mlqd.schedule(len(levels), cfg.cycle), lmax, cfg.eps, cfg.eps_inner, ost, stats=stats)
         gs = sv.step(st, replay=[stats.counts[0]])
         assert gs[0].n_lo == stats.n_lo
-        _compare_state(f"FC row {row} step {j}", sv, st, ost)
+        _compare_state(f"FC row {row} opacity {opac} step {j}", sv, st, ost)
     sv.close()
 
 
@@ -40,7 +42,7 @@ def test_fc_free_running_counts_match_the_oracle():
     dt, levels, cyc, lmax = ROWS[1]
     slabs, cfg, _ = inputs.config_fc(dt, levels, cyc, lmax)
     s = slabs[0]
-    note("FC free run, F cycle, 3 steps")
+    note("FC free run, F cycle, spectral opacities, 3 steps")
     pb = mlqd.problem_from_slab(s)
     ost = mlqd.initial_state(pb, s.T0)
     stats = mlqd.Stats()

@@ -11,7 +11,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from oracle import lo, planck
+from oracle import lo, opacity, planck
 from oracle.moments import Factors, factors
 from oracle.restrict import restrict
 from oracle.sweep import sweep
@@ -52,6 +52,35 @@ def test_opacity_tables(nx, ng):
     sv.close()
 
 
+@pytest.mark.parametrize("nx,ng,lo_nu,hi_nu", [(13, 40, 1e-4, 10.0), (300, 6, 0.01, 100.0), (2, 1, 0.01, 100.0)])
+def test_spectral_opacity_tables(nx, ng, lo_nu, hi_nu):
+    """Group averages of the spectral opacity (sigma_E,g at the radiation
+    temperature, emission sigma_B,g B_g = kappa B, Rosseland sigma_R,g) and
+    dS against the oracle's quadratures of the definitions, over radiation
+    temperatures from far below to far above the material temperature."""
+    note(f"spectral opacity nx={nx} ng={ng} nu in [{lo_nu}, {hi_nu}]")
+    slab = inputs.make_slab(nx, ng, 2, nu_lo=lo_nu, nu_hi=hi_nu, opacity=inputs.OPAC_SPECTRAL)
+    rng = np.random.default_rng(nx + ng)
+    T = 10 ** rng.uniform(-3, np.log10(1.5), nx)
+    Tr = T * 10 ** rng.uniform(-2, 2.5, nx)
+    Tr = np.clip(Tr, 1e-4, 3.0)
+    Eg = slab.aR * Tr ** 4
+    sv = _solver(slab, [ng, 1])
+    kap, B, sR, dS = sv.empty(K.TR_K_GI), sv.empty(K.TR_K_GI), sv.empty(K.TR_K_GI), sv.empty(K.TR_K_CELL)
+    sv.opacity(to_dev(T), kap, B, dS, Egrey=to_dev(Eg), sigR=sR)
+    Tr_ref = opacity.radiation_temperature(Eg, slab.aR)
+    sE_ref, src_ref, sR_ref = opacity.spectral_tables(slab.nu_edges, slab.C_cell, T, Tr_ref, slab.aR, slab.c)
+    dS_ref = 2 * opacity.emission_dT(slab.nu_edges, slab.C_cell, T, slab.aR, slab.c).sum(axis=0)
+    k = to_np(kap, (ng, nx))
+    assert_close("sigma_E", k, sE_ref, 1e-12, atol_scale=0.0)
+    assert_close("sigma_R", to_np(sR, (ng, nx)), sR_ref, 1e-12, atol_scale=0.0)
+    src = k * to_np(B, (ng, nx))
+    ok = np.abs(src - src_ref) <= 1e-12 * np.abs(src_ref) + 1e-300
+    assert ok.all(), f"emission mismatch at {np.argwhere(~ok)[0]}"
+    assert_close("dS", to_np(dS), dS_ref, 1e-12, atol_scale=0.0)
+    sv.close()
+
+
 @pytest.mark.parametrize("nx,ng,nmu", [(2, 3, 2), (50, 5, 8), (300, 4, 16), (700, 3, 32), (257, 2, 8)])
 def test_sweep_and_moments(nx, ng, nmu):
     note(f"sweep nx={nx} ng={ng} nmu={nmu}")
@@ -86,9 +115,12 @@ def _random_factors(rng, ng, nx):
                    Phi=np.stack([rng.uniform(0, 2, ng), -rng.uniform(0, 0.1, ng)], axis=1))
 
 
-@pytest.mark.parametrize("nx,ng", [(2, 1), (7, 3), (200, 2), (1000, 2), (2046, 1)])
-def test_lo_fine(nx, ng):
-    note(f"lo fine nx={nx} ng={ng}")
+@pytest.mark.parametrize("nx,ng,sepR", [(2, 1, False), (7, 3, False), (200, 2, False), (1000, 2, False),
+                                        (2046, 1, False), (7, 3, True), (513, 2, True)])
+def test_lo_fine(nx, ng, sepR):
+    """sepR: a Rosseland table of its own (the group averages of the spectral
+    opacity) instead of kappa for the edge opacities."""
+    note(f"lo fine nx={nx} ng={ng} separate sigma_R={sepR}")
     slab, _ = slab_case(nx, ng, 2)
     rng = np.random.default_rng(nx * 7 + ng)
     kap = 10 ** rng.uniform(-2, 4, (ng, nx))
@@ -97,11 +129,14 @@ def test_lo_fine(nx, ng):
     Eold = rng.uniform(0, 1, (ng, nx))
     Fold = rng.uniform(-0.5, 0.5, (ng, nx + 1))
     dx = np.diff(slab.x_edges)
-    ref = lo.solve_level(lo.fine_level(kap, B, fac, Eold, Fold, dx), dx, slab.c, slab.dt)
+    sR = kap * 10 ** rng.uniform(-1, 1, (ng, nx)) if sepR else None
+    ref = lo.solve_level(lo.fine_level(kap, B, fac, Eold, Fold, dx, sigR=sR), dx, slab.c, slab.dt)
     sv = _solver(slab, [ng, 1])
     E, F, Eb = sv.empty(K.TR_K_GI), sv.empty(K.TR_K_GE), sv.empty(K.TR_K_G2)
     co = dict(kappa=to_dev(kap), B=to_dev(B), f=to_dev(fac.f), fbnd=to_dev(fac.f_bnd), C=to_dev(fac.C),
               Phi=to_dev(fac.Phi), Eold=to_dev(Eold), Fold=to_dev(Fold))
+    if sepR:
+        co["sigRc"] = to_dev(sR)
     sv.lo_solve(0, co, E, F, Eb)
     assert_close("E", to_np(E, (ng, nx)), ref.E, 1e-12)
     assert_close("Ebnd", to_np(Eb, (ng, 2)), ref.Ebnd, 1e-12)
@@ -158,9 +193,10 @@ def _cmp_level(name, out, ref, P, nx, Esum_ref):
     assert_close(f"{name}.Esum", to_np(out["Esum"], (P, nx)), Esum_ref, 1e-12)
 
 
-@pytest.mark.parametrize("ng,P,nx", [(16, 4, 11), (256, 2, 9), (128, 1, 300), (260, 2, 5)])
-def test_restriction(ng, P, nx):
-    note(f"restrict ng={ng} P={P} nx={nx}")
+@pytest.mark.parametrize("ng,P,nx,sepR", [(16, 4, 11, False), (256, 2, 9, False), (128, 1, 300, False),
+                                          (260, 2, 5, False), (16, 4, 11, True), (256, 2, 9, True)])
+def test_restriction(ng, P, nx, sepR):
+    note(f"restrict ng={ng} P={P} nx={nx} separate sigma_R={sepR}")
     levels = [ng, P, 1] if P > 1 else [ng, 1]
     slab, _ = slab_case(nx, ng, 2)
     rng = np.random.default_rng(ng + P + nx)
@@ -170,11 +206,14 @@ def test_restriction(ng, P, nx):
     fac = _random_factors(rng, ng, nx)
     Eold = rng.uniform(0, 1, (ng, nx))
     Fold = rng.uniform(-0.5, 0.5, (ng, nx + 1))
-    fine = lo.fine_level(kap, B, fac, Eold, Fold, dx)
+    sR = kap * 10 ** rng.uniform(-1, 1, (ng, nx)) if sepR else None
+    fine = lo.fine_level(kap, B, fac, Eold, Fold, dx, sigR=sR)
     fs = lo.solve_level(fine, dx, slab.c, slab.dt)
     sv = _solver(slab, levels)
     co = dict(kappa=to_dev(kap), B=to_dev(B), f=to_dev(fac.f), fbnd=to_dev(fac.f_bnd), C=to_dev(fac.C),
               Phi=to_dev(fac.Phi), Eold=to_dev(Eold), Fold=to_dev(Fold))
+    if sepR:
+        co["sigRc"] = to_dev(sR)
     sol = dict(E=to_dev(fs.E), F=to_dev(fs.F), Ebnd=to_dev(fs.Ebnd))
     lev = 1
     out = _level_out(sv, lev)

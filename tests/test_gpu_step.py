@@ -61,9 +61,15 @@ def _compare_state(tag, sv, st, ref, slab_idx=0):
 
 
 @pytest.mark.parametrize("case", ["small_V", "W3", "F4", "W_r32", "vacuum_both", "two_cells_S2", "max_cells",
-                                  "thin", "thick"])
+                                  "thin", "thick", "spectral_V", "spectral_W", "spectral_F"])
 def test_step_replay(case):
-    if case == "small_V":
+    if case.startswith("spectral"):  # the paper's group averages of the spectral opacity
+        slab = inputs.make_slab(20, 16, 8, dt=0.004, nu_lo=1e-3, nu_hi=30.0, opacity=inputs.OPAC_SPECTRAL)
+        cyc = {"V": inputs.CYCLE_V, "W": inputs.CYCLE_W, "F": inputs.CYCLE_F}[case[-1]]
+        levels = {"V": [16, 1], "W": [16, 4, 1], "F": [16, 8, 2, 1]}[case[-1]]
+        cfg = inputs.SolverCfg(levels=levels, cycle=cyc, lmax=2)
+        nsteps = 2
+    elif case == "small_V":
         slabs, cfg, nsteps = inputs.config_small()
         slab, levels = slabs[0], cfg.levels
         nsteps = 2

@@ -84,24 +84,31 @@ def test_tridiagonal_matches_dense(nx):
     assert max(res) < 1e-12
 
 
-def _fine_from_physics(rng, G, nx, dx):
+def _fine_from_physics(rng, G, nx, dx, separate_sigR=False):
     """A fine level built like the solver builds it: cell factors, point
-    opacities, emission 2 kappa B, dx-weighted edge opacity."""
+    opacities, emission 2 kappa B, dx-weighted edge opacity (or, with
+    separate_sigR, a Rosseland opacity and an emission of their own, as the
+    group averages of a spectral opacity give)."""
     from oracle.moments import Factors
     kappa = 10 ** rng.uniform(-2, 4, (G, nx))
     B = rng.uniform(0.0, 1.0, (G, nx))
     fac = Factors(f=rng.uniform(0.25, 0.5, (G, nx)), f_bnd=rng.uniform(0.25, 0.6, (G, 2)),
                   C=np.stack([-rng.uniform(0.4, 0.6, G), rng.uniform(0.4, 0.6, G)], axis=1),
                   Phi=np.stack([rng.uniform(0, 2, G), np.zeros(G)], axis=1))
-    return lo.fine_level(kappa, B, fac, rng.uniform(0, 1, (G, nx)), rng.uniform(-0.5, 0.5, (G, nx + 1)), dx)
+    Eo, Fo = rng.uniform(0, 1, (G, nx)), rng.uniform(-0.5, 0.5, (G, nx + 1))
+    if separate_sigR:
+        return lo.fine_level(kappa, B, fac, Eo, Fo, dx, emis=rng.uniform(0, 2, (G, nx)) * kappa,
+                             sigR=kappa * 10 ** rng.uniform(-1, 1, (G, nx)))
+    return lo.fine_level(kappa, B, fac, Eo, Fo, dx)
 
 
-@pytest.mark.parametrize("G,P", [(16, 4), (16, 1), (32, 8), (12, 3)])
-def test_restriction_is_exact_projection(G, P):
+@pytest.mark.parametrize("G,P,sepR", [(16, 4, False), (16, 1, False), (32, 8, False), (12, 3, False),
+                                      (16, 4, True), (12, 1, True)])
+def test_restriction_is_exact_projection(G, P, sepR):
     rng = np.random.default_rng(G * 100 + P)
     nx = 9
     dx = rng.uniform(0.05, 0.2, nx)
-    fine = _fine_from_physics(rng, G, nx, dx)
+    fine = _fine_from_physics(rng, G, nx, dx, sepR)
     fs = lo.solve_level(fine, dx, C, 0.004)
     coarse = restrict(fine, fs, P, dx, C)
     cs = lo.solve_level(coarse, dx, C, 0.004)

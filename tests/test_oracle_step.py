@@ -247,3 +247,36 @@ def test_secant_pairs_consecutive_grey_stages(monkeypatch, levels, sched):
         assert np.all(D[~live] == 0.0)
         checked += np.count_nonzero(live)
     assert checked >= 24
+
+
+@pytest.mark.parametrize("levels,sched", [([8, 1], []), ([8, 4, 1], [1]), ([8, 4, 2, 1], [2, 1])])
+def test_multigrid_matches_single_grid_with_group_averaged_opacities(levels, sched):
+    """With the paper's group opacities (sigma_B,g, sigma_E,g at the radiation
+    temperature, Rosseland sigma_R,g of the spectral law) the V, W and F
+    cycles still reach the solution of the single-grid method (Alg. 1)."""
+    slab, pb = tiny_problem(nx=6, ng=8, nmu=4, dt=0.004, T0=0.01, C1=4.0, C2=1.0,
+                            opacity=inputs.OPAC_SPECTRAL)
+    assert pb.opacity == 1
+    st0 = mlqd.initial_state(pb, slab.T0)
+    ref, mg = st0, st0
+    for _ in range(2):
+        ref = mlqd.alg1_step(pb, ref, eps=1e-14)
+        mg = mlqd.step(pb, levels, sched, 4, 1e-14, 1e-15, mg)
+    np.testing.assert_allclose(mg.T, ref.T, rtol=1e-10)
+    np.testing.assert_allclose(mg.E, ref.E, rtol=1e-9, atol=1e-12 * ref.E.max())
+    # the group averages differ from the point law: a different solution
+    pt, _ = tiny_problem(nx=6, ng=8, nmu=4, dt=0.004, T0=0.01, C1=4.0, C2=1.0)
+    pp = mlqd.problem_from_slab(pt)
+    mp = mlqd.step(pp, levels, sched, 4, 1e-14, 1e-15, mlqd.initial_state(pp, slab.T0))
+    assert np.max(np.abs(mp.T - mlqd.step(pb, levels, sched, 4, 1e-14, 1e-15, st0).T) / mp.T) > 1e-3
+
+
+def test_step_energy_conservation_with_group_averaged_opacities():
+    slab, pb = tiny_problem(nx=10, ng=16, nmu=8, dt=0.01, opacity=inputs.OPAC_SPECTRAL)
+    st0 = mlqd.initial_state(pb, slab.T0)
+    st1 = mlqd.step(pb, [16, 4, 1], [1], 2, 1e-12, 1e-13, st0)
+    dx = pb.dx
+    lhs = np.sum(dx * ((st1.E.sum(axis=0) - st0.E.sum(axis=0)) + pb.cv * (st1.T - st0.T)))
+    F = st1.F.sum(axis=0)
+    rhs = -pb.dt * (F[-1] - F[0])
+    assert abs(lhs - rhs) < 1e-9 * np.sum(dx * (st1.E.sum(axis=0) + pb.cv * st1.T))
