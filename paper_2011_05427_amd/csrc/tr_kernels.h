@@ -69,7 +69,7 @@ struct Table {
 // Planck integrals (the initial state and the incoming radiation use B_g).
 void launch_opacity(const LaunchEnv &env, const Table &tab, int run, const Ctl *ctl, int pmode, int lcyc,
                     const double *T, double *kappa, double *B, double *dSpart, bool spec = false,
-                    const double *Eg = nullptr, double *sgr = nullptr);
+                    const double *Eg = nullptr, double *sgr = nullptr, double *dem = nullptr);
 // dS per cell from the chunk partials; tab items = (slab, first of 64 cells).
 void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *dSpart,
                    double *dS);
@@ -159,3 +159,32 @@ void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const doubl
                     const float *r, double *Ef);
 void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts);
 int upload_head_coef(const double *coef);
+
+// Alg. 1 (single-grid multigroup LOQD + MEB by Newton in T; see the kernels).
+struct A1Args {
+  LoIn in;                 // fine tables at T^k, QD factors, old-time values
+  const double *dem;       // gi: d/dT of the group emission at T^k
+  const double *T, *Told, *Tprev, *kprev;  // cell, cell, cell, gi (previous iterate)
+  const double *Ek;        // gi: E of the previous iterate
+  double *alpha, *beta;    // cell
+  double *w;               // gi
+  double *ra, *cp, *dn, *dp;  // Thomas rows, per slab at o_gi + 2 o_g, row j of group g at j ng + g
+  double *P;               // per slab ng nx nx partial products (at oP)
+  double *M, *rhs, *phi;   // per slab nx nx (at oM); cell; cell
+  const long long *oM, *oP;
+  const Ctl *ctl;          // slab iterates while ctl[slab].active
+  int first;               // first Newton iteration of the transport iteration (D = 0)
+  double *E, *F, *Ebnd;    // group solution (state)
+  double *Tout, *err;      // new T; per slab max|dT| / max|T|
+};
+
+void launch_a1_prep(const LaunchEnv &env, const Table &t_cell, const A1Args &a);
+void launch_a1_factor(const LaunchEnv &env, const Table &t_g, const A1Args &a);
+void launch_a1_solve(const LaunchEnv &env, const Table &t_g, const A1Args &a, bool with_phi);
+void launch_a1_rhs(const LaunchEnv &env, const Table &t_cell, const A1Args &a);
+void launch_a1_cols(const LaunchEnv &env, const Table &t_gi, const A1Args &a);
+void launch_a1_mred(const LaunchEnv &env, const Table &t_mm, const A1Args &a);
+void launch_a1_dense(const LaunchEnv &env, int nslab, const A1Args &a);
+void launch_a1_update(const LaunchEnv &env, int nslab, const A1Args &a, double *Tprev);
+void launch_a1_outer(const LaunchEnv &env, int nslab, const Ctl *ctl, const double *T, const double *Ts,
+                     const double *E, double *Esum, const double *Esp, double *out);

@@ -140,7 +140,8 @@ template <int RUN, bool SPEC>
 __device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbDev &pd, const Item it, const Ctl *ctl,
                                      int pmode, int lcyc, const double *__restrict__ T, double *__restrict__ kappa,
                                      double *__restrict__ B, double *__restrict__ dSpart,
-                                     const double *__restrict__ Eg = nullptr, double *__restrict__ sgr = nullptr) {
+                                     const double *__restrict__ Eg = nullptr, double *__restrict__ sgr = nullptr,
+                                     double *__restrict__ dem = nullptr) {
   constexpr int CB = 4 * RUN, NR = 64 / RUN;  // cells per block, runs per chunk
   __shared__ double part[NR][CB + 1];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
@@ -165,11 +166,13 @@ __device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbD
       const double K = S.aR * S.c * 0.5 / TR_PI4_15;
       for (int g = g0; g < g1; ++g) {
         double sE, src, sR;
-        dS += spectral_group(nue[g], nue[g + 1], Ti, Tr, Cc, K, sE, src, sR);
+        const double d = spectral_group(nue[g], nue[g + 1], Ti, Tr, Cc, K, sE, src, sR);
+        dS += d;
         const long long o = S.o_gi + (long long)g * nx + i;
         kappa[o] = sE;
         B[o] = src / sE;
         sgr[o] = sR;
+        if (dem) dem[o] = d;
       }
     } else {
       EdgeQ lo = edge_q(nue[g0], iT);
@@ -179,10 +182,12 @@ __device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbD
         if (g >= g1) break;
         const EdgeQ hi = edge_q(nue[g + 1], iT);
         double kap, Bg;
-        dS += planck_group(nuc[g], lo, hi, iT, Cc, scale, kap, Bg);
+        const double d = planck_group(nuc[g], lo, hi, iT, Cc, scale, kap, Bg);
+        dS += d;
         const long long o = S.o_gi + (long long)g * nx + i;
         kappa[o] = kap;
         B[o] = Bg;
+        if (dem) dem[o] = d;
         lo = hi;
       }
     }
@@ -210,8 +215,9 @@ __global__ __launch_bounds__(256) void k_opacity(const SlabDev *__restrict__ sd,
                                                  const Item *__restrict__ tab, const Ctl *ctl, int pmode, int lcyc,
                                                  const double *__restrict__ T, double *__restrict__ kappa,
                                                  double *__restrict__ B, double *__restrict__ dSpart,
-                                                 const double *__restrict__ Eg, double *__restrict__ sgr) {
-  opacity_block<RUN, SPEC>(sd, pd, tab[blockIdx.x], ctl, pmode, lcyc, T, kappa, B, dSpart, Eg, sgr);
+                                                 const double *__restrict__ Eg, double *__restrict__ sgr,
+                                                 double *__restrict__ dem) {
+  opacity_block<RUN, SPEC>(sd, pd, tab[blockIdx.x], ctl, pmode, lcyc, T, kappa, B, dSpart, Eg, sgr, dem);
 }
 
 // Sums the 64-group chunk partials of dS for every cell.  Block = 64 cells
@@ -2016,17 +2022,388 @@ __global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, d
 }
 
 // ---------------------------------------------------------------------------
+// Alg. 1 (paper Sec. 3.1): one transport iteration's multigroup LOQD
+// equations and multigroup MEB (Eq. eb-group) on the fine grid, solved
+// together by Newton iterations in T with the QD factors fixed (the paper
+// leaves the solver of this system open).  At the iterate T^k the group
+// emission e_g = 2 sigma_B,g B_g is linearised with its derivative e'_g and
+// the absorption c sigma_E,g E_g by the per-group secant derivative D_g of
+// sigma_E,g between consecutive iterates (Eq. f-derivative-d applied to each
+// group), so the cell MEB gives dT = alpha + beta phi with phi = sum_g c
+// sigma_E,g E_g:
+//   den = c_v/dt + S' - sum_g c D_g E_g^k,  alpha = (c_v (T^old - T^k)/dt - S) / den,
+//   beta = 1 / den,
+// and every group's balance gains the emission w_g dT, w_g = e'_g - c D_g E_g^k.
+// Eliminating the groups leaves a dense system for phi per slab,
+//   (I - sum_g c sigma_E,g A_g^{-1} diag(dx w_g beta)) phi = sum_g c sigma_E,g Y_g,
+// (A_g the group's tridiagonal LO matrix, Y_g its solution with the emission
+// e_g + w_g alpha), solved by Gaussian elimination with partial pivoting;
+// the groups are then solved with e_g + w_g (alpha + beta phi) and T^{k+1} =
+// T^k + alpha + beta phi.  At a fixed point dT = 0: the multigroup LOQD and MEB
+// equations hold exactly at T.
+// ---------------------------------------------------------------------------
+__device__ inline bool a1_on(const A1Args &a, int slab) { return a.ctl[slab].active != 0; }
+
+// Edge terms of the eliminated first moment (as in the LO solve): F_e = Ak -
+// ca E_R + cb E_L.
+__device__ inline void a1_edge(const LevelView &v, int e, double c, double inv_cdt, double &Ak, double &ca,
+                               double &cb) {
+  double ae, be, sr;
+  lv_edge<true>(v, e, ae, be, sr);
+  const double h = lv_h(v, e), A = h * inv_cdt;
+  const double k = 1.0 / (A + sr * h);
+  Ak = k * A * v.Fold[e];
+  ca = c * k * ae;
+  cb = c * k * be;
+}
+
+// Row j (0: E_{1/2}, 1..nx: cells, nx+1: E_{nx+1/2}) of group v's system;
+// the cell rows take the emission em (per unit length).  L / R: terms of the
+// edges j - 1 and j.
+__device__ inline void a1_row(const LevelView &v, int j, double c, double dt, double em, double AkL, double caL,
+                              double cbL, double AkR, double caR, double cbR, double &ra, double &rb, double &rc,
+                              double &rd) {
+  const int nx = v.nx;
+  if (j == 0) {
+    ra = 0.0;
+    rb = cbR - c * v.C[0];
+    rc = -caR;
+    rd = v.Phi[0] - AkR;
+  } else if (j <= nx) {
+    const int i = j - 1;
+    const double dxi = v.dx[i];
+    ra = -cbL;
+    rb = dxi / dt + c * v.kap[i] * dxi + cbR + caL;
+    rc = -caR;
+    rd = dxi * em + dxi / dt * v.Eold[i] - AkR + AkL;
+  } else {
+    ra = -cbL;
+    rb = caL + c * v.C[1];
+    rc = 0.0;
+    rd = AkL - v.Phi[1];
+  }
+}
+
+// Per cell: alpha, beta and the per-group emission couplings w_g.
+__global__ __launch_bounds__(256) void k_a1_prep(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                 const Item *__restrict__ tab, A1Args a) {
+  const Item it = tab[blockIdx.x];
+  if (!a1_on(a, it.slab)) return;
+  const SlabDev &S = sd[it.slab];
+  const int i = it.idx + threadIdx.x;
+  if (i >= S.nx) return;
+  const long long oc = S.o_cell + i;
+  const double Tk = a.T[oc], c = S.c;
+  const double dTs = Tk - a.Tprev[oc];
+  const bool sec = !a.first && fabs(dTs) > 1e-8 * fabs(Tk);
+  double Ssum = 0.0, Sp = 0.0, cDE = 0.0;
+  for (int g = 0; g < S.ng; ++g) {
+    const long long o = S.o_gi + (long long)g * S.nx + i;
+    Ssum += 2.0 * a.in.kappa[o] * a.in.B[o];
+    Sp += a.dem[o];
+    if (sec) cDE += c * (a.in.kappa[o] - a.kprev[o]) / dTs * a.Ek[o];
+  }
+  const bool use = sec && !(cDE > 0.5 * (S.cv / S.dt + Sp));
+  const double den = S.cv / S.dt + Sp - (use ? cDE : 0.0);
+  a.alpha[oc] = (S.cv * (a.Told[oc] - Tk) / S.dt - Ssum) / den;
+  a.beta[oc] = 1.0 / den;
+  for (int g = 0; g < S.ng; ++g) {
+    const long long o = S.o_gi + (long long)g * S.nx + i;
+    a.w[o] = a.dem[o] - (use ? c * (a.in.kappa[o] - a.kprev[o]) / dTs * a.Ek[o] : 0.0);
+  }
+}
+
+// Per group: Thomas factors of its matrix (no pivoting: column diagonally
+// dominant M-matrix).  Items = (slab, first of 256 groups).
+__global__ __launch_bounds__(256) void k_a1_factor(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                   const Item *__restrict__ tab, A1Args a) {
+  const Item it = tab[blockIdx.x];
+  if (!a1_on(a, it.slab)) return;
+  const SlabDev &S = sd[it.slab];
+  const int g = it.idx + threadIdx.x;
+  if (g >= S.ng) return;
+  const LevelView v = make_view<true>(S, pd, 0, a.in, g);
+  const long long base = S.o_gi + 2 * S.o_g;
+  const int nx = S.nx, ng = S.ng;
+  double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, cpp = 0.0;
+  for (int j = 0; j <= nx + 1; ++j) {
+    if (j <= nx) a1_edge(v, j, S.c, S.inv_cdt, AkR, caR, cbR);
+    double ra, rb, rc, rd;
+    a1_row(v, j, S.c, S.dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+    const double dnj = rb - ra * cpp;
+    cpp = rc / dnj;
+    const long long o = base + (long long)j * ng + g;
+    a.ra[o] = ra;
+    a.cp[o] = cpp;
+    a.dn[o] = dnj;
+    AkL = AkR;
+    caL = caR;
+    cbL = cbR;
+  }
+}
+
+// Per group: the solve with the cell emission 2 kappa B + w (alpha + beta
+// phi) (phi null: 0); writes E, the boundary E and, with F, the fluxes.
+__global__ __launch_bounds__(256) void k_a1_solve(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                  const Item *__restrict__ tab, A1Args a, int with_phi) {
+  const Item it = tab[blockIdx.x];
+  if (!a1_on(a, it.slab)) return;
+  const SlabDev &S = sd[it.slab];
+  const int g = it.idx + threadIdx.x;
+  if (g >= S.ng) return;
+  const LevelView v = make_view<true>(S, pd, 0, a.in, g);
+  const long long base = S.o_gi + 2 * S.o_g;
+  const int nx = S.nx, ng = S.ng;
+  const long long og = S.o_gi + (long long)g * nx;
+  double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, dpp = 0.0;
+  for (int j = 0; j <= nx + 1; ++j) {
+    if (j <= nx) a1_edge(v, j, S.c, S.inv_cdt, AkR, caR, cbR);
+    double em = 0.0;
+    if (j >= 1 && j <= nx) {
+      const long long oc = S.o_cell + j - 1, o = og + j - 1;
+      const double dT = a.alpha[oc] + (with_phi ? a.beta[oc] * a.phi[oc] : 0.0);
+      em = 2.0 * a.in.kappa[o] * a.in.B[o] + a.w[o] * dT;
+    }
+    double ra, rb, rc, rd;
+    a1_row(v, j, S.c, S.dt, em, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+    const long long o = base + (long long)j * ng + g;
+    dpp = (rd - a.ra[o] * dpp) / a.dn[o];
+    a.dp[o] = dpp;
+    AkL = AkR;
+    caL = caR;
+    cbL = cbR;
+  }
+  double *E = a.E + og, *Eb = a.Ebnd + 2 * S.o_g + 2 * g;
+  double u = 0.0;
+  for (int j = nx + 1; j >= 0; --j) {
+    const long long o = base + (long long)j * ng + g;
+    u = a.dp[o] - (j <= nx ? a.cp[o] * u : 0.0);
+    if (j == nx + 1)
+      Eb[1] = u;
+    else if (j == 0)
+      Eb[0] = u;
+    else
+      E[j - 1] = u;
+  }
+  if (a.F && with_phi) {
+    double *F = a.F + S.o_ge + (long long)g * (nx + 1);
+    for (int e = 0; e <= nx; ++e) {
+      double Ak, ca, cb;
+      a1_edge(v, e, S.c, S.inv_cdt, Ak, ca, cb);
+      const double uL = e == 0 ? Eb[0] : E[e - 1], uR = e == nx ? Eb[1] : E[e];
+      F[e] = Ak - ca * uR + cb * uL;
+    }
+  }
+}
+
+// Per cell: phi's right-hand side sum_g c kappa_g E_g (fixed group order).
+__global__ __launch_bounds__(256) void k_a1_rhs(const SlabDev *__restrict__ sd, const Item *__restrict__ tab,
+                                                A1Args a) {
+  const Item it = tab[blockIdx.x];
+  if (!a1_on(a, it.slab)) return;
+  const SlabDev &S = sd[it.slab];
+  const int i = it.idx + threadIdx.x;
+  if (i >= S.nx) return;
+  double r = 0.0;
+  for (int g = 0; g < S.ng; ++g) {
+    const long long o = S.o_gi + (long long)g * S.nx + i;
+    r += S.c * a.in.kappa[o] * a.E[o];
+  }
+  a.rhs[S.o_cell + i] = r;
+}
+
+// Per (group, column j): column j of A_g^{-1} restricted to the cells (unit
+// source in cell j), times c kappa_g,i and dx_j w_g,j beta_j, into P[g][i][j].
+// The column slots of P hold the forward-substitution values first.  Items
+// = (slab, first of 256 (g, j) pairs).
+__global__ __launch_bounds__(256) void k_a1_cols(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                 const Item *__restrict__ tab, A1Args a) {
+  const Item it = tab[blockIdx.x];
+  if (!a1_on(a, it.slab)) return;
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx, ng = S.ng;
+  const int q = it.idx + threadIdx.x;
+  if (q >= ng * nx) return;
+  const int g = q / nx, jc = q - g * nx;
+  const long long base = S.o_gi + 2 * S.o_g;
+  double *Pg = a.P + a.oP[it.slab] + (long long)g * nx * nx + jc;  // slot i at Pg[i nx]
+  // forward: rows r < jc + 1 are zero, row jc + 1 has the unit source
+  const int r = jc + 1;
+  double d = 1.0 / a.dn[base + (long long)r * ng + g];
+  Pg[(long long)jc * nx] = d;
+  for (int j = r + 1; j <= nx; ++j) {
+    const long long o = base + (long long)j * ng + g;
+    d = -a.ra[o] * d / a.dn[o];
+    Pg[(long long)(j - 1) * nx] = d;
+  }
+  const long long on = base + (long long)(nx + 1) * ng + g;
+  double z = -a.ra[on] * d / a.dn[on];  // row nx + 1 (boundary)
+  const long long oc = S.o_cell + jc;
+  const double u = pd.dx[oc] * a.w[S.o_gi + (long long)g * nx + jc] * a.beta[oc];
+  for (int j = nx; j >= 1; --j) {
+    const long long o = base + (long long)j * ng + g;
+    const double dj = j >= r ? Pg[(long long)(j - 1) * nx] : 0.0;
+    z = dj - a.cp[o] * z;
+    const int i = j - 1;
+    Pg[(long long)i * nx] = S.c * a.in.kappa[S.o_gi + (long long)g * nx + i] * z * u;
+  }
+}
+
+// Per (i, j): M_ij = delta_ij - sum_g P[g][i][j] (fixed group order).
+__global__ __launch_bounds__(256) void k_a1_mred(const SlabDev *__restrict__ sd, const Item *__restrict__ tab,
+                                                 A1Args a) {
+  const Item it = tab[blockIdx.x];
+  if (!a1_on(a, it.slab)) return;
+  const SlabDev &S = sd[it.slab];
+  const int nx = S.nx;
+  const int q = it.idx + threadIdx.x;
+  if (q >= nx * nx) return;
+  const double *P = a.P + a.oP[it.slab] + q;
+  double s = 0.0;
+  for (int g = 0; g < S.ng; ++g) s += P[(long long)g * nx * nx];
+  const int i = q / nx, j = q - i * nx;
+  a.M[a.oM[it.slab] + q] = (i == j ? 1.0 : 0.0) - s;
+}
+
+// One block per slab: Gaussian elimination with partial pivoting of M phi =
+// rhs (row-major in global memory), then back substitution; phi written.
+__global__ __launch_bounds__(256) void k_a1_dense(const SlabDev *__restrict__ sd, A1Args a) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  const int slab = blockIdx.x;
+  if (!a1_on(a, slab)) return;
+  const SlabDev &S = sd[slab];
+  const int n = S.nx, t = threadIdx.x;
+  double *M = a.M + a.oM[slab];
+  double *b = a.rhs + S.o_cell;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + t; i < n; i += blockDim.x) {
+      const double v = fabs(M[(long long)i * n + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    sv[t] = best;
+    si[t] = bi;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if (t < h && (sv[t + h] > sv[t] || (sv[t + h] == sv[t] && si[t + h] < si[t]))) {
+        sv[t] = sv[t + h];
+        si[t] = si[t + h];
+      }
+      __syncthreads();
+    }
+    const int p = si[0];
+    __syncthreads();
+    if (p != k) {
+      for (int j = k + t; j < n; j += blockDim.x) {
+        const double x = M[(long long)k * n + j];
+        M[(long long)k * n + j] = M[(long long)p * n + j];
+        M[(long long)p * n + j] = x;
+      }
+      if (t == 0) {
+        const double x = b[k];
+        b[k] = b[p];
+        b[p] = x;
+      }
+    }
+    __syncthreads();
+    const double piv = M[(long long)k * n + k];
+    for (int i = k + 1 + t; i < n; i += blockDim.x) {
+      const double l = M[(long long)i * n + k] / piv;
+      for (int j = k + 1; j < n; ++j) M[(long long)i * n + j] -= l * M[(long long)k * n + j];
+      b[i] -= l * b[k];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double *x = a.phi + S.o_cell;
+    for (int i = n - 1; i >= 0; --i) {
+      double s = b[i];
+      for (int j = i + 1; j < n; ++j) s -= M[(long long)i * n + j] * x[j];
+      x[i] = s / M[(long long)i * n + i];
+    }
+  }
+}
+
+// One block per slab (blockDim >= nx): T^{k+1} = T^k + alpha + beta phi
+// (floored at T^k / 2), the previous iterate's T kept, and max|dT| / max|T|.
+__global__ __launch_bounds__(512) void k_a1_update(const SlabDev *__restrict__ sd, A1Args a, double *Tprev) {
+  __shared__ double r0[512], r1[512];
+  const int slab = blockIdx.x;
+  if (!a1_on(a, slab)) return;
+  const SlabDev &S = sd[slab];
+  const int i = threadIdx.x;
+  double dT = 0.0, Tn = 0.0;
+  if (i < S.nx) {
+    const long long oc = S.o_cell + i;
+    const double Tk = a.T[oc];
+    Tn = Tk + a.alpha[oc] + a.beta[oc] * a.phi[oc];
+    if (Tn < 0.5 * Tk) Tn = 0.5 * Tk;
+    dT = fabs(Tn - Tk);
+    Tprev[oc] = Tk;
+    a.Tout[oc] = Tn;
+  }
+  r0[i] = dT;
+  r1[i] = fabs(Tn);
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (i < h) {
+      r0[i] = fmax(r0[i], r0[i + h]);
+      r1[i] = fmax(r1[i], r1[i + h]);
+    }
+    __syncthreads();
+  }
+  if (i == 0) a.err[slab] = r1[0] > 0.0 ? r0[0] / r1[0] : 0.0;
+}
+
+// One block per slab: max|T - Ts|, max|T|, max|Es - Esp|, max|Es| (outer
+// test of Alg. 1) into out[4 slab ..]; Esum = sum_g E_g per cell.
+__global__ __launch_bounds__(512) void k_a1_outer(const SlabDev *__restrict__ sd, const Ctl *ctl, const double *T,
+                                                  const double *Ts, const double *E, double *Esum,
+                                                  const double *Esp, double *out) {
+  __shared__ double r[4][512];
+  const int slab = blockIdx.x;
+  if (ctl[slab].active == 0) return;
+  const SlabDev &S = sd[slab];
+  const int i = threadIdx.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < S.nx) {
+    const long long oc = S.o_cell + i;
+    double e = 0.0;
+    for (int g = 0; g < S.ng; ++g) e += E[S.o_gi + (long long)g * S.nx + i];
+    Esum[oc] = e;
+    v[0] = fabs(T[oc] - Ts[oc]);
+    v[1] = fabs(T[oc]);
+    v[2] = fabs(e - Esp[oc]);
+    v[3] = fabs(e);
+  }
+  for (int k = 0; k < 4; ++k) r[k][i] = v[k];
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (i < h)
+      for (int k = 0; k < 4; ++k) r[k][i] = fmax(r[k][i], r[k][i + h]);
+    __syncthreads();
+  }
+  if (i == 0)
+    for (int k = 0; k < 4; ++k) out[4 * slab + k] = r[k][0];
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 static inline dim3 blocks(int n) { return dim3((unsigned)n); }
 
 void launch_opacity(const LaunchEnv &env, const Table &tab, int run, const Ctl *ctl, int pmode, int lcyc,
                     const double *T, double *kappa, double *B, double *dSpart, bool spec, const double *Eg,
-                    double *sgr) {
+                    double *sgr, double *dem) {
   if (tab.n == 0) return;
 #define TR_OP(R, SP)                                                                                                 \
   hipLaunchKernelGGL((k_opacity<R, SP>), blocks(tab.n), dim3(256), 0, env.stream, env.sd, env.pd, tab.d, ctl, pmode, \
-                     lcyc, T, kappa, B, dSpart, Eg, sgr)
+                     lcyc, T, kappa, B, dSpart, Eg, sgr, dem)
   if (spec) {
     if (run == 1) TR_OP(1, true); else TR_OP(4, true);
   } else {
@@ -2231,4 +2608,38 @@ int upload_head_coef(const double *coef) {
   for (int n = 1; n < TR_NRECIP; ++n) rec[n] = 1.0 / n;
   if (hipMemcpyToSymbol(HIP_SYMBOL(tr_recip), rec, sizeof(double) * TR_NRECIP) != hipSuccess) return -3;
   return hipMemcpyToSymbol(HIP_SYMBOL(tr_head_coef), coef, sizeof(double) * TR_NHEAD) == hipSuccess ? 0 : -3;
+}
+
+// Alg. 1 launchers (items: t_cell = (slab, first of 256 cells), t_g = (slab,
+// first of 256 groups), t_gi = (slab, first of 256 (g, i) pairs), t_mm =
+// (slab, first of 256 (i, j) pairs)).
+void launch_a1_prep(const LaunchEnv &env, const Table &t_cell, const A1Args &a) {
+  if (t_cell.n) hipLaunchKernelGGL(k_a1_prep, blocks(t_cell.n), dim3(256), 0, env.stream, env.sd, env.pd, t_cell.d, a);
+}
+void launch_a1_factor(const LaunchEnv &env, const Table &t_g, const A1Args &a) {
+  if (t_g.n) hipLaunchKernelGGL(k_a1_factor, blocks(t_g.n), dim3(256), 0, env.stream, env.sd, env.pd, t_g.d, a);
+}
+void launch_a1_solve(const LaunchEnv &env, const Table &t_g, const A1Args &a, bool with_phi) {
+  if (t_g.n)
+    hipLaunchKernelGGL(k_a1_solve, blocks(t_g.n), dim3(256), 0, env.stream, env.sd, env.pd, t_g.d, a, with_phi ? 1 : 0);
+}
+void launch_a1_rhs(const LaunchEnv &env, const Table &t_cell, const A1Args &a) {
+  if (t_cell.n) hipLaunchKernelGGL(k_a1_rhs, blocks(t_cell.n), dim3(256), 0, env.stream, env.sd, t_cell.d, a);
+}
+void launch_a1_cols(const LaunchEnv &env, const Table &t_gi, const A1Args &a) {
+  if (t_gi.n) hipLaunchKernelGGL(k_a1_cols, blocks(t_gi.n), dim3(256), 0, env.stream, env.sd, env.pd, t_gi.d, a);
+}
+void launch_a1_mred(const LaunchEnv &env, const Table &t_mm, const A1Args &a) {
+  if (t_mm.n) hipLaunchKernelGGL(k_a1_mred, blocks(t_mm.n), dim3(256), 0, env.stream, env.sd, t_mm.d, a);
+}
+void launch_a1_dense(const LaunchEnv &env, int nslab, const A1Args &a) {
+  hipLaunchKernelGGL(k_a1_dense, dim3((unsigned)nslab), dim3(256), 0, env.stream, env.sd, a);
+}
+void launch_a1_update(const LaunchEnv &env, int nslab, const A1Args &a, double *Tprev) {
+  hipLaunchKernelGGL(k_a1_update, dim3((unsigned)nslab), dim3(512), 0, env.stream, env.sd, a, Tprev);
+}
+void launch_a1_outer(const LaunchEnv &env, int nslab, const Ctl *ctl, const double *T, const double *Ts,
+                     const double *E, double *Esum, const double *Esp, double *out) {
+  hipLaunchKernelGGL(k_a1_outer, dim3((unsigned)nslab), dim3(512), 0, env.stream, env.sd, ctl, T, Ts, E, Esum, Esp,
+                     out);
 }

@@ -3,12 +3,13 @@
 Runs the Fleck-Cummings set-up (``inputs.fc_slab``) to t = 3 ns with every
 hierarchy, cycle and lmax of the two tables and prints the totals of transport
 iterations N_ti, cycles N_c and low-order solves N_lo beside the printed ones,
-with the GPU time per step.  The group opacities are the build's point
-evaluation at the group centre, not the paper's spectral averages
-(sigma_B,g, sigma_E,g(T_r), sigma_R,g), so the counts are context, not a
-parity check.
+with the GPU time per step.  The group opacities are the paper's spectral
+averages (sigma_B,g, sigma_E,g at the radiation temperature, Rosseland
+sigma_R,g; --opacity point: the point law at the group centre).  The
+radiation temperature and the Newton details are readings, so the counts are
+compared as context, not as a parity check.
 
-    python -m paper_2011_05427_amd.fc_tables [--tables 1 2] [--json out.json]
+    python -m paper_2011_05427_amd.fc_tables [--tables 1 2] [--opacity spectral|point] [--json out.json]
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TABLES = os.path.join(ROOT, "tests", "golden", "paper_tables.json")
 
 
-def run_row(row, tiles=None):
+def run_row(row, tiles=None, opacity=1):
     """One table row on the GPU; returns its totals and timing."""
     import torch
 
@@ -29,7 +30,7 @@ def run_row(row, tiles=None):
 
     dt = 0.02 if row["table"] == 1 else 0.04
     cyc = {"V": inputs.CYCLE_V, "W": inputs.CYCLE_W, "F": inputs.CYCLE_F}[row["cycle"]]
-    slabs, cfg, nsteps = inputs.config_fc(dt, row["levels"], cyc, row["lmax"])
+    slabs, cfg, nsteps = inputs.config_fc(dt, row["levels"], cyc, row["lmax"], opacity=opacity)
     assert nsteps == row["steps"]
     sv = binding.Solver(slabs, [cfg.levels], cfg)
     if tiles is not None:
@@ -53,13 +54,15 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--tables", type=int, nargs="*", default=[1, 2])
     ap.add_argument("--json", default=None)
+    ap.add_argument("--opacity", choices=["spectral", "point"], default="spectral")
     args = ap.parse_args(argv)
+    opac = 1 if args.opacity == "spectral" else 0
     rows = [r for r in json.load(open(TABLES))["rows"] if r["table"] in args.tables]
     out = []
     print("| table | grids | cycle | lmax | paper N_ti / N_c / N_lo | GPU N_ti / N_c / N_lo | ms per step |")
     print("|---|---|---|---|---|---|---|")
     for r in rows:
-        g = run_row(r)
+        g = run_row(r, opacity=opac)
         out.append({"paper": r, "gpu": g})
         print(f"| {r['table']} | {','.join(map(str, r['levels']))} | {r['cycle']} | {r['lmax']} | "
               f"{r['N_ti']} / {r['N_c']} / {r['N_lo']} | {g['N_ti']} / {g['N_c']} / {g['N_lo']} | "
