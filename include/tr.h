@@ -317,6 +317,34 @@ int tr_step(tr_ctx *ctx, const tr_state *st, const int *replay, tr_stats *stats,
 int tr_run(tr_ctx *ctx, const tr_state *st, int nsteps, tr_stats *stats, int *done, hipStream_t stream);
 
 /*
+ * Alg. 1 (paper Sec. 3.1): one backward-Euler step of every slab by the
+ * two-level QD method on the single fine frequency grid.  Transport
+ * iterations s = 0, 1, ... (no sweep at s = 0): opacities at T^(s), sweep,
+ * QD factors, then the multigroup LOQD equations (Eqs. mloqd1-d, mloqd2-d)
+ * and the multigroup MEB (Eq. eb-group) solved together for T^(s+1), E_g,
+ * F_g; stop from s = 1 on when the infinity-norm changes of T and of the
+ * total energy density sum_g E_g are at most eps (tr_solver_cfg) of their
+ * norms.  The paper leaves the solver of the coupled system open: here
+ * Newton iterations in T with the group emission linearised, a per-group
+ * secant derivative of sigma_E,g (Eq. f-derivative-d per group) and the
+ * cell MEB eliminated, so that the groups couple through phi = sum_g c
+ * sigma_E,g E_g; per slab the dense nx x nx system for phi is formed from
+ * the groups' tridiagonal factors and solved by Gaussian elimination with
+ * partial pivoting, all on the device; each Newton step ends when the
+ * relative temperature change reaches rounding.  State as for tr_step
+ * (I_prev in, I_out: the last sweep; E, F, Ebnd, f, fbnd, C, T, Egrey =
+ * sum_g E_g out).  stats (host, nullable): n_ti sweeps, n_c Newton
+ * iterations, n_lo group solves (two per group and Newton iteration),
+ * cycles[s] Newton iterations of transport iteration s.  The context's
+ * workspace for it (about 8 ng nx^2 + 100 ng nx bytes per slab) is
+ * allocated at the first call; the host synchronises the stream after
+ * every Newton iteration.  Errors: TR_EINVAL (a slab with more than 512
+ * cells), TR_ENOCONV (no convergence in max_outer transport or 60 Newton
+ * iterations), TR_ENAN, TR_EHIP, TR_ENOMEM.
+ */
+int tr_alg1_step(tr_ctx *ctx, const tr_state *st, tr_stats *stats, hipStream_t stream);
+
+/*
  * A8: cycle and lmax of the following tr_step calls (the context's grids stay:
  * V visits none of the intermediate grids, W the second grid, F every
  * intermediate grid from coarse to fine).  Which cycle, hierarchy and lmax

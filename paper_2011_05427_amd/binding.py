@@ -73,7 +73,7 @@ EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_in
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
            "tr_mlp_grad_noalloc", "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
            "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing",
-           "tr_prolong", "tr_set_schedule", "tr_run"]
+           "tr_prolong", "tr_set_schedule", "tr_run", "tr_alg1_step"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def load():
     lib.tr_set_sweep_timing.argtypes = [vp, C.c_int]
     lib.tr_set_schedule.argtypes = [vp, C.c_int, C.c_int]
     lib.tr_run.argtypes = [vp, C.POINTER(TrState), C.c_int, C.POINTER(TrStats), _ip, vp]
+    lib.tr_alg1_step.argtypes = [vp, C.POINTER(TrState), C.POINTER(TrStats), vp]
     lib.tr_prolong.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.tr_mlp_nparam.argtypes = []
     lib.tr_mlp_work_bytes.argtypes = [C.c_longlong]
@@ -299,6 +300,16 @@ class Solver:
             rp = arr.ctypes.data_as(_ip)
         code = self.lib.tr_step(self._ctx, C.byref(self._state(st)), rp, stats, self._stream())
         _check(code, "tr_step")
+        if swap:
+            st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
+        return stats
+
+    def alg1_step(self, st: Dict, stats=None, swap: bool = True):
+        """One time step of every slab by the single-grid method (Alg. 1);
+        returns the per-slab TrStats array."""
+        if stats is None:
+            stats = (TrStats * self.n)()
+        _check(self.lib.tr_alg1_step(self._ctx, C.byref(self._state(st)), stats, self._stream()), "tr_alg1_step")
         if swap:
             st["I_prev"], st["I_out"] = st["I_out"], st["I_prev"]
         return stats

@@ -115,6 +115,15 @@ struct tr_ctx {
   unsigned long long *d_seed_counts = nullptr;
   double *T_hist = nullptr;  // temperature at the start of the previous closure step
   int have_hist = 0;
+  // Alg. 1 (single-grid solve of the multigroup LOQD + MEB), allocated at
+  // its first use
+  struct A1Work {
+    bool ready = false;
+    double *dem, *kprev, *w, *ra, *cp, *dn, *dp, *P, *M, *rhs, *phi, *alpha, *beta, *Tprev, *Ts, *Esum, *Esp, *Er;
+    double *err, *outer, *h_err, *h_outer;  // device and pinned host copies (per slab)
+    long long *oM, *oP;
+    Table t_mm;
+  } a1{};
 };
 
 namespace {
@@ -444,6 +453,8 @@ int tr_destroy(tr_ctx *c) {
   if (c->h_count) (void)hipHostFree(c->h_count);
   if (c->h_ctl_out) (void)hipHostFree(c->h_ctl_out);
   if (c->h_ctl_in) (void)hipHostFree(c->h_ctl_in);
+  if (c->a1.h_err) (void)hipHostFree(c->a1.h_err);
+  if (c->a1.h_outer) (void)hipHostFree(c->a1.h_outer);
   delete c;
   return TR_OK;
 }
@@ -1433,3 +1444,200 @@ int tr_run(tr_ctx *c, const tr_state *s, int nsteps, tr_stats *stats, int *done,
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Alg. 1 on the GPU: one backward-Euler step by transport iterations whose
+// low-order stage solves the multigroup LOQD equations and the multigroup MEB
+// (Eq. eb-group) together on the fine grid (Newton in T, see the kernels).
+// ---------------------------------------------------------------------------
+#define TR_A1_MAXNX 512
+#define TR_A1_NEWTON 60
+
+namespace {
+
+int a1_alloc(tr_ctx *c) {
+  auto &a = c->a1;
+  if (a.ready) return TR_OK;
+  long long nM = 0, nP = 0;
+  std::vector<long long> hoM(c->nslab), hoP(c->nslab);
+  std::vector<Item> mm;
+  for (int k = 0; k < c->nslab; ++k) {
+    const SlabDev &S = c->hs[k];
+    hoM[k] = nM;
+    hoP[k] = nP;
+    nM += (long long)S.nx * S.nx;
+    nP += (long long)S.ng * S.nx * S.nx;
+    for (long long q = 0; q < (long long)S.nx * S.nx; q += 256) mm.push_back({k, (int)q});
+  }
+  const long long nrow = c->n_gi + 2 * c->n_g;
+  int rc;
+  double **gi[] = {&a.dem, &a.kprev, &a.w};
+  for (double **p : gi)
+    if ((rc = dalloc(c, p, c->n_gi))) return rc;
+  double **rows[] = {&a.ra, &a.cp, &a.dn, &a.dp};
+  for (double **p : rows)
+    if ((rc = dalloc(c, p, nrow))) return rc;
+  double **cells[] = {&a.rhs, &a.phi, &a.alpha, &a.beta, &a.Tprev, &a.Ts, &a.Esum, &a.Esp, &a.Er};
+  for (double **p : cells)
+    if ((rc = dalloc(c, p, c->n_cell))) return rc;
+  if ((rc = dalloc(c, &a.P, nP)) || (rc = dalloc(c, &a.M, nM)) || (rc = dalloc(c, &a.err, c->nslab)) ||
+      (rc = dalloc(c, &a.outer, 4LL * c->nslab)) || (rc = dalloc(c, &a.oM, c->nslab)) ||
+      (rc = dalloc(c, &a.oP, c->nslab)))
+    return rc;
+  if (hipMemcpy(a.oM, hoM.data(), 8 * hoM.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(a.oP, hoP.data(), 8 * hoP.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return TR_EHIP;
+  if ((rc = upload_table(c, mm, a.t_mm))) return rc;
+  if (hipHostMalloc((void **)&a.h_err, 8 * c->nslab, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&a.h_outer, 32 * c->nslab, hipHostMallocDefault) != hipSuccess)
+    return TR_ENOMEM;
+  a.ready = true;
+  return TR_OK;
+}
+
+// Control records of the slabs still iterating (sweep predication and the
+// Alg. 1 kernels): active, transport iteration so.
+int a1_upload_ctl(tr_ctx *c, const std::vector<int> &act, int so, hipStream_t st) {
+  for (int k = 0; k < c->nslab; ++k) {
+    Ctl r{};
+    r.active = act[k];
+    r.s = so;
+    c->h_ctl_in[k] = r;
+  }
+  return hip_err(hipMemcpyAsync(c->d_ctl, c->h_ctl_in, sizeof(Ctl) * c->nslab, hipMemcpyHostToDevice, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int tr_alg1_step(tr_ctx *c, const tr_state *s, tr_stats *stats, hipStream_t st) {
+  if (!c || !s || !s->T || !s->I_prev || !s->I_out || !s->E || !s->F || !s->Ebnd || !s->f || !s->fbnd || !s->C ||
+      !s->Egrey || s->I_prev == s->I_out)
+    return TR_EINVAL;
+  for (const SlabDev &S : c->hs)
+    if (S.nx > TR_A1_MAXNX) return TR_EINVAL;
+  int rc = a1_alloc(c);
+  if (rc) return rc;
+  auto &w = c->a1;
+  const int ns = c->nslab;
+  LaunchEnv env = env_of(c, st);
+  std::vector<int> act(ns, 1);
+  // step start: old-time copies, Phi of the incoming with the state's C
+  for (int k = 0; k < ns; ++k) {
+    Ctl r{};
+    r.active = 1;
+    c->h_ctl_in[k] = r;
+  }
+  launch_step_start(env, s->T, s->Egrey, s->E, s->F, c->n_cell, c->n_gi, c->n_ge, c->Told, c->Ts, c->Tcyc, c->Tstar,
+                    c->Es, c->Ecyc, c->Eold, c->Fold, c->h_ctl_in, c->d_ctl, ns, c->t_g, s->C, c->Phi, c->t_opac,
+                    c->opac_run, c->kappa, c->B, c->dSpart, c->spectral, c->sigR);
+  // radiation temperature of the spectral averages: from the total energy
+  // density of the latest solution (held during each Newton solve)
+  launch_copy(env, s->Egrey, w.Er, c->n_cell);
+  launch_copy(env, s->T, w.Ts, c->n_cell);
+  launch_copy(env, s->Egrey, w.Esp, c->n_cell);
+  A1Args a{};
+  a.in = fine_in(c, c->kappa, c->B, s->f, s->fbnd, s->C, c->Phi, c->Eold, c->Fold);
+  a.dem = w.dem;
+  a.T = s->T;
+  a.Told = c->Told;
+  a.Tprev = w.Tprev;
+  a.kprev = w.kprev;
+  a.Ek = s->E;
+  a.alpha = w.alpha;
+  a.beta = w.beta;
+  a.w = w.w;
+  a.ra = w.ra;
+  a.cp = w.cp;
+  a.dn = w.dn;
+  a.dp = w.dp;
+  a.P = w.P;
+  a.M = w.M;
+  a.rhs = w.rhs;
+  a.phi = w.phi;
+  a.oM = w.oM;
+  a.oP = w.oP;
+  a.ctl = c->d_ctl;
+  a.E = s->E;
+  a.F = s->F;
+  a.Ebnd = s->Ebnd;
+  a.Tout = s->T;
+  a.err = w.err;
+  std::vector<long long> n_ti(ns, 0), n_c(ns, 0), n_lo(ns, 0);
+  std::vector<int> newton_per_it;
+  for (int so = 0;; ++so) {
+    if ((rc = a1_upload_ctl(c, act, so, st))) return rc;
+    if (so > 0) {
+      // transport sweep with the opacities at the current T, QD factors
+      launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, s->T, c->kappa, c->B, c->dSpart,
+                     c->spectral, w.Er, c->sigR);
+      launch_sweeps(c, env, c->d_ctl, PRED_SWEEP, c->kappa, c->B, s->I_prev, s->I_out, c->mom, c->bnd);
+      launch_moments(env, c->t_gi, c->d_ctl, PRED_SWEEP, 0, c->mom, c->bnd, s->f, s->fbnd, s->C, c->Phi);
+      for (int k = 0; k < ns; ++k) n_ti[k] += act[k];
+    }
+    // Newton iterations of the multigroup LOQD + MEB at fixed factors
+    double prev_worst = 0.0;
+    int k = 0;
+    for (;; ++k) {
+      if (k >= TR_A1_NEWTON) return TR_ENOCONV;
+      launch_opacity(env, c->t_opac, c->opac_run, nullptr, PRED_ALL, 0, s->T, c->kappa, c->B, c->dSpart,
+                     c->spectral, w.Er, c->sigR, w.dem);
+      a.first = k == 0;
+      launch_a1_prep(env, c->t_cell, a);
+      launch_a1_factor(env, c->t_g, a);
+      launch_a1_solve(env, c->t_g, a, false);
+      launch_a1_rhs(env, c->t_cell, a);
+      launch_a1_cols(env, c->t_gi, a);
+      launch_a1_mred(env, w.t_mm, a);
+      launch_a1_dense(env, ns, a);
+      launch_a1_solve(env, c->t_g, a, true);
+      launch_a1_update(env, ns, a, w.Tprev);
+      launch_copy(env, c->kappa, w.kprev, c->n_gi);
+      if (hipMemcpyAsync(w.h_err, w.err, 8 * ns, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return TR_EHIP;
+      double worst = 0.0;
+      for (int q = 0; q < ns; ++q) {
+        if (!act[q]) continue;
+        if (!std::isfinite(w.h_err[q])) return TR_ENAN;
+        worst = std::max(worst, w.h_err[q]);
+        n_c[q] += 1;
+        n_lo[q] += 2LL * c->hs[q].ng;
+      }
+      // converged to rounding, or stalled there after a few iterations
+      if (worst <= 1e-15 || (k >= 3 && worst <= 1e-13 && worst >= 0.5 * prev_worst)) break;
+      prev_worst = worst;
+    }
+    newton_per_it.push_back(k + 1);
+    // outer test (from s = 1 on): T and the total energy density
+    launch_a1_outer(env, ns, c->d_ctl, s->T, w.Ts, s->E, w.Esum, w.Esp, w.outer);
+    if (hipMemcpyAsync(w.h_outer, w.outer, 32 * ns, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return TR_EHIP;
+    int left = 0;
+    for (int q = 0; q < ns; ++q) {
+      if (!act[q]) continue;
+      const double *o = w.h_outer + 4 * q;
+      if (so >= 1 && o[0] <= c->cfg.eps * o[1] && o[2] <= c->cfg.eps * o[3]) act[q] = 0;
+      left += act[q];
+    }
+    launch_copy(env, s->T, w.Ts, c->n_cell);
+    launch_copy(env, w.Esum, w.Esp, c->n_cell);
+    launch_copy(env, w.Esum, w.Er, c->n_cell);
+    if (left == 0) break;
+    if (so >= c->cfg.max_outer) return TR_ENOCONV;
+  }
+  launch_copy(env, w.Esum, s->Egrey, c->n_cell);
+  if (stats) {
+    for (int q = 0; q < ns; ++q) {
+      stats[q].n_ti += n_ti[q];
+      stats[q].n_c += n_c[q];
+      stats[q].n_lo += n_lo[q];
+      stats[q].n_outer = (int)newton_per_it.size();
+      for (int i = 0; i < 64; ++i) stats[q].cycles[i] = i < (int)newton_per_it.size() ? newton_per_it[i] : 0;
+    }
+  }
+  return hip_err(hipStreamSynchronize(st));
+}
+
+}  // extern "C"

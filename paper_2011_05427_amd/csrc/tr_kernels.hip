@@ -188,6 +188,9 @@ __device__ inline void opacity_block(const SlabDev *__restrict__ sd, const ProbD
         kappa[o] = kap;
         B[o] = Bg;
         if (dem) dem[o] = d;
+        // a context with spectral slabs reads sigma_R from its own table:
+        // the point law's sigma_R is kappa
+        if (SPEC) sgr[o] = kap;
         lo = hi;
       }
     }

@@ -193,3 +193,31 @@ def _init(sv):
     st = sv.new_state()
     sv.state_init(st, 0.001)
     return st
+
+
+def test_batch_of_point_and_spectral_slabs_replays_the_oracle():
+    """A context mixing the point opacity law and the spectral group averages
+    (a sigma_R table of its own for the whole context): one replayed W-cycle
+    step per slab against its own oracle run at 1e-10."""
+    slabs = [inputs.make_slab(30, 16, 8, dt=0.004, nu_lo=1e-3, nu_hi=30.0, opacity=inputs.OPAC_SPECTRAL),
+             inputs.make_slab(45, 32, 8, dt=0.004),
+             inputs.make_slab(20, 16, 4, dt=0.004, C1=5.0, C2=0.5, opacity=inputs.OPAC_SPECTRAL)]
+    levels = [[s.ng, s.ng // 8, 1] for s in slabs]
+    cfg = inputs.SolverCfg(levels=[0, 0, 1], cycle=inputs.CYCLE_W, lmax=2)
+    refs = []
+    for s, lv in zip(slabs, levels):
+        pb = mlqd.problem_from_slab(s)
+        stats = mlqd.Stats()
+        ref = mlqd.step(pb, lv, mlqd.schedule(3, cfg.cycle), cfg.lmax, cfg.eps, cfg.eps_inner,
+                        mlqd.initial_state(pb, 0.001), stats=stats)
+        refs.append((ref, stats.counts[0]))
+    note("mixed point / spectral batch of 3 slabs, one replayed W step")
+    sv = binding.Solver(slabs, levels, cfg)
+    st = _init(sv)
+    sv.step(st, replay=[c for _, c in refs])
+    for k, (ref, _) in enumerate(refs):
+        T, E, I = _slab_view(sv, st, k)
+        assert_close(f"slab {k} T", T, ref.T, 1e-10, atol_scale=0.0)
+        assert_close(f"slab {k} E", E.reshape(ref.E.shape), ref.E, 1e-10)
+        assert_close(f"slab {k} I", I.reshape(ref.I.shape), ref.I, 1e-10)
+    sv.close()
