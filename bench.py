@@ -490,6 +490,50 @@ def measure(workload, steps, warmup, tiles_opt=None, lmax_opt=None, fp32=False):
     return res, internals
 
 
+def alg1_vs_cycles(slabs, cfg, candidates, steps, warmup=1):
+    """Time-to-solution of the single-grid method (Alg. 1, tr_alg1_step) and
+    of multigrid cycles on the same steps from the initial condition:
+    candidates = [(name, levels, cycle, lmax)].  Reports ms per step, sweeps,
+    low-order work and the largest relative difference of the final T from
+    Alg. 1's."""
+    import numpy as np
+    import torch
+
+    from paper_2011_05427_amd import binding
+
+    def run(levels, cyc, lmax, alg1):
+        c = dataclasses.replace(cfg, levels=levels, cycle=cyc, lmax=lmax)
+        sv = binding.Solver(slabs, [levels] * len(slabs), c)
+        st = sv.new_state()
+        sv.state_init(st, slabs[0].T0)
+        for _ in range(warmup):  # workspace, graphs
+            sv.alg1_step(st) if alg1 else sv.step(st)
+        sv.state_init(st, slabs[0].T0)
+        acc = (binding.TrStats * len(slabs))()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sv.alg1_step(st, stats=acc) if alg1 else sv.step(st, stats=acc)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        T = st["T"].cpu().numpy().copy()
+        sv.close()
+        return {"ms_per_step": 1e3 * wall / steps, "sweeps": int(sum(a.n_ti for a in acc)),
+                ("newton_iterations" if alg1 else "cycles"): int(sum(a.n_c for a in acc)),
+                "lo_group_solves": int(sum(a.n_lo for a in acc))}, T
+
+    fine = candidates[0][1][0]
+    out = {}
+    a1, Ta = run([fine, 1], 0, 1, True)
+    out["alg1"] = a1
+    for name, levels, cyc, lmax in candidates:
+        r, Tm = run(levels, cyc, lmax, False)
+        r["max_rel_dT_vs_alg1"] = float(np.max(np.abs(Tm - Ta) / np.abs(Ta)))
+        r["speedup_vs_alg1"] = a1["ms_per_step"] / r["ms_per_step"]
+        out[name] = r
+    return out
+
+
 def mlqd_schedule(n_levels, cycle):
     """Grids visited after each grey solve in one cycle (the library's own
     rule: V none, W the second grid, F every intermediate grid); used only to
@@ -522,6 +566,7 @@ def main():
                     help="sweep tiles 'K1,..,K6:S1,..,S6' per slab-size bucket instead of the autotuner's")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the stage-adaptive schedule run")
+    ap.add_argument("--no-alg1", action="store_true", help="skip the single-grid (Alg. 1) comparison")
     ap.add_argument("--train-samples", type=int, default=1000000)
     ap.add_argument("--train-epochs", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -571,6 +616,24 @@ def main():
         if not args.no_cpu_baseline:
             r["cpu_baseline"] = cpu_baseline(extra, args.cpu_budget, xi["cfg"].lmax)
         out[{"paper": "paper_scale"}.get(extra, extra)] = r
+        torch.cuda.empty_cache()
+    if not args.no_alg1:
+        from paper_2011_05427_amd import inputs
+
+        ps, pcfg, _ = inputs.config_paper_scale()
+        lv = pcfg.levels
+        out["single_grid_vs_multigrid"] = {
+            "note": "Alg. 1 (single-grid multigroup LOQD + MEB by Newton on the device) against the multigrid "
+                    "cycles on the same steps from the initial condition; eps of each workload",
+            "paper_scale": dict(alg1_vs_cycles(ps, pcfg, [("V1", lv, 0, 1), ("W1", lv, 1, 1), ("F1", lv, 2, 1)],
+                                               steps=5), steps=5, levels=lv),
+        }
+        fs, fcfg, _ = inputs.config_fc(0.02)
+        out["single_grid_vs_multigrid"]["fleck_cummings"] = dict(
+            alg1_vs_cycles(fs, fcfg, [("V4", [256, 1], 0, 4), ("W2", [256, 32, 1], 1, 2),
+                                      ("F2", [256, 32, 16, 1], 2, 2), ("F1_6grids", [256, 128, 64, 32, 16, 1], 2, 1)],
+                           steps=20),
+            steps=20, dt=0.02, opacity="spectral group averages")
         torch.cuda.empty_cache()
     if args.copy_calibration:
         # a plain device copy of known size for the byte-counter calibration

@@ -8,8 +8,14 @@
  *  - Arrays named in a call are DEVICE pointers owned by the caller unless a
  *    comment says "host".  The library never frees caller memory.
  *  - Work is enqueued asynchronously on the given stream (0 = default stream);
- *    the caller synchronises.  tr_step synchronises internally once per
- *    transport iteration to read a convergence flag.
+ *    the caller synchronises.  tr_step and tr_run wait on the host until the
+ *    device has published the number of slabs still iterating: the
+ *    iteration's end kernel writes it, with an iteration serial number, into
+ *    coherent pinned host memory and the host spins on that serial (no
+ *    stream synchronisation); their outputs (T, E, F, I, factors) are ready
+ *    only in the order of the given stream: work queued there afterwards
+ *    sees them, a reader on another stream or on the host synchronises the
+ *    stream first.  tr_alg1_step synchronises the stream.
  *  - Every call returns TR_OK (0) or a negative TR_E* code; tr_error_string()
  *    gives a message.  Nothing throws across the ABI.
  *  - One context serves one stream at a time; calls on one context are not
@@ -18,8 +24,12 @@
  *    of a context created with TR_PREC_F32_STORAGE (binary32 storage) and the
  *    closure network calls (float32 parameters, bfloat16 products).
  *
- * Batched layout ("pooled" arrays).  A context holds n_slab independent slab
- * problems.  Every per-slab array is stored slab after slab in creation order;
+ * Batched layout ("pooled" arrays).  The library works in the canonical
+ * layout below (the one the CPU oracle and the tests use): intensities
+ * [g][m][i][corner] keep a corner pair in one 16-byte load and every
+ * (group, direction) row contiguous for the sweep's coalesced passes, so no
+ * pack/unpack between an internal and a user layout exists.  A context holds
+ * n_slab independent slab problems.  Every per-slab array is stored slab after slab in creation order;
  * tr_layout() returns, per slab, the element offset of its part in each kind
  * of pooled array.  Within one slab (nx cells, ng groups, nmu directions, cell
  * i, edge e = 0..nx at x_edges[e], group g, direction m, corner k = 0 (left,
