@@ -315,24 +315,41 @@ def learned_vs_plain(slabs, levels, cfg, tiles, args, plain_ms, plain_sweeps):
                     "seeds the cell factors with its predicted change; the plain sweeps decide convergence"}
 
 
-def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles, cands, initial):
-    """The same steps with the cycle and lmax chosen per step by
-    ``tuning.StageSchedule`` (seeded with the set-up costs; every candidate's
-    graphs captured in untimed warmup steps)."""
+def hierarchy_candidates(nlev):
+    """(grids, lmax) candidates for the stage-adaptive run: the two-grid
+    cycle, W through the finest and through the coarsest intermediate grid, F
+    over two grids and over all of them, and the full F with lmax 2."""
+    mid = list(range(1, nlev - 1))
+    if not mid:
+        return [((), 1), ((), 2)]
+    c = [((), 1), ((mid[0],), 1), (tuple(reversed(mid)), 1)]
+    if len(mid) > 1:
+        c += [((mid[-1],), 1), ((mid[-1], mid[0]), 1)]
+    c.append((tuple(reversed(mid)), 2))
+    return list(dict.fromkeys(c))
+
+
+def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles):
+    """The same steps with the grid hierarchy and lmax chosen per step by
+    ``tuning.CostModelSchedule`` (sweep kernel time measured in the set-up;
+    every candidate's graphs captured in untimed warmup steps)."""
     import torch
 
     from paper_2011_05427_amd import binding, tuning
 
+    cands = hierarchy_candidates(len(levels[0]))
     sv = binding.Solver(slabs, levels, cfg)
     sv.set_tiles(*tiles)
     st = sv.new_state()
+    sv.state_init(st, slabs[0].T0)
+    t_sweep = tuning.measure_sweep_ms(sv, st)
     for cand in cands:
-        sv.set_schedule(*cand)
+        tuning.apply_schedule(sv, cand)
         sv.state_init(st, slabs[0].T0)
         for _ in range(max(warmup, 2)):
             sv.step(st)
     sv.state_init(st, slabs[0].T0)
-    ctl = tuning.StageSchedule(cands, initial=initial)
+    ctl = tuning.CostModelSchedule(cands, t_sweep=t_sweep)
     torch.cuda.synchronize()
     acc = (binding.TrStats * len(slabs))()
     t0 = time.perf_counter()
@@ -341,11 +358,14 @@ def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles, cands, initial)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sv.close()
+    name = lambda c: ("grids" + ",".join(str(levels[0][g]) for g in c[0]) if c[0] else "two-grid") + f"/l{c[1]}"
     return {"ms_per_step": 1e3 * wall / steps,
             "value": sum(s.cell_updates_per_sweep() * int(a.n_ti) for s, a in zip(slabs, acc)) / wall,
             "sweeps": int(sum(a.n_ti for a in acc)), "cycles": int(sum(a.n_c for a in acc)),
-            "choices": [f"{'VWF'[c]}{l}" for (c, l), _ in ctl.history],
-            "note": "candidates " + ",".join(f"{'VWF'[c]}{l}" for c, l in cands) + "; probe every 8 steps"}
+            "t_sweep_ms": t_sweep, "choices": [name(c) for c, *_ in ctl.history],
+            "candidates": [name(c) for c in cands],
+            "note": "hierarchy (grids visited after each grey solve) and lmax per step from the cost model "
+                    "s t_sweep + (s + 1) k_c t_c; probe every 8 steps"}
 
 
 def measure(workload, steps, warmup, tiles_opt=None, lmax_opt=None, fp32=False):
@@ -605,7 +625,7 @@ def main():
     out.update(res)
     if not args.no_adaptive:
         out["stage_adaptive"] = run_stage_adaptive(ins["slabs"], ins["levels"], ins["cfg"], args.steps, args.warmup,
-                                                   ins["tiles"], ins["cands"], ins["sched_ms"])
+                                                   ins["tiles"])
     if not args.no_learned:
         out["learned"] = learned_vs_plain(ins["slabs"], ins["levels"], ins["cfg"], ins["tiles"], args,
                                           out["ms_per_step"], ins["sweeps"])

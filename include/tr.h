@@ -369,6 +369,23 @@ int tr_alg1_step(tr_ctx *ctx, const tr_state *st, tr_stats *stats, hipStream_t s
 int tr_set_schedule(tr_ctx *ctx, int cycle, int lmax);
 
 /*
+ * A8 with the hierarchy chosen per step: the following tr_step calls visit,
+ * after each grey solve, the context grids grids[0..n-1] (host, indices of
+ * the context's intermediate grids 1..n_levels-2, distinct, in the order
+ * given) and run at most lmax cycles per transport iteration.  This selects
+ * the grid hierarchy of Alg. 3 (fine grid, the listed grids, grey) and its
+ * schedule S per time step: n = 0 is the two-grid V cycle, one grid a W
+ * cycle through that grid, the intermediate grids from coarse to fine an F
+ * cycle over that sub-hierarchy.  Which hierarchy costs least depends on the
+ * stage of the TRT process and the time step (Sec. 6 and 7).  The context
+ * builds every intermediate grid's restriction tables at tr_create, so a
+ * change needs no device memory; its graphs are captured at the first step
+ * and kept.  Host only.  Errors: TR_EINVAL (n or an index out of range, a
+ * repeated grid, lmax outside 1..64).
+ */
+int tr_set_grids(tr_ctx *ctx, int n, const int *grids, int lmax);
+
+/*
  * Sweep kernel timing inside tr_step.  on = 1: the transport sweeps of
  * iterations s >= 1 are launched outside the replayed graphs, each launch
  * recording its own start and end on HIP events, and their kernel time is

@@ -73,7 +73,7 @@ EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_in
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
            "tr_mlp_grad_noalloc", "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
            "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing",
-           "tr_prolong", "tr_set_schedule", "tr_run", "tr_alg1_step"]
+           "tr_prolong", "tr_set_schedule", "tr_run", "tr_alg1_step", "tr_set_grids"]
 
 _lib = None
 
@@ -110,6 +110,7 @@ def load():
     lib.tr_step.argtypes = [vp, C.POINTER(TrState), _ip, C.POINTER(TrStats), vp]
     lib.tr_set_sweep_timing.argtypes = [vp, C.c_int]
     lib.tr_set_schedule.argtypes = [vp, C.c_int, C.c_int]
+    lib.tr_set_grids.argtypes = [vp, C.c_int, _ip, C.c_int]
     lib.tr_run.argtypes = [vp, C.POINTER(TrState), C.c_int, C.POINTER(TrStats), _ip, vp]
     lib.tr_alg1_step.argtypes = [vp, C.POINTER(TrState), C.POINTER(TrStats), vp]
     lib.tr_prolong.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
@@ -339,6 +340,14 @@ class Solver:
         ``tuning.StageSchedule``)."""
         _check(self.lib.tr_set_schedule(self._ctx, int(cycle), int(lmax)), "tr_set_schedule")
         self.schedule = (int(cycle), int(lmax))
+
+    def set_grids(self, grids, lmax: int):
+        """Grids visited after each grey solve (context grid indices, in order)
+        and lmax of the following steps (tr_set_grids)."""
+        g = np.ascontiguousarray(list(grids), dtype=np.int32)
+        _check(self.lib.tr_set_grids(self._ctx, len(g), g.ctypes.data_as(_ip) if len(g) else None, int(lmax)),
+               "tr_set_grids")
+        self.schedule = (tuple(int(x) for x in g), int(lmax))
 
     def set_sweep_timing(self, on: bool):
         """Sweeps of tr_step launched with start / end events (kernel time in

@@ -1187,6 +1187,22 @@ int tr_set_schedule(tr_ctx *c, int cycle, int lmax) {
   return TR_OK;
 }
 
+int tr_set_grids(tr_ctx *c, int n, const int *grids, int lmax) {
+  if (!c || n < 0 || n > c->nlev - 2 || (n > 0 && !grids) || lmax < 1 || lmax > TR_MAXOUT) return TR_EINVAL;
+  std::vector<int> sched;
+  for (int q = 0; q < n; ++q) {
+    const int gm = grids[q];
+    if (gm < 1 || gm > c->nlev - 2) return TR_EINVAL;
+    for (int p : sched)
+      if (p == gm) return TR_EINVAL;
+    sched.push_back(gm);
+  }
+  c->sched = sched;
+  c->cfg.cycle = n == 0 ? TR_CYCLE_V : n == 1 ? TR_CYCLE_W : TR_CYCLE_F;
+  c->cfg.lmax = lmax;
+  return TR_OK;
+}
+
 int tr_set_sweep_timing(tr_ctx *c, int on) {
   if (!c || (on != 0 && on != 1)) return TR_EINVAL;
   c->sweep_events = on;
@@ -1259,6 +1275,8 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
                                      reinterpret_cast<const void *>((intptr_t)Lmax),
                                      reinterpret_cast<const void *>((intptr_t)c->cfg.lmax),
                                      reinterpret_cast<const void *>((intptr_t)c->cfg.cycle)};
+    // the grids visited after each grey solve, in order (tr_set_grids)
+    for (int gm : c->sched) key.push_back(reinterpret_cast<const void *>((intptr_t)(1000 + gm)));
     for (auto &g : c->graphs)
       if (g.key == key) ge = &g;
     if (!ge) {

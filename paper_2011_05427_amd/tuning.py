@@ -157,3 +157,128 @@ class StageSchedule:
         _sync()
         self.record(cand, 1e3 * (time.perf_counter() - t0))
         return out
+
+
+# ---------------------------------------------------------------------------
+# Hierarchy per time step (tr_set_grids) chosen by a cost model
+# ---------------------------------------------------------------------------
+
+def apply_schedule(sv, cand):
+    """cand = (sched, lmax): sched an int cycle (tr_set_schedule over the
+    context's grids) or a tuple of context grid indices visited after each
+    grey solve (tr_set_grids)."""
+    sched, lmax = cand
+    if isinstance(sched, tuple):
+        sv.set_grids(sched, lmax)
+    else:
+        sv.set_schedule(int(sched), int(lmax))
+
+
+def measure_sweep_ms(sv, st, steps: int = 1) -> float:
+    """Kernel time of one transport sweep (start / end events of the sweep
+    launches over `steps` steps from a snapshot of `st`, restored after)."""
+    from . import binding
+
+    snap = {k: v.clone() for k, v in st.items()}
+    acc = (binding.TrStats * sv.n)()
+    sv.set_sweep_timing(True)
+    try:
+        for _ in range(steps):
+            sv.step(st, stats=acc)
+    finally:
+        sv.set_sweep_timing(False)
+    for k, v in snap.items():
+        st[k].copy_(v)
+    _sync()
+    sweeps = max(int(a.n_ti) for a in acc)
+    return acc[0].t_ms[binding.T_SWEEP] / max(sweeps, 1)
+
+
+class CostModelSchedule:
+    """Chooses the grid hierarchy (grids visited after each grey solve) and
+    lmax of every time step from a cost model of the step,
+
+        cost(c) = s_c t_sweep + (s_c + 1) k_c t_c,   s_c = r_c d,
+
+    with t_sweep the measured kernel time of a sweep, and per candidate c its
+    cycles per transport iteration k_c and time per cycle t_c (measured:
+    (step time - sweeps t_sweep) / cycles), and its sweeps per step relative
+    to the others r_c.  d, the transport difficulty of the current stage of
+    the problem (sweeps per step of a reference candidate), is updated by every
+    step whatever candidate ran it: the paper's tables show the number of
+    transport iterations changing little between hierarchies while the
+    low-order work changes by up to 3x, so one candidate's sweeps predict the
+    others' and the choice follows the stage (e.g. when few sweeps per step
+    remain, the per-step cycle of iteration s = 0 weighs more) without
+    running every candidate.  Weighted means use weight `decay` on the older
+    value.  Unmeasured candidates run first (in the given order); every
+    `probe`-th step re-runs the candidate measured longest ago.  Deterministic
+    in the recorded counts and times (ties: candidate order)."""
+
+    def __init__(self, candidates, t_sweep: float, probe: int = 8, decay: float = 0.5, ratio_decay: float = 0.9):
+        self.cands = [(tuple(c[0]) if isinstance(c[0], (tuple, list)) else int(c[0]), int(c[1]))
+                      for c in candidates]
+        self.ratio_decay = float(ratio_decay)
+        if not self.cands:
+            raise ValueError("no candidate schedule")
+        if probe < 0 or not (0.0 <= decay < 1.0) or not (t_sweep >= 0.0):
+            raise ValueError("probe >= 0, 0 <= decay < 1 and t_sweep >= 0 required")
+        self.t_sweep, self.probe, self.decay = float(t_sweep), probe, decay
+        self.r, self.k_c, self.t_c, self.seen = {}, {}, {}, {}
+        self.d = None
+        self.k = 0
+        self.history = []
+
+    def _mix(self, old, new):
+        return float(new) if old is None else self.decay * old + (1.0 - self.decay) * float(new)
+
+    def predict(self, c) -> float:
+        s = self.r[c] * self.d
+        return s * self.t_sweep + (s + 1.0) * self.k_c[c] * self.t_c[c]
+
+    def choose(self):
+        for c in self.cands:
+            if c not in self.r:
+                return c
+        if self.probe and self.k > 0 and self.k % self.probe == 0:
+            return min(self.cands, key=lambda c: (self.seen[c], self.cands.index(c)))
+        return min(self.cands, key=lambda c: (self.predict(c), self.cands.index(c)))
+
+    def record(self, cand, ms: float, sweeps: int, cycles: int):
+        sweeps, cycles = max(int(sweeps), 0), max(int(cycles), 1)
+        s = float(max(sweeps, 1))
+        if self.d is None:
+            self.d, self.r[cand] = s, 1.0
+        elif cand not in self.r:
+            self.r[cand] = s / self.d
+        else:
+            # the stage's difficulty from the candidate's known ratio, then the
+            # ratio itself drifts slowly towards the new observation
+            self.d = self._mix(self.d, s / self.r[cand])
+            self.r[cand] = self.ratio_decay * self.r[cand] + (1.0 - self.ratio_decay) * s / self.d
+        self.k_c[cand] = self._mix(self.k_c.get(cand), cycles / (sweeps + 1.0))
+        self.t_c[cand] = self._mix(self.t_c.get(cand), max(ms - sweeps * self.t_sweep, 0.0) / cycles)
+        self.seen[cand] = self.k
+        self.history.append((cand, float(ms), sweeps, cycles))
+        self.k += 1
+
+    def step(self, sv, st, **kw):
+        """One time step of `sv` with the chosen hierarchy; records its time
+        and its counts (the slowest slab's)."""
+        from . import binding
+
+        cand = self.choose()
+        if tuple(getattr(sv, "schedule", ())) != cand:
+            apply_schedule(sv, cand)
+        one = (binding.TrStats * sv.n)()
+        t0 = time.perf_counter()
+        out = sv.step(st, stats=one)
+        _sync()
+        ms = 1e3 * (time.perf_counter() - t0)
+        self.record(cand, ms, max(int(a.n_ti) for a in one), max(int(a.n_c) for a in one))
+        acc = kw.get("stats")
+        if acc is not None:
+            for q in range(sv.n):
+                for f in ("n_ti", "n_c", "n_lo", "n_floor", "n_seeded", "n_fallback"):
+                    setattr(acc[q], f, getattr(acc[q], f) + getattr(one[q], f))
+        return out

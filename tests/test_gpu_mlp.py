@@ -109,32 +109,55 @@ def test_features_and_targets_match_reference():
 
 
 def test_training_and_learned_steps_converge_to_plain():
-    slab = inputs.make_slab(50, 32, 8, dt=0.004)
+    """The closure trained on one slab's plain steps seeds a held-out slab
+    (other opacity constants and boundary temperature, 32 directions, where a
+    sweep costs most relative to inference): the learned steps reach the
+    plain solution to 1e-10 (the plain sweeps decide convergence), and the
+    test reports what the network gains or costs in sweeps and ms per step.
+    The seeding saves at most a fraction of a sweep per step here (exact
+    seeds save about a quarter of the sweeps), so the assertion on the gain
+    is only that seeding costs at most one extra sweep per step."""
+    import time
+
+    import torch
+
     levels = [32, 8, 1]
     cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_W, lmax=2, eps=1e-12, eps_inner=1e-13)
-    note("closure: data, training, learned vs plain")
-    ds = closure.generate(slab, cfg, levels, nsteps=8, n_samples=8 * 32 * 50, seed=0)
+    train_slab = inputs.make_slab(50, 32, 32, dt=0.004)
+    test_slab = inputs.make_slab(60, 32, 32, dt=0.004, C1=20.0, C2=4.0, T_left=0.9)
+    note("closure: data and training on one slab, learned vs plain on a held-out slab")
+    ds = closure.generate(train_slab, cfg, levels, nsteps=8, n_samples=8 * 32 * 50, seed=0)
     net, losses = closure.train(ds, epochs=30, batch=256, lr=2e-3, seed=0)
     print("closure losses", losses[0], losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
+    nsteps = 8
     runs = {}
     for learned in (False, True):
-        sv = binding.Solver([slab], [levels], cfg)
+        sv = binding.Solver([test_slab], [levels], cfg)
         if learned:
             sv.set_closure(net, ds.mean, ds.std)
         st = sv.new_state()
-        sv.state_init(st, slab.T0)
+        sv.state_init(st, test_slab.T0)
+        sv.step(st)  # graphs
+        sv.state_init(st, test_slab.T0)
         acc = (binding.TrStats * 1)()
-        for _ in range(8):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
             sv.step(st, stats=acc)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / nsteps
         runs[learned] = (to_np(st["T"]).copy(), to_np(st["E"]).copy(), acc[0].n_ti, acc[0].n_seeded,
-                         acc[0].n_fallback)
+                         acc[0].n_fallback, ms, acc[0].n_c)
         sv.close()
-    print("sweeps plain", runs[False][2], "learned", runs[True][2], "seeded", runs[True][3], "fallback",
-          runs[True][4], flush=True)
-    assert runs[True][3] > 0
-    assert rel_err(runs[True][0], runs[False][0]) < 1e-9
-    assert rel_err(runs[True][1], runs[False][1]) < 1e-9
+    p, q = runs[False], runs[True]
+    print(f"closure gain on the held-out slab: sweeps plain {p[2]} learned {q[2]} ({p[2] - q[2]:+d}), "
+          f"cycles {p[6]} / {q[6]}, ms/step plain {p[5]:.3f} learned {q[5]:.3f} (speedup {p[5] / q[5]:.2f}), "
+          f"seeded {q[3]} fallback {q[4]}", flush=True)
+    assert q[3] > 0
+    assert q[2] <= p[2] + nsteps
+    assert rel_err(q[0], p[0]) < 1e-10
+    assert rel_err(q[1], p[1]) < 1e-10
 
 
 @pytest.mark.parametrize("with_r", [False, True])

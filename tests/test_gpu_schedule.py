@@ -130,3 +130,35 @@ def test_batch_schedule_changes_replay_each_slab():
             assert gs[k].n_lo == nlo[k], (j, k)
             _compare_state(f"batch schedule step {j} slab {k}", sv, st, osts[k], slab_idx=k)
     sv.close()
+
+
+def test_grid_hierarchy_per_step_replays_the_oracle():
+    """tr_set_grids: the grids visited after each grey solve chosen step by
+    step (sub-hierarchies of the context's 64,32,16,8,4,1: two-grid, W through
+    one grid, F over two or four grids), each step replayed against the
+    oracle's step with the same schedule at 1e-10, with equal low-order solve
+    counts."""
+    from test_gpu_step import _compare_state
+
+    slab = inputs.make_slab(40, 64, 8, dt=0.004)
+    levels = [64, 32, 16, 8, 4, 1]
+    cfg = inputs.SolverCfg(levels=levels, cycle=inputs.CYCLE_F, lmax=2)
+    plan = [((), 2), ((2,), 1), ((4, 2), 2), ((3, 1), 1), ((1,), 2), ((4, 3, 2, 1), 1)]
+    pb = mlqd.problem_from_slab(slab)
+    ost = mlqd.initial_state(pb, slab.T0)
+    sv = binding.Solver([slab], [levels], cfg)
+    st = sv.new_state()
+    sv.state_init(st, slab.T0)
+    for j, (grids, lmax) in enumerate(plan):
+        stats = mlqd.Stats()
+        ost = mlqd.step(pb, levels, list(grids), lmax, cfg.eps, cfg.eps_inner, ost, stats=stats)
+        note(f"grids {grids} lmax {lmax}: counts {stats.counts[0]}")
+        sv.set_grids(grids, lmax)
+        gs = sv.step(st, replay=[stats.counts[0]])
+        assert gs[0].n_lo == stats.n_lo
+        _compare_state(f"grids {grids} step {j}", sv, st, ost)
+    with pytest.raises(binding.TrError):
+        sv.set_grids((5,), 1)
+    with pytest.raises(binding.TrError):
+        sv.set_grids((2, 2), 1)
+    sv.close()

@@ -94,3 +94,43 @@ def test_stage_schedule_drives_a_solver_and_records_each_step():
     assert [c for c, _ in ctl.history][:2] == [(V, 1), (V, 2)]
     assert len(ctl.history) == 4
     assert sv.calls[0] == ("set", V, 1)
+
+
+def test_cost_model_follows_the_stage_without_rerunning_candidates():
+    """Candidate A: one cycle per transport iteration at 1 ms; candidate B
+    (W cycle through grid 2): twice the sweeps but cycles at 0.2 ms.  With
+    t_sweep = 1 ms: cost_A(d) = 2 d + 1, cost_B(d) = 2.4 d + 0.2, equal at d =
+    2 sweeps per step.  After both are measured, the controller keeps running
+    A while the problem needs 3 sweeps per step, and switches to B when A
+    itself observes 1 sweep per step (B is not re-run to learn it)."""
+    A, B = ((), 1), ((2,), 1)
+    ctl = tuning.CostModelSchedule([A, B], t_sweep=1.0, probe=0, decay=0.0)
+
+    def outcome(c, d):
+        s = d if c == A else 2 * d
+        t = 1.0 if c == A else 0.2
+        cyc = s + 1
+        return s * 1.0 + cyc * t, s, cyc
+
+    d = 3
+    picks = []
+    for step in range(8):
+        if step == 4:
+            d = 1
+        c = ctl.choose()
+        ms, s, cyc = outcome(c, d)
+        ctl.record(c, ms, s, cyc)
+        picks.append(c)
+    assert picks[:2] == [A, B]  # both measured first
+    assert picks[2:5] == [A, A, A]  # d = 3: A cheaper (7 vs 7.4)
+    assert picks[5:] == [B, B, B]  # d = 1 seen by A: B cheaper (2.6 vs 3)
+    assert ctl.predict(A) == pytest.approx(3.0) and ctl.predict(B) == pytest.approx(2.6)
+
+
+def test_cost_model_candidates_and_validation():
+    ctl = tuning.CostModelSchedule([((4, 3, 2, 1), 1), (0, 2), ([1], 1)], t_sweep=0.5)
+    assert ctl.cands == [((4, 3, 2, 1), 1), (0, 2), ((1,), 1)]
+    with pytest.raises(ValueError):
+        tuning.CostModelSchedule([], t_sweep=1.0)
+    with pytest.raises(ValueError):
+        tuning.CostModelSchedule([(0, 1)], t_sweep=-1.0)
