@@ -71,53 +71,7 @@ def restrict_bytes(slab, n_stage_levels, n_cycles, n_steps):
     return (40.0 + 24.0 * n_stage_levels) * ge * n_cycles + 16.0 * (1 + n_stage_levels) * ge * n_steps
 
 
-def sweep_bytes(slab, ibytes=8):
-    """Algorithmic HBM bytes of one sweep of a slab: per cell-update read the
-    previous-time-level corner pair and write the new one (2 x 2 values of
-    ibytes each: 32 B in binary64, 16 B with binary32 storage); per (group,
-    cell, half range) write the two binary64 moment partials (16 B)."""
-    return 4.0 * ibytes * slab.cell_updates_per_sweep() + 32.0 * slab.ng * slab.nx
-
-
-SWEEP_SOURCES = ["paper_2011_05427_amd/csrc/tr_kernels.hip", "paper_2011_05427_amd/csrc/tr_device.h",
-                 "paper_2011_05427_amd/csrc/tr_common.h"]
-
-
-def sweep_source_hash():
-    """sha256 over the sweep kernel's source text (its section of the kernel
-    file plus the device headers it includes)."""
-    import hashlib
-
-    h = hashlib.sha256()
-    for rel in SWEEP_SOURCES:
-        text = open(os.path.join(ROOT, rel)).read()
-        if rel.endswith("tr_kernels.hip"):
-            a = text.index("// A2 (+ partial A3): SCB sweep")
-            b = text.index("// A3: QD factors")
-            text = text[a:b]
-        h.update(text.encode())
-    return h.hexdigest()
-
-
-def measured_traffic(workload, bytes_per_launch):
-    """HBM traffic of one sweep launch from the committed counter summary of
-    this workload (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-    calibration), or None when there is none or the sweep source changed
-    since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_traffic.md")
-    try:
-        for line in open(path):
-            if line.startswith("traffic-json: "):
-                d = json.loads(line[len("traffic-json: "):])
-                if d.get("sweep_source_sha256") != sweep_source_hash():
-                    return None
-                t = d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
-                return {"bytes_per_launch": t, "fetch_bytes_per_launch": d["fetch_bytes_per_launch"],
-                        "write_bytes_per_launch": d["write_bytes_per_launch"],
-                        "ratio_to_algorithmic": t / bytes_per_launch, "source": os.path.relpath(path, ROOT)}
-    except (OSError, ValueError, KeyError):
-        return None
-    return None
+from paper_2011_05427_amd.profsum import measured_traffic, sweep_bytes  # noqa: E402
 
 
 def cpu_baseline(workload, budget_s=20.0, lmax=None):
@@ -568,6 +522,11 @@ def mlqd_schedule(n_levels, cycle):
 EXTRA_STEPS = {"paper": 20, "batch": 4}
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -608,6 +567,7 @@ def main():
     if args.steps is None:
         args.steps = {"paper": 20, "small": 1, "large": 50, "batch": 4}[args.workload]
     res, ins = measure(args.workload, args.steps, args.warmup, args.tiles, args.lmax, args.fp32)
+    progress(f"{args.workload}: {res['ms_per_step']:.3f} ms per step")
     out = {
         "metric": "phase-space cell-updates/s per sweep; ms per converged time step, learned vs plain",
         "value": res.pop("value"),
@@ -626,9 +586,11 @@ def main():
     if not args.no_adaptive:
         out["stage_adaptive"] = run_stage_adaptive(ins["slabs"], ins["levels"], ins["cfg"], args.steps, args.warmup,
                                                    ins["tiles"])
+        progress("stage-adaptive run done")
     if not args.no_learned:
         out["learned"] = learned_vs_plain(ins["slabs"], ins["levels"], ins["cfg"], ins["tiles"], args,
                                           out["ms_per_step"], ins["sweeps"])
+        progress("learned closure run done")
     torch.cuda.empty_cache()
     for extra in [e for e in args.extras.split(",") if e and e != args.workload]:
         r, xi = measure(extra, EXTRA_STEPS.get(extra, 4), args.warmup)
@@ -636,6 +598,7 @@ def main():
         if not args.no_cpu_baseline:
             r["cpu_baseline"] = cpu_baseline(extra, args.cpu_budget, xi["cfg"].lmax)
         out[{"paper": "paper_scale"}.get(extra, extra)] = r
+        progress(f"{extra}: {r['ms_per_step']:.3f} ms per step")
         torch.cuda.empty_cache()
     if not args.no_alg1:
         from paper_2011_05427_amd import inputs
@@ -654,6 +617,7 @@ def main():
                                       ("F2", [256, 32, 16, 1], 2, 2), ("F1_6grids", [256, 128, 64, 32, 16, 1], 2, 1)],
                            steps=20),
             steps=20, dt=0.02, opacity="spectral group averages")
+        progress("single grid vs multigrid done")
         torch.cuda.empty_cache()
     if args.copy_calibration:
         # a plain device copy of known size for the byte-counter calibration
