@@ -18,7 +18,6 @@
 // oldest is destroyed beyond this.
 #define TR_GRAPH_CACHE 12
 
-#define TR_NHEAD 40
 #define TR_NBUCKET 6
 
 namespace {
@@ -157,31 +156,6 @@ int upload_table(tr_ctx *c, const std::vector<Item> &h, Table &t) {
 // Odd Bernoulli numbers vanish beyond B_1 = -1/2; the even ones follow from
 // B_2j / (2j)! = (-1)^(j+1) 2 zeta(2j) / (2 pi)^(2j), with zeta(2) = pi^2/6
 // and zeta(s >= 4) summed directly with an Euler-Maclaurin tail.
-void head_coefficients(double *out) {
-  const double pi = 3.14159265358979323846;
-  for (int k = 0; k < TR_NHEAD; ++k) out[k] = 0.0;
-  out[0] = 1.0 / 3.0;
-  out[1] = -0.5 / 4.0;
-  for (int k = 2; k < TR_NHEAD; k += 2) {
-    const int s = k;
-    double zeta;
-    if (s == 2) {
-      zeta = pi * pi / 6.0;
-    } else {
-      const int N = 64;
-      double acc = 0.0;
-      for (int n = N - 1; n >= 1; --n) acc += std::pow((double)n, -s);
-      const double Nd = N;
-      acc += std::pow(Nd, 1.0 - s) / (s - 1) + 0.5 * std::pow(Nd, -s) + s * std::pow(Nd, -s - 1.0) / 12.0 -
-             (double)s * (s + 1) * (s + 2) * std::pow(Nd, -s - 3.0) / 720.0;
-      zeta = acc;
-    }
-    const int j = k / 2;
-    const double sign = (j % 2 == 1) ? 1.0 : -1.0;
-    out[k] = sign * 2.0 * zeta / std::pow(2.0 * pi, k) / (k + 3);
-  }
-}
-
 std::vector<int> schedule_for(int cycle, int nlev) {
   std::vector<int> s;
   if (cycle == TR_CYCLE_V || nlev <= 2) return s;
@@ -606,15 +580,11 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     for (int g = 0; g <= P.ng; ++g) h_nue.push_back(P.nu_edges[g]);
     for (int g = 0; g < P.ng; ++g) h_nuc.push_back(P.nu_center[g]);
   }
-  // incoming radiation: computed after the head coefficients are on the device
   int rc = TR_OK;
   auto fail = [&](int code) {
     tr_destroy(c);
     return code;
   };
-  double coef[TR_NHEAD];
-  head_coefficients(coef);
-  if (upload_head_coef(coef)) return fail(TR_EHIP);
 
   double *d_dx, *d_C, *d_mu, *d_w, *d_nue, *d_nuc;
   if ((rc = dalloc(c, &d_dx, c->n_cell)) || (rc = dalloc(c, &d_C, c->n_cell)) || (rc = dalloc(c, &d_mu, c->n_mu)) ||

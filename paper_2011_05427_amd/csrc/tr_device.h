@@ -4,37 +4,90 @@
 #include "tr_common.h"
 
 // ---------------------------------------------------------------------------
+// 1/x from the hardware reciprocal estimate refined by two Newton steps,
+// which take the estimate's error to the binary64 rounding level.  For
+// normal, finite x of moderate exponent (what the low-order systems hold);
+// a * rcp_nr(b) then differs from a / b by a couple of ulps at most.
+// ---------------------------------------------------------------------------
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// ---------------------------------------------------------------------------
 // Planck integral  Q(x) = int_0^x t^3/(e^t - 1) dt  (total pi^4/15).
 // Below x = 2 the Bernoulli series t/(e^t-1) = sum B_k t^k / k! integrated
 // term by term; above, the geometric expansion 1/(e^t-1) = sum_n e^{-n t}
 // integrated exactly:  int_x^inf t^3 e^{-n t} dt = e^{-nx}(x^3/n + 3x^2/n^2 +
-// 6x/n^3 + 6/n^4).  The head coefficients c_k = B_k / (k! (k+3)) are filled
-// by the host at context creation.
+// 6x/n^3 + 6/n^4).  Both coefficient tables live in constant memory,
+// initialised when the code object loads.
 // ---------------------------------------------------------------------------
 #define TR_NHEAD 40
-#define TR_NRECIP 64
-extern __constant__ double tr_head_coef[TR_NHEAD];
-extern __constant__ double tr_recip[TR_NRECIP];  // 1/n, n < TR_NRECIP
 
 static constexpr double TR_PI4_15 = 6.4939394022668291491;  // pi^4 / 15
 static constexpr double TR_XSW = 2.0;
+
+// Head coefficients c_k = B_k / (k! (k + 3)): c_0 = 1/3, c_1 = -1/8, odd k > 1
+// vanish, and for even k, B_k / k! = (-1)^(k/2 + 1) 2 zeta(k) / (2 pi)^k with
+// zeta(2) = pi^2 / 6 and zeta(k), k >= 4, summed directly over n < 64 plus the
+// Euler-Maclaurin remainder N^(1-k)/(k-1) + N^-k/2 + k N^(-k-1)/12 - k(k+1)(k+2)
+// N^(-k-3)/720 at N = 64 (below 1e-25 relative to zeta(k)).
+struct TrHeadCoef {
+  double c[TR_NHEAD];
+};
+constexpr double tr_ipow(double x, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= x;
+  return r;
+}
+constexpr TrHeadCoef tr_make_head_coef() {
+  TrHeadCoef h{};
+  const double pi = 3.14159265358979323846;
+  h.c[0] = 1.0 / 3.0;
+  h.c[1] = -0.5 / 4.0;
+  for (int k = 2; k < TR_NHEAD; k += 2) {
+    double zeta;
+    if (k == 2) {
+      zeta = pi * pi / 6.0;
+    } else {
+      const int N = 64;
+      double acc = 0.0;
+      for (int n = N - 1; n >= 1; --n) acc += 1.0 / tr_ipow((double)n, k);
+      const double Nk = tr_ipow((double)N, k);
+      acc += (double)N / Nk / (k - 1) + 0.5 / Nk + k / (Nk * N) / 12.0 -
+             (double)k * (k + 1) * (k + 2) / (Nk * N * N * N) / 720.0;
+      zeta = acc;
+    }
+    const double sign = ((k / 2) % 2 == 1) ? 1.0 : -1.0;
+    h.c[k] = sign * 2.0 * zeta / tr_ipow(2.0 * pi, k) / (k + 3);
+  }
+  return h;
+}
+extern __constant__ TrHeadCoef tr_head;  // = tr_make_head_coef(), statically initialised
 
 // Head part int_0^x (x < 2): x^3 (c_0 + c_1 x + sum_{j>=1} c_2j x^2j); the
 // odd coefficients beyond c_1 vanish, so the even part is a polynomial in x^2.
 __device__ inline double q_head(double x) {
   const double y = x * x;
-  double acc = tr_head_coef[TR_NHEAD - 2];
+  double acc = tr_head.c[TR_NHEAD - 2];
 #pragma unroll
-  for (int k = TR_NHEAD - 4; k >= 2; k -= 2) acc = fma(acc, y, tr_head_coef[k]);
-  acc = fma(acc, y, fma(tr_head_coef[1], x, tr_head_coef[0]));
+  for (int k = TR_NHEAD - 4; k >= 2; k -= 2) acc = fma(acc, y, tr_head.c[k]);
+  acc = fma(acc, y, fma(tr_head.c[1], x, tr_head.c[0]));
   return acc * y * x;
 }
 
 // Tail part int_x^inf (x >= 2), given ex = e^{-x}.  Terms decay like e^{-nx};
-// n_max = 40/x + 2 keeps the truncation below 1e-17 relative.
+// n_max = 40/x + 2 (at most TR_NTAIL) keeps the truncation below 1e-17
+// relative.  The reciprocals 1/n come from a constant table (scalar loads
+// that run beside the vector arithmetic).
+#define TR_NTAIL 22
+extern __constant__ double tr_recip[TR_NTAIL + 1];  // 1/n, statically initialised
 __device__ inline double q_tail(double x, double ex) {
   if (!(ex > 0.0)) return 0.0;
-  const int nmax = min(TR_NRECIP - 1, (int)(40.0 / x) + 2);
+  const int nmax = min(TR_NTAIL, (int)(40.0 / x) + 2);
   double en = ex, acc = 0.0;
   double x2 = x * x, x3 = x2 * x;
   for (int n = 1; n <= nmax; ++n) {
@@ -67,14 +120,14 @@ __device__ inline EdgeQ edge_q(double nu, double inv_T) {
   } else if (x < TR_XSW) {
     e.head = q_head(x); e.tail = 0.0; e.is_tail = 0;
     double x2 = x * x;
-    e.g4 = x2 * x2 / expm1(x);
+    e.g4 = x2 * x2 * rcp_nr(expm1(x));
   } else if (isinf(x)) {
     e.head = 0.0; e.tail = 0.0; e.g4 = 0.0; e.is_tail = 1;
   } else {
     double ex = exp(-x);
     e.head = 0.0; e.tail = q_tail(x, ex); e.is_tail = 1;
     double x2 = x * x;
-    e.g4 = (ex > 0.0) ? x2 * x2 * ex / (1.0 - ex) : 0.0;
+    e.g4 = (ex > 0.0) ? x2 * x2 * ex * rcp_nr(1.0 - ex) : 0.0;
   }
   return e;
 }
@@ -84,20 +137,6 @@ __device__ inline double q_interval(const EdgeQ &lo, const EdgeQ &hi) {
   if (lo.is_tail) return lo.tail - hi.tail;           // both in the tail range
   if (!hi.is_tail) return hi.head - lo.head;          // both in the head range
   return (TR_PI4_15 - hi.tail) - lo.head;             // straddles x = 2
-}
-
-// ---------------------------------------------------------------------------
-// 1/x from the hardware reciprocal estimate refined by two Newton steps,
-// which take the estimate's error to the binary64 rounding level.  For
-// normal, finite x of moderate exponent (what the low-order systems hold);
-// a * rcp_nr(b) then differs from a / b by a couple of ulps at most.
-// ---------------------------------------------------------------------------
-__device__ inline double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
 }
 
 // ---------------------------------------------------------------------------

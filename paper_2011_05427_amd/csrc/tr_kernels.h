@@ -158,7 +158,6 @@ void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double
 void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const double *Ec, const double *Eprev,
                     const float *r, double *Ef);
 void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts);
-int upload_head_coef(const double *coef);
 
 // Alg. 1 (single-grid multigroup LOQD + MEB by Newton in T; see the kernels).
 struct A1Args {

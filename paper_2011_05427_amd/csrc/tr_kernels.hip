@@ -12,8 +12,13 @@
 #include "tr_device.h"
 #include "tr_kernels.h"
 
-__constant__ double tr_head_coef[TR_NHEAD];
-__constant__ double tr_recip[TR_NRECIP];
+// Coefficients of the Planck integral series: the Bernoulli head (computed at
+// compile time) and 1/n for the tail (index 0 unused).
+__constant__ TrHeadCoef tr_head = tr_make_head_coef();
+__constant__ double tr_recip[TR_NTAIL + 1] = {
+    0.0,        1.0,        1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,
+    1.0 / 8,    1.0 / 9,    1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15,
+    1.0 / 16,   1.0 / 17,   1.0 / 18, 1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22};
 
 // Ratios whose denominator is at or below this value (zero, negative, or close
 // to the subnormal range where intensities have lost their precision) use the
@@ -58,8 +63,9 @@ __device__ inline double planck_group(double nu, const EdgeQ &lo, const EdgeQ &h
   // 1 - e^{-y} from the same exponential unless y is small (cancellation)
   const double ey = exp(-y);
   const double om = y > 0.5 ? 1.0 - ey : -expm1(-y);
-  const double cn = Cc / (nu * nu);
-  kap = cn / nu * om;
+  const double inu = rcp_nr(nu);
+  const double cn = Cc * inu * inu;
+  kap = cn * inu * om;
   const double dkap = -cn * ey * iT * iT;
   return 2.0 * (dkap * Bg + kap * dBg);
 }
@@ -2603,14 +2609,6 @@ void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const doubl
 void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_seed_f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, env.stream, out, f, n, counts);
-}
-
-int upload_head_coef(const double *coef) {
-  double rec[TR_NRECIP];
-  rec[0] = 0.0;
-  for (int n = 1; n < TR_NRECIP; ++n) rec[n] = 1.0 / n;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(tr_recip), rec, sizeof(double) * TR_NRECIP) != hipSuccess) return -3;
-  return hipMemcpyToSymbol(HIP_SYMBOL(tr_head_coef), coef, sizeof(double) * TR_NHEAD) == hipSuccess ? 0 : -3;
 }
 
 // Alg. 1 launchers (items: t_cell = (slab, first of 256 cells), t_g = (slab,
