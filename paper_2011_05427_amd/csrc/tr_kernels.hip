@@ -292,7 +292,11 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int bytes) {
 }
 
 // Corner-pair storage of the intensities: binary64 or binary32 (the sweep
-// computes in binary64 either way).
+// computes in binary64 either way).  The sweep streams the intensities (each
+// read once and written once per sweep, gigabytes apart from their next use),
+// so its loads and stores carry the non-temporal hint (cache policy NT);
+// `load` without the hint serves data read again soon (the moment partials).
+#define TR_CPOL_NT 2
 template <typename TI>
 struct Pair;
 template <>
@@ -301,18 +305,21 @@ struct Pair<double> {
   static __device__ inline V load(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
   }
-  static __device__ inline void store(V v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, v), r, off, 0, 0);
+  static __device__ inline V load_stream(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, TR_CPOL_NT));
+  }
+  static __device__ inline void store_stream(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, v), r, off, 0, TR_CPOL_NT);
   }
 };
 template <>
 struct Pair<float> {
   typedef float2 V;
-  static __device__ inline V load(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  static __device__ inline V load_stream(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, TR_CPOL_NT));
   }
-  static __device__ inline void store(V v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tr_u32x2, v), r, off, 0, 0);
+  static __device__ inline void store_stream(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tr_u32x2, v), r, off, 0, TR_CPOL_NT);
   }
 };
 
@@ -419,7 +426,7 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
     const __amdgpu_buffer_rsrc_t r =
         buf_rsrc(ip + (long long)(m0 + (j0 < j1 ? j0 : 0)) * nx * 2, j0 < j1 ? rowb : 0);
 #pragma unroll
-    for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_mem(0, k) * 2 * (int)sizeof(TI));
+    for (int k = 0; k < K; ++k) nxt[k] = P::load_stream(r, cell_mem(0, k) * 2 * (int)sizeof(TI));
   }
   for (int pass = 0; pass < npass; ++pass) {
     double bb[K], ee[K], phi[K], chi[K], hh[K];
@@ -462,7 +469,7 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
         const bool same = j + 1 < j1;
         const __amdgpu_buffer_rsrc_t r = buf_rsrc(ip + (long long)(same ? m + 1 : m0 + j0) * nx * 2, rowb);
 #pragma unroll
-        for (int k = 0; k < K; ++k) nxt[k] = P::load(r, cell_mem(same ? pass : pass + 1, k) * 2 * (int)sizeof(TI));
+        for (int k = 0; k < K; ++k) nxt[k] = P::load_stream(r, cell_mem(same ? pass : pass + 1, k) * 2 * (int)sizeof(TI));
       }
       const double mum = mu[m], wm = w[m];
       const double amu = fabs(mum), a = 0.5 * amu, a2 = a * a, aamu = a * amu;
@@ -525,14 +532,14 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
           PV o;
           o.x = (TI)v.x;
           o.y = (TI)v.y;
-          P::store(o, ro, off[k]);
+          P::store_stream(o, ro, off[k]);
         }
         __builtin_amdgcn_wave_barrier();
       } else {
         PV o;
         o.x = (TI)ox[0];
         o.y = (TI)oy[0];
-        P::store(o, ro, off[0]);
+        P::store_stream(o, ro, off[0]);
       }
       const double cout = fma(readlane_f64(A, 63), cin, readlane_f64(Bc, 63));
       if (lane == j) carry = cout;

@@ -15,6 +15,13 @@
         ends with the ``traffic-json`` line that ``bench.py`` reads for
         ``roofline.traffic`` while the sweep source still hashes the same.
 
+    python -m paper_2011_05427_amd.profsum sq PASS1.csv [PASS2.csv ...] [--match NAME ...]
+        per kernel and grid size, the medians over dispatches of SQ counters
+        from one or more --pmc passes of the same command, per wavefront:
+        instructions by type, wave cycles, the fractions of wave time with a
+        vector ALU instruction active and waiting on a counter, and the mean
+        active lanes per vector instruction.
+
 The sweep kernel's algorithmic bytes and source hash live here so that the
 benchmark and the summaries agree on them.
 """
@@ -220,6 +227,43 @@ def traffic_summary(workload, fetch_csv, write_csv, kernel="k_sweep", command=No
     return "\n".join(out)
 
 
+# ---------------------------------------------------------------------------
+# SQ (wavefront) counters
+# ---------------------------------------------------------------------------
+
+def sq_table(csv_paths, match=None):
+    """Per (kernel, grid) medians of every counter found in the passes."""
+    med = defaultdict(dict)
+    for path in csv_paths:
+        vals = defaultdict(lambda: defaultdict(list))
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                key = f"{short_name(r['Kernel_Name'])} [grid {r['Grid_Size']}]"
+                vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        for key, cs in vals.items():
+            for c, v in cs.items():
+                med[key][c] = statistics.median(v)
+    cols = [("SQ_INSTS_VALU", "VALU"), ("SQ_INSTS_SALU", "SALU"), ("SQ_INSTS_SMEM", "SMEM"),
+            ("SQ_INSTS_VMEM_RD", "VMEM rd"), ("SQ_INSTS_VALU_TRANS_F64", "FP64 trans")]
+    lines = ["| kernel | waves | " + " | ".join(f"{n} / wave" for _, n in cols) +
+             " | wave cycles / wave | VALU active | waiting on counters | lanes per VALU instr |",
+             "|---|---|" + "---|" * len(cols) + "---|---|---|---|"]
+    for key in sorted(med):
+        if match and not any(m in key for m in match):
+            continue
+        m = med[key]
+        w = m.get("SQ_WAVES")
+        wc = m.get("SQ_WAVE_CYCLES")
+        if not w or not wc:
+            continue
+        per = " | ".join(f"{m[c] / w:.0f}" if c in m else "-" for c, _ in cols)
+        act = m.get("SQ_ACTIVE_INST_VALU")
+        lanes = (f"{m['SQ_THREAD_CYCLES_VALU'] / act:.1f}" if act and "SQ_THREAD_CYCLES_VALU" in m else "-")
+        lines.append(f"| `{key}` | {w:.0f} | {per} | {wc / w:.0f} | "
+                     f"{(act / wc if act else 0):.2f} | {m.get('SQ_WAIT_INST_ANY', 0) / wc:.2f} | {lanes} |")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -234,8 +278,13 @@ def main(argv=None):
     p.add_argument("--write", required=True)
     p.add_argument("--kernel", default="k_sweep")
     p.add_argument("--command", action="append", default=None, help="command line that made the counters")
+    q = sub.add_parser("sq")
+    q.add_argument("csv", nargs="+")
+    q.add_argument("--match", nargs="*", default=None)
     a = ap.parse_args(argv)
-    if a.cmd == "trace":
+    if a.cmd == "sq":
+        print(sq_table(a.csv, a.match))
+    elif a.cmd == "trace":
         print(trace_table(trace_durations(a.db, a.by_grid), a.match, a.top))
     else:
         print(traffic_summary(a.workload, a.fetch, a.write, a.kernel, a.command))
