@@ -84,8 +84,10 @@ void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int 
                     const double *bnd, double *f, double *fbnd, double *C, double *Phi);
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,
                const LoIn &in, const LoSol &sol);
-// Restriction work: coarse groups of r <= 16 finer groups are done in one pass;
-// larger r in a chunk pass plus a final pass over blocks of TR_RFIN_E edges.
+// Restriction work: coarse groups of r <= 16 finer groups are done in one pass
+// (except on wide slabs restricted to very few coarse groups, see
+// restrict_cpb); larger r in a chunk pass plus a final pass over blocks of
+// TR_RFIN_E edges.
 // old: also restrict the old-time E and F (out.Eold / out.Fold are written
 // only then).  mode 1 (fine to a stage level): kappa and B are computed at
 // the cell temperatures T instead of read, in tiles of 63 edges (tables from
@@ -107,7 +109,11 @@ __host__ __device__ inline int restrict_rcw(int r, int nto, int ne, int target) 
   return rcw;
 }
 __host__ __device__ inline int restrict_cpb(int r, int nto, int ne, int target) {
-  if (r <= 16) return 1;
+  // one pass unless the single pass would run few long wavefronts: a wide
+  // slab (8 or more edge tiles) restricted to very few coarse groups (under
+  // 256 wavefront items) takes the chunk pass from r = 8 up
+  const int ntile = (ne + 63) / 64;
+  if (r <= 16 && !(r >= 8 && ntile >= 8 && (long long)nto * ntile < 256)) return 1;
   const int rcw = restrict_rcw(r, nto, ne, target);
   return (r + 4 * rcw - 1) / (4 * rcw);
 }

@@ -43,6 +43,31 @@ def test_large_hierarchy_replay_matches_oracle():
     sv.close()
 
 
+@pytest.mark.parametrize("levels,cycle", [([256, 16, 1], inputs.CYCLE_W), ([256, 64, 16, 1], inputs.CYCLE_F)])
+def test_wide_slab_few_coarse_groups_replay(levels, cycle):
+    """A wide slab (520 cells: 9 edge tiles) restricted to 16 coarse groups
+    and to the grey group, where the restriction takes the chunk pass for r
+    = 16 instead of the single pass (stage restriction fine -> 16 with its dS
+    partials, coarse -> grey adding them), two replayed steps at 1e-10."""
+    import dataclasses
+
+    from test_gpu_step import _compare_state, _oracle_run
+
+    _, cfg0, _ = inputs.config_large()
+    cfg = dataclasses.replace(cfg0, cycle=cycle, lmax=1)
+    slab = inputs.make_slab(520, 256, 8)
+    note(f"wide slab replay nx=520 ng=256 nmu=8 levels={levels} cycle={'VWF'[cycle]}")
+    states, stats = _oracle_run(slab, cfg, levels, 2)
+    sv = binding.Solver([slab], [levels], cfg)
+    st = sv.new_state()
+    sv.state_init(st, slab.T0)
+    for j in range(2):
+        gs = sv.step(st, replay=[stats.counts[j]])
+        assert list(gs[0].cycles[:len(stats.counts[j])]) == stats.counts[j]
+        _compare_state(f"wide slab {levels} step {j}", sv, st, states[j + 1])
+    sv.close()
+
+
 def test_large_workload_sampled_sweep_and_energy_balance():
     import torch
 
