@@ -517,6 +517,21 @@ int tr_prolong(tr_ctx *ctx, int level, const double *E_coarse, const double *E_p
  */
 int tr_set_closure(tr_ctx *ctx, const float *params, const float *mean, const float *std);
 
+/*
+ * A9 (extension): the seeding step of the attached closure on its own, the
+ * kernel tr_step runs at s = 0.  For every (group, cell) of every slab it
+ * forms the network's inputs from T, T_prev (the previous step's start
+ * temperature; NULL: none), kappa (gi tables at T) and the factors f (gi),
+ * evaluates the network (bfloat16 products, float32 accumulation) and sets
+ * f <- f + 0.05 (2 s - 1), s the sigmoid of output 0, where that lies in
+ * (0, 1); elsewhere f is kept.  counts (device, 2 values, accumulated):
+ * factors seeded, factors kept.  All pointers are device pointers owned by the
+ * caller.  Errors: TR_EINVAL (no closure attached, a null pointer other
+ * than T_prev).
+ */
+int tr_closure_seed(tr_ctx *ctx, const double *T, const double *T_prev, const double *kappa, double *f,
+                    unsigned long long *counts, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

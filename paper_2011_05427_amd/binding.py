@@ -72,6 +72,7 @@ EXPORTS = ["tr_create", "tr_destroy", "tr_error_string", "tr_layout", "tr_set_in
            "tr_sweep", "tr_moments", "tr_lo_solve", "tr_restrict", "tr_grey_solve", "tr_state_init", "tr_step",
            "tr_mlp_nparam", "tr_mlp_work_bytes", "tr_mlp_train_work_bytes", "tr_mlp_forward", "tr_mlp_grad",
            "tr_mlp_grad_noalloc", "tr_mlp_adam", "tr_mlp_train_epoch", "tr_mlp_features", "tr_closure_targets", "tr_set_closure",
+           "tr_closure_seed",
            "tr_autotune", "tr_set_tiles", "tr_get_tiles", "tr_set_sweep_timing",
            "tr_prolong", "tr_set_schedule", "tr_run", "tr_alg1_step", "tr_set_grids"]
 
@@ -127,6 +128,7 @@ def load():
     lib.tr_mlp_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
     lib.tr_closure_targets.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp]
     lib.tr_set_closure.argtypes = [vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    lib.tr_closure_seed.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.tr_autotune.argtypes = [vp, vp, vp, C.c_int, _ip, _ip, _dp, vp]
     lib.tr_set_tiles.argtypes = [vp, _ip, _ip]
     lib.tr_get_tiles.argtypes = [vp, _ip, _ip, _ip]
@@ -438,6 +440,12 @@ def _solver_methods():
         _check(self.lib.tr_closure_targets(self._ctx, _ptr(f), _ptr(f_prev), _ptr(E_new), _ptr(E_prev), int(block),
                                            _ptr(Y), self._stream()), "tr_closure_targets")
 
+    def closure_seed(self, T, T_prev, kappa, f, counts):
+        """The attached closure's s = 0 seeding of f in place (T_prev may be
+        None); counts: int64 device tensor [2] (seeded, kept), accumulated."""
+        _check(self.lib.tr_closure_seed(self._ctx, _ptr(T), _ptr(T_prev), _ptr(kappa), _ptr(f), _ptr(counts),
+                                        self._stream()), "tr_closure_seed")
+
     def set_closure(self, mlp, mean=None, std=None):
         if mlp is None:
             _check(self.lib.tr_set_closure(self._ctx, None, None, None), "tr_set_closure")
@@ -472,6 +480,7 @@ def _solver_methods():
     Solver.mlp_features = mlp_features
     Solver.closure_targets = closure_targets
     Solver.set_closure = set_closure
+    Solver.closure_seed = closure_seed
 
 
 _solver_methods()

@@ -108,9 +108,6 @@ struct tr_ctx {
   // learned closure (seeding of the s = 0 cell factors)
   const float *mlp_params = nullptr;
   MlpStats mlp_stats{};
-  float *mlp_X = nullptr, *mlp_out = nullptr;
-  void *mlp_work = nullptr;
-  long long mlp_chunk = 0;
   unsigned long long *d_seed_counts = nullptr;
   double *T_hist = nullptr;  // temperature at the start of the previous closure step
   int have_hist = 0;
@@ -972,18 +969,19 @@ int tr_set_closure(tr_ctx *c, const float *params, const float *mean, const floa
     c->mlp_stats.mean[k] = mean[k];
     c->mlp_stats.std[k] = std[k];
   }
-  if (!c->mlp_X) {
-    c->mlp_chunk = std::min<long long>(c->n_gi, 1LL << 20);
+  if (!c->d_seed_counts) {
     int rc;
-    if ((rc = dalloc(c, &c->mlp_X, 8 * c->n_gi)) || (rc = dalloc(c, &c->mlp_out, 2 * c->n_gi)) ||
-        (rc = dalloc(c, &c->d_seed_counts, 2)) || (rc = dalloc(c, &c->T_hist, c->n_cell)))
-      return rc;
-    char *w = nullptr;
-    if ((rc = dalloc(c, &w, (long long)tr_mlp_work_bytes(c->mlp_chunk)))) return rc;
-    c->mlp_work = w;
+    if ((rc = dalloc(c, &c->d_seed_counts, 2)) || (rc = dalloc(c, &c->T_hist, c->n_cell))) return rc;
   }
   c->mlp_params = params;
   return TR_OK;
+}
+
+int tr_closure_seed(tr_ctx *c, const double *T, const double *T_prev, const double *kappa, double *f,
+                    unsigned long long *counts, hipStream_t st) {
+  if (!c || !c->mlp_params || !T || !kappa || !f || !counts) return TR_EINVAL;
+  launch_closure_seed(env_of(c, st), c->t_gi, T, T_prev, kappa, f, c->mlp_stats, c->mlp_params, counts);
+  return hip_err(hipGetLastError());
 }
 
 int tr_state_init(tr_ctx *c, const tr_state *s, double T0, hipStream_t st) {
@@ -1225,17 +1223,12 @@ int step_impl(tr_ctx *c, const tr_state *s, const int *replay, tr_stats *stats, 
     // learned closure: predicted cell factors replace the previous step's
     if (hipMemsetAsync(c->d_seed_counts, 0, 2 * sizeof(unsigned long long), gs) != hipSuccess) return TR_EHIP;
     // inputs at the step start: T^{j-1}, the previous step's T (after a
-    // first closure step), the current factors
-    launch_mlp_features(env, c->t_gi, c->Tstar, c->have_hist ? c->T_hist : nullptr, c->kappa, s->f, c->mlp_stats,
-                        c->mlp_X);
+    // first closure step), the current factors; inputs, network and seeding
+    // in one kernel
+    launch_closure_seed(env, c->t_gi, c->Tstar, c->have_hist ? c->T_hist : nullptr, c->kappa, s->f, c->mlp_stats,
+                        c->mlp_params, c->d_seed_counts);
     launch_copy(env, c->Tstar, c->T_hist, c->n_cell);
     c->have_hist = 1;
-    for (long long o = 0; o < c->n_gi; o += c->mlp_chunk) {
-      const long long n = std::min(c->mlp_chunk, c->n_gi - o);
-      int rc = tr_mlp_forward(c->mlp_params, c->mlp_X + 8 * o, n, c->mlp_out + 2 * o, c->mlp_work, gs);
-      if (rc) return rc;
-    }
-    launch_seed_f(env, c->mlp_out, s->f, c->n_gi, c->d_seed_counts);
   }
 
   // graphs for this state (ping-pong buffers give two keys per run)

@@ -164,6 +164,11 @@ void launch_closure_targets(const LaunchEnv &env, const Table &tab, const double
 void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const double *Ec, const double *Eprev,
                     const float *r, double *Ef);
 void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts);
+// A9 fused: inputs, network and seeding of f in one kernel (tab = the (slab,
+// first of 256 (g, i)) items); counts[0] += seeded, counts[1] += kept.
+void launch_closure_seed(const LaunchEnv &env, const Table &tab, const double *T, const double *Tprev,
+                         const double *kappa, double *f, const MlpStats &ms, const float *params,
+                         unsigned long long *counts);
 
 // Alg. 1 (single-grid multigroup LOQD + MEB by Newton in T; see the kernels).
 struct A1Args {

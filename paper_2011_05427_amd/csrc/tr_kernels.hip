@@ -11,6 +11,7 @@
 #include "tr.h"
 #include "tr_device.h"
 #include "tr_kernels.h"
+#include "tr_mlp_dev.h"
 
 // Coefficients of the Planck integral series: the Bernoulli head (computed at
 // compile time) and 1/n for the tail (index 0 unused).
@@ -2038,6 +2039,176 @@ __global__ __launch_bounds__(256) void k_seed_f(const float *__restrict__ out, d
 }
 
 // ---------------------------------------------------------------------------
+// A9 in one pass: the s = 0 seeding of the cell factors.  Per (group, cell)
+// sample: the closure inputs (as k_mlp_features), the network (bfloat16 MFMA
+// with float32 accumulation), the sigmoid of output 0 and the seeded factor
+// f + DF (2 s - 1), written where it stays inside (0, 1) and counted (as
+// k_seed_f).  The products are taken transposed, C[unit][sample] =
+// W^T[unit][k] X[k][sample]: the weights are the A operand (staged in LDS
+// once per block) and the activations the B operand, so a layer's
+// accumulators feed the next layer directly from registers.  A lane of a
+// 32 x 32 accumulator tile holds, for its sample column, the units
+// 8 (j / 4) + 4 h + (j % 4) (j < 16, h = lane / 32); read as two 16-wide K
+// chunks of 8 values per lane, chunk position 8 h + i then carries unit
+// 8 (i / 4) + 4 h + (i % 4) of the chunk, so the next layer's weights are
+// staged with K permuted the same way within every 16-wide block.
+// Block = TR_CLS_WAVES wavefronts; it loops over the 256-sample items of the
+// table (wavefront w takes samples 32 w .. 32 w + 31 of an item).
+// ---------------------------------------------------------------------------
+#define TR_CLS_WAVES 8
+#define TR_CLS_LD 136  // LDS row stride (bf16) of the staged 128-wide weights
+
+__device__ inline int cls_unit(int p) {  // K position within a layer -> unit
+  const int q = p >> 4, k = p & 15, h = k >> 3, i = k & 7;
+  return 16 * q + 8 * (i >> 2) + 4 * h + (i & 3);
+}
+
+__global__ __launch_bounds__(64 * TR_CLS_WAVES) void k_closure_seed(
+    const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab, int nitem,
+    const double *__restrict__ T, const double *__restrict__ Tprev, const double *__restrict__ kappa,
+    double *__restrict__ f, MlpStats ms, const float *__restrict__ params, unsigned long long *__restrict__ counts) {
+  using namespace trmlp;
+  __shared__ uint16_t W1t[NH * 24];
+  __shared__ uint16_t W2p[NH * TR_CLS_LD];
+  __shared__ uint16_t W3p[NH * TR_CLS_LD];
+  __shared__ uint16_t W4p[32 * TR_CLS_LD];
+  __shared__ float bias[3 * NH + NOUT];
+  __shared__ unsigned int s_ok, s_bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) s_ok = s_bad = 0;
+  for (int i = tid; i < NH * 24; i += nt) {
+    const int nn = i / 24, k = i - nn * 24;
+    W1t[i] = k < NINP ? to_bf16(params[OW1 + k * NH + nn]) : (uint16_t)0;
+  }
+  for (int i = tid; i < NH * NH; i += nt) {
+    const int nn = i / NH, p = i - nn * NH, u = cls_unit(p);
+    W2p[nn * TR_CLS_LD + p] = to_bf16(params[OW2 + u * NH + nn]);
+    W3p[nn * TR_CLS_LD + p] = to_bf16(params[OW3 + u * NH + nn]);
+  }
+  for (int i = tid; i < 32 * NH; i += nt) {
+    const int nn = i / NH, p = i - nn * NH;
+    W4p[nn * TR_CLS_LD + p] = nn < NOUT ? to_bf16(params[OW4 + cls_unit(p) * NOUT + nn]) : (uint16_t)0;
+  }
+  for (int i = tid; i < NH; i += nt) {
+    bias[i] = params[OB1 + i];
+    bias[NH + i] = params[OB2 + i];
+    bias[2 * NH + i] = params[OB3 + i];
+  }
+  if (tid < NOUT) bias[3 * NH + tid] = params[OB4 + tid];
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  unsigned int ok = 0, bad = 0;
+  for (int q = blockIdx.x; q < nitem; q += gridDim.x) {
+    // compiler-only barrier: keeps the staged weights' LDS reads inside the
+    // loop (hoisted, the 96 weight fragments of a pass would need 384 VGPRs)
+    asm volatile("" ::: "memory");
+    const Item it = tab[q];
+    const SlabDev &S = sd[it.slab];
+    const int nx = S.nx, ng = S.ng;
+    const int idx = it.idx + 32 * wv + r;
+    const bool valid = idx < ng * nx;
+    // inputs of sample r (lanes of both halves compute them; half 1 feeds
+    // the zero half of the 16-wide K step)
+    bf16x8 x;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = 0;
+    double fgi = 0.0;
+    if (valid) {
+      const int g = idx / nx, i = idx - g * nx;
+      const double *Tc = T + S.o_cell;
+      const double Ti = Tc[i];
+      const double Tl = i > 0 ? Tc[i - 1] : (S.T_left > 0.0 ? S.T_left : Ti);
+      const double Tr = i < nx - 1 ? Tc[i + 1] : Ti;
+      fgi = f[S.o_gi + idx];
+      const double in[TR_MLP_NFEAT] = {log(Ti),
+                                       log(pd.nu_c[S.o_g + g]),
+                                       log(kappa[S.o_gi + idx] * pd.dx[S.o_cell + i]),
+                                       log(Tl),
+                                       log(Tr),
+                                       fgi,
+                                       Tprev ? log(Ti / Tprev[S.o_cell + i]) : 0.0};
+      if (h == 0) {
+#pragma unroll
+        for (int k = 0; k < TR_MLP_NFEAT; ++k) x[k] = (short)to_bf16((float)((in[k] - ms.mean[k]) / ms.std[k]));
+      }
+    }
+    f32x16 acc[4];
+    // layer 1: K = 8 features (the upper half of the 16-wide step is zero)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W1t + (t * 32 + r) * 24 + 8 * h);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, x, acc[t], 0, 0, 0);
+    }
+    float o0 = 0.0f;
+#pragma unroll
+    for (int layer = 0; layer < 3; ++layer) {
+      // bias + ReLU of the layer's 128 units -> eight 16-wide K chunks
+      bf16x8 bq[8];
+      const float *bl = bias + layer * NH;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          tr_u32x4 w;
+#pragma unroll
+          for (int i = 0; i < 8; i += 2) {
+            const int j = 8 * c + i;
+            const float v0 = fmaxf(acc[t][j] + bl[32 * t + 8 * (j >> 2) + 4 * h + (j & 3)], 0.0f);
+            const float v1 = fmaxf(acc[t][j + 1] + bl[32 * t + 8 * ((j + 1) >> 2) + 4 * h + ((j + 1) & 3)], 0.0f);
+            w[i >> 1] = pack_bf16x2(v0, v1);
+          }
+          bq[2 * t + c] = __builtin_bit_cast(bf16x8, w);
+        }
+      }
+      if (layer < 2) {
+        const uint16_t *Wp = layer == 0 ? W2p : W3p;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+#pragma unroll
+          for (int kq = 0; kq < 8; ++kq) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Wp + (t * 32 + r) * TR_CLS_LD + kq * 16 + 8 * h);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[kq], acc[t], 0, 0, 0);
+          }
+        }
+      } else {
+        // output layer: rows 0 and 1 of one 32-row tile are the outputs
+        f32x16 out;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) out[j] = 0.0f;
+#pragma unroll
+        for (int kq = 0; kq < 8; ++kq) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W4p + r * TR_CLS_LD + kq * 16 + 8 * h);
+          out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[kq], out, 0, 0, 0);
+        }
+        o0 = out[0] + bias[3 * NH];  // row 0 of column r on the lanes of half 0
+      }
+    }
+    if (valid && h == 0) {
+      const float sg = 1.0f / (1.0f + expf(-o0));
+      const double cand = fgi + TR_MLP_DF * (2.0 * (double)sg - 1.0);
+      if (cand > 0.0 && cand < 1.0) {
+        f[S.o_gi + idx] = cand;
+        ++ok;
+      } else {
+        ++bad;
+      }
+    }
+  }
+  atomicAdd(&s_ok, ok);
+  atomicAdd(&s_bad, bad);
+  __syncthreads();
+  if (tid == 0) {
+    atomicAdd(&counts[0], (unsigned long long)s_ok);
+    atomicAdd(&counts[1], (unsigned long long)s_bad);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Alg. 1 (paper Sec. 3.1): one transport iteration's multigroup LOQD
 // equations and multigroup MEB (Eq. eb-group) on the fine grid, solved
 // together by Newton iterations in T with the QD factors fixed (the paper
@@ -2611,6 +2782,16 @@ void launch_prolong(const LaunchEnv &env, const Table &tab, int lev, const doubl
                     const float *r, double *Ef) {
   if (tab.n == 0) return;
   hipLaunchKernelGGL(k_prolong, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, lev, Ec, Eprev, r, Ef);
+}
+
+void launch_closure_seed(const LaunchEnv &env, const Table &tab, const double *T, const double *Tprev,
+                         const double *kappa, double *f, const MlpStats &ms, const float *params,
+                         unsigned long long *counts) {
+  if (tab.n == 0) return;
+  // at most one block per CU: every block stages the weights once
+  const unsigned nb = (unsigned)std::min(tab.n, 256);
+  hipLaunchKernelGGL(k_closure_seed, dim3(nb), dim3(64 * TR_CLS_WAVES), 0, env.stream, env.sd, env.pd, tab.d, tab.n,
+                     T, Tprev, kappa, f, ms, params, counts);
 }
 
 void launch_seed_f(const LaunchEnv &env, const float *out, double *f, long long n, unsigned long long *counts) {

@@ -10,25 +10,11 @@
 #include <vector>
 
 #include "tr.h"
+#include "tr_mlp_dev.h"
 
 namespace {
 
-constexpr int NH = 128, NINP = 8, NOUT = 2, NFEAT = 7;  // NFEAT of the NINP input columns are used
-// parameter vector offsets (float32): W1 [8][128], b1, W2 [128][128], b2, W3, b3, W4 [128][2], b4
-constexpr int OW1 = 0, OB1 = OW1 + NINP * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
-              OB3 = OW3 + NH * NH, OW4 = OB3 + NH, OB4 = OW4 + NH * NOUT, NPARAM = OB4 + NOUT;
-
-typedef short bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-// float -> bfloat16 bits, round to nearest, ties to even
-__device__ inline uint16_t to_bf16(float x) {
-  const uint32_t u = __float_as_uint(x);
-  const uint32_t lsb = (u >> 16) & 1u;
-  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
-}
-
-__device__ inline float from_bf16(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+using namespace trmlp;
 
 struct Gemm {
   const uint16_t *A;  // [M x K], element (m, k) at A[m * am + k * ak]

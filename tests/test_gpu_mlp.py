@@ -108,6 +108,52 @@ def test_features_and_targets_match_reference():
     sv.close()
 
 
+@pytest.mark.parametrize("with_prev", [False, True])
+def test_fused_seeding_matches_three_call_path(with_prev):
+    """tr_closure_seed (inputs, network and seeding in one kernel; the
+    weights are the A operand and the activations stay in registers between
+    layers) against the three-call path over a two-slab context with ragged
+    256-sample items: tr_mlp_features, tr_mlp_forward, then the seeding
+    formula f + 0.05 (2 s - 1) kept inside (0, 1).  Both run the network in
+    bfloat16 with float32 accumulation, in different orders (the products'
+    sums differ in the last float32 bits): seeded factors agree to 1e-5."""
+    import torch
+
+    slabs = [inputs.make_slab(37, 24, 4, T_left=0.9), inputs.make_slab(53, 40, 8, C1=9.0)]
+    levels = [[24, 6, 1], [40, 10, 1]]
+    sv = binding.Solver(slabs, levels, inputs.SolverCfg(levels=levels[0]))
+    note(f"fused seeding, 2 slabs, T_prev={'yes' if with_prev else 'no'}")
+    rng = np.random.default_rng(11)
+    theta = mlp.init_params(6)
+    net = binding.Mlp(theta)
+    mean, std = rng.normal(0, 1, mlp.NIN), rng.uniform(0.5, 2, mlp.NIN)
+    T = np.concatenate([10 ** rng.uniform(-3, 0, s.nx) for s in slabs])
+    Tp = T * rng.uniform(0.7, 1.3, T.size)
+    kap = np.concatenate([planck.opacity(s.nu_center, s.C_cell, T[o:o + s.nx]).ravel()
+                          for s, o in zip(slabs, sv.offsets(binding.TR_K_CELL))])
+    f = rng.uniform(0.02, 0.98, sv.total(binding.TR_K_GI))
+    f[:40] = rng.uniform(0.0, 0.03, 40)  # seeds that may leave (0, 1) are kept
+    T_prev = to_dev(Tp) if with_prev else None
+    X = sv.empty(binding.TR_K_GI, 8).float()
+    sv.mlp_features(to_dev(T), T_prev, to_dev(kap), to_dev(f), mean, std, X)
+    out = to_np(net.forward(X.reshape(-1, 8))).reshape(-1, 2).astype(np.float64)
+    cand = f + 0.05 * (2.0 * out[:, 0] - 1.0)
+    inside = (cand > 0.0) & (cand < 1.0)
+    ref = np.where(inside, cand, f)
+    sv.set_closure(net, mean, std)
+    fd = to_dev(f)
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    sv.closure_seed(to_dev(T), T_prev, to_dev(kap), fd, counts)
+    got = to_np(fd)
+    c = to_np(counts)
+    print(f"fused seeding: seeded {c[0]} kept {c[1]} of {f.size}; max |f - ref| {np.max(np.abs(got - ref)):.2e}",
+          flush=True)
+    assert int(c[0]) + int(c[1]) == f.size
+    assert abs(int(c[1]) - int(np.sum(~inside))) <= 2
+    assert np.max(np.abs(got - ref)) < 1e-5
+    sv.close()
+
+
 def test_training_and_learned_steps_converge_to_plain():
     """The closure trained on one slab's plain steps seeds a held-out slab
     (other opacity constants and boundary temperature, 32 directions, where a
