@@ -246,11 +246,9 @@ def run_steps(slabs, levels, cfg, steps, warmup, timing=False, tiles=None, closu
     return wall, acc
 
 
-def learned_vs_plain(slabs, levels, cfg, tiles, args, plain_ms, plain_sweeps):
+def train_closure(args):
     """Trains the closure on the plain solver's own steps of the paper-scale
-    workload (20 steps, a bounded sample of (group, cell) pairs), then times
-    this workload's steps with the closure seeding each step's factors (the
-    plain sweeps still decide convergence)."""
+    workload (its 20 steps, a bounded sample of (group, cell) pairs)."""
     from paper_2011_05427_amd import closure, inputs
 
     t0 = time.perf_counter()
@@ -258,13 +256,21 @@ def learned_vs_plain(slabs, levels, cfg, tiles, args, plain_ms, plain_sweeps):
     ds = closure.generate(train_slabs[0], train_cfg, train_cfg.levels, nsteps=train_steps,
                           n_samples=args.train_samples, seed=0)
     net, losses = closure.train(ds, epochs=args.train_epochs, batch=4096, lr=1e-3, seed=0)
-    train_s = time.perf_counter() - t0
-    wall, acc = run_steps(slabs, levels, cfg, args.steps, args.warmup, tiles=tiles, closure=(net, ds.mean, ds.std))
-    ms = 1e3 * wall / args.steps
+    return {"net": net, "ds": ds, "losses": losses, "train_s": time.perf_counter() - t0,
+            "epochs": args.train_epochs}
+
+
+def learned_vs_plain(slabs, levels, cfg, tiles, steps, warmup, plain_ms, plain_sweeps, trained):
+    """Times a workload's steps with the trained closure seeding each step's
+    factors (the plain sweeps still decide convergence)."""
+    ds = trained["ds"]
+    wall, acc = run_steps(slabs, levels, cfg, steps, warmup, tiles=tiles, closure=(trained["net"], ds.mean, ds.std))
+    ms = 1e3 * wall / steps
     return {"ms_per_step": ms, "plain_ms_per_step": plain_ms, "speedup": plain_ms / ms,
-            "sweeps": int(sum(a.n_ti for a in acc)), "plain_sweeps": plain_sweeps, "seeded": int(acc[0].n_seeded),
-            "fallback": int(acc[0].n_fallback), "train_s": train_s, "samples": int(ds.X.shape[0]),
-            "epochs": args.train_epochs, "loss_first": losses[0], "loss_last": losses[-1],
+            "sweeps": int(sum(a.n_ti for a in acc)), "plain_sweeps": plain_sweeps,
+            "seeded": int(sum(a.n_seeded for a in acc)), "fallback": int(sum(a.n_fallback for a in acc)),
+            "train_s": trained["train_s"], "samples": int(ds.X.shape[0]), "epochs": trained["epochs"],
+            "loss_first": trained["losses"][0], "loss_last": trained["losses"][-1],
             "note": "network trained on the paper-scale workload's plain steps; at the start of every step it "
                     "seeds the cell factors with its predicted change; the plain sweeps decide convergence"}
 
@@ -587,14 +593,20 @@ def main():
         out["stage_adaptive"] = run_stage_adaptive(ins["slabs"], ins["levels"], ins["cfg"], args.steps, args.warmup,
                                                    ins["tiles"])
         progress("stage-adaptive run done")
+    trained = None
     if not args.no_learned:
-        out["learned"] = learned_vs_plain(ins["slabs"], ins["levels"], ins["cfg"], ins["tiles"], args,
-                                          out["ms_per_step"], ins["sweeps"])
+        trained = train_closure(args)
+        out["learned"] = learned_vs_plain(ins["slabs"], ins["levels"], ins["cfg"], ins["tiles"], args.steps,
+                                          args.warmup, out["ms_per_step"], ins["sweeps"], trained)
         progress("learned closure run done")
     torch.cuda.empty_cache()
     for extra in [e for e in args.extras.split(",") if e and e != args.workload]:
         r, xi = measure(extra, EXTRA_STEPS.get(extra, 4), args.warmup)
         r["steps"] = EXTRA_STEPS.get(extra, 4)
+        if trained is not None and extra == "batch":
+            # the learned closure on the batched shapes as well
+            r["learned"] = learned_vs_plain(xi["slabs"], xi["levels"], xi["cfg"], xi["tiles"], r["steps"],
+                                            args.warmup, r["ms_per_step"], xi["sweeps"], trained)
         if not args.no_cpu_baseline:
             r["cpu_baseline"] = cpu_baseline(extra, args.cpu_budget, xi["cfg"].lmax)
         out[{"paper": "paper_scale"}.get(extra, extra)] = r

@@ -19,6 +19,7 @@
 #define TR_GRAPH_CACHE 12
 
 #define TR_NBUCKET 6
+#define TR_LLC_BYTES (256LL << 20)  // last-level (Infinity) cache of the device
 
 namespace {
 
@@ -40,6 +41,9 @@ struct tr_ctx {
   // the group averages (radiation temperature from the grey E) and write the
   // sigma_R table; grey stages take tables at T~ and the plain restriction
   bool spectral = false;
+  // the sweep streams its intensities past the caches (non-temporal hint)
+  // when the previous and new arrays together exceed the last-level cache
+  bool sweep_nt = false;
   std::vector<SlabDev> hs;  // host copies of the slab descriptors
   std::vector<double> h_inc;
   // totals per kind
@@ -233,8 +237,8 @@ int sweep_bucket(int nx) {
 void launch_sweeps(const tr_ctx *c, const LaunchEnv &env, const Ctl *ctl, int pmode, const double *kappa,
                    const double *B, const void *Ip, void *Io, double *mom, double *bnd, bool timed = false) {
   for (int b = 0; b < TR_NBUCKET; ++b)
-    launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], c->sweep_S[b], c->cfg.precision == TR_PREC_F32_STORAGE, ctl,
-                 pmode, 0, kappa, B, Ip, Io, mom, bnd, timed ? c->ev_sw[b][0] : nullptr,
+    launch_sweep(env, c->t_sweep_b[b], c->sweep_K[b], c->sweep_S[b], c->cfg.precision == TR_PREC_F32_STORAGE,
+                 c->sweep_nt, ctl, pmode, 0, kappa, B, Ip, Io, mom, bnd, timed ? c->ev_sw[b][0] : nullptr,
                  timed ? c->ev_sw[b][1] : nullptr);
 }
 
@@ -582,6 +586,10 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
     tr_destroy(c);
     return code;
   };
+  {
+    const long long ibytes = c->n_I * (cfg->precision == TR_PREC_F32_STORAGE ? 4 : 8);
+    c->sweep_nt = 2 * ibytes > TR_LLC_BYTES;
+  }
 
   double *d_dx, *d_C, *d_mu, *d_w, *d_nue, *d_nuc;
   if ((rc = dalloc(c, &d_dx, c->n_cell)) || (rc = dalloc(c, &d_C, c->n_cell)) || (rc = dalloc(c, &d_mu, c->n_mu)) ||
@@ -887,12 +895,12 @@ int tr_autotune(tr_ctx *c, const double *I_prev, double *I_out, int reps, int *K
     double best = 1e300;
     for (int q = 0; q < 12 && !rc; ++q) {
       const int kk = candK[q / 3], ss = candS[q % 3];
-      launch_sweep(env, c->t_sweep_b[b], kk, ss, f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
-                   c->bnd);
+      launch_sweep(env, c->t_sweep_b[b], kk, ss, f32, c->sweep_nt, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out,
+                   c->mom, c->bnd);
       if (hipEventRecord(e0, st) != hipSuccess) rc = TR_EHIP;
       for (int r = 0; r < reps; ++r)
-        launch_sweep(env, c->t_sweep_b[b], kk, ss, f32, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev, I_out, c->mom,
-                     c->bnd);
+        launch_sweep(env, c->t_sweep_b[b], kk, ss, f32, c->sweep_nt, nullptr, PRED_ALL, 0, c->kappa, c->B, I_prev,
+                     I_out, c->mom, c->bnd);
       float ms = 0.f;
       if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess)

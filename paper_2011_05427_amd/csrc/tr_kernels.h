@@ -77,9 +77,11 @@ void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int p
 // {1, 2, 4} wavefronts share the directions of one (group, half range).
 // f32: corner intensities stored as float (binary64 arithmetic inside).
 // With ev0 / ev1 the launch records the kernel's own start and end on them.
-void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool f32, const Ctl *ctl, int pmode,
-                  int lcyc, const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
-                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// nt_hint: stream the intensities past the caches (arrays larger than the
+// last-level cache; see Pair).
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool f32, bool nt_hint, const Ctl *ctl,
+                  int pmode, int lcyc, const double *kappa, const double *B, const void *Ip, void *Io, double *mom,
+                  double *bnd, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_moments(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int pmode, int lcyc, const double *mom,
                     const double *bnd, double *f, double *fbnd, double *C, double *Phi);
 void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *ctl, int pmode, int lcyc, int level,

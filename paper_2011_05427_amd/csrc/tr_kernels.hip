@@ -293,10 +293,12 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int bytes) {
 }
 
 // Corner-pair storage of the intensities: binary64 or binary32 (the sweep
-// computes in binary64 either way).  The sweep streams the intensities (each
-// read once and written once per sweep, gigabytes apart from their next use),
-// so its loads and stores carry the non-temporal hint (cache policy NT);
-// `load` without the hint serves data read again soon (the moment partials).
+// computes in binary64 either way).  When the intensity arrays are larger
+// than the last-level cache the sweep streams them (each read once and
+// written once per sweep, gigabytes apart from their next use) and its loads
+// and stores carry the non-temporal hint (cache policy NT); smaller ones keep
+// the default policy, so that the next sweep finds them cached.  `load`
+// without a hint serves data read again soon (the moment partials).
 #define TR_CPOL_NT 2
 template <typename TI>
 struct Pair;
@@ -306,21 +308,25 @@ struct Pair<double> {
   static __device__ inline V load(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
   }
+  template <bool NT>
   static __device__ inline V load_stream(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, TR_CPOL_NT));
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? TR_CPOL_NT : 0));
   }
+  template <bool NT>
   static __device__ inline void store_stream(V v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, v), r, off, 0, TR_CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(tr_u32x4, v), r, off, 0, NT ? TR_CPOL_NT : 0);
   }
 };
 template <>
 struct Pair<float> {
   typedef float2 V;
+  template <bool NT>
   static __device__ inline V load_stream(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, TR_CPOL_NT));
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, NT ? TR_CPOL_NT : 0));
   }
+  template <bool NT>
   static __device__ inline void store_stream(V v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tr_u32x2, v), r, off, 0, TR_CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tr_u32x2, v), r, off, 0, NT ? TR_CPOL_NT : 0);
   }
 };
 
@@ -377,7 +383,7 @@ __host__ __device__ inline int sweep_lds_doubles(int K, int split) {
 
 // One work unit's share of directions, sweeping in the direction of
 // decreasing x (REV, mu < 0) or increasing x.
-template <int K, typename TI, bool REV>
+template <int K, typename TI, bool REV, bool NT>
 __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, int split,
                                   const double *__restrict__ kappa, const double *__restrict__ Bt,
                                   const TI *__restrict__ Ip, TI *__restrict__ Io, double *__restrict__ mom,
@@ -427,7 +433,7 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
     const __amdgpu_buffer_rsrc_t r =
         buf_rsrc(ip + (long long)(m0 + (j0 < j1 ? j0 : 0)) * nx * 2, j0 < j1 ? rowb : 0);
 #pragma unroll
-    for (int k = 0; k < K; ++k) nxt[k] = P::load_stream(r, cell_mem(0, k) * 2 * (int)sizeof(TI));
+    for (int k = 0; k < K; ++k) nxt[k] = P::template load_stream<NT>(r, cell_mem(0, k) * 2 * (int)sizeof(TI));
   }
   for (int pass = 0; pass < npass; ++pass) {
     double bb[K], ee[K], phi[K], chi[K], hh[K];
@@ -470,7 +476,7 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
         const bool same = j + 1 < j1;
         const __amdgpu_buffer_rsrc_t r = buf_rsrc(ip + (long long)(same ? m + 1 : m0 + j0) * nx * 2, rowb);
 #pragma unroll
-        for (int k = 0; k < K; ++k) nxt[k] = P::load_stream(r, cell_mem(same ? pass : pass + 1, k) * 2 * (int)sizeof(TI));
+        for (int k = 0; k < K; ++k) nxt[k] = P::template load_stream<NT>(r, cell_mem(same ? pass : pass + 1, k) * 2 * (int)sizeof(TI));
       }
       const double mum = mu[m], wm = w[m];
       const double amu = fabs(mum), a = 0.5 * amu, a2 = a * a, aamu = a * amu;
@@ -533,14 +539,14 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
           PV o;
           o.x = (TI)v.x;
           o.y = (TI)v.y;
-          P::store_stream(o, ro, off[k]);
+          P::template store_stream<NT>(o, ro, off[k]);
         }
         __builtin_amdgcn_wave_barrier();
       } else {
         PV o;
         o.x = (TI)ox[0];
         o.y = (TI)oy[0];
-        P::store_stream(o, ro, off[0]);
+        P::template store_stream<NT>(o, ro, off[0]);
       }
       const double cout = fma(readlane_f64(A, 63), cin, readlane_f64(Bc, 63));
       if (lane == j) carry = cout;
@@ -621,7 +627,7 @@ __device__ inline void sweep_unit(const SlabDev &S, ProbDev pd, int g, int sub, 
 // shares one (group, half range), wavefront `sub` taking a contiguous share
 // of its directions; the moment and outflow partials are added through LDS
 // in wavefront order (more wavefronts in flight for small problems).
-template <int K, typename TI>
+template <int K, typename TI, bool NT>
 __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, ProbDev pd,
                                                const Item *__restrict__ tab, int nitems, int split, const Ctl *ctl,
                                                int pmode, int lcyc, const double *__restrict__ kappa,
@@ -642,9 +648,9 @@ __global__ __launch_bounds__(256) void k_sweep(const SlabDev *__restrict__ sd, P
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
   if (half)
-    sweep_unit<K, TI, true>(S, pd, it.idx, sub, split, kappa, Bt, Ip, Io, mom, bnd, sred);
+    sweep_unit<K, TI, true, NT>(S, pd, it.idx, sub, split, kappa, Bt, Ip, Io, mom, bnd, sred);
   else
-    sweep_unit<K, TI, false>(S, pd, it.idx, sub, split, kappa, Bt, Ip, Io, mom, bnd, sred);
+    sweep_unit<K, TI, false, NT>(S, pd, it.idx, sub, split, kappa, Bt, Ip, Io, mom, bnd, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -2605,25 +2611,33 @@ void launch_dS_sum(const LaunchEnv &env, const Table &tab, const Ctl *ctl, int p
   hipLaunchKernelGGL(k_dS_sum, blocks(tab.n), dim3(256), 0, env.stream, env.sd, tab.d, ctl, pmode, lcyc, dSpart, dS);
 }
 
-void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool f32, const Ctl *ctl, int pmode,
-                  int lcyc, const double *kappa, const double *B, const void *Ip, void *Io, double *mom, double *bnd,
-                  hipEvent_t ev0, hipEvent_t ev1) {
+void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool f32, bool nt_hint, const Ctl *ctl,
+                  int pmode, int lcyc, const double *kappa, const double *B, const void *Ip, void *Io, double *mom,
+                  double *bnd, hipEvent_t ev0, hipEvent_t ev1) {
   if (tab.n == 0) return;
   const int waves = 2 * tab.n;
   const int nb = split == 1 ? (waves + 3) / 4 : waves;
   const int nt = split == 1 ? 256 : 64 * split;
   const size_t lds = (size_t)sweep_lds_doubles(K, split) * sizeof(double);
-#define TR_SWEEP_K(KK, TT)                                                                                          \
-  do {                                                                                                              \
-    if (ev0)                                                                                                        \
-      hipExtLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(nt), lds, env.stream, ev0, ev1, 0, env.sd, env.pd, \
-                            tab.d, tab.n, split, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip),        \
-                            static_cast<TT *>(Io), mom, bnd);                                                     \
-    else                                                                                                            \
-      hipLaunchKernelGGL((k_sweep<KK, TT>), blocks(nb), dim3(nt), lds, env.stream, env.sd, env.pd, tab.d, tab.n,  \
-                         split, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip), static_cast<TT *>(Io), mom, \
-                         bnd);                                                                                      \
+#define TR_SWEEP_KN(KK, TT, NN)                                                                                      \
+  do {                                                                                                                 \
+    if (ev0)                                                                                                           \
+      hipExtLaunchKernelGGL((k_sweep<KK, TT, NN>), blocks(nb), dim3(nt), lds, env.stream, ev0, ev1, 0, env.sd,       \
+                            env.pd, tab.d, tab.n, split, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip),   \
+                            static_cast<TT *>(Io), mom, bnd);                                                        \
+    else                                                                                                               \
+      hipLaunchKernelGGL((k_sweep<KK, TT, NN>), blocks(nb), dim3(nt), lds, env.stream, env.sd, env.pd, tab.d, tab.n, \
+                         split, ctl, pmode, lcyc, kappa, B, static_cast<const TT *>(Ip), static_cast<TT *>(Io), mom,    \
+                         bnd);                                                                                         \
   } while (0)
+#define TR_SWEEP_K(KK, TT)                \
+  do {                                    \
+    if (stream_hint)                      \
+      TR_SWEEP_KN(KK, TT, true);          \
+    else                                  \
+      TR_SWEEP_KN(KK, TT, false);         \
+  } while (0)
+  const bool stream_hint = nt_hint;
   if (f32) {
     switch (K) {
       case 1: TR_SWEEP_K(1, float); break;
@@ -2639,6 +2653,7 @@ void launch_sweep(const LaunchEnv &env, const Table &tab, int K, int split, bool
       default: TR_SWEEP_K(4, double); break;
     }
   }
+#undef TR_SWEEP_KN
 #undef TR_SWEEP_K
 }
 
