@@ -52,6 +52,22 @@ __device__ inline bool pred_ok(const Ctl *ctl, int slab, int mode, int l) {
   return true;
 }
 
+// 1 - e^{-y} for 0 <= y < 0.1 by its Taylor series y - y^2/2! + ... - y^10/10!
+// (the remainder is below y^11/11! < 3e-19 relative).
+__device__ inline double om_series(double y) {
+  double p = -1.0 / 3628800.0;                 // -1/10!
+  p = fma(p, y, 1.0 / 362880.0);               //  1/9!
+  p = fma(p, y, -1.0 / 40320.0);               // -1/8!
+  p = fma(p, y, 1.0 / 5040.0);                 //  1/7!
+  p = fma(p, y, -1.0 / 720.0);                 // -1/6!
+  p = fma(p, y, 1.0 / 120.0);                  //  1/5!
+  p = fma(p, y, -1.0 / 24.0);                  // -1/4!
+  p = fma(p, y, 1.0 / 6.0);                    //  1/3!
+  p = fma(p, y, -0.5);                         // -1/2!
+  p = fma(p, y, 1.0);
+  return p * y;
+}
+
 // Opacity and group Planck function of group g (centre nu, edge integrals
 // lo / hi) in a cell (1/T = iT, opacity constant Cc, scale = a_R c T^4 / 2 /
 // (pi^4 / 15)); returns the group's term of dS = d/dT sum 2 kappa B.  Shared
@@ -61,12 +77,47 @@ __device__ inline double planck_group(double nu, const EdgeQ &lo, const EdgeQ &h
   Bg = scale * q_interval(lo, hi);
   const double dBg = (4.0 * Bg - scale * (hi.g4 - lo.g4)) * iT;
   const double y = nu * iT;
-  // 1 - e^{-y} from the same exponential unless y is small (cancellation)
+  // 1 - e^{-y}: from the same exponential for y >= 0.1 (relative error
+  // below 1e-15), else by its Taylor series (degree 10, below 1e-17)
   const double ey = exp(-y);
-  const double om = y > 0.5 ? 1.0 - ey : -expm1(-y);
+  const double om = y >= 0.1 ? 1.0 - ey : om_series(y);
   const double inu = rcp_nr(nu);
   const double cn = Cc * inu * inu;
   kap = cn * inu * om;
+  const double dkap = -cn * ey * iT * iT;
+  return 2.0 * (dkap * Bg + kap * dBg);
+}
+
+// Group Planck integral of a narrow interior group (nu_hi / nu_lo - 1 <=
+// 0.005) by 3-point Gauss-Legendre in x = nu / T: B_g = scale int x^3 / (e^x
+// - 1) and dB_g/dT = (scale / T) int x^4 e^x / (e^x - 1)^2 over [a/T, b/T]
+// (relative error below 1e-16 where the group carries emission); kappa as in
+// planck_group.  Returns the group's dS term.
+__device__ inline double planck_group_gl(double nu, double a, double b, double iT, double Cc, double scale,
+                                         double &kap, double &Bg) {
+  const double xa = a * iT, xb = b * iT;
+  const double hh = 0.5 * (xb - xa), xm = 0.5 * (xa + xb);
+  constexpr double r35 = 0.77459666924148337704;  // sqrt(3/5)
+  double q1 = 0.0, q2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double t = xm + hh * (j == 0 ? -r35 : j == 1 ? 0.0 : r35);
+    const double w = j == 1 ? 8.0 / 9.0 : 5.0 / 9.0;
+    const double et = exp(-t);
+    const double om = t >= 0.1 ? 1.0 - et : om_series(t);
+    const double ri = rcp_nr(om);
+    const double i1 = t * t * t * et * ri;
+    q1 = fma(w, i1, q1);
+    q2 = fma(w, i1 * t * ri, q2);
+  }
+  Bg = scale * hh * q1;
+  const double dBg = scale * iT * hh * q2;
+  const double y = nu * iT;
+  const double ey = exp(-y);
+  const double omk = y >= 0.1 ? 1.0 - ey : om_series(y);
+  const double inu = rcp_nr(nu);
+  const double cn = Cc * inu * inu;
+  kap = cn * inu * omk;
   const double dkap = -cn * ey * iT * iT;
   return 2.0 * (dkap * Bg + kap * dBg);
 }
@@ -1278,13 +1329,22 @@ __device__ inline double acc_groups(const SlabDev &S, ProbDev pd, int from, cons
     // the group's opacity and Planck integrals are evaluated
     const CellOpac co = cell_opac(S, pd, T, q.e - 1);
     EdgeQ lo = edge_q(co.nue[g0], co.iT);
+    bool lo_ok = true;  // lo holds edge g (narrow groups skip the edge series)
     for (int g = g0; g < g1; ++g) {
       EdgeVals a;
       load_group<FINE, OLD, RM_OPAC>(S, from, in, sol, g, true, q, 0.0, 0.0, 0.0, dsop, 0, a);
       double ka, Ba;
-      const EdgeQ hi = edge_q(co.nue[g + 1], co.iT);
-      dS += planck_group(co.nuc[g], lo, hi, co.iT, co.Cc, co.scale, ka, Ba);
-      lo = hi;
+      const double na = co.nue[g], nb = co.nue[g + 1];
+      if (na > 0.0 && nb <= 1.005 * na) {  // wavefront-uniform: the group's edges
+        dS += planck_group_gl(co.nuc[g], na, nb, co.iT, co.Cc, co.scale, ka, Ba);
+        lo_ok = false;
+      } else {
+        if (!lo_ok) lo = edge_q(na, co.iT);
+        const EdgeQ hi = edge_q(nb, co.iT);
+        dS += planck_group(co.nuc[g], lo, hi, co.iT, co.Cc, co.scale, ka, Ba);
+        lo = hi;
+        lo_ok = true;
+      }
       // right cell of the edge = own cell of the next lane
       const double ke = dpp_f64<DPP_WAVE_SHL1, 0xf>(ka, 0.0), Be = dpp_f64<DPP_WAVE_SHL1, 0xf>(Ba, 0.0);
       a.se = ke;

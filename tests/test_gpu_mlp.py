@@ -151,6 +151,9 @@ def test_fused_seeding_matches_three_call_path(with_prev):
     assert int(c[0]) + int(c[1]) == f.size
     assert abs(int(c[1]) - int(np.sum(~inside))) <= 2
     assert np.max(np.abs(got - ref)) < 1e-5
+    sv.set_closure(None)
+    with pytest.raises(binding.TrError):
+        sv.closure_seed(to_dev(T), T_prev, to_dev(kap), fd, counts)  # no closure attached
     sv.close()
 
 
