@@ -276,23 +276,26 @@ def learned_vs_plain(slabs, levels, cfg, tiles, steps, warmup, plain_ms, plain_s
 
 
 def hierarchy_candidates(nlev):
-    """(grids, lmax) candidates for the stage-adaptive run: the two-grid
-    cycle, W through the finest and through the coarsest intermediate grid, F
-    over two grids and over all of them, and the full F with lmax 2."""
+    """(grids, lmax) candidates: the two-grid cycle, W through each
+    intermediate grid, the coarsest intermediate grid with each finer one,
+    the full F, and lmax 2 through the coarsest and the finest intermediate
+    grid (grid indices of the workload's hierarchy)."""
     mid = list(range(1, nlev - 1))
-    if not mid:
-        return [((), 1), ((), 2)]
-    c = [((), 1), ((mid[0],), 1), (tuple(reversed(mid)), 1)]
+    cands = [((), 1)] + [((g,), 1) for g in mid]
     if len(mid) > 1:
-        c += [((mid[-1],), 1), ((mid[-1], mid[0]), 1)]
-    c.append((tuple(reversed(mid)), 2))
-    return list(dict.fromkeys(c))
+        cands += [((mid[-1], g), 1) for g in mid[:-1]] + [(tuple(reversed(mid)), 1)]
+        cands += [((mid[-1],), 2), ((mid[0],), 2)]
+    elif mid:
+        cands += [((mid[0],), 2)]
+    return list(dict.fromkeys(cands))
 
 
 def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles):
     """The same steps with the grid hierarchy and lmax chosen per step by
-    ``tuning.CostModelSchedule`` (sweep kernel time measured in the set-up;
-    every candidate's graphs captured in untimed warmup steps)."""
+    ``tuning.CostModelSchedule``.  Untimed set-up: the sweep kernel time, and
+    every candidate's first 2 steps from the initial state (after 2 steps
+    that capture its graphs), which seed the model with measurements over the
+    same steps."""
     import torch
 
     from paper_2011_05427_amd import binding, tuning
@@ -303,13 +306,23 @@ def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles):
     st = sv.new_state()
     sv.state_init(st, slabs[0].T0)
     t_sweep = tuning.measure_sweep_ms(sv, st)
+    seed = {}
     for cand in cands:
         tuning.apply_schedule(sv, cand)
         sv.state_init(st, slabs[0].T0)
         for _ in range(max(warmup, 2)):
             sv.step(st)
+        sv.state_init(st, slabs[0].T0)
+        acc = (binding.TrStats * len(slabs))()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            sv.step(st, stats=acc)
+        torch.cuda.synchronize()
+        seed[cand] = (1e3 * (time.perf_counter() - t0), max(int(a.n_ti) for a in acc),
+                      max(int(a.n_c) for a in acc), 2)
     sv.state_init(st, slabs[0].T0)
-    ctl = tuning.CostModelSchedule(cands, t_sweep=t_sweep)
+    ctl = tuning.CostModelSchedule(cands, t_sweep=t_sweep, seed=seed)
     torch.cuda.synchronize()
     acc = (binding.TrStats * len(slabs))()
     t0 = time.perf_counter()
@@ -324,8 +337,10 @@ def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles):
             "sweeps": int(sum(a.n_ti for a in acc)), "cycles": int(sum(a.n_c for a in acc)),
             "t_sweep_ms": t_sweep, "choices": [name(c) for c, *_ in ctl.history],
             "candidates": [name(c) for c in cands],
+            "set_up_ms_per_step": {name(c): v[0] / v[3] for c, v in seed.items()},
             "note": "hierarchy (grids visited after each grey solve) and lmax per step from the cost model "
-                    "s t_sweep + (s + 1) k_c t_c; probe every 8 steps"}
+                    "s t_sweep + (s + 1) k_c t_c, seeded by every candidate's first 2 steps from the initial "
+                    "state (untimed); every 8th step re-measures a candidate predicted within 25% of the best"}
 
 
 def measure(workload, steps, warmup, tiles_opt=None, lmax_opt=None, fp32=False):
@@ -470,6 +485,41 @@ def measure(workload, steps, warmup, tiles_opt=None, lmax_opt=None, fp32=False):
     return res, internals
 
 
+def fixed_hierarchies(slabs, levels, cfg, steps, tiles):
+    """ms per step, sweeps and cycles of fixed grid hierarchies (the grids
+    visited after each grey solve, tr_set_grids) and lmax over the same steps
+    from the initial condition, after 2 untimed steps that capture each one's
+    graphs: the two-grid cycle, W through each intermediate grid, pairs, the
+    full F, and lmax 2 for the best single grids."""
+    import torch
+
+    from paper_2011_05427_amd import binding, tuning
+
+    cands = hierarchy_candidates(len(levels[0]))
+    sv = binding.Solver(slabs, levels, cfg)
+    sv.set_tiles(*tiles)
+    st = sv.new_state()
+    out = {}
+    for cand in cands:
+        tuning.apply_schedule(sv, cand)
+        sv.state_init(st, slabs[0].T0)
+        for _ in range(2):
+            sv.step(st)
+        sv.state_init(st, slabs[0].T0)
+        torch.cuda.synchronize()
+        acc = (binding.TrStats * len(slabs))()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sv.step(st, stats=acc)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        name = (",".join(str(levels[0][g]) for g in cand[0]) or "two-grid") + f"/l{cand[1]}"
+        out[name] = {"ms_per_step": ms, "sweeps": int(sum(a.n_ti for a in acc)),
+                     "cycles": int(sum(a.n_c for a in acc)), "lo_group_solves": int(sum(a.n_lo for a in acc))}
+    sv.close()
+    return out
+
+
 def alg1_vs_cycles(slabs, cfg, candidates, steps, warmup=1):
     """Time-to-solution of the single-grid method (Alg. 1, tr_alg1_step) and
     of multigrid cycles on the same steps from the initial condition:
@@ -552,6 +602,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-closure comparison")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the stage-adaptive schedule run")
     ap.add_argument("--no-alg1", action="store_true", help="skip the single-grid (Alg. 1) comparison")
+    ap.add_argument("--hierarchies", action="store_true",
+                    help="also time fixed grid hierarchies of the workload over the same steps")
     ap.add_argument("--train-samples", type=int, default=1000000)
     ap.add_argument("--train-epochs", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -593,6 +645,10 @@ def main():
         out["stage_adaptive"] = run_stage_adaptive(ins["slabs"], ins["levels"], ins["cfg"], args.steps, args.warmup,
                                                    ins["tiles"])
         progress("stage-adaptive run done")
+    if args.hierarchies:
+        out["fixed_hierarchies"] = fixed_hierarchies(ins["slabs"], ins["levels"], ins["cfg"], args.steps,
+                                                     ins["tiles"])
+        progress("fixed hierarchies done")
     trained = None
     if not args.no_learned:
         trained = train_closure(args)

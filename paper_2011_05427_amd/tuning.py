@@ -212,22 +212,50 @@ class CostModelSchedule:
     remain, the per-step cycle of iteration s = 0 weighs more) without
     running every candidate.  Weighted means use weight `decay` on the older
     value.  Unmeasured candidates run first (in the given order); every
-    `probe`-th step re-runs the candidate measured longest ago.  Deterministic
-    in the recorded counts and times (ties: candidate order)."""
+    `probe`-th step re-runs the candidate measured longest ago among those
+    predicted within `probe_margin` of the best.  `seed` starts the model from
+    measurements of the candidates over the same steps (an untimed set-up).
+    Deterministic in the recorded counts and times (ties: candidate order)."""
 
-    def __init__(self, candidates, t_sweep: float, probe: int = 8, decay: float = 0.5, ratio_decay: float = 0.9):
-        self.cands = [(tuple(c[0]) if isinstance(c[0], (tuple, list)) else int(c[0]), int(c[1]))
-                      for c in candidates]
+    def __init__(self, candidates, t_sweep: float, probe: int = 8, decay: float = 0.5, ratio_decay: float = 0.9,
+                 seed=None, probe_margin: float = 1.25):
+        self.cands = [self._norm(c) for c in candidates]
         self.ratio_decay = float(ratio_decay)
         if not self.cands:
             raise ValueError("no candidate schedule")
-        if probe < 0 or not (0.0 <= decay < 1.0) or not (t_sweep >= 0.0):
-            raise ValueError("probe >= 0, 0 <= decay < 1 and t_sweep >= 0 required")
-        self.t_sweep, self.probe, self.decay = float(t_sweep), probe, decay
+        if probe < 0 or not (0.0 <= decay < 1.0) or not (t_sweep >= 0.0) or not (probe_margin >= 1.0):
+            raise ValueError("probe >= 0, 0 <= decay < 1, t_sweep >= 0 and probe_margin >= 1 required")
+        self.t_sweep, self.probe, self.decay, self.margin = float(t_sweep), probe, decay, float(probe_margin)
         self.r, self.k_c, self.t_c, self.seen = {}, {}, {}, {}
         self.d = None
         self.k = 0
         self.history = []
+        if seed:
+            self._seed(seed)
+
+    @staticmethod
+    def _norm(c):
+        return (tuple(c[0]) if isinstance(c[0], (tuple, list)) else int(c[0]), int(c[1]))
+
+    def _seed(self, seed):
+        """seed: {candidate: (ms, sweeps, cycles, steps)} measured over the
+        same steps from the same state (an untimed set-up), so that the
+        sweep ratios carry no difference of stage.  The first candidate of
+        the list with a measurement is the reference (r = 1)."""
+        seed = {self._norm(c): v for c, v in seed.items()}
+        ref = next((c for c in self.cands if c in seed), None)
+        if ref is None:
+            return
+        s_ref = max(float(seed[ref][1]), 1.0)
+        for c in self.cands:
+            if c not in seed:
+                continue
+            ms, sw, cyc, n = (float(x) for x in seed[c])
+            self.r[c] = max(sw, 1.0) / s_ref
+            self.k_c[c] = cyc / (sw + n)
+            self.t_c[c] = max(ms - sw * self.t_sweep, 0.0) / max(cyc, 1.0)
+            self.seen[c] = -1
+        self.d = s_ref / max(float(seed[ref][3]), 1.0)
 
     def _mix(self, old, new):
         return float(new) if old is None else self.decay * old + (1.0 - self.decay) * float(new)
@@ -240,9 +268,13 @@ class CostModelSchedule:
         for c in self.cands:
             if c not in self.r:
                 return c
+        best = min(self.cands, key=lambda c: (self.predict(c), self.cands.index(c)))
         if self.probe and self.k > 0 and self.k % self.probe == 0:
-            return min(self.cands, key=lambda c: (self.seen[c], self.cands.index(c)))
-        return min(self.cands, key=lambda c: (self.predict(c), self.cands.index(c)))
+            # re-measure the candidate measured longest ago among those
+            # predicted within the margin of the best
+            near = [c for c in self.cands if self.predict(c) <= self.margin * self.predict(best)]
+            return min(near, key=lambda c: (self.seen[c], self.cands.index(c)))
+        return best
 
     def record(self, cand, ms: float, sweeps: int, cycles: int):
         sweeps, cycles = max(int(sweeps), 0), max(int(cycles), 1)

@@ -127,6 +127,30 @@ def test_cost_model_follows_the_stage_without_rerunning_candidates():
     assert ctl.predict(A) == pytest.approx(3.0) and ctl.predict(B) == pytest.approx(2.6)
 
 
+def test_seeded_cost_model_starts_from_the_set_up_and_probes_near_candidates():
+    """Seeded with every candidate's first 2 steps from the same state, the
+    controller starts with the cheapest prediction (no order bias from the
+    changing difficulty of early steps), and its periodic probes re-run only
+    candidates predicted within the margin of the best."""
+    A, B, C = ((), 1), ((1,), 1), ((2, 1), 1)
+    # 2 steps: A 7 sweeps at 0.4 ms/cycle, B 6 sweeps at 0.45, C 6 sweeps at 2.0
+    seed = {A: (7 * 1.0 + 9 * 0.4, 7, 9, 2), B: (6 * 1.0 + 8 * 0.45, 6, 8, 2), C: (6 * 1.0 + 8 * 2.0, 6, 8, 2)}
+    ctl = tuning.CostModelSchedule([A, B, C], t_sweep=1.0, probe=2, decay=0.0, seed=seed, probe_margin=1.25)
+    assert ctl.d == pytest.approx(3.5) and ctl.r[B] == pytest.approx(6 / 7)
+    # predicted costs at d = 3.5: A 3.5 + 4.5 (9/9) 0.4 = 5.3; B 3 + 4 (8/8) 0.45 = 4.8; C 3 + 4 * 2 = 11
+    assert ctl.predict(A) == pytest.approx(5.3) and ctl.predict(B) == pytest.approx(4.8)
+    picks = []
+    for _ in range(6):
+        c = ctl.choose()
+        picks.append(c)
+        ms = {A: 5.3, B: 4.8, C: 11.0}[c] * 3.5 / 3.5
+        s_ = {A: 3.5, B: 3.0, C: 3.0}[c]
+        ctl.record(c, ms, round(s_), round(s_) + 1)
+    assert picks[0] == B
+    assert C not in picks  # far outside the margin: never re-run
+    assert A in picks  # within 25% of the best: re-measured by a probe
+
+
 def test_cost_model_candidates_and_validation():
     ctl = tuning.CostModelSchedule([((4, 3, 2, 1), 1), (0, 2), ([1], 1)], t_sweep=0.5)
     assert ctl.cands == [((4, 3, 2, 1), 1), (0, 2), ((1,), 1)]
@@ -134,3 +158,5 @@ def test_cost_model_candidates_and_validation():
         tuning.CostModelSchedule([], t_sweep=1.0)
     with pytest.raises(ValueError):
         tuning.CostModelSchedule([(0, 1)], t_sweep=-1.0)
+    with pytest.raises(ValueError):
+        tuning.CostModelSchedule([(0, 1)], t_sweep=1.0, probe_margin=0.5)
