@@ -122,6 +122,16 @@ __device__ inline double planck_group_gl(double nu, double a, double b, double i
   return 2.0 * (dkap * Bg + kap * dBg);
 }
 
+// sum_{j=0..k} y^j / j! (Horner), so that int_y^inf t^k e^{-t} dt =
+// k! e^{-y} tail_poly<k>(y).
+template <int K>
+__device__ inline double tail_poly(double y) {
+  double t = 1.0;
+#pragma unroll
+  for (int j = K; j >= 1; --j) t = fma(t, y * (1.0 / j), 1.0);
+  return t;
+}
+
 // Group averages of the spectral opacity sigma(nu, T) = Cc / nu^3 (1 -
 // e^{-nu/T}) over the group [a, b] (b may be +inf), paper Sec. 2 and Sec. 3.1:
 //  - src = sigma_B,g B_g = int sigma B(nu, T) dnu, closed form (the factor
@@ -130,14 +140,17 @@ __device__ inline double planck_group_gl(double nu, double a, double b, double i
 //    2 d(src)/dT = 2 Cc K e^{-a/T} ((1 + a/T)(1 - e^{-d}) - d e^{-d}), d = (b-a)/T;
 //  - sE = sigma_E,g(T, T_r), sR = sigma_R,g(T, T_r) from Gauss-Legendre
 //    panels (8 nodes) in y = nu / T_r over [a/T_r, min(b/T_r, max(a/T_r, 8) +
-//    64)]: panel width 1, or with rho = T_r / T > 1 min(1, max(1/rho, y/2))
-//    from the panel's start y.  The factor e^{-y rho} grows off the real axis
+//    64)]: panel width 1 (2.5 from y = 8 on), or with rho = T_r / T > 1
+//    min(1, max(1/rho, y/2)) from the panel's start y.  The factor e^{-y rho} grows off the real axis
 //    at the rate rho, so panels close to y = 0 must be short on the scale
 //    1/rho and may grow geometrically away from it (their width then stays
 //    below half their distance to the imaginary axis, where the poles of
 //    1/(1 - e^{-y rho}) lie; those of 1/(1 - e^{-y}) are at 2 pi i k).  Both
 //    integrals of a ratio carry the common factor e^{a/T_r}, so no weight
 //    over- or underflows in the Wien tail.
+// Groups that lie wholly in the Wien tail of both weights (a / T_r >= 40,
+// a / T >= 40, (b - a) / T_r >= 0.5) take the closed forms of the four
+// integrals instead of the panels.
 __device__ inline double spectral_group(double a, double b, double T, double Tr, double Cc, double K, double &sE,
                                         double &src, double &sR) {
   constexpr double gx[4] = {0.18343464249564978, 0.525532409916329, 0.7966664774136267, 0.9602898564975362};
@@ -150,13 +163,32 @@ __device__ inline double spectral_group(double a, double b, double T, double Tr,
   const double tl = isinf(d) ? 0.0 : d * exp(-d);
   const double dS = 2.0 * Cc * K * ea * ((1.0 + xa) * omd - tl);
   const double iTr = 1.0 / Tr, rho = Tr * iT;
-  const double ya = a * iTr;
-  const double ytop = fmin(b * iTr, fmax(ya, 8.0) + 64.0);
+  const double ya = a * iTr, yb = b * iTr;
+  const double sc = Cc * iTr * iTr * iTr;
+  if (ya >= 40.0 && ya * rho >= 40.0 && yb - ya >= 0.5) {
+    // Wien tail of both weights over the whole group: 1 / (1 - e^{-y}) and
+    // 1 - e^{-y rho} equal 1 to below 1e-17, and the integrals are closed:
+    // int_ya^yb y^k e^{ya - y} dy = k! (p_k(ya) - p_k(yb) e^{ya - yb})
+    const double E = isinf(yb) ? 0.0 : exp(ya - yb);
+    const double pb = isinf(yb) ? 0.0 : E;  // multiplies p_k(yb); zero for the open group
+    const double ybf = isinf(yb) ? ya : yb;
+    const double i0 = 1.0 - E;
+    const double i3 = 6.0 * (tail_poly<3>(ya) - tail_poly<3>(ybf) * pb);
+    const double i4 = 24.0 * (tail_poly<4>(ya) - tail_poly<4>(ybf) * pb);
+    const double i7 = 5040.0 * (tail_poly<7>(ya) - tail_poly<7>(ybf) * pb);
+    sE = sc * i0 / i3;
+    sR = sc * i4 / i7;
+    return dS;
+  }
+  const double ytop = fmin(yb, fmax(ya, 8.0) + 64.0);
   const double hs = rho > 1.0 ? 1.0 / rho : 1.0;
+  const double eya = exp(-ya);  // e^{-y} = e^{ya - y} e^{-ya} (zero beyond the double range)
   double nE = 0.0, dE = 0.0, nR = 0.0, dR = 0.0;
   double y0 = ya;
   for (int panel = 0; y0 < ytop && panel < 4096; ++panel) {
-    const double y1 = fmin(ytop, y0 + fmin(1.0, fmax(hs, 0.5 * y0)));
+    // width 2.5 from y = 8 on (every factor but e^{ya - y} is flat there; the
+    // 8-point rule's error on e^{-y} is then below 1e-16 relative)
+    const double y1 = fmin(ytop, y0 + fmin(y0 >= 8.0 ? 2.5 : 1.0, fmax(hs, 0.5 * y0)));
     const double hm = 0.5 * (y1 - y0), cm = 0.5 * (y1 + y0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -164,8 +196,12 @@ __device__ inline double spectral_group(double a, double b, double T, double Tr,
       const double y = cm + (q < 4 ? -hm : hm) * gx[k];
       const double wq = hm * gw[k];
       const double e1 = exp(ya - y);
-      const double io = 1.0 / (-expm1(-y));
-      const double oz = -expm1(-y * rho);
+      // 1 - e^{-y} and 1 - e^{-y rho}: from the exponentials for arguments
+      // of 0.1 and more, else by their Taylor series
+      const double omy = y >= 0.1 ? 1.0 - e1 * eya : om_series(y);
+      const double yr = y * rho;
+      const double oz = yr >= 0.1 ? 1.0 - exp(-yr) : om_series(yr);
+      const double io = 1.0 / omy;
       const double y3 = y * y * y;
       const double bw = e1 * io;           // B(nu, T_r) e^{a/T_r} / (K T_r^3 y^3)
       const double rw = y3 * y * bw * io;  // dB/dT'(nu, T_r) e^{a/T_r} / (K T_r^2)
@@ -176,7 +212,6 @@ __device__ inline double spectral_group(double a, double b, double T, double Tr,
     }
     y0 = y1;
   }
-  const double sc = Cc * iTr * iTr * iTr;
   sE = sc * nE / dE;
   sR = sc * nR / dR;
   return dS;
