@@ -1438,7 +1438,6 @@ int tr_run(tr_ctx *c, const tr_state *s, int nsteps, tr_stats *stats, int *done,
 // low-order stage solves the multigroup LOQD equations and the multigroup MEB
 // (Eq. eb-group) together on the fine grid (Newton in T, see the kernels).
 // ---------------------------------------------------------------------------
-#define TR_A1_MAXNX 512
 #define TR_A1_NEWTON 60
 
 namespace {
@@ -1504,7 +1503,7 @@ int tr_alg1_step(tr_ctx *c, const tr_state *s, tr_stats *stats, hipStream_t st) 
       !s->Egrey || s->I_prev == s->I_out)
     return TR_EINVAL;
   for (const SlabDev &S : c->hs)
-    if (S.nx > TR_A1_MAXNX) return TR_EINVAL;
+    if (S.nx > TR_A1_MAX_CELLS) return TR_EINVAL;
   int rc = a1_alloc(c);
   if (rc) return rc;
   auto &w = c->a1;

@@ -173,6 +173,7 @@ void launch_closure_seed(const LaunchEnv &env, const Table &tab, const double *T
                          unsigned long long *counts);
 
 // Alg. 1 (single-grid multigroup LOQD + MEB by Newton in T; see the kernels).
+#define TR_A1_MAX_CELLS 512  // cells per slab of the Alg. 1 dense solve
 struct A1Args {
   LoIn in;                 // fine tables at T^k, QD factors, old-time values
   const double *dem;       // gi: d/dT of the group emission at T^k

@@ -2558,16 +2558,19 @@ __global__ __launch_bounds__(256) void k_a1_mred(const SlabDev *__restrict__ sd,
 __global__ __launch_bounds__(256) void k_a1_dense(const SlabDev *__restrict__ sd, A1Args a) {
   __shared__ double sv[256];
   __shared__ int si[256];
+  __shared__ double sl[TR_A1_MAX_CELLS];  // multipliers of the current column
+  __shared__ double sx;
   const int slab = blockIdx.x;
   if (!a1_on(a, slab)) return;
   const SlabDev &S = sd[slab];
-  const int n = S.nx, t = threadIdx.x;
+  const int n = S.nx, t = threadIdx.x, nt = blockDim.x;
   double *M = a.M + a.oM[slab];
   double *b = a.rhs + S.o_cell;
   for (int k = 0; k < n; ++k) {
+    // pivot: the largest |M[i][k]|, i >= k (ties: the smallest i)
     double best = -1.0;
     int bi = k;
-    for (int i = k + t; i < n; i += blockDim.x) {
+    for (int i = k + t; i < n; i += nt) {
       const double v = fabs(M[(long long)i * n + k]);
       if (v > best) {
         best = v;
@@ -2577,7 +2580,7 @@ __global__ __launch_bounds__(256) void k_a1_dense(const SlabDev *__restrict__ sd
     sv[t] = best;
     si[t] = bi;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    for (int h = nt / 2; h > 0; h >>= 1) {
       if (t < h && (sv[t + h] > sv[t] || (sv[t + h] == sv[t] && si[t + h] < si[t]))) {
         sv[t] = sv[t + h];
         si[t] = si[t + h];
@@ -2587,7 +2590,7 @@ __global__ __launch_bounds__(256) void k_a1_dense(const SlabDev *__restrict__ sd
     const int p = si[0];
     __syncthreads();
     if (p != k) {
-      for (int j = k + t; j < n; j += blockDim.x) {
+      for (int j = k + t; j < n; j += nt) {
         const double x = M[(long long)k * n + j];
         M[(long long)k * n + j] = M[(long long)p * n + j];
         M[(long long)p * n + j] = x;
@@ -2599,21 +2602,34 @@ __global__ __launch_bounds__(256) void k_a1_dense(const SlabDev *__restrict__ sd
       }
     }
     __syncthreads();
+    // multipliers (thread per row), then the trailing update with a thread
+    // per column walking the rows (each row access coalesced)
     const double piv = M[(long long)k * n + k];
-    for (int i = k + 1 + t; i < n; i += blockDim.x) {
+    const double bk = b[k];
+    for (int i = k + 1 + t; i < n; i += nt) {
       const double l = M[(long long)i * n + k] / piv;
-      for (int j = k + 1; j < n; ++j) M[(long long)i * n + j] -= l * M[(long long)k * n + j];
-      b[i] -= l * b[k];
+      sl[i] = l;
+      b[i] -= l * bk;
+    }
+    __syncthreads();
+    for (int j = k + 1 + t; j < n; j += nt) {
+      const double mkj = M[(long long)k * n + j];
+      double *col = M + j;
+      for (int i = k + 1; i < n; ++i) col[(long long)i * n] -= sl[i] * mkj;
     }
     __syncthreads();
   }
-  if (t == 0) {
-    double *x = a.phi + S.o_cell;
-    for (int i = n - 1; i >= 0; --i) {
-      double s = b[i];
-      for (int j = i + 1; j < n; ++j) s -= M[(long long)i * n + j] * x[j];
-      x[i] = s / M[(long long)i * n + i];
+  // back substitution by columns: x_i, then every row above drops its term
+  double *x = a.phi + S.o_cell;
+  for (int i = n - 1; i >= 0; --i) {
+    if (t == 0) {
+      sx = b[i] / M[(long long)i * n + i];
+      x[i] = sx;
     }
+    __syncthreads();
+    const double xi = sx;
+    for (int r = t; r < i; r += nt) b[r] -= M[(long long)r * n + i] * xi;
+    __syncthreads();
   }
 }
 
