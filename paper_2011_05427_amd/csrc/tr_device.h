@@ -121,7 +121,7 @@ __device__ inline EdgeQ edge_q(double nu, double inv_T) {
     e.head = q_head(x); e.tail = 0.0; e.is_tail = 0;
     double x2 = x * x;
     e.g4 = x2 * x2 * rcp_nr(expm1(x));
-  } else if (isinf(x)) {
+  } else if (x >= 746.0) {  // e^{-x} underflows to zero (x = +inf included)
     e.head = 0.0; e.tail = 0.0; e.g4 = 0.0; e.is_tail = 1;
   } else {
     double ex = exp(-x);

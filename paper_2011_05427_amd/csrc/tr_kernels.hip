@@ -78,8 +78,10 @@ __device__ inline double planck_group(double nu, const EdgeQ &lo, const EdgeQ &h
   const double dBg = (4.0 * Bg - scale * (hi.g4 - lo.g4)) * iT;
   const double y = nu * iT;
   // 1 - e^{-y}: from the same exponential for y >= 0.1 (relative error
-  // below 1e-15), else by its Taylor series (degree 10, below 1e-17)
-  const double ey = exp(-y);
+  // below 1e-15), else by its Taylor series (degree 10, below 1e-17); e^{-y}
+  // underflows to zero from y = 746 on
+  double ey = 0.0;
+  if (y < 746.0) ey = exp(-y);
   const double om = y >= 0.1 ? 1.0 - ey : om_series(y);
   const double inu = rcp_nr(nu);
   const double cn = Cc * inu * inu;
