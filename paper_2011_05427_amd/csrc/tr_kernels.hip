@@ -1350,6 +1350,17 @@ __device__ inline void add_group(const EdgeVals &v, const EdgeGeo &q, double (&r
   r[R_PHI] += b0 ? v.P0 : b1 ? v.P1 : 0.0;
 }
 
+// Adds one finer group in RM_OPAC: kappa, B of the lane's own cell (ka, Ba);
+// the right cell of the edge is the own cell of the next lane.
+template <bool OLD, int MODE>
+__device__ inline void acc_opac_group(EdgeVals &a, const EdgeGeo &q, double ka, double Ba, double (&acc)[R_NA]) {
+  const double ke = dpp_f64<DPP_WAVE_SHL1, 0xf>(ka, 0.0), Be = dpp_f64<DPP_WAVE_SHL1, 0xf>(Ba, 0.0);
+  a.se = ke;
+  a.em = 2.0 * ke * Be;
+  a.sr = ka * q.wm + ke * q.we;
+  add_group<OLD, MODE>(a, q, acc);
+}
+
 // Adds finer groups [g0, g1) (wave-uniform) at this lane's edge, two groups'
 // loads in flight per step, in ascending group order (a missing second group
 // of an odd count adds zeros, which leaves the sums unchanged).  RM_OPAC:
@@ -1365,29 +1376,35 @@ __device__ inline double acc_groups(const SlabDev &S, ProbDev pd, int from, cons
     // one group per step: its loads are issued first and are in flight while
     // the group's opacity and Planck integrals are evaluated
     const CellOpac co = cell_opac(S, pd, T, q.e - 1);
-    EdgeQ lo = edge_q(co.nue[g0], co.iT);
-    bool lo_ok = true;  // lo holds edge g (narrow groups skip the edge series)
+    // narrow groups (Gauss-Legendre) first, then the wide ones by their edge
+    // integrals, each in ascending order: the edge series' coefficients are
+    // not live while the narrow groups are evaluated
     for (int g = g0; g < g1; ++g) {
+      const double na = co.nue[g], nb = co.nue[g + 1];
+      if (!(na > 0.0 && nb <= 1.005 * na)) continue;  // wavefront-uniform
       EdgeVals a;
       load_group<FINE, OLD, RM_OPAC>(S, from, in, sol, g, true, q, 0.0, 0.0, 0.0, dsop, 0, a);
       double ka, Ba;
+      dS += planck_group_gl(co.nuc[g], na, nb, co.iT, co.Cc, co.scale, ka, Ba);
+      acc_opac_group<OLD, MODE>(a, q, ka, Ba, acc);
+    }
+    EdgeQ lo;
+    bool lo_ok = false;  // lo holds edge g
+    for (int g = g0; g < g1; ++g) {
       const double na = co.nue[g], nb = co.nue[g + 1];
-      if (na > 0.0 && nb <= 1.005 * na) {  // wavefront-uniform: the group's edges
-        dS += planck_group_gl(co.nuc[g], na, nb, co.iT, co.Cc, co.scale, ka, Ba);
+      if (na > 0.0 && nb <= 1.005 * na) {
         lo_ok = false;
-      } else {
-        if (!lo_ok) lo = edge_q(na, co.iT);
-        const EdgeQ hi = edge_q(nb, co.iT);
-        dS += planck_group(co.nuc[g], lo, hi, co.iT, co.Cc, co.scale, ka, Ba);
-        lo = hi;
-        lo_ok = true;
+        continue;
       }
-      // right cell of the edge = own cell of the next lane
-      const double ke = dpp_f64<DPP_WAVE_SHL1, 0xf>(ka, 0.0), Be = dpp_f64<DPP_WAVE_SHL1, 0xf>(Ba, 0.0);
-      a.se = ke;
-      a.em = 2.0 * ke * Be;
-      a.sr = ka * q.wm + ke * q.we;
-      add_group<OLD, MODE>(a, q, acc);
+      EdgeVals a;
+      load_group<FINE, OLD, RM_OPAC>(S, from, in, sol, g, true, q, 0.0, 0.0, 0.0, dsop, 0, a);
+      double ka, Ba;
+      if (!lo_ok) lo = edge_q(na, co.iT);
+      const EdgeQ hi = edge_q(nb, co.iT);
+      dS += planck_group(co.nuc[g], lo, hi, co.iT, co.Cc, co.scale, ka, Ba);
+      lo = hi;
+      lo_ok = true;
+      acc_opac_group<OLD, MODE>(a, q, ka, Ba, acc);
     }
   } else {
     const int dsp = MODE == RM_DSF ? S.dsnp[from] / S.lev_ng[from] : 0;
