@@ -1502,8 +1502,11 @@ int tr_alg1_step(tr_ctx *c, const tr_state *s, tr_stats *stats, hipStream_t st) 
   if (!c || !s || !s->T || !s->I_prev || !s->I_out || !s->E || !s->F || !s->Ebnd || !s->f || !s->fbnd || !s->C ||
       !s->Egrey || s->I_prev == s->I_out)
     return TR_EINVAL;
-  for (const SlabDev &S : c->hs)
+  int max_nx = 0;
+  for (const SlabDev &S : c->hs) {
     if (S.nx > TR_A1_MAX_CELLS) return TR_EINVAL;
+    max_nx = std::max(max_nx, S.nx);
+  }
   int rc = a1_alloc(c);
   if (rc) return rc;
   auto &w = c->a1;
@@ -1577,7 +1580,7 @@ int tr_alg1_step(tr_ctx *c, const tr_state *s, tr_stats *stats, hipStream_t st) 
       launch_a1_rhs(env, c->t_cell, a);
       launch_a1_cols(env, c->t_gi, a);
       launch_a1_mred(env, w.t_mm, a);
-      launch_a1_dense(env, ns, a);
+      launch_a1_dense(env, ns, max_nx, a);
       launch_a1_solve(env, c->t_g, a, true);
       launch_a1_update(env, ns, a, w.Tprev);
       launch_copy(env, c->kappa, w.kprev, c->n_gi);

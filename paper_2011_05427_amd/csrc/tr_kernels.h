@@ -174,6 +174,11 @@ void launch_closure_seed(const LaunchEnv &env, const Table &tab, const double *T
 
 // Alg. 1 (single-grid multigroup LOQD + MEB by Newton in T; see the kernels).
 #define TR_A1_MAX_CELLS 512  // cells per slab of the Alg. 1 dense solve
+// The dense solve holds the matrix in registers up to TR_A1_REG_CELLS cells
+// (1024 threads, at most TR_A1_REG_SLOTS rows per thread: R = 1024 / nx row
+// groups need ceil(nx / R) <= 40 slots, true for nx <= 200).
+#define TR_A1_REG_CELLS 200
+#define TR_A1_REG_SLOTS 40
 struct A1Args {
   LoIn in;                 // fine tables at T^k, QD factors, old-time values
   const double *dem;       // gi: d/dT of the group emission at T^k
@@ -197,7 +202,7 @@ void launch_a1_solve(const LaunchEnv &env, const Table &t_g, const A1Args &a, bo
 void launch_a1_rhs(const LaunchEnv &env, const Table &t_cell, const A1Args &a);
 void launch_a1_cols(const LaunchEnv &env, const Table &t_gi, const A1Args &a);
 void launch_a1_mred(const LaunchEnv &env, const Table &t_mm, const A1Args &a);
-void launch_a1_dense(const LaunchEnv &env, int nslab, const A1Args &a);
+void launch_a1_dense(const LaunchEnv &env, int nslab, int max_nx, const A1Args &a);
 void launch_a1_update(const LaunchEnv &env, int nslab, const A1Args &a, double *Tprev);
 void launch_a1_outer(const LaunchEnv &env, int nslab, const Ctl *ctl, const double *T, const double *Ts,
                      const double *E, double *Esum, const double *Esp, double *out);

@@ -2652,6 +2652,127 @@ __global__ __launch_bounds__(256) void k_a1_dense(const SlabDev *__restrict__ sd
   }
 }
 
+// One block of 1024 threads per slab with the matrix in registers (nx <=
+// TR_A1_REG_CELLS): thread t < R n (R = ceil(n / NS) row groups, at most
+// 1024 / n) is column j = t mod n of row group q = t / n and holds rows i = q
+// NS + s (s < NS) of that column.  Gaussian elimination with partial pivoting
+// as in k_a1_dense (at step k the largest |M[i][k]| over the rows not yet
+// chosen, ties to the smallest i; multipliers M[i][k] times the pivot's
+// reciprocal), with the rows left in place: the pivot row of step k is
+// recorded, and a row leaves the elimination (multiplier 0) once chosen.
+// The pivot row, the multipliers and the right side live in LDS; a thread
+// keeps a bit per slot for rows still in the elimination.  Then back
+// substitution by columns in reverse step order.
+template <int NS>
+__global__ __launch_bounds__(1024) void k_a1_dense_reg(const SlabDev *__restrict__ sd, A1Args a) {
+  __shared__ double rowp[TR_A1_REG_CELLS];
+  __shared__ double sl[TR_A1_REG_CELLS + NS], sb[TR_A1_REG_CELLS + NS];  // + NS: slots past row n - 1
+  __shared__ int prow[TR_A1_REG_CELLS];                                    // pivot row of each step
+  __shared__ double cv[1024];
+  __shared__ int ci[1024];
+  __shared__ double s_x;
+  const int slab = blockIdx.x;
+  if (!a1_on(a, slab)) return;
+  const SlabDev &S = sd[slab];
+  const int n = S.nx, t = threadIdx.x;
+  const int R = (n + NS - 1) / NS;
+  const int q = t / n, j = t - q * n;
+  const bool own = q < R;  // threads R n .. 1023 hold nothing
+  const int r0 = q * NS;   // first row of the group
+  const int sn = own ? min(NS, n - r0) : 0;  // slots s < sn hold rows < n
+  const double *M = a.M + a.oM[slab];
+  double *b = a.rhs + S.o_cell;
+  double m[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) m[s] = s < sn ? M[(long long)(r0 + s) * n + j] : 0.0;
+  unsigned long long live = sn >= 64 ? ~0ull : ((1ull << sn) - 1);  // rows still in the elimination
+  if (t < n) sb[t] = b[t];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    // pivot candidates of column k, one per row group (rows in ascending
+    // order: ties keep the smaller)
+    if (own && j == k) {
+      double best = -1.0;
+      int bs = NS;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double v = fabs(m[s]);
+        const bool take = ((live >> s) & 1ull) && v > best;
+        best = take ? v : best;
+        bs = take ? s : bs;
+      }
+      cv[q] = best;
+      ci[q] = bs < NS ? r0 + bs : n;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double best = -1.0;
+      int bi = n;
+      for (int r = 0; r < R; ++r)
+        if (cv[r] > best) {
+          best = cv[r];
+          bi = ci[r];
+        }
+      prow[k] = bi;
+    }
+    __syncthreads();
+    const int p = prow[k];
+    const int dp = p - r0;  // slot of row p in this group (if 0 <= dp < NS)
+    if (own && dp >= 0 && dp < NS) {  // the group holding the pivot row
+      double vp = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) vp = s == dp ? m[s] : vp;
+      rowp[j] = vp;
+      live &= ~(1ull << dp);
+    }
+    __syncthreads();
+    if (own && j == k) {  // multipliers of column k (0 for rows out of the elimination)
+      const double rp = 1.0 / rowp[k], bp = sb[p];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double l = ((live >> s) & 1ull) ? m[s] * rp : 0.0;
+        sl[r0 + s] = l;
+        sb[r0 + s] -= l * bp;
+      }
+    }
+    __syncthreads();
+    if (own && j > k) {
+      const double mpj = rowp[j];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) m[s] -= sl[r0 + s] * mpj;
+    }
+    __syncthreads();
+  }
+  // back substitution by columns in reverse step order: x_k from the pivot
+  // row of step k, then the pivot rows of earlier steps drop their term
+  double *x = a.phi + S.o_cell;
+  unsigned long long pend = sn >= 64 ? ~0ull : ((1ull << sn) - 1);  // rows of steps < k
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = prow[k];
+    const int dp = p - r0;
+    const bool mine = own && dp >= 0 && dp < NS;
+    if (mine) pend &= ~(1ull << dp);
+    if (mine && j == k) {
+      double d = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) d = s == dp ? m[s] : d;
+      const double xk = sb[p] / d;
+      s_x = xk;
+      x[k] = xk;
+    }
+    __syncthreads();
+    if (own && j == k) {
+      const double xk = s_x;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double u = ((pend >> s) & 1ull) ? m[s] : 0.0;
+        sb[r0 + s] -= u * xk;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // One block per slab (blockDim >= nx): T^{k+1} = T^k + alpha + beta phi
 // (floored at T^k / 2), the previous iterate's T kept, and max|dT| / max|T|.
 __global__ __launch_bounds__(512) void k_a1_update(const SlabDev *__restrict__ sd, A1Args a, double *Tprev) {
@@ -2966,8 +3087,24 @@ void launch_a1_cols(const LaunchEnv &env, const Table &t_gi, const A1Args &a) {
 void launch_a1_mred(const LaunchEnv &env, const Table &t_mm, const A1Args &a) {
   if (t_mm.n) hipLaunchKernelGGL(k_a1_mred, blocks(t_mm.n), dim3(256), 0, env.stream, env.sd, t_mm.d, a);
 }
-void launch_a1_dense(const LaunchEnv &env, int nslab, const A1Args &a) {
-  hipLaunchKernelGGL(k_a1_dense, dim3((unsigned)nslab), dim3(256), 0, env.stream, env.sd, a);
+void launch_a1_dense(const LaunchEnv &env, int nslab, int max_nx, const A1Args &a) {
+  // registers for every slab of at most TR_A1_REG_CELLS cells (slots per
+  // thread from the largest: ceil(n / (1024 / n)) rows), else the
+  // global-memory elimination
+  const int ns = max_nx > 0 ? (max_nx + 1024 / max_nx - 1) / (1024 / max_nx) : 1;
+  if (max_nx > TR_A1_REG_CELLS)
+    hipLaunchKernelGGL(k_a1_dense, dim3((unsigned)nslab), dim3(256), 0, env.stream, env.sd, a);
+  else if (ns <= 8)
+    hipLaunchKernelGGL(k_a1_dense_reg<8>, dim3((unsigned)nslab), dim3(1024), 0, env.stream, env.sd, a);
+  else if (ns <= 16)
+    hipLaunchKernelGGL(k_a1_dense_reg<16>, dim3((unsigned)nslab), dim3(1024), 0, env.stream, env.sd, a);
+  else if (ns <= 24)
+    hipLaunchKernelGGL(k_a1_dense_reg<24>, dim3((unsigned)nslab), dim3(1024), 0, env.stream, env.sd, a);
+  else if (ns <= 32)
+    hipLaunchKernelGGL(k_a1_dense_reg<32>, dim3((unsigned)nslab), dim3(1024), 0, env.stream, env.sd, a);
+  else
+    hipLaunchKernelGGL(k_a1_dense_reg<TR_A1_REG_SLOTS>, dim3((unsigned)nslab), dim3(1024), 0, env.stream,
+                       env.sd, a);
 }
 void launch_a1_update(const LaunchEnv &env, int nslab, const A1Args &a, double *Tprev) {
   hipLaunchKernelGGL(k_a1_update, dim3((unsigned)nslab), dim3(512), 0, env.stream, env.sd, a, Tprev);
