@@ -43,6 +43,10 @@ CASES = {
     "spectral": dict(nx=8, ng=16, nmu=4, dt=0.004, T0=0.01, C1=4.0, C2=1.0, nu_lo=1e-3, nu_hi=30.0,
                      opacity=inputs.OPAC_SPECTRAL),
     "wider": dict(nx=60, ng=32, nmu=8, dt=0.002),
+    # the largest register-resident dense solve (40 rows per thread) and the
+    # global-memory elimination beyond it
+    "dense_registers_200": dict(nx=200, ng=4, nmu=2, dt=0.002, steps=1),
+    "dense_global_230": dict(nx=230, ng=4, nmu=2, dt=0.002, steps=1),
 }
 
 
@@ -50,15 +54,16 @@ CASES = {
 def test_alg1_steps_match_the_oracle(case):
     kw = dict(CASES[case])
     nx, ng, nmu = kw.pop("nx"), kw.pop("ng"), kw.pop("nmu")
+    steps = kw.pop("steps", 2)
     slab = inputs.make_slab(nx, ng, nmu, **kw)
     cfg = inputs.SolverCfg(levels=[ng, 1], eps=1e-13, max_outer=40)
-    note(f"Alg. 1 {case}: nx={nx} ng={ng} nmu={nmu}, 2 steps")
+    note(f"Alg. 1 {case}: nx={nx} ng={ng} nmu={nmu}, {steps} steps")
     pb = mlqd.problem_from_slab(slab)
     ref = mlqd.initial_state(pb, slab.T0)
     sv = binding.Solver([slab], [[ng, 1]], cfg)
     st = sv.new_state()
     sv.state_init(st, slab.T0)
-    for j in range(2):
+    for j in range(steps):
         ref = mlqd.alg1_step(pb, ref, eps=1e-13)
         gs = sv.alg1_step(st)
         note(f"  step {j}: {gs[0].n_ti} sweeps, Newton per transport iteration {list(gs[0].cycles[:gs[0].n_outer])}")
