@@ -2658,19 +2658,18 @@ __global__ __launch_bounds__(256) void k_a1_dense(const SlabDev *__restrict__ sd
 // NS + s (s < NS) of that column.  Gaussian elimination with partial pivoting
 // as in k_a1_dense (at step k the largest |M[i][k]| over the rows not yet
 // chosen, ties to the smallest i; multipliers M[i][k] times the pivot's
-// reciprocal), with the rows left in place: the pivot row of step k is
-// recorded, and a row leaves the elimination (multiplier 0) once chosen.
-// The pivot row, the multipliers and the right side live in LDS; a thread
-// keeps a bit per slot for rows still in the elimination.  Then back
-// substitution by columns in reverse step order.
+// reciprocal), with the rows left in place: the pivot row of each step is
+// recorded and a chosen row leaves the elimination.  Per step the owners of
+// column k copy it to LDS, one wavefront finds the pivot, a thread per row
+// forms its multiplier and right side while the pivot row's owners copy it
+// to LDS, and every thread of a column j > k updates its rows.  Back
+// substitution in reverse step order, a thread per row.
 template <int NS>
 __global__ __launch_bounds__(1024) void k_a1_dense_reg(const SlabDev *__restrict__ sd, A1Args a) {
   __shared__ double rowp[TR_A1_REG_CELLS];
-  __shared__ double sl[TR_A1_REG_CELLS + NS], sb[TR_A1_REG_CELLS + NS];  // + NS: slots past row n - 1
-  __shared__ int prow[TR_A1_REG_CELLS];                                    // pivot row of each step
-  __shared__ double cv[1024];
-  __shared__ int ci[1024];
-  __shared__ double s_x;
+  __shared__ double colk[TR_A1_REG_CELLS + NS], sl[TR_A1_REG_CELLS + NS];  // + NS: slots past row n - 1
+  __shared__ double sb[TR_A1_REG_CELLS];
+  __shared__ int prow[TR_A1_REG_CELLS], step_of[TR_A1_REG_CELLS];  // pivot row of a step, step of a row
   const int slab = blockIdx.x;
   if (!a1_on(a, slab)) return;
   const SlabDev &S = sd[slab];
@@ -2685,55 +2684,56 @@ __global__ __launch_bounds__(1024) void k_a1_dense_reg(const SlabDev *__restrict
   double m[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) m[s] = s < sn ? M[(long long)(r0 + s) * n + j] : 0.0;
-  unsigned long long live = sn >= 64 ? ~0ull : ((1ull << sn) - 1);  // rows still in the elimination
-  if (t < n) sb[t] = b[t];
+  if (t < n) {
+    sb[t] = b[t];
+    step_of[t] = n;  // not chosen yet
+  }
+  if (t < TR_A1_REG_CELLS + NS) sl[t] = 0.0;  // rows past n - 1 keep multiplier 0
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    // pivot candidates of column k, one per row group (rows in ascending
-    // order: ties keep the smaller)
     if (own && j == k) {
-      double best = -1.0;
-      int bs = NS;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const double v = fabs(m[s]);
-        const bool take = ((live >> s) & 1ull) && v > best;
-        best = take ? v : best;
-        bs = take ? s : bs;
-      }
-      cv[q] = best;
-      ci[q] = bs < NS ? r0 + bs : n;
+      for (int s = 0; s < NS; ++s) colk[r0 + s] = m[s];
     }
     __syncthreads();
-    if (t == 0) {
+    if (t < 64) {  // pivot: rows in ascending order per lane, ties to the smaller row
       double best = -1.0;
       int bi = n;
-      for (int r = 0; r < R; ++r)
-        if (cv[r] > best) {
-          best = cv[r];
-          bi = ci[r];
+      for (int i = t; i < n; i += 64) {
+        const double v = fabs(colk[i]);
+        if (step_of[i] == n && v > best) {
+          best = v;
+          bi = i;
         }
-      prow[k] = bi;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (t == 0) {
+        prow[k] = bi;
+        step_of[bi] = k;
+      }
     }
     __syncthreads();
     const int p = prow[k];
-    const int dp = p - r0;  // slot of row p in this group (if 0 <= dp < NS)
-    if (own && dp >= 0 && dp < NS) {  // the group holding the pivot row
+    if (t < n && t != p) {  // multiplier of row t (0 once chosen) and its right side
+      const double l = step_of[t] == n ? colk[t] * (1.0 / colk[p]) : 0.0;
+      sl[t] = l;
+      sb[t] -= l * sb[p];
+    }
+    if (t == p) sl[t] = 0.0;
+    const int dp = p - r0;
+    if (own && dp >= 0 && dp < NS) {  // the pivot row
       double vp = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) vp = s == dp ? m[s] : vp;
       rowp[j] = vp;
-      live &= ~(1ull << dp);
-    }
-    __syncthreads();
-    if (own && j == k) {  // multipliers of column k (0 for rows out of the elimination)
-      const double rp = 1.0 / rowp[k], bp = sb[p];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const double l = ((live >> s) & 1ull) ? m[s] * rp : 0.0;
-        sl[r0 + s] = l;
-        sb[r0 + s] -= l * bp;
-      }
     }
     __syncthreads();
     if (own && j > k) {
@@ -2743,32 +2743,19 @@ __global__ __launch_bounds__(1024) void k_a1_dense_reg(const SlabDev *__restrict
     }
     __syncthreads();
   }
-  // back substitution by columns in reverse step order: x_k from the pivot
-  // row of step k, then the pivot rows of earlier steps drop their term
+  // back substitution in reverse step order: x_k from the pivot row of step
+  // k, then the rows chosen at earlier steps drop their term
   double *x = a.phi + S.o_cell;
-  unsigned long long pend = sn >= 64 ? ~0ull : ((1ull << sn) - 1);  // rows of steps < k
   for (int k = n - 1; k >= 0; --k) {
-    const int p = prow[k];
-    const int dp = p - r0;
-    const bool mine = own && dp >= 0 && dp < NS;
-    if (mine) pend &= ~(1ull << dp);
-    if (mine && j == k) {
-      double d = 0.0;
+    if (own && j == k) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) d = s == dp ? m[s] : d;
-      const double xk = sb[p] / d;
-      s_x = xk;
-      x[k] = xk;
+      for (int s = 0; s < NS; ++s) colk[r0 + s] = m[s];
     }
     __syncthreads();
-    if (own && j == k) {
-      const double xk = s_x;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const double u = ((pend >> s) & 1ull) ? m[s] : 0.0;
-        sb[r0 + s] -= u * xk;
-      }
-    }
+    const int p = prow[k];
+    const double xk = sb[p] / colk[p];
+    if (t == 0) x[k] = xk;
+    if (t < n && step_of[t] < k) sb[t] -= colk[t] * xk;
     __syncthreads();
   }
 }
