@@ -2391,7 +2391,36 @@ __device__ inline void a1_row(const LevelView &v, int j, double c, double dt, do
   }
 }
 
-// Per cell: alpha, beta and the per-group emission couplings w_g.
+// Per cell: alpha, beta and the per-group emission couplings w_g.  The
+// arrays are passed as non-aliasing pointers (cell i's column of each [g][i]
+// array, stride nx) so that the group loops keep their loads in flight
+// across the stores.
+__device__ inline void a1_prep_cell(const SlabDev &S, const A1Args &a, long long oc, int nx,
+                                    const double *__restrict__ kap, const double *__restrict__ Bv,
+                                    const double *__restrict__ dem, const double *__restrict__ kprev,
+                                    const double *__restrict__ Ek, double *__restrict__ w) {
+  const double Tk = a.T[oc], c = S.c;
+  const double dTs = Tk - a.Tprev[oc];
+  const bool sec = !a.first && fabs(dTs) > 1e-8 * fabs(Tk);
+  double Ssum = 0.0, Sp = 0.0, cDE = 0.0;
+#pragma unroll 8
+  for (int g = 0; g < S.ng; ++g) {
+    const long long o = (long long)g * nx;
+    Ssum += 2.0 * kap[o] * Bv[o];
+    Sp += dem[o];
+    if (sec) cDE += c * (kap[o] - kprev[o]) / dTs * Ek[o];
+  }
+  const bool use = sec && !(cDE > 0.5 * (S.cv / S.dt + Sp));
+  const double den = S.cv / S.dt + Sp - (use ? cDE : 0.0);
+  a.alpha[oc] = (S.cv * (a.Told[oc] - Tk) / S.dt - Ssum) / den;
+  a.beta[oc] = 1.0 / den;
+#pragma unroll 8
+  for (int g = 0; g < S.ng; ++g) {
+    const long long o = (long long)g * nx;
+    w[o] = dem[o] - (use ? c * (kap[o] - kprev[o]) / dTs * Ek[o] : 0.0);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_a1_prep(const SlabDev *__restrict__ sd, ProbDev pd,
                                                  const Item *__restrict__ tab, A1Args a) {
   const Item it = tab[blockIdx.x];
@@ -2399,29 +2428,32 @@ __global__ __launch_bounds__(256) void k_a1_prep(const SlabDev *__restrict__ sd,
   const SlabDev &S = sd[it.slab];
   const int i = it.idx + threadIdx.x;
   if (i >= S.nx) return;
-  const long long oc = S.o_cell + i;
-  const double Tk = a.T[oc], c = S.c;
-  const double dTs = Tk - a.Tprev[oc];
-  const bool sec = !a.first && fabs(dTs) > 1e-8 * fabs(Tk);
-  double Ssum = 0.0, Sp = 0.0, cDE = 0.0;
-  for (int g = 0; g < S.ng; ++g) {
-    const long long o = S.o_gi + (long long)g * S.nx + i;
-    Ssum += 2.0 * a.in.kappa[o] * a.in.B[o];
-    Sp += a.dem[o];
-    if (sec) cDE += c * (a.in.kappa[o] - a.kprev[o]) / dTs * a.Ek[o];
-  }
-  const bool use = sec && !(cDE > 0.5 * (S.cv / S.dt + Sp));
-  const double den = S.cv / S.dt + Sp - (use ? cDE : 0.0);
-  a.alpha[oc] = (S.cv * (a.Told[oc] - Tk) / S.dt - Ssum) / den;
-  a.beta[oc] = 1.0 / den;
-  for (int g = 0; g < S.ng; ++g) {
-    const long long o = S.o_gi + (long long)g * S.nx + i;
-    a.w[o] = a.dem[o] - (use ? c * (a.in.kappa[o] - a.kprev[o]) / dTs * a.Ek[o] : 0.0);
-  }
+  const long long o = S.o_gi + i;
+  a1_prep_cell(S, a, S.o_cell + i, S.nx, a.in.kappa + o, a.in.B + o, a.dem + o, a.kprev + o, a.Ek + o, a.w + o);
 }
 
 // Per group: Thomas factors of its matrix (no pivoting: column diagonally
 // dominant M-matrix).  Items = (slab, first of 256 groups).
+__device__ inline void a1_factor_group(const SlabDev &S, const LevelView &v, int ng, double *__restrict__ ra_,
+                                       double *__restrict__ cp_, double *__restrict__ dn_) {
+  const int nx = S.nx;
+  double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, cpp = 0.0;
+  for (int j = 0; j <= nx + 1; ++j) {
+    if (j <= nx) a1_edge(v, j, S.c, S.inv_cdt, AkR, caR, cbR);
+    double ra, rb, rc, rd;
+    a1_row(v, j, S.c, S.dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+    const double dnj = rb - ra * cpp;
+    cpp = rc / dnj;
+    const long long o = (long long)j * ng;
+    ra_[o] = ra;
+    cp_[o] = cpp;
+    dn_[o] = dnj;
+    AkL = AkR;
+    caL = caR;
+    cbL = cbR;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_a1_factor(const SlabDev *__restrict__ sd, ProbDev pd,
                                                    const Item *__restrict__ tab, A1Args a) {
   const Item it = tab[blockIdx.x];
@@ -2430,27 +2462,60 @@ __global__ __launch_bounds__(256) void k_a1_factor(const SlabDev *__restrict__ s
   const int g = it.idx + threadIdx.x;
   if (g >= S.ng) return;
   const LevelView v = make_view<true>(S, pd, 0, a.in, g);
-  const long long base = S.o_gi + 2 * S.o_g;
-  const int nx = S.nx, ng = S.ng;
-  double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, cpp = 0.0;
+  const long long o = S.o_gi + 2 * S.o_g + g;  // row j of group g at o + j ng
+  a1_factor_group(S, v, S.ng, a.ra + o, a.cp + o, a.dn + o);
+}
+
+// Per group: the solve with the cell emission 2 kappa B + w (alpha + beta
+// phi) (phi null: 0); writes E, the boundary E and, with F, the fluxes.  The
+// rows (stride ng) and the outputs are non-aliasing pointers, so that a row's
+// loads need not wait for the previous row's store.
+__device__ inline void a1_solve_group(const SlabDev &S, const LevelView &v, const A1Args &a, int ng, int with_phi,
+                                      const double *__restrict__ ra_, const double *__restrict__ cp_,
+                                      const double *__restrict__ dn_, double *__restrict__ dp_,
+                                      const double *__restrict__ kap, const double *__restrict__ Bv,
+                                      const double *__restrict__ w, double *__restrict__ E, double *__restrict__ Eb,
+                                      double *__restrict__ F) {
+  const int nx = S.nx;
+  double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, dpp = 0.0;
   for (int j = 0; j <= nx + 1; ++j) {
     if (j <= nx) a1_edge(v, j, S.c, S.inv_cdt, AkR, caR, cbR);
+    double em = 0.0;
+    if (j >= 1 && j <= nx) {
+      const long long oc = S.o_cell + j - 1;
+      const double dT = a.alpha[oc] + (with_phi ? a.beta[oc] * a.phi[oc] : 0.0);
+      em = 2.0 * kap[j - 1] * Bv[j - 1] + w[j - 1] * dT;
+    }
     double ra, rb, rc, rd;
-    a1_row(v, j, S.c, S.dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
-    const double dnj = rb - ra * cpp;
-    cpp = rc / dnj;
-    const long long o = base + (long long)j * ng + g;
-    a.ra[o] = ra;
-    a.cp[o] = cpp;
-    a.dn[o] = dnj;
+    a1_row(v, j, S.c, S.dt, em, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+    const long long o = (long long)j * ng;
+    dpp = (rd - ra_[o] * dpp) / dn_[o];
+    dp_[o] = dpp;
     AkL = AkR;
     caL = caR;
     cbL = cbR;
   }
+  double u = 0.0;
+  for (int j = nx + 1; j >= 0; --j) {
+    const long long o = (long long)j * ng;
+    u = dp_[o] - (j <= nx ? cp_[o] * u : 0.0);
+    if (j == nx + 1)
+      Eb[1] = u;
+    else if (j == 0)
+      Eb[0] = u;
+    else
+      E[j - 1] = u;
+  }
+  if (F) {
+    for (int e = 0; e <= nx; ++e) {
+      double Ak, ca, cb;
+      a1_edge(v, e, S.c, S.inv_cdt, Ak, ca, cb);
+      const double uL = e == 0 ? Eb[0] : E[e - 1], uR = e == nx ? Eb[1] : E[e];
+      F[e] = Ak - ca * uR + cb * uL;
+    }
+  }
 }
 
-// Per group: the solve with the cell emission 2 kappa B + w (alpha + beta
-// phi) (phi null: 0); writes E, the boundary E and, with F, the fluxes.
 __global__ __launch_bounds__(256) void k_a1_solve(const SlabDev *__restrict__ sd, ProbDev pd,
                                                   const Item *__restrict__ tab, A1Args a, int with_phi) {
   const Item it = tab[blockIdx.x];
@@ -2459,48 +2524,11 @@ __global__ __launch_bounds__(256) void k_a1_solve(const SlabDev *__restrict__ sd
   const int g = it.idx + threadIdx.x;
   if (g >= S.ng) return;
   const LevelView v = make_view<true>(S, pd, 0, a.in, g);
-  const long long base = S.o_gi + 2 * S.o_g;
-  const int nx = S.nx, ng = S.ng;
-  const long long og = S.o_gi + (long long)g * nx;
-  double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, dpp = 0.0;
-  for (int j = 0; j <= nx + 1; ++j) {
-    if (j <= nx) a1_edge(v, j, S.c, S.inv_cdt, AkR, caR, cbR);
-    double em = 0.0;
-    if (j >= 1 && j <= nx) {
-      const long long oc = S.o_cell + j - 1, o = og + j - 1;
-      const double dT = a.alpha[oc] + (with_phi ? a.beta[oc] * a.phi[oc] : 0.0);
-      em = 2.0 * a.in.kappa[o] * a.in.B[o] + a.w[o] * dT;
-    }
-    double ra, rb, rc, rd;
-    a1_row(v, j, S.c, S.dt, em, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
-    const long long o = base + (long long)j * ng + g;
-    dpp = (rd - a.ra[o] * dpp) / a.dn[o];
-    a.dp[o] = dpp;
-    AkL = AkR;
-    caL = caR;
-    cbL = cbR;
-  }
-  double *E = a.E + og, *Eb = a.Ebnd + 2 * S.o_g + 2 * g;
-  double u = 0.0;
-  for (int j = nx + 1; j >= 0; --j) {
-    const long long o = base + (long long)j * ng + g;
-    u = a.dp[o] - (j <= nx ? a.cp[o] * u : 0.0);
-    if (j == nx + 1)
-      Eb[1] = u;
-    else if (j == 0)
-      Eb[0] = u;
-    else
-      E[j - 1] = u;
-  }
-  if (a.F && with_phi) {
-    double *F = a.F + S.o_ge + (long long)g * (nx + 1);
-    for (int e = 0; e <= nx; ++e) {
-      double Ak, ca, cb;
-      a1_edge(v, e, S.c, S.inv_cdt, Ak, ca, cb);
-      const double uL = e == 0 ? Eb[0] : E[e - 1], uR = e == nx ? Eb[1] : E[e];
-      F[e] = Ak - ca * uR + cb * uL;
-    }
-  }
+  const long long o = S.o_gi + 2 * S.o_g + g;  // row j of group g at o + j ng
+  const long long og = S.o_gi + (long long)g * S.nx;
+  double *F = (a.F && with_phi) ? a.F + S.o_ge + (long long)g * (S.nx + 1) : nullptr;
+  a1_solve_group(S, v, a, S.ng, with_phi, a.ra + o, a.cp + o, a.dn + o, a.dp + o, a.in.kappa + og, a.in.B + og,
+                 a.w + og, a.E + og, a.Ebnd + 2 * S.o_g + 2 * g, F);
 }
 
 // Per cell: phi's right-hand side sum_g c kappa_g E_g (fixed group order).
@@ -2523,6 +2551,32 @@ __global__ __launch_bounds__(256) void k_a1_rhs(const SlabDev *__restrict__ sd, 
 // source in cell j), times c kappa_g,i and dx_j w_g,j beta_j, into P[g][i][j].
 // The column slots of P hold the forward-substitution values first.  Items
 // = (slab, first of 256 (g, j) pairs).
+__device__ inline void a1_cols_column(const SlabDev &S, int ng, int jc, const double *__restrict__ ra_,
+                                      const double *__restrict__ cp_, const double *__restrict__ dn_,
+                                      const double *__restrict__ kap, double u, double *__restrict__ Pg) {
+  const int nx = S.nx;
+  // forward: rows r < jc + 1 are zero, row jc + 1 has the unit source
+  const int r = jc + 1;
+  double d = 1.0 / dn_[(long long)r * ng];
+  Pg[(long long)jc * nx] = d;
+#pragma unroll 8
+  for (int j = r + 1; j <= nx; ++j) {
+    const long long o = (long long)j * ng;
+    d = -ra_[o] * d / dn_[o];
+    Pg[(long long)(j - 1) * nx] = d;
+  }
+  const long long on = (long long)(nx + 1) * ng;
+  double z = -ra_[on] * d / dn_[on];  // row nx + 1 (boundary)
+#pragma unroll 8
+  for (int j = nx; j >= 1; --j) {
+    const long long o = (long long)j * ng;
+    const double dj = j >= r ? Pg[(long long)(j - 1) * nx] : 0.0;
+    z = dj - cp_[o] * z;
+    const int i = j - 1;
+    Pg[(long long)i * nx] = S.c * kap[i] * z * u;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_a1_cols(const SlabDev *__restrict__ sd, ProbDev pd,
                                                  const Item *__restrict__ tab, A1Args a) {
   const Item it = tab[blockIdx.x];
@@ -2532,28 +2586,11 @@ __global__ __launch_bounds__(256) void k_a1_cols(const SlabDev *__restrict__ sd,
   const int q = it.idx + threadIdx.x;
   if (q >= ng * nx) return;
   const int g = q / nx, jc = q - g * nx;
-  const long long base = S.o_gi + 2 * S.o_g;
-  double *Pg = a.P + a.oP[it.slab] + (long long)g * nx * nx + jc;  // slot i at Pg[i nx]
-  // forward: rows r < jc + 1 are zero, row jc + 1 has the unit source
-  const int r = jc + 1;
-  double d = 1.0 / a.dn[base + (long long)r * ng + g];
-  Pg[(long long)jc * nx] = d;
-  for (int j = r + 1; j <= nx; ++j) {
-    const long long o = base + (long long)j * ng + g;
-    d = -a.ra[o] * d / a.dn[o];
-    Pg[(long long)(j - 1) * nx] = d;
-  }
-  const long long on = base + (long long)(nx + 1) * ng + g;
-  double z = -a.ra[on] * d / a.dn[on];  // row nx + 1 (boundary)
-  const long long oc = S.o_cell + jc;
-  const double u = pd.dx[oc] * a.w[S.o_gi + (long long)g * nx + jc] * a.beta[oc];
-  for (int j = nx; j >= 1; --j) {
-    const long long o = base + (long long)j * ng + g;
-    const double dj = j >= r ? Pg[(long long)(j - 1) * nx] : 0.0;
-    z = dj - a.cp[o] * z;
-    const int i = j - 1;
-    Pg[(long long)i * nx] = S.c * a.in.kappa[S.o_gi + (long long)g * nx + i] * z * u;
-  }
+  const long long o = S.o_gi + 2 * S.o_g + g;  // row j of group g at o + j ng
+  const long long oc = S.o_cell + jc, og = S.o_gi + (long long)g * nx;
+  const double u = pd.dx[oc] * a.w[og + jc] * a.beta[oc];
+  a1_cols_column(S, ng, jc, a.ra + o, a.cp + o, a.dn + o, a.in.kappa + og, u,
+                 a.P + a.oP[it.slab] + (long long)g * nx * nx + jc);  // slot i at [i nx]
 }
 
 // Per (i, j): M_ij = delta_ij - sum_g P[g][i][j] (fixed group order).
