@@ -615,8 +615,8 @@ def main():
         print(json.dumps(_cpu_baseline_child(args.cpu_baseline_child, args.cpu_budget, args.cpu_lmax)))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the design notes describe how the path would shard)"}))
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 "
+                                   "(sharding over GPUs is described in the design notes, not built)"}))
         sys.exit(2)
 
     import torch

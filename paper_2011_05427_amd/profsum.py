@@ -198,7 +198,7 @@ def traffic_summary(workload, fetch_csv, write_csv, kernel="k_sweep", command=No
            "write_calibration_factor": wf, "algorithmic_bytes_per_launch": alg}
     out = [f"# {kernel} HBM traffic: {workload} workload (byte counters)", ""]
     if command:
-        out += ["Commands (GPU box), then this summary:", ""]
+        out += ["Commands (on the MI355X host), then this summary:", ""]
         out += ["    " + c for c in command] + [""]
     out += [
         "Counter values are KiB per dispatch.  The median over the kernel's dispatches",
