@@ -419,8 +419,8 @@ int tr_set_tiles(tr_ctx *ctx, const int *K, const int *split);
 int tr_get_tiles(const tr_ctx *ctx, int *K, int *split, int *items);
 
 /*
- * Learned closure (not part of the paper's method; its plain sweep stays the
- * judge).  A multilayer perceptron 7 -> 128 -> 128 -> 128 -> 2 with ReLU
+ * Learned closure (not part of the paper's method; the plain sweeps still
+ * decide convergence).  A multilayer perceptron 7 -> 128 -> 128 -> 128 -> 2 with ReLU
  * hidden layers; output 0 through a logistic sigmoid s predicts the change of
  * the group Eddington factor over a time step, f_seed = f + 0.05 (2 s - 1);
  * output 1 is a prolongation correction (log change of the within-block

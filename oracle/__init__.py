@@ -14,7 +14,7 @@ Modules (each function cites the passage of the paper it follows):
            mloqd-d-gamma) and the grey level coupled to the MEB (Eq. eb-Gamma-d)
   restrict restriction of coefficients to coarser frequency grids
            (Eqs. coeff-gamma, g-notation, eta-gamma, coeff-Gamma, eta-Gamma)
-  mlqd     time step driver (Alg. 3, with Alg. 2 as its V-cycle case)
+  mlqd     time stepping (Alg. 3, with Alg. 2 as its V-cycle case)
   mlp      FP64 reference of the learned closure network (forward/backward)
 
 Parity status: every function is pinned by CPU tests against closed forms,
