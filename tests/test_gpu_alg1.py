@@ -43,8 +43,11 @@ CASES = {
     "spectral": dict(nx=8, ng=16, nmu=4, dt=0.004, T0=0.01, C1=4.0, C2=1.0, nu_lo=1e-3, nu_hi=30.0,
                      opacity=inputs.OPAC_SPECTRAL),
     "wider": dict(nx=60, ng=32, nmu=8, dt=0.002),
-    # the largest register-resident dense solve (40 rows per thread) and the
-    # global-memory elimination beyond it
+    # every register-resident dense solve width (16, 24, 32 and 40 rows per
+    # thread) and the global-memory elimination beyond it
+    "dense_registers_100": dict(nx=100, ng=4, nmu=2, dt=0.002, steps=1),
+    "dense_registers_130": dict(nx=130, ng=4, nmu=2, dt=0.002, steps=1),
+    "dense_registers_160": dict(nx=160, ng=4, nmu=2, dt=0.002, steps=1),
     "dense_registers_200": dict(nx=200, ng=4, nmu=2, dt=0.002, steps=1),
     "dense_global_230": dict(nx=230, ng=4, nmu=2, dt=0.002, steps=1),
 }
