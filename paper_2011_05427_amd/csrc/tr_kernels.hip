@@ -2391,6 +2391,31 @@ __device__ inline void a1_row(const LevelView &v, int j, double c, double dt, do
   }
 }
 
+// a1_edge for an interior edge (0 < e < nx) and a1_row for a cell row (1 <=
+// j <= nx), without the boundary cases, so that a loop over them has no
+// branches between one row's loads and the next.
+__device__ inline void a1_edge_in(const LevelView &v, int e, double c, double inv_cdt, double &Ak, double &ca,
+                                  double &cb) {
+  const double dm = v.dx[e - 1], de = v.dx[e];
+  const double sr = (v.sgr[e - 1] * dm + v.sgr[e] * de) / (dm + de);
+  const double h = 0.5 * (dm + de), A = h * inv_cdt;
+  const double k = 1.0 / (A + sr * h);
+  Ak = k * A * v.Fold[e];
+  ca = c * k * v.f[e];
+  cb = c * k * v.f[e - 1];
+}
+
+__device__ inline void a1_row_in(const LevelView &v, int j, double c, double dt, double em, double AkL, double caL,
+                                 double cbL, double AkR, double caR, double cbR, double &ra, double &rb, double &rc,
+                                 double &rd) {
+  const int i = j - 1;
+  const double dxi = v.dx[i];
+  ra = -cbL;
+  rb = dxi / dt + c * v.kap[i] * dxi + cbR + caL;
+  rc = -caR;
+  rd = dxi * em + dxi / dt * v.Eold[i] - AkR + AkL;
+}
+
 // Per cell: alpha, beta and the per-group emission couplings w_g.  The
 // arrays are passed as non-aliasing pointers (cell i's column of each [g][i]
 // array, stride nx) so that the group loops keep their loads in flight
@@ -2437,11 +2462,10 @@ __global__ __launch_bounds__(256) void k_a1_prep(const SlabDev *__restrict__ sd,
 __device__ inline void a1_factor_group(const SlabDev &S, const LevelView &v, int ng, double *__restrict__ ra_,
                                        double *__restrict__ cp_, double *__restrict__ dn_) {
   const int nx = S.nx;
+  const double c = S.c, dt = S.dt, icdt = S.inv_cdt;
   double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, cpp = 0.0;
-  for (int j = 0; j <= nx + 1; ++j) {
-    if (j <= nx) a1_edge(v, j, S.c, S.inv_cdt, AkR, caR, cbR);
-    double ra, rb, rc, rd;
-    a1_row(v, j, S.c, S.dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  double ra, rb, rc, rd;
+  auto put = [&](int j) {  // Thomas factor of row j
     const double dnj = rb - ra * cpp;
     cpp = rc / dnj;
     const long long o = (long long)j * ng;
@@ -2451,7 +2475,21 @@ __device__ inline void a1_factor_group(const SlabDev &S, const LevelView &v, int
     AkL = AkR;
     caL = caR;
     cbL = cbR;
+  };
+  a1_edge(v, 0, c, icdt, AkR, caR, cbR);
+  a1_row(v, 0, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  put(0);
+#pragma unroll 4
+  for (int j = 1; j < nx; ++j) {
+    a1_edge_in(v, j, c, icdt, AkR, caR, cbR);
+    a1_row_in(v, j, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+    put(j);
   }
+  a1_edge(v, nx, c, icdt, AkR, caR, cbR);
+  a1_row_in(v, nx, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  put(nx);
+  a1_row(v, nx + 1, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  put(nx + 1);
 }
 
 __global__ __launch_bounds__(256) void k_a1_factor(const SlabDev *__restrict__ sd, ProbDev pd,
@@ -2477,39 +2515,52 @@ __device__ inline void a1_solve_group(const SlabDev &S, const LevelView &v, cons
                                       const double *__restrict__ w, double *__restrict__ E, double *__restrict__ Eb,
                                       double *__restrict__ F) {
   const int nx = S.nx;
+  const double c = S.c, dt = S.dt, icdt = S.inv_cdt;
+  const double *alpha = a.alpha + S.o_cell, *beta = a.beta + S.o_cell, *phi = a.phi + S.o_cell;
   double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, dpp = 0.0;
-  for (int j = 0; j <= nx + 1; ++j) {
-    if (j <= nx) a1_edge(v, j, S.c, S.inv_cdt, AkR, caR, cbR);
-    double em = 0.0;
-    if (j >= 1 && j <= nx) {
-      const long long oc = S.o_cell + j - 1;
-      const double dT = a.alpha[oc] + (with_phi ? a.beta[oc] * a.phi[oc] : 0.0);
-      em = 2.0 * kap[j - 1] * Bv[j - 1] + w[j - 1] * dT;
-    }
-    double ra, rb, rc, rd;
-    a1_row(v, j, S.c, S.dt, em, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  double ra, rb, rc, rd;
+  auto put = [&](int j) {  // forward substitution of row j
     const long long o = (long long)j * ng;
     dpp = (rd - ra_[o] * dpp) / dn_[o];
     dp_[o] = dpp;
     AkL = AkR;
     caL = caR;
     cbL = cbR;
+  };
+  auto em_of = [&](int j) {  // cell emission of row j (cell j - 1)
+    const int i = j - 1;
+    const double dT = alpha[i] + (with_phi ? beta[i] * phi[i] : 0.0);
+    return 2.0 * kap[i] * Bv[i] + w[i] * dT;
+  };
+  a1_edge(v, 0, c, icdt, AkR, caR, cbR);
+  a1_row(v, 0, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  put(0);
+#pragma unroll 4
+  for (int j = 1; j < nx; ++j) {
+    a1_edge_in(v, j, c, icdt, AkR, caR, cbR);
+    a1_row_in(v, j, c, dt, em_of(j), AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+    put(j);
   }
-  double u = 0.0;
-  for (int j = nx + 1; j >= 0; --j) {
+  a1_edge(v, nx, c, icdt, AkR, caR, cbR);
+  a1_row_in(v, nx, c, dt, em_of(nx), AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  put(nx);
+  a1_row(v, nx + 1, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
+  put(nx + 1);
+  // back substitution: the right boundary unknown, the cells, the left one
+  double u = dp_[(long long)(nx + 1) * ng];
+  Eb[1] = u;
+#pragma unroll 4
+  for (int j = nx; j >= 1; --j) {
     const long long o = (long long)j * ng;
-    u = dp_[o] - (j <= nx ? cp_[o] * u : 0.0);
-    if (j == nx + 1)
-      Eb[1] = u;
-    else if (j == 0)
-      Eb[0] = u;
-    else
-      E[j - 1] = u;
+    u = dp_[o] - cp_[o] * u;
+    E[j - 1] = u;
   }
+  u = dp_[0] - cp_[0] * u;
+  Eb[0] = u;
   if (F) {
     for (int e = 0; e <= nx; ++e) {
       double Ak, ca, cb;
-      a1_edge(v, e, S.c, S.inv_cdt, Ak, ca, cb);
+      a1_edge(v, e, c, icdt, Ak, ca, cb);
       const double uL = e == 0 ? Eb[0] : E[e - 1], uR = e == nx ? Eb[1] : E[e];
       F[e] = Ak - ca * uR + cb * uL;
     }
