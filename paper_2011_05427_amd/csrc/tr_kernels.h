@@ -98,14 +98,17 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
 // grey): those partials are added into out.dS.
 inline int restrict_tile(int mode) { return mode == 1 ? 63 : 64; }
 // In the chunk pass a block of 4 wavefronts covers 64 edges and 4 rcw finer
-// groups (rcw per wavefront), giving cpb chunk records per coarse group.  rcw
-// grows (fewer records to write and re-read) while a slab's pass keeps at
-// least `target` blocks (4096 over the slabs of a context), and so that
-// cpb <= 64.
+// groups (rcw per wavefront), giving cpb chunk records per coarse group.  On
+// slabs of 16 or more edge tiles rcw starts at 16 (or r / 8 if smaller), a
+// rule of the slab alone; it then grows (fewer records to write and re-read)
+// while a slab's pass keeps at least `target` blocks (4096 over the slabs of
+// a context), and so that cpb <= 64.
 #define TR_RFIN_E 11
 __host__ __device__ inline int restrict_rcw(int r, int nto, int ne, int target) {
   const int ntile = (ne + 63) / 64;
   int rcw = 1;
+  if (ntile >= 16)  // wide slabs: at least 16 finer groups per wavefront where r allows
+    while (rcw < 16 && 8 * rcw < r) rcw *= 2;
   while (rcw < 32 && 4 * rcw < r && (long long)nto * ((r + 8 * rcw - 1) / (8 * rcw)) * ntile >= target) rcw *= 2;
   while ((r + 4 * rcw - 1) / (4 * rcw) > 64) rcw *= 2;
   return rcw;

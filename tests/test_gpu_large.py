@@ -68,6 +68,31 @@ def test_wide_slab_few_coarse_groups_replay(levels, cycle):
     sv.close()
 
 
+def test_sixteen_tile_slab_chunk_widths_replay():
+    """A slab of 960 cells (16 edge tiles), where the chunk pass starts at 16
+    finer groups per wavefront (or r / 8): the fine -> grey restriction (r =
+    256) and the stage restriction fine -> 4 groups (r = 64) take the wider
+    chunks; F cycle on 256,16,4,1, two replayed steps at 1e-10."""
+    import dataclasses
+
+    from test_gpu_step import _compare_state, _oracle_run
+
+    _, cfg0, _ = inputs.config_large()
+    cfg = dataclasses.replace(cfg0, cycle=inputs.CYCLE_F, lmax=1)
+    levels = [256, 16, 4, 1]
+    slab = inputs.make_slab(960, 256, 8)
+    note(f"16-tile slab replay nx=960 ng=256 nmu=8 levels={levels} cycle=F")
+    states, stats = _oracle_run(slab, cfg, levels, 2)
+    sv = binding.Solver([slab], [levels], cfg)
+    st = sv.new_state()
+    sv.state_init(st, slab.T0)
+    for j in range(2):
+        gs = sv.step(st, replay=[stats.counts[j]])
+        assert list(gs[0].cycles[:len(stats.counts[j])]) == stats.counts[j]
+        _compare_state(f"16-tile slab step {j}", sv, st, states[j + 1])
+    sv.close()
+
+
 def test_large_workload_sampled_sweep_and_energy_balance():
     import torch
 
