@@ -191,7 +191,7 @@ int build_restrict_tables(tr_ctx *c, int from, int to, int mode = 0) {
     const int nf = S.lev_ng[from], nt = S.lev_ng[to];
     const int r = nf / nt;
     const int cpb = restrict_cpb(r, nt, ne, S.rtarget);
-    if (cpb == 1) {
+    if (restrict_single(r, nt, ne)) {
       // four wavefront items (coarse group, tile of edges) per block
       const int nwi = nt * ((ne + TE - 1) / TE);
       for (int q = 0; 4 * q < nwi; ++q) single.push_back({s, q});
@@ -540,7 +540,7 @@ int tr_create(tr_ctx **out, const tr_problem *probs, int n_slab, const tr_solver
         for (int b = a + 1; b < nlev; ++b) {
           const int r = P.level_ng[a] / P.level_ng[b];
           const int cpb = restrict_cpb(r, P.level_ng[b], P.nx + 1, S.rtarget);
-          if (cpb > 1) worst = std::max(worst, (long long)P.level_ng[b] * cpb);
+          if (!restrict_single(r, P.level_ng[b], P.nx + 1)) worst = std::max(worst, (long long)P.level_ng[b] * cpb);
         }
       c->n_red += worst * (P.nx + 1) * 22;  // up to 22 fields per record
     }

@@ -99,8 +99,8 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
 inline int restrict_tile(int mode) { return mode == 1 ? 63 : 64; }
 // In the chunk pass a block of 4 wavefronts covers 64 edges and 4 rcw finer
 // groups (rcw per wavefront), giving cpb chunk records per coarse group.  On
-// slabs of 16 or more edge tiles rcw starts at 16 (or r / 8 if smaller), a
-// rule of the slab alone; it then grows (fewer records to write and re-read)
+// slabs of 16 or more edge tiles rcw starts at 16 (or r / 4 if smaller: one
+// record per coarse group), a rule of the slab alone; it then grows (fewer records to write and re-read)
 // while a slab's pass keeps at least `target` blocks (4096 over the slabs of
 // a context), and so that cpb <= 64.
 #define TR_RFIN_E 11
@@ -108,17 +108,20 @@ __host__ __device__ inline int restrict_rcw(int r, int nto, int ne, int target) 
   const int ntile = (ne + 63) / 64;
   int rcw = 1;
   if (ntile >= 16)  // wide slabs: at least 16 finer groups per wavefront where r allows
-    while (rcw < 16 && 8 * rcw < r) rcw *= 2;
+    while (rcw < 16 && 4 * rcw < r) rcw *= 2;
   while (rcw < 32 && 4 * rcw < r && (long long)nto * ((r + 8 * rcw - 1) / (8 * rcw)) * ntile >= target) rcw *= 2;
   while ((r + 4 * rcw - 1) / (4 * rcw) > 64) rcw *= 2;
   return rcw;
 }
-__host__ __device__ inline int restrict_cpb(int r, int nto, int ne, int target) {
-  // one pass unless the single pass would run few long wavefronts: a wide
-  // slab (8 or more edge tiles) restricted to very few coarse groups (under
-  // 256 wavefront items) takes the chunk pass from r = 8 up
+// One pass unless the single pass would run few long wavefronts: a wide slab
+// (8 or more edge tiles) restricted to very few coarse groups (under 256
+// wavefront items) takes the chunk pass from r = 8 up.
+__host__ __device__ inline bool restrict_single(int r, int nto, int ne) {
   const int ntile = (ne + 63) / 64;
-  if (r <= 16 && !(r >= 8 && ntile >= 8 && (long long)nto * ntile < 256)) return 1;
+  return r <= 16 && !(r >= 8 && ntile >= 8 && (long long)nto * ntile < 256);
+}
+__host__ __device__ inline int restrict_cpb(int r, int nto, int ne, int target) {
+  if (restrict_single(r, nto, ne)) return 1;
   const int rcw = restrict_rcw(r, nto, ne, target);
   return (r + 4 * rcw - 1) / (4 * rcw);
 }
