@@ -119,10 +119,11 @@ struct tr_ctx {
   // its first use
   struct A1Work {
     bool ready = false;
-    double *dem, *kprev, *w, *ra, *cp, *dn, *dp, *P, *M, *rhs, *phi, *alpha, *beta, *Tprev, *Ts, *Esum, *Esp, *Er;
+    double *dem, *kprev, *w, *ra, *cp, *dn, *P, *M, *rhs, *phi, *alpha, *beta, *Tprev, *Ts, *Esum, *Esp, *Er;
     double *err, *outer, *h_err, *h_outer;  // device and pinned host copies (per slab)
     long long *oM, *oP;
-    Table t_mm;
+    Table t_mm, t_sg;  // (slab, 256-entry block of M) and (slab, group) items
+    int sg_threads = 64;  // block of the per-group solves
   } a1{};
 };
 
@@ -1447,7 +1448,7 @@ int a1_alloc(tr_ctx *c) {
   if (a.ready) return TR_OK;
   long long nM = 0, nP = 0;
   std::vector<long long> hoM(c->nslab), hoP(c->nslab);
-  std::vector<Item> mm;
+  std::vector<Item> mm, sg;
   for (int k = 0; k < c->nslab; ++k) {
     const SlabDev &S = c->hs[k];
     hoM[k] = nM;
@@ -1455,13 +1456,16 @@ int a1_alloc(tr_ctx *c) {
     nM += (long long)S.nx * S.nx;
     nP += (long long)S.ng * S.nx * S.nx;
     for (long long q = 0; q < (long long)S.nx * S.nx; q += 256) mm.push_back({k, (int)q});
+    for (int g = 0; g < S.ng; ++g) sg.push_back({k, g});
+    const int need = (S.nx + 2 + TR_LO_K - 1) / TR_LO_K;
+    a.sg_threads = std::max(a.sg_threads, (need + 63) / 64 * 64);
   }
   const long long nrow = c->n_gi + 2 * c->n_g;
   int rc;
   double **gi[] = {&a.dem, &a.kprev, &a.w};
   for (double **p : gi)
     if ((rc = dalloc(c, p, c->n_gi))) return rc;
-  double **rows[] = {&a.ra, &a.cp, &a.dn, &a.dp};
+  double **rows[] = {&a.ra, &a.cp, &a.dn};
   for (double **p : rows)
     if ((rc = dalloc(c, p, nrow))) return rc;
   double **cells[] = {&a.rhs, &a.phi, &a.alpha, &a.beta, &a.Tprev, &a.Ts, &a.Esum, &a.Esp, &a.Er};
@@ -1474,7 +1478,7 @@ int a1_alloc(tr_ctx *c) {
   if (hipMemcpy(a.oM, hoM.data(), 8 * hoM.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(a.oP, hoP.data(), 8 * hoP.size(), hipMemcpyHostToDevice) != hipSuccess)
     return TR_EHIP;
-  if ((rc = upload_table(c, mm, a.t_mm))) return rc;
+  if ((rc = upload_table(c, mm, a.t_mm)) || (rc = upload_table(c, sg, a.t_sg))) return rc;
   if (hipHostMalloc((void **)&a.h_err, 8 * c->nslab, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&a.h_outer, 32 * c->nslab, hipHostMallocDefault) != hipSuccess)
     return TR_ENOMEM;
@@ -1541,7 +1545,6 @@ int tr_alg1_step(tr_ctx *c, const tr_state *s, tr_stats *stats, hipStream_t st) 
   a.ra = w.ra;
   a.cp = w.cp;
   a.dn = w.dn;
-  a.dp = w.dp;
   a.P = w.P;
   a.M = w.M;
   a.rhs = w.rhs;
@@ -1576,12 +1579,12 @@ int tr_alg1_step(tr_ctx *c, const tr_state *s, tr_stats *stats, hipStream_t st) 
       a.first = k == 0;
       launch_a1_prep(env, c->t_cell, a);
       launch_a1_factor(env, c->t_g, a);
-      launch_a1_solve(env, c->t_g, a, false);
+      launch_a1_solve_blk(env, w.t_sg, w.sg_threads, a, false);
       launch_a1_rhs(env, c->t_cell, a);
       launch_a1_cols(env, c->t_gi, a);
       launch_a1_mred(env, w.t_mm, a);
       launch_a1_dense(env, ns, max_nx, a);
-      launch_a1_solve(env, c->t_g, a, true);
+      launch_a1_solve_blk(env, w.t_sg, w.sg_threads, a, true);
       launch_a1_update(env, ns, a, w.Tprev);
       launch_copy(env, c->kappa, w.kprev, c->n_gi);
       if (hipMemcpyAsync(w.h_err, w.err, 8 * ns, hipMemcpyDeviceToHost, st) != hipSuccess ||

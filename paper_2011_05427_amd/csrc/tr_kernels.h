@@ -192,7 +192,7 @@ struct A1Args {
   const double *Ek;        // gi: E of the previous iterate
   double *alpha, *beta;    // cell
   double *w;               // gi
-  double *ra, *cp, *dn, *dp;  // Thomas rows, per slab at o_gi + 2 o_g, row j of group g at j ng + g
+  double *ra, *cp, *dn;     // Thomas factors, per slab at o_gi + 2 o_g, row j of group g at j ng + g
   double *P;               // per slab ng nx nx partial products (at oP)
   double *M, *rhs, *phi;   // per slab nx nx (at oM); cell; cell
   const long long *oM, *oP;
@@ -204,7 +204,9 @@ struct A1Args {
 
 void launch_a1_prep(const LaunchEnv &env, const Table &t_cell, const A1Args &a);
 void launch_a1_factor(const LaunchEnv &env, const Table &t_g, const A1Args &a);
-void launch_a1_solve(const LaunchEnv &env, const Table &t_g, const A1Args &a, bool with_phi);
+// Per-group solves of Alg. 1: items (slab, group), threads >= (nx + 2) /
+// TR_LO_K of every slab (at most 512), 64 bytes of LDS per thread.
+void launch_a1_solve_blk(const LaunchEnv &env, const Table &t_sg, int threads, const A1Args &a, bool with_phi);
 void launch_a1_rhs(const LaunchEnv &env, const Table &t_cell, const A1Args &a);
 void launch_a1_cols(const LaunchEnv &env, const Table &t_gi, const A1Args &a);
 void launch_a1_mred(const LaunchEnv &env, const Table &t_mm, const A1Args &a);

@@ -2505,81 +2505,72 @@ __global__ __launch_bounds__(256) void k_a1_factor(const SlabDev *__restrict__ s
 }
 
 // Per group: the solve with the cell emission 2 kappa B + w (alpha + beta
-// phi) (phi null: 0); writes E, the boundary E and, with F, the fluxes.  The
-// rows (stride ng) and the outputs are non-aliasing pointers, so that a row's
-// loads need not wait for the previous row's store.
-__device__ inline void a1_solve_group(const SlabDev &S, const LevelView &v, const A1Args &a, int ng, int with_phi,
-                                      const double *__restrict__ ra_, const double *__restrict__ cp_,
-                                      const double *__restrict__ dn_, double *__restrict__ dp_,
-                                      const double *__restrict__ kap, const double *__restrict__ Bv,
-                                      const double *__restrict__ w, double *__restrict__ E, double *__restrict__ Eb,
-                                      double *__restrict__ F) {
-  const int nx = S.nx;
-  const double c = S.c, dt = S.dt, icdt = S.inv_cdt;
-  const double *alpha = a.alpha + S.o_cell, *beta = a.beta + S.o_cell, *phi = a.phi + S.o_cell;
-  double AkL = 0.0, caL = 0.0, cbL = 0.0, AkR, caR, cbR, dpp = 0.0;
-  double ra, rb, rc, rd;
-  auto put = [&](int j) {  // forward substitution of row j
-    const long long o = (long long)j * ng;
-    dpp = (rd - ra_[o] * dpp) / dn_[o];
-    dp_[o] = dpp;
-    AkL = AkR;
-    caL = caR;
-    cbL = cbR;
-  };
-  auto em_of = [&](int j) {  // cell emission of row j (cell j - 1)
-    const int i = j - 1;
-    const double dT = alpha[i] + (with_phi ? beta[i] * phi[i] : 0.0);
-    return 2.0 * kap[i] * Bv[i] + w[i] * dT;
-  };
-  a1_edge(v, 0, c, icdt, AkR, caR, cbR);
-  a1_row(v, 0, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
-  put(0);
-#pragma unroll 4
-  for (int j = 1; j < nx; ++j) {
-    a1_edge_in(v, j, c, icdt, AkR, caR, cbR);
-    a1_row_in(v, j, c, dt, em_of(j), AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
-    put(j);
-  }
-  a1_edge(v, nx, c, icdt, AkR, caR, cbR);
-  a1_row_in(v, nx, c, dt, em_of(nx), AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
-  put(nx);
-  a1_row(v, nx + 1, c, dt, 0.0, AkL, caL, cbL, AkR, caR, cbR, ra, rb, rc, rd);
-  put(nx + 1);
-  // back substitution: the right boundary unknown, the cells, the left one
-  double u = dp_[(long long)(nx + 1) * ng];
-  Eb[1] = u;
-#pragma unroll 4
-  for (int j = nx; j >= 1; --j) {
-    const long long o = (long long)j * ng;
-    u = dp_[o] - cp_[o] * u;
-    E[j - 1] = u;
-  }
-  u = dp_[0] - cp_[0] * u;
-  Eb[0] = u;
-  if (F) {
-    for (int e = 0; e <= nx; ++e) {
-      double Ak, ca, cb;
-      a1_edge(v, e, c, icdt, Ak, ca, cb);
-      const double uL = e == 0 ? Eb[0] : E[e - 1], uR = e == nx ? Eb[1] : E[e];
-      F[e] = Ak - ca * uR + cb * uL;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_a1_solve(const SlabDev *__restrict__ sd, ProbDev pd,
-                                                  const Item *__restrict__ tab, A1Args a, int with_phi) {
+// phi) (phi null: 0); writes E, the boundary E and, with phi, the fluxes.  A
+// block per (slab, group) item (blockDim T >= (nx + 2) / K): thread t builds
+// rows j = t K + k from its edges t K - 1 .. t K + K - 1 (rows past nx + 1 are
+// identity rows) and solves by the partitioned Thomas + PCR of the LO solver,
+// so that the rows' loads are coalesced over the threads; the fluxes take the
+// neighbouring row through LDS.
+template <int K>
+__global__ __launch_bounds__(512) void k_a1_solve_blk(const SlabDev *__restrict__ sd, ProbDev pd,
+                                                      const Item *__restrict__ tab, A1Args a, int with_phi) {
+  extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
   const Item it = tab[blockIdx.x];
   if (!a1_on(a, it.slab)) return;
   const SlabDev &S = sd[it.slab];
-  const int g = it.idx + threadIdx.x;
-  if (g >= S.ng) return;
+  const int g = it.idx, nx = S.nx, t = threadIdx.x;
   const LevelView v = make_view<true>(S, pd, 0, a.in, g);
-  const long long o = S.o_gi + 2 * S.o_g + g;  // row j of group g at o + j ng
-  const long long og = S.o_gi + (long long)g * S.nx;
-  double *F = (a.F && with_phi) ? a.F + S.o_ge + (long long)g * (S.nx + 1) : nullptr;
-  a1_solve_group(S, v, a, S.ng, with_phi, a.ra + o, a.cp + o, a.dn + o, a.dp + o, a.in.kappa + og, a.in.B + og,
-                 a.w + og, a.E + og, a.Ebnd + 2 * S.o_g + 2 * g, F);
+  const double c = S.c, dt = S.dt, icdt = S.inv_cdt;
+  const long long og = S.o_gi + (long long)g * nx;
+  double Ak[K + 1], ca[K + 1], cb[K + 1];  // edge t K + k - 1
+#pragma unroll
+  for (int k = 0; k <= K; ++k) {
+    const int e = t * K + k - 1;
+    Ak[k] = ca[k] = cb[k] = 0.0;
+    if (e >= 0 && e <= nx) a1_edge(v, e, c, icdt, Ak[k], ca[k], cb[k]);
+  }
+  double ra[K], rb[K], rc[K], rd[K], x[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int j = t * K + k;
+    ra[k] = 0.0;
+    rb[k] = 1.0;
+    rc[k] = 0.0;
+    rd[k] = 0.0;
+    if (j <= nx + 1) {
+      double em = 0.0;
+      if (j >= 1 && j <= nx) {
+        const long long oc = S.o_cell + j - 1;
+        const double dT = a.alpha[oc] + (with_phi ? a.beta[oc] * a.phi[oc] : 0.0);
+        em = 2.0 * a.in.kappa[og + j - 1] * a.in.B[og + j - 1] + a.w[og + j - 1] * dT;
+      }
+      a1_row(v, j, c, dt, em, Ak[k], ca[k], cb[k], Ak[k + 1], ca[k + 1], cb[k + 1], ra[k], rb[k], rc[k], rd[k]);
+    }
+  }
+  tri_solve_block<K>(ra, rb, rc, rd, x, lds, blockDim.x);
+  double *E = a.E + og, *Eb = a.Ebnd + 2 * S.o_g + 2 * g;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int j = t * K + k;
+    if (j == 0)
+      Eb[0] = x[k];
+    else if (j <= nx)
+      E[j - 1] = x[k];
+    else if (j == nx + 1)
+      Eb[1] = x[k];
+  }
+  if (a.F && with_phi) {
+    __syncthreads();  // the solver's LDS is free again
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[t * K + k] = x[k];
+    __syncthreads();
+    double *F = a.F + S.o_ge + (long long)g * (nx + 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = t * K + k;  // F_e = Ak - ca u_R + cb u_L, u_L = row e, u_R = row e + 1
+      if (e <= nx) F[e] = Ak[k + 1] - ca[k + 1] * lds[e + 1] + cb[k + 1] * lds[e];
+    }
+  }
 }
 
 // Per cell: phi's right-hand side sum_g c kappa_g E_g (fixed group order).
@@ -3149,9 +3140,10 @@ void launch_a1_prep(const LaunchEnv &env, const Table &t_cell, const A1Args &a) 
 void launch_a1_factor(const LaunchEnv &env, const Table &t_g, const A1Args &a) {
   if (t_g.n) hipLaunchKernelGGL(k_a1_factor, blocks(t_g.n), dim3(256), 0, env.stream, env.sd, env.pd, t_g.d, a);
 }
-void launch_a1_solve(const LaunchEnv &env, const Table &t_g, const A1Args &a, bool with_phi) {
-  if (t_g.n)
-    hipLaunchKernelGGL(k_a1_solve, blocks(t_g.n), dim3(256), 0, env.stream, env.sd, env.pd, t_g.d, a, with_phi ? 1 : 0);
+void launch_a1_solve_blk(const LaunchEnv &env, const Table &t_sg, int threads, const A1Args &a, bool with_phi) {
+  if (t_sg.n == 0) return;
+  hipLaunchKernelGGL(k_a1_solve_blk<TR_LO_K>, blocks(t_sg.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd,
+                     t_sg.d, a, with_phi ? 1 : 0);
 }
 void launch_a1_rhs(const LaunchEnv &env, const Table &t_cell, const A1Args &a) {
   if (t_cell.n) hipLaunchKernelGGL(k_a1_rhs, blocks(t_cell.n), dim3(256), 0, env.stream, env.sd, t_cell.d, a);
