@@ -2582,7 +2582,8 @@ __global__ __launch_bounds__(256) void k_a1_rhs(const SlabDev *__restrict__ sd, 
   const int i = it.idx + threadIdx.x;
   if (i >= S.nx) return;
   double r = 0.0;
-  for (int g = 0; g < S.ng; ++g) {
+#pragma unroll 8
+  for (int g = 0; g < S.ng; ++g) {  // unrolled: several groups' loads in flight, adds in group order
     const long long o = S.o_gi + (long long)g * S.nx + i;
     r += S.c * a.in.kappa[o] * a.E[o];
   }
@@ -2646,7 +2647,8 @@ __global__ __launch_bounds__(256) void k_a1_mred(const SlabDev *__restrict__ sd,
   if (q >= nx * nx) return;
   const double *P = a.P + a.oP[it.slab] + q;
   double s = 0.0;
-  for (int g = 0; g < S.ng; ++g) s += P[(long long)g * nx * nx];
+#pragma unroll 8
+  for (int g = 0; g < S.ng; ++g) s += P[(long long)g * nx * nx];  // several loads in flight, group order
   const int i = q / nx, j = q - i * nx;
   a.M[a.oM[it.slab] + q] = (i == j ? 1.0 : 0.0) - s;
 }
@@ -2884,7 +2886,8 @@ __global__ __launch_bounds__(512) void k_a1_outer(const SlabDev *__restrict__ sd
   if (i < S.nx) {
     const long long oc = S.o_cell + i;
     double e = 0.0;
-    for (int g = 0; g < S.ng; ++g) e += E[S.o_gi + (long long)g * S.nx + i];
+#pragma unroll 8
+    for (int g = 0; g < S.ng; ++g) e += E[S.o_gi + (long long)g * S.nx + i];  // loads in flight, group order
     Esum[oc] = e;
     v[0] = fabs(T[oc] - Ts[oc]);
     v[1] = fabs(T[oc]);
