@@ -2039,7 +2039,8 @@ __global__ __launch_bounds__(256) void k_group_sum(const SlabDev *__restrict__ s
   const int i = it.idx + threadIdx.x;
   if (i >= S.nx) return;
   double acc = 0.0;
-  for (int g = 0; g < S.ng; ++g) acc += E[S.o_gi + (long long)g * S.nx + i];
+#pragma unroll 8
+  for (int g = 0; g < S.ng; ++g) acc += E[S.o_gi + (long long)g * S.nx + i];  // loads in flight, group order
   out[S.o_cell + i] = acc;
 }
 
