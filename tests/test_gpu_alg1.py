@@ -50,6 +50,8 @@ CASES = {
     "dense_registers_160": dict(nx=160, ng=4, nmu=2, dt=0.002, steps=1),
     "dense_registers_200": dict(nx=200, ng=4, nmu=2, dt=0.002, steps=1),
     "dense_global_230": dict(nx=230, ng=4, nmu=2, dt=0.002, steps=1),
+    # the largest slab (512 cells): per-group solves on 192 threads
+    "dense_global_512": dict(nx=512, ng=4, nmu=2, dt=0.002, steps=1),
 }
 
 
