@@ -1378,10 +1378,15 @@ __device__ inline double acc_groups(const SlabDev &S, ProbDev pd, int from, cons
     const CellOpac co = cell_opac(S, pd, T, q.e - 1);
     // narrow groups (Gauss-Legendre) first, then the wide ones by their edge
     // integrals, each in ascending order: the edge series' coefficients are
-    // not live while the narrow groups are evaluated
+    // not live while the narrow groups are evaluated, and a wavefront with no
+    // wide group skips their loop (and the coefficients' loads) entirely
+    bool any_wide = false;
     for (int g = g0; g < g1; ++g) {
       const double na = co.nue[g], nb = co.nue[g + 1];
-      if (!(na > 0.0 && nb <= 1.005 * na)) continue;  // wavefront-uniform
+      if (!(na > 0.0 && nb <= 1.005 * na)) {  // wavefront-uniform
+        any_wide = true;
+        continue;
+      }
       EdgeVals a;
       load_group<FINE, OLD, RM_OPAC>(S, from, in, sol, g, true, q, 0.0, 0.0, 0.0, dsop, 0, a);
       double ka, Ba;
@@ -1390,7 +1395,7 @@ __device__ inline double acc_groups(const SlabDev &S, ProbDev pd, int from, cons
     }
     EdgeQ lo;
     bool lo_ok = false;  // lo holds edge g
-    for (int g = g0; g < g1; ++g) {
+    for (int g = g0; any_wide && g < g1; ++g) {
       const double na = co.nue[g], nb = co.nue[g + 1];
       if (na > 0.0 && nb <= 1.005 * na) {
         lo_ok = false;
