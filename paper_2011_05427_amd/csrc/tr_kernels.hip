@@ -1454,25 +1454,28 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   } else if (p == 0) {
     finalize_dS(S, e, o);
   }
-  const double rinv = 1.0 / r;
-  const double c = S.c;
+  // weighted averages by refined reciprocals (one per weight sum, within an
+  // ulp or two of the quotients); the plain average below TR_TINY weights
+  const double rinv = rcp_nr((double)r);
+  const double c = S.c, ic = rcp_nr(c);
   const long long pi = S.o_lpi[to] + (long long)p * nx;
   const long long pe = S.o_lpe[to] + (long long)p * (nx + 1);
   const long long p2 = S.o_lp2[to] + 2 * p;
   if (e < nx) {
-    o.sigE[pi + e] = (s[R_E] > TR_TINY) ? s[R_SEE] / s[R_E] : s[R_SE] * rinv;
+    o.sigE[pi + e] = (s[R_E] > TR_TINY) ? s[R_SEE] * rcp_nr(s[R_E]) : s[R_SE] * rinv;
     o.emis[pi + e] = s[R_EM];
     if (OLD) o.Eold[pi + e] = s[R_EOLD];
     o.Esum[pi + e] = s[R_E];
   }
-  const double abar = (s[R_ER] > TR_TINY) ? s[R_AER] / s[R_ER] : s[R_A] * rinv;
-  const double bbar = (s[R_EL] > TR_TINY) ? s[R_BEL] / s[R_EL] : s[R_B] * rinv;
-  const double sR = (s[R_AF] > TR_TINY) ? s[R_SAF] / s[R_AF] : s[R_S] * rinv;
+  const double iER = rcp_nr(s[R_ER]), iEL = rcp_nr(s[R_EL]);
+  const double abar = (s[R_ER] > TR_TINY) ? s[R_AER] * iER : s[R_A] * rinv;
+  const double bbar = (s[R_EL] > TR_TINY) ? s[R_BEL] * iEL : s[R_B] * rinv;
+  const double sR = (s[R_AF] > TR_TINY) ? s[R_SAF] * rcp_nr(s[R_AF]) : s[R_S] * rinv;
   const double *dx = pd.dx + S.o_cell;
   const double h = (e == 0) ? 0.5 * dx[0] : (e == nx) ? 0.5 * dx[nx - 1] : 0.5 * (dx[e - 1] + dx[e]);
   const double xi = h * (s[R_SF] - sR * s[R_F]);
-  const double eh = (xi > 0.0 && s[R_ER] > TR_TINY) ? xi / (c * s[R_ER]) : 0.0;
-  const double ec = (xi < 0.0 && s[R_EL] > TR_TINY) ? -xi / (c * s[R_EL]) : 0.0;
+  const double eh = (xi > 0.0 && s[R_ER] > TR_TINY) ? xi * ic * iER : 0.0;
+  const double ec = (xi < 0.0 && s[R_EL] > TR_TINY) ? -xi * ic * iEL : 0.0;
   o.a[pe + e] = abar + eh;
   o.b[pe + e] = bbar + ec;
   o.sigR[pe + e] = sR;
