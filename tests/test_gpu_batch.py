@@ -105,6 +105,34 @@ def test_batched_equals_individual():
             assert np.array_equal(a, b), (k, name)
 
 
+def test_wide_slab_in_a_batch_equals_alone():
+    """A 1000-cell slab (16 edge tiles: the chunk widths of the restriction
+    follow the slab alone) beside a small one: one free-running F-cycle step
+    of each inside the batch equals the step of the slab alone bit for bit."""
+    import dataclasses
+
+    _, cfg0, _ = inputs.config_large()
+    cfg = dataclasses.replace(cfg0, cycle=inputs.CYCLE_F, lmax=1)
+    slabs = [inputs.make_slab(1000, 256, 4), inputs.make_slab(100, 64, 4, C1=10.0, T_left=0.8)]
+    levels = [[256, 16, 4, 1], [64, 16, 4, 1]]
+    note("wide slab (1000 cells, 256 groups) and a small one, batched vs alone, one F step")
+    sv = binding.Solver(slabs, levels, cfg)
+    st = sv.new_state()
+    sv.state_init(st, 0.001)
+    sv.step(st)
+    batched = {k: _slab_view(sv, st, k) for k in range(2)}
+    sv.close()
+    for k, ref in batched.items():
+        one = binding.Solver([slabs[k]], [levels[k]], cfg)
+        s1 = one.new_state()
+        one.state_init(s1, 0.001)
+        one.step(s1)
+        got = _slab_view(one, s1, 0)
+        one.close()
+        for a, b, name in zip(got, ref, ("T", "E", "I")):
+            assert np.array_equal(a, b), (k, name)
+
+
 def test_batch_sampled_slabs_match_oracle():
     slabs, levels, cfg = _batch(20)
     small = sorted(range(20), key=lambda k: slabs[k].ng * slabs[k].nx * slabs[k].nmu)[:2]
