@@ -1190,10 +1190,12 @@ struct EdgeVals {
 };
 
 // Per-lane geometry of edge e: weights of the left / right cell in the
-// width-weighted fine sigma_R average (0 / 1 and 1 / 0 on the boundary edges).
+// width-weighted fine sigma_R average (0 / 1 and 1 / 0 on the boundary edges)
+// and h, the half width of the cells beside the edge (of the one cell on a
+// boundary edge).
 struct EdgeGeo {
   int e, nx;
-  double wm, we;
+  double wm, we, h;
 };
 
 __device__ inline EdgeGeo edge_geo(const SlabDev &S, ProbDev pd, int e) {
@@ -1202,9 +1204,11 @@ __device__ inline EdgeGeo edge_geo(const SlabDev &S, ProbDev pd, int e) {
   q.nx = S.nx;
   const __amdgpu_buffer_rsrc_t r = buf_rsrc(pd.dx + S.o_cell, S.nx * 8);
   const double dm = buf_load_f64(r, (e - 1) * 8), de = buf_load_f64(r, e * 8);
-  const double id = (e > 0 && e < S.nx) ? 1.0 / (dm + de) : 0.0;
+  // widths outside the slab read as zero
+  const double id = (e > 0 && e < S.nx) ? rcp_nr(dm + de) : 0.0;
   q.wm = (e == S.nx) ? 1.0 : dm * id;
   q.we = (e == 0) ? 1.0 : de * id;
+  q.h = 0.5 * (dm + de);
   return q;
 }
 
@@ -1446,7 +1450,7 @@ __device__ inline void finalize_dS(const SlabDev &S, int i, const LoOut &o) {
 
 // Final coefficients of coarse group p at edge e from the block sums.
 template <bool OLD, int MODE>
-__device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int e, int r, const double (&s)[R_NA],
+__device__ inline void finalize(const SlabDev &S, int to, int p, int e, double h, int r, const double (&s)[R_NA],
                                 const LoOut &o) {
   const int nx = S.nx;
   if (MODE == RM_DSF) {
@@ -1471,8 +1475,6 @@ __device__ inline void finalize(const SlabDev &S, ProbDev pd, int to, int p, int
   const double abar = (s[R_ER] > TR_TINY) ? s[R_AER] * iER : s[R_A] * rinv;
   const double bbar = (s[R_EL] > TR_TINY) ? s[R_BEL] * iEL : s[R_B] * rinv;
   const double sR = (s[R_AF] > TR_TINY) ? s[R_SAF] * rcp_nr(s[R_AF]) : s[R_S] * rinv;
-  const double *dx = pd.dx + S.o_cell;
-  const double h = (e == 0) ? 0.5 * dx[0] : (e == nx) ? 0.5 * dx[nx - 1] : 0.5 * (dx[e - 1] + dx[e]);
   const double xi = h * (s[R_SF] - sR * s[R_F]);
   const double eh = (xi > 0.0 && s[R_ER] > TR_TINY) ? xi * ic * iER : 0.0;
   const double ec = (xi < 0.0 && s[R_EL] > TR_TINY) ? -xi * ic * iEL : 0.0;
@@ -1525,7 +1527,7 @@ __global__ __launch_bounds__(256) void k_restrict(const SlabDev *__restrict__ sd
   for (int k = 0; k < R_NA; ++k) acc[k] = 0.0;
   const double dS = acc_groups<FINE, OLD, MODE>(S, pd, from, in, sol, p * r, (p + 1) * r, q, T, dsop, acc);
   if (MODE == RM_OPAC) store_dS_part(S, dsop, p, e - 1, dS);
-  if (e < ne && lane < TE) finalize<OLD, MODE>(S, pd, to, p, e, r, acc, out);
+  if (e < ne && lane < TE) finalize<OLD, MODE>(S, to, p, e, q.h, r, acc, out);
 }
 
 // Chunk pass (r > 16): block = (slab, chunk record qq = p cpb + bc, tile of
@@ -1640,7 +1642,7 @@ __global__ __launch_bounds__(256) void k_restrict_final(const SlabDev *__restric
       const int j = t * NF + q;
       s[rec_src<OLD>(q)] = U == 4 ? (sums[j] + sums[NP + j]) + (sums[2 * NP + j] + sums[3 * NP + j]) : sums[j];
     }
-    finalize<OLD, MODE>(S, pd, to, p, b * RE + t, r, s, out);
+    finalize<OLD, MODE>(S, to, p, b * RE + t, edge_geo(S, pd, b * RE + t).h, r, s, out);
   }
 }
 
