@@ -146,12 +146,112 @@ __device__ inline double q_interval(const EdgeQ &lo, const EdgeQ &hi) {
 // Thread t owns rows s = tK .. e = tK + K - 1 (rows >= N are identity rows).
 // Local elimination gives, for every partition, a row of x_s in terms of the
 // neighbours x_{s-1} (last row of partition t-1) and x_e, and a row of x_e in
-// terms of x_s and x_{e+1} (first row of partition t+1).  These 2T rows form a
-// tridiagonal "interface" system solved by parallel cyclic reduction in LDS;
-// the interior rows then follow by back substitution.  The systems here are
-// column diagonally dominant M-matrices, so no pivoting is needed.
-// lds must hold 8 * T doubles.
+// terms of x_s and x_{e+1} (first row of partition t+1).  These R = 2T rows
+// form a tridiagonal "interface" system, which one wavefront solves (see
+// tri_interface_wave); the interior rows then follow by back substitution.
+// The systems here are column diagonally dominant M-matrices, so no pivoting
+// is needed.  T is a multiple of 64 (at most 512); lds must hold
+// tri_lds_doubles(T) doubles.  On return lds[u] holds x_{uK}, the first
+// unknown of partition u, for every u < T.
 // ---------------------------------------------------------------------------
+// Stride of the solver's LDS arrays: R rows at skewed positions (see below).
+__host__ __device__ constexpr int tri_lds_stride(int T) { return 2 * T + 64; }
+__host__ __device__ constexpr int tri_lds_doubles(int T) { return 7 * tri_lds_stride(T); }
+
+// The interface system, solved by wavefront 0 (lanes l = 0..63).  Lane l owns
+// the M = R / 64 consecutive rows lM .. lM + M - 1, stored at positions
+// l (M + 1) + i (one spare slot per lane, so that the lanes' strided accesses
+// spread over the LDS banks) of the arrays A, B, C, D.  The lane eliminates
+// its rows by itself, as a thread does its K rows: its first row in terms of
+// the previous lane's last unknown and its own last, its last row in terms of
+// its first unknown and the next lane's first.  These 128 rows are tridiagonal
+// again and are solved by cyclic reduction across the lanes with shuffles (no
+// block barrier); the lane's inner rows then follow by back substitution from
+// the rows its forward elimination left in H, Q (reciprocal pivots) and G.
+// Every unknown is written over its row's d in D.
+__device__ inline void tri_interface_wave(const double *__restrict__ A, const double *__restrict__ B,
+                                          const double *__restrict__ C, double *__restrict__ D,
+                                          double *__restrict__ H, double *__restrict__ Q, double *__restrict__ G,
+                                          int M) {
+  const int l = threadIdx.x;
+  const int p0 = l * (M + 1);
+  // forward (rows 1 .. M-1 in terms of x_first) and backward (rows M-2 .. 0
+  // in terms of x_last) elimination, interleaved: they are independent chains
+  double eta = A[p0 + 1], bet = B[p0 + 1], del = D[p0 + 1], cpr = C[p0 + 1];
+  double ib = rcp_nr(bet);
+  H[p0 + 1] = eta;
+  Q[p0 + 1] = ib;
+  G[p0 + 1] = del;
+  double ual = A[p0 + M - 2], ube = B[p0 + M - 2], uga = C[p0 + M - 2], ude = D[p0 + M - 2];
+  for (int k = 0; k < M - 2; ++k) {
+    const int id = p0 + k + 2, iu = p0 + M - 3 - k;
+    const double ad = A[id], bd = B[id], cd = C[id], dd = D[id];
+    const double au = A[iu], bu = B[iu], cu = C[iu], du = D[iu];
+    const double r = ad * ib;
+    eta = -r * eta;
+    bet = bd - r * cpr;
+    del = dd - r * del;
+    cpr = cd;
+    ib = rcp_nr(bet);
+    if (k + 2 <= M - 2) {
+      H[id] = eta;
+      Q[id] = ib;
+      G[id] = del;
+    }
+    const double ru = cu * rcp_nr(ube);
+    ube = bu - ru * ual;
+    uga = -ru * uga;
+    ude = du - ru * ude;
+    ual = au;
+  }
+  // the lane's two rows, scaled to a unit diagonal:
+  // row 0: a0 x_{prev last} + x_first + c0 x_last = d0
+  // row 1: a1 x_first + x_last + c1 x_{next first} = d1
+  const double s0 = rcp_nr(ube), s1 = ib;
+  double a0 = ual * s0, c0 = uga * s0, d0 = ude * s0;
+  double a1 = eta * s1, c1 = cpr * s1, d1 = del * s1;
+  // cyclic reduction over the 128 rows 2l + q: at distance st, row i takes
+  // rows i - st and i + st (zero outside 0..127) and then couples i -+ 2 st
+#pragma unroll
+  for (int st = 1; st < 128; st <<= 1) {
+    double la0, lc0, ld0, ua0, uc0, ud0, la1, lc1, ld1, ua1, uc1, ud1;
+    if (st == 1) {
+      const bool lo = l >= 1, hi = l <= 62;
+      const double pa = __shfl_up(a1, 1), pc = __shfl_up(c1, 1), pd = __shfl_up(d1, 1);
+      const double na = __shfl_down(a0, 1), nc = __shfl_down(c0, 1), nd = __shfl_down(d0, 1);
+      la0 = lo ? pa : 0.0; lc0 = lo ? pc : 0.0; ld0 = lo ? pd : 0.0;
+      ua0 = a1; uc0 = c1; ud0 = d1;
+      la1 = a0; lc1 = c0; ld1 = d0;
+      ua1 = hi ? na : 0.0; uc1 = hi ? nc : 0.0; ud1 = hi ? nd : 0.0;
+    } else {
+      const int sh = st >> 1;
+      const bool lo = l >= sh, hi = l + sh <= 63;
+      const double p0a = __shfl_up(a0, sh), p0c = __shfl_up(c0, sh), p0d = __shfl_up(d0, sh);
+      const double p1a = __shfl_up(a1, sh), p1c = __shfl_up(c1, sh), p1d = __shfl_up(d1, sh);
+      const double n0a = __shfl_down(a0, sh), n0c = __shfl_down(c0, sh), n0d = __shfl_down(d0, sh);
+      const double n1a = __shfl_down(a1, sh), n1c = __shfl_down(c1, sh), n1d = __shfl_down(d1, sh);
+      la0 = lo ? p0a : 0.0; lc0 = lo ? p0c : 0.0; ld0 = lo ? p0d : 0.0;
+      la1 = lo ? p1a : 0.0; lc1 = lo ? p1c : 0.0; ld1 = lo ? p1d : 0.0;
+      ua0 = hi ? n0a : 0.0; uc0 = hi ? n0c : 0.0; ud0 = hi ? n0d : 0.0;
+      ua1 = hi ? n1a : 0.0; uc1 = hi ? n1c : 0.0; ud1 = hi ? n1d : 0.0;
+    }
+    const double n0 = rcp_nr(1.0 - a0 * lc0 - c0 * ua0), n1 = rcp_nr(1.0 - a1 * lc1 - c1 * ua1);
+    const double na0 = -a0 * la0 * n0, nc0 = -c0 * uc0 * n0, nd0 = (d0 - a0 * ld0 - c0 * ud0) * n0;
+    const double na1 = -a1 * la1 * n1, nc1 = -c1 * uc1 * n1, nd1 = (d1 - a1 * ld1 - c1 * ud1) * n1;
+    a0 = na0; c0 = nc0; d0 = nd0;
+    a1 = na1; c1 = nc1; d1 = nd1;
+  }
+  const double xf = d0, xl = d1;
+  D[p0] = xf;
+  D[p0 + M - 1] = xl;
+  double xn = xl;
+  for (int i = M - 2; i >= 1; --i) {
+    const double xi = (G[p0 + i] - H[p0 + i] * xf - C[p0 + i] * xn) * Q[p0 + i];
+    D[p0 + i] = xi;
+    xn = xi;
+  }
+}
+
 template <int K>
 __device__ inline void tri_solve_block(const double (&a)[K], const double (&b)[K], const double (&c)[K],
                                        const double (&d)[K], double (&x)[K], double *lds, int T) {
@@ -179,63 +279,29 @@ __device__ inline void tri_solve_block(const double (&a)[K], const double (&b)[K
     cv = -r * cv;
     dv = d[i] - r * dv;
   }
-  // interface rows: 2t -> x_s, 2t+1 -> x_e
-  double *ra = lds, *rb = lds + 2 * T, *rc = lds + 4 * T, *rd = lds + 6 * T;
-  ra[2 * t] = a[0];
-  rb[2 * t] = bv;
-  rc[2 * t] = cv;
-  rd[2 * t] = dv;
-  ra[2 * t + 1] = ah[K - 1];
-  rb[2 * t + 1] = bh[K - 1];
-  rc[2 * t + 1] = c[K - 1];
-  rd[2 * t + 1] = dh[K - 1];
+  // interface rows 2t (x_s) and 2t + 1 (x_e), both in lane 2t / M's range
+  const int M = T >> 5, S = tri_lds_stride(T);
+  double *A = lds, *B = lds + S, *C = lds + 2 * S, *D = lds + 3 * S;
+  const int ps = 2 * t + (2 * t) / M;
+  A[ps] = a[0];
+  B[ps] = bv;
+  C[ps] = cv;
+  D[ps] = dv;
+  A[ps + 1] = ah[K - 1];
+  B[ps + 1] = bh[K - 1];
+  C[ps + 1] = c[K - 1];
+  D[ps + 1] = dh[K - 1];
   __syncthreads();
-  const int R = 2 * T;
-  for (int st = 1; st < R; st <<= 1) {
-    double na[2], nb[2], nc[2], nd[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      int i = 2 * t + q;
-      double ai = ra[i], bi = rb[i], ci = rc[i], di = rd[i];
-      double al = 0.0, ga = 0.0;
-      double am = 0.0, cm = 0.0, dm = 0.0, ap = 0.0, cp = 0.0, dp = 0.0;
-      if (i - st >= 0) {
-        al = ai * rcp_nr(rb[i - st]);
-        am = ra[i - st];
-        cm = rc[i - st];
-        dm = rd[i - st];
-      }
-      if (i + st < R) {
-        ga = ci * rcp_nr(rb[i + st]);
-        ap = ra[i + st];
-        cp = rc[i + st];
-        dp = rd[i + st];
-      }
-      na[q] = -al * am;
-      nc[q] = -ga * cp;
-      nb[q] = bi - al * cm - ga * ap;
-      nd[q] = di - al * dm - ga * dp;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      int i = 2 * t + q;
-      ra[i] = na[q];
-      rb[i] = nb[q];
-      rc[i] = nc[q];
-      rd[i] = nd[q];
-    }
-    __syncthreads();
-  }
-  const double xs = rd[2 * t] * rcp_nr(rb[2 * t]);
-  const double xe = rd[2 * t + 1] * rcp_nr(rb[2 * t + 1]);
+  if (t < 64) tri_interface_wave(A, B, C, D, lds + 4 * S, lds + 5 * S, lds + 6 * S, M);
+  __syncthreads();
+  const double xs = D[ps], xe = D[ps + 1];
   x[0] = xs;
   x[K - 1] = xe;
 #pragma unroll
   for (int i = K - 2; i >= 1; --i) x[i] = (dh[i] - ah[i] * xs - c[i] * x[i + 1]) * ib[i];
-  __syncthreads();
-  // publish the first unknown of every partition for neighbours (reuse ra)
-  ra[t] = xs;
+  // publish the first unknown of every partition for neighbours (the A
+  // array is no longer read)
+  lds[t] = xs;
   __syncthreads();
 }
 

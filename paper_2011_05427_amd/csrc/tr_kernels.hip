@@ -1110,7 +1110,7 @@ __device__ inline void level_out(const SlabDev &S, int level, int p, const LoSol
 template <int K, bool FINE, bool MOM>
 __global__ __launch_bounds__(512) void k_lo(const SlabDev *__restrict__ sd, ProbDev pd, const Item *__restrict__ tab,
                                             const Ctl *ctl, int pmode, int lcyc, int level, LoIn in, LoSol sol) {
-  extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
+  extern __shared__ double lds[];  // tri_lds_doubles(blockDim) doubles (launch argument)
   const Item it = tab[blockIdx.x];
   if (!pred_ok(ctl, it.slab, pmode, lcyc)) return;
   const SlabDev &S = sd[it.slab];
@@ -1688,7 +1688,7 @@ template <int K>
 __global__ __launch_bounds__(512) void k_grey(const SlabDev *__restrict__ sd, ProbDev pd,
                                               const Item *__restrict__ tab, Ctl *ctl, int pmode, int lcyc,
                                               GreyArgs ga) {
-  extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
+  extern __shared__ double lds[];  // tri_lds_doubles(blockDim) doubles (launch argument)
   __shared__ int s_flag[2];
   // every scalar input (work item, descriptor, control record) is read
   // without branches so that the loads overlap: the control record is read
@@ -2525,7 +2525,7 @@ __global__ __launch_bounds__(256) void k_a1_factor(const SlabDev *__restrict__ s
 template <int K>
 __global__ __launch_bounds__(512) void k_a1_solve_blk(const SlabDev *__restrict__ sd, ProbDev pd,
                                                       const Item *__restrict__ tab, A1Args a, int with_phi) {
-  extern __shared__ double lds[];  // 8 blockDim doubles (launch argument)
+  extern __shared__ double lds[];  // tri_lds_doubles(blockDim) doubles (launch argument)
   const Item it = tab[blockIdx.x];
   if (!a1_on(a, it.slab)) return;
   const SlabDev &S = sd[it.slab];
@@ -3000,13 +3000,13 @@ void launch_lo(const LaunchEnv &env, const Table &tab, int threads, const Ctl *c
                const LoIn &in, const LoSol &sol) {
   if (tab.n == 0) return;
   if (level == 0 && in.mom)
-    hipLaunchKernelGGL((k_lo<TR_LO_K, true, true>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd,
+    hipLaunchKernelGGL((k_lo<TR_LO_K, true, true>), blocks(tab.n), dim3(threads), tri_lds_doubles(threads) * sizeof(double), env.stream, env.sd, env.pd,
                        tab.d, ctl, pmode, lcyc, level, in, sol);
   else if (level == 0)
-    hipLaunchKernelGGL((k_lo<TR_LO_K, true, false>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
+    hipLaunchKernelGGL((k_lo<TR_LO_K, true, false>), blocks(tab.n), dim3(threads), tri_lds_doubles(threads) * sizeof(double), env.stream, env.sd, env.pd, tab.d, ctl,
                        pmode, lcyc, level, in, sol);
   else
-    hipLaunchKernelGGL((k_lo<TR_LO_K, false, false>), blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl,
+    hipLaunchKernelGGL((k_lo<TR_LO_K, false, false>), blocks(tab.n), dim3(threads), tri_lds_doubles(threads) * sizeof(double), env.stream, env.sd, env.pd, tab.d, ctl,
                        pmode, lcyc, level, in, sol);
 }
 
@@ -3049,7 +3049,7 @@ void launch_restrict(const LaunchEnv &env, const RestrictTables &rt, const Ctl *
 void launch_grey(const LaunchEnv &env, const Table &tab, int threads, Ctl *ctl, int pmode, int lcyc,
                  const GreyArgs &ga) {
   if (tab.n == 0) return;
-  hipLaunchKernelGGL(k_grey<TR_GREY_K>, blocks(tab.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd, tab.d, ctl, pmode,
+  hipLaunchKernelGGL(k_grey<TR_GREY_K>, blocks(tab.n), dim3(threads), tri_lds_doubles(threads) * sizeof(double), env.stream, env.sd, env.pd, tab.d, ctl, pmode,
                      lcyc, ga);
 }
 
@@ -3156,7 +3156,7 @@ void launch_a1_factor(const LaunchEnv &env, const Table &t_g, const A1Args &a) {
 }
 void launch_a1_solve_blk(const LaunchEnv &env, const Table &t_sg, int threads, const A1Args &a, bool with_phi) {
   if (t_sg.n == 0) return;
-  hipLaunchKernelGGL(k_a1_solve_blk<TR_LO_K>, blocks(t_sg.n), dim3(threads), 64 * threads, env.stream, env.sd, env.pd,
+  hipLaunchKernelGGL(k_a1_solve_blk<TR_LO_K>, blocks(t_sg.n), dim3(threads), tri_lds_doubles(threads) * sizeof(double), env.stream, env.sd, env.pd,
                      t_sg.d, a, with_phi ? 1 : 0);
 }
 void launch_a1_rhs(const LaunchEnv &env, const Table &t_cell, const A1Args &a) {
