@@ -914,19 +914,30 @@ __device__ inline void lo_load(const LevelView &v, RowData<K> &R, const FacSrc *
       __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tr_u32x2, fc[k + 1]), fs->rf, (t * K - 1 + k) * 8, 0,
                                             0);
   }
+  // cell values of cells t K - 2 .. t K + K - 1 (the thread's cells and one
+  // on each side), each loaded once: edge q = e - t K + 1 lies between cells
+  // q and q + 1 of these
+  double dxv[K + 2], fv[K + 2], sgv[K + 2];
+#pragma unroll
+  for (int j = 0; j < K + 2; ++j) {
+    const int i = t * K - 2 + j;
+    dxv[j] = buf_load_f64(r_dx, i * 8);
+    if (FINE) {
+      fv[j] = MOM ? fc[j] : buf_load_f64(buf_rsrc(v.f, cb), i * 8);
+      sgv[j] = buf_load_f64(buf_rsrc(v.sgr, cb), i * 8);
+    }
+  }
 #pragma unroll
   for (int q = 0; q <= K; ++q) {
     const int e = t * K - 1 + q;
     const bool in = e >= 0 && e <= nx;
-    const double dxm = buf_load_f64(r_dx, (e - 1) * 8), dxe = buf_load_f64(r_dx, e * 8);
+    const double dxm = dxv[q], dxe = dxv[q + 1];
     R.h[q] = in ? 0.5 * (dxm + dxe) : 1.0;
     R.Fo[q] = buf_load_f64(r_Fo, e * 8);
     if (FINE) {
       // cell sigma_R of the edge's two cells (the kappa table under the point law)
-      const __amdgpu_buffer_rsrc_t r_f = buf_rsrc(v.f, cb), r_k = buf_rsrc(v.sgr, cb);
-      const double fe = MOM ? fc[q + 1] : buf_load_f64(r_f, e * 8);
-      const double fm = MOM ? fc[q] : buf_load_f64(r_f, (e - 1) * 8);
-      const double ke = buf_load_f64(r_k, e * 8), km = buf_load_f64(r_k, (e - 1) * 8);
+      const double fe = fv[q + 1], fm = fv[q];
+      const double ke = sgv[q + 1], km = sgv[q];
       // boundary factors are added (the cell loads are zero there), so that
       // no load is conditional
       R.ae[q] = fe + (e == nx ? (MOM ? fs->bf.fb1 : v.fbnd[1]) : 0.0);
@@ -941,13 +952,15 @@ __device__ inline void lo_load(const LevelView &v, RowData<K> &R, const FacSrc *
       R.sr[q] = buf_load_f64(buf_rsrc(v.sigR, eb), e * 8);
     }
   }
+  // kappa is the sigma_R table itself unless a separate one is given
+  const bool kap_is_sgr = FINE && v.kap == v.sgr;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int i = t * K + k - 1;
-    R.dx[k] = buf_load_f64(r_dx, i * 8);
+    R.dx[k] = dxv[k + 1];
     R.Eo[k] = buf_load_f64(r_Eo, i * 8);
     if (FINE) {
-      const double kap = buf_load_f64(buf_rsrc(v.kap, cb), i * 8);
+      const double kap = kap_is_sgr ? sgv[k + 1] : buf_load_f64(buf_rsrc(v.kap, cb), i * 8);
       R.se[k] = kap;
       R.em[k] = 2.0 * kap * buf_load_f64(buf_rsrc(v.Bt, cb), i * 8);
     } else {
