@@ -294,8 +294,10 @@ def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles):
     """The same steps with the grid hierarchy and lmax chosen per step by
     ``tuning.CostModelSchedule``.  Untimed set-up: the sweep kernel time, and
     every candidate's first 2 steps from the initial state (after 2 steps
-    that capture its graphs), which seed the model with measurements over the
-    same steps."""
+    that capture its graphs), which seed the model's cycle costs with
+    measurements over the same steps; the sweep ratios start at 1 (the
+    set-up's transient steps overstate their differences) and are learned
+    from the timed steps."""
     import torch
 
     from paper_2011_05427_amd import binding, tuning
@@ -322,7 +324,7 @@ def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles):
         seed[cand] = (1e3 * (time.perf_counter() - t0), max(int(a.n_ti) for a in acc),
                       max(int(a.n_c) for a in acc), 2)
     sv.state_init(st, slabs[0].T0)
-    ctl = tuning.CostModelSchedule(cands, t_sweep=t_sweep, seed=seed)
+    ctl = tuning.CostModelSchedule(cands, t_sweep=t_sweep, seed=seed, ratio_prior=1.0)
     torch.cuda.synchronize()
     acc = (binding.TrStats * len(slabs))()
     t0 = time.perf_counter()
@@ -339,8 +341,9 @@ def run_stage_adaptive(slabs, levels, cfg, steps, warmup, tiles):
             "candidates": [name(c) for c in cands],
             "set_up_ms_per_step": {name(c): v[0] / v[3] for c, v in seed.items()},
             "note": "hierarchy (grids visited after each grey solve) and lmax per step from the cost model "
-                    "s t_sweep + (s + 1) k_c t_c, seeded by every candidate's first 2 steps from the initial "
-                    "state (untimed); every 8th step re-measures a candidate predicted within 25% of the best"}
+                    "s t_sweep + (s + 1) k_c t_c, cycle costs seeded by every candidate's first 2 steps from "
+                    "the initial state (untimed), sweep ratios starting at 1 and learned from the timed steps; "
+                    "every 8th step re-measures a candidate predicted within 25% of the best"}
 
 
 def measure(workload, steps, warmup, tiles_opt=None, lmax_opt=None, fp32=False):

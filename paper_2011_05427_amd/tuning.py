@@ -215,10 +215,17 @@ class CostModelSchedule:
     `probe`-th step re-runs the candidate measured longest ago among those
     predicted within `probe_margin` of the best.  `seed` starts the model from
     measurements of the candidates over the same steps (an untimed set-up).
-    Deterministic in the recorded counts and times (ties: candidate order)."""
+    `ratio_prior`, if given, replaces the seeded sweep ratios by that value
+    for every candidate: the set-up's first steps from the initial state are
+    the problem's hardest transient, where the hierarchies' sweep counts
+    differ most, so their ratios can rank a candidate by a difference that the
+    later steps do not have; the prior (1: the transport iterations do not
+    depend on the hierarchy) keeps the seeded cycle costs and lets the
+    recorded steps move the ratios.  Deterministic in the recorded counts and
+    times (ties: candidate order)."""
 
     def __init__(self, candidates, t_sweep: float, probe: int = 8, decay: float = 0.5, ratio_decay: float = 0.9,
-                 seed=None, probe_margin: float = 1.25):
+                 seed=None, probe_margin: float = 1.25, ratio_prior=None):
         self.cands = [self._norm(c) for c in candidates]
         self.ratio_decay = float(ratio_decay)
         if not self.cands:
@@ -230,6 +237,9 @@ class CostModelSchedule:
         self.d = None
         self.k = 0
         self.history = []
+        if ratio_prior is not None and not (float(ratio_prior) > 0.0):
+            raise ValueError("ratio_prior > 0 required")
+        self.ratio_prior = None if ratio_prior is None else float(ratio_prior)
         if seed:
             self._seed(seed)
 
@@ -251,7 +261,7 @@ class CostModelSchedule:
             if c not in seed:
                 continue
             ms, sw, cyc, n = (float(x) for x in seed[c])
-            self.r[c] = max(sw, 1.0) / s_ref
+            self.r[c] = max(sw, 1.0) / s_ref if self.ratio_prior is None else self.ratio_prior
             self.k_c[c] = cyc / (sw + n)
             self.t_c[c] = max(ms - sw * self.t_sweep, 0.0) / max(cyc, 1.0)
             self.seen[c] = -1

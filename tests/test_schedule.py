@@ -151,6 +151,31 @@ def test_seeded_cost_model_starts_from_the_set_up_and_probes_near_candidates():
     assert A in picks  # within 25% of the best: re-measured by a probe
 
 
+def test_ratio_prior_keeps_seeded_cycle_costs_and_learns_the_ratios():
+    """With a ratio prior, a candidate whose set-up steps needed more sweeps
+    but whose cycles are cheaper is taken first; the recorded steps then move
+    its ratio towards what it needs."""
+    A, B = ((), 1), ((1,), 1)
+    # set-up: A 8 sweeps at 0.4 ms per cycle, B 6 sweeps at 0.6 ms per cycle
+    seed = {A: (8 * 1.0 + 10 * 0.4, 8, 10, 2), B: (6 * 1.0 + 8 * 0.6, 6, 8, 2)}
+    plain = tuning.CostModelSchedule([A, B], t_sweep=1.0, probe=0, decay=0.5, seed=seed)
+    # d = 4: A 4 + 5 * 0.4 = 6.0, B 3 + 4 * 0.6 = 5.4 (the set-up's ratio 6 / 8)
+    assert plain.predict(A) == pytest.approx(6.0) and plain.predict(B) == pytest.approx(5.4)
+    assert plain.choose() == B
+    ctl = tuning.CostModelSchedule([A, B], t_sweep=1.0, probe=0, decay=0.5, seed=seed, ratio_prior=1.0)
+    assert ctl.r[A] == 1.0 and ctl.r[B] == 1.0
+    assert ctl.k_c[A] == pytest.approx(10 / 10) and ctl.t_c[A] == pytest.approx(0.4)
+    # equal sweeps: A 4 + 5 * 0.4 = 6.0, B 4 + 5 * 0.6 = 7.0
+    assert ctl.predict(B) == pytest.approx(7.0)
+    assert ctl.choose() == A
+    # A needs twice the sweeps that B needs at the same stage: its ratio rises
+    ctl.record(B, 3 * 1.0 + 4 * 0.6, 3, 4)
+    ctl.record(A, 6 * 1.0 + 7 * 0.4, 6, 7)
+    assert ctl.r[A] > 1.0
+    with pytest.raises(ValueError):
+        tuning.CostModelSchedule([A], t_sweep=1.0, ratio_prior=0.0)
+
+
 def test_cost_model_candidates_and_validation():
     ctl = tuning.CostModelSchedule([((4, 3, 2, 1), 1), (0, 2), ([1], 1)], t_sweep=0.5)
     assert ctl.cands == [((4, 3, 2, 1), 1), (0, 2), ((1,), 1)]
